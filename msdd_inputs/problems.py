@@ -1,0 +1,549 @@
+"""Seeded synthetic problem generators (inputs only).
+
+This module builds the *inputs* of the multilevel spectral domain
+decomposition method: a structured mesh of the unit square/cube, a
+coefficient field, conforming Q1 element matrices (scalar diffusion and
+trilinear linear elasticity), the assembled stiffness matrix on the free
+dofs (Dirichlet dofs eliminated), the load vector, an overlapping box
+partition of the elements, the partition-of-unity weights and the
+parent maps of the coarse levels.
+
+It holds none of the method's arithmetic (no local matrices, no
+eigenproblems, no coarse spaces, no Krylov solver).  Both the CPU oracle
+and the GPU library consume exactly these arrays.
+
+Paper sections followed:
+  * Sec. 3.3 (continuous Galerkin): a_tau(u,v) = int_tau (K grad u).grad v,
+    l(v) = int f v; element-wise stiffness matrices.
+  * Sec. 2.2 (hierarchical domain decomposition): finest level = element
+    partition plus delta layers of overlap; coarser levels group subdomain
+    indices (nonoverlapping index sets J_{l,i}); level 0 is one subdomain.
+  * Sec. 2.3 (partition of unity definition): chi_{l,i} vanishes on the
+    interior subdomain boundary and the weights sum to one.  The concrete
+    construction (nodal multiplicity weights) is not given by the paper;
+    we use d_i(p) = [p in Dir_i] / #{j : p in Dir_j}.
+"""
+from __future__ import annotations
+
+import dataclasses
+import itertools
+from typing import List, Optional, Sequence
+
+import numpy as np
+import scipy.fft
+import scipy.sparse as sp
+
+# ----------------------------------------------------------------------------
+# Reference Q1 element: 2 Gauss points per direction on [0,1]^d.
+# Node a of the reference cell has coordinates bit_d(a) in {0,1}^d
+# (x fastest), i.e. lexicographic local numbering.
+# ----------------------------------------------------------------------------
+
+
+def _gauss2():
+    g = 1.0 / np.sqrt(3.0)
+    return np.array([(1 - g) / 2, (1 + g) / 2]), np.array([0.5, 0.5])
+
+
+def q1_shape(dim: int, x: np.ndarray):
+    """Values [2^dim] and reference gradients [2^dim, dim] of Q1 at x."""
+    nn = 2 ** dim
+    val = np.ones(nn)
+    grad = np.ones((nn, dim))
+    for a in range(nn):
+        for d in range(dim):
+            bit = (a >> d) & 1
+            f = x[d] if bit else 1.0 - x[d]
+            df = 1.0 if bit else -1.0
+            val[a] *= f
+            for e in range(dim):
+                grad[a, e] *= df if e == d else f
+    return val, grad
+
+
+def _quad_points(dim: int):
+    p, w = _gauss2()
+    for idx in itertools.product(range(2), repeat=dim):
+        yield np.array([p[i] for i in idx]), float(np.prod([w[i] for i in idx]))
+
+
+def q1_laplace_element(dim: int, h: float) -> np.ndarray:
+    """Stiffness of -div(grad u) on an axis-parallel cube of side h (unit coefficient)."""
+    nn = 2 ** dim
+    K = np.zeros((nn, nn))
+    for x, w in _quad_points(dim):
+        _, g = q1_shape(dim, x)
+        g = g / h
+        K += w * h ** dim * (g @ g.T)
+    return K
+
+
+def q1_load_element(dim: int, h: float, ncomp: int = 1, f: Sequence[float] = (1.0,)) -> np.ndarray:
+    """Element load vector int f phi_a for a constant body force f (length ncomp)."""
+    nn = 2 ** dim
+    out = np.zeros(nn * ncomp)
+    for x, w in _quad_points(dim):
+        v, _ = q1_shape(dim, x)
+        for a in range(nn):
+            for c in range(ncomp):
+                out[a * ncomp + c] += w * h ** dim * v[a] * f[c]
+    return out
+
+
+def isotropic_voigt(E: float, nu: float) -> np.ndarray:
+    """6x6 isotropic elasticity matrix, engineering shear strains, order xx,yy,zz,yz,xz,xy."""
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = E / (2 * (1 + nu))
+    C = np.zeros((6, 6))
+    C[:3, :3] = lam
+    C[np.arange(3), np.arange(3)] += 2 * mu
+    C[np.arange(3, 6), np.arange(3, 6)] = mu
+    return C
+
+
+def fibre_voigt(E_f: float, nu: float, axis: Sequence[float]) -> np.ndarray:
+    """Isotropic unit-modulus matrix plus (E_f - 1) a(x)a(x)a(x)a along the fibre axis a.
+
+    sigma = C eps with the added term (E_f-1) a (a^T eps a); in Voigt form with
+    engineering shears this is (E_f-1) v v^T with v = (a1^2,a2^2,a3^2,a2a3,a1a3,a1a2).
+    """
+    a = np.asarray(axis, float)
+    a = a / np.linalg.norm(a)
+    v = np.array([a[0] ** 2, a[1] ** 2, a[2] ** 2, a[1] * a[2], a[0] * a[2], a[0] * a[1]])
+    return isotropic_voigt(1.0, nu) + (E_f - 1.0) * np.outer(v, v)
+
+
+def q1_elasticity_element(h: float, C: np.ndarray) -> np.ndarray:
+    """24x24 trilinear hexahedral elasticity stiffness on a cube of side h.
+
+    Dof ordering: 3*a + c (node a, component c).
+    """
+    K = np.zeros((24, 24))
+    for x, w in _quad_points(3):
+        _, g = q1_shape(3, x)
+        g = g / h
+        B = np.zeros((6, 24))
+        for a in range(8):
+            gx, gy, gz = g[a]
+            B[0, 3 * a + 0] = gx
+            B[1, 3 * a + 1] = gy
+            B[2, 3 * a + 2] = gz
+            B[3, 3 * a + 1] = gz
+            B[3, 3 * a + 2] = gy
+            B[4, 3 * a + 0] = gz
+            B[4, 3 * a + 2] = gx
+            B[5, 3 * a + 0] = gy
+            B[5, 3 * a + 1] = gx
+        K += w * h ** 3 * (B.T @ C @ B)
+    return K
+
+
+# ----------------------------------------------------------------------------
+# Structured mesh of the unit cube [0,1]^dim with N^dim elements.
+# ----------------------------------------------------------------------------
+
+
+def element_nodes(dim: int, N: int) -> np.ndarray:
+    """[N^dim, 2^dim] global node ids (lexicographic, x fastest)."""
+    M = N + 1
+    ev = np.stack(np.meshgrid(*([np.arange(N)] * dim), indexing="ij"), -1).reshape(-1, dim)[:, ::-1]
+    # ev[e] = (ex, ey[, ez]) with element id e = ex + N*ey (+ N^2 ez)
+    nodes = np.zeros((ev.shape[0], 2 ** dim), dtype=np.int64)
+    for a in range(2 ** dim):
+        off = np.array([(a >> d) & 1 for d in range(dim)])
+        c = ev + off
+        gid = np.zeros(ev.shape[0], dtype=np.int64)
+        for d in reversed(range(dim)):
+            gid = gid * M + c[:, d]
+        nodes[:, a] = gid
+    return nodes
+
+
+def element_coords(dim: int, N: int) -> np.ndarray:
+    """[N^dim, dim] integer element coordinates (ex, ey[, ez]) for element id e."""
+    return np.stack(np.meshgrid(*([np.arange(N)] * dim), indexing="ij"), -1).reshape(-1, dim)[:, ::-1]
+
+
+def boundary_nodes(dim: int, N: int, which: str = "all") -> np.ndarray:
+    M = N + 1
+    c = np.stack(np.meshgrid(*([np.arange(M)] * dim), indexing="ij"), -1).reshape(-1, dim)[:, ::-1]
+    if which == "all":
+        mask = np.any((c == 0) | (c == N), axis=1)
+    elif which == "x0":
+        mask = c[:, 0] == 0
+    elif which == "x01":
+        mask = (c[:, 0] == 0) | (c[:, 0] == N)
+    else:
+        raise ValueError(which)
+    return mask
+
+
+@dataclasses.dataclass
+class Problem:
+    """All arrays a caller hands to the solver (and to the oracle)."""
+    name: str
+    dim: int
+    ncomp: int
+    N: int
+    n: int                      # free dofs
+    elem_dofs: np.ndarray       # int32 [n_elem, k], -1 = eliminated Dirichlet dof
+    elem_mat: np.ndarray        # float64 [n_elem, k, k]
+    A: sp.csr_matrix            # free-dof stiffness, float64
+    b: np.ndarray               # load vector on free dofs
+    sub_elem_ptr: np.ndarray    # int64 [P_L+1]
+    sub_elem: np.ndarray        # int32 element ids of T_{h,L,i}
+    sub_dof_ptr: np.ndarray     # int64 [P_L+1]
+    sub_dof: np.ndarray         # int32 sorted free dofs of T_{h,L,i} (Neumann space)
+    sub_pou: np.ndarray         # float64 partition-of-unity weight per (i, dof)
+    n_levels: int               # L+1
+    parents: List[np.ndarray]   # parents[0]: level L -> L-1, parents[1]: L-1 -> L-2, ...
+    eta: float
+    coeff: Optional[np.ndarray] = None  # per-element scalar coefficient (diffusion) or material id
+    box_shape: Optional[tuple] = None   # subdomains per dimension on the finest level
+
+    @property
+    def n_elem(self):
+        return self.elem_dofs.shape[0]
+
+    @property
+    def k(self):
+        return self.elem_dofs.shape[1]
+
+    @property
+    def n_sub(self):
+        return len(self.sub_elem_ptr) - 1
+
+    def csr_arrays(self):
+        A = self.A
+        return (A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float64))
+
+    def sub_dofs(self, i):
+        return self.sub_dof[self.sub_dof_ptr[i]:self.sub_dof_ptr[i + 1]]
+
+    def sub_weights(self, i):
+        return self.sub_pou[self.sub_dof_ptr[i]:self.sub_dof_ptr[i + 1]]
+
+    def sub_elems(self, i):
+        return self.sub_elem[self.sub_elem_ptr[i]:self.sub_elem_ptr[i + 1]]
+
+
+def _split(n: int, p: int) -> np.ndarray:
+    return np.array([(i * n) // p for i in range(p + 1)])
+
+
+def box_partition(dim: int, N: int, P: int, delta: int):
+    """Overlapping box partition: P^dim boxes of elements, each grown by delta layers."""
+    cuts = _split(N, P)
+    ec = element_coords(dim, N)
+    ptr = [0]
+    lists = []
+    for bidx in itertools.product(range(P), repeat=dim):
+        b = bidx[::-1]  # b[0] fastest -> subdomain id = bx + P*by (+P^2 bz)
+        mask = np.ones(ec.shape[0], bool)
+        for d in range(dim):
+            lo = max(cuts[b[d]] - delta, 0)
+            hi = min(cuts[b[d] + 1] + delta, N)
+            mask &= (ec[:, d] >= lo) & (ec[:, d] < hi)
+        el = np.nonzero(mask)[0].astype(np.int32)
+        lists.append(el)
+        ptr.append(ptr[-1] + len(el))
+    return np.array(ptr, np.int64), np.concatenate(lists)
+
+
+def group_parents(dim: int, P: int, G: int) -> np.ndarray:
+    """Nonoverlapping grouping of a P^dim box grid into a G^dim grid of coarse subdomains."""
+    par = np.zeros(P ** dim, np.int32)
+    for bidx in itertools.product(range(P), repeat=dim):
+        b = bidx[::-1]
+        i = sum(b[d] * P ** d for d in range(dim))
+        g = [(b[d] * G) // P for d in range(dim)]
+        par[i] = sum(g[d] * G ** d for d in range(dim))
+    return par
+
+
+def neumann_spaces_and_pou(n: int, elem_dofs: np.ndarray, sub_elem_ptr, sub_elem):
+    """V-bar dofs (free dofs of the subdomain's elements) and nodal multiplicity PoU."""
+    P = len(sub_elem_ptr) - 1
+    valid = elem_dofs >= 0
+    deg = np.bincount(elem_dofs[valid], minlength=n)
+    vbar, dirs = [], []
+    for i in range(P):
+        el = sub_elem[sub_elem_ptr[i]:sub_elem_ptr[i + 1]]
+        ed = elem_dofs[el]
+        ed = ed[ed >= 0]
+        cnt = np.bincount(ed, minlength=n)
+        dofs = np.nonzero(cnt)[0]
+        vbar.append(dofs.astype(np.int32))
+        dirs.append(cnt[dofs] == deg[dofs])
+    mult = np.zeros(n)
+    for i in range(P):
+        mult[vbar[i][dirs[i]]] += 1
+    if np.any(mult == 0):
+        raise ValueError("some free dof lies in no subdomain interior (overlap too small)")
+    ptr = [0]
+    w = []
+    for i in range(P):
+        wi = np.where(dirs[i], 1.0 / mult[vbar[i]], 0.0)
+        w.append(wi)
+        ptr.append(ptr[-1] + len(vbar[i]))
+    return np.array(ptr, np.int64), np.concatenate(vbar), np.concatenate(w)
+
+
+def assemble(n: int, elem_dofs: np.ndarray, elem_mat: np.ndarray) -> sp.csr_matrix:
+    ne, k = elem_dofs.shape
+    r = np.repeat(elem_dofs, k, axis=1).reshape(-1)
+    c = np.tile(elem_dofs, (1, k)).reshape(-1)
+    v = elem_mat.reshape(-1)
+    m = (r >= 0) & (c >= 0)
+    A = sp.coo_matrix((v[m], (r[m], c[m])), shape=(n, n)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
+
+
+def build_problem(name: str, dim: int, N: int, coeff: np.ndarray, P: int, delta: int,
+                  n_levels: int, eta: float, groups: Sequence[int] = (),
+                  elasticity_materials: Optional[List[np.ndarray]] = None,
+                  bc: str = "all", force: Sequence[float] = (1.0,)) -> Problem:
+    """Assemble a structured-box problem.
+
+    coeff: per-element scalar diffusion coefficient, or (elasticity) per-element
+    material index into elasticity_materials (list of 6x6 Voigt matrices).
+    groups: number of coarse subdomains per dimension for levels L-1, L-2, ...
+    """
+    h = 1.0 / N
+    nodes = element_nodes(dim, N)
+    ne = nodes.shape[0]
+    bmask = boundary_nodes(dim, N, bc)
+    nn = (N + 1) ** dim
+    if elasticity_materials is None:
+        ncomp = 1
+        free = ~bmask
+        num = -np.ones(nn, np.int64)
+        num[free] = np.arange(free.sum())
+        elem_dofs = num[nodes].astype(np.int32)
+        Kref = q1_laplace_element(dim, h)
+        elem_mat = coeff[:, None, None] * Kref[None]
+        fe = q1_load_element(dim, h, 1, force)
+    else:
+        ncomp = 3
+        assert dim == 3
+        free_node = ~bmask
+        num = -np.ones(nn * 3, np.int64)
+        fd = np.repeat(free_node, 3)
+        num[fd] = np.arange(fd.sum())
+        elem_dofs = np.zeros((ne, 24), np.int32)
+        for a in range(8):
+            for c in range(3):
+                elem_dofs[:, 3 * a + c] = num[3 * nodes[:, a] + c]
+        Ks = np.stack([q1_elasticity_element(h, C) for C in elasticity_materials])
+        elem_mat = Ks[coeff]
+        fe = q1_load_element(3, h, 3, force)
+    n = int(elem_dofs.max()) + 1
+    A = assemble(n, elem_dofs, elem_mat)
+    b = np.zeros(n)
+    ed = elem_dofs.reshape(-1)
+    fv = np.tile(fe, ne)
+    m = ed >= 0
+    np.add.at(b, ed[m], fv[m])
+    sep, se = box_partition(dim, N, P, delta)
+    sdp, sd, sw = neumann_spaces_and_pou(n, elem_dofs, sep, se)
+    parents = []
+    cur = P
+    for G in groups:
+        parents.append(group_parents(dim, cur, G))
+        cur = G
+    assert len(parents) == n_levels - 2, (len(parents), n_levels)
+    return Problem(name=name, dim=dim, ncomp=ncomp, N=N, n=n, elem_dofs=elem_dofs,
+                   elem_mat=np.ascontiguousarray(elem_mat), A=A, b=b, sub_elem_ptr=sep,
+                   sub_elem=se, sub_dof_ptr=sdp, sub_dof=sd, sub_pou=sw, n_levels=n_levels,
+                   parents=parents, eta=eta, coeff=coeff, box_shape=(P,) * dim)
+
+
+# ----------------------------------------------------------------------------
+# Coefficient fields
+# ----------------------------------------------------------------------------
+
+
+def channels_2d(N: int, rows_sets: Sequence[Sequence[int]], k_hi: float = 1e6) -> np.ndarray:
+    ec = element_coords(2, N)
+    k = np.ones(ec.shape[0])
+    for rows in rows_sets:
+        for r in rows:
+            k[ec[:, 1] == r] = k_hi
+    return k
+
+
+def inclusions_2d(N: int, seed: int, frac: float = 0.10, smin: int = 2, smax: int = 8,
+                  k_hi: float = 1e6) -> np.ndarray:
+    """Seeded random square inclusions (side U{smin..smax}) until the union covers >= frac."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mask = np.zeros((N, N), bool)  # [ey, ex]
+    while mask.mean() < frac:
+        s = int(rng.integers(smin, smax + 1))
+        x0 = int(rng.integers(0, N - s + 1))
+        y0 = int(rng.integers(0, N - s + 1))
+        mask[y0:y0 + s, x0:x0 + s] = True
+    return np.where(mask.reshape(-1), k_hi, 1.0)
+
+
+def gaussian_field(dim: int, N: int, seed: int, sigma2: float = 4.0, ell: float = 0.05) -> np.ndarray:
+    """Stationary Gaussian field with covariance sigma2*exp(-r/ell) on element centres.
+
+    Circulant embedding: the covariance is wrapped on a periodic grid of
+    side m >= 2N; m is doubled until the embedding spectrum is nonnegative
+    (up to round-off); the sample is the real part of an FFT of complex
+    white noise scaled by sqrt(spectrum).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = 1.0 / N
+    m = 2 * N
+    while True:
+        idx = np.arange(m)
+        dd = np.minimum(idx, m - idx) * h
+        grids = np.meshgrid(*([dd] * dim), indexing="ij")
+        r = np.sqrt(sum(g * g for g in grids))
+        c = sigma2 * np.exp(-r / ell)
+        lam = np.real(scipy.fft.fftn(c))
+        if lam.min() >= -1e-8 * lam.max():
+            break
+        m *= 2
+    lam = np.maximum(lam, 0.0)
+    xi = rng.standard_normal(lam.shape) + 1j * rng.standard_normal(lam.shape)
+    g = scipy.fft.ifftn(np.sqrt(lam) * xi) * np.sqrt(lam.size)
+    g = np.real(g)[tuple([slice(0, N)] * dim)]
+    # element id e = ex + N ey (+N^2 ez): array axes (ez, ey, ex)
+    return np.ascontiguousarray(g).reshape(-1)
+
+
+def bars_3d(N: int, seed: int, nbars: int = 3, thick: int = 2) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mask = np.zeros((N, N, N), bool)  # [ez, ey, ex]
+    for _ in range(nbars):
+        ax = int(rng.integers(0, 3))
+        c1 = int(rng.integers(0, N - thick + 1))
+        c2 = int(rng.integers(0, N - thick + 1))
+        sl = [slice(c1, c1 + thick), slice(c2, c2 + thick)]
+        full = [None, None, None]
+        # axis index in (x,y,z); array axes are (z,y,x)
+        arr_ax = 2 - ax
+        others = [a for a in range(3) if a != arr_ax]
+        full[arr_ax] = slice(0, N)
+        full[others[0]] = sl[0]
+        full[others[1]] = sl[1]
+        mask[tuple(full)] = True
+    return mask.reshape(-1)
+
+
+# ----------------------------------------------------------------------------
+# The workloads (synthetic stand-ins for the paper's test problems)
+# ----------------------------------------------------------------------------
+
+C1_ROWS = ((12, 13), (25, 26), (37, 38), (50, 51))
+
+
+def config1() -> Problem:
+    """64x64 Q1, 4 channels of k=1e6, 4x4 boxes, overlap 2, 2 levels, eta=0.1."""
+    N = 64
+    k = channels_2d(N, C1_ROWS)
+    return build_problem("c1_channels_64", 2, N, k, P=4, delta=2, n_levels=2, eta=0.1)
+
+
+def config2(seed: int = 2) -> Problem:
+    """512x512 Q1, binary inclusions (10%, sides 2..8, k=1e6), 16x16 boxes, overlap 2,
+    3 levels (256 -> 16 -> 1), eta=0.1."""
+    N = 512
+    k = inclusions_2d(N, seed)
+    return build_problem("c2_inclusions_512", 2, N, k, P=16, delta=2, n_levels=3, eta=0.1,
+                         groups=(4,))
+
+
+def config3(E_fibre: float = 1e3, nu: float = 0.3) -> Problem:
+    """48^3 trilinear elasticity, 16 plies 3 elements thick (fibre 0/90 deg alternating with
+    resin), clamped at x=0, body force -z; 6^3 boxes, overlap 1, 3 levels (216 -> 27 -> 1)."""
+    N = 48
+    ec = element_coords(3, N)
+    ply = ec[:, 2] // 3
+    mats = [isotropic_voigt(1.0, nu), fibre_voigt(E_fibre, nu, (1, 0, 0)),
+            fibre_voigt(E_fibre, nu, (0, 1, 0))]
+    mat = np.where(ply % 2 == 1, 0, np.where(ply % 4 == 0, 1, 2)).astype(np.int64)
+    return build_problem("c3_composite_48", 3, N, mat, P=6, delta=1, n_levels=3, eta=0.1,
+                         groups=(3,), elasticity_materials=mats, bc="x0", force=(0.0, 0.0, -1.0))
+
+
+def config5(seed: int = 5, N: int = 96) -> Problem:
+    """96^3 Q1 diffusion, seeded bars (k=1e6) over a log-normal field; 8^3 boxes, overlap 1,
+    3 levels (512 -> 64 -> 1)."""
+    g = gaussian_field(3, N, seed)
+    k = np.exp(g)
+    k[bars_3d(N, seed)] = 1e6
+    return build_problem("c5_mixed_96", 3, N, k, P=8, delta=1, n_levels=3, eta=0.1, groups=(4,))
+
+
+def config4_members(seed: int = 4, count: int = 32):
+    """Sizes of the batch of independent 2D log-normal problems."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Ns = rng.integers(128, 1025, size=count)
+    out = []
+    for b, N in enumerate(Ns):
+        P = int(np.clip(round(N / 32), 4, 32))
+        G = max(2, int(np.ceil(P / 4)))
+        out.append((int(N), P, G, 4000 + b))
+    return out
+
+
+def config4_problem(N: int, P: int, G: int, seed: int) -> Problem:
+    k = np.exp(gaussian_field(2, N, seed))
+    return build_problem(f"c4_lognormal_{N}", 2, N, k, P=P, delta=2, n_levels=3, eta=0.1,
+                         groups=(G,))
+
+
+def small_problem(N: int = 8, P: int = 2, delta: int = 1, n_levels: int = 2, groups=(),
+                  dim: int = 2, contrast: float = 1.0, seed: int = 0, eta: float = 0.1,
+                  kind: str = "random") -> Problem:
+    """Tiny test meshes with optional random high-contrast coefficient."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ne = N ** dim
+    if contrast == 1.0:
+        k = np.ones(ne)
+    elif kind == "random":
+        k = np.where(rng.random(ne) < 0.2, contrast, 1.0)
+    elif kind == "channels":
+        ec = element_coords(dim, N)
+        k = np.where((ec[:, 1] % 4) == 1, contrast, 1.0)
+    else:
+        raise ValueError(kind)
+    return build_problem(f"small_{dim}d_{N}", dim, N, k, P=P, delta=delta, n_levels=n_levels,
+                         eta=eta, groups=groups)
+
+
+def small_elasticity(N: int = 4, P: int = 2, delta: int = 1, n_levels: int = 2, groups=(),
+                     E_fibre: float = 10.0, eta: float = 0.1) -> Problem:
+    ec = element_coords(3, N)
+    mats = [isotropic_voigt(1.0, 0.3), fibre_voigt(E_fibre, 0.3, (1, 0, 0))]
+    mat = (ec[:, 2] % 2).astype(np.int64)
+    return build_problem(f"small_elast_{N}", 3, N, mat, P=P, delta=delta, n_levels=n_levels,
+                         eta=eta, groups=groups, elasticity_materials=mats, bc="x0",
+                         force=(0.0, 0.0, -1.0))
+
+
+def free_dof_coords(prob: Problem):
+    """Coordinates [n, dim] and component index [n] of each free dof (for rigid-body tests)."""
+    dim, N = prob.dim, prob.N
+    M = N + 1
+    nn = M ** dim
+    c = np.stack(np.meshgrid(*([np.arange(M)] * dim), indexing="ij"), -1).reshape(-1, dim)[:, ::-1]
+    c = c / N
+    nodes = element_nodes(dim, N)
+    coords = np.zeros((prob.n, dim))
+    comp = np.zeros(prob.n, np.int64)
+    k = prob.k
+    for a in range(2 ** dim):
+        for cc in range(prob.ncomp):
+            col = a * prob.ncomp + cc
+            dd = prob.elem_dofs[:, col]
+            m = dd >= 0
+            coords[dd[m]] = c[nodes[m, a]]
+            comp[dd[m]] = cc
+    assert nn > 0 and k > 0
+    return coords, comp
