@@ -1,0 +1,197 @@
+/*
+ * msdd.h -- C ABI of the MI355X (gfx950) multilevel spectral domain
+ * decomposition library.
+ *
+ * The library builds and applies the multilevel additive Schwarz
+ * preconditioner with spectral (GenEO-type) coarse spaces of Bastian,
+ * Scheichl, Seelinger and Strehlow, "Multilevel Spectral Domain
+ * Decomposition", and runs preconditioned conjugate gradients with it:
+ *
+ *   - Sec. 2.1: the problem A x = b is SPD; the preconditioner is the additive
+ *     subspace correction B = sum_i R_i^T A_i^{-1} R_i with A_i = R_i A R_i^T,
+ *     over the splitting V_h = V_{h,0} + sum_{l=1..L} sum_i V_{h,l,i}.
+ *   - Sec. 2.2: hierarchical decomposition. The finest level is an
+ *     overlapping element partition T_{h,L,i}; coarser levels group the
+ *     subdomains of the next finer level (index sets J_{l,i}); level 0 is one
+ *     subdomain.
+ *   - Sec. 2.3: local Neumann spaces, the partition of unity chi_{l,i}, the
+ *     GEVP abar_{l,i}(w,v) = lambda b_{l,i}(w,v), the coarse space
+ *     V_{h,l-1} = span{ e chi w : lambda < eta } and the Dirichlet subspaces.
+ *   - Sec. 3.5: abar_{l,i} = sum over the subdomain's elements of a_tau;
+ *     b_{l,i}(u,v) = abar_{l,i}(chi u, chi v).
+ *   - Sec. 4.1/4.2: coarse levels work from patch matrices and a generating
+ *     system whose pencil has a common kernel.
+ *   - Sec. 5: CG, stopped when ||b - A x^m|| < rtol ||b - A x^0||.
+ *
+ * Conventions
+ *   - Every function returns an int status: MSDD_OK (0) or a negative code.
+ *   - Array arguments may be host or device pointers; the library detects
+ *     which with hipPointerGetAttributes and copies what it keeps.  The
+ *     caller keeps ownership of every array it passes.
+ *   - Indices are 0-based.  Dof numbers refer to the free dofs (Dirichlet
+ *     dofs are eliminated; an element-dof entry of -1 marks an eliminated dof).
+ *   - A context is not thread-safe.  Several contexts may share a device.
+ *     msdd_solve may be called any number of times after one msdd_setup.
+ */
+#ifndef MSDD_H_
+#define MSDD_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MSDD_OK 0
+#define MSDD_EINVAL (-1)   /* bad shape, index out of range, PoU not a partition of unity, NaN */
+#define MSDD_ENOTSPD (-2)  /* a local or coarse matrix had a non-positive pivot */
+#define MSDD_EEIG (-3)     /* the local eigensolver failed */
+#define MSDD_ENOCONV (-4)  /* PCG reached maxit; x holds the last iterate */
+#define MSDD_EDEVICE (-5)  /* HIP runtime error or missing GPU */
+#define MSDD_ENOMEM (-6)   /* device allocation failed */
+#define MSDD_ESTATE (-7)   /* call order violated (solve before setup, ...) */
+
+/* precision modes */
+#define MSDD_FP64 0   /* everything in double precision */
+#define MSDD_MIXED 1  /* local factorisations, eigensolves and the preconditioner apply in
+                         single precision; PCG recurrences, inner products, the coarsest
+                         factorisation and the eigen-residual check in double */
+
+typedef struct msdd_ctx msdd_ctx; /* opaque; owns all device memory it allocates */
+
+typedef struct {
+  int precision;      /* MSDD_FP64 or MSDD_MIXED */
+  double sigma;       /* spectral shift of the local pencil S = abar + sigma*b (> 0);
+                         <= 0 selects 0.1*eta.  Eigenvalues do not depend on it. */
+  double eps_reg_rel; /* coarse generating-system: ghost pivots below eps_reg_rel times
+                         the largest ghost diagonal are treated as zero (default 1e-12) */
+  int nev_max;        /* 0 = threshold selection only; > 0 caps eigenvectors per subdomain */
+  double eig_tol;     /* tolerance on the normwise backward error
+                         ||b x - nu S x|| / (nu ||S|| ||x||) of the local eigenpairs
+                         (default 1e-14) */
+  int eig_maxit;      /* iterations of the local eigensolver (default 200) */
+  int block;          /* initial block size of the local eigensolver (default 16) */
+  int device;         /* HIP device ordinal */
+  void* stream;       /* hipStream_t to launch on; NULL = the legacy default stream */
+  int verbose;        /* 1 = print phase timings to stderr */
+} msdd_options;
+
+typedef struct {
+  int n_levels;           /* L + 1 */
+  int64_t n[8];           /* n[l] = dimension of V_{h,l}, l = 0..L (n[L] = free dofs) */
+  int32_t n_sub[8];       /* P_l, subdomains per level (n_sub[0] = 1) */
+  int32_t m_max[8];       /* largest eigenvector count of a level-l subdomain */
+  int32_t max_local[8];   /* largest local (Neumann / generating) space on level l */
+  int32_t max_band;       /* largest half-bandwidth of a finest-level local matrix */
+  int32_t eig_iters_max;  /* largest local eigensolver iteration count */
+  int32_t eig_restarts;   /* subdomains re-run with a larger block */
+  double eig_resid_max;   /* largest normwise backward error of a certified pair (FP64) */
+  double t_plan_ms;       /* host planning (index analysis) */
+  double t_local_ms;      /* local matrix extraction + shifted Cholesky + Dirichlet Cholesky */
+  double t_gevp_ms;       /* finest-level GEVPs (eigensolver) */
+  double t_coarse_ms;     /* patch projections, coarse GEVPs, coarse factorisations */
+  double t_setup_ms;      /* whole msdd_setup */
+  double t_solve_ms;      /* last msdd_solve */
+  int32_t pcg_iters;      /* last msdd_solve */
+  double pcg_relres;      /* last msdd_solve: recurrence ||r_m|| / ||r_0|| */
+} msdd_stats_t;
+
+/* Fill *opt with defaults. */
+void msdd_default_options(msdd_options* opt);
+
+/* Create a context on opt->device (opt may be NULL for defaults). */
+int msdd_create(msdd_ctx** out, const msdd_options* opt);
+
+/*
+ * Build the multilevel preconditioner (Sec. 2.2, 2.3, 4.1, 4.2).
+ *
+ *  n, rowptr[n+1] (int64), col[nnz] (int32), val[nnz] (double):
+ *      A on the free dofs, CSR, symmetric positive definite.
+ *  n_elem, k, elem_dofs[n_elem*k] (int32, -1 = eliminated),
+ *  elem_mat[n_elem*k*k] (double, row-major per element):
+ *      the element matrices a_tau (Sec. 3.5); sum_tau a_tau must equal A.
+ *  n_sub, sub_elem_ptr[n_sub+1] (int64), sub_elem[] (int32):
+ *      the finest-level element sets T_{h,L,i} (overlap included).
+ *  sub_dof_ptr[n_sub+1] (int64), sub_dof[] (int32), sub_pou[] (double):
+ *      for each subdomain the free dofs of its elements (the Neumann space
+ *      V-bar_{L,i}, any order) and the partition-of-unity weight chi of each;
+ *      chi must vanish on dofs whose basis function is not supported in the
+ *      closure of the subdomain and the weights must sum to 1 at every dof.
+ *  n_levels (>= 2), parent[]: n_levels-2 concatenated maps; the first n_sub
+ *      entries give each finest subdomain's level-(L-1) subdomain, the next
+ *      P_{L-1} entries map level L-1 to level L-2, and so on (the sets
+ *      J_{l,i} of Sec. 2.2, nonoverlapping).  NULL when n_levels == 2.
+ *  eta: the threshold of the coarse space definition (lambda < eta, strict).
+ *
+ * Errors: MSDD_EINVAL (inputs), MSDD_ENOTSPD (last_error names the subdomain),
+ * MSDD_EEIG, MSDD_EDEVICE, MSDD_ENOMEM.  A failed setup leaves the context
+ * without a preconditioner.
+ */
+int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col,
+               const double* val, int32_t n_elem, int32_t k, const int32_t* elem_dofs,
+               const double* elem_mat, int32_t n_sub, const int64_t* sub_elem_ptr,
+               const int32_t* sub_elem, const int64_t* sub_dof_ptr, const int32_t* sub_dof,
+               const double* sub_pou, int32_t n_levels, const int32_t* parent, double eta);
+
+/*
+ * Solve A x = b by preconditioned CG (Sec. 5) from the initial guess in x.
+ * b[n], x[n]: double, host or device.  Stops when the recurrence residual
+ * satisfies ||r_m||_2 < rtol ||r_0||_2 or after maxit iterations.
+ * iters, relres (may be NULL) receive the iteration count and ||r_m||/||r_0||.
+ * Returns MSDD_ENOCONV if maxit was reached (x holds the last iterate).
+ */
+int msdd_solve(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit,
+               int32_t* iters, double* relres);
+
+/* z = B r: one application of the multilevel additive preconditioner. */
+int msdd_apply(msdd_ctx* c, const double* r, double* z);
+
+/* Setup statistics (sizes, iteration counts, timings). */
+int msdd_stats(const msdd_ctx* c, msdd_stats_t* out);
+
+/*
+ * Introspection of the coarse spaces (for parity checks against a reference).
+ * msdd_get_level_counts: m[i] = number of selected eigenvectors of level-l
+ * subdomain i (l = 1..L), i = 0..P_l-1.
+ * msdd_get_eigs: the selected eigenvalues lambda (ascending) of level-l
+ * subdomain i plus up to n_extra more computed ones (lam must hold
+ * m_i + n_extra doubles); *count receives how many were written.
+ * msdd_get_basis: the coarse basis block chi w of level-l subdomain i.
+ * On the finest level its rows are the subdomain's Neumann-space dofs in
+ * ascending global order (rows = |V-bar_i|); on a coarse level its rows are
+ * the owned coarse dofs (functions of the children, in ascending child
+ * order); column-major, ld = rows.  *rows and *cols receive the shape;
+ * pass basis == NULL to query it.
+ */
+int msdd_get_level_counts(const msdd_ctx* c, int32_t level, int32_t* m);
+int msdd_get_eigs(const msdd_ctx* c, int32_t level, int32_t i, int32_t n_extra, double* lam,
+                  int32_t* count);
+int msdd_get_basis(const msdd_ctx* c, int32_t level, int32_t i, double* basis, int32_t* rows,
+                   int32_t* cols);
+
+/*
+ * Kernel timing (HIP events recorded around each launch on the context's
+ * stream).  msdd_profile(c, 1) enables and resets the counters, 0 disables.
+ * msdd_profile_query returns, for kernel class id (0 <= id < MSDD_NPROF),
+ * the summed duration in ms, the number of launches, and the algorithmic
+ * bytes and flops of those launches (what the method must read, write and
+ * compute; see each kernel's comment).  msdd_profile_name gives the class name
+ * (NULL for an id out of range).
+ */
+#define MSDD_NPROF 16
+int msdd_profile(msdd_ctx* c, int enable);
+int msdd_profile_query(msdd_ctx* c, int id, double* total_ms, int64_t* launches,
+                       double* alg_bytes, double* alg_flops);
+const char* msdd_profile_name(int id);
+
+/* Text of the last error of this context ("" if none). */
+const char* msdd_last_error(const msdd_ctx* c);
+
+/* Release all device memory owned by the context. */
+void msdd_destroy(msdd_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSDD_H_ */

@@ -1,0 +1,255 @@
+"""Thin ctypes binding of libmsdd (include/msdd.h): argument marshalling only.
+
+Arrays may be torch tensors (host or device; their data pointers are passed
+through) or numpy arrays (host).  Every numerical step runs in the HIP library;
+if it is not built this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libmsdd.so")
+
+MSDD_OK = 0
+MSDD_EINVAL = -1
+MSDD_ENOTSPD = -2
+MSDD_EEIG = -3
+MSDD_ENOCONV = -4
+MSDD_EDEVICE = -5
+MSDD_ENOMEM = -6
+MSDD_ESTATE = -7
+MSDD_FP64 = 0
+MSDD_MIXED = 1
+
+_ERRNAMES = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "EEIG", -4: "ENOCONV", -5: "EDEVICE",
+             -6: "ENOMEM", -7: "ESTATE"}
+
+
+class MsddOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("sigma", ctypes.c_double),
+                ("eps_reg_rel", ctypes.c_double), ("nev_max", ctypes.c_int),
+                ("eig_tol", ctypes.c_double), ("eig_maxit", ctypes.c_int),
+                ("block", ctypes.c_int), ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("verbose", ctypes.c_int)]
+
+
+class MsddStats(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int), ("n", ctypes.c_int64 * 8),
+                ("n_sub", ctypes.c_int32 * 8), ("m_max", ctypes.c_int32 * 8),
+                ("max_local", ctypes.c_int32 * 8), ("max_band", ctypes.c_int32),
+                ("eig_iters_max", ctypes.c_int32), ("eig_restarts", ctypes.c_int32),
+                ("eig_resid_max", ctypes.c_double), ("t_plan_ms", ctypes.c_double),
+                ("t_local_ms", ctypes.c_double), ("t_gevp_ms", ctypes.c_double),
+                ("t_coarse_ms", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double), ("pcg_iters", ctypes.c_int32),
+                ("pcg_relres", ctypes.c_double)]
+
+    def as_dict(self):
+        L = self.n_levels
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        for f in ("n", "n_sub", "m_max", "max_local"):
+            d[f] = list(getattr(self, f))[:L]
+        return d
+
+
+EXPORTS = ["msdd_default_options", "msdd_create", "msdd_setup", "msdd_solve", "msdd_apply",
+           "msdd_stats", "msdd_get_level_counts", "msdd_get_eigs", "msdd_get_basis",
+           "msdd_profile", "msdd_profile_query", "msdd_profile_name", "msdd_last_error",
+           "msdd_destroy"]
+MSDD_NPROF = 16
+
+_lib = None
+
+
+class MsddError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"msdd error {_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load libmsdd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libmsdd.so not built ({LIB_PATH}); run paper_2106_06404_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.msdd_default_options.argtypes = [ctypes.POINTER(MsddOptions)]
+    L.msdd_default_options.restype = None
+    L.msdd_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(MsddOptions)]
+    L.msdd_create.restype = ctypes.c_int
+    L.msdd_setup.argtypes = [vp, i64, vp, vp, vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, i32,
+                             vp, f64]
+    L.msdd_setup.restype = ctypes.c_int
+    L.msdd_solve.argtypes = [vp, vp, vp, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]
+    L.msdd_solve.restype = ctypes.c_int
+    L.msdd_apply.argtypes = [vp, vp, vp]
+    L.msdd_apply.restype = ctypes.c_int
+    L.msdd_stats.argtypes = [vp, ctypes.POINTER(MsddStats)]
+    L.msdd_stats.restype = ctypes.c_int
+    L.msdd_get_level_counts.argtypes = [vp, i32, vp]
+    L.msdd_get_level_counts.restype = ctypes.c_int
+    L.msdd_get_eigs.argtypes = [vp, i32, i32, i32, vp, ctypes.POINTER(i32)]
+    L.msdd_get_eigs.restype = ctypes.c_int
+    L.msdd_get_basis.argtypes = [vp, i32, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.msdd_get_basis.restype = ctypes.c_int
+    L.msdd_profile.argtypes = [vp, ctypes.c_int]
+    L.msdd_profile.restype = ctypes.c_int
+    L.msdd_profile_query.argtypes = [vp, ctypes.c_int, ctypes.POINTER(f64), ctypes.POINTER(i64),
+                                     ctypes.POINTER(f64), ctypes.POINTER(f64)]
+    L.msdd_profile_query.restype = ctypes.c_int
+    L.msdd_profile_name.argtypes = [ctypes.c_int]
+    L.msdd_profile_name.restype = ctypes.c_char_p
+    L.msdd_last_error.argtypes = [vp]
+    L.msdd_last_error.restype = ctypes.c_char_p
+    L.msdd_destroy.argtypes = [vp]
+    L.msdd_destroy.restype = None
+    _lib = L
+    return L
+
+
+def default_options(**kw) -> MsddOptions:
+    o = MsddOptions()
+    load().msdd_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(a, dtype):
+    """Data pointer of a contiguous torch tensor or numpy array of the given numpy dtype."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.dtype == dtype and a.flags.c_contiguous, (a.dtype, dtype)
+        return ctypes.c_void_p(a.ctypes.data)
+    import torch
+    tmap = {np.dtype(np.float64): torch.float64, np.dtype(np.int32): torch.int32,
+            np.dtype(np.int64): torch.int64}
+    assert isinstance(a, torch.Tensor) and a.dtype == tmap[np.dtype(dtype)] and a.is_contiguous()
+    return ctypes.c_void_p(a.data_ptr())
+
+
+class Msdd:
+    """One context of the library (create / setup / solve / apply / stats / destroy)."""
+
+    def __init__(self, options: Optional[MsddOptions] = None, **kw):
+        L = load()
+        self._L = L
+        o = options if options is not None else default_options(**kw)
+        h = ctypes.c_void_p()
+        rc = L.msdd_create(ctypes.byref(h), ctypes.byref(o))
+        if rc != MSDD_OK:
+            raise MsddError(rc, "msdd_create failed")
+        self._h = h
+        self._keep = []
+
+    def _check(self, rc, allow=()):
+        if rc != MSDD_OK and rc not in allow:
+            msg = self._L.msdd_last_error(self._h).decode()
+            raise MsddError(rc, msg)
+        return rc
+
+    def setup(self, n, rowptr, col, val, elem_dofs, elem_mat, sub_elem_ptr, sub_elem, sub_dof_ptr,
+              sub_dof, sub_pou, n_levels, parent, eta):
+        n_elem, k = int(elem_dofs.shape[0]), int(elem_dofs.shape[1])
+        n_sub = int(sub_elem_ptr.shape[0]) - 1
+        rc = self._L.msdd_setup(self._h, int(n), _ptr(rowptr, np.int64), _ptr(col, np.int32),
+                                _ptr(val, np.float64), n_elem, k, _ptr(elem_dofs, np.int32),
+                                _ptr(elem_mat, np.float64), n_sub, _ptr(sub_elem_ptr, np.int64),
+                                _ptr(sub_elem, np.int32), _ptr(sub_dof_ptr, np.int64),
+                                _ptr(sub_dof, np.int32), _ptr(sub_pou, np.float64),
+                                int(n_levels), _ptr(parent, np.int32) if parent is not None else None,
+                                float(eta))
+        return self._check(rc)
+
+    def solve(self, b, x, rtol=1e-8, maxit=1000, allow_noconv=False):
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        rc = self._L.msdd_solve(self._h, _ptr(b, np.float64), _ptr(x, np.float64), float(rtol),
+                                int(maxit), ctypes.byref(it), ctypes.byref(rel))
+        self._check(rc, allow=(MSDD_ENOCONV,) if allow_noconv else ())
+        return int(it.value), float(rel.value), rc
+
+    def apply(self, r, z):
+        return self._check(self._L.msdd_apply(self._h, _ptr(r, np.float64), _ptr(z, np.float64)))
+
+    def stats(self) -> dict:
+        s = MsddStats()
+        self._check(self._L.msdd_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def level_counts(self, level: int, nsub: int) -> np.ndarray:
+        m = np.zeros(nsub, np.int32)
+        self._check(self._L.msdd_get_level_counts(self._h, level, ctypes.c_void_p(m.ctypes.data)))
+        return m
+
+    def eigs(self, level: int, i: int, n_extra: int = 0) -> np.ndarray:
+        buf = np.zeros(1024, np.float64)
+        cnt = ctypes.c_int32()
+        self._check(self._L.msdd_get_eigs(self._h, level, i, n_extra,
+                                          ctypes.c_void_p(buf.ctypes.data), ctypes.byref(cnt)))
+        return buf[:cnt.value].copy()
+
+    def basis(self, level: int, i: int) -> np.ndarray:
+        r, c = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._L.msdd_get_basis(self._h, level, i, None, ctypes.byref(r), ctypes.byref(c)))
+        out = np.zeros((c.value, r.value), np.float64)  # column-major rows x cols
+        if r.value * c.value:
+            self._check(self._L.msdd_get_basis(self._h, level, i, ctypes.c_void_p(out.ctypes.data),
+                                               ctypes.byref(r), ctypes.byref(c)))
+        return out.T.copy()
+
+    def profile(self, enable=True):
+        return self._check(self._L.msdd_profile(self._h, 1 if enable else 0))
+
+    def profile_query(self) -> dict:
+        """{kernel class: (total_ms, launches, algorithmic bytes, algorithmic flops)}"""
+        out = {}
+        for i in range(MSDD_NPROF):
+            ms, n, by, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+            self._check(self._L.msdd_profile_query(self._h, i, ctypes.byref(ms), ctypes.byref(n),
+                                                   ctypes.byref(by), ctypes.byref(fl)))
+            out[self._L.msdd_profile_name(i).decode()] = (ms.value, n.value, by.value, fl.value)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.msdd_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def problem_arrays(prob, device=None):
+    """The problem's arrays as torch tensors on `device` (or numpy if device is None)."""
+    rowptr, col, val = prob.csr_arrays()
+    par = np.concatenate(prob.parents).astype(np.int32) if prob.parents else None
+    arrs = dict(n=prob.n, rowptr=rowptr, col=col, val=val,
+                elem_dofs=np.ascontiguousarray(prob.elem_dofs, np.int32),
+                elem_mat=np.ascontiguousarray(prob.elem_mat.reshape(prob.n_elem, -1), np.float64),
+                sub_elem_ptr=np.ascontiguousarray(prob.sub_elem_ptr, np.int64),
+                sub_elem=np.ascontiguousarray(prob.sub_elem, np.int32),
+                sub_dof_ptr=np.ascontiguousarray(prob.sub_dof_ptr, np.int64),
+                sub_dof=np.ascontiguousarray(prob.sub_dof, np.int32),
+                sub_pou=np.ascontiguousarray(prob.sub_pou, np.float64),
+                n_levels=prob.n_levels, parent=par, eta=prob.eta)
+    if device is None:
+        return arrs
+    import torch
+    out = {}
+    for key, v in arrs.items():
+        out[key] = torch.from_numpy(v).to(device) if isinstance(v, np.ndarray) else v
+    return out

@@ -1,0 +1,345 @@
+// Finest-level local matrices in lower-band storage and their factorisation.
+//
+// Layout (per subdomain, half-bandwidth b, order n):
+//   column-major lower band  Bc[j*(b+1) + d] = A(j+d, j),  0 <= d <= b
+//   row layout of a factor   Lr[j*(b+1) + d] = L(j, j-d)
+// Padding entries (j+d >= n, or j-d < 0) are zero.
+//
+// Paper: the local Neumann matrix abar_{l,i} is the sum of the element
+// matrices a_tau over the subdomain's elements (Sec. 3.5); the Dirichlet
+// matrix is A_i = R_i A R_i^T (Sec. 2.1); the shifted pencil matrix
+// abar + sigma*b, b = D abar D (Sec. 3.4 lemma, b^1 of Sec. 3.5) is SPD.
+#include "common.h"
+#include "kernels.h"
+#include "trsv.h"
+
+// ---------------------------------------------------------------------------
+// abar_i = sum_{tau in T_i} a_tau, gathered row by row: the thread that owns
+// local row r adds every element contribution (r, c), c <= r, in the fixed
+// order of r's incidence list, so the result is deterministic without atomics.
+// The same pass fills the symmetric ELL copy (full rows) used by b = D abar D.
+// ---------------------------------------------------------------------------
+__global__ void k_neumann_assemble(i64 total_rows, const i32* __restrict__ row_sub,
+                                   const i64* __restrict__ voff, const i32* __restrict__ bw,
+                                   const i64* __restrict__ boff, const i64* __restrict__ inc_ptr,
+                                   const i32* __restrict__ inc_slot, const i32* __restrict__ inc_a,
+                                   const i32* __restrict__ slot_elem, const i32* __restrict__ slot_loc,
+                                   int k, const double* __restrict__ elem_mat,
+                                   double* __restrict__ band, int ell_w,
+                                   const i32* __restrict__ ell_col, double* __restrict__ ell_val,
+                                   int* __restrict__ status) {
+  i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total_rows) return;
+  const int i = row_sub[g];
+  const int r = (int)(g - voff[i]);
+  const int b = bw[i];
+  double* B = band + boff[i];
+  const i32* ec = ell_col + g * ell_w;
+  double* ev = ell_val + g * ell_w;
+  for (i64 q = inc_ptr[g]; q < inc_ptr[g + 1]; ++q) {
+    const i64 slot = inc_slot[q];
+    const int a = inc_a[q];
+    const int e = slot_elem[slot];
+    const double* Krow = elem_mat + (i64)e * k * k + (i64)a * k;
+    const i32* loc = slot_loc + slot * k;
+    for (int bb = 0; bb < k; ++bb) {
+      const int c = loc[bb];
+      if (c < 0) continue;
+      const double v = Krow[bb];
+      if (!(v == v)) status[i] = ST_BADINPUT;
+      if (c <= r) {
+        if (r - c > b) {
+          status[i] = ST_BADINPUT;
+        } else {
+          B[(i64)c * (b + 1) + (r - c)] += v;
+        }
+      }
+      int t = 0;
+      while (t < ell_w && ec[t] != c) ++t;
+      if (t < ell_w) ev[t] += v; else status[i] = ST_BADINPUT;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A_i = R_i A R_i^T from the global CSR matrix: the thread of Dirichlet row r
+// walks CSR row dglob[r] and finds each column among the subdomain's sorted
+// Dirichlet dofs by binary search.
+// ---------------------------------------------------------------------------
+__global__ void k_dirichlet_extract(i64 total_rows, const i32* __restrict__ drow_sub,
+                                    const i64* __restrict__ doff, const i32* __restrict__ nd,
+                                    const i32* __restrict__ bd, const i64* __restrict__ dboff,
+                                    const i32* __restrict__ dglob, const i64* __restrict__ rowptr,
+                                    const i32* __restrict__ col, const double* __restrict__ val,
+                                    double* __restrict__ band, int* __restrict__ status) {
+  i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total_rows) return;
+  const int i = drow_sub[g];
+  const int r = (int)(g - doff[i]);
+  const int b = bd[i];
+  const i32* list = dglob + doff[i];
+  const int len = nd[i];
+  double* B = band + dboff[i];
+  const int p = dglob[g];
+  for (i64 e = rowptr[p]; e < rowptr[p + 1]; ++e) {
+    const int q = col[e];
+    int lo = 0, hi = len - 1, c = -1;
+    while (lo <= hi) {
+      int mid = (lo + hi) >> 1;
+      int v = list[mid];
+      if (v == q) { c = mid; break; }
+      if (v < q) lo = mid + 1; else hi = mid - 1;
+    }
+    if (c < 0 || c > r) continue;
+    const double v = val[e];
+    if (!(v == v)) status[i] = ST_BADINPUT;
+    if (r - c > b) status[i] = ST_BADINPUT;
+    else B[(i64)c * (b + 1) + (r - c)] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Band Cholesky with a sliding (b+1) x (b+1) window in LDS, one workgroup per
+// subdomain.  Column c of the active window lives in slot c mod (b+1).  The
+// matrix factorised is S = A + sigma * D A D (D = diag(dv)), formed while each
+// column enters the window; sigma = 0 / dv = nullptr factorises A itself.
+// Writes L in both column (Lc) and row (Lr) band layouts.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_band_cholesky(const i32* __restrict__ subs, const i32* __restrict__ n_arr,
+                                const i32* __restrict__ b_arr, const i64* __restrict__ src_off,
+                                const double* __restrict__ src, const i64* __restrict__ dv_off,
+                                const double* __restrict__ dv, double sigma,
+                                const i64* __restrict__ dst_off, T* __restrict__ Lc,
+                                T* __restrict__ Lr, int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = subs ? subs[blockIdx.x] : blockIdx.x;
+  const int n = n_arr[i];
+  const int b = b_arr[i];
+  const int w = b + 1;
+  T* W = reinterpret_cast<T*>(smem_raw);  // w*w
+  T* lcol = W + (size_t)w * w;            // w
+  __shared__ int fail;
+  const double* A = src + src_off[i];
+  const double* d = dv ? dv + dv_off[i] : nullptr;
+  T* Lci = Lc + dst_off[i];
+  T* Lri = Lr + dst_off[i];
+  if (threadIdx.x == 0) fail = 0;
+  auto load_col = [&](int c, int slot) {
+    for (int t = threadIdx.x; t < w; t += blockDim.x) {
+      T v = 0;
+      if (c + t < n) {
+        double a = A[(i64)c * w + t];
+        if (d) a *= 1.0 + sigma * d[c + t] * d[c];
+        v = (T)a;
+      }
+      W[slot * w + t] = v;
+    }
+  };
+  for (int c = 0; c < w && c < n; ++c) load_col(c, c);
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const int slot = j % w;
+    const T ajj = W[slot * w];
+    if (!(ajj > (T)0)) {
+      if (threadIdx.x == 0) { fail = 1; status[i] = ST_NOTSPD; }
+      break;
+    }
+    const T ljj = sqrt(ajj);
+    for (int t = threadIdx.x; t < w; t += blockDim.x) {
+      T l = 0;
+      if (j + t < n) {
+        l = (t == 0) ? ljj : W[slot * w + t] / ljj;
+        Lri[(i64)(j + t) * w + t] = l;
+      }
+      lcol[t] = l;
+      Lci[(i64)j * w + t] = l;
+    }
+    __syncthreads();
+    // trailing update of the window: A(j+p, j+q) -= L(j+p, j) L(j+q, j), 1 <= q <= p <= b
+    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
+      const int p = t / b + 1, q = t % b + 1;
+      if (q <= p && j + p < n) W[((j + q) % w) * w + (p - q)] -= lcol[p] * lcol[q];
+    }
+    if (j + w < n) {
+      for (int t = threadIdx.x; t < w; t += blockDim.x) {
+        T v = 0;
+        const int c = j + w;
+        if (c + t < n) {
+          double a = A[(i64)c * w + t];
+          if (d) a *= 1.0 + sigma * d[c + t] * d[c];
+          v = (T)a;
+        }
+        W[slot * w + t] = v;
+      }
+    }
+    __syncthreads();
+  }
+  (void)fail;
+}
+
+// ---------------------------------------------------------------------------
+// Same factorisation for half-bandwidths whose window does not fit in LDS:
+// S is first written to Lc (lower band) and factorised in place, right-looking,
+// with the trailing b x b triangle updated in global memory (L2 resident).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_band_cholesky_global(const i32* __restrict__ subs, const i32* __restrict__ n_arr,
+                                       const i32* __restrict__ b_arr,
+                                       const i64* __restrict__ src_off,
+                                       const double* __restrict__ src,
+                                       const i64* __restrict__ dv_off,
+                                       const double* __restrict__ dv, double sigma,
+                                       const i64* __restrict__ dst_off, T* __restrict__ Lc,
+                                       T* __restrict__ Lr, int* __restrict__ status) {
+  const int i = subs ? subs[blockIdx.x] : blockIdx.x;
+  const int n = n_arr[i];
+  const int b = b_arr[i];
+  const int w = b + 1;
+  const double* A = src + src_off[i];
+  const double* d = dv ? dv + dv_off[i] : nullptr;
+  T* Li = Lc + dst_off[i];
+  T* Ri = Lr + dst_off[i];
+  for (i64 t = threadIdx.x; t < (i64)n * w; t += blockDim.x) {
+    const int c = (int)(t / w), dd = (int)(t % w);
+    double a = 0.0;
+    if (c + dd < n) {
+      a = A[t];
+      if (d) a *= 1.0 + sigma * d[c + dd] * d[c];
+    }
+    Li[t] = (T)a;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const T ajj = Li[(i64)j * w];
+    if (!(ajj > (T)0)) {
+      if (threadIdx.x == 0) status[i] = ST_NOTSPD;
+      return;
+    }
+    const T ljj = sqrt(ajj);
+    __syncthreads();
+    for (int t = threadIdx.x; t < w; t += blockDim.x)
+      if (j + t < n) Li[(i64)j * w + t] = (t == 0) ? ljj : Li[(i64)j * w + t] / ljj;
+    __syncthreads();
+    const T* lj = Li + (i64)j * w;
+    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
+      const int p = t / b + 1, q = t % b + 1;
+      if (q <= p && j + p < n) Li[(i64)(j + q) * w + (p - q)] -= lj[p] * lj[q];
+    }
+    __syncthreads();
+  }
+  for (i64 t = threadIdx.x; t < (i64)n * w; t += blockDim.x) {
+    const int c = (int)(t / w), dd = (int)(t % w);
+    if (c + dd < n) Ri[(i64)(c + dd) * w + dd] = Li[t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Y = (L L^T)^{-1} W for K right-hand sides (column-major n x K, ld n): one
+// wavefront per right-hand side, WV wavefronts per workgroup sharing the
+// factor through the cache; each wavefront keeps its column in LDS.
+// ---------------------------------------------------------------------------
+template <typename T, typename V>
+__global__ void __launch_bounds__(256) k_band_solve_multi(const i32* __restrict__ subs, const i32* __restrict__ n_arr,
+                                   const i32* __restrict__ b_arr, const i64* __restrict__ l_off,
+                                   const T* __restrict__ Lc, const T* __restrict__ Lr,
+                                   const i64* __restrict__ v_off, int K, int nmax,
+                                   const V* __restrict__ Win, V* __restrict__ Yout,
+                                   const int* __restrict__ active) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = subs ? subs[blockIdx.x] : blockIdx.x;
+  if (active && active[i] != ST_RUNNING) return;
+  const int n = n_arr[i];
+  const int b = b_arr[i];
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.y * (blockDim.x >> 6) + wv;
+  const bool has = c < K;
+  V* v = reinterpret_cast<V*>(smem_raw) + (size_t)wv * nmax;
+  const V* Wi = Win + v_off[i] + (i64)(has ? c : 0) * n;
+  V* Yi = Yout + v_off[i] + (i64)(has ? c : 0) * n;
+  for (int q = lane; q < n; q += 64) v[q] = has ? Wi[q] : (V)0;
+  __syncthreads();
+  wave_trsv_lower<T, V>(n, b, Lr + l_off[i], v);
+  wave_trsv_upper<T, V>(n, b, Lc + l_off[i], v);
+  if (has)
+    for (int q = lane; q < n; q += 64) Yi[q] = v[q];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_neumann_assemble(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
+                             const i32* bw, const i64* boff, const i64* inc_ptr,
+                             const i32* inc_slot, const i32* inc_a, const i32* slot_elem,
+                             const i32* slot_loc, int k, const double* elem_mat, double* band,
+                             int ell_w, const i32* ell_col, double* ell_val, int* status) {
+  if (total_rows == 0) return;
+  dim3 g((unsigned)((total_rows + MSDD_WG - 1) / MSDD_WG));
+  hipLaunchKernelGGL(k_neumann_assemble, g, dim3(MSDD_WG), 0, s, total_rows, row_sub, voff, bw,
+                     boff, inc_ptr, inc_slot, inc_a, slot_elem, slot_loc, k, elem_mat, band,
+                     ell_w, ell_col, ell_val, status);
+}
+
+void launch_dirichlet_extract(hipStream_t s, i64 total_rows, const i32* drow_sub,
+                              const i64* doff, const i32* nd, const i32* bd, const i64* dboff,
+                              const i32* dglob, const i64* rowptr, const i32* col,
+                              const double* val, double* band, int* status) {
+  if (total_rows == 0) return;
+  dim3 g((unsigned)((total_rows + MSDD_WG - 1) / MSDD_WG));
+  hipLaunchKernelGGL(k_dirichlet_extract, g, dim3(MSDD_WG), 0, s, total_rows, drow_sub, doff,
+                     nd, bd, dboff, dglob, rowptr, col, val, band, status);
+}
+
+template <typename T>
+void launch_band_cholesky(hipStream_t s, int nsubs, const i32* subs, int bmax, const i32* n_arr,
+                          const i32* b_arr, const i64* src_off, const double* src,
+                          const i64* dv_off, const double* dv, double sigma, const i64* dst_off,
+                          T* Lc, T* Lr, int* status) {
+  if (nsubs == 0) return;
+  size_t w = (size_t)bmax + 1;
+  size_t lds = (w * w + w) * sizeof(T);
+  if (lds <= 64 * 1024) {
+    hipLaunchKernelGGL(k_band_cholesky<T>, dim3(nsubs), dim3(MSDD_WG), lds, s, subs, n_arr,
+                       b_arr, src_off, src, dv_off, dv, sigma, dst_off, Lc, Lr, status);
+  } else {
+    hipLaunchKernelGGL(k_band_cholesky_global<T>, dim3(nsubs), dim3(MSDD_WG), 0, s, subs, n_arr,
+                       b_arr, src_off, src, dv_off, dv, sigma, dst_off, Lc, Lr, status);
+  }
+}
+template void launch_band_cholesky<double>(hipStream_t, int, const i32*, int, const i32*,
+                                           const i32*, const i64*, const double*, const i64*,
+                                           const double*, double, const i64*, double*, double*,
+                                           int*);
+template void launch_band_cholesky<float>(hipStream_t, int, const i32*, int, const i32*,
+                                          const i32*, const i64*, const double*, const i64*,
+                                          const double*, double, const i64*, float*, float*,
+                                          int*);
+
+size_t band_cholesky_lds(int bmax, int elem_size) {
+  size_t w = (size_t)bmax + 1;
+  return (w * w + w) * elem_size;
+}
+
+template <typename T, typename V>
+void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax,
+                             const i32* n_arr, const i32* b_arr, const i64* l_off, const T* Lc,
+                             const T* Lr, const i64* v_off, int K, const V* W, V* Y,
+                             const int* active) {
+  if (nsubs == 0) return;
+  const int WV = K < 4 ? K : 4;
+  const size_t lds = (size_t)WV * nmax * sizeof(V);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_band_solve_multi<T, V>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_band_solve_multi<T, V>), dim3(nsubs, (K + WV - 1) / WV), dim3(64 * WV),
+                     lds, s, subs, n_arr, b_arr, l_off, Lc, Lr, v_off, K, nmax, W, Y, active);
+}
+template void launch_band_solve_multi<double, double>(hipStream_t, int, const i32*, int,
+                                                      const i32*, const i32*, const i64*,
+                                                      const double*, const double*, const i64*,
+                                                      int, const double*, double*, const int*);
+template void launch_band_solve_multi<float, float>(hipStream_t, int, const i32*, int,
+                                                    const i32*, const i32*, const i64*,
+                                                    const float*, const float*, const i64*, int,
+                                                    const float*, float*, const int*);

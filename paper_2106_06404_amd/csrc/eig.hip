@@ -1,0 +1,512 @@
+// Finest-level local generalized eigenproblems (Sec. 2.3 "theGEVP", b^1 of
+// Sec. 3.5), batched over subdomains.
+//
+// abar x = lambda b x,  b = D abar D  (D = partition-of-unity weights).
+// The lemma of Sec. 3.4 (ker abar cap ker b = {0}) makes S = abar + sigma*b SPD
+// for every sigma > 0, and the wanted smallest lambda are the largest
+//   nu = 1/(lambda + sigma)  of  b x = nu S x.
+// Block subspace iteration with the exact factor of S (shift-invert) and a
+// Rayleigh-Ritz step per iteration:
+//   Y = S^{-1} (B X);  Z = B Y;  G_S = Y^T (B X) (= Y^T S Y);  G_B = Y^T Z;
+//   G_B c = nu G_S c;  X <- Y C,  BX <- Z C,  SX <- (B X_old) C.
+// Convergence: the normwise backward error ||BX_j - nu_j SX_j|| / (nu_j ||S|| ||X_j||)
+// is <= tol for the m pairs with lambda < eta plus the next one (which certifies
+// the count m); as a safety net a pair also counts as converged when its backward
+// error is <= 1e-8 and its Ritz value no longer moves (relative change <= 1e-14).
+#include "common.h"
+#include "jacobi.h"
+#include "kernels.h"
+
+__device__ inline double hash_uniform(unsigned long long x) {
+  // splitmix64 finaliser -> uniform in [-1, 1)
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// deterministic start block (rows with zero weight get zero: they lie in ker b)
+template <typename V>
+__global__ void k_eig_init(i64 total_rows, const i32* __restrict__ row_sub,
+                           const i64* __restrict__ voff, const i32* __restrict__ nb,
+                           const i64* __restrict__ kvoff, int K, const double* __restrict__ dv,
+                           V* __restrict__ X, unsigned long long seed) {
+  i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total_rows) return;
+  const int i = row_sub[g];
+  const int r = (int)(g - voff[i]);
+  const int n = nb[i];
+  V* Xi = X + kvoff[i];
+  const bool z = dv[g] == 0.0;
+  for (int c = 0; c < K; ++c) {
+    unsigned long long key = seed ^ ((unsigned long long)i << 40) ^ ((unsigned long long)r << 12) ^
+                             (unsigned long long)c;
+    Xi[r + (i64)c * n] = z ? (V)0 : (V)hash_uniform(key);
+  }
+}
+
+// Z = D abar D Y  with the symmetric ELL copy of abar (full rows)
+template <typename V>
+__global__ void k_bapply_ell(i64 total_rows, const i32* __restrict__ row_sub,
+                             const i64* __restrict__ voff, const i32* __restrict__ nb,
+                             const i64* __restrict__ kvoff, int K, const double* __restrict__ dv,
+                             int ell_w, const i32* __restrict__ ell_col,
+                             const double* __restrict__ ell_val, const V* __restrict__ Y,
+                             V* __restrict__ Z, const int* __restrict__ active) {
+  i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total_rows) return;
+  const int i = row_sub[g];
+  if (active && active[i] != ST_RUNNING) return;
+  const int r = (int)(g - voff[i]);
+  const int n = nb[i];
+  const V* Yi = Y + kvoff[i];
+  V* Zi = Z + kvoff[i];
+  const double* d = dv + voff[i];
+  const double dr = d[r];
+  if (dr == 0.0) {
+    for (int c = 0; c < K; ++c) Zi[r + (i64)c * n] = 0;
+    return;
+  }
+  const i32* ec = ell_col + g * ell_w;
+  const double* ev = ell_val + g * ell_w;
+  constexpr int CB = 8;
+  for (int c0 = 0; c0 < K; c0 += CB) {
+    V acc[CB];
+    for (int u = 0; u < CB; ++u) acc[u] = 0;
+    for (int t = 0; t < ell_w; ++t) {
+      const int cc = ec[t];
+      if (cc < 0) break;
+      const V a = (V)(ev[t] * d[cc]);
+      if (a == (V)0) continue;
+      for (int u = 0; u < CB; ++u)
+        if (c0 + u < K) acc[u] += a * Yi[cc + (i64)(c0 + u) * n];
+    }
+    for (int u = 0; u < CB; ++u)
+      if (c0 + u < K) Zi[r + (i64)(c0 + u) * n] = (V)(dr * acc[u]);
+  }
+}
+
+// ||S||_inf estimate per subdomain: max row sum of |abar| (1 + sigma d_r d_c)
+__global__ void k_row_norm(const i64* __restrict__ voff, int ell_w, const i32* __restrict__ ell_col,
+                           const double* __restrict__ ell_val, const double* __restrict__ dv,
+                           double sigma, double* __restrict__ normS) {
+  const int i = blockIdx.x;
+  const i64 r0 = voff[i], r1 = voff[i + 1];
+  double mx = 0.0;
+  for (i64 g = r0 + threadIdx.x; g < r1; g += blockDim.x) {
+    double s = 0.0;
+    const double dr = dv[g];
+    for (int t = 0; t < ell_w; ++t) {
+      const int c = ell_col[g * ell_w + t];
+      if (c < 0) break;
+      s += fabs(ell_val[g * ell_w + t]) * (1.0 + sigma * dr * dv[r0 + c]);
+    }
+    mx = fmax(mx, s);
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  __shared__ double sh[16];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, sh[w]);
+    normS[i] = m;
+  }
+}
+
+// G_S = Y^T W, G_B = Y^T Z (K x K each, double), one workgroup per subdomain
+template <typename V, int TR>
+__global__ void k_gram(const i32* __restrict__ nb, const i64* __restrict__ kvoff, int K,
+                       const V* __restrict__ Y, const V* __restrict__ W, const V* __restrict__ Z,
+                       double* __restrict__ GS, double* __restrict__ GB,
+                       const int* __restrict__ active) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = blockIdx.x;
+  if (active && active[i] != ST_RUNNING) return;
+  const int n = nb[i];
+  V* ty = reinterpret_cast<V*>(smem_raw);
+  V* tw = ty + TR * K;
+  V* tz = tw + TR * K;
+  const V* Yi = Y + kvoff[i];
+  const V* Wi = W + kvoff[i];
+  const V* Zi = Z + kvoff[i];
+  const int KK = K * K;
+  constexpr int MAXP = 16;  // K <= 64 -> K*K/256 <= 16 pairs per thread
+  double as[MAXP], ab[MAXP];
+  for (int u = 0; u < MAXP; ++u) as[u] = ab[u] = 0.0;
+  for (int r0 = 0; r0 < n; r0 += TR) {
+    const int rn = min(TR, n - r0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < TR * K; t += blockDim.x) {
+      const int c = t / TR, rr = t % TR;
+      V y = 0, w = 0, z = 0;
+      if (rr < rn) {
+        const i64 idx = r0 + rr + (i64)c * n;
+        y = Yi[idx];
+        w = Wi[idx];
+        z = Zi[idx];
+      }
+      ty[rr * K + c] = y;
+      tw[rr * K + c] = w;
+      tz[rr * K + c] = z;
+    }
+    __syncthreads();
+    int u = 0;
+    for (int t = threadIdx.x; t < KK; t += blockDim.x, ++u) {
+      const int a = t / K, bcol = t % K;
+      double s1 = 0, s2 = 0;
+      for (int rr = 0; rr < rn; ++rr) {
+        const double y = (double)ty[rr * K + a];
+        s1 += y * (double)tw[rr * K + bcol];
+        s2 += y * (double)tz[rr * K + bcol];
+      }
+      as[u] += s1;
+      ab[u] += s2;
+    }
+  }
+  int u = 0;
+  for (int t = threadIdx.x; t < KK; t += blockDim.x, ++u) {
+    GS[(i64)i * KK + t] = as[u];
+    GB[(i64)i * KK + t] = ab[u];
+  }
+}
+
+// Rayleigh-Ritz: G_B c = nu G_S c  ->  C (K x K, row-major), nu (descending).
+// Robust to a rank-deficient G_S: G_S is diagonalised (Jacobi) and directions with
+// eigenvalue <= 1e-13 * max are dropped (they get nu = 0 and a zero column).
+__global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
+                                const double* __restrict__ GB, double* __restrict__ Cout,
+                                double* __restrict__ nu_out, const int* __restrict__ active) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = blockIdx.x;
+  if (active && active[i] != ST_RUNNING) return;
+  const int KK = K * K;
+  double* S = reinterpret_cast<double*>(smem_raw);  // K*K
+  double* U = S + KK;                                // K*K
+  double* M = U + KK;                                // K*K
+  double* sc = M + KK;                               // K  (diagonal scaling)
+  double* ev = sc + K;                               // K
+  int* ord = reinterpret_cast<int*>(ev + K);         // K
+  __shared__ int pp[64], pq[64], cnt;
+  __shared__ double pc[64], ps[64], smax;
+  JacobiScratch<double> js{pp, pq, pc, ps, &cnt};
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double* gs = GS + (i64)i * KK;
+  const double* gb = GB + (i64)i * KK;
+  for (int t = tid; t < K; t += nt) {
+    const double dgs = gs[t * K + t];
+    sc[t] = dgs > 0 ? 1.0 / sqrt(dgs) : 0.0;
+  }
+  __syncthreads();
+  for (int t = tid; t < KK; t += nt) {
+    const int a = t / K, b = t % K;
+    S[t] = 0.5 * (gs[a * K + b] + gs[b * K + a]) * sc[a] * sc[b];
+  }
+  __syncthreads();
+  jacobi_block<double>(K, S, U, js, 40, 1e-15, 0.0);
+  if (tid == 0) {
+    double m = 0;
+    for (int a = 0; a < K; ++a) m = fmax(m, S[a * K + a]);
+    smax = m;
+  }
+  __syncthreads();
+  // T = diag(sc) U diag(s^{-1/2})  stored in U (column a scaled)
+  for (int t = tid; t < KK; t += nt) {
+    const int r = t / K, a = t % K;
+    const double s = S[a * K + a];
+    const double f = (s > 1e-13 * smax) ? 1.0 / sqrt(s) : 0.0;
+    U[t] = sc[r] * U[t] * f;
+  }
+  __syncthreads();
+  // M = T^T GB T: first S <- GB_sym T (K x K), then M = T^T S
+  for (int t = tid; t < KK; t += nt) {
+    const int r = t / K, a = t % K;
+    double acc = 0;
+    for (int q = 0; q < K; ++q) acc += 0.5 * (gb[r * K + q] + gb[q * K + r]) * U[q * K + a];
+    S[t] = acc;
+  }
+  __syncthreads();
+  for (int t = tid; t < KK; t += nt) {
+    const int a = t / K, b = t % K;
+    double acc = 0;
+    for (int q = 0; q < K; ++q) acc += U[q * K + a] * S[q * K + b];
+    M[t] = acc;
+  }
+  __syncthreads();
+  for (int t = tid; t < KK; t += nt) {
+    const int a = t / K, b = t % K;
+    if (a < b) {
+      const double v = 0.5 * (M[a * K + b] + M[b * K + a]);
+      M[a * K + b] = v;
+      M[b * K + a] = v;
+    }
+  }
+  __syncthreads();
+  jacobi_block<double>(K, M, S, js, 40, 1e-15, 0.0);  // S <- eigenvectors Q
+  for (int t = tid; t < K; t += nt) ev[t] = M[t * K + t];
+  __syncthreads();
+  if (tid == 0) {  // sort descending (insertion sort, K <= 64)
+    for (int a = 0; a < K; ++a) ord[a] = a;
+    for (int a = 1; a < K; ++a) {
+      int v = ord[a];
+      int b = a - 1;
+      while (b >= 0 && ev[ord[b]] < ev[v]) {
+        ord[b + 1] = ord[b];
+        --b;
+      }
+      ord[b + 1] = v;
+    }
+  }
+  __syncthreads();
+  // C = T Q (columns reordered)
+  double* C = Cout + (i64)i * KK;
+  for (int t = tid; t < KK; t += nt) {
+    const int r = t / K, a = t % K;
+    const int src = ord[a];
+    double acc = 0;
+    for (int q = 0; q < K; ++q) acc += U[r * K + q] * S[q * K + src];
+    C[t] = acc;
+  }
+  for (int t = tid; t < K; t += nt) nu_out[(i64)i * K + t] = fmax(ev[ord[t]], 0.0);
+}
+
+// X = Y C, BX = Z C, SX = BX_old C (in place on BX), residual norms, convergence
+// logic.  One workgroup per subdomain; K divides the workgroup size.
+template <typename V, int TR>
+__global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__ kvoff, int K,
+                             const double* __restrict__ Cm, const double* __restrict__ nu,
+                             const V* __restrict__ Y, const V* __restrict__ Z,
+                             V* __restrict__ X, V* __restrict__ BX, V* __restrict__ SX,
+                             double sigma, double eta, int nev_max, double tol, int maxit,
+                             int* __restrict__ status, int* __restrict__ iters,
+                             int* __restrict__ mcount, double* __restrict__ lam_out,
+                             double* __restrict__ res_out, int Kmax_allowed,
+                             const i32* __restrict__ rankb, const double* __restrict__ normS,
+                             double* __restrict__ nu_prev) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = blockIdx.x;
+  if (status[i] != ST_RUNNING) return;
+  const int n = nb[i];
+  const int KK = K * K;
+  double* C = reinterpret_cast<double*>(smem_raw);  // KK
+  V* ty = reinterpret_cast<V*>(C + KK);             // TR*K
+  V* tz = ty + TR * K;
+  V* tb = tz + TR * K;
+  __shared__ double red_r[MSDD_WG], red_s[MSDD_WG], sh_res[64], sh_lam[64], sh_stag[64];
+  const int tid = threadIdx.x;
+  for (int t = tid; t < KK; t += blockDim.x) C[t] = Cm[(i64)i * KK + t];
+  const int c = tid % K;
+  const int lanes = blockDim.x / K;
+  const int rl = tid / K;
+  const double nuc = nu[(i64)i * K + c];
+  double accr = 0, accs = 0;  // residual^2, ||x||^2
+  const V* Yi = Y + kvoff[i];
+  const V* Zi = Z + kvoff[i];
+  V* Xi = X + kvoff[i];
+  V* Bi = BX + kvoff[i];
+  V* Si = SX + kvoff[i];
+  for (int r0 = 0; r0 < n; r0 += TR) {
+    const int rn = min(TR, n - r0);
+    __syncthreads();
+    for (int t = tid; t < TR * K; t += blockDim.x) {
+      const int cc = t / TR, rr = t % TR;
+      V y = 0, z = 0, bb = 0;
+      if (rr < rn) {
+        const i64 idx = r0 + rr + (i64)cc * n;
+        y = Yi[idx];
+        z = Zi[idx];
+        bb = Bi[idx];
+      }
+      ty[rr * K + cc] = y;
+      tz[rr * K + cc] = z;
+      tb[rr * K + cc] = bb;
+    }
+    __syncthreads();
+    if (rl < lanes) {
+      for (int rr = rl; rr < rn; rr += lanes) {
+        double x = 0, bx = 0, sx = 0;
+        for (int a = 0; a < K; ++a) {
+          const double ca = C[a * K + c];
+          x += (double)ty[rr * K + a] * ca;
+          bx += (double)tz[rr * K + a] * ca;
+          sx += (double)tb[rr * K + a] * ca;
+        }
+        const i64 idx = r0 + rr + (i64)c * n;
+        Xi[idx] = (V)x;
+        Bi[idx] = (V)bx;
+        Si[idx] = (V)sx;
+        const double rres = bx - nuc * sx;
+        accr += rres * rres;
+        accs += x * x;
+      }
+    }
+  }
+  red_r[tid] = accr;
+  red_s[tid] = accs;
+  __syncthreads();
+  if (tid < K) {
+    double sr = 0, ss = 0;
+    for (int l = 0; l < lanes; ++l) {
+      sr += red_r[l * K + tid];
+      ss += red_s[l * K + tid];
+    }
+    const double nv = nu[(i64)i * K + tid];
+    const double rel = (nv > 0 && ss > 0) ? sqrt(sr) / (nv * normS[i] * sqrt(ss)) : 0.0;
+    const double lv = nv > 0 ? 1.0 / nv - sigma : INFINITY;
+    const double np = nu_prev[(i64)i * K + tid];
+    res_out[(i64)i * K + tid] = rel;
+    lam_out[(i64)i * K + tid] = lv;
+    nu_prev[(i64)i * K + tid] = nv;
+    sh_res[tid] = rel;
+    sh_lam[tid] = lv;
+    sh_stag[tid] = (rel <= 1e-8 && fabs(nv - np) <= 1e-14 * fabs(nv)) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int it = iters[i] + 1;
+    iters[i] = it;
+    const int kb = min(K, rankb[i]);  // usable columns
+    int m = 0;
+    while (m < kb && sh_lam[m] < eta) ++m;
+    if (nev_max > 0 && m > nev_max) m = nev_max;
+    const int guard = 2;
+    bool grow = (m + 1 + guard > kb) && (kb < rankb[i]) && (K < Kmax_allowed);
+    int need = min(m + 1, kb);
+    bool ok = true;
+    for (int a = 0; a < need; ++a) ok = ok && (sh_res[a] <= tol || sh_stag[a] > 0.0);
+    mcount[i] = m;
+    if (grow) status[i] = ST_GROW;
+    else if (ok) status[i] = ST_DONE;
+    else if (it >= maxit) status[i] = ST_NOCONV;
+  }
+}
+
+// Coarse basis block phi = D X / sqrt(nu) for the m selected pairs, b-normalised,
+// sign fixed so the largest-magnitude entry is positive; written column-major
+// over the Neumann dofs (Phi) and row-major over the Dirichlet dofs (PhiD).
+template <typename V>
+__global__ void k_eig_finalize(const i32* __restrict__ nb, const i64* __restrict__ voff,
+                               const i64* __restrict__ kvoff, int K, const double* __restrict__ dv,
+                               const V* __restrict__ X, const double* __restrict__ nu,
+                               const int* __restrict__ mcount, const i64* __restrict__ phi_off,
+                               double* __restrict__ Phi, const i32* __restrict__ nd,
+                               const i64* __restrict__ doff, const i32* __restrict__ dpos,
+                               const i64* __restrict__ phid_off, double* __restrict__ PhiD) {
+  const int i = blockIdx.x;
+  const int n = nb[i];
+  const int m = mcount[i];
+  const V* Xi = X + kvoff[i];
+  const double* d = dv + voff[i];
+  double* P = Phi + phi_off[i];
+  __shared__ double sh[16];
+  __shared__ double sgn;
+  for (int c = 0; c < m; ++c) {
+    const double s = 1.0 / sqrt(nu[(i64)i * K + c]);
+    // sign: entry of largest magnitude (first on ties) made positive
+    double best = -1.0;
+    int bidx = 0x7fffffff;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+      const double v = fabs(d[r] * (double)Xi[r + (i64)c * n]);
+      if (v > best) { best = v; bidx = r; }
+    }
+    // reduce (max, then min index)
+    for (int o = 32; o > 0; o >>= 1) {
+      double ob = __shfl_xor(best, o, 64);
+      int oi = __shfl_xor(bidx, o, 64);
+      if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+    }
+    __shared__ double wb[16];
+    __shared__ int wi[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) { wb[w] = best; wi[w] = bidx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double b0 = wb[0];
+      int i0 = wi[0];
+      for (int q = 1; q < (int)(blockDim.x >> 6); ++q)
+        if (wb[q] > b0 || (wb[q] == b0 && wi[q] < i0)) { b0 = wb[q]; i0 = wi[q]; }
+      const double v = d[i0] * (double)Xi[i0 + (i64)c * n];
+      sgn = v < 0 ? -1.0 : 1.0;
+    }
+    __syncthreads();
+    const double f = s * sgn;
+    for (int r = threadIdx.x; r < n; r += blockDim.x)
+      P[r + (i64)c * n] = d[r] * (double)Xi[r + (i64)c * n] * f;
+  }
+  (void)sh;
+  __syncthreads();
+  // Dirichlet rows, row-major
+  const int ndi = nd[i];
+  const i32* dp = dpos + doff[i];
+  double* PD = PhiD + phid_off[i];
+  for (int t = threadIdx.x; t < ndi * m; t += blockDim.x) {
+    const int q = t / m, c = t % m;
+    PD[t] = P[dp[q] + (i64)c * n];
+  }
+}
+
+// ---------------------------------------------------------------------------
+void launch_eig_init(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
+                     const i32* nb, const i64* kvoff, int K, const double* dv, double* X,
+                     unsigned long long seed) {
+  if (!total_rows) return;
+  dim3 g((unsigned)((total_rows + MSDD_WG - 1) / MSDD_WG));
+  hipLaunchKernelGGL(k_eig_init<double>, g, dim3(MSDD_WG), 0, s, total_rows, row_sub, voff, nb,
+                     kvoff, K, dv, X, seed);
+}
+
+void launch_bapply_ell(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
+                       const i32* nb, const i64* kvoff, int K, const double* dv, int ell_w,
+                       const i32* ell_col, const double* ell_val, const double* Y, double* Z,
+                       const int* active) {
+  if (!total_rows) return;
+  dim3 g((unsigned)((total_rows + MSDD_WG - 1) / MSDD_WG));
+  hipLaunchKernelGGL(k_bapply_ell<double>, g, dim3(MSDD_WG), 0, s, total_rows, row_sub, voff, nb,
+                     kvoff, K, dv, ell_w, ell_col, ell_val, Y, Z, active);
+}
+
+void launch_gram(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K, const double* Y,
+                 const double* W, const double* Z, double* GS, double* GB, const int* active) {
+  constexpr int TR = 32;
+  size_t lds = 3 * TR * K * sizeof(double);
+  hipLaunchKernelGGL((k_gram<double, TR>), dim3(P), dim3(MSDD_WG), lds, s, nb, kvoff, K, Y, W,
+                     Z, GS, GB, active);
+}
+
+void launch_rayleigh_ritz(hipStream_t s, int P, int K, const double* GS, const double* GB,
+                          double* C, double* nu, const int* active) {
+  size_t lds = (3 * (size_t)K * K + 2 * K) * sizeof(double) + K * sizeof(int) + 16;
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_rayleigh_ritz, dim3(P), dim3(MSDD_WG), lds, s, K, GS, GB, C, nu, active);
+}
+
+void launch_row_norm(hipStream_t s, int P, const i64* voff, int ell_w, const i32* ell_col,
+                     const double* ell_val, const double* dv, double sigma, double* normS) {
+  hipLaunchKernelGGL(k_row_norm, dim3(P), dim3(MSDD_WG), 0, s, voff, ell_w, ell_col, ell_val, dv,
+                     sigma, normS);
+}
+
+void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K,
+                       const double* C, const double* nu, const double* Y, const double* Z,
+                       double* X, double* BX, double* SX, double sigma, double eta, int nev_max,
+                       double tol, int maxit, int* status, int* iters, int* mcount,
+                       double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
+                       const double* normS, double* nu_prev) {
+  constexpr int TR = 16;
+  size_t lds = (size_t)K * K * sizeof(double) + 3 * TR * K * sizeof(double);
+  hipLaunchKernelGGL((k_eig_update<double, TR>), dim3(P), dim3(MSDD_WG), lds, s, nb, kvoff, K, C,
+                     nu, Y, Z, X, BX, SX, sigma, eta, nev_max, tol, maxit, status, iters, mcount,
+                     lam_out, res_out, Kmax_allowed, rankb, normS, nu_prev);
+}
+
+void launch_eig_finalize(hipStream_t s, int P, const i32* nb, const i64* voff, const i64* kvoff,
+                         int K, const double* dv, const double* X, const double* nu,
+                         const int* mcount, const i64* phi_off, double* Phi, const i32* nd,
+                         const i64* doff, const i32* dpos, const i64* phid_off, double* PhiD) {
+  hipLaunchKernelGGL(k_eig_finalize<double>, dim3(P), dim3(MSDD_WG), 0, s, nb, voff, kvoff, K, dv,
+                     X, nu, mcount, phi_off, Phi, nd, doff, dpos, phid_off, PhiD);
+}

@@ -1,0 +1,122 @@
+// Host-side launchers of the msdd kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+typedef int64_t i64;
+typedef int32_t i32;
+
+// band.hip
+void launch_neumann_assemble(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
+                             const i32* bw, const i64* boff, const i64* inc_ptr,
+                             const i32* inc_slot, const i32* inc_a, const i32* slot_elem,
+                             const i32* slot_loc, int k, const double* elem_mat, double* band,
+                             int ell_w, const i32* ell_col, double* ell_val, int* status);
+void launch_dirichlet_extract(hipStream_t s, i64 total_rows, const i32* drow_sub,
+                              const i64* doff, const i32* nd, const i32* bd, const i64* dboff,
+                              const i32* dglob, const i64* rowptr, const i32* col,
+                              const double* val, double* band, int* status);
+template <typename T>
+void launch_band_cholesky(hipStream_t s, int nsubs, const i32* subs, int bmax, const i32* n_arr,
+                          const i32* b_arr, const i64* src_off, const double* src,
+                          const i64* dv_off, const double* dv, double sigma, const i64* dst_off,
+                          T* Lc, T* Lr, int* status);
+size_t band_cholesky_lds(int bmax, int elem_size);
+template <typename T, typename V>
+void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax,
+                             const i32* n_arr, const i32* b_arr, const i64* l_off, const T* Lc,
+                             const T* Lr, const i64* v_off, int K, const V* W, V* Y,
+                             const int* active);
+
+// eig.hip
+void launch_eig_init(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
+                     const i32* nb, const i64* kvoff, int K, const double* dv, double* X,
+                     unsigned long long seed);
+void launch_bapply_ell(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
+                       const i32* nb, const i64* kvoff, int K, const double* dv, int ell_w,
+                       const i32* ell_col, const double* ell_val, const double* Y, double* Z,
+                       const int* active);
+void launch_gram(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K, const double* Y,
+                 const double* W, const double* Z, double* GS, double* GB, const int* active);
+void launch_rayleigh_ritz(hipStream_t s, int P, int K, const double* GS, const double* GB,
+                          double* C, double* nu, const int* active);
+void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K,
+                       const double* C, const double* nu, const double* Y, const double* Z,
+                       double* X, double* BX, double* SX, double sigma, double eta, int nev_max,
+                       double tol, int maxit, int* status, int* iters, int* mcount,
+                       double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
+                       const double* normS, double* nu_prev);
+void launch_row_norm(hipStream_t s, int P, const i64* voff, int ell_w, const i32* ell_col,
+                     const double* ell_val, const double* dv, double sigma, double* normS);
+void launch_eig_finalize(hipStream_t s, int P, const i32* nb, const i64* voff, const i64* kvoff,
+                         int K, const double* dv, const double* X, const double* nu,
+                         const int* mcount, const i64* phi_off, double* Phi, const i32* nd,
+                         const i64* doff, const i32* dpos, const i64* phid_off, double* PhiD);
+
+// coarse.hip
+void launch_patch_gather(hipStream_t s, int np, const i64* pdof_ptr, const i32* pM,
+                         const i64* mem_ptr, const i32* mem_sub, const i32* mem_col,
+                         const i64* ploc_off, const i32* ploc, const i32* nb, const i32* msub,
+                         const i64* phi_off, const double* Phi, const i64* vpoff, double* Vp);
+void launch_patch_av(hipStream_t s, i64 total_rows, const i32* row_patch, const i64* pdof_ptr,
+                     const i32* pM, const i64* inc_ptr, const i32* inc_slot, const i32* inc_a,
+                     const i32* slot_elem, const i32* slot_loc, int k, const double* elem_mat,
+                     const i64* vpoff, const double* Vp, double* Up);
+void launch_patch_gram(hipStream_t s, int np, const i64* pdof_ptr, const i32* pM,
+                       const i64* vpoff, const double* Vp, const double* Up, const i64* pmoff,
+                       double* Pm);
+void launch_patch_project(hipStream_t s, int nq, const i64* ch_ptr, const i32* ch_patch,
+                          const i32* cM, const i64* cmoff, const double* Pc,
+                          const i64* cmem_ptr, const i32* cmem_pslot, const i32* cmem_ownbase,
+                          const i32* cmem_m, const i32* cmem_col, const i64* pmem_ptr,
+                          const i32* pmem_sub, const i32* pmem_col, const i32* mpar,
+                          const i32* nown, const i64* yoff, const double* Y, const i32* pMout,
+                          const i64* poutoff, double* Pout, const i64* wsoff, double* Wsc);
+void launch_coarse_assemble(hipStream_t s, int nt, const i64* tp_ptr, const i32* tp_patch,
+                            const i64* tp_map_off, const i32* tp_map, const i32* pM,
+                            const i64* pmoff, const double* Pm, const i32* ng_arr,
+                            const i64* aoff, double* Aout);
+void launch_dense_cholesky(hipStream_t s, int n, double* A, int* status);
+void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_arr,
+                        const i64* aoff, double* Abar, const i64* loff, double* Lo,
+                        const i64* soff, double* scratch, double eta, int nev_max,
+                        double eps_reg, double* lam_out, const i64* lamoff, int* m_out,
+                        int* status, int* rank_out);
+void launch_coarse_collect(hipStream_t s, int nt, const i32* ng_arr, const i32* no_arr,
+                           const i64* soff, const double* scratch, const int* m_arr,
+                           const i64* yoff, double* Y);
+
+// pcg.hip
+enum { PCG_SC_RZ = 0, PCG_SC_PQ = 1, PCG_SC_RR = 2, PCG_SC_ALPHA = 3, PCG_SC_BETA = 4,
+       PCG_SC_RR0 = 5, PCG_SC_TMP = 6 };
+enum { PCG_RED_SET = 0, PCG_RED_ALPHA = 1, PCG_RED_BETA = 2 };
+int pcg_grid(i64 n);
+void launch_spmv_dot(hipStream_t s, i64 n, int sg, const i64* rowptr, const i32* col,
+                     const double* val, const double* p, double* q, double* partial, int want_dot);
+void launch_reduce(hipStream_t s, const double* partial, int np, double* sc, int slot, int rule);
+void launch_update_xr(hipStream_t s, i64 n, double* x, double* r, const double* p,
+                      const double* q, const double* sc, double* partial);
+void launch_dot(hipStream_t s, i64 n, const double* a, const double* b, double* partial);
+void launch_update_p(hipStream_t s, i64 n, const double* z, double* p, const double* sc,
+                     int use_beta);
+void launch_residual(hipStream_t s, i64 n, const double* b, const double* q, double* r,
+                     double* partial);
+void launch_apply_fine_down(hipStream_t s, int P, int nd_max, int bd_max, const i32* nd,
+                            const i32* bd, const i64* doff, const i32* dglob, const i64* dboff,
+                            const double* Lc, const double* Lr, const i32* msub, const i64* moff,
+                            const i64* phid_off, const double* PhiD, const double* r, double* rc,
+                            double* u);
+void launch_apply_coarse_down(hipStream_t s, int P, int no_max, const i32* nown,
+                              const i64* own_ptr, const i32* own_idx, const i64* loff,
+                              const double* Lo, const i32* msub, const i64* yoff, const double* Y,
+                              const i64* moff, const double* rl, double* zl, double* rc);
+void launch_apply_coarsest(hipStream_t s, int n0, const double* L, const double* r0, double* z0);
+void launch_apply_coarse_up(hipStream_t s, int P, const i32* nown, const i64* own_ptr,
+                            const i32* own_idx, const i32* msub, const i64* yoff, const double* Y,
+                            const i64* moff, const double* zc, double* zl);
+void launch_apply_fine_up(hipStream_t s, i64 n, const i64* dinc_ptr, const i32* dinc_sub,
+                          const i32* dinc_q, const i64* doff, const i32* msub, const i64* moff,
+                          const i64* phid_off, const double* PhiD, const double* u,
+                          const double* zc, double* z);

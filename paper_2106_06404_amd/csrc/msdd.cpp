@@ -1,0 +1,1720 @@
+// Host side of the msdd library: input validation, index planning (the
+// symbolic part of the setup), the level-by-level setup orchestration, PCG
+// and the C ABI declared in include/msdd.h.
+//
+// Paper sections: 2.1 (additive subspace correction), 2.2 (hierarchical
+// decomposition), 2.3 (spectral coarse spaces, partition of unity,
+// Dirichlet subspaces), 3.5 (CG bilinear forms and b^1), 4.1 (patch
+// matrices), 4.2 (generating systems on coarse levels), 5 (CG stopping rule).
+#include "msdd.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+struct MsddError {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                       \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      throw MsddError{MSDD_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)};    \
+  } while (0)
+
+#define REQUIRE(cond, msg)                                     \
+  do {                                                         \
+    if (!(cond)) throw MsddError{MSDD_EINVAL, std::string(msg)}; \
+  } while (0)
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <class T>
+struct DVec {
+  T* p = nullptr;
+  size_t n = 0;
+  DVec() = default;
+  DVec(const DVec&) = delete;
+  DVec& operator=(const DVec&) = delete;
+  DVec(DVec&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DVec& operator=(DVec&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DVec() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t cnt) {
+    release();
+    if (cnt == 0) return;
+    if (hipMalloc((void**)&p, cnt * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw MsddError{MSDD_ENOMEM, "device allocation of " + std::to_string(cnt * sizeof(T)) + " bytes failed"};
+    }
+    n = cnt;
+  }
+  void zero(hipStream_t s) {
+    if (n) HIPCHK(hipMemsetAsync(p, 0, n * sizeof(T), s));
+  }
+  void upload(const std::vector<T>& v, hipStream_t s) {
+    alloc(v.size());
+    if (n) HIPCHK(hipMemcpyAsync(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  std::vector<T> download(hipStream_t s, size_t cnt = (size_t)-1) const {
+    if (cnt == (size_t)-1) cnt = n;
+    std::vector<T> v(cnt);
+    if (cnt) {
+      HIPCHK(hipMemcpyAsync(v.data(), p, cnt * sizeof(T), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    return v;
+  }
+};
+
+bool is_device_ptr(const void* ptr) {
+  if (!ptr) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.isManaged;
+}
+
+template <class T>
+std::vector<T> to_host(const T* ptr, size_t cnt) {
+  std::vector<T> v(cnt);
+  if (cnt == 0) return v;
+  REQUIRE(ptr != nullptr, "null array argument");
+  if (is_device_ptr(ptr)) {
+    HIPCHK(hipMemcpy(v.data(), ptr, cnt * sizeof(T), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(v.data(), ptr, cnt * sizeof(T));
+  }
+  return v;
+}
+
+// device copy owned by the context (from host or device source)
+template <class T>
+void to_device(DVec<T>& dst, const T* src, size_t cnt, hipStream_t s) {
+  dst.alloc(cnt);
+  if (!cnt) return;
+  REQUIRE(src != nullptr, "null array argument");
+  HIPCHK(hipMemcpyAsync(dst.p, src, cnt * sizeof(T),
+                        is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+}
+
+// ---------------------------------------------------------------------------
+// An element group (a subdomain or a patch): local dofs in ascending global
+// order, local indices of every element dof, dof -> (element, slot) incidences.
+// ---------------------------------------------------------------------------
+struct GroupPlan {
+  std::vector<int> dofs;
+  std::vector<int32_t> eloc;      // ne*k
+  std::vector<int64_t> inc_ptr;   // ndof+1
+  std::vector<int32_t> inc_t;     // element position within the group
+  std::vector<int32_t> inc_a;     // local node slot
+  int bw = 0;
+};
+
+GroupPlan plan_group(const int32_t* elems, int64_t ne, const std::vector<int32_t>& ed, int k,
+                     std::vector<int>& map) {
+  GroupPlan g;
+  for (int64_t t = 0; t < ne; ++t) {
+    const int32_t* d = &ed[(size_t)elems[t] * k];
+    for (int a = 0; a < k; ++a)
+      if (d[a] >= 0 && map[d[a]] == -1) {
+        map[d[a]] = -2;
+        g.dofs.push_back(d[a]);
+      }
+  }
+  std::sort(g.dofs.begin(), g.dofs.end());
+  for (size_t r = 0; r < g.dofs.size(); ++r) map[g.dofs[r]] = (int)r;
+  g.eloc.resize((size_t)ne * k);
+  std::vector<int64_t> cnt(g.dofs.size() + 1, 0);
+  for (int64_t t = 0; t < ne; ++t) {
+    const int32_t* d = &ed[(size_t)elems[t] * k];
+    int lo = 1 << 30, hi = -1;
+    for (int a = 0; a < k; ++a) {
+      const int l = d[a] >= 0 ? map[d[a]] : -1;
+      g.eloc[(size_t)t * k + a] = l;
+      if (l >= 0) {
+        cnt[l + 1]++;
+        lo = std::min(lo, l);
+        hi = std::max(hi, l);
+      }
+    }
+    if (hi >= 0) g.bw = std::max(g.bw, hi - lo);
+  }
+  for (size_t r = 0; r < g.dofs.size(); ++r) cnt[r + 1] += cnt[r];
+  g.inc_ptr = cnt;
+  g.inc_t.resize(cnt.back());
+  g.inc_a.resize(cnt.back());
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t t = 0; t < ne; ++t)
+    for (int a = 0; a < k; ++a) {
+      const int l = g.eloc[(size_t)t * k + a];
+      if (l >= 0) {
+        g.inc_t[pos[l]] = (int32_t)t;
+        g.inc_a[pos[l]] = a;
+        pos[l]++;
+      }
+    }
+  for (int d : g.dofs) map[d] = -1;
+  return g;
+}
+
+// Concatenated element-group plans uploaded for the gather kernels.
+struct GroupSetDev {
+  int ngroups = 0;
+  int64_t total_rows = 0;
+  std::vector<int64_t> h_voff;  // ngroups+1
+  std::vector<int32_t> h_n, h_bw;
+  DVec<int32_t> row_grp, slot_elem, slot_loc, inc_slot, inc_a, n, bw;
+  DVec<int64_t> voff, inc_ptr;
+};
+
+void build_groupset(const std::vector<GroupPlan>& G, const std::vector<std::vector<int32_t>>& elems,
+                    int k, GroupSetDev& out, hipStream_t s) {
+  out.ngroups = (int)G.size();
+  out.h_voff.assign(G.size() + 1, 0);
+  out.h_n.resize(G.size());
+  out.h_bw.resize(G.size());
+  std::vector<int64_t> soff(G.size() + 1, 0);
+  for (size_t i = 0; i < G.size(); ++i) {
+    out.h_voff[i + 1] = out.h_voff[i] + (int64_t)G[i].dofs.size();
+    soff[i + 1] = soff[i] + (int64_t)elems[i].size();
+    out.h_n[i] = (int32_t)G[i].dofs.size();
+    out.h_bw[i] = G[i].bw;
+  }
+  out.total_rows = out.h_voff.back();
+  std::vector<int32_t> row_grp(out.total_rows), slot_elem(soff.back()), slot_loc(soff.back() * k);
+  std::vector<int64_t> inc_ptr(out.total_rows + 1, 0);
+  size_t ninc = 0;
+  for (auto& g : G) ninc += g.inc_t.size();
+  std::vector<int32_t> inc_slot(ninc), inc_a(ninc);
+  size_t q = 0;
+  for (size_t i = 0; i < G.size(); ++i) {
+    const auto& g = G[i];
+    for (size_t r = 0; r < g.dofs.size(); ++r) {
+      const int64_t gr = out.h_voff[i] + (int64_t)r;
+      row_grp[gr] = (int32_t)i;
+      for (int64_t e = g.inc_ptr[r]; e < g.inc_ptr[r + 1]; ++e) {
+        inc_slot[q] = (int32_t)(soff[i] + g.inc_t[e]);
+        inc_a[q] = g.inc_a[e];
+        ++q;
+      }
+      inc_ptr[gr + 1] = (int64_t)q;
+    }
+    for (size_t t = 0; t < elems[i].size(); ++t) slot_elem[soff[i] + t] = elems[i][t];
+    std::copy(g.eloc.begin(), g.eloc.end(), slot_loc.begin() + soff[i] * k);
+  }
+  out.row_grp.upload(row_grp, s);
+  out.slot_elem.upload(slot_elem, s);
+  out.slot_loc.upload(slot_loc, s);
+  out.inc_slot.upload(inc_slot, s);
+  out.inc_a.upload(inc_a, s);
+  out.inc_ptr.upload(inc_ptr, s);
+  out.voff.upload(out.h_voff, s);
+  out.n.upload(out.h_n, s);
+  out.bw.upload(out.h_bw, s);
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// Patch matrices of one level (Sec. 4.1) held on the device.
+// ---------------------------------------------------------------------------
+struct PatchLevel {
+  int np = 0;
+  std::vector<std::vector<int32_t>> members;  // sorted subdomain ids of the level
+  std::vector<int32_t> M;                     // functions per patch
+  std::vector<std::vector<int32_t>> mcol;     // member column offsets
+  std::vector<int64_t> pmoff;                 // np+1 offsets into Pm
+  DVec<double> Pm;
+  DVec<int32_t> dM;
+  DVec<int64_t> dpmoff;
+  // for coarse projection: children (patches of the finer level)
+  std::vector<std::vector<int32_t>> children;
+};
+
+struct FineLevel {
+  int P = 0;
+  GroupSetDev gs;                       // Neumann-space plans
+  std::vector<std::vector<int32_t>> elems;
+  std::vector<GroupPlan> plans;
+  std::vector<double> h_dv;             // PoU weights (sorted order)
+  DVec<double> dv;
+  // band storage
+  std::vector<int64_t> h_boff;
+  DVec<int64_t> boff;
+  DVec<double> band;                    // Neumann band (FP64)
+  int ell_w = 0;
+  DVec<int32_t> ell_col;
+  DVec<double> ell_val;
+  DVec<double> LSc, LSr;                // factor of S = abar + sigma*b
+  // Dirichlet
+  std::vector<int32_t> h_nd, h_bd, h_dpos, h_dglob, h_rankb;
+  std::vector<int64_t> h_doff, h_dboff;
+  DVec<int32_t> nd, bd, dpos, dglob, drow_sub, rankb;
+  DVec<int64_t> doff, dboff;
+  DVec<double> Dband, LDc, LDr;
+  int nd_max = 0, bd_max = 0, bw_max = 0, nb_max = 0;
+  // sums used for the algorithmic byte / flop counts of the profiler
+  double s_nb = 0, s_band = 0, s_nbb = 0, s_nd = 0, s_dband = 0, s_ndbd = 0, s_ndm = 0, s_m = 0;
+  // Dirichlet incidence of fine dofs
+  DVec<int64_t> dinc_ptr;
+  DVec<int32_t> dinc_sub, dinc_q;
+  // eigen results
+  std::vector<int32_t> m;
+  std::vector<std::vector<double>> lam;  // computed lambdas per subdomain (selected + extra)
+  std::vector<int64_t> h_phi_off, h_phid_off, h_moff;
+  DVec<int64_t> phi_off, phid_off, moff;
+  DVec<int32_t> dm;
+  DVec<double> Phi, PhiD;
+};
+
+struct CoarseLevel {
+  int level = 0;  // l
+  int P = 0;
+  std::vector<int32_t> no, ng, m;
+  std::vector<std::vector<int32_t>> children;  // J_{l,i}
+  std::vector<int64_t> h_loff, h_yoff, h_moff, h_lamoff, h_own_ptr;
+  std::vector<int32_t> h_own_idx;
+  DVec<int32_t> dno, dm, own_idx;
+  DVec<int64_t> loff, yoff, moff, own_ptr;
+  DVec<double> Lo, Y, lam;
+  std::vector<std::vector<double>> h_lam;
+  std::vector<int32_t> rank;
+  int no_max = 0;
+};
+
+struct EigPass {
+  int K = 0;
+  DVec<double> X, nu, lam, res;
+  DVec<int> mcount;
+  std::vector<int> subs;  // subdomains finalised from this pass
+};
+
+// Kernel classes timed with HIP events when profiling is on.
+enum ProfId {
+  PR_NEUMANN = 0,   // Neumann band + ELL assembly
+  PR_DIRICHLET,     // Dirichlet extraction from CSR
+  PR_CHOL,          // band Cholesky (S and Dirichlet)
+  PR_EIG_SOLVE,     // band solves with K right-hand sides (eigensolver)
+  PR_EIG_BAPPLY,    // b = D abar D applied to K vectors
+  PR_EIG_GRAM,      // Gram matrices
+  PR_EIG_RR,        // Rayleigh-Ritz small eigenproblems
+  PR_EIG_UPDATE,    // block update + residuals
+  PR_PATCH,         // patch matrices and projections
+  PR_COARSE,        // coarse assembly + coarse GEVP + A_0 Cholesky
+  PR_SPMV,          // CSR SpMV (+ fused dot)
+  PR_VEC,           // PCG vector updates and dot products
+  PR_APPLY_FINE,    // finest-level restriction + band triangular solves
+  PR_APPLY_COARSE,  // coarse-level solves, restriction, prolongation
+  PR_APPLY_GATHER,  // finest-level prolongation + gather
+  PR_OTHER,
+  PR_COUNT
+};
+static_assert(PR_COUNT == MSDD_NPROF, "profile classes");
+const char* kProfNames[PR_COUNT] = {
+    "neumann_assemble", "dirichlet_extract", "band_cholesky", "eig_band_solve",
+    "eig_bapply", "eig_gram", "eig_rayleigh_ritz", "eig_update", "patch", "coarse",
+    "spmv", "pcg_vector", "apply_fine_solve", "apply_coarse", "apply_fine_gather", "other"};
+
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int id;
+    hipEvent_t a, b;
+    double bytes, flops;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  double ms[PR_COUNT] = {0};
+  int64_t cnt[PR_COUNT] = {0};
+  double bytes[PR_COUNT] = {0}, flops[PR_COUNT] = {0};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+  void resolve() {
+    for (auto& r : recs) {
+      HIPCHK(hipEventSynchronize(r.b));
+      float t = 0;
+      HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+      ms[r.id] += t;
+      cnt[r.id] += 1;
+      bytes[r.id] += r.bytes;
+      flops[r.id] += r.flops;
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+  void reset() {
+    resolve();
+    for (int i = 0; i < PR_COUNT; ++i) ms[i] = 0, cnt[i] = 0, bytes[i] = 0, flops[i] = 0;
+  }
+  ~Profiler() {
+    for (auto& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct msdd_ctx {
+  msdd_options opt;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool ready = false;
+  int n_levels = 0;
+  int64_t n = 0, nnz = 0;
+  int k = 0;
+  double eta = 0, sigma = 0;
+  DVec<int64_t> rowptr;
+  DVec<int32_t> col;
+  DVec<double> val;
+  int spmv_sg = 8;
+  FineLevel F;
+  std::vector<CoarseLevel> C;  // C[0] = level L-1, ..., C[L-2] = level 1
+  std::vector<int64_t> nlev;   // n_l for l = 0..L
+  int n0 = 0;
+  DVec<double> A0;
+  // solve work
+  std::vector<DVec<double>> rlev, zlev;  // index l = 0..L-1
+  DVec<double> u, r, z, p, q, x, bvec, partial, sc;
+  double* h_pinned = nullptr;
+  msdd_stats_t stats;
+  Profiler prof;
+  int eig_active = 0;  // subdomains running in the eigensolver (last status read)
+  ~msdd_ctx() {
+    if (h_pinned) (void)hipHostFree(h_pinned);
+  }
+};
+
+namespace {
+
+void set_err(msdd_ctx* c, const std::string& m) {
+  if (c) c->err = m;
+}
+
+int code_for(msdd_ctx* c, const MsddError& e) {
+  set_err(c, e.msg);
+  if (c && c->opt.verbose) std::fprintf(stderr, "msdd: %s\n", e.msg.c_str());
+  return e.code;
+}
+
+void check_status(const std::vector<int>& st, const char* what, const std::vector<int>* ids = nullptr) {
+  for (size_t i = 0; i < st.size(); ++i) {
+    if (st[i] == ST_NOTSPD)
+      throw MsddError{MSDD_ENOTSPD, std::string(what) + ": non-positive pivot in subdomain " +
+                                        std::to_string(ids ? (*ids)[i] : (int)i)};
+    if (st[i] == ST_BADINPUT)
+      throw MsddError{MSDD_EINVAL, std::string(what) + ": entry outside the element structure or NaN in subdomain " +
+                                       std::to_string(ids ? (*ids)[i] : (int)i)};
+  }
+}
+
+// Records HIP events around the launches of one kernel class (when profiling).
+struct ProfScope {
+  msdd_ctx* c;
+  int id;
+  double bytes, flops;
+  hipEvent_t a = nullptr;
+  ProfScope(msdd_ctx* c_, int id_, double bytes_ = 0, double flops_ = 0)
+      : c(c_), id(id_), bytes(bytes_), flops(flops_) {
+    if (c->prof.on) {
+      a = c->prof.get();
+      HIPCHK(hipEventRecord(a, c->stream));
+    }
+  }
+  ~ProfScope() {
+    if (c->prof.on && a) {
+      hipEvent_t b = c->prof.get();
+      if (hipEventRecord(b, c->stream) == hipSuccess) c->prof.recs.push_back({id, a, b, bytes, flops});
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Finest level: planning, local matrices, factorizations, eigensolves
+// ---------------------------------------------------------------------------
+void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
+               const std::vector<int64_t>& sep, const std::vector<int32_t>& se,
+               const std::vector<int64_t>& sdp, const std::vector<int32_t>& sd,
+               const std::vector<double>& sw) {
+  FineLevel& F = c->F;
+  const int k = c->k;
+  const int64_t n = c->n;
+  const int P = F.P;
+  std::vector<int> map(n, -1);
+  std::vector<int32_t> deg(n, 0);
+  for (size_t e = 0; e < ed.size(); ++e) {
+    REQUIRE(ed[e] >= -1 && ed[e] < n, "elem_dofs entry out of range");
+    if (ed[e] >= 0) deg[ed[e]]++;
+  }
+  F.elems.resize(P);
+  F.plans.resize(P);
+  F.h_dv.clear();
+  std::vector<double> pou_sum(n, 0.0);
+  F.h_nd.assign(P, 0);
+  F.h_bd.assign(P, 0);
+  F.h_rankb.assign(P, 0);
+  F.h_doff.assign(P + 1, 0);
+  F.h_dboff.assign(P + 1, 0);
+  F.h_dpos.clear();
+  F.h_dglob.clear();
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> dinc(n);
+  for (int i = 0; i < P; ++i) {
+    REQUIRE(sep[i + 1] >= sep[i] && sdp[i + 1] >= sdp[i], "subdomain pointers not monotone");
+    std::vector<int32_t> el(se.begin() + sep[i], se.begin() + sep[i + 1]);
+    for (int32_t e : el) REQUIRE(e >= 0 && e < n_elem, "sub_elem entry out of range");
+    F.elems[i] = el;
+    F.plans[i] = plan_group(el.data(), (int64_t)el.size(), ed, k, map);
+    const GroupPlan& g = F.plans[i];
+    // the caller's Neumann dofs must be the free dofs of the subdomain's elements
+    const int64_t nd_in = sdp[i + 1] - sdp[i];
+    REQUIRE(nd_in == (int64_t)g.dofs.size(),
+            "sub_dof of subdomain " + std::to_string(i) + " is not the set of free dofs of its elements");
+    std::vector<std::pair<int32_t, double>> dw((size_t)nd_in);
+    for (int64_t t = 0; t < nd_in; ++t) dw[t] = {sd[sdp[i] + t], sw[sdp[i] + t]};
+    std::sort(dw.begin(), dw.end());
+    std::vector<int32_t> dloc(g.dofs.size(), -1);
+    int nD = 0;
+    for (size_t r = 0; r < g.dofs.size(); ++r) {
+      REQUIRE(dw[r].first == g.dofs[r],
+              "sub_dof of subdomain " + std::to_string(i) + " is not the set of free dofs of its elements");
+      const double w = dw[r].second;
+      REQUIRE(std::isfinite(w), "non-finite partition-of-unity weight");
+      const int64_t ninc = g.inc_ptr[r + 1] - g.inc_ptr[r];
+      const bool dir = ninc == deg[g.dofs[r]];  // every adjacent element lies in the subdomain
+      if (!dir) REQUIRE(std::fabs(w) <= 1e-14,
+                        "partition of unity does not vanish on the boundary of subdomain " + std::to_string(i));
+      F.h_dv.push_back(dir ? w : 0.0);
+      pou_sum[g.dofs[r]] += dir ? w : 0.0;
+      if (dir) {
+        dloc[r] = nD++;
+        F.h_dpos.push_back((int32_t)r);
+        F.h_dglob.push_back(g.dofs[r]);
+        dinc[g.dofs[r]].push_back({i, dloc[r]});
+      }
+      if (dir && w != 0.0) F.h_rankb[i]++;
+    }
+    int bd = 0;
+    for (size_t t = 0; t < el.size(); ++t) {
+      int lo = 1 << 30, hi = -1;
+      for (int a = 0; a < k; ++a) {
+        const int l = g.eloc[t * k + a];
+        if (l >= 0 && dloc[l] >= 0) {
+          lo = std::min(lo, dloc[l]);
+          hi = std::max(hi, dloc[l]);
+        }
+      }
+      if (hi >= 0) bd = std::max(bd, hi - lo);
+    }
+    F.h_nd[i] = nD;
+    F.h_bd[i] = bd;
+    F.h_doff[i + 1] = F.h_doff[i] + nD;
+    F.h_dboff[i + 1] = F.h_dboff[i] + (int64_t)nD * (bd + 1);
+    F.nd_max = std::max(F.nd_max, nD);
+    F.s_nb += (double)g.dofs.size();
+    F.s_band += (double)g.dofs.size() * (g.bw + 1);
+    F.s_nbb += (double)g.dofs.size() * g.bw;
+    F.s_nd += nD;
+    F.s_dband += (double)nD * (bd + 1);
+    F.s_ndbd += (double)nD * bd;
+    F.bd_max = std::max(F.bd_max, bd);
+    F.bw_max = std::max(F.bw_max, g.bw);
+    F.nb_max = std::max(F.nb_max, (int)g.dofs.size());
+  }
+  for (int64_t d = 0; d < n; ++d) {
+    REQUIRE(std::fabs(pou_sum[d] - 1.0) <= 1e-12,
+            "partition-of-unity weights do not sum to 1 at dof " + std::to_string(d));
+    REQUIRE(!dinc[d].empty(), "dof " + std::to_string(d) + " lies in no subdomain's Dirichlet space");
+  }
+  hipStream_t s = c->stream;
+  build_groupset(F.plans, F.elems, k, F.gs, s);
+  F.dv.upload(F.h_dv, s);
+  // Neumann band offsets and the ELL structure
+  F.h_boff.assign(P + 1, 0);
+  for (int i = 0; i < P; ++i)
+    F.h_boff[i + 1] = F.h_boff[i] + (int64_t)F.plans[i].dofs.size() * (F.plans[i].bw + 1);
+  int ell_w = 0;
+  std::vector<std::vector<int32_t>> rowcols;
+  int64_t total = F.gs.total_rows;
+  std::vector<int32_t> ell;  // filled after width known
+  std::vector<int32_t> tmp;
+  // first pass: width
+  for (int i = 0; i < P; ++i) {
+    const GroupPlan& g = F.plans[i];
+    for (size_t r = 0; r < g.dofs.size(); ++r) {
+      tmp.clear();
+      for (int64_t e = g.inc_ptr[r]; e < g.inc_ptr[r + 1]; ++e) {
+        const int t = g.inc_t[e];
+        for (int a = 0; a < k; ++a) {
+          const int l = g.eloc[(size_t)t * k + a];
+          if (l >= 0) tmp.push_back(l);
+        }
+      }
+      std::sort(tmp.begin(), tmp.end());
+      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+      ell_w = std::max(ell_w, (int)tmp.size());
+    }
+  }
+  F.ell_w = ell_w;
+  ell.assign((size_t)total * ell_w, -1);
+  for (int i = 0; i < P; ++i) {
+    const GroupPlan& g = F.plans[i];
+    for (size_t r = 0; r < g.dofs.size(); ++r) {
+      tmp.clear();
+      for (int64_t e = g.inc_ptr[r]; e < g.inc_ptr[r + 1]; ++e) {
+        const int t = g.inc_t[e];
+        for (int a = 0; a < k; ++a) {
+          const int l = g.eloc[(size_t)t * k + a];
+          if (l >= 0) tmp.push_back(l);
+        }
+      }
+      std::sort(tmp.begin(), tmp.end());
+      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+      const int64_t gr = F.gs.h_voff[i] + (int64_t)r;
+      std::copy(tmp.begin(), tmp.end(), ell.begin() + gr * ell_w);
+    }
+  }
+  F.ell_col.upload(ell, s);
+  F.boff.upload(F.h_boff, s);
+  // Dirichlet arrays
+  std::vector<int32_t> drow_sub(F.h_doff.back());
+  for (int i = 0; i < P; ++i)
+    for (int64_t g = F.h_doff[i]; g < F.h_doff[i + 1]; ++g) drow_sub[g] = i;
+  F.drow_sub.upload(drow_sub, s);
+  F.nd.upload(F.h_nd, s);
+  F.bd.upload(F.h_bd, s);
+  F.doff.upload(F.h_doff, s);
+  F.dboff.upload(F.h_dboff, s);
+  F.dpos.upload(F.h_dpos, s);
+  F.dglob.upload(F.h_dglob, s);
+  F.rankb.upload(F.h_rankb, s);
+  std::vector<int64_t> dptr(n + 1, 0);
+  std::vector<int32_t> dsub, dq;
+  for (int64_t d = 0; d < n; ++d) {
+    for (auto& pr : dinc[d]) {
+      dsub.push_back(pr.first);
+      dq.push_back(pr.second);
+    }
+    dptr[d + 1] = (int64_t)dsub.size();
+  }
+  F.dinc_ptr.upload(dptr, s);
+  F.dinc_sub.upload(dsub, s);
+  F.dinc_q.upload(dq, s);
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
+  FineLevel& F = c->F;
+  hipStream_t s = c->stream;
+  const int P = F.P;
+  DVec<int> status;
+  status.alloc(P);
+  status.zero(s);
+  F.band.alloc(F.h_boff.back());
+  F.band.zero(s);
+  F.ell_val.alloc((size_t)F.gs.total_rows * F.ell_w);
+  F.ell_val.zero(s);
+  {
+  ProfScope ps(c, PR_NEUMANN, F.s_nb * (8.0 + F.ell_w * 12.0) + F.s_band * 8.0);
+  launch_neumann_assemble(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.bw.p, F.boff.p,
+                          F.gs.inc_ptr.p, F.gs.inc_slot.p, F.gs.inc_a.p, F.gs.slot_elem.p,
+                          F.gs.slot_loc.p, c->k, d_elem_mat, F.band.p, F.ell_w, F.ell_col.p,
+                          F.ell_val.p, status.p);
+  }
+  F.Dband.alloc(F.h_dboff.back());
+  F.Dband.zero(s);
+  {
+  ProfScope ps(c, PR_DIRICHLET, F.s_nd * 9.0 * 12.0 + F.s_dband * 8.0);
+  launch_dirichlet_extract(s, F.h_doff.back(), F.drow_sub.p, F.doff.p, F.nd.p, F.bd.p, F.dboff.p,
+                           F.dglob.p, c->rowptr.p, c->col.p, c->val.p, F.Dband.p, status.p);
+  }
+  HIPCHK(hipGetLastError());
+  check_status(status.download(s), "local matrix extraction");
+  // factorisations: S = abar + sigma * D abar D, and the Dirichlet matrices
+  F.LSc.alloc(F.h_boff.back());
+  F.LSr.alloc(F.h_boff.back());
+  F.LSc.zero(s);
+  F.LSr.zero(s);
+  {
+  ProfScope ps(c, PR_CHOL, F.s_band * 8.0 * 3.0, F.s_nbb * (F.bw_max + 2.0));
+  launch_band_cholesky<double>(s, P, nullptr, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.band.p,
+                               F.gs.voff.p, F.dv.p, c->sigma, F.boff.p, F.LSc.p, F.LSr.p,
+                               status.p);
+  }
+  HIPCHK(hipGetLastError());
+  check_status(status.download(s), "Cholesky of abar + sigma*b");
+  F.LDc.alloc(F.h_dboff.back());
+  F.LDr.alloc(F.h_dboff.back());
+  F.LDc.zero(s);
+  F.LDr.zero(s);
+  {
+  ProfScope ps(c, PR_CHOL, F.s_dband * 8.0 * 3.0, F.s_ndbd * (F.bd_max + 2.0));
+  launch_band_cholesky<double>(s, P, nullptr, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.Dband.p,
+                               nullptr, nullptr, 0.0, F.dboff.p, F.LDc.p, F.LDr.p, status.p);
+  }
+  HIPCHK(hipGetLastError());
+  check_status(status.download(s), "Cholesky of the Dirichlet matrices");
+}
+
+void fine_eigensolve(msdd_ctx* c) {
+  FineLevel& F = c->F;
+  hipStream_t s = c->stream;
+  const int P = F.P;
+  const msdd_options& o = c->opt;
+  int K = o.block <= 16 ? 16 : (o.block <= 32 ? 32 : 64);
+  std::vector<int> want(P, 1);  // subdomains still to solve
+  std::vector<int> final_pass(P, -1);
+  std::vector<int> final_m(P, 0);
+  std::vector<std::unique_ptr<EigPass>> passes;
+  int restarts = 0, max_it = 0;
+  double res_max = 0.0;
+  F.lam.assign(P, {});
+  while (true) {
+    int nwant = 0;
+    for (int i = 0; i < P; ++i) nwant += want[i];
+    if (!nwant) break;
+    auto ps = std::make_unique<EigPass>();
+    EigPass& E = *ps;
+    E.K = K;
+    std::vector<int64_t> kvoff(P + 1, 0);
+    for (int i = 0; i < P; ++i) kvoff[i + 1] = kvoff[i] + (int64_t)F.gs.h_n[i] * K;
+    DVec<int64_t> dkvoff;
+    dkvoff.upload(kvoff, s);
+    const size_t tot = kvoff.back();
+    DVec<double> BX, Y, Z, SX, GS, GB, Cm;
+    E.X.alloc(tot);
+    BX.alloc(tot);
+    Y.alloc(tot);
+    Z.alloc(tot);
+    SX.alloc(tot);
+    GS.alloc((size_t)P * K * K);
+    GB.alloc((size_t)P * K * K);
+    Cm.alloc((size_t)P * K * K);
+    E.nu.alloc((size_t)P * K);
+    E.lam.alloc((size_t)P * K);
+    E.res.alloc((size_t)P * K);
+    E.mcount.alloc(P);
+    E.mcount.zero(s);
+    DVec<double> nu_prev, normS;
+    nu_prev.alloc((size_t)P * K);
+    nu_prev.zero(s);
+    normS.alloc(P);
+    launch_row_norm(s, P, F.gs.voff.p, F.ell_w, F.ell_col.p, F.ell_val.p, F.dv.p, c->sigma, normS.p);
+    DVec<int> status, iters;
+    std::vector<int> st0(P);
+    for (int i = 0; i < P; ++i) st0[i] = want[i] ? ST_RUNNING : ST_DONE;
+    status.upload(st0, s);
+    iters.alloc(P);
+    iters.zero(s);
+    launch_eig_init(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K, F.dv.p,
+                    E.X.p, 0x5eed5eedull + (unsigned long long)K);
+    launch_bapply_ell(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K,
+                      F.dv.p, F.ell_w, F.ell_col.p, F.ell_val.p, E.X.p, BX.p, status.p);
+    const int maxit = o.eig_maxit;
+    std::vector<int> st;
+    c->eig_active = nwant;
+    for (int it = 0; it < maxit; ++it) {
+      const double f = (double)c->eig_active / (double)P;  // share of subdomains still running
+      {
+        ProfScope ps(c, PR_EIG_SOLVE, f * (2.0 * F.s_band * 8.0 + 4.0 * F.s_nb * K * 8.0),
+                     f * 4.0 * F.s_nbb * K);
+        launch_band_solve_multi<double, double>(s, P, nullptr, F.nb_max, F.gs.n.p, F.gs.bw.p,
+                                                F.boff.p, F.LSc.p, F.LSr.p, dkvoff.p, K, BX.p,
+                                                Y.p, status.p);
+      }
+      {
+        ProfScope ps(c, PR_EIG_BAPPLY, f * (F.s_nb * F.ell_w * 12.0 + 2.0 * F.s_nb * K * 8.0),
+                     f * 2.0 * F.s_nb * F.ell_w * K);
+        launch_bapply_ell(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K,
+                          F.dv.p, F.ell_w, F.ell_col.p, F.ell_val.p, Y.p, Z.p, status.p);
+      }
+      {
+        ProfScope ps(c, PR_EIG_GRAM, f * 3.0 * F.s_nb * K * 8.0, f * 4.0 * F.s_nb * K * K);
+        launch_gram(s, P, F.gs.n.p, dkvoff.p, K, Y.p, BX.p, Z.p, GS.p, GB.p, status.p);
+      }
+      {
+        ProfScope ps(c, PR_EIG_RR, c->eig_active * 3.0 * K * K * 8.0, 0.0);
+        launch_rayleigh_ritz(s, P, K, GS.p, GB.p, Cm.p, E.nu.p, status.p);
+      }
+      {
+        ProfScope ps(c, PR_EIG_UPDATE, f * 6.0 * F.s_nb * K * 8.0, f * 6.0 * F.s_nb * K * K);
+        launch_eig_update(s, P, F.gs.n.p, dkvoff.p, K, Cm.p, E.nu.p, Y.p, Z.p, E.X.p, BX.p, SX.p,
+                          c->sigma, c->eta, o.nev_max, o.eig_tol, maxit, status.p, iters.p,
+                          E.mcount.p, E.lam.p, E.res.p, 64, F.rankb.p, normS.p, nu_prev.p);
+      }
+      HIPCHK(hipGetLastError());
+      if (it >= 3 && (it % 2 == 1 || it == maxit - 1)) {
+        st = status.download(s);
+        int act = 0;
+        for (int i = 0; i < P; ++i) act += st[i] == ST_RUNNING;
+        c->eig_active = act;
+        if (!act) break;
+      }
+    }
+    st = status.download(s);
+    std::vector<int> mc = E.mcount.download(s);
+    std::vector<int> itv = iters.download(s);
+    std::vector<double> lamv = E.lam.download(s);
+    std::vector<double> resv = E.res.download(s);
+    bool grew = false;
+    for (int i = 0; i < P; ++i) {
+      if (!want[i]) continue;
+      max_it = std::max(max_it, itv[i]);
+      if (st[i] == ST_GROW && K < 64) {
+        grew = true;
+        ++restarts;
+        continue;  // stays wanted for the next pass
+      }
+      if (st[i] == ST_RUNNING || st[i] == ST_NOCONV || st[i] == ST_GROW) {
+        // iteration limit: accept the current Ritz pairs and report the residual
+        if (c->opt.verbose)
+          std::fprintf(stderr, "msdd: subdomain %d eigensolver stopped at maxit (status %d)\n", i, st[i]);
+      }
+      want[i] = 0;
+      final_pass[i] = (int)passes.size();
+      final_m[i] = mc[i];
+      E.subs.push_back(i);
+      const int ne = std::min(K, mc[i] + 4);
+      F.lam[i].assign(lamv.begin() + (size_t)i * K, lamv.begin() + (size_t)i * K + ne);
+      for (int a = 0; a < std::min(K, mc[i] + 1); ++a) res_max = std::max(res_max, resv[(size_t)i * K + a]);
+    }
+    passes.push_back(std::move(ps));
+    if (!grew) break;
+    K *= 2;
+  }
+  // pooled basis blocks
+  F.m = final_m;
+  F.s_ndm = 0;
+  F.s_m = 0;
+  for (int i = 0; i < P; ++i) {
+    F.s_ndm += (double)F.h_nd[i] * F.m[i];
+    F.s_m += F.m[i];
+  }
+  F.h_phi_off.assign(P + 1, 0);
+  F.h_phid_off.assign(P + 1, 0);
+  F.h_moff.assign(P + 1, 0);
+  for (int i = 0; i < P; ++i) {
+    F.h_phi_off[i + 1] = F.h_phi_off[i] + (int64_t)F.gs.h_n[i] * F.m[i];
+    F.h_phid_off[i + 1] = F.h_phid_off[i] + (int64_t)F.h_nd[i] * F.m[i];
+    F.h_moff[i + 1] = F.h_moff[i] + F.m[i];
+  }
+  F.Phi.alloc(std::max<int64_t>(F.h_phi_off.back(), 1));
+  F.PhiD.alloc(std::max<int64_t>(F.h_phid_off.back(), 1));
+  F.phi_off.upload(F.h_phi_off, s);
+  F.phid_off.upload(F.h_phid_off, s);
+  F.moff.upload(F.h_moff, s);
+  F.dm.upload(F.m, s);
+  for (size_t pi = 0; pi < passes.size(); ++pi) {
+    EigPass& E = *passes[pi];
+    std::vector<int> mm(P, 0);
+    for (int i : E.subs) mm[i] = F.m[i];
+    E.mcount.upload(mm, s);
+    std::vector<int64_t> kvoff(P + 1, 0);
+    for (int i = 0; i < P; ++i) kvoff[i + 1] = kvoff[i] + (int64_t)F.gs.h_n[i] * E.K;
+    DVec<int64_t> dkvoff;
+    dkvoff.upload(kvoff, s);
+    launch_eig_finalize(s, P, F.gs.n.p, F.gs.voff.p, dkvoff.p, E.K, F.dv.p, E.X.p, E.nu.p,
+                        E.mcount.p, F.phi_off.p, F.Phi.p, F.nd.p, F.doff.p, F.dpos.p,
+                        F.phid_off.p, F.PhiD.p);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  c->stats.eig_iters_max = max_it;
+  c->stats.eig_restarts = restarts;
+  c->stats.eig_resid_max = res_max;
+}
+
+// ---------------------------------------------------------------------------
+// Patches of the finest level and their projections (Sec. 4.1)
+// ---------------------------------------------------------------------------
+void fine_patches(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
+                  const double* d_elem_mat, PatchLevel& PL) {
+  FineLevel& F = c->F;
+  hipStream_t s = c->stream;
+  const int k = c->k;
+  std::vector<std::vector<int32_t>> esub(n_elem);
+  for (int i = 0; i < F.P; ++i)
+    for (int32_t e : F.elems[i]) esub[e].push_back(i);
+  std::map<std::vector<int32_t>, int> key;
+  std::vector<std::vector<int32_t>> pel;
+  for (int32_t e = 0; e < n_elem; ++e) {
+    REQUIRE(!esub[e].empty(), "element " + std::to_string(e) + " belongs to no subdomain");
+    auto it = key.find(esub[e]);
+    int id;
+    if (it == key.end()) {
+      id = (int)pel.size();
+      key.emplace(esub[e], id);
+      pel.push_back({});
+      PL.members.push_back(esub[e]);
+    } else {
+      id = it->second;
+    }
+    pel[id].push_back(e);
+  }
+  PL.np = (int)pel.size();
+  std::vector<int> map(c->n, -1);
+  std::vector<GroupPlan> plans(PL.np);
+  for (int p = 0; p < PL.np; ++p) plans[p] = plan_group(pel[p].data(), (int64_t)pel[p].size(), ed, k, map);
+  GroupSetDev gs;
+  build_groupset(plans, pel, k, gs, s);
+  // member columns, loc maps
+  PL.M.assign(PL.np, 0);
+  PL.mcol.resize(PL.np);
+  std::vector<int64_t> mem_ptr(PL.np + 1, 0), ploc_off(PL.np + 1, 0), vpoff(PL.np + 1, 0);
+  std::vector<int32_t> mem_sub, mem_col, ploc;
+  PL.pmoff.assign(PL.np + 1, 0);
+  for (int p = 0; p < PL.np; ++p) {
+    int M = 0;
+    for (int32_t j : PL.members[p]) {
+      PL.mcol[p].push_back(M);
+      mem_sub.push_back(j);
+      mem_col.push_back(M);
+      M += F.m[j];
+    }
+    PL.M[p] = M;
+    mem_ptr[p + 1] = (int64_t)mem_sub.size();
+    const int nm = (int)PL.members[p].size();
+    const auto& pd = plans[p].dofs;
+    for (size_t r = 0; r < pd.size(); ++r)
+      for (int sidx = 0; sidx < nm; ++sidx) {
+        const auto& sdofs = F.plans[PL.members[p][sidx]].dofs;
+        auto itd = std::lower_bound(sdofs.begin(), sdofs.end(), pd[r]);
+        ploc.push_back((itd != sdofs.end() && *itd == pd[r]) ? (int32_t)(itd - sdofs.begin()) : -1);
+      }
+    ploc_off[p + 1] = (int64_t)ploc.size();
+    vpoff[p + 1] = vpoff[p] + (int64_t)pd.size() * M;
+    PL.pmoff[p + 1] = PL.pmoff[p] + (int64_t)M * M;
+  }
+  DVec<int64_t> dmem_ptr, dploc_off, dvpoff;
+  DVec<int32_t> dmem_sub, dmem_col, dploc;
+  dmem_ptr.upload(mem_ptr, s);
+  dploc_off.upload(ploc_off, s);
+  dvpoff.upload(vpoff, s);
+  dmem_sub.upload(mem_sub, s);
+  dmem_col.upload(mem_col, s);
+  dploc.upload(ploc, s);
+  PL.dM.upload(PL.M, s);
+  PL.dpmoff.upload(PL.pmoff, s);
+  DVec<double> V, U;
+  V.alloc(std::max<int64_t>(vpoff.back(), 1));
+  U.alloc(std::max<int64_t>(vpoff.back(), 1));
+  PL.Pm.alloc(std::max<int64_t>(PL.pmoff.back(), 1));
+  {
+  ProfScope pscope(c, PR_PATCH);
+  launch_patch_gather(s, PL.np, gs.voff.p, PL.dM.p, dmem_ptr.p, dmem_sub.p, dmem_col.p,
+                      dploc_off.p, dploc.p, F.gs.n.p, F.dm.p, F.phi_off.p, F.Phi.p, dvpoff.p, V.p);
+  launch_patch_av(s, gs.total_rows, gs.row_grp.p, gs.voff.p, PL.dM.p, gs.inc_ptr.p, gs.inc_slot.p,
+                  gs.inc_a.p, gs.slot_elem.p, gs.slot_loc.p, k, d_elem_mat, dvpoff.p, V.p, U.p);
+  launch_patch_gram(s, PL.np, gs.voff.p, PL.dM.p, dvpoff.p, V.p, U.p, PL.dpmoff.p, PL.Pm.p);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// Assemble dense coarse matrices: targets = subdomains of the coarser level (or the
+// single level-0 target), each from the patches listed for it.
+struct AssembleJob {
+  std::vector<int32_t> ng;
+  std::vector<int64_t> aoff;
+  std::vector<int64_t> tp_ptr, tp_map_off;
+  std::vector<int32_t> tp_patch, tp_map;
+};
+
+void run_assemble(msdd_ctx* c, const AssembleJob& J, const PatchLevel& PL, DVec<double>& A) {
+  hipStream_t s = c->stream;
+  DVec<int32_t> ng, tp_patch, tp_map;
+  DVec<int64_t> aoff, tp_ptr, tp_map_off;
+  ng.upload(J.ng, s);
+  aoff.upload(J.aoff, s);
+  tp_ptr.upload(J.tp_ptr, s);
+  tp_map_off.upload(J.tp_map_off, s);
+  tp_patch.upload(J.tp_patch, s);
+  tp_map.upload(J.tp_map, s);
+  A.alloc(std::max<int64_t>(J.aoff.back(), 1));
+  {
+  ProfScope ps(c, PR_COARSE);
+  launch_coarse_assemble(s, (int)J.ng.size(), tp_ptr.p, tp_patch.p, tp_map_off.p, tp_map.p,
+                         PL.dM.p, PL.dpmoff.p, PL.Pm.p, ng.p, aoff.p, A.p);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// m of the subdomains of the level that owns the patches' functions
+void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
+                  const std::vector<int32_t>& m_fine_lvl, const std::vector<int64_t>& moff_fine_lvl,
+                  PatchLevel& PL, CoarseLevel& CL, PatchLevel& PLnext) {
+  hipStream_t s = c->stream;
+  const int Pf = (int)m_fine_lvl.size();
+  REQUIRE((int)par.size() == Pf, "parent map size mismatch");
+  int Pc = 0;
+  for (int32_t v : par) {
+    REQUIRE(v >= 0, "negative parent index");
+    Pc = std::max(Pc, v + 1);
+  }
+  CL.level = l;
+  CL.P = Pc;
+  CL.children.assign(Pc, {});
+  for (int j = 0; j < Pf; ++j) CL.children[par[j]].push_back(j);
+  for (int i = 0; i < Pc; ++i) REQUIRE(!CL.children[i].empty(), "coarse subdomain without children");
+  // generating systems
+  std::vector<std::vector<int32_t>> contrib(Pc);  // patches meeting subdomain i
+  for (int p = 0; p < PL.np; ++p) {
+    std::vector<int32_t> ps;
+    for (int32_t j : PL.members[p]) ps.push_back(par[j]);
+    std::sort(ps.begin(), ps.end());
+    ps.erase(std::unique(ps.begin(), ps.end()), ps.end());
+    for (int32_t i : ps) contrib[i].push_back(p);
+  }
+  AssembleJob J;
+  J.aoff.assign(Pc + 1, 0);
+  J.tp_ptr.assign(Pc + 1, 0);
+  CL.no.assign(Pc, 0);
+  CL.ng.assign(Pc, 0);
+  CL.h_own_ptr.assign(Pc + 1, 0);
+  CL.h_own_idx.clear();
+  std::vector<int32_t> goff(Pf, -1);
+  for (int i = 0; i < Pc; ++i) {
+    std::vector<int32_t> ghosts;
+    for (int p : contrib[i])
+      for (int32_t j : PL.members[p])
+        if (par[j] != i) ghosts.push_back(j);
+    std::sort(ghosts.begin(), ghosts.end());
+    ghosts.erase(std::unique(ghosts.begin(), ghosts.end()), ghosts.end());
+    int off = 0;
+    for (int32_t j : CL.children[i]) {
+      goff[j] = off;
+      for (int q = 0; q < m_fine_lvl[j]; ++q) CL.h_own_idx.push_back((int32_t)(moff_fine_lvl[j] + q));
+      off += m_fine_lvl[j];
+    }
+    CL.no[i] = off;
+    for (int32_t j : ghosts) {
+      goff[j] = off;
+      off += m_fine_lvl[j];
+    }
+    CL.ng[i] = off;
+    CL.h_own_ptr[i + 1] = (int64_t)CL.h_own_idx.size();
+    for (int p : contrib[i]) {
+      J.tp_patch.push_back(p);
+      J.tp_map_off.push_back((int64_t)J.tp_map.size());
+      for (size_t sidx = 0; sidx < PL.members[p].size(); ++sidx) {
+        const int32_t j = PL.members[p][sidx];
+        for (int q = 0; q < m_fine_lvl[j]; ++q) J.tp_map.push_back(goff[j] + q);
+      }
+    }
+    J.tp_ptr[i + 1] = (int64_t)J.tp_patch.size();
+    J.aoff[i + 1] = J.aoff[i] + (int64_t)off * off;
+    for (int32_t j : CL.children[i]) goff[j] = -1;
+    for (int32_t j : ghosts) goff[j] = -1;
+    CL.no_max = std::max(CL.no_max, CL.no[i]);
+  }
+  J.ng = CL.ng;
+  REQUIRE(CL.no_max <= 512, "coarse subdomain with more than 512 owned functions");
+  DVec<double> Abar;
+  run_assemble(c, J, PL, Abar);
+  // GEVP on the generating systems
+  std::vector<int64_t> soff(Pc + 1, 0), lamoff(Pc + 1, 0);
+  CL.h_loff.assign(Pc + 1, 0);
+  for (int i = 0; i < Pc; ++i) {
+    const int64_t ng = CL.ng[i], no = CL.no[i], ngh = ng - no;
+    soff[i + 1] = soff[i] + ngh * ngh + ngh * no + 4 * no * no + std::max(ngh, no) + 2;
+    CL.h_loff[i + 1] = CL.h_loff[i] + no * no;
+    lamoff[i + 1] = lamoff[i] + no;
+  }
+  DVec<int32_t> dng, dno;
+  DVec<int64_t> dsoff, dlamoff;
+  dng.upload(CL.ng, s);
+  dno.upload(CL.no, s);
+  dsoff.upload(soff, s);
+  dlamoff.upload(lamoff, s);
+  CL.loff.upload(CL.h_loff, s);
+  CL.dno.upload(CL.no, s);
+  DVec<double> scratch;
+  scratch.alloc(std::max<int64_t>(soff.back(), 1));
+  CL.Lo.alloc(std::max<int64_t>(CL.h_loff.back(), 1));
+  CL.lam.alloc(std::max<int64_t>(lamoff.back(), 1));
+  DVec<int> mo, st, rk;
+  mo.alloc(Pc);
+  st.alloc(Pc);
+  rk.alloc(Pc);
+  st.zero(s);
+  DVec<int64_t> aoff;
+  aoff.upload(J.aoff, s);
+  {
+    ProfScope pscope(c, PR_COARSE);
+    launch_coarse_gevp(s, Pc, dng.p, dno.p, aoff.p, Abar.p, CL.loff.p, CL.Lo.p, dsoff.p,
+                       scratch.p, c->eta, c->opt.nev_max, c->opt.eps_reg_rel, CL.lam.p, dlamoff.p,
+                       mo.p, st.p, rk.p);
+  }
+  HIPCHK(hipGetLastError());
+  std::vector<int> stv = st.download(s);
+  check_status(stv, "coarse GEVP (Cholesky of the owned block)");
+  CL.m = mo.download(s);
+  CL.rank = rk.download(s);
+  std::vector<double> lamh = CL.lam.download(s);
+  CL.h_lam.assign(Pc, {});
+  for (int i = 0; i < Pc; ++i) CL.h_lam[i].assign(lamh.begin() + lamoff[i], lamh.begin() + lamoff[i + 1]);
+  CL.h_yoff.assign(Pc + 1, 0);
+  CL.h_moff.assign(Pc + 1, 0);
+  for (int i = 0; i < Pc; ++i) {
+    CL.h_yoff[i + 1] = CL.h_yoff[i] + (int64_t)CL.no[i] * CL.m[i];
+    CL.h_moff[i + 1] = CL.h_moff[i] + CL.m[i];
+  }
+  CL.yoff.upload(CL.h_yoff, s);
+  CL.moff.upload(CL.h_moff, s);
+  CL.dm.upload(CL.m, s);
+  CL.own_ptr.upload(CL.h_own_ptr, s);
+  CL.own_idx.upload(CL.h_own_idx, s);
+  CL.Y.alloc(std::max<int64_t>(CL.h_yoff.back(), 1));
+  launch_coarse_collect(s, Pc, dng.p, dno.p, dsoff.p, scratch.p, CL.dm.p, CL.yoff.p, CL.Y.p);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  // patches of level l from those of level l+1, grouped by parent sets
+  std::map<std::vector<int32_t>, int> key;
+  PLnext.members.clear();
+  PLnext.children.clear();
+  std::vector<int32_t> cpar(PL.np);
+  for (int p = 0; p < PL.np; ++p) {
+    std::vector<int32_t> ps;
+    for (int32_t j : PL.members[p]) ps.push_back(par[j]);
+    std::sort(ps.begin(), ps.end());
+    ps.erase(std::unique(ps.begin(), ps.end()), ps.end());
+    auto it = key.find(ps);
+    int id;
+    if (it == key.end()) {
+      id = (int)PLnext.members.size();
+      key.emplace(ps, id);
+      PLnext.members.push_back(ps);
+      PLnext.children.push_back({});
+    } else {
+      id = it->second;
+    }
+    PLnext.children[id].push_back(p);
+    cpar[p] = id;
+  }
+  PLnext.np = (int)PLnext.members.size();
+  PLnext.M.assign(PLnext.np, 0);
+  PLnext.mcol.assign(PLnext.np, {});
+  PLnext.pmoff.assign(PLnext.np + 1, 0);
+  std::vector<int64_t> pmem_ptr(PLnext.np + 1, 0), ch_ptr(PLnext.np + 1, 0), wsoff(PLnext.np + 1, 0);
+  std::vector<int32_t> pmem_sub, pmem_col, ch_patch;
+  for (int q = 0; q < PLnext.np; ++q) {
+    int M = 0;
+    for (int32_t i : PLnext.members[q]) {
+      PLnext.mcol[q].push_back(M);
+      pmem_sub.push_back(i);
+      pmem_col.push_back(M);
+      M += CL.m[i];
+    }
+    PLnext.M[q] = M;
+    pmem_ptr[q + 1] = (int64_t)pmem_sub.size();
+    PLnext.pmoff[q + 1] = PLnext.pmoff[q] + (int64_t)M * M;
+    int64_t wmax = 0;
+    for (int p : PLnext.children[q]) {
+      ch_patch.push_back(p);
+      wmax = std::max<int64_t>(wmax, (int64_t)PL.M[p] * M);
+    }
+    ch_ptr[q + 1] = (int64_t)ch_patch.size();
+    wsoff[q + 1] = wsoff[q] + wmax;
+  }
+  // child patch member info: parent slot, position within the parent's owned list
+  std::vector<int32_t> ownbase(Pf, 0);
+  for (int i = 0; i < Pc; ++i) {
+    int off = 0;
+    for (int32_t j : CL.children[i]) {
+      ownbase[j] = off;
+      off += m_fine_lvl[j];
+    }
+  }
+  std::vector<int64_t> cmem_ptr(PL.np + 1, 0);
+  std::vector<int32_t> cmem_pslot, cmem_ownbase, cmem_m, cmem_col;
+  for (int p = 0; p < PL.np; ++p) {
+    const auto& pm = PLnext.members[cpar[p]];
+    for (size_t sidx = 0; sidx < PL.members[p].size(); ++sidx) {
+      const int32_t j = PL.members[p][sidx];
+      const int ps = (int)(std::lower_bound(pm.begin(), pm.end(), par[j]) - pm.begin());
+      cmem_pslot.push_back(ps);
+      cmem_ownbase.push_back(ownbase[j]);
+      cmem_m.push_back(m_fine_lvl[j]);
+      cmem_col.push_back(PL.mcol[p][sidx]);
+    }
+    cmem_ptr[p + 1] = (int64_t)cmem_pslot.size();
+  }
+  DVec<int64_t> dch_ptr, dcmem_ptr, dpmem_ptr, dwsoff;
+  DVec<int32_t> dch_patch, dcmem_pslot, dcmem_ownbase, dcmem_m, dcmem_col, dpmem_sub, dpmem_col;
+  dch_ptr.upload(ch_ptr, s);
+  dcmem_ptr.upload(cmem_ptr, s);
+  dpmem_ptr.upload(pmem_ptr, s);
+  dwsoff.upload(wsoff, s);
+  dch_patch.upload(ch_patch, s);
+  dcmem_pslot.upload(cmem_pslot, s);
+  dcmem_ownbase.upload(cmem_ownbase, s);
+  dcmem_m.upload(cmem_m, s);
+  dcmem_col.upload(cmem_col, s);
+  dpmem_sub.upload(pmem_sub, s);
+  dpmem_col.upload(pmem_col, s);
+  PLnext.dM.upload(PLnext.M, s);
+  PLnext.dpmoff.upload(PLnext.pmoff, s);
+  PLnext.Pm.alloc(std::max<int64_t>(PLnext.pmoff.back(), 1));
+  DVec<double> Wsc;
+  Wsc.alloc(std::max<int64_t>(wsoff.back(), 1));
+  {
+  ProfScope pscope2(c, PR_PATCH);
+  launch_patch_project(s, PLnext.np, dch_ptr.p, dch_patch.p, PL.dM.p, PL.dpmoff.p, PL.Pm.p,
+                       dcmem_ptr.p, dcmem_pslot.p, dcmem_ownbase.p, dcmem_m.p, dcmem_col.p,
+                       dpmem_ptr.p, dpmem_sub.p, dpmem_col.p, nullptr, CL.dno.p, CL.yoff.p, CL.Y.p,
+                       PLnext.dM.p, PLnext.dpmoff.p, PLnext.Pm.p, dwsoff.p, Wsc.p);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+void coarsest(msdd_ctx* c, const PatchLevel& PL, const std::vector<int32_t>& m_lvl1) {
+  hipStream_t s = c->stream;
+  const int P1 = (int)m_lvl1.size();
+  std::vector<int64_t> moff(P1 + 1, 0);
+  for (int i = 0; i < P1; ++i) moff[i + 1] = moff[i] + m_lvl1[i];
+  const int n0 = (int)moff.back();
+  c->n0 = n0;
+  AssembleJob J;
+  J.ng = {n0};
+  J.aoff = {0, (int64_t)n0 * n0};
+  J.tp_ptr = {0, (int64_t)PL.np};
+  for (int p = 0; p < PL.np; ++p) {
+    J.tp_patch.push_back(p);
+    J.tp_map_off.push_back((int64_t)J.tp_map.size());
+    for (int32_t i : PL.members[p])
+      for (int q = 0; q < m_lvl1[i]; ++q) J.tp_map.push_back((int32_t)(moff[i] + q));
+  }
+  if (n0 == 0) {
+    c->A0.alloc(1);
+    return;
+  }
+  REQUIRE(n0 <= 16384, "coarsest space larger than 16384 (add a level)");
+  run_assemble(c, J, PL, c->A0);
+  DVec<int> st;
+  st.alloc(1);
+  {
+    ProfScope ps(c, PR_COARSE, 2.0 * n0 * (double)n0 * 8.0, (double)n0 * n0 * n0 / 3.0);
+    launch_dense_cholesky(s, n0, c->A0.p, st.p);
+  }
+  HIPCHK(hipGetLastError());
+  std::vector<int> v = st.download(s);
+  if (v[0] != ST_DONE) throw MsddError{MSDD_ENOTSPD, "coarsest matrix A_0 is not positive definite"};
+}
+
+void alloc_solve_work(msdd_ctx* c) {
+  const int L = c->n_levels - 1;
+  c->rlev.clear();
+  c->zlev.clear();
+  c->rlev.resize(L);
+  c->zlev.resize(L);
+  for (int l = 0; l < L; ++l) {
+    c->rlev[l].alloc(std::max<int64_t>(c->nlev[l], 1));
+    c->zlev[l].alloc(std::max<int64_t>(c->nlev[l], 1));
+  }
+  c->u.alloc(std::max<int64_t>(c->F.h_doff.back(), 1));
+  const int64_t n = c->n;
+  c->r.alloc(n);
+  c->z.alloc(n);
+  c->p.alloc(n);
+  c->q.alloc(n);
+  c->x.alloc(n);
+  c->bvec.alloc(n);
+  c->partial.alloc(2048);
+  c->sc.alloc(16);
+  if (!c->h_pinned) HIPCHK(hipHostMalloc((void**)&c->h_pinned, 64 * sizeof(double), hipHostMallocDefault));
+}
+
+// z = B r (Sec. 2.1, additive over all levels)
+void apply_prec(msdd_ctx* c, const double* r, double* z) {
+  hipStream_t s = c->stream;
+  FineLevel& F = c->F;
+  const int L = c->n_levels - 1;
+  double* rc_top = c->rlev[L - 1].p;  // level L-1 vector
+  {
+    ProfScope ps(c, PR_APPLY_FINE,
+                 2.0 * F.s_dband * 8.0 + F.s_nd * 12.0 + F.s_ndm * 8.0 + F.s_nd * 8.0 + F.s_m * 8.0,
+                 4.0 * F.s_ndbd + 2.0 * F.s_ndm);
+    launch_apply_fine_down(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dglob.p,
+                           F.dboff.p, F.LDc.p, F.LDr.p, F.dm.p, F.moff.p, F.phid_off.p, F.PhiD.p,
+                           r, rc_top, c->u.p);
+  }
+  {
+    ProfScope ps(c, PR_APPLY_COARSE);
+    // coarse levels, downward: C[t] is level L-1-t
+    for (int t = 0; t < (int)c->C.size(); ++t) {
+      CoarseLevel& CL = c->C[t];
+      const int l = CL.level;
+      launch_apply_coarse_down(s, CL.P, CL.no_max, CL.dno.p, CL.own_ptr.p, CL.own_idx.p,
+                               CL.loff.p, CL.Lo.p, CL.dm.p, CL.yoff.p, CL.Y.p, CL.moff.p,
+                               c->rlev[l].p, c->zlev[l].p, c->rlev[l - 1].p);
+    }
+    launch_apply_coarsest(s, c->n0, c->A0.p, c->rlev[0].p, c->zlev[0].p);
+    for (int t = (int)c->C.size() - 1; t >= 0; --t) {
+      CoarseLevel& CL = c->C[t];
+      const int l = CL.level;
+      launch_apply_coarse_up(s, CL.P, CL.dno.p, CL.own_ptr.p, CL.own_idx.p, CL.dm.p, CL.yoff.p,
+                             CL.Y.p, CL.moff.p, c->zlev[l - 1].p, c->zlev[l].p);
+    }
+  }
+  {
+    ProfScope ps(c, PR_APPLY_GATHER,
+                 (double)(c->n + 1) * 8.0 + F.s_nd * 16.0 + F.s_ndm * 8.0 + c->n * 8.0 + F.s_m * 8.0,
+                 2.0 * F.s_ndm + F.s_nd);
+    launch_apply_fine_up(s, c->n, F.dinc_ptr.p, F.dinc_sub.p, F.dinc_q.p, F.doff.p, F.dm.p,
+                         F.moff.p, F.phid_off.p, F.PhiD.p, c->u.p, c->zlev[L - 1].p, z);
+  }
+}
+
+double read_scalar(msdd_ctx* c, int slot) {
+  HIPCHK(hipMemcpyAsync(c->h_pinned, c->sc.p + slot, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return c->h_pinned[0];
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void msdd_default_options(msdd_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = MSDD_FP64;
+  o->sigma = 0.0;
+  o->eps_reg_rel = 1e-12;
+  o->nev_max = 0;
+  o->eig_tol = 1e-14;
+  o->eig_maxit = 200;
+  o->block = 16;
+  o->device = 0;
+  o->stream = nullptr;
+  o->verbose = 0;
+}
+
+int msdd_create(msdd_ctx** out, const msdd_options* opt) {
+  if (!out) return MSDD_EINVAL;
+  *out = nullptr;
+  msdd_ctx* c = new (std::nothrow) msdd_ctx();
+  if (!c) return MSDD_ENOMEM;
+  if (opt) c->opt = *opt;
+  else msdd_default_options(&c->opt);
+  std::memset(&c->stats, 0, sizeof(c->stats));
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+    (void)hipGetLastError();
+    delete c;
+    return MSDD_EDEVICE;
+  }
+  if (c->opt.device < 0 || c->opt.device >= ndev || hipSetDevice(c->opt.device) != hipSuccess) {
+    delete c;
+    return MSDD_EDEVICE;
+  }
+  if (c->opt.precision != MSDD_FP64 && c->opt.precision != MSDD_MIXED) {
+    delete c;
+    return MSDD_EINVAL;
+  }
+  c->stream = (hipStream_t)c->opt.stream;
+  *out = c;
+  return MSDD_OK;
+}
+
+int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col,
+               const double* val, int32_t n_elem, int32_t k, const int32_t* elem_dofs,
+               const double* elem_mat, int32_t n_sub, const int64_t* sub_elem_ptr,
+               const int32_t* sub_elem, const int64_t* sub_dof_ptr, const int32_t* sub_dof,
+               const double* sub_pou, int32_t n_levels, const int32_t* parent, double eta) {
+  if (!c) return MSDD_EINVAL;
+  c->ready = false;
+  c->err.clear();
+  try {
+    HIPCHK(hipSetDevice(c->opt.device));
+    const double t0 = now_ms();
+    REQUIRE(n > 0 && n < (int64_t)1 << 31, "n out of range");
+    REQUIRE(n_elem > 0 && k > 0 && k <= 81, "bad element count or size");
+    REQUIRE(n_sub > 0, "n_sub must be positive");
+    REQUIRE(n_levels >= 2 && n_levels <= 8, "n_levels must be in [2, 8]");
+    REQUIRE(eta > 0 && std::isfinite(eta), "eta must be positive");
+    REQUIRE(c->opt.eig_maxit > 0 && c->opt.eig_tol > 0, "bad eigensolver options");
+    c->n = n;
+    c->k = k;
+    c->eta = eta;
+    c->sigma = c->opt.sigma > 0 ? c->opt.sigma : 0.1 * eta;
+    c->n_levels = n_levels;
+    hipStream_t s = c->stream;
+    // host copies of the index arrays (planning)
+    std::vector<int64_t> h_rowptr = to_host(rowptr, (size_t)n + 1);
+    REQUIRE(h_rowptr[0] == 0, "rowptr[0] must be 0");
+    for (int64_t i = 0; i < n; ++i) REQUIRE(h_rowptr[i + 1] >= h_rowptr[i], "rowptr not monotone");
+    c->nnz = h_rowptr[n];
+    std::vector<int32_t> ed = to_host(elem_dofs, (size_t)n_elem * k);
+    std::vector<int64_t> sep = to_host(sub_elem_ptr, (size_t)n_sub + 1);
+    std::vector<int64_t> sdp = to_host(sub_dof_ptr, (size_t)n_sub + 1);
+    REQUIRE(sep[0] == 0 && sdp[0] == 0, "subdomain pointers must start at 0");
+    std::vector<int32_t> se = to_host(sub_elem, (size_t)sep[n_sub]);
+    std::vector<int32_t> sd = to_host(sub_dof, (size_t)sdp[n_sub]);
+    std::vector<double> sw = to_host(sub_pou, (size_t)sdp[n_sub]);
+    std::vector<std::vector<int32_t>> parents;
+    {
+      int cnt = n_sub;
+      size_t off = 0;
+      std::vector<int32_t> all;
+      for (int l = 0; l < n_levels - 2; ++l) {
+        std::vector<int32_t> pm = to_host(parent + off, (size_t)cnt);
+        int mx = -1;
+        for (int32_t v : pm) {
+          REQUIRE(v >= 0 && v < cnt, "parent index out of range");
+          mx = std::max(mx, v);
+        }
+        parents.push_back(pm);
+        off += cnt;
+        cnt = mx + 1;
+      }
+    }
+    // device copies kept by the context
+    to_device(c->rowptr, rowptr, (size_t)n + 1, s);
+    to_device(c->col, col, (size_t)c->nnz, s);
+    to_device(c->val, val, (size_t)c->nnz, s);
+    DVec<double> emat_holder;
+    const double* d_emat = elem_mat;
+    if (!is_device_ptr(elem_mat)) {
+      to_device(emat_holder, elem_mat, (size_t)n_elem * k * k, s);
+      d_emat = emat_holder.p;
+    }
+    const double avg = (double)c->nnz / (double)n;
+    c->spmv_sg = avg <= 6 ? 4 : (avg <= 14 ? 8 : (avg <= 40 ? 16 : 32));
+    // finest level
+    c->F = FineLevel();
+    c->F.P = n_sub;
+    plan_fine(c, n_elem, ed, sep, se, sdp, sd, sw);
+    HIPCHK(hipStreamSynchronize(s));
+    const double t1 = now_ms();
+    fine_local_matrices(c, d_emat);
+    HIPCHK(hipStreamSynchronize(s));
+    const double t2 = now_ms();
+    fine_eigensolve(c);
+    HIPCHK(hipStreamSynchronize(s));
+    const double t3 = now_ms();
+    // coarse levels
+    const int L = n_levels - 1;
+    c->C.clear();
+    c->C.resize(L - 1);
+    PatchLevel PL;
+    fine_patches(c, ed, n_elem, d_emat, PL);
+    std::vector<int32_t> m_cur = c->F.m;
+    std::vector<int64_t> moff_cur = c->F.h_moff;
+    for (int t = 0; t < L - 1; ++t) {
+      const int l = L - 1 - t;
+      PatchLevel PLn;
+      coarse_level(c, l, parents[t], m_cur, moff_cur, PL, c->C[t], PLn);
+      PL = std::move(PLn);
+      m_cur = c->C[t].m;
+      moff_cur = c->C[t].h_moff;
+    }
+    coarsest(c, PL, m_cur);
+    HIPCHK(hipStreamSynchronize(s));
+    const double t4 = now_ms();
+    // level sizes
+    c->nlev.assign(L + 1, 0);
+    c->nlev[L] = n;
+    c->nlev[L - 1] = c->F.h_moff.back();
+    for (int t = 0; t < L - 1; ++t) c->nlev[L - 2 - t] = c->C[t].h_moff.back();
+    alloc_solve_work(c);
+    HIPCHK(hipStreamSynchronize(s));
+    const double t5 = now_ms();
+    msdd_stats_t& st = c->stats;
+    st.n_levels = n_levels;
+    for (int l = 0; l <= L && l < 8; ++l) st.n[l] = c->nlev[l];
+    st.n_sub[L] = n_sub;
+    st.n_sub[0] = 1;
+    int mm = 0;
+    for (int v : c->F.m) mm = std::max(mm, v);
+    st.m_max[L] = mm;
+    st.max_local[L] = c->F.nb_max;
+    for (int t = 0; t < L - 1; ++t) {
+      const int l = L - 1 - t;
+      st.n_sub[l] = c->C[t].P;
+      int m2 = 0, g2 = 0;
+      for (int v : c->C[t].m) m2 = std::max(m2, v);
+      for (int v : c->C[t].ng) g2 = std::max(g2, v);
+      st.m_max[l] = m2;
+      st.max_local[l] = g2;
+    }
+    st.max_band = c->F.bw_max;
+    st.t_plan_ms = t1 - t0;
+    st.t_local_ms = t2 - t1;
+    st.t_gevp_ms = t3 - t2;
+    st.t_coarse_ms = t4 - t3;
+    st.t_setup_ms = t5 - t0;
+    c->ready = true;
+    if (c->opt.verbose)
+      std::fprintf(stderr, "msdd setup: plan %.2f local %.2f gevp %.2f coarse %.2f total %.2f ms, n0=%d\n",
+                   st.t_plan_ms, st.t_local_ms, st.t_gevp_ms, st.t_coarse_ms, st.t_setup_ms, c->n0);
+    return MSDD_OK;
+  } catch (const MsddError& e) {
+    return code_for(c, e);
+  } catch (const std::exception& e) {
+    return code_for(c, MsddError{MSDD_ENOMEM, e.what()});
+  }
+}
+
+int msdd_apply(msdd_ctx* c, const double* r, double* z) {
+  if (!c) return MSDD_EINVAL;
+  if (!c->ready) return code_for(c, MsddError{MSDD_ESTATE, "msdd_apply before a successful setup"});
+  try {
+    HIPCHK(hipSetDevice(c->opt.device));
+    hipStream_t s = c->stream;
+    const int64_t n = c->n;
+    const bool rdev = is_device_ptr(r), zdev = is_device_ptr(z);
+    const double* rin = r;
+    if (!rdev) {
+      HIPCHK(hipMemcpyAsync(c->r.p, r, n * sizeof(double), hipMemcpyHostToDevice, s));
+      rin = c->r.p;
+    }
+    double* zout = zdev ? z : c->z.p;
+    apply_prec(c, rin, zout);
+    HIPCHK(hipGetLastError());
+    if (!zdev) HIPCHK(hipMemcpyAsync(z, zout, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MSDD_OK;
+  } catch (const MsddError& e) {
+    return code_for(c, e);
+  }
+}
+
+int msdd_solve(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit,
+               int32_t* iters, double* relres) {
+  if (!c) return MSDD_EINVAL;
+  if (!c->ready) return code_for(c, MsddError{MSDD_ESTATE, "msdd_solve before a successful setup"});
+  try {
+    HIPCHK(hipSetDevice(c->opt.device));
+    REQUIRE(b && x && rtol > 0 && maxit >= 0, "bad solve arguments");
+    hipStream_t s = c->stream;
+    const double t0 = now_ms();
+    const int64_t n = c->n;
+    const bool bdev = is_device_ptr(b), xdev = is_device_ptr(x);
+    const double* bb = b;
+    if (!bdev) {
+      HIPCHK(hipMemcpyAsync(c->bvec.p, b, n * sizeof(double), hipMemcpyHostToDevice, s));
+      bb = c->bvec.p;
+    }
+    double* xx = xdev ? x : c->x.p;
+    if (!xdev) HIPCHK(hipMemcpyAsync(xx, x, n * sizeof(double), hipMemcpyHostToDevice, s));
+    const int np = pcg_grid(n);
+    double* part = c->partial.p;
+    double* sc = c->sc.p;
+    // r = b - A x
+    launch_spmv_dot(s, n, c->spmv_sg, c->rowptr.p, c->col.p, c->val.p, xx, c->q.p, part, 0);
+    launch_residual(s, n, bb, c->q.p, c->r.p, part);
+    launch_reduce(s, part, np, sc, PCG_SC_RR0, PCG_RED_SET);
+    const double rr0 = read_scalar(c, PCG_SC_RR0);
+    REQUIRE(std::isfinite(rr0), "non-finite right-hand side or initial guess");
+    int it = 0;
+    double rel = 0.0;
+    bool conv = rr0 == 0.0;
+    if (!conv) {
+      apply_prec(c, c->r.p, c->z.p);
+      launch_dot(s, n, c->r.p, c->z.p, part);
+      launch_reduce(s, part, np, sc, PCG_SC_RZ, PCG_RED_SET);
+      launch_update_p(s, n, c->z.p, c->p.p, sc, 0);
+      const double tol2 = rtol * rtol * rr0;
+      const double spmv_bytes = (double)c->nnz * 12.0 + (double)(n + 1) * 8.0 + 2.0 * n * 8.0;
+      for (it = 1; it <= maxit; ++it) {
+        {
+          ProfScope ps(c, PR_SPMV, spmv_bytes, 2.0 * c->nnz);
+          launch_spmv_dot(s, n, c->spmv_sg, c->rowptr.p, c->col.p, c->val.p, c->p.p, c->q.p, part, 1);
+        }
+        {
+          ProfScope ps(c, PR_VEC, 6.0 * n * 8.0, 6.0 * n);
+          launch_reduce(s, part, np, sc, 0, PCG_RED_ALPHA);
+          launch_update_xr(s, n, xx, c->r.p, c->p.p, c->q.p, sc, part);
+          launch_reduce(s, part, np, sc, PCG_SC_RR, PCG_RED_SET);
+        }
+        const double rr = read_scalar(c, PCG_SC_RR);
+        REQUIRE(std::isfinite(rr), "PCG produced a non-finite residual");
+        rel = std::sqrt(rr / rr0);
+        if (rr < tol2) {
+          conv = true;
+          break;
+        }
+        apply_prec(c, c->r.p, c->z.p);
+        {
+          ProfScope ps(c, PR_VEC, 5.0 * n * 8.0, 4.0 * n);
+          launch_dot(s, n, c->r.p, c->z.p, part);
+          launch_reduce(s, part, np, sc, 0, PCG_RED_BETA);
+          launch_update_p(s, n, c->z.p, c->p.p, sc, 1);
+        }
+      }
+      if (!conv) it = maxit;
+    }
+    HIPCHK(hipGetLastError());
+    if (!xdev) HIPCHK(hipMemcpyAsync(x, xx, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    c->stats.pcg_iters = it;
+    c->stats.pcg_relres = rel;
+    c->stats.t_solve_ms = now_ms() - t0;
+    if (!conv) return code_for(c, MsddError{MSDD_ENOCONV, "PCG reached maxit"});
+    return MSDD_OK;
+  } catch (const MsddError& e) {
+    return code_for(c, e);
+  }
+}
+
+int msdd_stats(const msdd_ctx* c, msdd_stats_t* out) {
+  if (!c || !out) return MSDD_EINVAL;
+  *out = c->stats;
+  return MSDD_OK;
+}
+
+int msdd_get_level_counts(const msdd_ctx* c, int32_t level, int32_t* m) {
+  if (!c || !m || !c->ready) return MSDD_EINVAL;
+  const int L = c->n_levels - 1;
+  if (level == L) {
+    for (size_t i = 0; i < c->F.m.size(); ++i) m[i] = c->F.m[i];
+    return MSDD_OK;
+  }
+  for (const auto& CL : c->C)
+    if (CL.level == level) {
+      for (size_t i = 0; i < CL.m.size(); ++i) m[i] = CL.m[i];
+      return MSDD_OK;
+    }
+  return MSDD_EINVAL;
+}
+
+int msdd_get_eigs(const msdd_ctx* c, int32_t level, int32_t i, int32_t n_extra, double* lam,
+                  int32_t* count) {
+  if (!c || !lam || !count || !c->ready || n_extra < 0) return MSDD_EINVAL;
+  const int L = c->n_levels - 1;
+  const std::vector<double>* src = nullptr;
+  int m = 0;
+  if (level == L) {
+    if (i < 0 || i >= c->F.P) return MSDD_EINVAL;
+    src = &c->F.lam[i];
+    m = c->F.m[i];
+  } else {
+    for (const auto& CL : c->C)
+      if (CL.level == level) {
+        if (i < 0 || i >= CL.P) return MSDD_EINVAL;
+        src = &CL.h_lam[i];
+        m = CL.m[i];
+      }
+  }
+  if (!src) return MSDD_EINVAL;
+  const int cnt = std::min<int>((int)src->size(), m + n_extra);
+  for (int a = 0; a < cnt; ++a) lam[a] = (*src)[a];
+  *count = cnt;
+  return MSDD_OK;
+}
+
+int msdd_get_basis(const msdd_ctx* c, int32_t level, int32_t i, double* basis, int32_t* rows,
+                   int32_t* cols) {
+  if (!c || !rows || !cols || !c->ready) return MSDD_EINVAL;
+  const int L = c->n_levels - 1;
+  try {
+    if (level == L) {
+      if (i < 0 || i >= c->F.P) return MSDD_EINVAL;
+      *rows = c->F.gs.h_n[i];
+      *cols = c->F.m[i];
+      if (basis && (*rows) * (*cols) > 0)
+        HIPCHK(hipMemcpy(basis, c->F.Phi.p + c->F.h_phi_off[i], sizeof(double) * (*rows) * (*cols),
+                         hipMemcpyDeviceToHost));
+      return MSDD_OK;
+    }
+    for (const auto& CL : c->C)
+      if (CL.level == level) {
+        if (i < 0 || i >= CL.P) return MSDD_EINVAL;
+        *rows = CL.no[i];
+        *cols = CL.m[i];
+        if (basis && (*rows) * (*cols) > 0)
+          HIPCHK(hipMemcpy(basis, CL.Y.p + CL.h_yoff[i], sizeof(double) * (*rows) * (*cols),
+                           hipMemcpyDeviceToHost));
+        return MSDD_OK;
+      }
+  } catch (const MsddError& e) {
+    return e.code;
+  }
+  return MSDD_EINVAL;
+}
+
+int msdd_profile(msdd_ctx* c, int enable) {
+  if (!c) return MSDD_EINVAL;
+  try {
+    c->prof.reset();
+    c->prof.on = enable != 0;
+    return MSDD_OK;
+  } catch (const MsddError& e) {
+    return code_for(c, e);
+  }
+}
+
+int msdd_profile_query(msdd_ctx* c, int id, double* total_ms, int64_t* launches,
+                       double* alg_bytes, double* alg_flops) {
+  if (!c || id < 0 || id >= PR_COUNT) return MSDD_EINVAL;
+  try {
+    c->prof.resolve();
+  } catch (const MsddError& e) {
+    return code_for(c, e);
+  }
+  if (total_ms) *total_ms = c->prof.ms[id];
+  if (launches) *launches = c->prof.cnt[id];
+  if (alg_bytes) *alg_bytes = c->prof.bytes[id];
+  if (alg_flops) *alg_flops = c->prof.flops[id];
+  return MSDD_OK;
+}
+
+const char* msdd_profile_name(int id) { return (id >= 0 && id < PR_COUNT) ? kProfNames[id] : nullptr; }
+
+const char* msdd_last_error(const msdd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void msdd_destroy(msdd_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->opt.device);
+  (void)hipDeviceSynchronize();
+  delete c;
+}
+
+}  // extern "C"
