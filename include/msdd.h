@@ -64,8 +64,9 @@ typedef struct {
   int precision;      /* MSDD_FP64 or MSDD_MIXED */
   double sigma;       /* spectral shift of the local pencil S = abar + sigma*b (> 0);
                          <= 0 selects 0.1*eta.  Eigenvalues do not depend on it. */
-  double eps_reg_rel; /* coarse generating-system: ghost pivots below eps_reg_rel times
-                         the largest ghost diagonal are treated as zero (default 1e-12) */
+  double eps_reg_rel; /* coarse generating systems: eigenvectors of abar + b with an
+                         eigenvalue below eps_reg_rel times the largest are treated as their
+                         common kernel and removed (default 1e-12) */
   int nev_max;        /* 0 = threshold selection only; > 0 caps eigenvectors per subdomain */
   double eig_tol;     /* tolerance on the normwise backward error
                          ||b x - nu S x|| / (nu ||S|| ||x||) of the local eigenpairs

@@ -11,12 +11,11 @@
 // Sec. 4.2: on levels l < L the Neumann space is spanned by a generating
 // system (owned functions plus restrictions of the neighbours' functions), so
 // ker A cap ker B != {0}.  With the 0/1 owned mask as partition of unity,
-// B = [[A_oo, 0], [0, 0]] and the finite spectrum of A x = lambda B x is that of
-// the generalized Schur pencil (A_oo - A_og A_gg^- A_go) y = lambda A_oo y,
-// which is independent of the choice of generalized inverse; we take the one
-// of a diagonally pivoted Cholesky factorisation of A_gg (pivots below
-// eps_reg * max diag treated as zero), which plays the role of the paper's
-// regularised LDL^T.
+// B = [[A_oo, 0], [0, 0]].  The common kernel is removed by compression: the
+// eigenvectors of A + B whose eigenvalue is below eps_reg times the largest are
+// dropped (in exact arithmetic exactly ker A cap ker B, the mu = 0 part of the
+// paper's regularised transformation), and the definite pencil is solved on
+// the rest.
 #include "common.h"
 #include "jacobi.h"
 #include "kernels.h"
@@ -251,230 +250,216 @@ __global__ void k_dense_cholesky(int n, double* A, int* status) {
   if (threadIdx.x == 0) status[0] = ok ? ST_DONE : ST_NOTSPD;
 }
 
-// Coarse GEVP of one level-(l-1) subdomain per workgroup (see file header).
-// Abar: ng x ng column-major, owned functions first (no of them).
-// Outputs: Lo (no x no, lower Cholesky factor of A_oo, column-major),
-// Yout (no x m, column-major: selected eigenvectors, b-normalised),
-// lam (no entries, ascending), m, rank of the ghost block.
+// Coarse GEVP of one level-(l-1) subdomain per workgroup, on its generating system
+// (owned functions first, no of them; Abar is ng x ng column-major):
+//   S = Abar + B with B = D Abar D, D the 0/1 owned mask;
+//   S = Q diag(s) Q^T (Jacobi); keep s > tau * max(s) (the rest is the numerical
+//   kernel of abar and b, their common kernel in exact arithmetic);
+//   Qk = Q_keep diag(s_keep)^{-1/2};  C = Qk^T B Qk = Qk_o^T A_oo Qk_o;
+//   C = Y diag(mu) Y^T (Jacobi);  lambda = 1/mu - 1;  select lambda < eta;
+//   x = Qk y / sqrt(mu) (b-normalised); the coarse basis block is x on the owned rows.
+// The owned block A_oo is the level's Dirichlet matrix; its Cholesky factor is kept.
+// Scratch layout per target (doubles): S ng^2 | Q ng^2 | Qk ng^2 | C ng^2 | Yc ng^2 | ints ng.
 __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restrict__ no_arr,
                               const i64* __restrict__ aoff, double* __restrict__ Abar,
                               const i64* __restrict__ loff, double* __restrict__ Lo,
                               const i64* __restrict__ soff, double* __restrict__ scratch,
-                              double eta, int nev_max, double eps_reg,
+                              double eta, int nev_max, double tau,
                               double* __restrict__ lam_out, const i64* __restrict__ lamoff,
                               int* __restrict__ m_out, int* __restrict__ status,
                               int* __restrict__ rank_out) {
   const int t = blockIdx.x;
   const int ng = ng_arr[t], no = no_arr[t];
-  const int ngh = ng - no;
-  double* A = Abar + aoff[t];
+  const double* A = Abar + aoff[t];
   double* L = Lo + loff[t];
-  double* G = scratch + soff[t];             // ngh*ngh
-  double* Z = G + (i64)ngh * ngh;            // ngh*no  (rows: pivoted ghosts)
-  double* Sc = Z + (i64)ngh * no;            // no*no
-  double* Mm = Sc + (i64)no * no;            // no*no (row-major for Jacobi)
-  double* Qm = Mm + (i64)no * no;            // no*no
-  double* Yt = Qm + (i64)no * no;            // no*no (selected eigenvectors)
-  int* perm = reinterpret_cast<int*>(Yt + (i64)no * no);  // max(ngh, no)
-  __shared__ int sh_rank, sh_piv, sh_fail, cnt;
-  __shared__ double sh_dmax, red_v[16];
-  __shared__ int red_i[16];
-  __shared__ int pp[256], pq[256];
-  __shared__ double pc[256], ps[256];
+  const i64 g2 = (i64)ng * ng;
+  double* S = scratch + soff[t];
+  double* Q = S + g2;
+  double* Qk = Q + g2;
+  double* C = Qk + g2;
+  double* Yc = C + g2;
+  int* keep = reinterpret_cast<int*>(Yc + g2);
+  __shared__ int sh_fail, cnt, sh_r, sh_m;
+  __shared__ double sh_smax, sh_fro, red[32];
+  __shared__ int pp[512], pq[512];
+  __shared__ double pc[512], ps[512];
   const int tid = threadIdx.x, nt = blockDim.x;
   if (no == 0) {
     if (tid == 0) { m_out[t] = 0; status[t] = ST_DONE; rank_out[t] = 0; }
     return;
   }
-  // (a) pivoted Cholesky of the ghost block
-  for (i64 e = tid; e < (i64)ngh * ngh; e += nt) {
-    const int r = (int)(e % ngh), c = (int)(e / ngh);
-    G[e] = A[(no + r) + (i64)(no + c) * ng];
+  // S (row-major, symmetric) and its Frobenius norm
+  double fro = 0.0;
+  for (i64 e = tid; e < g2; e += nt) {
+    const int r = (int)(e / ng), c = (int)(e % ng);
+    const double a = 0.5 * (A[r + (i64)c * ng] + A[c + (i64)r * ng]);
+    const double v = (r < no && c < no) ? 2.0 * a : a;
+    S[e] = v;
+    fro += v * v;
   }
-  for (int r = tid; r < ngh; r += nt) perm[r] = r;
-  if (tid == 0) {
-    double dm = 0;
-    for (int r = 0; r < ngh; ++r) dm = fmax(dm, A[(no + r) + (i64)(no + r) * ng]);
-    sh_dmax = dm;
-    sh_rank = ngh;
-  }
+  fro = block_sum(fro, red);
+  if (tid == 0) sh_fro = sqrt(fro);
   __syncthreads();
-  for (int k = 0; k < ngh; ++k) {
-    // argmax of the remaining diagonal
-    double bv = -1.0;
-    int bi = 0x7fffffff;
-    for (int r = k + tid; r < ngh; r += nt) {
-      const double v = G[r + (i64)r * ngh];
-      if (v > bv || (v == bv && r < bi)) { bv = v; bi = r; }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    if ((tid & 63) == 0) { red_v[tid >> 6] = bv; red_i[tid >> 6] = bi; }
-    __syncthreads();
-    if (tid == 0) {
-      double v0 = red_v[0];
-      int i0 = red_i[0];
-      for (int w = 1; w < nt / 64; ++w)
-        if (red_v[w] > v0 || (red_v[w] == v0 && red_i[w] < i0)) { v0 = red_v[w]; i0 = red_i[w]; }
-      sh_piv = i0;
-      if (!(v0 > eps_reg * sh_dmax)) sh_rank = k;
-    }
-    __syncthreads();
-    if (sh_rank == k) break;
-    const int pv = sh_piv;
-    if (pv != k) {  // symmetric swap of rows/cols k and pv
-      for (int c = tid; c < ngh; c += nt) {
-        const double x = G[k + (i64)c * ngh];
-        G[k + (i64)c * ngh] = G[pv + (i64)c * ngh];
-        G[pv + (i64)c * ngh] = x;
-      }
-      __syncthreads();
-      for (int r = tid; r < ngh; r += nt) {
-        const double x = G[r + (i64)k * ngh];
-        G[r + (i64)k * ngh] = G[r + (i64)pv * ngh];
-        G[r + (i64)pv * ngh] = x;
-      }
-      if (tid == 0) {
-        const int x = perm[k];
-        perm[k] = perm[pv];
-        perm[pv] = x;
-      }
-      __syncthreads();
-    }
-    const double l = sqrt(G[k + (i64)k * ngh]);
-    __syncthreads();
-    for (int r = k + tid; r < ngh; r += nt)
-      G[r + (i64)k * ngh] = (r == k) ? l : G[r + (i64)k * ngh] / l;
-    __syncthreads();
-    const int rem = ngh - k - 1;
-    for (i64 e = tid; e < (i64)rem * rem; e += nt) {
-      const int r = k + 1 + (int)(e % rem), c = k + 1 + (int)(e / rem);
-      if (c <= r) {
-        const double v = G[r + (i64)c * ngh] - G[r + (i64)k * ngh] * G[c + (i64)k * ngh];
-        G[r + (i64)c * ngh] = v;
-        G[c + (i64)r * ngh] = v;
-      }
-    }
-    __syncthreads();
-  }
-  const int rk = sh_rank;
-  // (b) Z = L11^{-1} A_{g1,o}   (rk x no), thread per owned column
-  for (int c = tid; c < no; c += nt) {
-    for (int r = 0; r < rk; ++r) {
-      double v = A[(no + perm[r]) + (i64)c * ng];
-      for (int q = 0; q < r; ++q) v -= G[r + (i64)q * ngh] * Z[q + (i64)c * ngh];
-      Z[r + (i64)c * ngh] = v / G[r + (i64)r * ngh];
-    }
-  }
-  __syncthreads();
-  // (c) Sc = A_oo - Z^T Z ; copy A_oo into L
-  for (i64 e = tid; e < (i64)no * no; e += nt) {
-    const int r = (int)(e % no), c = (int)(e / no);
-    double v = A[r + (i64)c * ng];
-    L[r + (i64)c * no] = 0.5 * (A[r + (i64)c * ng] + A[c + (i64)r * ng]);
-    for (int q = 0; q < rk; ++q) v -= Z[q + (i64)r * ngh] * Z[q + (i64)c * ngh];
-    Sc[e] = v;
-  }
-  __syncthreads();
-  for (i64 e = tid; e < (i64)no * no; e += nt) {
-    const int r = (int)(e % no), c = (int)(e / no);
-    if (r < c) {
-      const double v = 0.5 * (Sc[r + (i64)c * no] + Sc[c + (i64)r * no]);
-      Sc[r + (i64)c * no] = v;
-      Sc[c + (i64)r * no] = v;
-    }
-  }
-  __syncthreads();
-  // (d) Cholesky of A_oo (the level's Dirichlet matrix)
-  if (!dense_cholesky_block(no, L, no, &sh_fail)) {
-    if (tid == 0) { status[t] = ST_NOTSPD; m_out[t] = 0; }
-    return;
-  }
-  // (e) M = L^{-1} Sc L^{-T}: first Sc <- L^{-1} Sc (columns), then M = L^{-1} (Sc)^T
-  for (int c = tid; c < no; c += nt) {
-    for (int r = 0; r < no; ++r) {
-      double v = Sc[r + (i64)c * no];
-      for (int q = 0; q < r; ++q) v -= L[r + (i64)q * no] * Sc[q + (i64)c * no];
-      Sc[r + (i64)c * no] = v / L[r + (i64)r * no];
-    }
-  }
-  __syncthreads();
-  // Mm (row-major): column c of M = L^{-1} (row c of Sc)^T
-  for (int c = tid; c < no; c += nt) {
-    for (int r = 0; r < no; ++r) {
-      double v = Sc[c + (i64)r * no];
-      for (int q = 0; q < r; ++q) v -= L[r + (i64)q * no] * Mm[(i64)q * no + c];
-      Mm[(i64)r * no + c] = v / L[r + (i64)r * no];
-    }
-  }
-  __syncthreads();
-  for (i64 e = tid; e < (i64)no * no; e += nt) {
-    const int r = (int)(e / no), c = (int)(e % no);
-    if (r < c) {
-      const double v = 0.5 * (Mm[(i64)r * no + c] + Mm[(i64)c * no + r]);
-      Mm[(i64)r * no + c] = v;
-      Mm[(i64)c * no + r] = v;
-    }
-  }
-  __syncthreads();
-  // (f) eigenvalues lambda of M (they lie in [0,1])
   JacobiScratch<double> js{pp, pq, pc, ps, &cnt};
-  jacobi_block<double>(no, Mm, Qm, js, 60, 1e-15, 0.0);
-  // (g) sort ascending, select, back-transform y = L^{-T} q into Yt (no x m)
-  double* lam = lam_out + lamoff[t];
+  jacobi_block<double>(ng, S, Q, js, 60, 2.220446049250313e-16, 1e-18 * sh_fro);
   if (tid == 0) {
-    int* ord = perm;  // reuse
-    for (int a = 0; a < no; ++a) ord[a] = a;
-    for (int a = 1; a < no; ++a) {
+    double smax = 0.0;
+    for (int a = 0; a < ng; ++a) smax = fmax(smax, S[(i64)a * ng + a]);
+    int r = 0;
+    for (int a = 0; a < ng; ++a)
+      if (S[(i64)a * ng + a] > tau * smax) keep[r++] = a;
+    sh_smax = smax;
+    sh_r = r;
+  }
+  __syncthreads();
+  const int r = sh_r;
+  // Qk (ng x r, row-major): kept eigenvectors scaled by s^{-1/2}
+  for (i64 e = tid; e < (i64)ng * r; e += nt) {
+    const int row = (int)(e / r), k = (int)(e % r);
+    const int a = keep[k];
+    Qk[e] = Q[(i64)row * ng + a] / sqrt(S[(i64)a * ng + a]);
+  }
+  __syncthreads();
+  // C = Qk_o^T A_oo Qk_o: first Q <- A_oo Qk_o (no x r), then C (r x r, row-major)
+  for (i64 e = tid; e < (i64)no * r; e += nt) {
+    const int row = (int)(e / r), k = (int)(e % r);
+    double acc = 0.0;
+    for (int q = 0; q < no; ++q) acc += 0.5 * (A[row + (i64)q * ng] + A[q + (i64)row * ng]) * Qk[(i64)q * r + k];
+    Q[e] = acc;
+  }
+  __syncthreads();
+  for (i64 e = tid; e < (i64)r * r; e += nt) {
+    const int a = (int)(e / r), b = (int)(e % r);
+    if (a > b) continue;
+    double acc = 0.0;
+    for (int q = 0; q < no; ++q) acc += Qk[(i64)q * r + a] * Q[(i64)q * r + b];
+    C[(i64)a * r + b] = acc;
+    C[(i64)b * r + a] = acc;
+  }
+  __syncthreads();
+  double fc = 0.0;
+  for (i64 e = tid; e < (i64)r * r; e += nt) fc += C[e] * C[e];
+  fc = block_sum(fc, red);
+  jacobi_block<double>(r, C, Yc, js, 60, 2.220446049250313e-16, 1e-18 * sqrt(fc));
+  // sort mu descending, lambda = 1/mu - 1 ascending
+  double* lam = lam_out + lamoff[t];
+  int* ord = keep;  // reused (r entries)
+  if (tid == 0) {
+    for (int a = 0; a < r; ++a) ord[a] = a;
+    for (int a = 1; a < r; ++a) {
       const int v = ord[a];
-      const double lv = Mm[(i64)v * no + v];
+      const double mv = C[(i64)v * r + v];
       int b = a - 1;
-      while (b >= 0 && Mm[(i64)ord[b] * no + ord[b]] > lv) {
+      while (b >= 0 && C[(i64)ord[b] * r + ord[b]] < mv) {
         ord[b + 1] = ord[b];
         --b;
       }
       ord[b + 1] = v;
     }
-    int m = 0;
-    for (int a = 0; a < no; ++a) {
-      const double lv = fmax(Mm[(i64)ord[a] * no + ord[a]], 0.0);
-      lam[a] = lv;
+    int m = 0, nl = 0;
+    for (int a = 0; a < r && nl < no; ++a) {
+      const double mu = C[(i64)ord[a] * r + ord[a]];
+      if (mu <= 1e-12) break;
+      const double lv = fmax(1.0 / mu - 1.0, 0.0);
+      lam[nl++] = lv;
       if (lv < eta) ++m;
     }
+    for (int a = nl; a < no; ++a) lam[a] = INFINITY;
     if (nev_max > 0 && m > nev_max) m = nev_max;
+    sh_m = m;
     m_out[t] = m;
-    rank_out[t] = rk;
-    status[t] = ST_DONE;
+    rank_out[t] = r;
   }
   __syncthreads();
-  const int m = m_out[t];
-  for (int c = tid; c < m; c += nt) {
-    const int src = perm[c];
-    for (int r = no - 1; r >= 0; --r) {
-      double v = Qm[(i64)r * no + src];
-      for (int q = r + 1; q < no; ++q) v -= L[q + (i64)r * no] * Yt[q + (i64)c * no];
-      Yt[r + (i64)c * no] = v / L[r + (i64)r * no];
-    }
+  const int m = sh_m;
+  // selected b-normalised eigenvectors, owned rows: Xo[row, c] = (Qk_o y_c)[row] / sqrt(mu_c)
+  double* Xo = S;  // reuse S as no x m column-major output
+  for (i64 e = tid; e < (i64)no * m; e += nt) {
+    const int row = (int)(e % no), c = (int)(e / no);
+    const int src = ord[c];
+    const double mu = C[(i64)src * r + src];
+    double acc = 0.0;
+    for (int k = 0; k < r; ++k) acc += Qk[(i64)row * r + k] * Yc[(i64)k * r + src];
+    Xo[row + (i64)c * no] = acc / sqrt(mu);
+  }
+  // Dirichlet factor of the owned block
+  for (i64 e = tid; e < (i64)no * no; e += nt) {
+    const int rr = (int)(e % no), cc = (int)(e / no);
+    L[e] = 0.5 * (A[rr + (i64)cc * ng] + A[cc + (i64)rr * ng]);
+  }
+  __syncthreads();
+  if (!dense_cholesky_block(no, L, no, &sh_fail)) {
+    if (tid == 0) status[t] = ST_NOTSPD;
+    return;
+  }
+  if (tid == 0) status[t] = ST_DONE;
+}
+
+// Dense lower factor (column-major, n x n) -> the row and column band layouts with
+// b = n-1 used by the blocked wavefront solves: R[j*n+d] = L(j,j-d), C[j*n+d] = L(j+d,j).
+__global__ void k_dense_to_layouts(const i64* __restrict__ off, const i32* __restrict__ n_arr,
+                                   const double* __restrict__ L, double* __restrict__ R,
+                                   double* __restrict__ C) {
+  const int t = blockIdx.x;
+  const int n = n_arr[t];
+  const double* Lt = L + off[t];
+  double* Rt = R + off[t];
+  double* Ct = C + off[t];
+  for (i64 e = threadIdx.x; e < (i64)n * n; e += blockDim.x) {
+    const int j = (int)(e / n), d = (int)(e % n);
+    Rt[e] = (d <= j) ? Lt[j + (i64)(j - d) * n] : 0.0;
+    Ct[e] = (j + d < n) ? Lt[(j + d) + (i64)j * n] : 0.0;
   }
 }
 
-// Copy the selected eigenvectors (left in the scratch) to the pooled basis, fixing signs.
-// Scratch layout per target: G ngh^2 | Z ngh*no | Sc, Mm, Qm, Yt no^2 each | ints.
+// Explicit inverse of SPD blocks from their Cholesky factors (coarse levels and A_0):
+// the apply then costs one parallel matrix-vector product instead of two
+// sequential triangular sweeps.  Step 1: Linv = L^{-1} (one thread per column,
+// forward substitution); step 2: Inv = Linv^T Linv (one thread per entry).
+// grid: (ceil(nmax / 256), targets); L, Linv, Inv column-major n x n at off[t].
+__global__ void k_tri_inverse(const i64* __restrict__ off, const i32* __restrict__ n_arr,
+                              const double* __restrict__ L, double* __restrict__ Linv) {
+  const int t = blockIdx.y;
+  const int n = n_arr[t];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double* Lt = L + off[t];
+  double* X = Linv + off[t];
+  for (int r = 0; r < c; ++r) X[r + (i64)c * n] = 0.0;
+  for (int r = c; r < n; ++r) {
+    double v = (r == c) ? 1.0 : 0.0;
+    for (int q = c; q < r; ++q) v -= Lt[r + (i64)q * n] * X[q + (i64)c * n];
+    X[r + (i64)c * n] = v / Lt[r + (i64)r * n];
+  }
+}
+
+__global__ void k_gram_lower(const i64* __restrict__ off, const i32* __restrict__ n_arr,
+                             const double* __restrict__ Linv, double* __restrict__ Inv) {
+  const int t = blockIdx.y;
+  const int n = n_arr[t];
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (i64)n * n) return;
+  const int a = (int)(e % n), b = (int)(e / n);
+  const double* X = Linv + off[t];
+  const int r0 = a > b ? a : b;
+  double acc = 0.0;
+  for (int r = r0; r < n; ++r) acc += X[r + (i64)a * n] * X[r + (i64)b * n];
+  Inv[off[t] + e] = acc;
+}
+
+// Copy the selected eigenvectors (left at the start of the scratch) to the pooled basis,
+// fixing signs (largest-magnitude owned entry positive).
 __global__ void k_coarse_collect(const i32* __restrict__ ng_arr, const i32* __restrict__ no_arr,
                                  const i64* __restrict__ soff, const double* __restrict__ scratch,
                                  const int* __restrict__ m_arr, const i64* __restrict__ yoff,
                                  double* __restrict__ Y) {
   const int t = blockIdx.x;
-  const int ng = ng_arr[t], no = no_arr[t];
-  const int ngh = ng - no;
+  const int no = no_arr[t];
   const int m = m_arr[t];
-  const double* Z = scratch + soff[t] + (i64)ngh * ngh + (i64)ngh * no + 3 * (i64)no * no;
+  const double* Z = scratch + soff[t];
   double* Yt = Y + yoff[t];
+  __shared__ double sgn;
   for (int c = 0; c < m; ++c) {
-    __shared__ double sgn;
     if (threadIdx.x == 0) {
       double best = -1, v = 0;
       for (int r = 0; r < no; ++r) {
@@ -487,6 +472,7 @@ __global__ void k_coarse_collect(const i32* __restrict__ ng_arr, const i32* __re
     for (int r = threadIdx.x; r < no; r += blockDim.x) Yt[r + (i64)c * no] = sgn * Z[r + (i64)c * no];
     __syncthreads();
   }
+  (void)ng_arr;
 }
 
 // ---------------------------------------------------------------------------
@@ -543,9 +529,23 @@ void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_
                         double eps_reg, double* lam_out, const i64* lamoff, int* m_out,
                         int* status, int* rank_out) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_coarse_gevp, dim3(nt), dim3(MSDD_WG), 0, s, ng_arr, no_arr, aoff, Abar,
+  hipLaunchKernelGGL(k_coarse_gevp, dim3(nt), dim3(1024), 0, s, ng_arr, no_arr, aoff, Abar,
                      loff, Lo, soff, scratch, eta, nev_max, eps_reg, lam_out, lamoff, m_out,
                      status, rank_out);
+}
+void launch_dense_to_layouts(hipStream_t s, int nt, const i64* off, const i32* n_arr,
+                             const double* L, double* R, double* C) {
+  if (!nt) return;
+  hipLaunchKernelGGL(k_dense_to_layouts, dim3(nt), dim3(MSDD_WG), 0, s, off, n_arr, L, R, C);
+}
+void launch_spd_inverse(hipStream_t s, int nt, int nmax, const i64* off, const i32* n_arr,
+                        const double* L, double* Linv, double* Inv) {
+  if (!nt || nmax <= 0) return;
+  hipLaunchKernelGGL(k_tri_inverse, dim3((nmax + 255) / 256, nt), dim3(256), 0, s, off, n_arr, L,
+                     Linv);
+  const i64 nn = (i64)nmax * nmax;
+  hipLaunchKernelGGL(k_gram_lower, dim3((unsigned)((nn + 255) / 256), nt), dim3(256), 0, s, off,
+                     n_arr, Linv, Inv);
 }
 void launch_coarse_collect(hipStream_t s, int nt, const i32* ng_arr, const i32* no_arr,
                            const i64* soff, const double* scratch, const int* m_arr,

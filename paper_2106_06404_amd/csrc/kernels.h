@@ -28,7 +28,7 @@ template <typename T, typename V>
 void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax,
                              const i32* n_arr, const i32* b_arr, const i64* l_off, const T* Lc,
                              const T* Lr, const i64* v_off, int K, const V* W, V* Y,
-                             const int* active);
+                             const int* active, int bmax);
 
 // eig.hip
 void launch_eig_init(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
@@ -84,6 +84,10 @@ void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_
                         const i64* soff, double* scratch, double eta, int nev_max,
                         double eps_reg, double* lam_out, const i64* lamoff, int* m_out,
                         int* status, int* rank_out);
+void launch_dense_to_layouts(hipStream_t s, int nt, const i64* off, const i32* n_arr,
+                             const double* L, double* R, double* C);
+void launch_spd_inverse(hipStream_t s, int nt, int nmax, const i64* off, const i32* n_arr,
+                        const double* L, double* Linv, double* Inv);
 void launch_coarse_collect(hipStream_t s, int nt, const i32* ng_arr, const i32* no_arr,
                            const i64* soff, const double* scratch, const int* m_arr,
                            const i64* yoff, double* Y);
@@ -110,9 +114,10 @@ void launch_apply_fine_down(hipStream_t s, int P, int nd_max, int bd_max, const 
                             double* u);
 void launch_apply_coarse_down(hipStream_t s, int P, int no_max, const i32* nown,
                               const i64* own_ptr, const i32* own_idx, const i64* loff,
-                              const double* Lo, const i32* msub, const i64* yoff, const double* Y,
-                              const i64* moff, const double* rl, double* zl, double* rc);
-void launch_apply_coarsest(hipStream_t s, int n0, const double* L, const double* r0, double* z0);
+                              const double* Inv, const i32* msub, const i64* yoff,
+                              const double* Y, const i64* moff, const double* rl, double* zl,
+                              double* rc);
+void launch_apply_coarsest(hipStream_t s, int n0, const double* Inv, const double* r0, double* z0);
 void launch_apply_coarse_up(hipStream_t s, int P, const i32* nown, const i64* own_ptr,
                             const i32* own_idx, const i32* msub, const i64* yoff, const double* Y,
                             const i64* moff, const double* zc, double* zl);

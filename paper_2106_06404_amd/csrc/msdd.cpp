@@ -305,7 +305,7 @@ struct CoarseLevel {
   std::vector<int32_t> h_own_idx;
   DVec<int32_t> dno, dm, own_idx;
   DVec<int64_t> loff, yoff, moff, own_ptr;
-  DVec<double> Lo, Y, lam;
+  DVec<double> Lo, Inv, Y, lam;
   std::vector<std::vector<double>> h_lam;
   std::vector<int32_t> rank;
   int no_max = 0;
@@ -412,7 +412,7 @@ struct msdd_ctx {
   std::vector<CoarseLevel> C;  // C[0] = level L-1, ..., C[L-2] = level 1
   std::vector<int64_t> nlev;   // n_l for l = 0..L
   int n0 = 0;
-  DVec<double> A0;
+  DVec<double> A0, A0inv;
   // solve work
   std::vector<DVec<double>> rlev, zlev;  // index l = 0..L-1
   DVec<double> u, r, z, p, q, x, bvec, partial, sc;
@@ -426,6 +426,9 @@ struct msdd_ctx {
 };
 
 namespace {
+
+// verbose: print the time since *t0 under a label and restart the clock
+void vlog(msdd_ctx* c, const char* what, double* t0);
 
 void set_err(msdd_ctx* c, const std::string& m) {
   if (c) c->err = m;
@@ -446,6 +449,12 @@ void check_status(const std::vector<int>& st, const char* what, const std::vecto
       throw MsddError{MSDD_EINVAL, std::string(what) + ": entry outside the element structure or NaN in subdomain " +
                                        std::to_string(ids ? (*ids)[i] : (int)i)};
   }
+}
+
+void vlog(msdd_ctx* c, const char* what, double* t0) {
+  const double t = now_ms();
+  if (c->opt.verbose) std::fprintf(stderr, "msdd:   %-34s %8.2f ms\n", what, t - *t0);
+  *t0 = t;
 }
 
 // Records HIP events around the launches of one kernel class (when profiling).
@@ -498,6 +507,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   F.h_dpos.clear();
   F.h_dglob.clear();
   std::vector<std::vector<std::pair<int32_t, int32_t>>> dinc(n);
+  double tv = now_ms();
   for (int i = 0; i < P; ++i) {
     REQUIRE(sep[i + 1] >= sep[i] && sdp[i + 1] >= sdp[i], "subdomain pointers not monotone");
     std::vector<int32_t> el(se.begin() + sep[i], se.begin() + sep[i + 1]);
@@ -566,8 +576,10 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
     REQUIRE(!dinc[d].empty(), "dof " + std::to_string(d) + " lies in no subdomain's Dirichlet space");
   }
   hipStream_t s = c->stream;
+  vlog(c, "plan: subdomain groups + PoU check", &tv);
   build_groupset(F.plans, F.elems, k, F.gs, s);
   F.dv.upload(F.h_dv, s);
+  vlog(c, "plan: groupset upload", &tv);
   // Neumann band offsets and the ELL structure
   F.h_boff.assign(P + 1, 0);
   for (int i = 0; i < P; ++i)
@@ -613,6 +625,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
       std::copy(tmp.begin(), tmp.end(), ell.begin() + gr * ell_w);
     }
   }
+  vlog(c, "plan: ELL structure", &tv);
   F.ell_col.upload(ell, s);
   F.boff.upload(F.h_boff, s);
   // Dirichlet arrays
@@ -640,6 +653,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   F.dinc_sub.upload(dsub, s);
   F.dinc_q.upload(dq, s);
   HIPCHK(hipStreamSynchronize(s));
+  vlog(c, "plan: Dirichlet + incidence upload", &tv);
 }
 
 void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
@@ -759,7 +773,7 @@ void fine_eigensolve(msdd_ctx* c) {
                      f * 4.0 * F.s_nbb * K);
         launch_band_solve_multi<double, double>(s, P, nullptr, F.nb_max, F.gs.n.p, F.gs.bw.p,
                                                 F.boff.p, F.LSc.p, F.LSr.p, dkvoff.p, K, BX.p,
-                                                Y.p, status.p);
+                                                Y.p, status.p, F.bw_max);
       }
       {
         ProfScope ps(c, PR_EIG_BAPPLY, f * (F.s_nb * F.ell_w * 12.0 + 2.0 * F.s_nb * K * 8.0),
@@ -871,6 +885,7 @@ void fine_patches(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
   FineLevel& F = c->F;
   hipStream_t s = c->stream;
   const int k = c->k;
+  double tv = now_ms();
   std::vector<std::vector<int32_t>> esub(n_elem);
   for (int i = 0; i < F.P; ++i)
     for (int32_t e : F.elems[i]) esub[e].push_back(i);
@@ -891,11 +906,14 @@ void fine_patches(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
     pel[id].push_back(e);
   }
   PL.np = (int)pel.size();
+  vlog(c, "patches: element keys", &tv);
   std::vector<int> map(c->n, -1);
   std::vector<GroupPlan> plans(PL.np);
   for (int p = 0; p < PL.np; ++p) plans[p] = plan_group(pel[p].data(), (int64_t)pel[p].size(), ed, k, map);
+  vlog(c, "patches: group plans", &tv);
   GroupSetDev gs;
   build_groupset(plans, pel, k, gs, s);
+  vlog(c, "patches: groupset upload", &tv);
   // member columns, loc maps
   PL.M.assign(PL.np, 0);
   PL.mcol.resize(PL.np);
@@ -924,6 +942,7 @@ void fine_patches(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
     vpoff[p + 1] = vpoff[p] + (int64_t)pd.size() * M;
     PL.pmoff[p + 1] = PL.pmoff[p] + (int64_t)M * M;
   }
+  vlog(c, "patches: member maps", &tv);
   DVec<int64_t> dmem_ptr, dploc_off, dvpoff;
   DVec<int32_t> dmem_sub, dmem_col, dploc;
   dmem_ptr.upload(mem_ptr, s);
@@ -948,6 +967,7 @@ void fine_patches(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
+  vlog(c, "patches: upload + kernels", &tv);
 }
 
 // Assemble dense coarse matrices: targets = subdomains of the coarser level (or the
@@ -991,6 +1011,7 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
     REQUIRE(v >= 0, "negative parent index");
     Pc = std::max(Pc, v + 1);
   }
+  double tv = now_ms();
   CL.level = l;
   CL.P = Pc;
   CL.children.assign(Pc, {});
@@ -1048,15 +1069,20 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
     CL.no_max = std::max(CL.no_max, CL.no[i]);
   }
   J.ng = CL.ng;
-  REQUIRE(CL.no_max <= 512, "coarse subdomain with more than 512 owned functions");
+  int ng_max = 0;
+  for (int v : CL.ng) ng_max = std::max(ng_max, v);
+  REQUIRE(ng_max <= 1024, "coarse generating system with more than 1024 functions");
+  vlog(c, "coarse: generating-system plan", &tv);
   DVec<double> Abar;
   run_assemble(c, J, PL, Abar);
+  vlog(c, "coarse: assemble (upload + kernel)", &tv);
   // GEVP on the generating systems
   std::vector<int64_t> soff(Pc + 1, 0), lamoff(Pc + 1, 0);
   CL.h_loff.assign(Pc + 1, 0);
   for (int i = 0; i < Pc; ++i) {
     const int64_t ng = CL.ng[i], no = CL.no[i], ngh = ng - no;
-    soff[i + 1] = soff[i] + ngh * ngh + ngh * no + 4 * no * no + std::max(ngh, no) + 2;
+    soff[i + 1] = soff[i] + 5 * ng * ng + ng + 2;
+    (void)ngh;
     CL.h_loff[i + 1] = CL.h_loff[i] + no * no;
     lamoff[i + 1] = lamoff[i] + no;
   }
@@ -1087,6 +1113,7 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
   }
   HIPCHK(hipGetLastError());
   std::vector<int> stv = st.download(s);
+  vlog(c, "coarse: GEVP kernel", &tv);
   check_status(stv, "coarse GEVP (Cholesky of the owned block)");
   CL.m = mo.download(s);
   CL.rank = rk.download(s);
@@ -1106,6 +1133,14 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
   CL.own_idx.upload(CL.h_own_idx, s);
   CL.Y.alloc(std::max<int64_t>(CL.h_yoff.back(), 1));
   launch_coarse_collect(s, Pc, dng.p, dno.p, dsoff.p, scratch.p, CL.dm.p, CL.yoff.p, CL.Y.p);
+  {
+    DVec<double> Linv;
+    Linv.alloc(std::max<int64_t>(CL.h_loff.back(), 1));
+    CL.Inv.alloc(std::max<int64_t>(CL.h_loff.back(), 1));
+    launch_spd_inverse(s, Pc, CL.no_max, CL.loff.p, CL.dno.p, CL.Lo.p, Linv.p, CL.Inv.p);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   // patches of level l from those of level l+1, grouped by parent sets
@@ -1199,6 +1234,7 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
   Wsc.alloc(std::max<int64_t>(wsoff.back(), 1));
   {
   ProfScope pscope2(c, PR_PATCH);
+  vlog(c, "coarse: next-level patch plan", &tv);
   launch_patch_project(s, PLnext.np, dch_ptr.p, dch_patch.p, PL.dM.p, PL.dpmoff.p, PL.Pm.p,
                        dcmem_ptr.p, dcmem_pslot.p, dcmem_ownbase.p, dcmem_m.p, dcmem_col.p,
                        dpmem_ptr.p, dpmem_sub.p, dpmem_col.p, nullptr, CL.dno.p, CL.yoff.p, CL.Y.p,
@@ -1206,6 +1242,7 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
+  vlog(c, "coarse: patch projection kernel", &tv);
 }
 
 void coarsest(msdd_ctx* c, const PatchLevel& PL, const std::vector<int32_t>& m_lvl1) {
@@ -1229,7 +1266,7 @@ void coarsest(msdd_ctx* c, const PatchLevel& PL, const std::vector<int32_t>& m_l
     c->A0.alloc(1);
     return;
   }
-  REQUIRE(n0 <= 16384, "coarsest space larger than 16384 (add a level)");
+  REQUIRE(n0 <= 8192, "coarsest space larger than 8192 (add a level)");
   run_assemble(c, J, PL, c->A0);
   DVec<int> st;
   st.alloc(1);
@@ -1240,6 +1277,19 @@ void coarsest(msdd_ctx* c, const PatchLevel& PL, const std::vector<int32_t>& m_l
   HIPCHK(hipGetLastError());
   std::vector<int> v = st.download(s);
   if (v[0] != ST_DONE) throw MsddError{MSDD_ENOTSPD, "coarsest matrix A_0 is not positive definite"};
+  DVec<int64_t> off0;
+  DVec<int32_t> nn0;
+  off0.upload(std::vector<int64_t>{0}, s);
+  nn0.upload(std::vector<int32_t>{n0}, s);
+  {
+    DVec<double> Linv;
+    Linv.alloc((size_t)n0 * n0);
+    c->A0inv.alloc((size_t)n0 * n0);
+    ProfScope ps(c, PR_COARSE, 3.0 * n0 * (double)n0 * 8.0, 2.0 * (double)n0 * n0 * n0 / 3.0);
+    launch_spd_inverse(s, 1, n0, off0.p, nn0.p, c->A0.p, Linv.p, c->A0inv.p);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
 }
 
 void alloc_solve_work(msdd_ctx* c) {
@@ -1286,10 +1336,10 @@ void apply_prec(msdd_ctx* c, const double* r, double* z) {
       CoarseLevel& CL = c->C[t];
       const int l = CL.level;
       launch_apply_coarse_down(s, CL.P, CL.no_max, CL.dno.p, CL.own_ptr.p, CL.own_idx.p,
-                               CL.loff.p, CL.Lo.p, CL.dm.p, CL.yoff.p, CL.Y.p, CL.moff.p,
+                               CL.loff.p, CL.Inv.p, CL.dm.p, CL.yoff.p, CL.Y.p, CL.moff.p,
                                c->rlev[l].p, c->zlev[l].p, c->rlev[l - 1].p);
     }
-    launch_apply_coarsest(s, c->n0, c->A0.p, c->rlev[0].p, c->zlev[0].p);
+    launch_apply_coarsest(s, c->n0, c->A0inv.p, c->rlev[0].p, c->zlev[0].p);
     for (int t = (int)c->C.size() - 1; t >= 0; --t) {
       CoarseLevel& CL = c->C[t];
       const int l = CL.level;
@@ -1384,6 +1434,7 @@ int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     c->sigma = c->opt.sigma > 0 ? c->opt.sigma : 0.1 * eta;
     c->n_levels = n_levels;
     hipStream_t s = c->stream;
+    double tv = now_ms();
     // host copies of the index arrays (planning)
     std::vector<int64_t> h_rowptr = to_host(rowptr, (size_t)n + 1);
     REQUIRE(h_rowptr[0] == 0, "rowptr[0] must be 0");
@@ -1423,6 +1474,7 @@ int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
       to_device(emat_holder, elem_mat, (size_t)n_elem * k * k, s);
       d_emat = emat_holder.p;
     }
+    vlog(c, "setup: input copies", &tv);
     const double avg = (double)c->nnz / (double)n;
     c->spmv_sg = avg <= 6 ? 4 : (avg <= 14 ? 8 : (avg <= 40 ? 16 : 32));
     // finest level

@@ -110,40 +110,59 @@ __global__ void k_residual(i64 n, const double* __restrict__ b, const double* __
 //   r_loc = R_i r (Dirichlet dofs), rc[i,:] = PhiD_i^T r_loc (restriction to the
 //   next coarser level), u_i = A_i^{-1} r_loc by blocked band triangular solves.
 // ---------------------------------------------------------------------------
+template <int WMAX>
 __global__ void __launch_bounds__(64) k_apply_fine_down(
     const i32* __restrict__ nd, const i32* __restrict__ bd, const i64* __restrict__ doff,
     const i32* __restrict__ dglob, const i64* __restrict__ dboff, const double* __restrict__ Lc,
     const double* __restrict__ Lr, const i32* __restrict__ msub, const i64* __restrict__ moff,
     const i64* __restrict__ phid_off, const double* __restrict__ PhiD,
-    const double* __restrict__ r, double* __restrict__ rc, double* __restrict__ u) {
+    const double* __restrict__ r, double* __restrict__ rc, double* __restrict__ u, int nd_max) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = blockIdx.x;
   const int n = nd[i];
   const int b = bd[i];
-  double* rl = reinterpret_cast<double*>(smem_raw);  // n
+  double* rl = reinterpret_cast<double*>(smem_raw);  // nd_max
+  double* stage = rl + nd_max;                       // 2*64*(b+1) when staged
   const int tid = threadIdx.x;
   const i32* dg = dglob + doff[i];
   for (int q = tid; q < n; q += 64) rl[q] = r[dg[q]];
   __syncthreads();
-  // restriction rc = PhiD^T r_loc
+  // restriction rc = PhiD^T r_loc, eight columns per pass over the rows
   const int m = msub[i];
   const double* PD = PhiD + phid_off[i];
-  for (int c = 0; c < m; ++c) {
-    double s = 0.0;
-    for (int q = tid; q < n; q += 64) s += PD[(i64)q * m + c] * rl[q];
-    s = wave_sum(s);
-    if (tid == 0) rc[moff[i] + c] = s;
+  for (int c0 = 0; c0 < m; c0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int u2 = 0; u2 < 8; ++u2) acc[u2] = 0.0;
+    for (int q = tid; q < n; q += 64) {
+      const double x = rl[q];
+      const double* prow = PD + (i64)q * m + c0;
+#pragma unroll
+      for (int u2 = 0; u2 < 8; ++u2)
+        if (c0 + u2 < m) acc[u2] += prow[u2] * x;
+    }
+#pragma unroll
+    for (int u2 = 0; u2 < 8; ++u2) {
+      const double s2 = wave_sum(acc[u2]);
+      if (tid == 0 && c0 + u2 < m) rc[moff[i] + c0 + u2] = s2;
+    }
   }
-  wave_trsv_lower<double, double>(n, b, Lr + dboff[i], rl);
-  wave_trsv_upper<double, double>(n, b, Lc + dboff[i], rl);
+  if (WMAX > 0) {
+    wg_trsv_staged<double, double, 1, (WMAX > 0 ? WMAX : 1), false>(n, b, Lr + dboff[i], rl, stage);
+    wg_trsv_staged<double, double, 1, (WMAX > 0 ? WMAX : 1), true>(n, b, Lc + dboff[i], rl, stage);
+  } else {
+    wave_trsv_lower<double, double>(n, b, Lr + dboff[i], rl);
+    wave_trsv_upper<double, double>(n, b, Lc + dboff[i], rl);
+  }
   double* ui = u + doff[i];
   for (int q = tid; q < n; q += 64) ui[q] = rl[q];
 }
 
 // coarse level l: per subdomain, r_o = r_l[own]; rc = Y^T r_o; z_l[own] = A_oo^{-1} r_o
+// with the explicit inverse (column-major, symmetric)
 __global__ void k_apply_coarse_down(const i32* __restrict__ nown, const i64* __restrict__ own_ptr,
                                     const i32* __restrict__ own_idx, const i64* __restrict__ loff,
-                                    const double* __restrict__ Lo, const i32* __restrict__ msub,
+                                    const double* __restrict__ Inv, const i32* __restrict__ msub,
                                     const i64* __restrict__ yoff, const double* __restrict__ Y,
                                     const i64* __restrict__ moff, const double* __restrict__ rl,
                                     double* __restrict__ zl, double* __restrict__ rc) {
@@ -151,7 +170,6 @@ __global__ void k_apply_coarse_down(const i32* __restrict__ nown, const i64* __r
   const int i = blockIdx.x;
   const int no = nown[i];
   double* v = reinterpret_cast<double*>(smem_raw);
-  __shared__ double xj;
   const i32* own = own_idx + own_ptr[i];
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int o = tid; o < no; o += nt) v[o] = rl[own[o]];
@@ -163,61 +181,22 @@ __global__ void k_apply_coarse_down(const i32* __restrict__ nown, const i64* __r
     for (int o = 0; o < no; ++o) s += Yi[o + (i64)c * no] * v[o];
     rc[moff[i] + c] = s;
   }
-  const double* L = Lo + loff[i];
-  for (int j = 0; j < no; ++j) {
-    __syncthreads();
-    if (tid == 0) {
-      xj = v[j] / L[j + (i64)j * no];
-      v[j] = xj;
-    }
-    __syncthreads();
-    const double x = xj;
-    for (int rr = j + 1 + tid; rr < no; rr += nt) v[rr] -= L[rr + (i64)j * no] * x;
+  const double* A = Inv + loff[i];
+  for (int o = tid; o < no; o += nt) {
+    double s = 0.0;
+    for (int q = 0; q < no; ++q) s += A[o + (i64)q * no] * v[q];
+    zl[own[o]] = s;
   }
-  for (int j = no - 1; j >= 0; --j) {
-    __syncthreads();
-    if (tid == 0) {
-      xj = v[j] / L[j + (i64)j * no];
-      v[j] = xj;
-    }
-    __syncthreads();
-    const double x = xj;
-    for (int rr = tid; rr < j; rr += nt) v[rr] -= L[j + (i64)rr * no] * x;
-  }
-  __syncthreads();
-  for (int o = tid; o < no; o += nt) zl[own[o]] = v[o];
 }
 
-// coarsest level: z0 = A_0^{-1} r0 (dense Cholesky factor, column-major)
-__global__ void k_apply_coarsest(int n0, const double* __restrict__ L,
+// coarsest level: z0 = A_0^{-1} r0 with the explicit inverse, one thread per row
+__global__ void k_apply_coarsest(int n0, const double* __restrict__ Inv,
                                  const double* __restrict__ r0, double* __restrict__ z0) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* v = reinterpret_cast<double*>(smem_raw);
-  __shared__ double xj;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int o = tid; o < n0; o += nt) v[o] = r0[o];
-  for (int j = 0; j < n0; ++j) {
-    __syncthreads();
-    if (tid == 0) {
-      xj = v[j] / L[j + (i64)j * n0];
-      v[j] = xj;
-    }
-    __syncthreads();
-    const double x = xj;
-    for (int rr = j + 1 + tid; rr < n0; rr += nt) v[rr] -= L[rr + (i64)j * n0] * x;
-  }
-  for (int j = n0 - 1; j >= 0; --j) {
-    __syncthreads();
-    if (tid == 0) {
-      xj = v[j] / L[j + (i64)j * n0];
-      v[j] = xj;
-    }
-    __syncthreads();
-    const double x = xj;
-    for (int rr = tid; rr < j; rr += nt) v[rr] -= L[j + (i64)rr * n0] * x;
-  }
-  __syncthreads();
-  for (int o = tid; o < n0; o += nt) z0[o] = v[o];
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n0) return;
+  double s = 0.0;
+  for (int q = 0; q < n0; ++q) s += Inv[o + (i64)q * n0] * r0[q];
+  z0[o] = s;
 }
 
 // coarse level l, upward: z_l[own] += Y z_{l-1}[i,:]
@@ -307,28 +286,31 @@ void launch_apply_fine_down(hipStream_t s, int P, int nd_max, int bd_max, const 
                             const double* Lc, const double* Lr, const i32* msub, const i64* moff,
                             const i64* phid_off, const double* PhiD, const double* r, double* rc,
                             double* u) {
-  const size_t lds = (size_t)nd_max * sizeof(double);
-  (void)bd_max;
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_apply_fine_down,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_apply_fine_down, dim3(P), dim3(64), lds, s, nd, bd, doff, dglob, dboff, Lc,
-                     Lr, msub, moff, phid_off, PhiD, r, rc, u);
+  const int w = bd_max + 1;
+  const int wmax = w <= 40 ? 40 : (w <= 64 ? 64 : 0);
+  const size_t lds = ((size_t)nd_max + (wmax ? 2 * 64 * (size_t)w : 0)) * sizeof(double);
+#define MSDD_AFD(WM)                                                                           \
+  {                                                                                            \
+    if (lds > 65536)                                                                           \
+      (void)hipFuncSetAttribute((const void*)k_apply_fine_down<WM>,                            \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);         \
+    hipLaunchKernelGGL(k_apply_fine_down<WM>, dim3(P), dim3(64), lds, s, nd, bd, doff, dglob,  \
+                       dboff, Lc, Lr, msub, moff, phid_off, PhiD, r, rc, u, nd_max);           \
+  }
+  if (wmax == 40) MSDD_AFD(40) else if (wmax == 64) MSDD_AFD(64) else MSDD_AFD(0)
+#undef MSDD_AFD
 }
 void launch_apply_coarse_down(hipStream_t s, int P, int no_max, const i32* nown,
                               const i64* own_ptr, const i32* own_idx, const i64* loff,
-                              const double* Lo, const i32* msub, const i64* yoff, const double* Y,
-                              const i64* moff, const double* rl, double* zl, double* rc) {
+                              const double* Inv, const i32* msub, const i64* yoff,
+                              const double* Y, const i64* moff, const double* rl, double* zl,
+                              double* rc) {
   hipLaunchKernelGGL(k_apply_coarse_down, dim3(P), dim3(MSDD_WG), (size_t)no_max * sizeof(double),
-                     s, nown, own_ptr, own_idx, loff, Lo, msub, yoff, Y, moff, rl, zl, rc);
+                     s, nown, own_ptr, own_idx, loff, Inv, msub, yoff, Y, moff, rl, zl, rc);
 }
-void launch_apply_coarsest(hipStream_t s, int n0, const double* L, const double* r0, double* z0) {
+void launch_apply_coarsest(hipStream_t s, int n0, const double* Inv, const double* r0, double* z0) {
   if (n0 <= 0) return;
-  const size_t lds = (size_t)n0 * sizeof(double);
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_apply_coarsest,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_apply_coarsest, dim3(1), dim3(MSDD_WG), lds, s, n0, L, r0, z0);
+  hipLaunchKernelGGL(k_apply_coarsest, dim3((n0 + 127) / 128), dim3(128), 0, s, n0, Inv, r0, z0);
 }
 void launch_apply_coarse_up(hipStream_t s, int P, const i32* nown, const i64* own_ptr,
                             const i32* own_idx, const i32* msub, const i64* yoff, const double* Y,
