@@ -56,7 +56,9 @@ extern "C" {
 #define MSDD_FP64 0   /* everything in double precision */
 #define MSDD_MIXED 1  /* local factorisations, eigensolves and the preconditioner apply in
                          single precision; PCG recurrences, inner products, the coarsest
-                         factorisation and the eigen-residual check in double */
+                         factorisation and the eigen-residual check in double.
+                         Not available in this version: msdd_create returns
+                         MSDD_EINVAL for it. */
 
 typedef struct msdd_ctx msdd_ctx; /* opaque; owns all device memory it allocates */
 
@@ -180,7 +182,7 @@ int msdd_get_basis(const msdd_ctx* c, int32_t level, int32_t i, double* basis, i
  * compute; see each kernel's comment).  msdd_profile_name gives the class name
  * (NULL for an id out of range).
  */
-#define MSDD_NPROF 16
+#define MSDD_NPROF 17
 int msdd_profile(msdd_ctx* c, int enable);
 int msdd_profile_query(msdd_ctx* c, int id, double* total_ms, int64_t* launches,
                        double* alg_bytes, double* alg_flops);

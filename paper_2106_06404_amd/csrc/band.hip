@@ -10,6 +10,7 @@
 // matrix is A_i = R_i A R_i^T (Sec. 2.1); the shifted pencil matrix
 // abar + sigma*b, b = D abar D (Sec. 3.4 lemma, b^1 of Sec. 3.5) is SPD.
 #include "common.h"
+#include <algorithm>
 #include "kernels.h"
 #include "trsv.h"
 
@@ -320,6 +321,64 @@ template void launch_band_cholesky<float>(hipStream_t, int, const i32*, int, con
                                           const i32*, const i64*, const double*, const i64*,
                                           const double*, double, const i64*, float*, float*,
                                           int*);
+
+// Cholesky factor L (column layout Lc[j*w + d] = L(j+d, j)) -> LDL^T factor A =
+// Lt D Lt^T.  Row layout F[j*w + d] = L(j, j-d) / L(j-d, j-d) (d >= 1, 0 before
+// the first column), F[j*w] = 1 / L(j, j)^2 (the inverse of D).  grid.y = subdomain.
+template <typename T>
+__global__ void k_band_to_ldl(const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
+                              const i64* __restrict__ off, const T* __restrict__ Lc,
+                              T* __restrict__ F) {
+  const int i = blockIdx.y;
+  const int n = n_arr[i], w = b_arr[i] + 1;
+  const T* L = Lc + off[i];
+  T* Fi = F + off[i];
+  const i64 cnt = (i64)n * w;
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (i64)gridDim.x * blockDim.x) {
+    const int j = (int)(e / w), d = (int)(e - (i64)j * w);
+    T v = 0;
+    if (d == 0) {
+      const T l = L[(i64)j * w];
+      v = (T)1 / (l * l);
+    } else if (j - d >= 0) {
+      v = L[(i64)(j - d) * w + d] / L[(i64)(j - d) * w];
+    }
+    Fi[e] = v;
+  }
+}
+
+// In place on the column layout, after k_band_to_ldl has read it: column c of L
+// becomes column c of the unit factor, Lc[c*w + d] = L(c+d, c) / L(c, c) (0 past
+// the last row), and Lc[c*w] = 1 / L(c, c)^2.  One thread per column.
+template <typename T>
+__global__ void k_band_unit_cols(const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
+                                 const i64* __restrict__ off, T* __restrict__ Lc) {
+  const int i = blockIdx.y;
+  const int n = n_arr[i], w = b_arr[i] + 1;
+  T* L = Lc + off[i];
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    T* col = L + (i64)c * w;
+    const T l = col[0];
+    const T il = (T)1 / l;
+    for (int d = 1; d < w; ++d) col[d] = (c + d < n) ? col[d] * il : (T)0;
+    col[0] = il * il;
+  }
+}
+
+template <typename T>
+void launch_band_to_ldl(hipStream_t s, int nsubs, int nmax, int bmax, const i32* n_arr,
+                        const i32* b_arr, const i64* off, T* Lc, T* F) {
+  if (nsubs == 0 || nmax == 0) return;
+  const i64 cnt = (i64)nmax * (bmax + 1);
+  const int gx = (int)std::min<i64>((cnt + 255) / 256, 64);
+  hipLaunchKernelGGL(k_band_to_ldl<T>, dim3(gx, nsubs), dim3(256), 0, s, n_arr, b_arr, off, Lc, F);
+  const int gc = std::min((nmax + 255) / 256, 16);
+  hipLaunchKernelGGL(k_band_unit_cols<T>, dim3(gc, nsubs), dim3(256), 0, s, n_arr, b_arr, off, Lc);
+}
+template void launch_band_to_ldl<double>(hipStream_t, int, int, int, const i32*, const i32*,
+                                         const i64*, double*, double*);
+template void launch_band_to_ldl<float>(hipStream_t, int, int, int, const i32*, const i32*,
+                                        const i64*, float*, float*);
 
 size_t band_cholesky_lds(int bmax, int elem_size) {
   size_t w = (size_t)bmax + 1;

@@ -36,11 +36,20 @@ __device__ inline void jacobi_pair(int r, int k, int m, int& p, int& q) {
 }
 
 // Returns the number of sweeps used (or -1 if max_sweeps was hit).
-template <typename R>
+// Each round: (1) the rotation of every pair of the round is computed from the
+// current A; (2) A <- J^T A J is applied block by block: the 2x2 block of rows
+// {p_k, q_k} and columns {p_k', q_k'} depends only on that block and the two
+// rotations, so every block is rotated in one pass (row rotation first, then
+// the column rotation), V <- V J in the same pass; one barrier per phase.
+// Pairs without a rotation act as the identity; blocks of two such pairs are
+// skipped.  With n odd, the dummy index m-1 = n drops out of its pair.
+template <typename R, int JU = 4>
 __device__ int jacobi_block(int n, R* A, R* V, JacobiScratch<R> s, int max_sweeps, R eps,
                             R floor_abs) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int t = tid; t < n * n; t += nt) V[t] = (t / n == t % n) ? (R)1 : (R)0;
+  const int lane = tid & 63, wv = tid >> 6, nwv = (nt + 63) >> 6;
+  for (int r0 = wv; r0 < n; r0 += nwv)
+    for (int c0 = lane; c0 < n; c0 += 64) V[r0 * n + c0] = (r0 == c0) ? (R)1 : (R)0;
   __syncthreads();
   if (n <= 1) return 0;
   const int m = (n & 1) ? n + 1 : n;
@@ -67,46 +76,108 @@ __device__ int jacobi_block(int n, R* A, R* V, JacobiScratch<R> s, int max_sweep
             atomicAdd(s.cnt, 1);
           }
         }
-        s.pp[k] = use ? p : -1;
+        s.pp[k] = use ? p : -1 - p;  // the index survives in the unused case
         s.pq[k] = q;
         s.pc[k] = c;
         s.ps[k] = sn;
       }
       __syncthreads();
-      // rows p, q
-      for (int t = tid; t < np * n; t += nt) {
-        const int k = t / n, j = t % n;
-        const int p = s.pp[k];
-        if (p < 0) continue;
-        const int q = s.pq[k];
-        const R c = s.pc[k], sn = s.ps[k];
-        const R x = A[p * n + j], y = A[q * n + j];
-        A[p * n + j] = c * x - sn * y;
-        A[q * n + j] = sn * x + c * y;
-      }
-      __syncthreads();
-      // columns p, q of A and V
-      for (int t = tid; t < np * n; t += nt) {
-        const int row = t / np, k = t % np;
-        const int p = s.pp[k];
-        if (p < 0) continue;
-        const int q = s.pq[k];
-        const R c = s.pc[k], sn = s.ps[k];
-        R x = A[row * n + p], y = A[row * n + q];
-        A[row * n + p] = c * x - sn * y;
-        A[row * n + q] = sn * x + c * y;
-        x = V[row * n + p];
-        y = V[row * n + q];
-        V[row * n + p] = c * x - sn * y;
-        V[row * n + q] = sn * x + c * y;
-      }
-      __syncthreads();
-      for (int k = tid; k < np; k += nt) {
-        const int p = s.pp[k];
-        if (p < 0) continue;
-        const int q = s.pq[k];
-        A[p * n + q] = 0;
-        A[q * n + p] = 0;
+      // A <- J^T A J on 2x2 blocks (pair k = rows, pair k2 = columns), then V <- V J.
+      // Each thread first loads JU work items, then rotates and stores them, so the
+      // loads of a round are in flight together (the compiler cannot move a load
+      // above a store to the same array by itself).
+      {
+        const int nblk2 = np * np;
+        for (int t0 = tid; t0 < nblk2; t0 += nt * JU) {
+          R x[JU], y[JU], z[JU], w[JU];
+          int ia[JU], ib[JU];  // flat index of A[p][p2]; -1 = nothing to do
+          int dq[JU], dq2[JU];  // row / column offsets of q, q2 (0 when absent)
+#pragma unroll
+          for (int u = 0; u < JU; ++u) {
+            const int t = t0 + u * nt;
+            ia[u] = -1;
+            x[u] = y[u] = z[u] = w[u] = 0;
+            dq[u] = dq2[u] = 0;
+            ib[u] = 0;
+            if (t < nblk2) {
+              const int k = t / np, k2 = t - k * np;
+              const int pk = s.pp[k], pk2 = s.pp[k2];
+              if (pk >= 0 || pk2 >= 0) {
+                const int p = pk >= 0 ? pk : -1 - pk, q = s.pq[k];
+                const int p2 = pk2 >= 0 ? pk2 : -1 - pk2, q2 = s.pq[k2];
+                ia[u] = p * n + p2;
+                ib[u] = k * np + k2;
+                dq[u] = q < n ? (q - p) * n : 0;
+                dq2[u] = q2 < n ? q2 - p2 : 0;
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < JU; ++u) {
+            if (ia[u] >= 0) {
+              const int a0 = ia[u];
+              x[u] = A[a0];
+              z[u] = A[a0 + dq2[u]];
+              y[u] = A[a0 + dq[u]];
+              w[u] = A[a0 + dq[u] + dq2[u]];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < JU; ++u) {
+            if (ia[u] < 0) continue;
+            const int k = ib[u] / np, k2 = ib[u] - k * np;
+            const R c = s.pc[k], sn = s.ps[k], c2 = s.pc[k2], s2 = s.ps[k2];
+            const R x1 = c * x[u] - sn * y[u], y1 = sn * x[u] + c * y[u];
+            const R z1 = c * z[u] - sn * w[u], w1 = sn * z[u] + c * w[u];
+            R npp = c2 * x1 - s2 * z1, npq = s2 * x1 + c2 * z1;
+            R nqp = c2 * y1 - s2 * w1, nqq = s2 * y1 + c2 * w1;
+            if (k == k2 && s.pp[k] >= 0) {
+              npq = 0;
+              nqp = 0;
+            }
+            const int a0 = ia[u];
+            // absent q / q2 (odd n): the aliased writes below are skipped
+            if (dq[u] != 0 && dq2[u] != 0) A[a0 + dq[u] + dq2[u]] = nqq;
+            if (dq[u] != 0) A[a0 + dq[u]] = nqp;
+            if (dq2[u] != 0) A[a0 + dq2[u]] = npq;
+            A[a0] = npp;
+          }
+        }
+        const int nv = n * np;
+        for (int t0 = tid; t0 < nv; t0 += nt * JU) {
+          R x[JU], y[JU];
+          int ia[JU], ib[JU];
+#pragma unroll
+          for (int u = 0; u < JU; ++u) {
+            const int t = t0 + u * nt;
+            ia[u] = -1;
+            ib[u] = 0;
+            x[u] = y[u] = 0;
+            if (t < nv) {
+              const int row = t / np, k2 = t - row * np;
+              const int pk2 = s.pp[k2];
+              if (pk2 >= 0) {
+                ia[u] = row * n + pk2;
+                ib[u] = k2;
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < JU; ++u) {
+            if (ia[u] >= 0) {
+              x[u] = V[ia[u]];
+              y[u] = V[ia[u] - s.pp[ib[u]] + s.pq[ib[u]]];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < JU; ++u) {
+            if (ia[u] < 0) continue;
+            const int k2 = ib[u];
+            const R c2 = s.pc[k2], s2 = s.ps[k2];
+            V[ia[u]] = c2 * x[u] - s2 * y[u];
+            V[ia[u] - s.pp[k2] + s.pq[k2]] = s2 * x[u] + c2 * y[u];
+          }
+        }
       }
       __syncthreads();
     }

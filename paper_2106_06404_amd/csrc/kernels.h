@@ -23,6 +23,11 @@ void launch_band_cholesky(hipStream_t s, int nsubs, const i32* subs, int bmax, c
                           const i32* b_arr, const i64* src_off, const double* src,
                           const i64* dv_off, const double* dv, double sigma, const i64* dst_off,
                           T* Lc, T* Lr, int* status);
+// Cholesky factor (column layout) -> LDL^T factor in row layout F and, in place,
+// in column layout Lc (both with 1/D on the diagonal slot).
+template <typename T>
+void launch_band_to_ldl(hipStream_t s, int nsubs, int nmax, int bmax, const i32* n_arr,
+                        const i32* b_arr, const i64* off, T* Lc, T* F);
 size_t band_cholesky_lds(int bmax, int elem_size);
 template <typename T, typename V>
 void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax,
@@ -107,11 +112,13 @@ void launch_update_p(hipStream_t s, i64 n, const double* z, double* p, const dou
                      int use_beta);
 void launch_residual(hipStream_t s, i64 n, const double* b, const double* q, double* r,
                      double* partial);
-void launch_apply_fine_down(hipStream_t s, int P, int nd_max, int bd_max, const i32* nd,
-                            const i32* bd, const i64* doff, const i32* dglob, const i64* dboff,
-                            const double* Lc, const double* Lr, const i32* msub, const i64* moff,
-                            const i64* phid_off, const double* PhiD, const double* r, double* rc,
-                            double* u);
+void launch_apply_fine_restrict(hipStream_t s, int P, int nd_max, const i32* nd, const i64* doff,
+                                const i32* dglob, const i32* msub, const i64* moff,
+                                const i64* phid_off, const double* PhiD, const double* r,
+                                double* rc, double* u);
+void launch_apply_fine_solve(hipStream_t s, int P, int nd_max, int bd_max, const i32* nd,
+                             const i32* bd, const i64* doff, const i64* dboff, const double* Fc,
+                             const double* Fr, double* u);
 void launch_apply_coarse_down(hipStream_t s, int P, int no_max, const i32* nown,
                               const i64* own_ptr, const i32* own_idx, const i64* loff,
                               const double* Inv, const i32* msub, const i64* yoff,

@@ -11,13 +11,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -102,6 +106,39 @@ bool is_device_ptr(const void* ptr) {
     return false;
   }
   return a.type == hipMemoryTypeDevice || a.isManaged;
+}
+
+int host_threads(int work) {
+  unsigned hc = std::thread::hardware_concurrency();
+  int nt = (int)std::min<unsigned>(hc ? hc : 1, 16);
+  return std::max(1, std::min(nt, work));
+}
+
+// f(i, thread) for i in [0, n) on nthr threads (dynamic schedule); MsddError from a
+// worker is rethrown on the caller.
+template <class F>
+void parallel_for(int n, int nthr, F f) {
+  if (nthr <= 1 || n <= 1) {
+    for (int i = 0; i < n; ++i) f(i, 0);
+    return;
+  }
+  std::atomic<int> next(0);
+  std::vector<std::thread> th;
+  std::vector<MsddError> errs;
+  std::mutex mu;
+  for (int t = 0; t < nthr; ++t)
+    th.emplace_back([&, t] {
+      try {
+        int i;
+        while ((i = next++) < n) f(i, t);
+      } catch (const MsddError& e) {
+        std::lock_guard<std::mutex> g(mu);
+        errs.push_back(e);
+        next = n;
+      }
+    });
+  for (auto& x : th) x.join();
+  if (!errs.empty()) throw errs.front();
 }
 
 template <class T>
@@ -332,9 +369,10 @@ enum ProfId {
   PR_COARSE,        // coarse assembly + coarse GEVP + A_0 Cholesky
   PR_SPMV,          // CSR SpMV (+ fused dot)
   PR_VEC,           // PCG vector updates and dot products
-  PR_APPLY_FINE,    // finest-level restriction + band triangular solves
+  PR_APPLY_FINE,    // finest-level band triangular solves (LDL^T sweeps)
   PR_APPLY_COARSE,  // coarse-level solves, restriction, prolongation
   PR_APPLY_GATHER,  // finest-level prolongation + gather
+  PR_APPLY_RESTRICT,  // finest-level gather of r + restriction to level L-1
   PR_OTHER,
   PR_COUNT
 };
@@ -342,7 +380,8 @@ static_assert(PR_COUNT == MSDD_NPROF, "profile classes");
 const char* kProfNames[PR_COUNT] = {
     "neumann_assemble", "dirichlet_extract", "band_cholesky", "eig_band_solve",
     "eig_bapply", "eig_gram", "eig_rayleigh_ritz", "eig_update", "patch", "coarse",
-    "spmv", "pcg_vector", "apply_fine_solve", "apply_coarse", "apply_fine_gather", "other"};
+    "spmv", "pcg_vector", "apply_fine_solve", "apply_coarse", "apply_fine_gather",
+    "apply_fine_restrict", "other"};
 
 struct Profiler {
   bool on = false;
@@ -481,6 +520,15 @@ struct ProfScope {
 // ---------------------------------------------------------------------------
 // Finest level: planning, local matrices, factorizations, eigensolves
 // ---------------------------------------------------------------------------
+// Per-subdomain planning results (computed in parallel, merged in subdomain order).
+struct SubPlan {
+  std::vector<double> dv;            // PoU weight per Neumann dof (0 off the Dirichlet set)
+  std::vector<int32_t> dpos, dglob;  // Dirichlet dofs: local Neumann index, global dof
+  std::vector<int32_t> ell_ptr, ell_col;  // local CSR of the Neumann matrix pattern
+  int nD = 0, bd = 0, rankb = 0, ell_w = 0;
+  std::string err;
+};
+
 void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
                const std::vector<int64_t>& sep, const std::vector<int32_t>& se,
                const std::vector<int64_t>& sdp, const std::vector<int32_t>& sd,
@@ -489,16 +537,99 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   const int k = c->k;
   const int64_t n = c->n;
   const int P = F.P;
-  std::vector<int> map(n, -1);
+  double tv = now_ms();
   std::vector<int32_t> deg(n, 0);
   for (size_t e = 0; e < ed.size(); ++e) {
     REQUIRE(ed[e] >= -1 && ed[e] < n, "elem_dofs entry out of range");
     if (ed[e] >= 0) deg[ed[e]]++;
   }
-  F.elems.resize(P);
-  F.plans.resize(P);
+  for (int i = 0; i < P; ++i)
+    REQUIRE(sep[i + 1] >= sep[i] && sdp[i + 1] >= sdp[i], "subdomain pointers not monotone");
+  for (int32_t e : se) REQUIRE(e >= 0 && e < n_elem, "sub_elem entry out of range");
+  F.elems.assign(P, {});
+  F.plans.assign(P, {});
+  std::vector<SubPlan> sp(P);
+  const int nthr = host_threads(P);
+  std::vector<std::vector<int>> maps(nthr);
+  parallel_for(P, nthr, [&](int i, int t) {
+    if (maps[t].empty()) maps[t].assign(n, -1);
+    SubPlan& S = sp[i];
+    std::vector<int32_t> el(se.begin() + sep[i], se.begin() + sep[i + 1]);
+    F.plans[i] = plan_group(el.data(), (int64_t)el.size(), ed, k, maps[t]);
+    F.elems[i] = std::move(el);
+    const GroupPlan& g = F.plans[i];
+    const auto& els = F.elems[i];
+    // the caller's Neumann dofs must be the free dofs of the subdomain's elements
+    const int64_t nd_in = sdp[i + 1] - sdp[i];
+    if (nd_in != (int64_t)g.dofs.size()) {
+      S.err = "sub_dof of subdomain " + std::to_string(i) + " is not the set of free dofs of its elements";
+      return;
+    }
+    std::vector<std::pair<int32_t, double>> dw((size_t)nd_in);
+    for (int64_t q = 0; q < nd_in; ++q) dw[q] = {sd[sdp[i] + q], sw[sdp[i] + q]};
+    std::sort(dw.begin(), dw.end());
+    const int nb = (int)g.dofs.size();
+    std::vector<int32_t> dloc(nb, -1);
+    S.dv.resize(nb);
+    for (int r = 0; r < nb; ++r) {
+      if (dw[r].first != g.dofs[r]) {
+        S.err = "sub_dof of subdomain " + std::to_string(i) + " is not the set of free dofs of its elements";
+        return;
+      }
+      const double w = dw[r].second;
+      if (!std::isfinite(w)) {
+        S.err = "non-finite partition-of-unity weight";
+        return;
+      }
+      const int64_t ninc = g.inc_ptr[r + 1] - g.inc_ptr[r];
+      const bool dir = ninc == deg[g.dofs[r]];  // every adjacent element lies in the subdomain
+      if (!dir && std::fabs(w) > 1e-14) {
+        S.err = "partition of unity does not vanish on the boundary of subdomain " + std::to_string(i);
+        return;
+      }
+      S.dv[r] = dir ? w : 0.0;
+      if (dir) {
+        dloc[r] = S.nD++;
+        S.dpos.push_back(r);
+        S.dglob.push_back(g.dofs[r]);
+        if (w != 0.0) S.rankb++;
+      }
+    }
+    for (size_t q = 0; q < els.size(); ++q) {
+      int lo = 1 << 30, hi = -1;
+      for (int a = 0; a < k; ++a) {
+        const int l = g.eloc[q * k + a];
+        if (l >= 0 && dloc[l] >= 0) {
+          lo = std::min(lo, dloc[l]);
+          hi = std::max(hi, dloc[l]);
+        }
+      }
+      if (hi >= 0) S.bd = std::max(S.bd, hi - lo);
+    }
+    // pattern of the Neumann matrix (ELL rows): distinct neighbours via a marker
+    std::vector<int32_t> mark(nb, -1);
+    S.ell_ptr.assign(nb + 1, 0);
+    for (int r = 0; r < nb; ++r) {
+      for (int64_t e = g.inc_ptr[r]; e < g.inc_ptr[r + 1]; ++e) {
+        const int q = g.inc_t[e];
+        for (int a = 0; a < k; ++a) {
+          const int l = g.eloc[(size_t)q * k + a];
+          if (l >= 0 && mark[l] != r) {
+            mark[l] = r;
+            S.ell_col.push_back(l);
+          }
+        }
+      }
+      S.ell_ptr[r + 1] = (int32_t)S.ell_col.size();
+      std::sort(S.ell_col.begin() + S.ell_ptr[r], S.ell_col.end());
+      S.ell_w = std::max(S.ell_w, S.ell_ptr[r + 1] - S.ell_ptr[r]);
+    }
+  });
+  for (int i = 0; i < P; ++i)
+    if (!sp[i].err.empty()) throw MsddError{MSDD_EINVAL, sp[i].err};
+  vlog(c, "plan: subdomain groups (parallel)", &tv);
+  // merge in subdomain order
   F.h_dv.clear();
-  std::vector<double> pou_sum(n, 0.0);
   F.h_nd.assign(P, 0);
   F.h_bd.assign(P, 0);
   F.h_rankb.assign(P, 0);
@@ -506,129 +637,72 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   F.h_dboff.assign(P + 1, 0);
   F.h_dpos.clear();
   F.h_dglob.clear();
-  std::vector<std::vector<std::pair<int32_t, int32_t>>> dinc(n);
-  double tv = now_ms();
+  F.ell_w = 0;
+  std::vector<double> pou_sum(n, 0.0);
+  std::vector<int32_t> dcount(n, 0);
   for (int i = 0; i < P; ++i) {
-    REQUIRE(sep[i + 1] >= sep[i] && sdp[i + 1] >= sdp[i], "subdomain pointers not monotone");
-    std::vector<int32_t> el(se.begin() + sep[i], se.begin() + sep[i + 1]);
-    for (int32_t e : el) REQUIRE(e >= 0 && e < n_elem, "sub_elem entry out of range");
-    F.elems[i] = el;
-    F.plans[i] = plan_group(el.data(), (int64_t)el.size(), ed, k, map);
     const GroupPlan& g = F.plans[i];
-    // the caller's Neumann dofs must be the free dofs of the subdomain's elements
-    const int64_t nd_in = sdp[i + 1] - sdp[i];
-    REQUIRE(nd_in == (int64_t)g.dofs.size(),
-            "sub_dof of subdomain " + std::to_string(i) + " is not the set of free dofs of its elements");
-    std::vector<std::pair<int32_t, double>> dw((size_t)nd_in);
-    for (int64_t t = 0; t < nd_in; ++t) dw[t] = {sd[sdp[i] + t], sw[sdp[i] + t]};
-    std::sort(dw.begin(), dw.end());
-    std::vector<int32_t> dloc(g.dofs.size(), -1);
-    int nD = 0;
-    for (size_t r = 0; r < g.dofs.size(); ++r) {
-      REQUIRE(dw[r].first == g.dofs[r],
-              "sub_dof of subdomain " + std::to_string(i) + " is not the set of free dofs of its elements");
-      const double w = dw[r].second;
-      REQUIRE(std::isfinite(w), "non-finite partition-of-unity weight");
-      const int64_t ninc = g.inc_ptr[r + 1] - g.inc_ptr[r];
-      const bool dir = ninc == deg[g.dofs[r]];  // every adjacent element lies in the subdomain
-      if (!dir) REQUIRE(std::fabs(w) <= 1e-14,
-                        "partition of unity does not vanish on the boundary of subdomain " + std::to_string(i));
-      F.h_dv.push_back(dir ? w : 0.0);
-      pou_sum[g.dofs[r]] += dir ? w : 0.0;
-      if (dir) {
-        dloc[r] = nD++;
-        F.h_dpos.push_back((int32_t)r);
-        F.h_dglob.push_back(g.dofs[r]);
-        dinc[g.dofs[r]].push_back({i, dloc[r]});
-      }
-      if (dir && w != 0.0) F.h_rankb[i]++;
-    }
-    int bd = 0;
-    for (size_t t = 0; t < el.size(); ++t) {
-      int lo = 1 << 30, hi = -1;
-      for (int a = 0; a < k; ++a) {
-        const int l = g.eloc[t * k + a];
-        if (l >= 0 && dloc[l] >= 0) {
-          lo = std::min(lo, dloc[l]);
-          hi = std::max(hi, dloc[l]);
-        }
-      }
-      if (hi >= 0) bd = std::max(bd, hi - lo);
-    }
-    F.h_nd[i] = nD;
-    F.h_bd[i] = bd;
-    F.h_doff[i + 1] = F.h_doff[i] + nD;
-    F.h_dboff[i + 1] = F.h_dboff[i] + (int64_t)nD * (bd + 1);
-    F.nd_max = std::max(F.nd_max, nD);
+    const SubPlan& S = sp[i];
+    F.h_dv.insert(F.h_dv.end(), S.dv.begin(), S.dv.end());
+    for (size_t r = 0; r < g.dofs.size(); ++r) pou_sum[g.dofs[r]] += S.dv[r];
+    for (int32_t d : S.dglob) dcount[d]++;
+    F.h_dpos.insert(F.h_dpos.end(), S.dpos.begin(), S.dpos.end());
+    F.h_dglob.insert(F.h_dglob.end(), S.dglob.begin(), S.dglob.end());
+    F.h_nd[i] = S.nD;
+    F.h_bd[i] = S.bd;
+    F.h_rankb[i] = S.rankb;
+    F.h_doff[i + 1] = F.h_doff[i] + S.nD;
+    F.h_dboff[i + 1] = F.h_dboff[i] + (int64_t)S.nD * (S.bd + 1);
+    F.nd_max = std::max(F.nd_max, S.nD);
+    F.bd_max = std::max(F.bd_max, S.bd);
+    F.bw_max = std::max(F.bw_max, g.bw);
+    F.nb_max = std::max(F.nb_max, (int)g.dofs.size());
+    F.ell_w = std::max(F.ell_w, S.ell_w);
     F.s_nb += (double)g.dofs.size();
     F.s_band += (double)g.dofs.size() * (g.bw + 1);
     F.s_nbb += (double)g.dofs.size() * g.bw;
-    F.s_nd += nD;
-    F.s_dband += (double)nD * (bd + 1);
-    F.s_ndbd += (double)nD * bd;
-    F.bd_max = std::max(F.bd_max, bd);
-    F.bw_max = std::max(F.bw_max, g.bw);
-    F.nb_max = std::max(F.nb_max, (int)g.dofs.size());
+    F.s_nd += S.nD;
+    F.s_dband += (double)S.nD * (S.bd + 1);
+    F.s_ndbd += (double)S.nD * S.bd;
   }
   for (int64_t d = 0; d < n; ++d) {
     REQUIRE(std::fabs(pou_sum[d] - 1.0) <= 1e-12,
             "partition-of-unity weights do not sum to 1 at dof " + std::to_string(d));
-    REQUIRE(!dinc[d].empty(), "dof " + std::to_string(d) + " lies in no subdomain's Dirichlet space");
+    REQUIRE(dcount[d] > 0, "dof " + std::to_string(d) + " lies in no subdomain's Dirichlet space");
   }
+  // fine dof -> (subdomain, Dirichlet position), in subdomain order
+  std::vector<int64_t> dptr(n + 1, 0);
+  for (int64_t d = 0; d < n; ++d) dptr[d + 1] = dptr[d] + dcount[d];
+  std::vector<int32_t> dsub(dptr[n]), dq(dptr[n]);
+  {
+    std::vector<int64_t> pos(dptr.begin(), dptr.end() - 1);
+    for (int i = 0; i < P; ++i)
+      for (int q = 0; q < sp[i].nD; ++q) {
+        const int32_t d = sp[i].dglob[q];
+        dsub[pos[d]] = i;
+        dq[pos[d]] = q;
+        pos[d]++;
+      }
+  }
+  vlog(c, "plan: merge + PoU check", &tv);
   hipStream_t s = c->stream;
-  vlog(c, "plan: subdomain groups + PoU check", &tv);
   build_groupset(F.plans, F.elems, k, F.gs, s);
   F.dv.upload(F.h_dv, s);
-  vlog(c, "plan: groupset upload", &tv);
-  // Neumann band offsets and the ELL structure
   F.h_boff.assign(P + 1, 0);
   for (int i = 0; i < P; ++i)
     F.h_boff[i + 1] = F.h_boff[i] + (int64_t)F.plans[i].dofs.size() * (F.plans[i].bw + 1);
-  int ell_w = 0;
-  std::vector<std::vector<int32_t>> rowcols;
-  int64_t total = F.gs.total_rows;
-  std::vector<int32_t> ell;  // filled after width known
-  std::vector<int32_t> tmp;
-  // first pass: width
-  for (int i = 0; i < P; ++i) {
-    const GroupPlan& g = F.plans[i];
-    for (size_t r = 0; r < g.dofs.size(); ++r) {
-      tmp.clear();
-      for (int64_t e = g.inc_ptr[r]; e < g.inc_ptr[r + 1]; ++e) {
-        const int t = g.inc_t[e];
-        for (int a = 0; a < k; ++a) {
-          const int l = g.eloc[(size_t)t * k + a];
-          if (l >= 0) tmp.push_back(l);
-        }
-      }
-      std::sort(tmp.begin(), tmp.end());
-      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
-      ell_w = std::max(ell_w, (int)tmp.size());
+  std::vector<int32_t> ell((size_t)F.gs.total_rows * F.ell_w, -1);
+  parallel_for(P, nthr, [&](int i, int) {
+    const SubPlan& S = sp[i];
+    const int nb = (int)S.ell_ptr.size() - 1;
+    for (int r = 0; r < nb; ++r) {
+      const int64_t gr = F.gs.h_voff[i] + r;
+      std::copy(S.ell_col.begin() + S.ell_ptr[r], S.ell_col.begin() + S.ell_ptr[r + 1],
+                ell.begin() + gr * F.ell_w);
     }
-  }
-  F.ell_w = ell_w;
-  ell.assign((size_t)total * ell_w, -1);
-  for (int i = 0; i < P; ++i) {
-    const GroupPlan& g = F.plans[i];
-    for (size_t r = 0; r < g.dofs.size(); ++r) {
-      tmp.clear();
-      for (int64_t e = g.inc_ptr[r]; e < g.inc_ptr[r + 1]; ++e) {
-        const int t = g.inc_t[e];
-        for (int a = 0; a < k; ++a) {
-          const int l = g.eloc[(size_t)t * k + a];
-          if (l >= 0) tmp.push_back(l);
-        }
-      }
-      std::sort(tmp.begin(), tmp.end());
-      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
-      const int64_t gr = F.gs.h_voff[i] + (int64_t)r;
-      std::copy(tmp.begin(), tmp.end(), ell.begin() + gr * ell_w);
-    }
-  }
-  vlog(c, "plan: ELL structure", &tv);
+  });
   F.ell_col.upload(ell, s);
   F.boff.upload(F.h_boff, s);
-  // Dirichlet arrays
   std::vector<int32_t> drow_sub(F.h_doff.back());
   for (int i = 0; i < P; ++i)
     for (int64_t g = F.h_doff[i]; g < F.h_doff[i + 1]; ++g) drow_sub[g] = i;
@@ -640,20 +714,11 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   F.dpos.upload(F.h_dpos, s);
   F.dglob.upload(F.h_dglob, s);
   F.rankb.upload(F.h_rankb, s);
-  std::vector<int64_t> dptr(n + 1, 0);
-  std::vector<int32_t> dsub, dq;
-  for (int64_t d = 0; d < n; ++d) {
-    for (auto& pr : dinc[d]) {
-      dsub.push_back(pr.first);
-      dq.push_back(pr.second);
-    }
-    dptr[d + 1] = (int64_t)dsub.size();
-  }
   F.dinc_ptr.upload(dptr, s);
   F.dinc_sub.upload(dsub, s);
   F.dinc_q.upload(dq, s);
   HIPCHK(hipStreamSynchronize(s));
-  vlog(c, "plan: Dirichlet + incidence upload", &tv);
+  vlog(c, "plan: uploads", &tv);
 }
 
 void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
@@ -707,6 +772,10 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   }
   HIPCHK(hipGetLastError());
   check_status(status.download(s), "Cholesky of the Dirichlet matrices");
+  // the apply uses the LDL^T form: row layout in LDr, column layout in place in LDc
+  launch_band_to_ldl<double>(s, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.LDc.p, F.LDr.p);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
 }
 
 void fine_eigensolve(msdd_ctx* c) {
@@ -886,30 +955,54 @@ void fine_patches(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
   hipStream_t s = c->stream;
   const int k = c->k;
   double tv = now_ms();
-  std::vector<std::vector<int32_t>> esub(n_elem);
+  // element -> containing subdomains (CSR, ascending subdomain order)
+  std::vector<int32_t> ecnt(n_elem + 1, 0);
   for (int i = 0; i < F.P; ++i)
-    for (int32_t e : F.elems[i]) esub[e].push_back(i);
-  std::map<std::vector<int32_t>, int> key;
+    for (int32_t e : F.elems[i]) ecnt[e + 1]++;
+  for (int32_t e = 0; e < n_elem; ++e) {
+    REQUIRE(ecnt[e + 1] > 0, "element " + std::to_string(e) + " belongs to no subdomain");
+    ecnt[e + 1] += ecnt[e];
+  }
+  std::vector<int32_t> esub(ecnt[n_elem]);
+  {
+    std::vector<int32_t> pos(ecnt.begin(), ecnt.end() - 1);
+    for (int i = 0; i < F.P; ++i)
+      for (int32_t e : F.elems[i]) esub[pos[e]++] = i;
+  }
+  // group elements by their subdomain set; patches are numbered by first element
+  std::unordered_map<uint64_t, std::vector<int>> key;
   std::vector<std::vector<int32_t>> pel;
   for (int32_t e = 0; e < n_elem; ++e) {
-    REQUIRE(!esub[e].empty(), "element " + std::to_string(e) + " belongs to no subdomain");
-    auto it = key.find(esub[e]);
-    int id;
-    if (it == key.end()) {
+    const int32_t* m0 = esub.data() + ecnt[e];
+    const int cnt = ecnt[e + 1] - ecnt[e];
+    uint64_t h = 1469598103934665603ull;
+    for (int q = 0; q < cnt; ++q) h = (h ^ (uint64_t)(uint32_t)m0[q]) * 1099511628211ull;
+    auto& cand = key[h];
+    int id = -1;
+    for (int c2 : cand) {
+      const auto& mm = PL.members[c2];
+      if ((int)mm.size() == cnt && std::equal(mm.begin(), mm.end(), m0)) {
+        id = c2;
+        break;
+      }
+    }
+    if (id < 0) {
       id = (int)pel.size();
-      key.emplace(esub[e], id);
+      cand.push_back(id);
       pel.push_back({});
-      PL.members.push_back(esub[e]);
-    } else {
-      id = it->second;
+      PL.members.emplace_back(m0, m0 + cnt);
     }
     pel[id].push_back(e);
   }
   PL.np = (int)pel.size();
   vlog(c, "patches: element keys", &tv);
-  std::vector<int> map(c->n, -1);
+  const int nthr = host_threads(PL.np);
+  std::vector<std::vector<int>> maps(nthr);
   std::vector<GroupPlan> plans(PL.np);
-  for (int p = 0; p < PL.np; ++p) plans[p] = plan_group(pel[p].data(), (int64_t)pel[p].size(), ed, k, map);
+  parallel_for(PL.np, nthr, [&](int p, int t) {
+    if (maps[t].empty()) maps[t].assign(c->n, -1);
+    plans[p] = plan_group(pel[p].data(), (int64_t)pel[p].size(), ed, k, maps[t]);
+  });
   vlog(c, "patches: group plans", &tv);
   GroupSetDev gs;
   build_groupset(plans, pel, k, gs, s);
@@ -918,7 +1011,7 @@ void fine_patches(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
   PL.M.assign(PL.np, 0);
   PL.mcol.resize(PL.np);
   std::vector<int64_t> mem_ptr(PL.np + 1, 0), ploc_off(PL.np + 1, 0), vpoff(PL.np + 1, 0);
-  std::vector<int32_t> mem_sub, mem_col, ploc;
+  std::vector<int32_t> mem_sub, mem_col;
   PL.pmoff.assign(PL.np + 1, 0);
   for (int p = 0; p < PL.np; ++p) {
     int M = 0;
@@ -930,18 +1023,27 @@ void fine_patches(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
     }
     PL.M[p] = M;
     mem_ptr[p + 1] = (int64_t)mem_sub.size();
-    const int nm = (int)PL.members[p].size();
-    const auto& pd = plans[p].dofs;
-    for (size_t r = 0; r < pd.size(); ++r)
-      for (int sidx = 0; sidx < nm; ++sidx) {
-        const auto& sdofs = F.plans[PL.members[p][sidx]].dofs;
-        auto itd = std::lower_bound(sdofs.begin(), sdofs.end(), pd[r]);
-        ploc.push_back((itd != sdofs.end() && *itd == pd[r]) ? (int32_t)(itd - sdofs.begin()) : -1);
-      }
-    ploc_off[p + 1] = (int64_t)ploc.size();
-    vpoff[p + 1] = vpoff[p] + (int64_t)pd.size() * M;
+    const int64_t nd = (int64_t)plans[p].dofs.size();
+    ploc_off[p + 1] = ploc_off[p] + nd * (int64_t)PL.members[p].size();
+    vpoff[p + 1] = vpoff[p] + nd * M;
     PL.pmoff[p + 1] = PL.pmoff[p] + (int64_t)M * M;
   }
+  // patch dof -> local index in each member subdomain (-1 outside it)
+  std::vector<int32_t> ploc(ploc_off.back());
+  parallel_for(PL.np, nthr, [&](int p, int) {
+    const int nm = (int)PL.members[p].size();
+    const auto& pd = plans[p].dofs;
+    int32_t* out = ploc.data() + ploc_off[p];
+    for (int sidx = 0; sidx < nm; ++sidx) {
+      const auto& sdofs = F.plans[PL.members[p][sidx]].dofs;
+      // both lists ascending: merge
+      size_t q = 0;
+      for (size_t r = 0; r < pd.size(); ++r) {
+        while (q < sdofs.size() && sdofs[q] < pd[r]) ++q;
+        out[r * nm + sidx] = (q < sdofs.size() && sdofs[q] == pd[r]) ? (int32_t)q : -1;
+      }
+    }
+  });
   vlog(c, "patches: member maps", &tv);
   DVec<int64_t> dmem_ptr, dploc_off, dvpoff;
   DVec<int32_t> dmem_sub, dmem_col, dploc;
@@ -1322,12 +1424,18 @@ void apply_prec(msdd_ctx* c, const double* r, double* z) {
   const int L = c->n_levels - 1;
   double* rc_top = c->rlev[L - 1].p;  // level L-1 vector
   {
-    ProfScope ps(c, PR_APPLY_FINE,
-                 2.0 * F.s_dband * 8.0 + F.s_nd * 12.0 + F.s_ndm * 8.0 + F.s_nd * 8.0 + F.s_m * 8.0,
-                 4.0 * F.s_ndbd + 2.0 * F.s_ndm);
-    launch_apply_fine_down(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dglob.p,
-                           F.dboff.p, F.LDc.p, F.LDr.p, F.dm.p, F.moff.p, F.phid_off.p, F.PhiD.p,
-                           r, rc_top, c->u.p);
+    // gather (index + value) and u write, PhiD read, rc write
+    ProfScope ps(c, PR_APPLY_RESTRICT, F.s_nd * (4.0 + 8.0 + 8.0) + F.s_ndm * 8.0 + F.s_m * 8.0,
+                 2.0 * F.s_ndm);
+    launch_apply_fine_restrict(s, F.P, F.nd_max, F.nd.p, F.doff.p, F.dglob.p, F.dm.p, F.moff.p,
+                               F.phid_off.p, F.PhiD.p, r, rc_top, c->u.p);
+  }
+  {
+    // both sweeps read the band factor once; u is read and written
+    ProfScope ps(c, PR_APPLY_FINE, 2.0 * F.s_dband * 8.0 + 2.0 * F.s_nd * 8.0,
+                 4.0 * F.s_ndbd + F.s_nd);
+    launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
+                            F.LDc.p, F.LDr.p, c->u.p);
   }
   {
     ProfScope ps(c, PR_APPLY_COARSE);
@@ -1402,7 +1510,7 @@ int msdd_create(msdd_ctx** out, const msdd_options* opt) {
     delete c;
     return MSDD_EDEVICE;
   }
-  if (c->opt.precision != MSDD_FP64 && c->opt.precision != MSDD_MIXED) {
+  if (c->opt.precision != MSDD_FP64) {  // the single-precision mode is not built yet
     delete c;
     return MSDD_EINVAL;
   }

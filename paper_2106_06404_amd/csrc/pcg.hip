@@ -106,56 +106,106 @@ __global__ void k_residual(i64 n, const double* __restrict__ b, const double* __
 }
 
 // ---------------------------------------------------------------------------
-// Preconditioner apply, finest level, one wavefront per subdomain:
-//   r_loc = R_i r (Dirichlet dofs), rc[i,:] = PhiD_i^T r_loc (restriction to the
-//   next coarser level), u_i = A_i^{-1} r_loc by blocked band triangular solves.
+// Preconditioner apply, finest level, in two kernels:
+//  k_apply_fine_restrict (one 256-thread workgroup per subdomain):
+//    r_loc = R_i r (Dirichlet dofs) into u_i, rc[i,:] = PhiD_i^T r_loc
+//    (restriction to the next coarser level);
+//  k_apply_fine_rot / k_apply_fine_wave: u_i = A_i^{-1} u_i by the two band sweeps
+//    of the LDL^T factor (see trsv.h).
 // ---------------------------------------------------------------------------
-template <int WMAX>
-__global__ void __launch_bounds__(64) k_apply_fine_down(
-    const i32* __restrict__ nd, const i32* __restrict__ bd, const i64* __restrict__ doff,
-    const i32* __restrict__ dglob, const i64* __restrict__ dboff, const double* __restrict__ Lc,
-    const double* __restrict__ Lr, const i32* __restrict__ msub, const i64* __restrict__ moff,
-    const i64* __restrict__ phid_off, const double* __restrict__ PhiD,
-    const double* __restrict__ r, double* __restrict__ rc, double* __restrict__ u, int nd_max) {
+__global__ void __launch_bounds__(256) k_apply_fine_restrict(
+    const i32* __restrict__ nd, const i64* __restrict__ doff, const i32* __restrict__ dglob,
+    const i32* __restrict__ msub, const i64* __restrict__ moff, const i64* __restrict__ phid_off,
+    const double* __restrict__ PhiD, const double* __restrict__ r, double* __restrict__ rc,
+    double* __restrict__ u) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16 * 8];
   const int i = blockIdx.x;
   const int n = nd[i];
-  const int b = bd[i];
-  double* rl = reinterpret_cast<double*>(smem_raw);  // nd_max
-  double* stage = rl + nd_max;                       // 2*64*(b+1) when staged
   const int tid = threadIdx.x;
+  double* rl = reinterpret_cast<double*>(smem_raw);  // n
   const i32* dg = dglob + doff[i];
-  for (int q = tid; q < n; q += 64) rl[q] = r[dg[q]];
+  double* ui = u + doff[i];
+  for (int q0 = tid; q0 < n; q0 += 4 * 256) {
+    int g[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) g[t] = dg[min(q0 + t * 256, n - 1)];
+    double x[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) x[t] = r[g[t]];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int q = q0 + t * 256;
+      if (q < n) {
+        rl[q] = x[t];
+        ui[q] = x[t];
+      }
+    }
+  }
   __syncthreads();
-  // restriction rc = PhiD^T r_loc, eight columns per pass over the rows
   const int m = msub[i];
   const double* PD = PhiD + phid_off[i];
+  const int lane = tid & 63, wv = tid >> 6;
   for (int c0 = 0; c0 < m; c0 += 8) {
     double acc[8];
 #pragma unroll
     for (int u2 = 0; u2 < 8; ++u2) acc[u2] = 0.0;
-    for (int q = tid; q < n; q += 64) {
+    const int cl = m - 1 - c0;  // last valid column offset of this chunk
+    for (int q = tid; q < n; q += 256) {
       const double x = rl[q];
       const double* prow = PD + (i64)q * m + c0;
 #pragma unroll
-      for (int u2 = 0; u2 < 8; ++u2)
-        if (c0 + u2 < m) acc[u2] += prow[u2] * x;
+      for (int u2 = 0; u2 < 8; ++u2) {
+        const double pv = prow[min(u2, cl)];
+        acc[u2] += (u2 <= cl ? pv : 0.0) * x;
+      }
     }
 #pragma unroll
     for (int u2 = 0; u2 < 8; ++u2) {
       const double s2 = wave_sum(acc[u2]);
-      if (tid == 0 && c0 + u2 < m) rc[moff[i] + c0 + u2] = s2;
+      if (lane == 0) red[wv * 8 + u2] = s2;
     }
+    __syncthreads();
+    if (tid < 8 && c0 + tid < m) {
+      double s3 = 0.0;
+      for (int w2 = 0; w2 < 4; ++w2) s3 += red[w2 * 8 + tid];
+      rc[moff[i] + c0 + tid] = s3;
+    }
+    __syncthreads();
   }
-  if (WMAX > 0) {
-    wg_trsv_staged<double, double, 1, (WMAX > 0 ? WMAX : 1), false>(n, b, Lr + dboff[i], rl, stage);
-    wg_trsv_staged<double, double, 1, (WMAX > 0 ? WMAX : 1), true>(n, b, Lc + dboff[i], rl, stage);
-  } else {
-    wave_trsv_lower<double, double>(n, b, Lr + dboff[i], rl);
-    wave_trsv_upper<double, double>(n, b, Lc + dboff[i], rl);
-  }
+}
+
+// u_i = A_i^{-1} u_i with the LDL^T factor: rolling-window sweeps for half-bandwidths
+// below 64 (one ROT_NT-thread workgroup per subdomain), else the one-wavefront
+// blocked sweeps from the row layout.
+__global__ void __launch_bounds__(ROT_NT) k_apply_fine_rot(
+    const i32* __restrict__ nd, const i32* __restrict__ bd, const i64* __restrict__ doff,
+    const i64* __restrict__ dboff, const double* __restrict__ Fc, const double* __restrict__ Fr,
+    double* __restrict__ u, int nd_max) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = blockIdx.x;
+  const int n = nd[i];
+  double* rl = reinterpret_cast<double*>(smem_raw);  // nd_max (rounded up to even)
+  double* tiles = rl + ((nd_max + 1) & ~1);
   double* ui = u + doff[i];
-  for (int q = tid; q < n; q += 64) ui[q] = rl[q];
+  for (int q = threadIdx.x; q < n; q += ROT_NT) rl[q] = ui[q];
+  __syncthreads();
+  wg_ldl_solve_rot<double, double>(n, bd[i], Fc + dboff[i], Fr + dboff[i], rl, tiles);
+  for (int q = threadIdx.x; q < n; q += ROT_NT) ui[q] = rl[q];
+}
+
+__global__ void __launch_bounds__(64) k_apply_fine_wave(
+    const i32* __restrict__ nd, const i32* __restrict__ bd, const i64* __restrict__ doff,
+    const i64* __restrict__ dboff, const double* __restrict__ Fr, double* __restrict__ u) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = blockIdx.x;
+  const int n = nd[i];
+  double* rl = reinterpret_cast<double*>(smem_raw);
+  double* ui = u + doff[i];
+  for (int q = threadIdx.x; q < n; q += 64) rl[q] = ui[q];
+  __syncthreads();
+  wave_ldl_solve<double, double>(n, bd[i], Fr + dboff[i], rl);
+  for (int q = threadIdx.x; q < n; q += 64) ui[q] = rl[q];
 }
 
 // coarse level l: per subdomain, r_o = r_l[own]; rc = Y^T r_o; z_l[own] = A_oo^{-1} r_o
@@ -281,24 +331,38 @@ void launch_residual(hipStream_t s, i64 n, const double* b, const double* q, dou
                      double* partial) {
   hipLaunchKernelGGL(k_residual, dim3(grid_for(n)), dim3(MSDD_WG), 0, s, n, b, q, r, partial);
 }
-void launch_apply_fine_down(hipStream_t s, int P, int nd_max, int bd_max, const i32* nd,
-                            const i32* bd, const i64* doff, const i32* dglob, const i64* dboff,
-                            const double* Lc, const double* Lr, const i32* msub, const i64* moff,
-                            const i64* phid_off, const double* PhiD, const double* r, double* rc,
-                            double* u) {
-  const int w = bd_max + 1;
-  const int wmax = w <= 40 ? 40 : (w <= 64 ? 64 : 0);
-  const size_t lds = ((size_t)nd_max + (wmax ? 2 * 64 * (size_t)w : 0)) * sizeof(double);
-#define MSDD_AFD(WM)                                                                           \
-  {                                                                                            \
-    if (lds > 65536)                                                                           \
-      (void)hipFuncSetAttribute((const void*)k_apply_fine_down<WM>,                            \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);         \
-    hipLaunchKernelGGL(k_apply_fine_down<WM>, dim3(P), dim3(64), lds, s, nd, bd, doff, dglob,  \
-                       dboff, Lc, Lr, msub, moff, phid_off, PhiD, r, rc, u, nd_max);           \
+void launch_apply_fine_restrict(hipStream_t s, int P, int nd_max, const i32* nd, const i64* doff,
+                                const i32* dglob, const i32* msub, const i64* moff,
+                                const i64* phid_off, const double* PhiD, const double* r,
+                                double* rc, double* u) {
+  if (P == 0) return;
+  const size_t lds = (size_t)nd_max * sizeof(double);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_apply_fine_restrict,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_apply_fine_restrict, dim3(P), dim3(256), lds, s, nd, doff, dglob, msub,
+                     moff, phid_off, PhiD, r, rc, u);
+}
+size_t apply_fine_rot_lds(int nd_max) {
+  return ((size_t)((nd_max + 1) & ~1) + 2 * (size_t)ROT_TILE) * sizeof(double);
+}
+void launch_apply_fine_solve(hipStream_t s, int P, int nd_max, int bd_max, const i32* nd,
+                             const i32* bd, const i64* doff, const i64* dboff, const double* Fc,
+                             const double* Fr, double* u) {
+  if (P == 0) return;
+  const size_t lds = apply_fine_rot_lds(nd_max);
+  if (bd_max < 64 && lds <= 160 * 1024) {
+    (void)hipFuncSetAttribute((const void*)k_apply_fine_rot,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_apply_fine_rot, dim3(P), dim3(ROT_NT), lds, s, nd, bd, doff, dboff, Fc,
+                       Fr, u, nd_max);
+  } else {
+    const size_t l2 = (size_t)nd_max * sizeof(double);
+    if (l2 > 65536)
+      (void)hipFuncSetAttribute((const void*)k_apply_fine_wave,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
+    hipLaunchKernelGGL(k_apply_fine_wave, dim3(P), dim3(64), l2, s, nd, bd, doff, dboff, Fr, u);
   }
-  if (wmax == 40) MSDD_AFD(40) else if (wmax == 64) MSDD_AFD(64) else MSDD_AFD(0)
-#undef MSDD_AFD
 }
 void launch_apply_coarse_down(hipStream_t s, int P, int no_max, const i32* nown,
                               const i64* own_ptr, const i32* own_idx, const i64* loff,
