@@ -19,7 +19,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "setup+solve sec to rel-res 1e-8 (plain FP64 vs mixed/learned); local GEVPs/s"
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VALU_PEAK_TFS = 78.6      # MI355X FP64 vector (256 CUs, 2.4 GHz)
+
+# Kernel classes bound by arithmetic rather than HBM traffic (the rest are priced
+# against HBM with their algorithmic bytes).
+ALU_CLASSES = {"coarse_gevp"}
 
 WORKLOADS = {
     "c2": ("2D scalar diffusion, Q1 512x512, seeded binary inclusions (10%, squares 2-8, k=1e6), "
@@ -66,6 +71,60 @@ def cpu_baseline(prob, budget_s=20.0):
             "local_gevps_per_s": 1.0 / per}
 
 
+def roofline_entry(name, rec):
+    """Achieved = algorithmic work per launch / average launch duration (HIP events on
+    the launching stream), against the MI355X peak of the resource that bounds it."""
+    tot_ms, launches, byts, flops = rec
+    avg_ms = tot_ms / launches
+    if name in ALU_CLASSES:
+        ach = (flops / launches) / (avg_ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": FP64_VALU_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": ach / FP64_VALU_PEAK_TFS, "traffic": traffic_for(name),
+                "alg_flops_per_launch": flops / launches, "avg_launch_ms": avg_ms,
+                "launches": launches}
+    ach = (byts / launches) / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(name),
+            "alg_bytes_per_launch": byts / launches, "avg_launch_ms": avg_ms, "launches": launches}
+
+
+def traffic_for(name):
+    """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE + WRITE_SIZE,
+    scaled by the copy-kernel calibration), from profiles/traffic.md; None when no
+    measurement exists or the kernel's source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        for line in f:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 4 and cells[0] == name:
+                h = hashlib.sha256()
+                for fn in cells[2].split("+"):
+                    src = os.path.join(ROOT, "paper_2106_06404_amd", "csrc", fn.strip())
+                    if not os.path.exists(src):
+                        return None
+                    with open(src, "rb") as g:
+                        h.update(g.read())
+                if h.hexdigest()[:16] != cells[3]:
+                    return None
+                return float(cells[1])
+    return None
+
+
+def copy_calibration(nbytes=1 << 30):
+    """A plain device copy of known size: run under rocprofv3 --pmc FETCH_SIZE (then
+    WRITE_SIZE) to calibrate the counters (it reads and writes nbytes once)."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,7 +133,12 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
               f"of the method is described in DESIGN.md, not run.", file=sys.stderr)
@@ -119,11 +183,9 @@ def main():
     true_rel = float(np.linalg.norm(prob.b - prob.A @ xh) / np.linalg.norm(prob.b))
     n_gevp = sum(st["n_sub"][1:])
     gevp_s = (st["t_gevp_ms"] + st["t_coarse_ms"]) * 1e-3
-    # dominant kernel class with algorithmic bytes: roofline
-    ranked = sorted(((v[0], k) for k, v in prof.items() if v[1] > 0), reverse=True)
-    dom = next(k for _, k in ranked if prof[k][2] > 0)
-    tot_ms, launches, byts, flops = prof[dom]
-    achieved = (byts / launches) / (tot_ms / launches * 1e-3) / 1e9
+    # roofline of every kernel class, and of the dominant one (largest time per step)
+    rl_all = {k: roofline_entry(k, v) for k, v in prof.items() if v[1] > 0}
+    dom = max(rl_all, key=lambda k: prof[k][0])
     out = {
         "metric": METRIC,
         "value": ms_per_step * 1e-3,
@@ -145,11 +207,12 @@ def main():
         "true_relres": true_rel,
         "local_gevps_per_s": n_gevp / gevp_s,
         "coarse_sizes": st["n"],
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": byts / launches,
-                     "avg_launch_ms": tot_ms / launches, "launches": launches},
-        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items() if v[1] > 0},
+        "roofline": dict(rl_all[dom], kernel=dom),
+        "roofline_by_kernel": {k: {"ms_per_step": prof[k][0] / args.steps,
+                                   "launches_per_step": prof[k][1] / args.steps,
+                                   "bound": r["bound"], "achieved": r["achieved"],
+                                   "unit": r["unit"], "frac": r["frac"]}
+                               for k, r in sorted(rl_all.items(), key=lambda kv: -prof[kv[0]][0])},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)

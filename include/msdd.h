@@ -182,7 +182,7 @@ int msdd_get_basis(const msdd_ctx* c, int32_t level, int32_t i, double* basis, i
  * compute; see each kernel's comment).  msdd_profile_name gives the class name
  * (NULL for an id out of range).
  */
-#define MSDD_NPROF 17
+#define MSDD_NPROF 18
 int msdd_profile(msdd_ctx* c, int enable);
 int msdd_profile_query(msdd_ctx* c, int id, double* total_ms, int64_t* launches,
                        double* alg_bytes, double* alg_flops);

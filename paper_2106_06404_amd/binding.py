@@ -61,7 +61,7 @@ EXPORTS = ["msdd_default_options", "msdd_create", "msdd_setup", "msdd_solve", "m
            "msdd_stats", "msdd_get_level_counts", "msdd_get_eigs", "msdd_get_basis",
            "msdd_profile", "msdd_profile_query", "msdd_profile_name", "msdd_last_error",
            "msdd_destroy"]
-MSDD_NPROF = 17
+MSDD_NPROF = 18
 
 _lib = None
 

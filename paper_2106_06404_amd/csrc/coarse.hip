@@ -253,7 +253,7 @@ __global__ void k_dense_cholesky(int n, double* A, int* status) {
 // Coarse GEVP of one level-(l-1) subdomain per workgroup, on its generating system
 // (owned functions first, no of them; Abar is ng x ng column-major):
 //   S = Abar + B with B = D Abar D, D the 0/1 owned mask;
-//   S = Q diag(s) Q^T (Jacobi); keep s > tau * max(s) (the rest is the numerical
+//   S = Q diag(s) Q^T (Jacobi, Q and Y stored transposed); keep s > tau * max(s) (the rest is the numerical
 //   kernel of abar and b, their common kernel in exact arithmetic);
 //   Qk = Q_keep diag(s_keep)^{-1/2};  C = Qk^T B Qk = Qk_o^T A_oo Qk_o;
 //   C = Y diag(mu) Y^T (Jacobi);  lambda = 1/mu - 1;  select lambda < eta;
@@ -267,7 +267,8 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
                               double eta, int nev_max, double tau,
                               double* __restrict__ lam_out, const i64* __restrict__ lamoff,
                               int* __restrict__ m_out, int* __restrict__ status,
-                              int* __restrict__ rank_out) {
+                              int* __restrict__ rank_out, int* __restrict__ sweeps_out,
+                              int ng_max, int in_lds) {
   const int t = blockIdx.x;
   const int ng = ng_arr[t], no = no_arr[t];
   const double* A = Abar + aoff[t];
@@ -279,13 +280,26 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   double* C = Qk + g2;
   double* Yc = C + g2;
   int* keep = reinterpret_cast<int*>(Yc + g2);
-  __shared__ int sh_fail, cnt, sh_r, sh_m;
+  __shared__ int sh_fail, cnt, sh_r, sh_m, nrot, nrot1;
   __shared__ double sh_smax, sh_fro, red[32];
-  __shared__ int pp[512], pq[512];
-  __shared__ double pc[512], ps[512];
+  // dynamic LDS: Jacobi pair data, then (in_lds) the matrix being diagonalised
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int npm = (ng_max + 2) / 2;
+  double* pc = reinterpret_cast<double*>(smem_raw);
+  double* ps = pc + npm;
+  int* pp = reinterpret_cast<int*>(ps + npm);
+  int* pq = pp + npm;
+  double* Alds = reinterpret_cast<double*>(smem_raw) + 2 * npm + npm;  // after 2 int arrays
+  double* Sx = in_lds ? Alds : S;  // S, then C, live in LDS when they fit
+  double* Cx = in_lds ? Alds : C;
   const int tid = threadIdx.x, nt = blockDim.x;
   if (no == 0) {
-    if (tid == 0) { m_out[t] = 0; status[t] = ST_DONE; rank_out[t] = 0; }
+    if (tid == 0) {
+      m_out[t] = 0;
+      status[t] = ST_DONE;
+      rank_out[t] = 0;
+      for (int q = 0; q < 4; ++q) sweeps_out[4 * t + q] = 0;
+    }
     return;
   }
   // S (row-major, symmetric) and its Frobenius norm
@@ -294,20 +308,25 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
     const int r = (int)(e / ng), c = (int)(e % ng);
     const double a = 0.5 * (A[r + (i64)c * ng] + A[c + (i64)r * ng]);
     const double v = (r < no && c < no) ? 2.0 * a : a;
-    S[e] = v;
+    Sx[e] = v;
     fro += v * v;
   }
   fro = block_sum(fro, red);
   if (tid == 0) sh_fro = sqrt(fro);
   __syncthreads();
-  JacobiScratch<double> js{pp, pq, pc, ps, &cnt};
-  jacobi_block<double>(ng, S, Q, js, 60, 2.220446049250313e-16, 1e-18 * sh_fro);
+  if (tid == 0) nrot = 0;
+  JacobiScratch<double> js{pp, pq, pc, ps, &cnt, &nrot};
+  // separate calls so that the LDS case is compiled with LDS accesses
+  const int sw1 = in_lds ? jacobi_block<double, 4, true, 10>(ng, Alds, Q, js, 60, 2.220446049250313e-16, 1e-18 * sh_fro)
+                         : jacobi_block<double, 4, true, 10>(ng, S, Q, js, 60, 2.220446049250313e-16, 1e-18 * sh_fro);
   if (tid == 0) {
+    nrot1 = nrot;  // rotations of the ng x ng diagonalisation
+    nrot = 0;
     double smax = 0.0;
-    for (int a = 0; a < ng; ++a) smax = fmax(smax, S[(i64)a * ng + a]);
+    for (int a = 0; a < ng; ++a) smax = fmax(smax, Sx[(i64)a * ng + a]);
     int r = 0;
     for (int a = 0; a < ng; ++a)
-      if (S[(i64)a * ng + a] > tau * smax) keep[r++] = a;
+      if (Sx[(i64)a * ng + a] > tau * smax) keep[r++] = a;
     sh_smax = smax;
     sh_r = r;
   }
@@ -317,7 +336,7 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   for (i64 e = tid; e < (i64)ng * r; e += nt) {
     const int row = (int)(e / r), k = (int)(e % r);
     const int a = keep[k];
-    Qk[e] = Q[(i64)row * ng + a] / sqrt(S[(i64)a * ng + a]);
+    Qk[e] = Q[(i64)a * ng + row] / sqrt(Sx[(i64)a * ng + a]);  // Q stored transposed
   }
   __syncthreads();
   // C = Qk_o^T A_oo Qk_o: first Q <- A_oo Qk_o (no x r), then C (r x r, row-major)
@@ -333,14 +352,21 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
     if (a > b) continue;
     double acc = 0.0;
     for (int q = 0; q < no; ++q) acc += Qk[(i64)q * r + a] * Q[(i64)q * r + b];
-    C[(i64)a * r + b] = acc;
-    C[(i64)b * r + a] = acc;
+    Cx[(i64)a * r + b] = acc;
+    Cx[(i64)b * r + a] = acc;
   }
   __syncthreads();
   double fc = 0.0;
-  for (i64 e = tid; e < (i64)r * r; e += nt) fc += C[e] * C[e];
+  for (i64 e = tid; e < (i64)r * r; e += nt) fc += Cx[e] * Cx[e];
   fc = block_sum(fc, red);
-  jacobi_block<double>(r, C, Yc, js, 60, 2.220446049250313e-16, 1e-18 * sqrt(fc));
+  const int sw2 = in_lds ? jacobi_block<double, 4, true, 10>(r, Alds, Yc, js, 60, 2.220446049250313e-16, 1e-18 * sqrt(fc))
+                         : jacobi_block<double, 4, true, 10>(r, C, Yc, js, 60, 2.220446049250313e-16, 1e-18 * sqrt(fc));
+  if (tid == 0) {
+    sweeps_out[4 * t] = sw1;
+    sweeps_out[4 * t + 1] = sw2;
+    sweeps_out[4 * t + 2] = nrot1;  // rotations on the ng x ng matrix
+    sweeps_out[4 * t + 3] = nrot;   // rotations on the r x r matrix
+  }
   // sort mu descending, lambda = 1/mu - 1 ascending
   double* lam = lam_out + lamoff[t];
   int* ord = keep;  // reused (r entries)
@@ -348,9 +374,9 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
     for (int a = 0; a < r; ++a) ord[a] = a;
     for (int a = 1; a < r; ++a) {
       const int v = ord[a];
-      const double mv = C[(i64)v * r + v];
+      const double mv = Cx[(i64)v * r + v];
       int b = a - 1;
-      while (b >= 0 && C[(i64)ord[b] * r + ord[b]] < mv) {
+      while (b >= 0 && Cx[(i64)ord[b] * r + ord[b]] < mv) {
         ord[b + 1] = ord[b];
         --b;
       }
@@ -358,7 +384,7 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
     }
     int m = 0, nl = 0;
     for (int a = 0; a < r && nl < no; ++a) {
-      const double mu = C[(i64)ord[a] * r + ord[a]];
+      const double mu = Cx[(i64)ord[a] * r + ord[a]];
       if (mu <= 1e-12) break;
       const double lv = fmax(1.0 / mu - 1.0, 0.0);
       lam[nl++] = lv;
@@ -377,9 +403,9 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   for (i64 e = tid; e < (i64)no * m; e += nt) {
     const int row = (int)(e % no), c = (int)(e / no);
     const int src = ord[c];
-    const double mu = C[(i64)src * r + src];
+    const double mu = Cx[(i64)src * r + src];
     double acc = 0.0;
-    for (int k = 0; k < r; ++k) acc += Qk[(i64)row * r + k] * Yc[(i64)k * r + src];
+    for (int k = 0; k < r; ++k) acc += Qk[(i64)row * r + k] * Yc[(i64)src * r + k];  // Yc transposed
     Xo[row + (i64)c * no] = acc / sqrt(mu);
   }
   // Dirichlet factor of the owned block
@@ -527,11 +553,19 @@ void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_
                         const i64* aoff, double* Abar, const i64* loff, double* Lo,
                         const i64* soff, double* scratch, double eta, int nev_max,
                         double eps_reg, double* lam_out, const i64* lamoff, int* m_out,
-                        int* status, int* rank_out) {
+                        int* status, int* rank_out, int* sweeps_out, int ng_max) {
   if (!nt) return;
-  hipLaunchKernelGGL(k_coarse_gevp, dim3(nt), dim3(1024), 0, s, ng_arr, no_arr, aoff, Abar,
+  const int npm = (ng_max + 2) / 2;
+  const size_t pairs = (size_t)npm * (2 * sizeof(double) + 2 * sizeof(int));
+  const size_t full = pairs + (size_t)ng_max * ng_max * sizeof(double);
+  const int in_lds = full <= 150 * 1024;
+  const size_t lds = in_lds ? full : pairs;
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_coarse_gevp,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_coarse_gevp, dim3(nt), dim3(1024), lds, s, ng_arr, no_arr, aoff, Abar,
                      loff, Lo, soff, scratch, eta, nev_max, eps_reg, lam_out, lamoff, m_out,
-                     status, rank_out);
+                     status, rank_out, sweeps_out, ng_max, in_lds);
 }
 void launch_dense_to_layouts(hipStream_t s, int nt, const i64* off, const i32* n_arr,
                              const double* L, double* R, double* C) {

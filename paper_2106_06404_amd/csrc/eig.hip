@@ -190,7 +190,7 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
   int* ord = reinterpret_cast<int*>(ev + K);         // K
   __shared__ int pp[64], pq[64], cnt;
   __shared__ double pc[64], ps[64], smax;
-  JacobiScratch<double> js{pp, pq, pc, ps, &cnt};
+  JacobiScratch<double> js{pp, pq, pc, ps, &cnt, nullptr};
   const int tid = threadIdx.x, nt = blockDim.x;
   const double* gs = GS + (i64)i * KK;
   const double* gb = GB + (i64)i * KK;

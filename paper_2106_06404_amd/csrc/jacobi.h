@@ -17,6 +17,7 @@ struct JacobiScratch {
   R* pc;
   R* ps;
   int* cnt;  // single int
+  int* tot;  // single int: rotations applied (accumulated; may be null)
 };
 
 template <typename R>
@@ -43,8 +44,11 @@ __device__ inline void jacobi_pair(int r, int k, int m, int& p, int& q) {
 // the column rotation), V <- V J in the same pass; one barrier per phase.
 // Pairs without a rotation act as the identity; blocks of two such pairs are
 // skipped.  With n odd, the dummy index m-1 = n drops out of its pair.
-template <typename R, int JU = 4>
-__device__ int jacobi_block(int n, R* A, R* V, JacobiScratch<R> s, int max_sweeps, R eps,
+// VT: V is stored transposed (V[col*n + row]); the column updates of V then touch
+// two contiguous rows, which matters when V lives in global memory.  JU / JV: work
+// items per thread whose loads are issued together (A blocks / V entries).
+template <typename R, int JU = 4, bool VT = false, int JV = JU>
+__device__ __forceinline__ int jacobi_block(int n, R* A, R* V, JacobiScratch<R> s, int max_sweeps, R eps,
                             R floor_abs) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, nwv = (nt + 63) >> 6;
@@ -144,38 +148,43 @@ __device__ int jacobi_block(int n, R* A, R* V, JacobiScratch<R> s, int max_sweep
           }
         }
         const int nv = n * np;
-        for (int t0 = tid; t0 < nv; t0 += nt * JU) {
-          R x[JU], y[JU];
-          int ia[JU], ib[JU];
+        for (int t0 = tid; t0 < nv; t0 += nt * JV) {
+          R x[JV], y[JV];
+          int ia[JV], ib[JV];
 #pragma unroll
-          for (int u = 0; u < JU; ++u) {
+          for (int u = 0; u < JV; ++u) {
             const int t = t0 + u * nt;
             ia[u] = -1;
             ib[u] = 0;
             x[u] = y[u] = 0;
             if (t < nv) {
-              const int row = t / np, k2 = t - row * np;
+              // VT: consecutive threads take consecutive rows of one column pair
+              const int row = VT ? t % n : t / np;
+              const int k2 = VT ? t / n : t - row * np;
               const int pk2 = s.pp[k2];
               if (pk2 >= 0) {
-                ia[u] = row * n + pk2;
+                ia[u] = VT ? pk2 * n + row : row * n + pk2;
                 ib[u] = k2;
               }
             }
           }
 #pragma unroll
-          for (int u = 0; u < JU; ++u) {
+          for (int u = 0; u < JV; ++u) {
             if (ia[u] >= 0) {
+              const int k2 = ib[u];
+              const int dq = VT ? (s.pq[k2] - s.pp[k2]) * n : s.pq[k2] - s.pp[k2];
               x[u] = V[ia[u]];
-              y[u] = V[ia[u] - s.pp[ib[u]] + s.pq[ib[u]]];
+              y[u] = V[ia[u] + dq];
             }
           }
 #pragma unroll
-          for (int u = 0; u < JU; ++u) {
+          for (int u = 0; u < JV; ++u) {
             if (ia[u] < 0) continue;
             const int k2 = ib[u];
+            const int dq = VT ? (s.pq[k2] - s.pp[k2]) * n : s.pq[k2] - s.pp[k2];
             const R c2 = s.pc[k2], s2 = s.ps[k2];
             V[ia[u]] = c2 * x[u] - s2 * y[u];
-            V[ia[u] - s.pp[k2] + s.pq[k2]] = s2 * x[u] + c2 * y[u];
+            V[ia[u] + dq] = s2 * x[u] + c2 * y[u];
           }
         }
       }
@@ -183,6 +192,7 @@ __device__ int jacobi_block(int n, R* A, R* V, JacobiScratch<R> s, int max_sweep
     }
     const int c = *s.cnt;
     __syncthreads();
+    if (tid == 0 && s.tot) *s.tot += c;
     if (c == 0) break;
   }
   return sweep < max_sweeps ? sweep + 1 : -1;

@@ -88,7 +88,7 @@ void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_
                         const i64* aoff, double* Abar, const i64* loff, double* Lo,
                         const i64* soff, double* scratch, double eta, int nev_max,
                         double eps_reg, double* lam_out, const i64* lamoff, int* m_out,
-                        int* status, int* rank_out);
+                        int* status, int* rank_out, int* sweeps_out, int ng_max);
 void launch_dense_to_layouts(hipStream_t s, int nt, const i64* off, const i32* n_arr,
                              const double* L, double* R, double* C);
 void launch_spd_inverse(hipStream_t s, int nt, int nmax, const i64* off, const i32* n_arr,

@@ -366,13 +366,14 @@ enum ProfId {
   PR_EIG_RR,        // Rayleigh-Ritz small eigenproblems
   PR_EIG_UPDATE,    // block update + residuals
   PR_PATCH,         // patch matrices and projections
-  PR_COARSE,        // coarse assembly + coarse GEVP + A_0 Cholesky
+  PR_COARSE,        // coarse assembly, coarse factorisations and inverses, A_0
   PR_SPMV,          // CSR SpMV (+ fused dot)
   PR_VEC,           // PCG vector updates and dot products
   PR_APPLY_FINE,    // finest-level band triangular solves (LDL^T sweeps)
   PR_APPLY_COARSE,  // coarse-level solves, restriction, prolongation
   PR_APPLY_GATHER,  // finest-level prolongation + gather
   PR_APPLY_RESTRICT,  // finest-level gather of r + restriction to level L-1
+  PR_COARSE_GEVP,     // coarse-level GEVPs on the generating systems (Jacobi)
   PR_OTHER,
   PR_COUNT
 };
@@ -381,7 +382,7 @@ const char* kProfNames[PR_COUNT] = {
     "neumann_assemble", "dirichlet_extract", "band_cholesky", "eig_band_solve",
     "eig_bapply", "eig_gram", "eig_rayleigh_ritz", "eig_update", "patch", "coarse",
     "spmv", "pcg_vector", "apply_fine_solve", "apply_coarse", "apply_fine_gather",
-    "apply_fine_restrict", "other"};
+    "apply_fine_restrict", "coarse_gevp", "other"};
 
 struct Profiler {
   bool on = false;
@@ -1200,22 +1201,46 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
   scratch.alloc(std::max<int64_t>(soff.back(), 1));
   CL.Lo.alloc(std::max<int64_t>(CL.h_loff.back(), 1));
   CL.lam.alloc(std::max<int64_t>(lamoff.back(), 1));
-  DVec<int> mo, st, rk;
+  DVec<int> mo, st, rk, sweeps;
   mo.alloc(Pc);
   st.alloc(Pc);
   rk.alloc(Pc);
+  sweeps.alloc(4 * Pc);
   st.zero(s);
   DVec<int64_t> aoff;
   aoff.upload(J.aoff, s);
+  std::vector<int> sw;
+  std::vector<int> rkh;
   {
-    ProfScope pscope(c, PR_COARSE);
+    // flops: each Jacobi rotation of an n x n matrix rotates two rows and two columns
+    // of it and two eigenvector columns, 3 flops per rotated entry (18 n); counted
+    // from the rotations the kernel reports
+    ProfScope pscope(c, PR_COARSE_GEVP);
     launch_coarse_gevp(s, Pc, dng.p, dno.p, aoff.p, Abar.p, CL.loff.p, CL.Lo.p, dsoff.p,
                        scratch.p, c->eta, c->opt.nev_max, c->opt.eps_reg_rel, CL.lam.p, dlamoff.p,
-                       mo.p, st.p, rk.p);
+                       mo.p, st.p, rk.p, sweeps.p,
+                       Pc ? *std::max_element(CL.ng.begin(), CL.ng.end()) : 0);
+    HIPCHK(hipGetLastError());
+    sw = sweeps.download(s);
+    rkh = rk.download(s);
+    double fl = 0.0;
+    for (int i = 0; i < Pc; ++i)
+      fl += 18.0 * ((double)sw[4 * i + 2] * CL.ng[i] + (double)sw[4 * i + 3] * rkh[i]);
+    pscope.flops = fl;
   }
-  HIPCHK(hipGetLastError());
   std::vector<int> stv = st.download(s);
   vlog(c, "coarse: GEVP kernel", &tv);
+  if (c->opt.verbose) {
+    int ngm = 0, s1 = 0, s2 = 0, rmax = 0;
+    for (int i = 0; i < Pc; ++i) {
+      ngm = std::max(ngm, CL.ng[i]);
+      s1 = std::max(s1, sw[4 * i]);
+      s2 = std::max(s2, sw[4 * i + 1]);
+      rmax = std::max(rmax, rkh[i]);
+    }
+    fprintf(stderr, "msdd:   coarse level %d: %d subdomains, ng max %d, rank max %d, Jacobi sweeps max %d / %d\n",
+            l, Pc, ngm, rmax, s1, s2);
+  }
   check_status(stv, "coarse GEVP (Cholesky of the owned block)");
   CL.m = mo.download(s);
   CL.rank = rk.download(s);
