@@ -147,6 +147,13 @@ int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
 int msdd_solve(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit,
                int32_t* iters, double* relres);
 
+/*
+ * Residual history of the last msdd_solve: relres[k] = ||r_k||_2 / ||r_0||_2 for
+ * k = 0..iters (recurrence residuals, Sec. 5).  Writes min(cap, iters+1) values
+ * (relres may be NULL to query); *count receives iters+1 (0 before any solve).
+ */
+int msdd_solve_history(const msdd_ctx* c, double* relres, int32_t cap, int32_t* count);
+
 /* z = B r: one application of the multilevel additive preconditioner. */
 int msdd_apply(msdd_ctx* c, const double* r, double* z);
 

@@ -57,7 +57,8 @@ class MsddStats(ctypes.Structure):
         return d
 
 
-EXPORTS = ["msdd_default_options", "msdd_create", "msdd_setup", "msdd_solve", "msdd_apply",
+EXPORTS = ["msdd_default_options", "msdd_create", "msdd_setup", "msdd_solve",
+           "msdd_solve_history", "msdd_apply",
            "msdd_stats", "msdd_get_level_counts", "msdd_get_eigs", "msdd_get_basis",
            "msdd_profile", "msdd_profile_query", "msdd_profile_name", "msdd_last_error",
            "msdd_destroy"]
@@ -91,6 +92,8 @@ def load():
     L.msdd_setup.restype = ctypes.c_int
     L.msdd_solve.argtypes = [vp, vp, vp, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]
     L.msdd_solve.restype = ctypes.c_int
+    L.msdd_solve_history.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
+    L.msdd_solve_history.restype = ctypes.c_int
     L.msdd_apply.argtypes = [vp, vp, vp]
     L.msdd_apply.restype = ctypes.c_int
     L.msdd_stats.argtypes = [vp, ctypes.POINTER(MsddStats)]
@@ -178,6 +181,15 @@ class Msdd:
                                 int(maxit), ctypes.byref(it), ctypes.byref(rel))
         self._check(rc, allow=(MSDD_ENOCONV,) if allow_noconv else ())
         return int(it.value), float(rel.value), rc
+
+    def history(self) -> np.ndarray:
+        """||r_k|| / ||r_0||, k = 0..iters, of the last solve."""
+        cnt = ctypes.c_int32()
+        self._check(self._L.msdd_solve_history(self._h, None, 0, ctypes.byref(cnt)))
+        buf = np.zeros(max(cnt.value, 1), np.float64)
+        self._check(self._L.msdd_solve_history(self._h, ctypes.c_void_p(buf.ctypes.data),
+                                               cnt.value, ctypes.byref(cnt)))
+        return buf[:cnt.value].copy()
 
     def apply(self, r, z):
         return self._check(self._L.msdd_apply(self._h, _ptr(r, np.float64), _ptr(z, np.float64)))

@@ -458,6 +458,7 @@ struct msdd_ctx {
   DVec<double> u, r, z, p, q, x, bvec, partial, sc;
   double* h_pinned = nullptr;
   msdd_stats_t stats;
+  std::vector<double> hist;  // ||r_k|| / ||r_0||, k = 0..iters, of the last solve
   Profiler prof;
   int eig_active = 0;  // subdomains running in the eigensolver (last status read)
   ~msdd_ctx() {
@@ -1736,6 +1737,7 @@ int msdd_solve(msdd_ctx* c, const double* b, double* x, double rtol, int32_t max
     launch_reduce(s, part, np, sc, PCG_SC_RR0, PCG_RED_SET);
     const double rr0 = read_scalar(c, PCG_SC_RR0);
     REQUIRE(std::isfinite(rr0), "non-finite right-hand side or initial guess");
+    c->hist.assign(1, 1.0);
     int it = 0;
     double rel = 0.0;
     bool conv = rr0 == 0.0;
@@ -1760,6 +1762,7 @@ int msdd_solve(msdd_ctx* c, const double* b, double* x, double rtol, int32_t max
         const double rr = read_scalar(c, PCG_SC_RR);
         REQUIRE(std::isfinite(rr), "PCG produced a non-finite residual");
         rel = std::sqrt(rr / rr0);
+        c->hist.push_back(rel);
         if (rr < tol2) {
           conv = true;
           break;
@@ -1787,6 +1790,15 @@ int msdd_solve(msdd_ctx* c, const double* b, double* x, double rtol, int32_t max
   } catch (const MsddError& e) {
     return code_for(c, e);
   }
+}
+
+int msdd_solve_history(const msdd_ctx* c, double* relres, int32_t cap, int32_t* count) {
+  if (!c || !count || cap < 0) return MSDD_EINVAL;
+  const int32_t nh = (int32_t)c->hist.size();
+  *count = nh;
+  if (relres)
+    for (int32_t k = 0; k < std::min(nh, cap); ++k) relres[k] = c->hist[k];
+  return MSDD_OK;
 }
 
 int msdd_stats(const msdd_ctx* c, msdd_stats_t* out) {
