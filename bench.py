@@ -150,37 +150,49 @@ def main():
     dev = "cuda:0"
     arrs = B.problem_arrays(prob, device=dev)
     b = torch.from_numpy(prob.b).to(dev)
-    x = torch.zeros_like(b)
     torch.cuda.synchronize()
-    ctx = B.Msdd(verbose=1 if args.verbose else 0)
 
-    def step():
-        ctx.setup(**arrs)
-        x.zero_()
-        it, rel, _ = ctx.solve(b, x, 1e-8, 5000)
-        return it, rel
+    def measure(precision):
+        """warm-up steps, then exactly args.steps timed steps (setup + solve), inputs
+        resident in HBM; synchronised on both sides of the timed region."""
+        x = torch.zeros_like(b)
+        ctx = B.Msdd(verbose=1 if args.verbose else 0, precision=precision)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    setup_ms, solve_ms, iters = [], [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        it, rel = step()
+        def step():
+            ctx.setup(**arrs)
+            x.zero_()
+            it, rel, _ = ctx.solve(b, x, 1e-8, 5000)
+            return it, rel
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        setup_ms, solve_ms, iters = [], [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            it, rel = step()
+            st = ctx.stats()
+            setup_ms.append(st["t_setup_ms"])
+            solve_ms.append(st["t_solve_ms"])
+            iters.append(it)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = ctx.profile_query()
+        ctx.profile(False)
         st = ctx.stats()
-        setup_ms.append(st["t_setup_ms"])
-        solve_ms.append(st["t_solve_ms"])
-        iters.append(it)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = ctx.profile_query()
-    ctx.profile(False)
-    st = ctx.stats()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    # true residual of the last solution (host check, outside the timed region)
-    xh = x.cpu().numpy()
-    true_rel = float(np.linalg.norm(prob.b - prob.A @ xh) / np.linalg.norm(prob.b))
+        ctx.close()
+        # true residual of the last solution (host check, outside the timed region)
+        xh = x.cpu().numpy()
+        true_rel = float(np.linalg.norm(prob.b - prob.A @ xh) / np.linalg.norm(prob.b))
+        return dict(ms_per_step=(t1 - t0) * 1e3 / args.steps, prof=prof, st=st, iters=iters,
+                    setup_ms=setup_ms, solve_ms=solve_ms, true_rel=true_rel)
+
+    r64 = measure(B.MSDD_FP64)
+    r32 = measure(B.MSDD_MIXED)
+    prof, st, iters = r64["prof"], r64["st"], r64["iters"]
+    setup_ms, solve_ms, true_rel = r64["setup_ms"], r64["solve_ms"], r64["true_rel"]
+    ms_per_step = r64["ms_per_step"]
     n_gevp = sum(st["n_sub"][1:])
     gevp_s = (st["t_gevp_ms"] + st["t_coarse_ms"]) * 1e-3
     # roofline of every kernel class, and of the dominant one (largest time per step)
@@ -213,6 +225,22 @@ def main():
                                    "bound": r["bound"], "achieved": r["achieved"],
                                    "unit": r["unit"], "frac": r["frac"]}
                                for k, r in sorted(rl_all.items(), key=lambda kv: -prof[kv[0]][0])},
+    }
+    p32 = r32["prof"]
+    out["mixed"] = {
+        "what": ("finest-level Dirichlet factorisations and the fine-level solves of the "
+                 "preconditioner apply in FP32 (diagonally scaled); eigensolves, coarse levels "
+                 "and PCG in FP64; same stopping rule"),
+        "s_per_step": r32["ms_per_step"] * 1e-3,
+        "setup_s": float(np.median(r32["setup_ms"])) * 1e-3,
+        "solve_s": float(np.median(r32["solve_ms"])) * 1e-3,
+        "pcg_iters": r32["iters"][-1],
+        "true_relres": r32["true_rel"],
+        "speedup_vs_fp64": ms_per_step / r32["ms_per_step"],
+        "solve_speedup_vs_fp64": (float(np.median(solve_ms)) / float(np.median(r32["solve_ms"]))),
+        "apply_fine_solve": (dict(roofline_entry("apply_fine_solve", p32["apply_fine_solve"]),
+                                  traffic=None)
+                             if p32.get("apply_fine_solve", (0, 0))[1] else None),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)

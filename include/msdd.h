@@ -54,11 +54,11 @@ extern "C" {
 
 /* precision modes */
 #define MSDD_FP64 0   /* everything in double precision */
-#define MSDD_MIXED 1  /* local factorisations, eigensolves and the preconditioner apply in
-                         single precision; PCG recurrences, inner products, the coarsest
-                         factorisation and the eigen-residual check in double.
-                         Not available in this version: msdd_create returns
-                         MSDD_EINVAL for it. */
+#define MSDD_MIXED 1  /* finest-level Dirichlet factorisations and their solves in the
+                         preconditioner apply in single precision (on the diagonally
+                         scaled matrices diag(A_i)^{-1/2} A_i diag(A_i)^{-1/2}); local
+                         eigensolves, coarse levels, the coarsest factorisation, PCG
+                         recurrences and inner products in double */
 
 typedef struct msdd_ctx msdd_ctx; /* opaque; owns all device memory it allocates */
 

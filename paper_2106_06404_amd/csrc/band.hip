@@ -380,6 +380,46 @@ template void launch_band_to_ldl<double>(hipStream_t, int, int, int, const i32*,
 template void launch_band_to_ldl<float>(hipStream_t, int, int, int, const i32*, const i32*,
                                         const i64*, float*, float*);
 
+// Diagonal scaling of the Dirichlet band matrices (column layout B[c*w + d] =
+// A(c+d, c)): sc[j] = 1/sqrt(A(j,j)), then B <- diag(sc) B diag(sc) in place (unit
+// diagonal).  With coefficient jumps the scaled matrix is far better conditioned,
+// which lets its factorisation run in single precision.  grid.y = subdomain.
+__global__ void k_band_diag_scale(const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
+                                  const i64* __restrict__ off, const i64* __restrict__ doff,
+                                  const double* __restrict__ B, double* __restrict__ sc,
+                                  int* __restrict__ status) {
+  const int i = blockIdx.y;
+  const int n = n_arr[i], w = b_arr[i] + 1;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const double a = B[off[i] + (i64)j * w];
+    if (!(a > 0.0)) status[i] = ST_NOTSPD;
+    sc[doff[i] + j] = a > 0.0 ? 1.0 / sqrt(a) : 0.0;
+  }
+}
+__global__ void k_band_apply_scale(const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
+                                   const i64* __restrict__ off, const i64* __restrict__ doff,
+                                   double* __restrict__ B, const double* __restrict__ sc) {
+  const int i = blockIdx.y;
+  const int n = n_arr[i], w = b_arr[i] + 1;
+  const double* si = sc + doff[i];
+  double* Bi = B + off[i];
+  const i64 cnt = (i64)n * w;
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (i64)gridDim.x * blockDim.x) {
+    const int c = (int)(e / w), d = (int)(e - (i64)c * w);
+    if (c + d < n) Bi[e] *= si[c] * si[c + d];
+  }
+}
+void launch_band_scale(hipStream_t s, int nsubs, int nmax, int bmax, const i32* n_arr,
+                       const i32* b_arr, const i64* off, const i64* doff, double* B, double* sc,
+                       int* status) {
+  if (nsubs == 0 || nmax == 0) return;
+  hipLaunchKernelGGL(k_band_diag_scale, dim3(std::min((nmax + 255) / 256, 16), nsubs), dim3(256), 0,
+                     s, n_arr, b_arr, off, doff, B, sc, status);
+  const i64 cnt = (i64)nmax * (bmax + 1);
+  hipLaunchKernelGGL(k_band_apply_scale, dim3((int)std::min<i64>((cnt + 255) / 256, 64), nsubs),
+                     dim3(256), 0, s, n_arr, b_arr, off, doff, B, sc);
+}
+
 size_t band_cholesky_lds(int bmax, int elem_size) {
   size_t w = (size_t)bmax + 1;
   return (w * w + w) * elem_size;

@@ -28,6 +28,9 @@ void launch_band_cholesky(hipStream_t s, int nsubs, const i32* subs, int bmax, c
 template <typename T>
 void launch_band_to_ldl(hipStream_t s, int nsubs, int nmax, int bmax, const i32* n_arr,
                         const i32* b_arr, const i64* off, T* Lc, T* F);
+void launch_band_scale(hipStream_t s, int nsubs, int nmax, int bmax, const i32* n_arr,
+                       const i32* b_arr, const i64* off, const i64* doff, double* B, double* sc,
+                       int* status);
 size_t band_cholesky_lds(int bmax, int elem_size);
 template <typename T, typename V>
 void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax,
@@ -116,9 +119,12 @@ void launch_apply_fine_restrict(hipStream_t s, int P, int nd_max, const i32* nd,
                                 const i32* dglob, const i32* msub, const i64* moff,
                                 const i64* phid_off, const double* PhiD, const double* r,
                                 double* rc, double* u);
+// u_i = A_i^{-1} u_i with the LDL^T factor (Fc column layout, Fr row layout) in double
+// (fp32 = 0) or single precision (fp32 = 1; Fc, Fr are float and the factor is that of
+// diag(scale) A_i diag(scale), scale given per Dirichlet dof).
 void launch_apply_fine_solve(hipStream_t s, int P, int nd_max, int bd_max, const i32* nd,
-                             const i32* bd, const i64* doff, const i64* dboff, const double* Fc,
-                             const double* Fr, double* u);
+                             const i32* bd, const i64* doff, const i64* dboff, const void* Fc,
+                             const void* Fr, int fp32, const double* scale, double* u);
 void launch_apply_coarse_down(hipStream_t s, int P, int no_max, const i32* nown,
                               const i64* own_ptr, const i32* own_idx, const i64* loff,
                               const double* Inv, const i32* msub, const i64* yoff,

@@ -318,6 +318,8 @@ struct FineLevel {
   DVec<int32_t> nd, bd, dpos, dglob, drow_sub, rankb;
   DVec<int64_t> doff, dboff;
   DVec<double> Dband, LDc, LDr;
+  DVec<float> LDc32, LDr32;  // single-precision mode: factor of diag(sc) A_i diag(sc)
+  DVec<double> dscale;       // sc per Dirichlet dof (single-precision mode)
   int nd_max = 0, bd_max = 0, bw_max = 0, nb_max = 0;
   // sums used for the algorithmic byte / flop counts of the profiler
   double s_nb = 0, s_band = 0, s_nbb = 0, s_nd = 0, s_dband = 0, s_ndbd = 0, s_ndm = 0, s_m = 0;
@@ -763,6 +765,30 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   }
   HIPCHK(hipGetLastError());
   check_status(status.download(s), "Cholesky of abar + sigma*b");
+  if (c->opt.precision == MSDD_MIXED) {
+    // single precision: factor diag(sc) A_i diag(sc), sc = diag(A_i)^{-1/2}
+    F.dscale.alloc(std::max<int64_t>(F.h_doff.back(), 1));
+    launch_band_scale(s, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.doff.p, F.Dband.p,
+                      F.dscale.p, status.p);
+    HIPCHK(hipGetLastError());
+    check_status(status.download(s), "Dirichlet matrix diagonal");
+    F.LDc32.alloc(F.h_dboff.back());
+    F.LDr32.alloc(F.h_dboff.back());
+    F.LDc32.zero(s);
+    F.LDr32.zero(s);
+    {
+    ProfScope ps(c, PR_CHOL, F.s_dband * (8.0 + 2.0 * 4.0), F.s_ndbd * (F.bd_max + 2.0));
+    launch_band_cholesky<float>(s, P, nullptr, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.Dband.p,
+                                nullptr, nullptr, 0.0, F.dboff.p, F.LDc32.p, F.LDr32.p, status.p);
+    }
+    HIPCHK(hipGetLastError());
+    check_status(status.download(s), "single-precision Cholesky of the scaled Dirichlet matrices");
+    launch_band_to_ldl<float>(s, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.LDc32.p,
+                              F.LDr32.p);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return;
+  }
   F.LDc.alloc(F.h_dboff.back());
   F.LDr.alloc(F.h_dboff.back());
   F.LDc.zero(s);
@@ -1457,11 +1483,18 @@ void apply_prec(msdd_ctx* c, const double* r, double* z) {
                                F.phid_off.p, F.PhiD.p, r, rc_top, c->u.p);
   }
   {
-    // both sweeps read the band factor once; u is read and written
-    ProfScope ps(c, PR_APPLY_FINE, 2.0 * F.s_dband * 8.0 + 2.0 * F.s_nd * 8.0,
+    // both sweeps read the band factor once; u is read and written (and the scaling
+    // read twice in single precision)
+    const bool f32 = c->opt.precision == MSDD_MIXED;
+    ProfScope ps(c, PR_APPLY_FINE,
+                 2.0 * F.s_dband * (f32 ? 4.0 : 8.0) + 2.0 * F.s_nd * 8.0 + (f32 ? 2.0 * F.s_nd * 8.0 : 0.0),
                  4.0 * F.s_ndbd + F.s_nd);
-    launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
-                            F.LDc.p, F.LDr.p, c->u.p);
+    if (f32)
+      launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
+                              F.LDc32.p, F.LDr32.p, 1, F.dscale.p, c->u.p);
+    else
+      launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
+                              F.LDc.p, F.LDr.p, 0, nullptr, c->u.p);
   }
   {
     ProfScope ps(c, PR_APPLY_COARSE);
@@ -1536,7 +1569,7 @@ int msdd_create(msdd_ctx** out, const msdd_options* opt) {
     delete c;
     return MSDD_EDEVICE;
   }
-  if (c->opt.precision != MSDD_FP64) {  // the single-precision mode is not built yet
+  if (c->opt.precision != MSDD_FP64 && c->opt.precision != MSDD_MIXED) {
     delete c;
     return MSDD_EINVAL;
   }

@@ -178,34 +178,39 @@ __global__ void __launch_bounds__(256) k_apply_fine_restrict(
 // u_i = A_i^{-1} u_i with the LDL^T factor: rolling-window sweeps for half-bandwidths
 // below 64 (one ROT_NT-thread workgroup per subdomain), else the one-wavefront
 // blocked sweeps from the row layout.
+template <typename T>
 __global__ void __launch_bounds__(ROT_NT) k_apply_fine_rot(
     const i32* __restrict__ nd, const i32* __restrict__ bd, const i64* __restrict__ doff,
-    const i64* __restrict__ dboff, const double* __restrict__ Fc, const double* __restrict__ Fr,
-    double* __restrict__ u, int nd_max) {
+    const i64* __restrict__ dboff, const T* __restrict__ Fc, const T* __restrict__ Fr,
+    const double* __restrict__ scale, double* __restrict__ u, int nd_max) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = blockIdx.x;
   const int n = nd[i];
-  double* rl = reinterpret_cast<double*>(smem_raw);  // nd_max (rounded up to even)
-  double* tiles = rl + ((nd_max + 1) & ~1);
+  T* rl = reinterpret_cast<T*>(smem_raw);  // nd_max (rounded up to a multiple of 4)
+  T* tiles = rl + ((nd_max + 3) & ~3);
   double* ui = u + doff[i];
-  for (int q = threadIdx.x; q < n; q += ROT_NT) rl[q] = ui[q];
+  const double* si = scale ? scale + doff[i] : nullptr;
+  for (int q = threadIdx.x; q < n; q += ROT_NT) rl[q] = (T)(si ? ui[q] * si[q] : ui[q]);
   __syncthreads();
-  wg_ldl_solve_rot<double, double>(n, bd[i], Fc + dboff[i], Fr + dboff[i], rl, tiles);
-  for (int q = threadIdx.x; q < n; q += ROT_NT) ui[q] = rl[q];
+  wg_ldl_solve_rot<T, T>(n, bd[i], Fc + dboff[i], Fr + dboff[i], rl, tiles);
+  for (int q = threadIdx.x; q < n; q += ROT_NT) ui[q] = si ? (double)rl[q] * si[q] : (double)rl[q];
 }
 
+template <typename T>
 __global__ void __launch_bounds__(64) k_apply_fine_wave(
     const i32* __restrict__ nd, const i32* __restrict__ bd, const i64* __restrict__ doff,
-    const i64* __restrict__ dboff, const double* __restrict__ Fr, double* __restrict__ u) {
+    const i64* __restrict__ dboff, const T* __restrict__ Fr, const double* __restrict__ scale,
+    double* __restrict__ u) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = blockIdx.x;
   const int n = nd[i];
-  double* rl = reinterpret_cast<double*>(smem_raw);
+  T* rl = reinterpret_cast<T*>(smem_raw);
   double* ui = u + doff[i];
-  for (int q = threadIdx.x; q < n; q += 64) rl[q] = ui[q];
+  const double* si = scale ? scale + doff[i] : nullptr;
+  for (int q = threadIdx.x; q < n; q += 64) rl[q] = (T)(si ? ui[q] * si[q] : ui[q]);
   __syncthreads();
-  wave_ldl_solve<double, double>(n, bd[i], Fr + dboff[i], rl);
-  for (int q = threadIdx.x; q < n; q += 64) ui[q] = rl[q];
+  wave_ldl_solve<T, T>(n, bd[i], Fr + dboff[i], rl);
+  for (int q = threadIdx.x; q < n; q += 64) ui[q] = si ? (double)rl[q] * si[q] : (double)rl[q];
 }
 
 // coarse level l: per subdomain, r_o = r_l[own]; rc = Y^T r_o; z_l[own] = A_oo^{-1} r_o
@@ -343,25 +348,41 @@ void launch_apply_fine_restrict(hipStream_t s, int P, int nd_max, const i32* nd,
   hipLaunchKernelGGL(k_apply_fine_restrict, dim3(P), dim3(256), lds, s, nd, doff, dglob, msub,
                      moff, phid_off, PhiD, r, rc, u);
 }
-size_t apply_fine_rot_lds(int nd_max) {
-  return ((size_t)((nd_max + 1) & ~1) + 2 * (size_t)ROT_TILE) * sizeof(double);
+size_t apply_fine_rot_lds(int nd_max, size_t elem) {
+  return ((size_t)((nd_max + 3) & ~3) + 2 * (size_t)ROT_TILE) * elem;
 }
 void launch_apply_fine_solve(hipStream_t s, int P, int nd_max, int bd_max, const i32* nd,
-                             const i32* bd, const i64* doff, const i64* dboff, const double* Fc,
-                             const double* Fr, double* u) {
+                             const i32* bd, const i64* doff, const i64* dboff, const void* Fc,
+                             const void* Fr, int fp32, const double* scale, double* u) {
   if (P == 0) return;
-  const size_t lds = apply_fine_rot_lds(nd_max);
+  const size_t lds = apply_fine_rot_lds(nd_max, fp32 ? sizeof(float) : sizeof(double));
   if (bd_max < 64 && lds <= 160 * 1024) {
-    (void)hipFuncSetAttribute((const void*)k_apply_fine_rot,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_apply_fine_rot, dim3(P), dim3(ROT_NT), lds, s, nd, bd, doff, dboff, Fc,
-                       Fr, u, nd_max);
+    if (fp32) {
+      (void)hipFuncSetAttribute((const void*)k_apply_fine_rot<float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(k_apply_fine_rot<float>, dim3(P), dim3(ROT_NT), lds, s, nd, bd, doff,
+                         dboff, (const float*)Fc, (const float*)Fr, scale, u, nd_max);
+    } else {
+      (void)hipFuncSetAttribute((const void*)k_apply_fine_rot<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(k_apply_fine_rot<double>, dim3(P), dim3(ROT_NT), lds, s, nd, bd, doff,
+                         dboff, (const double*)Fc, (const double*)Fr, scale, u, nd_max);
+    }
   } else {
     const size_t l2 = (size_t)nd_max * sizeof(double);
-    if (l2 > 65536)
-      (void)hipFuncSetAttribute((const void*)k_apply_fine_wave,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
-    hipLaunchKernelGGL(k_apply_fine_wave, dim3(P), dim3(64), l2, s, nd, bd, doff, dboff, Fr, u);
+    if (fp32) {
+      if (l2 > 65536)
+        (void)hipFuncSetAttribute((const void*)k_apply_fine_wave<float>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
+      hipLaunchKernelGGL(k_apply_fine_wave<float>, dim3(P), dim3(64), l2, s, nd, bd, doff, dboff,
+                         (const float*)Fr, scale, u);
+    } else {
+      if (l2 > 65536)
+        (void)hipFuncSetAttribute((const void*)k_apply_fine_wave<double>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
+      hipLaunchKernelGGL(k_apply_fine_wave<double>, dim3(P), dim3(64), l2, s, nd, bd, doff, dboff,
+                         (const double*)Fr, scale, u);
+    }
   }
 }
 void launch_apply_coarse_down(hipStream_t s, int P, int no_max, const i32* nown,

@@ -214,6 +214,33 @@ def test_c1_local_eigenpairs_residual():
     m.close()
 
 
+@pytest.mark.parametrize("case", ["c1", "three_level"])
+def test_mixed_precision_apply(case):
+    """Single-precision Dirichlet factors and fine-level solves (MSDD_MIXED): the coarse
+    spaces are those of double precision (bitwise), PCG reaches the same recurrence
+    tolerance in at most 3 more iterations, and the true residual stays within 10x of
+    the double-precision run's (its error against the oracle is stated, not bounded)."""
+    from paper_2106_06404_amd import binding as B
+    prob = (P.config1() if case == "c1" else
+            P.small_problem(N=20, P=4, delta=2, contrast=1e4, n_levels=3, groups=(2,), seed=12))
+    out = {}
+    for prec in (B.MSDD_FP64, B.MSDD_MIXED):
+        m, _ = _setup(prob, precision=prec)
+        L = prob.n_levels - 1
+        counts = m.level_counts(L, prob.n_sub)
+        eigs = [m.eigs(L, i, 0) for i in range(prob.n_sub)]
+        it, rel, x = _solve(m, prob)
+        tr = np.linalg.norm(prob.b - prob.A @ x) / np.linalg.norm(prob.b)
+        out[prec] = (counts, eigs, it, rel, x, tr)
+        m.close()
+    c64, e64, it64, _, x64, tr64 = out[B.MSDD_FP64]
+    c32, e32, it32, rel32, x32, tr32 = out[B.MSDD_MIXED]
+    assert np.array_equal(c64, c32)
+    assert all(np.array_equal(a, b) for a, b in zip(e64, e32))
+    assert rel32 < 1e-8 and it32 <= it64 + 3
+    assert tr32 <= 10 * tr64 + 1e-12
+
+
 def test_single_subdomain_empty_coarse_space():
     prob = P.small_problem(N=10, P=1, delta=0, contrast=1e3, seed=3)
     m, _ = _setup(prob)
