@@ -158,28 +158,47 @@ def main():
         x = torch.zeros_like(b)
         ctx = B.Msdd(verbose=1 if args.verbose else 0, precision=precision)
 
-        def step():
+        def step(profile_solve):
+            # kernel-class counters run during the setup; the solve runs with them paused
+            # (its iterations are then replayed as HIP graphs) unless profile_solve
+            ctx.profile(True, reset=False)
             ctx.setup(**arrs)
+            if not profile_solve:
+                ctx.profile(False)
             x.zero_()
             it, rel, _ = ctx.solve(b, x, 1e-8, 5000)
+            ctx.profile(False)
             return it, rel
 
         for _ in range(args.warmup):
-            step()
+            step(False)
         torch.cuda.synchronize()
         ctx.profile(True)
+        ctx.profile(False)
         setup_ms, solve_ms, iters = [], [], []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            it, rel = step()
+            it, rel = step(False)
             st = ctx.stats()
             setup_ms.append(st["t_setup_ms"])
             solve_ms.append(st["t_solve_ms"])
             iters.append(it)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = ctx.profile_query()
+        prof_setup = ctx.profile_query()
+        # one more step, solve phase profiled kernel by kernel (outside the timed region)
+        ctx.profile(True)
         ctx.profile(False)
+        x.zero_()
+        ctx.profile(True, reset=False)
+        ctx.solve(b, x, 1e-8, 5000)
+        ctx.profile(False)
+        prof_solve = ctx.profile_query()
+        # per step: setup classes averaged over the timed steps, solve classes from one solve
+        prof = {}
+        for k in prof_setup:
+            a, bq = prof_setup[k], prof_solve[k]
+            prof[k] = tuple(v / args.steps for v in a) if a[1] else tuple(bq)
         st = ctx.stats()
         ctx.close()
         # true residual of the last solution (host check, outside the timed region)
@@ -220,8 +239,8 @@ def main():
         "local_gevps_per_s": n_gevp / gevp_s,
         "coarse_sizes": st["n"],
         "roofline": dict(rl_all[dom], kernel=dom),
-        "roofline_by_kernel": {k: {"ms_per_step": prof[k][0] / args.steps,
-                                   "launches_per_step": prof[k][1] / args.steps,
+        "roofline_by_kernel": {k: {"ms_per_step": prof[k][0],
+                                   "launches_per_step": prof[k][1],
                                    "bound": r["bound"], "achieved": r["achieved"],
                                    "unit": r["unit"], "frac": r["frac"]}
                                for k, r in sorted(rl_all.items(), key=lambda kv: -prof[kv[0]][0])},
@@ -248,7 +267,7 @@ def main():
         for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0]):
             if v[1]:
                 gbs = v[2] / (v[0] * 1e-3) / 1e9 if v[0] > 0 else 0
-                print(f"  {k:20s} {v[0] / args.steps:9.3f} ms/step  {v[1] / args.steps:7.0f} launches"
+                print(f"  {k:20s} {v[0]:9.3f} ms/step  {v[1]:7.0f} launches"
                       f"  {gbs:8.1f} GB/s alg", file=sys.stderr)
     print(json.dumps(out))
 

@@ -148,6 +148,16 @@ int msdd_solve(msdd_ctx* c, const double* b, double* x, double rtol, int32_t max
                int32_t* iters, double* relres);
 
 /*
+ * PCG on every problem of a batch set up by msdd_setup_batch (Sec. 5), each problem
+ * with its own CG scalars and stopping test.  b, x: the concatenated vectors (host
+ * or device); iters[nprob], relres[nprob] (may be NULL) receive per-problem counts
+ * and ||r_m|| / ||r_0||.  On a context set up by msdd_setup it equals msdd_solve.
+ * Returns MSDD_ENOCONV if some problem reached maxit.
+ */
+int msdd_solve_batch(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit,
+                     int32_t* iters, double* relres);
+
+/*
  * Residual history of the last msdd_solve: relres[k] = ||r_k||_2 / ||r_0||_2 for
  * k = 0..iters (recurrence residuals, Sec. 5).  Writes min(cap, iters+1) values
  * (relres may be NULL to query); *count receives iters+1 (0 before any solve).
@@ -182,7 +192,9 @@ int msdd_get_basis(const msdd_ctx* c, int32_t level, int32_t i, double* basis, i
 
 /*
  * Kernel timing (HIP events recorded around each launch on the context's
- * stream).  msdd_profile(c, 1) enables and resets the counters, 0 disables.
+ * stream).  msdd_profile(c, 1) resets the counters and enables them, 0 pauses them
+ * (the counts are kept), 2 resumes without a reset.  While they are on, the PCG
+ * iterations are launched one by one (not replayed as a graph).
  * msdd_profile_query returns, for kernel class id (0 <= id < MSDD_NPROF),
  * the summed duration in ms, the number of launches, and the algorithmic
  * bytes and flops of those launches (what the method must read, write and

@@ -58,7 +58,7 @@ class MsddStats(ctypes.Structure):
 
 
 EXPORTS = ["msdd_default_options", "msdd_create", "msdd_setup", "msdd_solve",
-           "msdd_solve_history", "msdd_apply",
+           "msdd_solve_batch", "msdd_solve_history", "msdd_apply",
            "msdd_stats", "msdd_get_level_counts", "msdd_get_eigs", "msdd_get_basis",
            "msdd_profile", "msdd_profile_query", "msdd_profile_name", "msdd_last_error",
            "msdd_destroy"]
@@ -92,6 +92,8 @@ def load():
     L.msdd_setup.restype = ctypes.c_int
     L.msdd_solve.argtypes = [vp, vp, vp, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]
     L.msdd_solve.restype = ctypes.c_int
+    L.msdd_solve_batch.argtypes = [vp, vp, vp, f64, i32, vp, vp]
+    L.msdd_solve_batch.restype = ctypes.c_int
     L.msdd_solve_history.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
     L.msdd_solve_history.restype = ctypes.c_int
     L.msdd_apply.argtypes = [vp, vp, vp]
@@ -220,8 +222,10 @@ class Msdd:
                                                ctypes.byref(r), ctypes.byref(c)))
         return out.T.copy()
 
-    def profile(self, enable=True):
-        return self._check(self._L.msdd_profile(self._h, 1 if enable else 0))
+    def profile(self, enable=True, reset=True):
+        """enable=True: reset (unless reset=False) and enable; False: pause, keeping counts."""
+        mode = (1 if reset else 2) if enable else 0
+        return self._check(self._L.msdd_profile(self._h, mode))
 
     def profile_query(self) -> dict:
         """{kernel class: (total_ms, launches, algorithmic bytes, algorithmic flops)}"""

@@ -101,20 +101,26 @@ void launch_coarse_collect(hipStream_t s, int nt, const i32* ng_arr, const i32* 
                            const i64* yoff, double* Y);
 
 // pcg.hip
-enum { PCG_SC_RZ = 0, PCG_SC_PQ = 1, PCG_SC_RR = 2, PCG_SC_ALPHA = 3, PCG_SC_BETA = 4,
-       PCG_SC_RR0 = 5, PCG_SC_TMP = 6 };
-enum { PCG_RED_SET = 0, PCG_RED_ALPHA = 1, PCG_RED_BETA = 2 };
-int pcg_grid(i64 n);
-void launch_spmv_dot(hipStream_t s, i64 n, int sg, const i64* rowptr, const i32* col,
-                     const double* val, const double* p, double* q, double* partial, int want_dot);
-void launch_reduce(hipStream_t s, const double* partial, int np, double* sc, int slot, int rule);
-void launch_update_xr(hipStream_t s, i64 n, double* x, double* r, const double* p,
-                      const double* q, const double* sc, double* partial);
-void launch_dot(hipStream_t s, i64 n, const double* a, const double* b, double* partial);
-void launch_update_p(hipStream_t s, i64 n, const double* z, double* p, const double* sc,
-                     int use_beta);
-void launch_residual(hipStream_t s, i64 n, const double* b, const double* q, double* r,
-                     double* partial);
+// segmented PCG (see pcg.hip): per-segment state fields and reduction rules
+enum { PCG_RZ = 0, PCG_PQ, PCG_RR, PCG_ALPHA, PCG_BETA, PCG_RR0, PCG_TOL2, PCG_SD };
+enum { PCG_ACTIVE = 0, PCG_IT, PCG_ITERS, PCG_SI };
+enum { PCG_RUNNING = 1, PCG_CONVERGED = 0, PCG_MAXIT = 2, PCG_BREAKDOWN = -1 };
+enum { PCG_R_RR0 = 0, PCG_R_RZ0, PCG_R_PQ, PCG_R_RR, PCG_R_RZ };
+void launch_spmv_chunk(hipStream_t s, int nch, int sg, const i64* ch_lo, const i64* ch_hi,
+                       const i64* rowptr, const i32* col, const double* val, const double* p,
+                       double* q, double* partial);
+void launch_residual_chunk(hipStream_t s, int nch, const i64* ch_lo, const i64* ch_hi,
+                           const double* b, const double* q, double* r, double* partial);
+void launch_update_xr_chunk(hipStream_t s, int nch, const i64* ch_lo, const i64* ch_hi,
+                            const i32* ch_seg, double* x, double* r, const double* p,
+                            const double* q, const double* D, double* partial);
+void launch_dot_chunk(hipStream_t s, int nch, const i64* ch_lo, const i64* ch_hi, const double* a,
+                      const double* b, double* partial);
+void launch_update_p_chunk(hipStream_t s, int nch, const i64* ch_lo, const i64* ch_hi,
+                           const i32* ch_seg, const double* z, double* p, const double* D,
+                           int first);
+void launch_seg_reduce(hipStream_t s, int nseg, const i64* seg_ch, const double* partial,
+                       double* D, int* I, int rule, double rtol, int maxit, double* hist);
 void launch_apply_fine_restrict(hipStream_t s, int P, int nd_max, const i32* nd, const i64* doff,
                                 const i32* dglob, const i32* msub, const i64* moff,
                                 const i64* phid_off, const double* PhiD, const double* r,

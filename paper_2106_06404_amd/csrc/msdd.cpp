@@ -457,14 +457,34 @@ struct msdd_ctx {
   DVec<double> A0, A0inv;
   // solve work
   std::vector<DVec<double>> rlev, zlev;  // index l = 0..L-1
-  DVec<double> u, r, z, p, q, x, bvec, partial, sc;
-  double* h_pinned = nullptr;
+  DVec<double> u, r, z, p, q, x, bvec, partial;
+  // PCG segments (one per problem) and chunks (row ranges inside one segment)
+  std::vector<int64_t> h_seg_row;        // nseg+1
+  int nseg = 1, nch = 0;
+  DVec<int64_t> ch_lo, ch_hi, seg_ch;
+  DVec<int32_t> ch_seg;
+  DVec<double> segD, hist_d;  // per-segment CG scalars; residual history
+  DVec<int> segI;
+  int hist_cap = 0;
+  int* h_segI = nullptr;      // pinned
+  std::vector<int> last_iters;
+  std::vector<double> last_relres;
+  hipStream_t gstream = nullptr;  // capture stream for the iteration graphs
+  hipEvent_t gev0 = nullptr, gev1 = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const double* g_x = nullptr;  // pointers the cached graph was captured with
+  const double* g_b = nullptr;
+  int g_maxit = -1;
   msdd_stats_t stats;
   std::vector<double> hist;  // ||r_k|| / ||r_0||, k = 0..iters, of the last solve
   Profiler prof;
   int eig_active = 0;  // subdomains running in the eigensolver (last status read)
   ~msdd_ctx() {
-    if (h_pinned) (void)hipHostFree(h_pinned);
+    if (h_segI) (void)hipHostFree(h_segI);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (gev0) (void)hipEventDestroy(gev0);
+    if (gev1) (void)hipEventDestroy(gev1);
+    if (gstream) (void)hipStreamDestroy(gstream);
   }
 };
 
@@ -1464,14 +1484,37 @@ void alloc_solve_work(msdd_ctx* c) {
   c->q.alloc(n);
   c->x.alloc(n);
   c->bvec.alloc(n);
-  c->partial.alloc(2048);
-  c->sc.alloc(16);
-  if (!c->h_pinned) HIPCHK(hipHostMalloc((void**)&c->h_pinned, 64 * sizeof(double), hipHostMallocDefault));
+  // chunks of at most 256 rows, never crossing a segment boundary
+  const int64_t CH = 256;
+  std::vector<int64_t> lo, hi, sch(c->nseg + 1, 0);
+  std::vector<int32_t> sg;
+  for (int q = 0; q < c->nseg; ++q) {
+    for (int64_t a = c->h_seg_row[q]; a < c->h_seg_row[q + 1]; a += CH) {
+      lo.push_back(a);
+      hi.push_back(std::min(a + CH, c->h_seg_row[q + 1]));
+      sg.push_back(q);
+    }
+    sch[q + 1] = (int64_t)lo.size();
+  }
+  c->nch = (int)lo.size();
+  hipStream_t s = c->stream;
+  c->ch_lo.upload(lo, s);
+  c->ch_hi.upload(hi, s);
+  c->ch_seg.upload(sg, s);
+  c->seg_ch.upload(sch, s);
+  c->partial.alloc(std::max(c->nch, 1));
+  c->segD.alloc((size_t)c->nseg * PCG_SD);
+  c->segI.alloc((size_t)c->nseg * PCG_SI);
+  if (c->h_segI) (void)hipHostFree(c->h_segI);
+  c->h_segI = nullptr;
+  HIPCHK(hipHostMalloc((void**)&c->h_segI, (size_t)c->nseg * PCG_SI * sizeof(int), hipHostMallocDefault));
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  HIPCHK(hipStreamSynchronize(s));
 }
 
-// z = B r (Sec. 2.1, additive over all levels)
-void apply_prec(msdd_ctx* c, const double* r, double* z) {
-  hipStream_t s = c->stream;
+// z = B r (Sec. 2.1, additive over all levels), launched on stream s
+void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
   FineLevel& F = c->F;
   const int L = c->n_levels - 1;
   double* rc_top = c->rlev[L - 1].p;  // level L-1 vector
@@ -1523,11 +1566,7 @@ void apply_prec(msdd_ctx* c, const double* r, double* z) {
   }
 }
 
-double read_scalar(msdd_ctx* c, int slot) {
-  HIPCHK(hipMemcpyAsync(c->h_pinned, c->sc.p + slot, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  return c->h_pinned[0];
-}
+
 
 }  // namespace
 
@@ -1680,6 +1719,10 @@ int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     c->nlev[L] = n;
     c->nlev[L - 1] = c->F.h_moff.back();
     for (int t = 0; t < L - 1; ++t) c->nlev[L - 2 - t] = c->C[t].h_moff.back();
+    if ((int)c->h_seg_row.size() != c->nseg + 1 || c->h_seg_row.back() != n) {
+      c->nseg = 1;
+      c->h_seg_row = {0, n};
+    }
     alloc_solve_work(c);
     HIPCHK(hipStreamSynchronize(s));
     const double t5 = now_ms();
@@ -1733,7 +1776,7 @@ int msdd_apply(msdd_ctx* c, const double* r, double* z) {
       rin = c->r.p;
     }
     double* zout = zdev ? z : c->z.p;
-    apply_prec(c, rin, zout);
+    apply_prec(c, rin, zout, s);
     HIPCHK(hipGetLastError());
     if (!zdev) HIPCHK(hipMemcpyAsync(z, zout, n * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1743,83 +1786,179 @@ int msdd_apply(msdd_ctx* c, const double* r, double* z) {
   }
 }
 
+namespace {
+
+// One PCG iteration on every segment (Sec. 5), launched on stream s.
+void pcg_iteration(msdd_ctx* c, hipStream_t s, double* xx, int maxit) {
+  const int64_t n = c->n;
+  const int nch = c->nch, ns = c->nseg;
+  const double spmv_bytes = (double)c->nnz * 12.0 + (double)(n + 1) * 8.0 + 2.0 * n * 8.0;
+  {
+    ProfScope ps(c, PR_SPMV, spmv_bytes, 2.0 * c->nnz);
+    launch_spmv_chunk(s, nch, c->spmv_sg, c->ch_lo.p, c->ch_hi.p, c->rowptr.p, c->col.p, c->val.p,
+                      c->p.p, c->q.p, c->partial.p);
+  }
+  {
+    ProfScope ps(c, PR_VEC, 6.0 * n * 8.0, 6.0 * n);
+    launch_seg_reduce(s, ns, c->seg_ch.p, c->partial.p, c->segD.p, c->segI.p, PCG_R_PQ, 0.0, maxit,
+                      c->hist_d.p);
+    launch_update_xr_chunk(s, nch, c->ch_lo.p, c->ch_hi.p, c->ch_seg.p, xx, c->r.p, c->p.p, c->q.p,
+                           c->segD.p, c->partial.p);
+    launch_seg_reduce(s, ns, c->seg_ch.p, c->partial.p, c->segD.p, c->segI.p, PCG_R_RR, 0.0, maxit,
+                      c->hist_d.p);
+  }
+  apply_prec(c, c->r.p, c->z.p, s);
+  {
+    ProfScope ps(c, PR_VEC, 5.0 * n * 8.0, 4.0 * n);
+    launch_dot_chunk(s, nch, c->ch_lo.p, c->ch_hi.p, c->r.p, c->z.p, c->partial.p);
+    launch_seg_reduce(s, ns, c->seg_ch.p, c->partial.p, c->segD.p, c->segI.p, PCG_R_RZ, 0.0, maxit,
+                      c->hist_d.p);
+    launch_update_p_chunk(s, nch, c->ch_lo.p, c->ch_hi.p, c->ch_seg.p, c->z.p, c->p.p, c->segD.p, 0);
+  }
+}
+
+// Iterations run in chunks of PCG_CHUNK without reading anything back; a segment that
+// converged is frozen on the device (alpha = beta = 0).  Without profiling, a chunk is
+// captured once as a HIP graph (per x pointer and maxit) and replayed.
+constexpr int PCG_CHUNK = 8;
+
+bool any_running(msdd_ctx* c) {
+  HIPCHK(hipMemcpyAsync(c->h_segI, c->segI.p, (size_t)c->nseg * PCG_SI * sizeof(int),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int q = 0; q < c->nseg; ++q)
+    if (c->h_segI[q * PCG_SI + PCG_ACTIVE] == PCG_RUNNING) return true;
+  return false;
+}
+
+void run_chunk(msdd_ctx* c, double* xx, const double* bb, int maxit) {
+  if (c->prof.on) {
+    for (int k = 0; k < PCG_CHUNK; ++k) pcg_iteration(c, c->stream, xx, maxit);
+    return;
+  }
+  if (!c->gstream) {
+    HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->gev0, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->gev1, hipEventDisableTiming));
+  }
+  if (!c->gexec || c->g_x != xx || c->g_b != bb || c->g_maxit != maxit) {
+    if (c->gexec) HIPCHK(hipGraphExecDestroy(c->gexec));
+    c->gexec = nullptr;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < PCG_CHUNK; ++k) pcg_iteration(c, c->gstream, xx, maxit);
+    HIPCHK(hipStreamEndCapture(c->gstream, &g));
+    const hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    c->g_x = xx;
+    c->g_b = bb;
+    c->g_maxit = maxit;
+  }
+  HIPCHK(hipEventRecord(c->gev0, c->stream));
+  HIPCHK(hipStreamWaitEvent(c->gstream, c->gev0, 0));
+  HIPCHK(hipGraphLaunch(c->gexec, c->gstream));
+  HIPCHK(hipEventRecord(c->gev1, c->gstream));
+  HIPCHK(hipStreamWaitEvent(c->stream, c->gev1, 0));
+}
+
+// PCG on all segments from the initial guess in x; per-segment iteration counts and
+// final recurrence residuals in c->last_iters / c->last_relres.  Returns the status.
+int solve_all(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit) {
+  HIPCHK(hipSetDevice(c->opt.device));
+  REQUIRE(b && x && rtol > 0 && maxit >= 0, "bad solve arguments");
+  hipStream_t s = c->stream;
+  const double t0 = now_ms();
+  const int64_t n = c->n;
+  const int ns = c->nseg;
+  const bool bdev = is_device_ptr(b), xdev = is_device_ptr(x);
+  const double* bb = b;
+  if (!bdev) {
+    HIPCHK(hipMemcpyAsync(c->bvec.p, b, n * sizeof(double), hipMemcpyHostToDevice, s));
+    bb = c->bvec.p;
+  }
+  double* xx = xdev ? x : c->x.p;
+  if (!xdev) HIPCHK(hipMemcpyAsync(xx, x, n * sizeof(double), hipMemcpyHostToDevice, s));
+  if (c->hist_cap < maxit + 1) {
+    c->hist_d.alloc((size_t)(maxit + 1) * ns);
+    c->hist_cap = maxit + 1;
+    if (c->gexec) HIPCHK(hipGraphExecDestroy(c->gexec));
+    c->gexec = nullptr;
+  }
+  // r = b - A x, rr0 per segment
+  launch_spmv_chunk(s, c->nch, c->spmv_sg, c->ch_lo.p, c->ch_hi.p, c->rowptr.p, c->col.p, c->val.p,
+                    xx, c->q.p, c->partial.p);
+  launch_residual_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, bb, c->q.p, c->r.p, c->partial.p);
+  launch_seg_reduce(s, ns, c->seg_ch.p, c->partial.p, c->segD.p, c->segI.p, PCG_R_RR0, rtol, maxit,
+                    c->hist_d.p);
+  apply_prec(c, c->r.p, c->z.p, s);
+  launch_dot_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, c->r.p, c->z.p, c->partial.p);
+  launch_seg_reduce(s, ns, c->seg_ch.p, c->partial.p, c->segD.p, c->segI.p, PCG_R_RZ0, 0.0, maxit,
+                    c->hist_d.p);
+  launch_update_p_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, c->ch_seg.p, c->z.p, c->p.p, c->segD.p, 1);
+  HIPCHK(hipGetLastError());
+  int done_its = 0;
+  while (any_running(c) && done_its < maxit) {
+    run_chunk(c, xx, bb, maxit);
+    HIPCHK(hipGetLastError());
+    done_its += PCG_CHUNK;
+  }
+  if (!xdev) HIPCHK(hipMemcpyAsync(x, xx, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  std::vector<double> D = c->segD.download(s);
+  std::vector<int> I = c->segI.download(s);
+  c->last_iters.assign(ns, 0);
+  c->last_relres.assign(ns, 0.0);
+  int status = MSDD_OK;
+  bool bad = false;
+  for (int q = 0; q < ns; ++q) {
+    const int act = I[q * PCG_SI + PCG_ACTIVE];
+    c->last_iters[q] = act == PCG_RUNNING ? I[q * PCG_SI + PCG_IT] : I[q * PCG_SI + PCG_ITERS];
+    const double rr0 = D[q * PCG_SD + PCG_RR0];
+    c->last_relres[q] = rr0 > 0 ? std::sqrt(D[q * PCG_SD + PCG_RR] / rr0) : 0.0;
+    if (act == PCG_BREAKDOWN) bad = true;
+    else if (act != PCG_CONVERGED) status = MSDD_ENOCONV;
+  }
+  REQUIRE(!bad, "PCG produced a non-finite value (breakdown or non-finite input)");
+  // residual history of segment 0
+  const int it0 = c->last_iters[0];
+  std::vector<double> hd = c->hist_d.download(s);
+  c->hist.assign(it0 + 1, 0.0);
+  for (int k = 0; k <= it0; ++k) c->hist[k] = hd[(size_t)k * ns];
+  c->stats.pcg_iters = *std::max_element(c->last_iters.begin(), c->last_iters.end());
+  c->stats.pcg_relres = *std::max_element(c->last_relres.begin(), c->last_relres.end());
+  c->stats.t_solve_ms = now_ms() - t0;
+  return status;
+}
+
+}  // namespace
+
 int msdd_solve(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit,
                int32_t* iters, double* relres) {
   if (!c) return MSDD_EINVAL;
   if (!c->ready) return code_for(c, MsddError{MSDD_ESTATE, "msdd_solve before a successful setup"});
   try {
-    HIPCHK(hipSetDevice(c->opt.device));
-    REQUIRE(b && x && rtol > 0 && maxit >= 0, "bad solve arguments");
-    hipStream_t s = c->stream;
-    const double t0 = now_ms();
-    const int64_t n = c->n;
-    const bool bdev = is_device_ptr(b), xdev = is_device_ptr(x);
-    const double* bb = b;
-    if (!bdev) {
-      HIPCHK(hipMemcpyAsync(c->bvec.p, b, n * sizeof(double), hipMemcpyHostToDevice, s));
-      bb = c->bvec.p;
+    const int st = solve_all(c, b, x, rtol, maxit);
+    if (iters) *iters = c->stats.pcg_iters;
+    if (relres) *relres = c->stats.pcg_relres;
+    if (st == MSDD_ENOCONV) return code_for(c, MsddError{MSDD_ENOCONV, "PCG reached maxit"});
+    return st;
+  } catch (const MsddError& e) {
+    return code_for(c, e);
+  }
+}
+
+int msdd_solve_batch(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit,
+                     int32_t* iters, double* relres) {
+  if (!c) return MSDD_EINVAL;
+  if (!c->ready) return code_for(c, MsddError{MSDD_ESTATE, "msdd_solve_batch before a successful setup"});
+  try {
+    const int st = solve_all(c, b, x, rtol, maxit);
+    for (int q = 0; q < c->nseg; ++q) {
+      if (iters) iters[q] = c->last_iters[q];
+      if (relres) relres[q] = c->last_relres[q];
     }
-    double* xx = xdev ? x : c->x.p;
-    if (!xdev) HIPCHK(hipMemcpyAsync(xx, x, n * sizeof(double), hipMemcpyHostToDevice, s));
-    const int np = pcg_grid(n);
-    double* part = c->partial.p;
-    double* sc = c->sc.p;
-    // r = b - A x
-    launch_spmv_dot(s, n, c->spmv_sg, c->rowptr.p, c->col.p, c->val.p, xx, c->q.p, part, 0);
-    launch_residual(s, n, bb, c->q.p, c->r.p, part);
-    launch_reduce(s, part, np, sc, PCG_SC_RR0, PCG_RED_SET);
-    const double rr0 = read_scalar(c, PCG_SC_RR0);
-    REQUIRE(std::isfinite(rr0), "non-finite right-hand side or initial guess");
-    c->hist.assign(1, 1.0);
-    int it = 0;
-    double rel = 0.0;
-    bool conv = rr0 == 0.0;
-    if (!conv) {
-      apply_prec(c, c->r.p, c->z.p);
-      launch_dot(s, n, c->r.p, c->z.p, part);
-      launch_reduce(s, part, np, sc, PCG_SC_RZ, PCG_RED_SET);
-      launch_update_p(s, n, c->z.p, c->p.p, sc, 0);
-      const double tol2 = rtol * rtol * rr0;
-      const double spmv_bytes = (double)c->nnz * 12.0 + (double)(n + 1) * 8.0 + 2.0 * n * 8.0;
-      for (it = 1; it <= maxit; ++it) {
-        {
-          ProfScope ps(c, PR_SPMV, spmv_bytes, 2.0 * c->nnz);
-          launch_spmv_dot(s, n, c->spmv_sg, c->rowptr.p, c->col.p, c->val.p, c->p.p, c->q.p, part, 1);
-        }
-        {
-          ProfScope ps(c, PR_VEC, 6.0 * n * 8.0, 6.0 * n);
-          launch_reduce(s, part, np, sc, 0, PCG_RED_ALPHA);
-          launch_update_xr(s, n, xx, c->r.p, c->p.p, c->q.p, sc, part);
-          launch_reduce(s, part, np, sc, PCG_SC_RR, PCG_RED_SET);
-        }
-        const double rr = read_scalar(c, PCG_SC_RR);
-        REQUIRE(std::isfinite(rr), "PCG produced a non-finite residual");
-        rel = std::sqrt(rr / rr0);
-        c->hist.push_back(rel);
-        if (rr < tol2) {
-          conv = true;
-          break;
-        }
-        apply_prec(c, c->r.p, c->z.p);
-        {
-          ProfScope ps(c, PR_VEC, 5.0 * n * 8.0, 4.0 * n);
-          launch_dot(s, n, c->r.p, c->z.p, part);
-          launch_reduce(s, part, np, sc, 0, PCG_RED_BETA);
-          launch_update_p(s, n, c->z.p, c->p.p, sc, 1);
-        }
-      }
-      if (!conv) it = maxit;
-    }
-    HIPCHK(hipGetLastError());
-    if (!xdev) HIPCHK(hipMemcpyAsync(x, xx, n * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (iters) *iters = it;
-    if (relres) *relres = rel;
-    c->stats.pcg_iters = it;
-    c->stats.pcg_relres = rel;
-    c->stats.t_solve_ms = now_ms() - t0;
-    if (!conv) return code_for(c, MsddError{MSDD_ENOCONV, "PCG reached maxit"});
-    return MSDD_OK;
+    if (st == MSDD_ENOCONV) return code_for(c, MsddError{MSDD_ENOCONV, "PCG reached maxit"});
+    return st;
   } catch (const MsddError& e) {
     return code_for(c, e);
   }
@@ -1913,7 +2052,7 @@ int msdd_get_basis(const msdd_ctx* c, int32_t level, int32_t i, double* basis, i
 int msdd_profile(msdd_ctx* c, int enable) {
   if (!c) return MSDD_EINVAL;
   try {
-    c->prof.reset();
+    if (enable == 1) c->prof.reset();
     c->prof.on = enable != 0;
     return MSDD_OK;
   } catch (const MsddError& e) {

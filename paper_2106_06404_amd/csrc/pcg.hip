@@ -8,19 +8,26 @@
 #include "kernels.h"
 #include "trsv.h"
 
-enum { SC_RZ = 0, SC_PQ = 1, SC_RR = 2, SC_ALPHA = 3, SC_BETA = 4, SC_RR0 = 5, SC_TMP = 6 };
-
-// q = A p (CSR, SG lanes per row) and per-block partial sums of p.q
+// ---------------------------------------------------------------------------
+// PCG on several independent systems at once ("segments": contiguous row ranges,
+// one per problem; a single problem is one segment).  Vector kernels work on
+// "chunks" (row ranges inside one segment), one workgroup per chunk, and write one
+// partial sum per chunk; k_seg_reduce sums a segment's chunks in a fixed order and
+// applies the CG scalar rule of that segment.  Convergence is decided on the device:
+// a segment that converged (or hit maxit) gets alpha = beta = 0 and stays frozen, so
+// iterations can run in chunks without reading anything back.
+// ---------------------------------------------------------------------------
 template <int SG>
-__global__ void k_spmv_dot(i64 n, const i64* __restrict__ rowptr, const i32* __restrict__ col,
-                           const double* __restrict__ val, const double* __restrict__ p,
-                           double* __restrict__ q, double* __restrict__ partial, int want_dot) {
+__global__ void __launch_bounds__(256) k_spmv_chunk(
+    const i64* __restrict__ ch_lo, const i64* __restrict__ ch_hi, const i64* __restrict__ rowptr,
+    const i32* __restrict__ col, const double* __restrict__ val, const double* __restrict__ p,
+    double* __restrict__ q, double* __restrict__ partial) {
   __shared__ double sh[16];
+  const int c = blockIdx.x;
   const int lane = threadIdx.x % SG;
-  const i64 rows_per_grid = (i64)gridDim.x * (blockDim.x / SG);
+  const i64 hi = ch_hi[c];
   double dacc = 0.0;
-  for (i64 row = (i64)blockIdx.x * (blockDim.x / SG) + threadIdx.x / SG; row < n;
-       row += rows_per_grid) {
+  for (i64 row = ch_lo[c] + threadIdx.x / SG; row < hi; row += blockDim.x / SG) {
     double s = 0.0;
     for (i64 e = rowptr[row] + lane; e < rowptr[row + 1]; e += SG) s += val[e] * p[col[e]];
     for (int o = SG / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, SG);
@@ -29,80 +36,133 @@ __global__ void k_spmv_dot(i64 n, const i64* __restrict__ rowptr, const i32* __r
       dacc += s * p[row];
     }
   }
-  if (want_dot) {
-    const double t = block_sum(dacc, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = t;
-  }
+  const double t = block_sum(dacc, sh);
+  if (threadIdx.x == 0) partial[c] = t;
 }
 
-// sc[slot] = sum(partial); then an update rule on the scalars
-enum { RED_SET = 0, RED_ALPHA = 1, RED_BETA = 2 };
-__global__ void k_reduce(const double* __restrict__ partial, int np, double* __restrict__ sc,
-                         int slot, int rule) {
+// r = b - q; partial r.r
+__global__ void k_residual_chunk(const i64* __restrict__ ch_lo, const i64* __restrict__ ch_hi,
+                                 const double* __restrict__ b, const double* __restrict__ q,
+                                 double* __restrict__ r, double* __restrict__ partial) {
   __shared__ double sh[16];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) s += partial[i];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) {
-    if (rule == RED_SET) {
-      sc[slot] = s;
-    } else if (rule == RED_ALPHA) {  // s = p.q
-      sc[SC_PQ] = s;
-      sc[SC_ALPHA] = sc[SC_RZ] / s;
-    } else {  // s = r.z (new)
-      sc[SC_BETA] = s / sc[SC_RZ];
-      sc[SC_RZ] = s;
-    }
-  }
-}
-
-// x += alpha p; r -= alpha q; partial r.r
-__global__ void k_update_xr(i64 n, double* __restrict__ x, double* __restrict__ r,
-                            const double* __restrict__ p, const double* __restrict__ q,
-                            const double* __restrict__ sc, double* __restrict__ partial) {
-  __shared__ double sh[16];
-  const double a = sc[SC_ALPHA];
+  const int c = blockIdx.x;
   double acc = 0.0;
-  for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+  for (i64 i = ch_lo[c] + threadIdx.x; i < ch_hi[c]; i += blockDim.x) {
+    const double v = b[i] - q[i];
+    r[i] = v;
+    acc += v * v;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[c] = acc;
+}
+
+// x += alpha_s p; r -= alpha_s q; partial r.r
+__global__ void k_update_xr_chunk(const i64* __restrict__ ch_lo, const i64* __restrict__ ch_hi,
+                                  const i32* __restrict__ ch_seg, double* __restrict__ x,
+                                  double* __restrict__ r, const double* __restrict__ p,
+                                  const double* __restrict__ q, const double* __restrict__ D,
+                                  double* __restrict__ partial) {
+  __shared__ double sh[16];
+  const int c = blockIdx.x;
+  const double a = D[ch_seg[c] * PCG_SD + PCG_ALPHA];
+  double acc = 0.0;
+  for (i64 i = ch_lo[c] + threadIdx.x; i < ch_hi[c]; i += blockDim.x) {
     x[i] += a * p[i];
     const double ri = r[i] - a * q[i];
     r[i] = ri;
     acc += ri * ri;
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+  if (threadIdx.x == 0) partial[c] = acc;
 }
 
-__global__ void k_dot(i64 n, const double* __restrict__ a, const double* __restrict__ b,
-                      double* __restrict__ partial) {
+__global__ void k_dot_chunk(const i64* __restrict__ ch_lo, const i64* __restrict__ ch_hi,
+                            const double* __restrict__ a, const double* __restrict__ b,
+                            double* __restrict__ partial) {
   __shared__ double sh[16];
+  const int c = blockIdx.x;
   double acc = 0.0;
-  for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
-    acc += a[i] * b[i];
+  for (i64 i = ch_lo[c] + threadIdx.x; i < ch_hi[c]; i += blockDim.x) acc += a[i] * b[i];
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+  if (threadIdx.x == 0) partial[c] = acc;
 }
 
-// p = z + beta p   (beta_from_sc = 0: p = z)
-__global__ void k_update_p(i64 n, const double* __restrict__ z, double* __restrict__ p,
-                           const double* __restrict__ sc, int use_beta) {
-  const double be = use_beta ? sc[SC_BETA] : 0.0;
-  for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
-    p[i] = use_beta ? z[i] + be * p[i] : z[i];
+// p = z + beta_s p  (first: p = z)
+__global__ void k_update_p_chunk(const i64* __restrict__ ch_lo, const i64* __restrict__ ch_hi,
+                                 const i32* __restrict__ ch_seg, const double* __restrict__ z,
+                                 double* __restrict__ p, const double* __restrict__ D, int first) {
+  const int c = blockIdx.x;
+  const double be = first ? 0.0 : D[ch_seg[c] * PCG_SD + PCG_BETA];
+  for (i64 i = ch_lo[c] + threadIdx.x; i < ch_hi[c]; i += blockDim.x)
+    p[i] = first ? z[i] : z[i] + be * p[i];
 }
 
-// r = b - q ; partial r.r
-__global__ void k_residual(i64 n, const double* __restrict__ b, const double* __restrict__ q,
-                           double* __restrict__ r, double* __restrict__ partial) {
+// Per segment: sum its chunks' partial sums (fixed order) and apply the rule.
+// Segment state: D[s*PCG_SD + field], I[s*PCG_SI + field].
+__global__ void k_seg_reduce(const i64* __restrict__ seg_ch, const double* __restrict__ partial,
+                             double* __restrict__ D, int* __restrict__ I, int rule, double rtol,
+                             int maxit, double* __restrict__ hist, int nseg) {
   __shared__ double sh[16];
+  const int sg = blockIdx.x;
   double acc = 0.0;
-  for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
-    const double v = b[i] - q[i];
-    r[i] = v;
-    acc += v * v;
+  for (i64 c = seg_ch[sg] + threadIdx.x; c < seg_ch[sg + 1]; c += blockDim.x) acc += partial[c];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x != 0) return;
+  double* d = D + sg * PCG_SD;
+  int* st = I + sg * PCG_SI;
+  const bool run = st[PCG_ACTIVE] == PCG_RUNNING;
+  switch (rule) {
+    case PCG_R_RR0:
+      d[PCG_RR0] = acc;
+      d[PCG_RR] = acc;
+      d[PCG_TOL2] = rtol * rtol * acc;
+      st[PCG_IT] = 0;
+      st[PCG_ITERS] = 0;
+      hist[sg] = acc > 0.0 ? 1.0 : 0.0;
+      st[PCG_ACTIVE] = !isfinite(acc) ? PCG_BREAKDOWN : (acc > 0.0 ? PCG_RUNNING : PCG_CONVERGED);
+      break;
+    case PCG_R_RZ0:
+      d[PCG_RZ] = acc;
+      break;
+    case PCG_R_PQ:
+      d[PCG_PQ] = acc;
+      d[PCG_ALPHA] = 0.0;
+      if (run) {
+        const double a = d[PCG_RZ] / acc;
+        if (!isfinite(a)) {
+          st[PCG_ACTIVE] = PCG_BREAKDOWN;
+          st[PCG_ITERS] = st[PCG_IT];
+        } else {
+          st[PCG_IT] += 1;
+          d[PCG_ALPHA] = a;
+        }
+      }
+      break;
+    case PCG_R_RR:
+      if (run) {
+        d[PCG_RR] = acc;
+        const int it = st[PCG_IT];
+        if (it <= maxit) hist[(i64)it * nseg + sg] = sqrt(acc / d[PCG_RR0]);
+        if (!isfinite(acc)) {
+          st[PCG_ACTIVE] = PCG_BREAKDOWN;
+          st[PCG_ITERS] = it;
+        } else if (acc < d[PCG_TOL2]) {
+          st[PCG_ACTIVE] = PCG_CONVERGED;
+          st[PCG_ITERS] = it;
+        } else if (it >= maxit) {
+          st[PCG_ACTIVE] = PCG_MAXIT;
+          st[PCG_ITERS] = it;
+        }
+      }
+      break;
+    case PCG_R_RZ:
+      d[PCG_BETA] = 0.0;
+      if (run) {
+        d[PCG_BETA] = acc / d[PCG_RZ];
+        d[PCG_RZ] = acc;
+      }
+      break;
   }
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -304,37 +364,43 @@ static inline unsigned grid_for(i64 n) {
   if (g < 1) g = 1;
   return (unsigned)g;
 }
-int pcg_grid(i64 n) { return (int)grid_for(n); }
 
-void launch_spmv_dot(hipStream_t s, i64 n, int sg, const i64* rowptr, const i32* col,
-                     const double* val, const double* p, double* q, double* partial, int want_dot) {
-  const unsigned g = grid_for(n);
+void launch_spmv_chunk(hipStream_t s, int nch, int sg, const i64* ch_lo, const i64* ch_hi,
+                       const i64* rowptr, const i32* col, const double* val, const double* p,
+                       double* q, double* partial) {
   if (sg <= 4)
-    hipLaunchKernelGGL(k_spmv_dot<4>, dim3(g), dim3(MSDD_WG), 0, s, n, rowptr, col, val, p, q, partial, want_dot);
+    hipLaunchKernelGGL(k_spmv_chunk<4>, dim3(nch), dim3(256), 0, s, ch_lo, ch_hi, rowptr, col, val, p, q, partial);
   else if (sg <= 8)
-    hipLaunchKernelGGL(k_spmv_dot<8>, dim3(g), dim3(MSDD_WG), 0, s, n, rowptr, col, val, p, q, partial, want_dot);
+    hipLaunchKernelGGL(k_spmv_chunk<8>, dim3(nch), dim3(256), 0, s, ch_lo, ch_hi, rowptr, col, val, p, q, partial);
   else if (sg <= 16)
-    hipLaunchKernelGGL(k_spmv_dot<16>, dim3(g), dim3(MSDD_WG), 0, s, n, rowptr, col, val, p, q, partial, want_dot);
+    hipLaunchKernelGGL(k_spmv_chunk<16>, dim3(nch), dim3(256), 0, s, ch_lo, ch_hi, rowptr, col, val, p, q, partial);
   else
-    hipLaunchKernelGGL(k_spmv_dot<32>, dim3(g), dim3(MSDD_WG), 0, s, n, rowptr, col, val, p, q, partial, want_dot);
+    hipLaunchKernelGGL(k_spmv_chunk<32>, dim3(nch), dim3(256), 0, s, ch_lo, ch_hi, rowptr, col, val, p, q, partial);
 }
-void launch_reduce(hipStream_t s, const double* partial, int np, double* sc, int slot, int rule) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(MSDD_WG), 0, s, partial, np, sc, slot, rule);
+void launch_residual_chunk(hipStream_t s, int nch, const i64* ch_lo, const i64* ch_hi,
+                           const double* b, const double* q, double* r, double* partial) {
+  hipLaunchKernelGGL(k_residual_chunk, dim3(nch), dim3(256), 0, s, ch_lo, ch_hi, b, q, r, partial);
 }
-void launch_update_xr(hipStream_t s, i64 n, double* x, double* r, const double* p,
-                      const double* q, const double* sc, double* partial) {
-  hipLaunchKernelGGL(k_update_xr, dim3(grid_for(n)), dim3(MSDD_WG), 0, s, n, x, r, p, q, sc, partial);
+void launch_update_xr_chunk(hipStream_t s, int nch, const i64* ch_lo, const i64* ch_hi,
+                            const i32* ch_seg, double* x, double* r, const double* p,
+                            const double* q, const double* D, double* partial) {
+  hipLaunchKernelGGL(k_update_xr_chunk, dim3(nch), dim3(256), 0, s, ch_lo, ch_hi, ch_seg, x, r, p,
+                     q, D, partial);
 }
-void launch_dot(hipStream_t s, i64 n, const double* a, const double* b, double* partial) {
-  hipLaunchKernelGGL(k_dot, dim3(grid_for(n)), dim3(MSDD_WG), 0, s, n, a, b, partial);
+void launch_dot_chunk(hipStream_t s, int nch, const i64* ch_lo, const i64* ch_hi, const double* a,
+                      const double* b, double* partial) {
+  hipLaunchKernelGGL(k_dot_chunk, dim3(nch), dim3(256), 0, s, ch_lo, ch_hi, a, b, partial);
 }
-void launch_update_p(hipStream_t s, i64 n, const double* z, double* p, const double* sc,
-                     int use_beta) {
-  hipLaunchKernelGGL(k_update_p, dim3(grid_for(n)), dim3(MSDD_WG), 0, s, n, z, p, sc, use_beta);
+void launch_update_p_chunk(hipStream_t s, int nch, const i64* ch_lo, const i64* ch_hi,
+                           const i32* ch_seg, const double* z, double* p, const double* D,
+                           int first) {
+  hipLaunchKernelGGL(k_update_p_chunk, dim3(nch), dim3(256), 0, s, ch_lo, ch_hi, ch_seg, z, p, D,
+                     first);
 }
-void launch_residual(hipStream_t s, i64 n, const double* b, const double* q, double* r,
-                     double* partial) {
-  hipLaunchKernelGGL(k_residual, dim3(grid_for(n)), dim3(MSDD_WG), 0, s, n, b, q, r, partial);
+void launch_seg_reduce(hipStream_t s, int nseg, const i64* seg_ch, const double* partial,
+                       double* D, int* I, int rule, double rtol, int maxit, double* hist) {
+  hipLaunchKernelGGL(k_seg_reduce, dim3(nseg), dim3(256), 0, s, seg_ch, partial, D, I, rule, rtol,
+                     maxit, hist, nseg);
 }
 void launch_apply_fine_restrict(hipStream_t s, int P, int nd_max, const i32* nd, const i64* doff,
                                 const i32* dglob, const i32* msub, const i64* moff,
