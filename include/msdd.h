@@ -138,6 +138,27 @@ int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
                const double* sub_pou, int32_t n_levels, const int32_t* parent, double eta);
 
 /*
+ * Build the preconditioners of nprob independent problems in one setup (one set of
+ * batched launches for all their subdomains and levels).  The arguments describe the
+ * union of the problems exactly as for msdd_setup, with:
+ *  prob_dof_ptr[nprob+1] (int64): problem t owns the dofs [prob_dof_ptr[t],
+ *      prob_dof_ptr[t+1]); prob_dof_ptr[0] = 0, prob_dof_ptr[nprob] = n;
+ *  A block diagonal over the problems; every subdomain (on every level) inside one
+ *      problem; subdomains ordered by problem on every level (the parent maps number
+ *      the coarse subdomains of problem 0 first, and so on);
+ *  level 0 is one subdomain per problem (a dense block of A_0 per problem).
+ * All problems share n_levels and eta.  Solve with msdd_solve_batch (one CG per
+ * problem).  Errors as msdd_setup; MSDD_EINVAL names a violated batch rule.
+ */
+int msdd_setup_batch(msdd_ctx* c, int32_t nprob, const int64_t* prob_dof_ptr, int64_t n,
+                     const int64_t* rowptr, const int32_t* col, const double* val,
+                     int32_t n_elem, int32_t k, const int32_t* elem_dofs,
+                     const double* elem_mat, int32_t n_sub, const int64_t* sub_elem_ptr,
+                     const int32_t* sub_elem, const int64_t* sub_dof_ptr,
+                     const int32_t* sub_dof, const double* sub_pou, int32_t n_levels,
+                     const int32_t* parent, double eta);
+
+/*
  * Solve A x = b by preconditioned CG (Sec. 5) from the initial guess in x.
  * b[n], x[n]: double, host or device.  Stops when the recurrence residual
  * satisfies ||r_m||_2 < rtol ||r_0||_2 or after maxit iterations.

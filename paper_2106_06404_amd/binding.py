@@ -57,7 +57,7 @@ class MsddStats(ctypes.Structure):
         return d
 
 
-EXPORTS = ["msdd_default_options", "msdd_create", "msdd_setup", "msdd_solve",
+EXPORTS = ["msdd_default_options", "msdd_create", "msdd_setup", "msdd_setup_batch", "msdd_solve",
            "msdd_solve_batch", "msdd_solve_history", "msdd_apply",
            "msdd_stats", "msdd_get_level_counts", "msdd_get_eigs", "msdd_get_basis",
            "msdd_profile", "msdd_profile_query", "msdd_profile_name", "msdd_last_error",
@@ -90,6 +90,9 @@ def load():
     L.msdd_setup.argtypes = [vp, i64, vp, vp, vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, i32,
                              vp, f64]
     L.msdd_setup.restype = ctypes.c_int
+    L.msdd_setup_batch.argtypes = [vp, i32, vp, i64, vp, vp, vp, i32, i32, vp, vp, i32, vp, vp, vp,
+                                   vp, vp, i32, vp, f64]
+    L.msdd_setup_batch.restype = ctypes.c_int
     L.msdd_solve.argtypes = [vp, vp, vp, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]
     L.msdd_solve.restype = ctypes.c_int
     L.msdd_solve_batch.argtypes = [vp, vp, vp, f64, i32, vp, vp]
@@ -176,6 +179,32 @@ class Msdd:
                                 float(eta))
         return self._check(rc)
 
+    def setup_batch(self, prob_dof_ptr, n, rowptr, col, val, elem_dofs, elem_mat, sub_elem_ptr,
+                    sub_elem, sub_dof_ptr, sub_dof, sub_pou, n_levels, parent, eta):
+        n_elem, k = int(elem_dofs.shape[0]), int(elem_dofs.shape[1])
+        n_sub = int(sub_elem_ptr.shape[0]) - 1
+        nprob = int(prob_dof_ptr.shape[0]) - 1
+        self._nprob = nprob
+        rc = self._L.msdd_setup_batch(
+            self._h, nprob, _ptr(prob_dof_ptr, np.int64), int(n), _ptr(rowptr, np.int64),
+            _ptr(col, np.int32), _ptr(val, np.float64), n_elem, k, _ptr(elem_dofs, np.int32),
+            _ptr(elem_mat, np.float64), n_sub, _ptr(sub_elem_ptr, np.int64),
+            _ptr(sub_elem, np.int32), _ptr(sub_dof_ptr, np.int64), _ptr(sub_dof, np.int32),
+            _ptr(sub_pou, np.float64), int(n_levels),
+            _ptr(parent, np.int32) if parent is not None else None, float(eta))
+        return self._check(rc)
+
+    def solve_batch(self, b, x, rtol=1e-8, maxit=1000, allow_noconv=False):
+        """One CG per problem of a batch: (iters[nprob], relres[nprob], status)."""
+        nprob = getattr(self, "_nprob", 1)
+        it = np.zeros(nprob, np.int32)
+        rel = np.zeros(nprob, np.float64)
+        rc = self._L.msdd_solve_batch(self._h, _ptr(b, np.float64), _ptr(x, np.float64),
+                                      float(rtol), int(maxit), ctypes.c_void_p(it.ctypes.data),
+                                      ctypes.c_void_p(rel.ctypes.data))
+        self._check(rc, allow=(MSDD_ENOCONV,) if allow_noconv else ())
+        return it, rel, rc
+
     def solve(self, b, x, rtol=1e-8, maxit=1000, allow_noconv=False):
         it = ctypes.c_int32()
         rel = ctypes.c_double()
@@ -247,6 +276,49 @@ class Msdd:
             self.close()
         except Exception:
             pass
+
+
+def batch_arrays(probs, device=None):
+    """Arrays of the union of several problems for Msdd.setup_batch (indices offset per
+    problem; problems must share n_levels, eta and the element size)."""
+    parts = [problem_arrays(p) for p in probs]
+    assert len({a["n_levels"] for a in parts}) == 1 and len({a["eta"] for a in parts}) == 1
+    nb = np.cumsum([0] + [a["n"] for a in parts])
+    eb = np.cumsum([0] + [a["elem_dofs"].shape[0] for a in parts])
+    nnzb = np.cumsum([0] + [a["col"].shape[0] for a in parts])
+    sb_e = np.cumsum([0] + [a["sub_elem"].shape[0] for a in parts])
+    sb_d = np.cumsum([0] + [a["sub_dof"].shape[0] for a in parts])
+    out = dict(n=int(nb[-1]), n_levels=parts[0]["n_levels"], eta=parts[0]["eta"],
+               prob_dof_ptr=nb.astype(np.int64))
+    out["rowptr"] = np.concatenate([parts[0]["rowptr"][:1]] +
+                                   [a["rowptr"][1:] + nnzb[t] for t, a in enumerate(parts)]).astype(np.int64)
+    out["col"] = np.concatenate([a["col"] + nb[t] for t, a in enumerate(parts)]).astype(np.int32)
+    out["val"] = np.concatenate([a["val"] for a in parts])
+    out["elem_dofs"] = np.concatenate([np.where(a["elem_dofs"] >= 0, a["elem_dofs"] + nb[t], -1)
+                                       for t, a in enumerate(parts)]).astype(np.int32)
+    out["elem_mat"] = np.concatenate([a["elem_mat"] for a in parts])
+    out["sub_elem_ptr"] = np.concatenate([[0]] + [a["sub_elem_ptr"][1:] + sb_e[t]
+                                                  for t, a in enumerate(parts)]).astype(np.int64)
+    out["sub_elem"] = np.concatenate([a["sub_elem"] + eb[t] for t, a in enumerate(parts)]).astype(np.int32)
+    out["sub_dof_ptr"] = np.concatenate([[0]] + [a["sub_dof_ptr"][1:] + sb_d[t]
+                                                 for t, a in enumerate(parts)]).astype(np.int64)
+    out["sub_dof"] = np.concatenate([a["sub_dof"] + nb[t] for t, a in enumerate(parts)]).astype(np.int32)
+    out["sub_pou"] = np.concatenate([a["sub_pou"] for a in parts])
+    if parts[0]["parent"] is None:
+        out["parent"] = None
+    else:
+        maps = []
+        for lvl in range(len(probs[0].parents)):
+            base = 0
+            for p in probs:
+                maps.append(np.asarray(p.parents[lvl], np.int64) + base)
+                base += int(np.max(p.parents[lvl])) + 1
+        out["parent"] = np.concatenate(maps).astype(np.int32)
+    if device is None:
+        return out
+    import torch
+    return {k: (torch.from_numpy(v).to(device) if isinstance(v, np.ndarray) else v)
+            for k, v in out.items()}
 
 
 def problem_arrays(prob, device=None):

@@ -244,10 +244,14 @@ __device__ bool dense_cholesky_block(int n, double* A, int lda, int* fail_sh) {
   return true;
 }
 
-__global__ void k_dense_cholesky(int n, double* A, int* status) {
+// One dense SPD block per workgroup (the coarsest level: one block per problem).
+__global__ void k_dense_cholesky(const i64* __restrict__ off, const i32* __restrict__ n_arr,
+                                 double* __restrict__ A, int* __restrict__ status) {
   __shared__ int f;
-  bool ok = dense_cholesky_block(n, A, n, &f);
-  if (threadIdx.x == 0) status[0] = ok ? ST_DONE : ST_NOTSPD;
+  const int t = blockIdx.x;
+  const int n = n_arr[t];
+  bool ok = n == 0 || dense_cholesky_block(n, A + off[t], n, &f);
+  if (threadIdx.x == 0) status[t] = ok ? ST_DONE : ST_NOTSPD;
 }
 
 // Coarse GEVP of one level-(l-1) subdomain per workgroup, on its generating system
@@ -546,8 +550,10 @@ void launch_coarse_assemble(hipStream_t s, int nt, const i64* tp_ptr, const i32*
   hipLaunchKernelGGL(k_coarse_assemble, dim3(nt), dim3(MSDD_WG), 0, s, tp_ptr, tp_patch,
                      tp_map_off, tp_map, pM, pmoff, Pm, ng_arr, aoff, Aout);
 }
-void launch_dense_cholesky(hipStream_t s, int n, double* A, int* status) {
-  hipLaunchKernelGGL(k_dense_cholesky, dim3(1), dim3(1024), 0, s, n, A, status);
+void launch_dense_cholesky(hipStream_t s, int nt, const i64* off, const i32* n_arr, double* A,
+                           int* status) {
+  if (nt == 0) return;
+  hipLaunchKernelGGL(k_dense_cholesky, dim3(nt), dim3(1024), 0, s, off, n_arr, A, status);
 }
 void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_arr,
                         const i64* aoff, double* Abar, const i64* loff, double* Lo,

@@ -31,7 +31,8 @@ template <typename V>
 __global__ void k_eig_init(i64 total_rows, const i32* __restrict__ row_sub,
                            const i64* __restrict__ voff, const i32* __restrict__ nb,
                            const i64* __restrict__ kvoff, int K, const double* __restrict__ dv,
-                           V* __restrict__ X, unsigned long long seed) {
+                           V* __restrict__ X, unsigned long long seed,
+                           const i32* __restrict__ seed_id) {
   i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total_rows) return;
   const int i = row_sub[g];
@@ -39,8 +40,11 @@ __global__ void k_eig_init(i64 total_rows, const i32* __restrict__ row_sub,
   const int n = nb[i];
   V* Xi = X + kvoff[i];
   const bool z = dv[g] == 0.0;
+  // the start block depends on the subdomain's index within its problem, so a problem
+  // gets the same start whether it is set up alone or in a batch
+  const unsigned long long sid = (unsigned long long)seed_id[i];
   for (int c = 0; c < K; ++c) {
-    unsigned long long key = seed ^ ((unsigned long long)i << 40) ^ ((unsigned long long)r << 12) ^
+    unsigned long long key = seed ^ (sid << 40) ^ ((unsigned long long)r << 12) ^
                              (unsigned long long)c;
     Xi[r + (i64)c * n] = z ? (V)0 : (V)hash_uniform(key);
   }
@@ -450,11 +454,11 @@ __global__ void k_eig_finalize(const i32* __restrict__ nb, const i64* __restrict
 // ---------------------------------------------------------------------------
 void launch_eig_init(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
                      const i32* nb, const i64* kvoff, int K, const double* dv, double* X,
-                     unsigned long long seed) {
+                     unsigned long long seed, const i32* seed_id) {
   if (!total_rows) return;
   dim3 g((unsigned)((total_rows + MSDD_WG - 1) / MSDD_WG));
   hipLaunchKernelGGL(k_eig_init<double>, g, dim3(MSDD_WG), 0, s, total_rows, row_sub, voff, nb,
-                     kvoff, K, dv, X, seed);
+                     kvoff, K, dv, X, seed, seed_id);
 }
 
 void launch_bapply_ell(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,

@@ -41,7 +41,7 @@ void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax
 // eig.hip
 void launch_eig_init(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
                      const i32* nb, const i64* kvoff, int K, const double* dv, double* X,
-                     unsigned long long seed);
+                     unsigned long long seed, const i32* seed_id);
 void launch_bapply_ell(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
                        const i32* nb, const i64* kvoff, int K, const double* dv, int ell_w,
                        const i32* ell_col, const double* ell_val, const double* Y, double* Z,
@@ -86,7 +86,8 @@ void launch_coarse_assemble(hipStream_t s, int nt, const i64* tp_ptr, const i32*
                             const i64* tp_map_off, const i32* tp_map, const i32* pM,
                             const i64* pmoff, const double* Pm, const i32* ng_arr,
                             const i64* aoff, double* Aout);
-void launch_dense_cholesky(hipStream_t s, int n, double* A, int* status);
+void launch_dense_cholesky(hipStream_t s, int nt, const i64* off, const i32* n_arr, double* A,
+                           int* status);
 void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_arr,
                         const i64* aoff, double* Abar, const i64* loff, double* Lo,
                         const i64* soff, double* scratch, double eta, int nev_max,
@@ -136,7 +137,8 @@ void launch_apply_coarse_down(hipStream_t s, int P, int no_max, const i32* nown,
                               const double* Inv, const i32* msub, const i64* yoff,
                               const double* Y, const i64* moff, const double* rl, double* zl,
                               double* rc);
-void launch_apply_coarsest(hipStream_t s, int n0, const double* Inv, const double* r0, double* z0);
+void launch_apply_coarsest(hipStream_t s, int nt, int nmax, const i64* zoff, const i64* aoff,
+                           const i32* n_arr, const double* Inv, const double* r0, double* z0);
 void launch_apply_coarse_up(hipStream_t s, int P, const i32* nown, const i64* own_ptr,
                             const i32* own_idx, const i32* msub, const i64* yoff, const double* Y,
                             const i64* moff, const double* zc, double* zl);

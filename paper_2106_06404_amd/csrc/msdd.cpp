@@ -319,6 +319,7 @@ struct FineLevel {
   DVec<int64_t> doff, dboff;
   DVec<double> Dband, LDc, LDr;
   DVec<float> LDc32, LDr32;  // single-precision mode: factor of diag(sc) A_i diag(sc)
+  DVec<int32_t> seed_id;     // index of the subdomain within its problem (start blocks)
   DVec<double> dscale;       // sc per Dirichlet dof (single-precision mode)
   int nd_max = 0, bd_max = 0, bw_max = 0, nb_max = 0;
   // sums used for the algorithmic byte / flop counts of the profiler
@@ -454,7 +455,11 @@ struct msdd_ctx {
   std::vector<CoarseLevel> C;  // C[0] = level L-1, ..., C[L-2] = level 1
   std::vector<int64_t> nlev;   // n_l for l = 0..L
   int n0 = 0;
-  DVec<double> A0, A0inv;
+  DVec<double> A0, A0inv;       // level 0: dense blocks, one per problem
+  int n0_blocks = 1, n0_max = 0;
+  std::vector<int64_t> h_a0off;
+  DVec<int64_t> a0off, z0off;
+  DVec<int32_t> n0blk;
   // solve work
   std::vector<DVec<double>> rlev, zlev;  // index l = 0..L-1
   DVec<double> u, r, z, p, q, x, bvec, partial;
@@ -877,7 +882,7 @@ void fine_eigensolve(msdd_ctx* c) {
     iters.alloc(P);
     iters.zero(s);
     launch_eig_init(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K, F.dv.p,
-                    E.X.p, 0x5eed5eedull + (unsigned long long)K);
+                    E.X.p, 0x5eed5eedull + (unsigned long long)K, F.seed_id.p);
     launch_bapply_ell(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K,
                       F.dv.p, F.ell_w, F.ell_col.p, F.ell_val.p, E.X.p, BX.p, status.p);
     const int maxit = o.eig_maxit;
@@ -1419,48 +1424,84 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
   vlog(c, "coarse: patch projection kernel", &tv);
 }
 
-void coarsest(msdd_ctx* c, const PatchLevel& PL, const std::vector<int32_t>& m_lvl1) {
+// Level 0: one dense block per problem (a single problem: A_0 itself), assembled from
+// the patches of level 1 (Sec. 4.1), factorised and inverted.  prob[i] = problem of
+// level-1 subdomain i (nondecreasing).
+void coarsest(msdd_ctx* c, const PatchLevel& PL, const std::vector<int32_t>& m_lvl1,
+              const std::vector<int32_t>& prob, int nprob) {
   hipStream_t s = c->stream;
   const int P1 = (int)m_lvl1.size();
   std::vector<int64_t> moff(P1 + 1, 0);
   for (int i = 0; i < P1; ++i) moff[i + 1] = moff[i] + m_lvl1[i];
-  const int n0 = (int)moff.back();
-  c->n0 = n0;
-  AssembleJob J;
-  J.ng = {n0};
-  J.aoff = {0, (int64_t)n0 * n0};
-  J.tp_ptr = {0, (int64_t)PL.np};
-  for (int p = 0; p < PL.np; ++p) {
-    J.tp_patch.push_back(p);
-    J.tp_map_off.push_back((int64_t)J.tp_map.size());
-    for (int32_t i : PL.members[p])
-      for (int q = 0; q < m_lvl1[i]; ++q) J.tp_map.push_back((int32_t)(moff[i] + q));
+  c->n0 = (int)moff.back();
+  // per problem: level-0 range [zoff, zoff + n0_t)
+  std::vector<int64_t> zoff(nprob + 1, 0);
+  {
+    std::vector<int64_t> cnt(nprob, 0);
+    for (int i = 0; i < P1; ++i) cnt[prob[i]] += m_lvl1[i];
+    for (int t = 0; t < nprob; ++t) zoff[t + 1] = zoff[t] + cnt[t];
   }
-  if (n0 == 0) {
+  AssembleJob J;
+  J.ng.resize(nprob);
+  J.aoff.assign(nprob + 1, 0);
+  int nmax = 0;
+  for (int t = 0; t < nprob; ++t) {
+    J.ng[t] = (int32_t)(zoff[t + 1] - zoff[t]);
+    REQUIRE(J.ng[t] <= 8192, "coarsest space of a problem larger than 8192 (add a level)");
+    J.aoff[t + 1] = J.aoff[t] + (int64_t)J.ng[t] * J.ng[t];
+    nmax = std::max(nmax, J.ng[t]);
+  }
+  std::vector<std::vector<int>> tpatch(nprob);
+  for (int p = 0; p < PL.np; ++p) {
+    const int t = prob[PL.members[p][0]];
+    for (int32_t i : PL.members[p]) REQUIRE(prob[i] == t, "a patch spans two problems");
+    tpatch[t].push_back(p);
+  }
+  J.tp_ptr.assign(nprob + 1, 0);
+  for (int t = 0; t < nprob; ++t) {
+    for (int p : tpatch[t]) {
+      J.tp_patch.push_back(p);
+      J.tp_map_off.push_back((int64_t)J.tp_map.size());
+      for (int32_t i : PL.members[p])
+        for (int q = 0; q < m_lvl1[i]; ++q) J.tp_map.push_back((int32_t)(moff[i] + q - zoff[t]));
+    }
+    J.tp_ptr[t + 1] = (int64_t)J.tp_patch.size();
+  }
+  c->n0_blocks = nprob;
+  c->n0_max = nmax;
+  c->h_a0off = J.aoff;
+  c->a0off.upload(J.aoff, s);
+  c->z0off.upload(zoff, s);
+  c->n0blk.upload(J.ng, s);
+  if (c->n0 == 0) {
     c->A0.alloc(1);
+    c->A0inv.alloc(1);
     return;
   }
-  REQUIRE(n0 <= 8192, "coarsest space larger than 8192 (add a level)");
   run_assemble(c, J, PL, c->A0);
   DVec<int> st;
-  st.alloc(1);
+  st.alloc(nprob);
+  double fl = 0.0, by = 0.0;
+  for (int t = 0; t < nprob; ++t) {
+    fl += (double)J.ng[t] * J.ng[t] * J.ng[t] / 3.0;
+    by += 2.0 * J.ng[t] * (double)J.ng[t] * 8.0;
+  }
   {
-    ProfScope ps(c, PR_COARSE, 2.0 * n0 * (double)n0 * 8.0, (double)n0 * n0 * n0 / 3.0);
-    launch_dense_cholesky(s, n0, c->A0.p, st.p);
+    ProfScope ps(c, PR_COARSE, by, fl);
+    launch_dense_cholesky(s, nprob, c->a0off.p, c->n0blk.p, c->A0.p, st.p);
   }
   HIPCHK(hipGetLastError());
   std::vector<int> v = st.download(s);
-  if (v[0] != ST_DONE) throw MsddError{MSDD_ENOTSPD, "coarsest matrix A_0 is not positive definite"};
-  DVec<int64_t> off0;
-  DVec<int32_t> nn0;
-  off0.upload(std::vector<int64_t>{0}, s);
-  nn0.upload(std::vector<int32_t>{n0}, s);
+  for (int t = 0; t < nprob; ++t)
+    if (v[t] != ST_DONE)
+      throw MsddError{MSDD_ENOTSPD, "coarsest matrix A_0 of problem " + std::to_string(t) +
+                                        " is not positive definite"};
   {
     DVec<double> Linv;
-    Linv.alloc((size_t)n0 * n0);
-    c->A0inv.alloc((size_t)n0 * n0);
-    ProfScope ps(c, PR_COARSE, 3.0 * n0 * (double)n0 * 8.0, 2.0 * (double)n0 * n0 * n0 / 3.0);
-    launch_spd_inverse(s, 1, n0, off0.p, nn0.p, c->A0.p, Linv.p, c->A0inv.p);
+    Linv.alloc((size_t)J.aoff.back());
+    c->A0inv.alloc((size_t)J.aoff.back());
+    ProfScope ps(c, PR_COARSE, 1.5 * by, 2.0 * fl);
+    launch_spd_inverse(s, nprob, nmax, c->a0off.p, c->n0blk.p, c->A0.p, Linv.p, c->A0inv.p);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -1549,7 +1590,8 @@ void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
                                CL.loff.p, CL.Inv.p, CL.dm.p, CL.yoff.p, CL.Y.p, CL.moff.p,
                                c->rlev[l].p, c->zlev[l].p, c->rlev[l - 1].p);
     }
-    launch_apply_coarsest(s, c->n0, c->A0inv.p, c->rlev[0].p, c->zlev[0].p);
+    launch_apply_coarsest(s, c->n0_blocks, c->n0_max, c->z0off.p, c->a0off.p, c->n0blk.p,
+                          c->A0inv.p, c->rlev[0].p, c->zlev[0].p);
     for (int t = (int)c->C.size() - 1; t >= 0; --t) {
       CoarseLevel& CL = c->C[t];
       const int l = CL.level;
@@ -1617,15 +1659,18 @@ int msdd_create(msdd_ctx** out, const msdd_options* opt) {
   return MSDD_OK;
 }
 
-int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col,
+namespace {
+int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col,
                const double* val, int32_t n_elem, int32_t k, const int32_t* elem_dofs,
                const double* elem_mat, int32_t n_sub, const int64_t* sub_elem_ptr,
                const int32_t* sub_elem, const int64_t* sub_dof_ptr, const int32_t* sub_dof,
-               const double* sub_pou, int32_t n_levels, const int32_t* parent, double eta) {
+               const double* sub_pou, int32_t n_levels, const int32_t* parent, double eta,
+               int32_t nprob, const int64_t* prob_dof_ptr) {
   if (!c) return MSDD_EINVAL;
   c->ready = false;
   c->err.clear();
   try {
+    REQUIRE(nprob >= 1, "nprob must be positive");
     HIPCHK(hipSetDevice(c->opt.device));
     const double t0 = now_ms();
     REQUIRE(n > 0 && n < (int64_t)1 << 31, "n out of range");
@@ -1670,6 +1715,52 @@ int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
         cnt = mx + 1;
       }
     }
+    // problems of a batch: dof ranges; every subdomain lies in one problem, subdomains
+    // are ordered by problem on every level, and A does not couple problems
+    std::vector<int64_t> pdp = prob_dof_ptr ? to_host(prob_dof_ptr, (size_t)nprob + 1)
+                                            : std::vector<int64_t>{0, n};
+    REQUIRE(pdp[0] == 0 && pdp[nprob] == n, "problem dof pointers must run from 0 to n");
+    for (int t = 0; t < nprob; ++t) REQUIRE(pdp[t + 1] > pdp[t], "empty problem in the batch");
+    std::vector<int32_t> prob_cur(n_sub, 0);
+    if (nprob > 1) {
+      for (int i = 0; i < n_sub; ++i) {
+        REQUIRE(sdp[i + 1] > sdp[i], "subdomain without dofs in a batch");
+        const int32_t d0 = sd[sdp[i]];
+        REQUIRE(d0 >= 0 && d0 < n, "sub_dof entry out of range");
+        const int t = (int)(std::upper_bound(pdp.begin(), pdp.end(), (int64_t)d0) - pdp.begin()) - 1;
+        for (int64_t q = sdp[i]; q < sdp[i + 1]; ++q)
+          REQUIRE(sd[q] >= pdp[t] && sd[q] < pdp[t + 1],
+                  "subdomain " + std::to_string(i) + " spans two problems");
+        prob_cur[i] = t;
+        REQUIRE(i == 0 || t >= prob_cur[i - 1], "subdomains must be ordered by problem");
+      }
+      std::vector<char> has(nprob, 0);
+      for (int32_t t : prob_cur) has[t] = 1;
+      for (int t = 0; t < nprob; ++t) REQUIRE(has[t], "problem " + std::to_string(t) + " has no subdomain");
+      std::vector<int32_t> hcol = to_host(col, (size_t)c->nnz);
+      for (int t = 0; t < nprob; ++t)
+        for (int64_t r = pdp[t]; r < pdp[t + 1]; ++r)
+          for (int64_t e = h_rowptr[r]; e < h_rowptr[r + 1]; ++e)
+            REQUIRE(hcol[e] >= pdp[t] && hcol[e] < pdp[t + 1], "the matrix couples two problems");
+    }
+    std::vector<std::vector<int32_t>> prob_lvl(1, prob_cur);  // [0] = finest, then coarser
+    for (const auto& pm : parents) {
+      const auto& pf = prob_lvl.back();
+      int cnt = 0;
+      for (int32_t v : pm) cnt = std::max(cnt, v + 1);
+      std::vector<int32_t> pc(cnt, -1);
+      for (size_t j = 0; j < pm.size(); ++j) {
+        REQUIRE(pc[pm[j]] < 0 || pc[pm[j]] == pf[j], "a coarse subdomain spans two problems");
+        pc[pm[j]] = pf[j];
+      }
+      for (int i = 0; i < cnt; ++i) {
+        REQUIRE(pc[i] >= 0, "coarse subdomain " + std::to_string(i) + " has no children");
+        REQUIRE(i == 0 || pc[i] >= pc[i - 1], "coarse subdomains must be ordered by problem");
+      }
+      prob_lvl.push_back(pc);
+    }
+    c->nseg = nprob;
+    c->h_seg_row = pdp;
     // device copies kept by the context
     to_device(c->rowptr, rowptr, (size_t)n + 1, s);
     to_device(c->col, col, (size_t)c->nnz, s);
@@ -1687,6 +1778,14 @@ int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     c->F = FineLevel();
     c->F.P = n_sub;
     plan_fine(c, n_elem, ed, sep, se, sdp, sd, sw);
+    {
+      std::vector<int32_t> sid(n_sub);
+      for (int i = 0, first = 0; i < n_sub; ++i) {
+        if (i > 0 && prob_cur[i] != prob_cur[i - 1]) first = i;
+        sid[i] = i - first;
+      }
+      c->F.seed_id.upload(sid, s);
+    }
     HIPCHK(hipStreamSynchronize(s));
     const double t1 = now_ms();
     fine_local_matrices(c, d_emat);
@@ -1711,7 +1810,7 @@ int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
       m_cur = c->C[t].m;
       moff_cur = c->C[t].h_moff;
     }
-    coarsest(c, PL, m_cur);
+    coarsest(c, PL, m_cur, prob_lvl.back(), nprob);
     HIPCHK(hipStreamSynchronize(s));
     const double t4 = now_ms();
     // level sizes
@@ -1719,10 +1818,6 @@ int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     c->nlev[L] = n;
     c->nlev[L - 1] = c->F.h_moff.back();
     for (int t = 0; t < L - 1; ++t) c->nlev[L - 2 - t] = c->C[t].h_moff.back();
-    if ((int)c->h_seg_row.size() != c->nseg + 1 || c->h_seg_row.back() != n) {
-      c->nseg = 1;
-      c->h_seg_row = {0, n};
-    }
     alloc_solve_work(c);
     HIPCHK(hipStreamSynchronize(s));
     const double t5 = now_ms();
@@ -1730,7 +1825,7 @@ int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     st.n_levels = n_levels;
     for (int l = 0; l <= L && l < 8; ++l) st.n[l] = c->nlev[l];
     st.n_sub[L] = n_sub;
-    st.n_sub[0] = 1;
+    st.n_sub[0] = nprob;
     int mm = 0;
     for (int v : c->F.m) mm = std::max(mm, v);
     st.m_max[L] = mm;
@@ -1760,6 +1855,29 @@ int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
   } catch (const std::exception& e) {
     return code_for(c, MsddError{MSDD_ENOMEM, e.what()});
   }
+}
+}  // namespace
+
+int msdd_setup(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col,
+               const double* val, int32_t n_elem, int32_t k, const int32_t* elem_dofs,
+               const double* elem_mat, int32_t n_sub, const int64_t* sub_elem_ptr,
+               const int32_t* sub_elem, const int64_t* sub_dof_ptr, const int32_t* sub_dof,
+               const double* sub_pou, int32_t n_levels, const int32_t* parent, double eta) {
+  return setup_impl(c, n, rowptr, col, val, n_elem, k, elem_dofs, elem_mat, n_sub, sub_elem_ptr,
+                    sub_elem, sub_dof_ptr, sub_dof, sub_pou, n_levels, parent, eta, 1, nullptr);
+}
+
+int msdd_setup_batch(msdd_ctx* c, int32_t nprob, const int64_t* prob_dof_ptr, int64_t n,
+                     const int64_t* rowptr, const int32_t* col, const double* val,
+                     int32_t n_elem, int32_t k, const int32_t* elem_dofs,
+                     const double* elem_mat, int32_t n_sub, const int64_t* sub_elem_ptr,
+                     const int32_t* sub_elem, const int64_t* sub_dof_ptr,
+                     const int32_t* sub_dof, const double* sub_pou, int32_t n_levels,
+                     const int32_t* parent, double eta) {
+  if (!prob_dof_ptr) return c ? code_for(c, MsddError{MSDD_EINVAL, "null prob_dof_ptr"}) : MSDD_EINVAL;
+  return setup_impl(c, n, rowptr, col, val, n_elem, k, elem_dofs, elem_mat, n_sub, sub_elem_ptr,
+                    sub_elem, sub_dof_ptr, sub_dof, sub_pou, n_levels, parent, eta, nprob,
+                    prob_dof_ptr);
 }
 
 int msdd_apply(msdd_ctx* c, const double* r, double* z) {

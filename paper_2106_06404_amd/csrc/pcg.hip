@@ -304,14 +304,23 @@ __global__ void k_apply_coarse_down(const i32* __restrict__ nown, const i64* __r
   }
 }
 
-// coarsest level: z0 = A_0^{-1} r0 with the explicit inverse, one thread per row
-__global__ void k_apply_coarsest(int n0, const double* __restrict__ Inv,
-                                 const double* __restrict__ r0, double* __restrict__ z0) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= n0) return;
-  double s = 0.0;
-  for (int q = 0; q < n0; ++q) s += Inv[o + (i64)q * n0] * r0[q];
-  z0[o] = s;
+// coarsest level: z0 = A_0^{-1} r0 with the explicit inverse of each diagonal block
+// (one block per problem).  One wavefront per row: row o of the symmetric inverse is
+// its column o, read contiguously.  grid = (ceil(n_max / 4), blocks), 256 threads.
+__global__ void __launch_bounds__(256) k_apply_coarsest(
+    const i64* __restrict__ zoff, const i64* __restrict__ aoff, const i32* __restrict__ n_arr,
+    const double* __restrict__ Inv, const double* __restrict__ r0, double* __restrict__ z0) {
+  const int t = blockIdx.y;
+  const int n = n_arr[t];
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (o >= n) return;
+  const double* col = Inv + aoff[t] + (i64)o * n;
+  const double* r = r0 + zoff[t];
+  double acc = 0.0;
+  for (int q = lane; q < n; q += 64) acc += col[q] * r[q];
+  acc = wave_sum(acc);
+  if (lane == 0) z0[zoff[t] + o] = acc;
 }
 
 // coarse level l, upward: z_l[own] += Y z_{l-1}[i,:]
@@ -459,9 +468,11 @@ void launch_apply_coarse_down(hipStream_t s, int P, int no_max, const i32* nown,
   hipLaunchKernelGGL(k_apply_coarse_down, dim3(P), dim3(MSDD_WG), (size_t)no_max * sizeof(double),
                      s, nown, own_ptr, own_idx, loff, Inv, msub, yoff, Y, moff, rl, zl, rc);
 }
-void launch_apply_coarsest(hipStream_t s, int n0, const double* Inv, const double* r0, double* z0) {
-  if (n0 <= 0) return;
-  hipLaunchKernelGGL(k_apply_coarsest, dim3((n0 + 127) / 128), dim3(128), 0, s, n0, Inv, r0, z0);
+void launch_apply_coarsest(hipStream_t s, int nt, int nmax, const i64* zoff, const i64* aoff,
+                           const i32* n_arr, const double* Inv, const double* r0, double* z0) {
+  if (nt <= 0 || nmax <= 0) return;
+  hipLaunchKernelGGL(k_apply_coarsest, dim3((nmax + 3) / 4, nt), dim3(256), 0, s, zoff, aoff,
+                     n_arr, Inv, r0, z0);
 }
 void launch_apply_coarse_up(hipStream_t s, int P, const i32* nown, const i64* own_ptr,
                             const i32* own_idx, const i32* msub, const i64* yoff, const double* Y,

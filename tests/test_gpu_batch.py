@@ -1,0 +1,84 @@
+"""Several problems in one setup (msdd_setup_batch) and one CG per problem
+(msdd_solve_batch), against the same problems set up one by one.
+
+Every per-subdomain computation of the batch is the computation of the single
+problem (the problems share no subdomain, patch or coarse block, and the PCG
+reductions chunk each problem's rows from its own first row), so the batch must
+reproduce the individual runs bitwise: counts, eigenvalues, iteration counts and
+solutions."""
+import numpy as np
+import pytest
+
+from msdd_inputs import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _members(levels):
+    if levels == 2:
+        return [P.small_problem(N=16, P=4, delta=1, contrast=1e4, seed=3),
+                P.small_problem(N=23, P=3, delta=2, contrast=1e6, seed=21),
+                P.small_problem(N=12, P=2, delta=1, contrast=1.0, seed=5)]
+    return [P.small_problem(N=16, P=4, delta=1, contrast=1e4, n_levels=3, groups=(2,), seed=11),
+            P.small_problem(N=20, P=4, delta=2, contrast=1e4, n_levels=3, groups=(2,), seed=12),
+            P.small_problem(N=24, P=6, delta=1, contrast=1e6, n_levels=3, groups=(3,), seed=13)]
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_batch_equals_individual_runs(levels):
+    import torch
+    from paper_2106_06404_amd import binding as B
+    probs = _members(levels)
+    single = []
+    for prob in probs:
+        m = B.Msdd()
+        m.setup(**B.problem_arrays(prob, device="cuda:0"))
+        L = prob.n_levels - 1
+        lv = {l: [m.eigs(l, i, 0) for i in range(len(m.level_counts(l, n_l)))]
+              for l, n_l in [(L, prob.n_sub)] + [(l, m.stats()["n_sub"][l]) for l in range(1, L)]}
+        b = torch.from_numpy(prob.b).cuda()
+        x = torch.zeros_like(b)
+        it, rel, _ = m.solve(b, x, 1e-8, 1000)
+        torch.cuda.synchronize()
+        single.append((lv, it, x.cpu().numpy()))
+        m.close()
+    arrs = B.batch_arrays(probs, device="cuda:0")
+    m = B.Msdd()
+    m.setup_batch(**arrs)
+    st = m.stats()
+    assert st["n_sub"][0] == len(probs)
+    L = levels - 1
+    for l in range(1, L + 1):
+        off = 0
+        for t, prob in enumerate(probs):
+            for i, lam in enumerate(single[t][0][l]):
+                assert np.array_equal(m.eigs(l, off + i, 0), lam), (l, t, i)
+            off += len(single[t][0][l])
+    b = torch.from_numpy(np.concatenate([p.b for p in probs])).cuda()
+    x = torch.zeros_like(b)
+    its, rels, _ = m.solve_batch(b, x, 1e-8, 1000)
+    torch.cuda.synchronize()
+    xh = x.cpu().numpy()
+    base = 0
+    for t, prob in enumerate(probs):
+        assert its[t] == single[t][1], (t, its[t], single[t][1])
+        assert rels[t] < 1e-8
+        assert np.array_equal(xh[base:base + prob.n], single[t][2]), t
+        base += prob.n
+    m.close()
+
+
+def test_batch_rules_are_checked():
+    from paper_2106_06404_amd import binding as B
+    probs = _members(2)
+    arrs = B.batch_arrays(probs)
+    m = B.Msdd()
+    bad = dict(arrs)
+    ptr = arrs["prob_dof_ptr"].copy()
+    ptr[1] -= 5   # problem 0's last dofs now belong to problem 1: its subdomains straddle
+    bad["prob_dof_ptr"] = ptr
+    with pytest.raises(B.MsddError) as e:
+        m.setup_batch(**bad)
+    assert e.value.code == B.MSDD_EINVAL
+    m.setup_batch(**arrs)   # the context is still usable
+    m.close()
