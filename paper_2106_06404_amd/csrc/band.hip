@@ -236,40 +236,52 @@ __global__ void k_band_cholesky_global(const i32* __restrict__ subs, const i32* 
 }
 
 // ---------------------------------------------------------------------------
-// Y = (L L^T)^{-1} W for K right-hand sides (column-major n x K, ld n): one
-// wavefront per right-hand side, WV wavefronts per workgroup sharing the
-// factor through the cache; each wavefront keeps its column in LDS.
+// Y = A^{-1} W for K right-hand sides (column-major n x K, ld n) with the LDL^T
+// factor of A (Fc column layout, Fr row layout, see trsv.h).  Half-bandwidths below
+// 64: NW right-hand sides per workgroup, rolling-window sweeps sharing tables in LDS;
+// otherwise one wavefront per right-hand side with the blocked sweeps.
 // ---------------------------------------------------------------------------
-template <typename T, typename V, int NWV, int WMAX>
-__global__ void __launch_bounds__(64 * NWV) k_band_solve_multi(
+template <typename T, typename V, int NW>
+__global__ void __launch_bounds__(64 * NW) k_band_solve_rot(
     const i32* __restrict__ subs, const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
-    const i64* __restrict__ l_off, const T* __restrict__ Lc, const T* __restrict__ Lr,
-    const i64* __restrict__ v_off, int K, int nmax, const V* __restrict__ Win,
-    V* __restrict__ Yout, const int* __restrict__ active) {
+    const i64* __restrict__ l_off, const T* __restrict__ Fc, const T* __restrict__ Fr,
+    const i64* __restrict__ v_off, int K, const V* __restrict__ Win, V* __restrict__ Yout,
+    const int* __restrict__ active) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = subs ? subs[blockIdx.x] : blockIdx.x;
   if (active && active[i] != ST_RUNNING) return;
   const int n = n_arr[i];
-  const int b = b_arr[i];
-  const int wv = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int c = blockIdx.y * NWV + wv;
-  const bool has = c < K;
-  V* v = reinterpret_cast<V*>(smem_raw) + (size_t)wv * nmax;
-  T* stage = reinterpret_cast<T*>(reinterpret_cast<V*>(smem_raw) + (size_t)NWV * nmax);
-  const V* Wi = Win + v_off[i] + (i64)(has ? c : 0) * n;
-  V* Yi = Yout + v_off[i] + (i64)(has ? c : 0) * n;
-  for (int q = lane; q < n; q += 64) v[q] = has ? Wi[q] : (V)0;
-  __syncthreads();
-  if (WMAX > 0) {
-    wg_trsv_staged<T, V, NWV, (WMAX > 0 ? WMAX : 1), false>(n, b, Lr + l_off[i], v, stage);
-    wg_trsv_staged<T, V, NWV, (WMAX > 0 ? WMAX : 1), true>(n, b, Lc + l_off[i], v, stage);
-  } else {
-    wave_trsv_lower<T, V>(n, b, Lr + l_off[i], v);
-    wave_trsv_upper<T, V>(n, b, Lc + l_off[i], v);
+  const int c0 = blockIdx.y * NW;
+  const int ncol = min(NW, K - c0);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  V* Y = Yout + v_off[i] + (i64)c0 * n;
+  if (wave < ncol) {
+    // each lane copies the rows it will own in the forward sweep
+    const V* Wc = Win + v_off[i] + (i64)(c0 + wave) * n;
+    V* Yc = Y + (i64)wave * n;
+    for (int q = lane; q < n; q += 64) Yc[q] = Wc[q];
   }
-  if (has)
-    for (int q = lane; q < n; q += 64) Yi[q] = v[q];
+  wg_ldl_solve_rot_cols<T, V, NW>(n, b_arr[i], Fc + l_off[i], Fr + l_off[i], Y, ncol,
+                                  reinterpret_cast<V*>(smem_raw));
+}
+
+template <typename T, typename V>
+__global__ void __launch_bounds__(64) k_band_solve_wave(
+    const i32* __restrict__ subs, const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
+    const i64* __restrict__ l_off, const T* __restrict__ Fr, const i64* __restrict__ v_off,
+    const V* __restrict__ Win, V* __restrict__ Yout, const int* __restrict__ active) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = subs ? subs[blockIdx.x] : blockIdx.x;
+  if (active && active[i] != ST_RUNNING) return;
+  const int n = n_arr[i];
+  const int c = blockIdx.y;
+  V* v = reinterpret_cast<V*>(smem_raw);
+  const V* Wc = Win + v_off[i] + (i64)c * n;
+  V* Yc = Yout + v_off[i] + (i64)c * n;
+  for (int q = threadIdx.x; q < n; q += 64) v[q] = Wc[q];
+  __syncthreads();
+  wave_ldl_solve<T, V>(n, b_arr[i], Fr + l_off[i], v);
+  for (int q = threadIdx.x; q < n; q += 64) Yc[q] = v[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -427,39 +439,31 @@ size_t band_cholesky_lds(int bmax, int elem_size) {
 
 template <typename T, typename V>
 void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax,
-                             const i32* n_arr, const i32* b_arr, const i64* l_off, const T* Lc,
-                             const T* Lr, const i64* v_off, int K, const V* W, V* Y,
+                             const i32* n_arr, const i32* b_arr, const i64* l_off, const T* Fc,
+                             const T* Fr, const i64* v_off, int K, const V* W, V* Y,
                              const int* active, int bmax) {
-  if (nsubs == 0) return;
-  const int w = bmax + 1;
-  const int wmax = w <= 40 ? 40 : (w <= 64 ? 64 : 0);
-  // waves per workgroup: as many right-hand sides as fit next to the staged factor
-  const size_t stage_b = wmax ? 2 * 64 * (size_t)w * sizeof(T) : 0;
-  int nwv = 8;
-  while (nwv > 1 && (size_t)nwv * nmax * sizeof(V) + stage_b > 150 * 1024) nwv /= 2;
-  const size_t lds = (size_t)nwv * nmax * sizeof(V) + stage_b;
-  dim3 grid(nsubs, (K + nwv - 1) / nwv);
-#define MSDD_SOLVE_CASE(NW, WM)                                                              \
-  if (nwv == NW && wmax == WM) {                                                             \
-    const void* fn = (const void*)k_band_solve_multi<T, V, NW, WM>;                          \
-    if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-    hipLaunchKernelGGL((k_band_solve_multi<T, V, NW, WM>), grid, dim3(64 * NW), lds, s, subs,   \
-                       n_arr, b_arr, l_off, Lc, Lr, v_off, K, nmax, W, Y, active);           \
-    return;                                                                                  \
+  if (nsubs == 0 || K == 0) return;
+  if (bmax < 64) {
+    const size_t lds = 2 * (size_t)ROT_TILE * sizeof(V);
+    if (K >= 16) {
+      (void)hipFuncSetAttribute((const void*)k_band_solve_rot<T, V, 16>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL((k_band_solve_rot<T, V, 16>), dim3(nsubs, (K + 15) / 16), dim3(1024), lds,
+                         s, subs, n_arr, b_arr, l_off, Fc, Fr, v_off, K, W, Y, active);
+    } else {
+      (void)hipFuncSetAttribute((const void*)k_band_solve_rot<T, V, 8>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL((k_band_solve_rot<T, V, 8>), dim3(nsubs, (K + 7) / 8), dim3(512), lds, s,
+                         subs, n_arr, b_arr, l_off, Fc, Fr, v_off, K, W, Y, active);
+    }
+    return;
   }
-  MSDD_SOLVE_CASE(8, 40)
-  MSDD_SOLVE_CASE(4, 40)
-  MSDD_SOLVE_CASE(2, 40)
-  MSDD_SOLVE_CASE(1, 40)
-  MSDD_SOLVE_CASE(8, 64)
-  MSDD_SOLVE_CASE(4, 64)
-  MSDD_SOLVE_CASE(2, 64)
-  MSDD_SOLVE_CASE(1, 64)
-  MSDD_SOLVE_CASE(8, 0)
-  MSDD_SOLVE_CASE(4, 0)
-  MSDD_SOLVE_CASE(2, 0)
-  MSDD_SOLVE_CASE(1, 0)
-#undef MSDD_SOLVE_CASE
+  const size_t lds = (size_t)nmax * sizeof(V);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_band_solve_wave<T, V>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_band_solve_wave<T, V>), dim3(nsubs, K), dim3(64), lds, s, subs, n_arr,
+                     b_arr, l_off, Fr, v_off, W, Y, active);
 }
 template void launch_band_solve_multi<double, double>(hipStream_t, int, const i32*, int,
                                                       const i32*, const i32*, const i64*,

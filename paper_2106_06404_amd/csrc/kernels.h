@@ -32,10 +32,11 @@ void launch_band_scale(hipStream_t s, int nsubs, int nmax, int bmax, const i32* 
                        const i32* b_arr, const i64* off, const i64* doff, double* B, double* sc,
                        int* status);
 size_t band_cholesky_lds(int bmax, int elem_size);
+// Y = A^{-1} W for K columns per subdomain with the LDL^T factor (Fc, Fr layouts).
 template <typename T, typename V>
 void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax,
-                             const i32* n_arr, const i32* b_arr, const i64* l_off, const T* Lc,
-                             const T* Lr, const i64* v_off, int K, const V* W, V* Y,
+                             const i32* n_arr, const i32* b_arr, const i64* l_off, const T* Fc,
+                             const T* Fr, const i64* v_off, int K, const V* W, V* Y,
                              const int* active, int bmax);
 
 // eig.hip

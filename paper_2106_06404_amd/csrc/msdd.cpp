@@ -311,7 +311,7 @@ struct FineLevel {
   int ell_w = 0;
   DVec<int32_t> ell_col;
   DVec<double> ell_val;
-  DVec<double> LSc, LSr;                // factor of S = abar + sigma*b
+  DVec<double> LSc, LSr;                // LDL^T factor of S = abar + sigma*b (column, row layouts)
   // Dirichlet
   std::vector<int32_t> h_nd, h_bd, h_dpos, h_dglob, h_rankb;
   std::vector<int64_t> h_doff, h_dboff;
@@ -790,6 +790,10 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   }
   HIPCHK(hipGetLastError());
   check_status(status.download(s), "Cholesky of abar + sigma*b");
+  // the eigensolver's solves use the LDL^T form: row layout in LSr, column layout in LSc
+  launch_band_to_ldl<double>(s, P, F.nb_max, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.LSc.p,
+                             F.LSr.p);
+  HIPCHK(hipGetLastError());
   if (c->opt.precision == MSDD_MIXED) {
     // single precision: factor diag(sc) A_i diag(sc), sc = diag(A_i)^{-1/2}
     F.dscale.alloc(std::max<int64_t>(F.h_doff.back(), 1));
