@@ -18,6 +18,7 @@
 // the rest.
 #include "common.h"
 #include "jacobi.h"
+#include "symeig.h"
 #include "kernels.h"
 
 // V[p] (npd x M, column-major): values of the patch's coarse functions at the patch dofs
@@ -284,18 +285,14 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   double* C = Qk + g2;
   double* Yc = C + g2;
   int* keep = reinterpret_cast<int*>(Yc + g2);
-  __shared__ int sh_fail, cnt, sh_r, sh_m, nrot, nrot1;
-  __shared__ double sh_smax, sh_fro, red[32];
-  // dynamic LDS: Jacobi pair data, then (in_lds) the matrix being diagonalised
+  __shared__ int sh_fail, sh_r, sh_m;
+  __shared__ double sh_smax, red[32];
+  // dynamic LDS: eigenvalues d (ng_max), workspace (4 ng_max), then (in_lds) the matrix
+  // being diagonalised, later its eigenvector copy
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int npm = (ng_max + 2) / 2;
-  double* pc = reinterpret_cast<double*>(smem_raw);
-  double* ps = pc + npm;
-  int* pp = reinterpret_cast<int*>(ps + npm);
-  int* pq = pp + npm;
-  double* Alds = reinterpret_cast<double*>(smem_raw) + 2 * npm + npm;  // after 2 int arrays
-  double* Sx = in_lds ? Alds : S;  // S, then C, live in LDS when they fit
-  double* Cx = in_lds ? Alds : C;
+  double* d = reinterpret_cast<double*>(smem_raw);
+  double* wsp = d + ng_max;
+  double* Alds = wsp + 4 * ng_max;
   const int tid = threadIdx.x, nt = blockDim.x;
   if (no == 0) {
     if (tid == 0) {
@@ -306,31 +303,25 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
     }
     return;
   }
-  // S (row-major, symmetric) and its Frobenius norm
-  double fro = 0.0;
+  double* Sx = in_lds ? Alds : S;  // S, then C, live in LDS when they fit
+  double* Cx = in_lds ? Alds : C;
+  // S (row-major, symmetric)
   for (i64 e = tid; e < g2; e += nt) {
     const int r = (int)(e / ng), c = (int)(e % ng);
     const double a = 0.5 * (A[r + (i64)c * ng] + A[c + (i64)r * ng]);
-    const double v = (r < no && c < no) ? 2.0 * a : a;
-    Sx[e] = v;
-    fro += v * v;
+    Sx[e] = (r < no && c < no) ? 2.0 * a : a;
   }
-  fro = block_sum(fro, red);
-  if (tid == 0) sh_fro = sqrt(fro);
   __syncthreads();
-  if (tid == 0) nrot = 0;
-  JacobiScratch<double> js{pp, pq, pc, ps, &cnt, &nrot};
-  // separate calls so that the LDS case is compiled with LDS accesses
-  const int sw1 = in_lds ? jacobi_block<double, 4, true, 10>(ng, Alds, Q, js, 60, 2.220446049250313e-16, 1e-18 * sh_fro)
-                         : jacobi_block<double, 4, true, 10>(ng, S, Q, js, 60, 2.220446049250313e-16, 1e-18 * sh_fro);
+  // S = Q diag(d) Q^T (Q transposed in global memory); separate calls so that the LDS
+  // case is compiled with LDS accesses
+  const int st1 = in_lds ? wg_syev<double>(ng, Alds, Q, Alds, d, wsp, red)
+                         : wg_syev<double>(ng, S, Q, nullptr, d, wsp, red);
   if (tid == 0) {
-    nrot1 = nrot;  // rotations of the ng x ng diagonalisation
-    nrot = 0;
     double smax = 0.0;
-    for (int a = 0; a < ng; ++a) smax = fmax(smax, Sx[(i64)a * ng + a]);
+    for (int a = 0; a < ng; ++a) smax = fmax(smax, d[a]);
     int r = 0;
     for (int a = 0; a < ng; ++a)
-      if (Sx[(i64)a * ng + a] > tau * smax) keep[r++] = a;
+      if (d[a] > tau * smax) keep[r++] = a;
     sh_smax = smax;
     sh_r = r;
   }
@@ -340,7 +331,7 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   for (i64 e = tid; e < (i64)ng * r; e += nt) {
     const int row = (int)(e / r), k = (int)(e % r);
     const int a = keep[k];
-    Qk[e] = Q[(i64)a * ng + row] / sqrt(Sx[(i64)a * ng + a]);  // Q stored transposed
+    Qk[e] = Q[(i64)a * ng + row] / sqrt(d[a]);  // Q stored transposed
   }
   __syncthreads();
   // C = Qk_o^T A_oo Qk_o: first Q <- A_oo Qk_o (no x r), then C (r x r, row-major)
@@ -360,17 +351,16 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
     Cx[(i64)b * r + a] = acc;
   }
   __syncthreads();
-  double fc = 0.0;
-  for (i64 e = tid; e < (i64)r * r; e += nt) fc += Cx[e] * Cx[e];
-  fc = block_sum(fc, red);
-  const int sw2 = in_lds ? jacobi_block<double, 4, true, 10>(r, Alds, Yc, js, 60, 2.220446049250313e-16, 1e-18 * sqrt(fc))
-                         : jacobi_block<double, 4, true, 10>(r, C, Yc, js, 60, 2.220446049250313e-16, 1e-18 * sqrt(fc));
+  // C = Y diag(mu) Y^T (Y transposed in Yc); mu in d
+  const int st2 = in_lds ? wg_syev<double>(r, Alds, Yc, Alds, d, wsp, red)
+                         : wg_syev<double>(r, C, Yc, nullptr, d, wsp, red);
   if (tid == 0) {
-    sweeps_out[4 * t] = sw1;
-    sweeps_out[4 * t + 1] = sw2;
-    sweeps_out[4 * t + 2] = nrot1;  // rotations on the ng x ng matrix
-    sweeps_out[4 * t + 3] = nrot;   // rotations on the r x r matrix
+    sweeps_out[4 * t] = st1;
+    sweeps_out[4 * t + 1] = st2;
+    sweeps_out[4 * t + 2] = ng;
+    sweeps_out[4 * t + 3] = r;
   }
+  const bool ql_failed = st1 < 0 || st2 < 0;
   // sort mu descending, lambda = 1/mu - 1 ascending
   double* lam = lam_out + lamoff[t];
   int* ord = keep;  // reused (r entries)
@@ -378,9 +368,9 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
     for (int a = 0; a < r; ++a) ord[a] = a;
     for (int a = 1; a < r; ++a) {
       const int v = ord[a];
-      const double mv = Cx[(i64)v * r + v];
+      const double mv = d[v];
       int b = a - 1;
-      while (b >= 0 && Cx[(i64)ord[b] * r + ord[b]] < mv) {
+      while (b >= 0 && d[ord[b]] < mv) {
         ord[b + 1] = ord[b];
         --b;
       }
@@ -388,7 +378,7 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
     }
     int m = 0, nl = 0;
     for (int a = 0; a < r && nl < no; ++a) {
-      const double mu = Cx[(i64)ord[a] * r + ord[a]];
+      const double mu = d[ord[a]];
       if (mu <= 1e-12) break;
       const double lv = fmax(1.0 / mu - 1.0, 0.0);
       lam[nl++] = lv;
@@ -407,7 +397,7 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   for (i64 e = tid; e < (i64)no * m; e += nt) {
     const int row = (int)(e % no), c = (int)(e / no);
     const int src = ord[c];
-    const double mu = Cx[(i64)src * r + src];
+    const double mu = d[src];
     double acc = 0.0;
     for (int k = 0; k < r; ++k) acc += Qk[(i64)row * r + k] * Yc[(i64)src * r + k];  // Yc transposed
     Xo[row + (i64)c * no] = acc / sqrt(mu);
@@ -422,7 +412,7 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
     if (tid == 0) status[t] = ST_NOTSPD;
     return;
   }
-  if (tid == 0) status[t] = ST_DONE;
+  if (tid == 0) status[t] = ql_failed ? ST_NOCONV : ST_DONE;
 }
 
 // Dense lower factor (column-major, n x n) -> the row and column band layouts with
@@ -561,11 +551,10 @@ void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_
                         double eps_reg, double* lam_out, const i64* lamoff, int* m_out,
                         int* status, int* rank_out, int* sweeps_out, int ng_max) {
   if (!nt) return;
-  const int npm = (ng_max + 2) / 2;
-  const size_t pairs = (size_t)npm * (2 * sizeof(double) + 2 * sizeof(int));
-  const size_t full = pairs + (size_t)ng_max * ng_max * sizeof(double);
+  const size_t vecs = 5 * (size_t)ng_max * sizeof(double);
+  const size_t full = vecs + (size_t)ng_max * ng_max * sizeof(double);
   const int in_lds = full <= 150 * 1024;
-  const size_t lds = in_lds ? full : pairs;
+  const size_t lds = in_lds ? full : vecs;
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_coarse_gevp,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

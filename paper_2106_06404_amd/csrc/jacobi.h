@@ -48,8 +48,11 @@ __device__ inline void jacobi_pair(int r, int k, int m, int& p, int& q) {
 // two contiguous rows, which matters when V lives in global memory.  JU / JV: work
 // items per thread whose loads are issued together (A blocks / V entries).
 template <typename R, int JU = 4, bool VT = false, int JV = JU>
+// skip_below: pairs whose two diagonal entries are both below it are not rotated
+// (for a positive semi-definite A the whole 2x2 block is then below it: its
+// rotations only mix directions that the caller discards).
 __device__ __forceinline__ int jacobi_block(int n, R* A, R* V, JacobiScratch<R> s, int max_sweeps, R eps,
-                            R floor_abs) {
+                            R floor_abs, R skip_below = 0) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, nwv = (nt + 63) >> 6;
   for (int r0 = wv; r0 < n; r0 += nwv)
@@ -71,7 +74,8 @@ __device__ __forceinline__ int jacobi_block(int n, R* A, R* V, JacobiScratch<R> 
         if (q < n) {
           const R apq = A[p * n + q];
           const R app = A[p * n + p], aqq = A[q * n + q];
-          if (fabs(apq) > eps * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
+          if (fabs(apq) > eps * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs &&
+              (fabs(app) >= skip_below || fabs(aqq) >= skip_below)) {
             const R theta = (aqq - app) / (2 * apq);
             const R t = (theta >= 0 ? (R)1 : (R)-1) / (fabs(theta) + sqrt((R)1 + theta * theta));
             c = (R)1 / sqrt((R)1 + t * t);

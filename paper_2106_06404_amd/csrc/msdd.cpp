@@ -516,6 +516,9 @@ void check_status(const std::vector<int>& st, const char* what, const std::vecto
     if (st[i] == ST_BADINPUT)
       throw MsddError{MSDD_EINVAL, std::string(what) + ": entry outside the element structure or NaN in subdomain " +
                                        std::to_string(ids ? (*ids)[i] : (int)i)};
+    if (st[i] == ST_NOCONV)
+      throw MsddError{MSDD_EEIG, std::string(what) + ": eigensolver did not converge in subdomain " +
+                                     std::to_string(ids ? (*ids)[i] : (int)i)};
   }
 }
 
@@ -1268,9 +1271,9 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
   std::vector<int> sw;
   std::vector<int> rkh;
   {
-    // flops: each Jacobi rotation of an n x n matrix rotates two rows and two columns
-    // of it and two eigenvector columns, 3 flops per rotated entry (18 n); counted
-    // from the rotations the kernel reports
+    // flops of the two symmetric eigendecompositions (sizes ng and r): Householder
+    // tridiagonalisation and accumulation of Q, 8/3 n^3, and the QL rotations applied
+    // to the eigenvectors, counted as 3 n^2 per QL step (steps reported by the kernel)
     ProfScope pscope(c, PR_COARSE_GEVP);
     launch_coarse_gevp(s, Pc, dng.p, dno.p, aoff.p, Abar.p, CL.loff.p, CL.Lo.p, dsoff.p,
                        scratch.p, c->eta, c->opt.nev_max, c->opt.eps_reg_rel, CL.lam.p, dlamoff.p,
@@ -1281,7 +1284,10 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
     rkh = rk.download(s);
     double fl = 0.0;
     for (int i = 0; i < Pc; ++i)
-      fl += 18.0 * ((double)sw[4 * i + 2] * CL.ng[i] + (double)sw[4 * i + 3] * rkh[i]);
+      for (int q = 0; q < 2; ++q) {
+        const double nn = sw[4 * i + 2 + q];
+        fl += 8.0 / 3.0 * nn * nn * nn + 3.0 * nn * nn * std::max(sw[4 * i + q], 0);
+      }
     pscope.flops = fl;
   }
   std::vector<int> stv = st.download(s);
@@ -1294,10 +1300,10 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
       s2 = std::max(s2, sw[4 * i + 1]);
       rmax = std::max(rmax, rkh[i]);
     }
-    fprintf(stderr, "msdd:   coarse level %d: %d subdomains, ng max %d, rank max %d, Jacobi sweeps max %d / %d\n",
+    fprintf(stderr, "msdd:   coarse level %d: %d subdomains, ng max %d, rank max %d, QL steps max %d / %d\n",
             l, Pc, ngm, rmax, s1, s2);
   }
-  check_status(stv, "coarse GEVP (Cholesky of the owned block)");
+  check_status(stv, "coarse GEVP (eigensolver or Cholesky of the owned block)");
   CL.m = mo.download(s);
   CL.rank = rk.download(s);
   std::vector<double> lamh = CL.lam.download(s);

@@ -1,0 +1,224 @@
+// Workgroup-parallel symmetric eigensolver for one dense n x n matrix:
+// Householder reduction to tridiagonal form, then implicit QL iteration with
+// Wilkinson-type shifts on the tridiagonal matrix (the textbook symmetric QR/QL
+// algorithm, Golub and Van Loan, "Matrix Computations", Sec. 8.3), with the
+// orthogonal transformations accumulated into the eigenvector matrix.
+//
+//   A  : n x n symmetric, row-major (LDS or global); overwritten (the Householder
+//        vectors are kept in its strictly lower part).
+//   Zt : n x n output, eigenvectors stored transposed: Zt[a*n + k] = component k of
+//        eigenvector a (so rotations of eigenvector pairs touch two contiguous rows).
+//        If Zl is not null, the QL rotations run on the copy Zl (LDS, n x n) and the
+//        result is copied to Zt.
+//   d  : n eigenvalues (LDS), unsorted, d[a] belongs to eigenvector a.
+//   w  : LDS workspace of 4n entries.
+// All threads of the workgroup must call it.  Returns the number of QL steps, or -1
+// if some eigenvalue needed more than 60 QL steps.
+#pragma once
+#include "common.h"
+
+template <typename R>
+__device__ __forceinline__ int wg_syev(int n, R* A, R* Zt, R* Zl, R* d, R* w, R* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  R* e = w;          // subdiagonal: e[i] = T(i+1, i)
+  R* beta = w + n;   // Householder scalars
+  R* v = w + 2 * n;  // current Householder vector / rotation cosines
+  R* sn = w + 3 * n;  // rotation sines
+  __shared__ R sh_alpha, sh_beta, sh_k;
+  __shared__ int sh_state[5];  // l, m, lo, iterations at l, failed
+  if (n == 1) {
+    if (tid == 0) {
+      d[0] = A[0];
+      Zt[0] = (R)1;
+    }
+    __syncthreads();
+    return 0;
+  }
+  // ---- 1. tridiagonalisation: for k = 0..n-3, H_k = I - beta v v^T zeroes A[k+2.., k]
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;  // length of the vector (rows k+1..n-1)
+    R part = 0;
+    for (int i = k + 2 + tid; i < n; i += nt) part += A[(i64)i * n + k] * A[(i64)i * n + k];
+    const R sig = block_sum(part, red);
+    if (tid == 0) {
+      const R x0 = A[(i64)(k + 1) * n + k];
+      if (sig == (R)0) {  // already reduced: no reflection
+        sh_alpha = x0;
+        sh_beta = 0;
+      } else {
+        const R nx = sqrt(x0 * x0 + sig);
+        const R alpha = x0 >= 0 ? -nx : nx;
+        const R v0 = x0 - alpha;
+        sh_alpha = alpha;
+        sh_beta = (R)2 / (v0 * v0 + sig);
+        A[(i64)(k + 1) * n + k] = v0;  // v stored in column k below the diagonal
+      }
+      e[k] = sh_alpha;
+      beta[k] = sh_beta;
+    }
+    __syncthreads();
+    const R bt = sh_beta;
+    if (bt != (R)0) {
+      for (int i = tid; i < m; i += nt) v[i] = A[(i64)(k + 1 + i) * n + k];
+      __syncthreads();
+      // p = bt * A_sub v  (rows k+1..n-1), 8 threads per row
+      for (int i0 = 0; i0 < m; i0 += nt / 8) {
+        const int i = i0 + tid / 8, l8 = tid & 7;
+        R acc = 0;
+        if (i < m) {
+          const R* Ar = A + (i64)(k + 1 + i) * n + (k + 1);
+          for (int j = l8; j < m; j += 8) acc += Ar[j] * v[j];
+        }
+        for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 8);
+        if (i < m && l8 == 0) sn[i] = bt * acc;
+      }
+      __syncthreads();
+      // K = bt/2 v^T p ; q = p - K v (in sn)
+      R kp = 0;
+      for (int i = tid; i < m; i += nt) kp += v[i] * sn[i];
+      kp = block_sum(kp, red);
+      const R Kc = (R)0.5 * bt * kp;
+      for (int i = tid; i < m; i += nt) sn[i] -= Kc * v[i];
+      __syncthreads();
+      // A_sub -= v q^T + q v^T
+      for (i64 t = tid; t < (i64)m * m; t += nt) {
+        const int i = (int)(t / m), j = (int)(t - (i64)i * m);
+        A[(i64)(k + 1 + i) * n + (k + 1 + j)] -= v[i] * sn[j] + sn[i] * v[j];
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < n; i += nt) d[i] = A[(i64)i * n + i];
+  if (tid == 0) {
+    e[n - 2] = A[(i64)(n - 1) * n + (n - 2)];
+    beta[n - 2] = 0;
+    e[n - 1] = 0;
+  }
+  __syncthreads();
+  // ---- 2. Q = H_0 H_1 ... H_{n-3}, accumulated backwards, stored transposed in Zt
+  for (i64 t = tid; t < (i64)n * n; t += nt) Zt[t] = (t / n == t % n) ? (R)1 : (R)0;
+  __syncthreads();
+  for (int k = n - 3; k >= 0; --k) {
+    const R bt = beta[k];
+    if (bt == (R)0) continue;
+    const int m = n - k - 1;
+    for (int i = tid; i < m; i += nt) v[i] = A[(i64)(k + 1 + i) * n + k];
+    __syncthreads();
+    // Q[k+1:, k+1:] -= bt v (v^T Q[k+1:, k+1:]):  wq_c = v . Zt[c][k+1:], 8 threads per c
+    for (int c0 = 0; c0 < m; c0 += nt / 8) {
+      const int c = c0 + tid / 8, l8 = tid & 7;
+      R acc = 0;
+      if (c < m) {
+        const R* Zr = Zt + (i64)(k + 1 + c) * n + (k + 1);
+        for (int r = l8; r < m; r += 8) acc += Zr[r] * v[r];
+      }
+      for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 8);
+      if (c < m && l8 == 0) sn[c] = bt * acc;
+    }
+    __syncthreads();
+    for (i64 t = tid; t < (i64)m * m; t += nt) {
+      const int c = (int)(t / m), r = (int)(t - (i64)c * m);
+      Zt[(i64)(k + 1 + c) * n + (k + 1 + r)] -= sn[c] * v[r];
+    }
+    __syncthreads();
+  }
+  R* Z = Zl ? Zl : Zt;
+  if (Zl) {
+    for (i64 t = tid; t < (i64)n * n; t += nt) Zl[t] = Zt[t];
+    __syncthreads();
+  }
+  // ---- 3. implicit QL on (d, e); each step's rotations are computed by one thread
+  // (they depend on each other) and applied by all threads to the rows of Z
+  const R eps = (R)2.220446049250313e-16;
+  if (tid == 0) {
+    sh_state[0] = 0;  // l
+    sh_state[3] = 0;  // iterations at this l
+    sh_state[4] = 0;  // failed
+  }
+  __syncthreads();
+  int steps = 0;
+  while (true) {
+    if (tid == 0) {
+      int l = sh_state[0], it = sh_state[3];
+      int flag = 0, m = l, lo = 0;
+      while (l < n) {
+        m = l;
+        while (m < n - 1) {
+          const R dd = fabs(d[m]) + fabs(d[m + 1]);
+          if (fabs(e[m]) <= eps * dd) break;
+          ++m;
+        }
+        if (m == l || it >= 60) {  // eigenvalue l converged (or gave up)
+          if (m != l) sh_state[4] = 1;
+          ++l;
+          it = 0;
+          continue;
+        }
+        break;
+      }
+      if (l >= n) {
+        flag = 2;
+      } else {
+        ++it;
+        R g = (d[l + 1] - d[l]) / ((R)2 * e[l]);
+        R r = sqrt(g * g + (R)1);
+        g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+        R s = 1, c = 1, p = 0;
+        int i;
+        lo = l;
+        for (i = m - 1; i >= l; --i) {
+          const R f = s * e[i], bb = c * e[i];
+          r = sqrt(f * f + g * g);
+          e[i + 1] = r;
+          if (r == (R)0) {  // deflation inside the sweep
+            d[i + 1] -= p;
+            e[m] = 0;
+            lo = i + 1;
+            break;
+          }
+          s = f / r;
+          c = g / r;
+          g = d[i + 1] - p;
+          r = (d[i] - g) * s + (R)2 * c * bb;
+          p = s * r;
+          d[i + 1] = g + p;
+          g = c * r - bb;
+          v[i] = c;
+          sn[i] = s;
+        }
+        if (i < l) {
+          d[l] -= p;
+          e[l] = g;
+          e[m] = 0;
+        }
+        flag = 1;
+      }
+      sh_state[0] = l;
+      sh_state[1] = m;
+      sh_state[2] = lo;
+      sh_state[3] = it;
+      sh_k = (R)flag;
+    }
+    __syncthreads();
+    if (sh_k == (R)2) break;
+    ++steps;
+    // rotations i = m-1 down to lo on eigenvector rows (i, i+1) of Z (transposed)
+    const int m = sh_state[1], lo = sh_state[2];
+    for (int k = tid; k < n; k += nt) {
+      R zi1 = Z[(i64)m * n + k];
+      for (int i = m - 1; i >= lo; --i) {
+        const R zi = Z[(i64)i * n + k];
+        const R c = v[i], s = sn[i];
+        Z[(i64)(i + 1) * n + k] = s * zi + c * zi1;
+        zi1 = c * zi - s * zi1;
+      }
+      Z[(i64)lo * n + k] = zi1;
+    }
+    __syncthreads();
+  }
+  if (Zl) {
+    for (i64 t = tid; t < (i64)n * n; t += nt) Zt[t] = Zl[t];
+    __syncthreads();
+  }
+  return sh_state[4] ? -1 : steps;
+}
