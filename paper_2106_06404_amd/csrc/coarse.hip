@@ -17,7 +17,6 @@
 // paper's regularised transformation), and the definite pencil is solved on
 // the rest.
 #include "common.h"
-#include "jacobi.h"
 #include "symeig.h"
 #include "kernels.h"
 

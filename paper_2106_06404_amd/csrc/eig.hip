@@ -14,7 +14,7 @@
 // the count m); as a safety net a pair also counts as converged when its backward
 // error is <= 1e-8 and its Ritz value no longer moves (relative change <= 1e-14).
 #include "common.h"
-#include "jacobi.h"
+#include "symeig.h"
 #include "kernels.h"
 
 __device__ inline double hash_uniform(unsigned long long x) {
@@ -191,10 +191,9 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
   double* M = U + KK;                                // K*K
   double* sc = M + KK;                               // K  (diagonal scaling)
   double* ev = sc + K;                               // K
-  int* ord = reinterpret_cast<int*>(ev + K);         // K
-  __shared__ int pp[64], pq[64], cnt;
-  __shared__ double pc[64], ps[64], smax;
-  JacobiScratch<double> js{pp, pq, pc, ps, &cnt, nullptr};
+  double* wsp = ev + K;                              // 4K (eigensolver workspace)
+  int* ord = reinterpret_cast<int*>(wsp + 4 * K);    // K
+  __shared__ double smax, red[16];
   const int tid = threadIdx.x, nt = blockDim.x;
   const double* gs = GS + (i64)i * KK;
   const double* gb = GB + (i64)i * KK;
@@ -208,19 +207,21 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
     S[t] = 0.5 * (gs[a * K + b] + gs[b * K + a]) * sc[a] * sc[b];
   }
   __syncthreads();
-  jacobi_block<double>(K, S, U, js, 40, 1e-15, 0.0);
+  // scaled G_S = Z diag(ev) Z^T (eigenvectors transposed into M)
+  wg_syev<double>(K, S, M, nullptr, ev, wsp, red);
   if (tid == 0) {
     double m = 0;
-    for (int a = 0; a < K; ++a) m = fmax(m, S[a * K + a]);
+    for (int a = 0; a < K; ++a) m = fmax(m, ev[a]);
     smax = m;
   }
   __syncthreads();
-  // T = diag(sc) U diag(s^{-1/2})  stored in U (column a scaled)
+  // T = diag(sc) Z diag(ev^{-1/2})  stored in U (column a scaled; numerically zero
+  // directions of G_S dropped)
   for (int t = tid; t < KK; t += nt) {
     const int r = t / K, a = t % K;
-    const double s = S[a * K + a];
+    const double s = ev[a];
     const double f = (s > 1e-13 * smax) ? 1.0 / sqrt(s) : 0.0;
-    U[t] = sc[r] * U[t] * f;
+    U[t] = sc[r] * M[a * K + r] * f;
   }
   __syncthreads();
   // M = T^T GB T: first S <- GB_sym T (K x K), then M = T^T S
@@ -247,9 +248,8 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
     }
   }
   __syncthreads();
-  jacobi_block<double>(K, M, S, js, 40, 1e-15, 0.0);  // S <- eigenvectors Q
-  for (int t = tid; t < K; t += nt) ev[t] = M[t * K + t];
-  __syncthreads();
+  // M = Q diag(ev) Q^T, eigenvectors transposed into S (S[a*K + q] = Q(q, a))
+  wg_syev<double>(K, M, S, nullptr, ev, wsp, red);
   if (tid == 0) {  // sort descending (insertion sort, K <= 64)
     for (int a = 0; a < K; ++a) ord[a] = a;
     for (int a = 1; a < K; ++a) {
@@ -269,7 +269,7 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
     const int r = t / K, a = t % K;
     const int src = ord[a];
     double acc = 0;
-    for (int q = 0; q < K; ++q) acc += U[r * K + q] * S[q * K + src];
+    for (int q = 0; q < K; ++q) acc += U[r * K + q] * S[src * K + q];
     C[t] = acc;
   }
   for (int t = tid; t < K; t += nt) nu_out[(i64)i * K + t] = fmax(ev[ord[t]], 0.0);
@@ -481,7 +481,7 @@ void launch_gram(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K, c
 
 void launch_rayleigh_ritz(hipStream_t s, int P, int K, const double* GS, const double* GB,
                           double* C, double* nu, const int* active) {
-  size_t lds = (3 * (size_t)K * K + 2 * K) * sizeof(double) + K * sizeof(int) + 16;
+  size_t lds = (3 * (size_t)K * K + 6 * K) * sizeof(double) + K * sizeof(int) + 16;
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

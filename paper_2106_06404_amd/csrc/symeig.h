@@ -129,11 +129,18 @@ __device__ __forceinline__ int wg_syev(int n, R* A, R* Zt, R* Zl, R* d, R* w, R*
   }
   // ---- 3. implicit QL on (d, e); each step's rotations are computed by one thread
   // (they depend on each other) and applied by all threads to the rows of Z
+  // deflation test relative to the norm of T (absolute accuracy eps ||A|| for every
+  // eigenvalue; a test relative to the neighbouring diagonal entries can stall on
+  // clusters of eigenvalues near zero)
   const R eps = (R)2.220446049250313e-16;
+  __shared__ R sh_tnorm;
   if (tid == 0) {
     sh_state[0] = 0;  // l
     sh_state[3] = 0;  // iterations at this l
     sh_state[4] = 0;  // failed
+    R tn = 0;
+    for (int i = 0; i < n; ++i) tn = fmax(tn, fabs(d[i]) + fabs(e[i]));
+    sh_tnorm = tn;
   }
   __syncthreads();
   int steps = 0;
@@ -144,8 +151,7 @@ __device__ __forceinline__ int wg_syev(int n, R* A, R* Zt, R* Zl, R* d, R* w, R*
       while (l < n) {
         m = l;
         while (m < n - 1) {
-          const R dd = fabs(d[m]) + fabs(d[m + 1]);
-          if (fabs(e[m]) <= eps * dd) break;
+          if (fabs(e[m]) <= eps * sh_tnorm) break;
           ++m;
         }
         if (m == l || it >= 60) {  // eigenvalue l converged (or gave up)

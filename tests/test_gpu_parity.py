@@ -161,10 +161,14 @@ def test_c2_full_against_golden():
         ~eps ||A|| ||x|| / ||b|| = 3e-6.  GPU and oracle histories agree to 4 digits for
         the first 60 iterations and stay within a factor 1.85 afterwards, but a spike
         (iteration 95: 4.9e-6 against 8.3e-6) moves the crossing of 1e-5 by two
-        iterations, and the oracle's last step lands at 0.98e-8.  So iteration counts to
-        every tolerance 1e-2 ... 1e-8 are compared within +-2 (the +-1 bar holds on the
-        other workloads), the whole history within a factor 3.2 (10^0.5), the solution
-        at sampled dofs within 1e-7 and the true residual below 1e-5."""
+        iterations.  Below the attainable accuracy the recurrence residual is dominated
+        by rounding: it contracts by about 0.77 per iteration near 1e-8 (oracle history,
+        iterations 115-120), so the history bound below (a factor 10^0.5) allows the
+        crossing of 1e-8 to move by log(10^0.5)/log(1/0.77) = 4.4 iterations; the oracle's
+        last step lands at 0.98e-8.  So crossings of 1e-2 ... 1e-7 are compared within +-2
+        (the +-1 bar holds on the other workloads), the final count within +-4, the whole
+        history within a factor 10^0.5, the solution at sampled dofs within 1e-7 and the
+        true residual below 1e-5."""
     with open(os.path.join(HERE, "golden", "c2_oracle.json")) as f:
         g = json.load(f)
     prob = P.config2()
@@ -185,7 +189,7 @@ def test_c2_full_against_golden():
     ho = ho / ho[0]
     for tau in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7):
         assert abs(_first_below(h, tau) - _first_below(ho, tau)) <= 2, tau
-    assert abs(it - g["pcg"]["iters"]) <= 2
+    assert abs(it - g["pcg"]["iters"]) <= 4
     k = min(len(h), len(ho))
     assert np.max(np.abs(np.log10(h[:k] / ho[:k]))) <= 0.5
     idx = np.array(g["pcg"]["x_sample_idx"])
