@@ -177,8 +177,9 @@ __global__ void k_gram(const i32* __restrict__ nb, const i64* __restrict__ kvoff
 }
 
 // Rayleigh-Ritz: G_B c = nu G_S c  ->  C (K x K, row-major), nu (descending).
-// Robust to a rank-deficient G_S: G_S is diagonalised (Jacobi) and directions with
-// eigenvalue <= 1e-13 * max are dropped (they get nu = 0 and a zero column).
+// Robust to a rank-deficient G_S: a Cholesky factorisation of the diagonally scaled
+// G_S drops the columns that depend on earlier ones (they get nu = 0 and a zero
+// column); the projected standard problem is solved by cyclic Jacobi.
 __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
                                 const double* __restrict__ GB, double* __restrict__ Cout,
                                 double* __restrict__ nu_out, const int* __restrict__ active) {
@@ -193,7 +194,6 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
   double* ev = sc + K;                               // K
   double* wsp = ev + K;                              // 4K (eigensolver workspace)
   int* ord = reinterpret_cast<int*>(wsp + 4 * K);    // K
-  __shared__ double smax, red[16];
   const int tid = threadIdx.x, nt = blockDim.x;
   const double* gs = GS + (i64)i * KK;
   const double* gb = GB + (i64)i * KK;
@@ -207,21 +207,44 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
     S[t] = 0.5 * (gs[a * K + b] + gs[b * K + a]) * sc[a] * sc[b];
   }
   __syncthreads();
-  // scaled G_S = Z diag(ev) Z^T (eigenvectors transposed into M)
-  wg_syev<double>(K, S, M, nullptr, ev, wsp, red);
-  if (tid == 0) {
-    double m = 0;
-    for (int a = 0; a < K; ++a) m = fmax(m, ev[a]);
-    smax = m;
+  // scaled G_S = L L^T by a Cholesky factorisation that drops dependent columns: a
+  // column whose pivot (its squared G_S-distance from the span of the kept earlier
+  // columns, relative to its own G_S-norm, which the scaling makes 1) is <= 1e-13
+  // gets a zero column in L.  L overwrites the lower triangle of S; ord[j] = kept.
+  for (int j = 0; j < K; ++j) {
+    if (tid == 0) {
+      const double dj = S[j * K + j];
+      ord[j] = dj > 1e-13;
+      S[j * K + j] = dj > 1e-13 ? sqrt(dj) : 0.0;
+    }
+    __syncthreads();
+    const double ljj = S[j * K + j];
+    for (int r = j + 1 + tid; r < K; r += nt) S[r * K + j] = ljj > 0.0 ? S[r * K + j] / ljj : 0.0;
+    __syncthreads();
+    const int m = K - j - 1;
+    for (int t = tid; t < m * m; t += nt) {
+      const int r = j + 1 + t / m, c = j + 1 + t % m;
+      if (c <= r) S[r * K + c] -= S[r * K + j] * S[c * K + j];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // T = diag(sc) Z diag(ev^{-1/2})  stored in U (column a scaled; numerically zero
-  // directions of G_S dropped)
+  // Z = L^{-1} (rows of dropped columns are zero), row by row into M
+  for (int a = 0; a < K; ++a) {
+    for (int c = tid; c < K; c += nt) {
+      double z = 0.0;
+      if (ord[a] && c <= a) {
+        double acc = c == a ? 1.0 : 0.0;
+        for (int k = c; k < a; ++k) acc -= S[a * K + k] * M[k * K + c];
+        z = acc / S[a * K + a];
+      }
+      M[a * K + c] = z;
+    }
+    __syncthreads();
+  }
+  // T = diag(sc) L^{-T} in U: T^T G_S T = I on the kept columns, zero columns elsewhere
   for (int t = tid; t < KK; t += nt) {
     const int r = t / K, a = t % K;
-    const double s = ev[a];
-    const double f = (s > 1e-13 * smax) ? 1.0 / sqrt(s) : 0.0;
-    U[t] = sc[r] * M[a * K + r] * f;
+    U[t] = sc[r] * M[a * K + r];
   }
   __syncthreads();
   // M = T^T GB T: first S <- GB_sym T (K x K), then M = T^T S
@@ -249,7 +272,7 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
   }
   __syncthreads();
   // M = Q diag(ev) Q^T, eigenvectors transposed into S (S[a*K + q] = Q(q, a))
-  wg_syev<double>(K, M, S, nullptr, ev, wsp, red);
+  wg_jacobi<double>(K, M, S, ev);
   if (tid == 0) {  // sort descending (insertion sort, K <= 64)
     for (int a = 0; a < K; ++a) ord[a] = a;
     for (int a = 1; a < K; ++a) {
@@ -485,7 +508,9 @@ void launch_rayleigh_ritz(hipStream_t s, int P, int K, const double* GS, const d
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_rayleigh_ritz, dim3(P), dim3(MSDD_WG), lds, s, K, GS, GB, C, nu, active);
+  // one wave per subdomain for K = 16 (the Jacobi rounds update K^2/4 blocks), four above
+  const int nt = K <= 16 ? 64 : 256;
+  hipLaunchKernelGGL(k_rayleigh_ritz, dim3(P), dim3(nt), lds, s, K, GS, GB, C, nu, active);
 }
 
 void launch_row_norm(hipStream_t s, int P, const i64* voff, int ell_w, const i32* ell_col,

@@ -228,3 +228,109 @@ __device__ __forceinline__ int wg_syev(int n, R* A, R* Zt, R* Zl, R* d, R* w, R*
   }
   return sh_state[4] ? -1 : steps;
 }
+
+// Workgroup-parallel cyclic Jacobi eigensolver for one small symmetric matrix
+// (n even, n <= 64): the round-robin ("tournament") ordering gives n/2 disjoint
+// rotation planes per round, each annihilating one off-diagonal pair with the
+// symmetric Schur rotation (Golub and Van Loan, Sec. 8.5); the n/2 rotations of a
+// round are applied together as 2x2 block updates of A, so one round costs one
+// parallel rotation step.  A matrix that is nearly diagonal already (the Gram
+// matrices of a subspace iteration close to convergence) finishes in one or two
+// sweeps.
+//   A  : n x n symmetric, row-major (LDS); overwritten, its diagonal holds the
+//        eigenvalues on return.
+//   Zt : n x n output (LDS), eigenvectors stored transposed (Zt[a*n + k] = component k
+//        of eigenvector a), as in wg_syev.
+//   d  : n eigenvalues, unsorted.
+// A rotation is skipped when |a_pq| <= 1e-16 sqrt(|a_pp a_qq|) (relative test:
+// graded eigenvalues keep their relative accuracy).  All threads must call it.
+// Returns the number of sweeps, or -1 after 40 sweeps without convergence.
+template <typename R>
+__device__ __forceinline__ int wg_jacobi(int n, R* A, R* Zt, R* d) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ R rc[64], rs[64];
+  __shared__ int pp[32], pq[32];
+  __shared__ int sh_flag;
+  const R tol = (R)1e-16;
+  const int h = n / 2;
+  for (int t = tid; t < n * n; t += nt) Zt[t] = (t / n == t % n) ? (R)1 : (R)0;
+  int sweeps = 0;
+  for (; sweeps < 40; ++sweeps) {
+    // convergence test over all off-diagonal pairs
+    if (tid == 0) sh_flag = 0;
+    __syncthreads();
+    int any = 0;
+    for (int t = tid; t < n * n; t += nt) {
+      const int p = t / n, q = t - p * n;
+      if (p < q) {
+        const R apq = A[t];
+        if (apq != (R)0 && fabs(apq) > tol * sqrt(fabs(A[p * n + p] * A[q * n + q]))) any = 1;
+      }
+    }
+    if (any) sh_flag = 1;
+    __syncthreads();
+    if (!sh_flag) break;
+    for (int r = 0; r < n - 1; ++r) {
+      // rotation of each pair of this round
+      for (int k = tid; k < h; k += nt) {
+        int p, q;
+        if (k == 0) {
+          p = n - 1;
+          q = r;
+        } else {
+          p = (r + k) % (n - 1);
+          q = (r - k + n - 1) % (n - 1);
+        }
+        const R apq = A[p * n + q], app = A[p * n + p], aqq = A[q * n + q];
+        R c = 1, s = 0;
+        if (apq != (R)0 && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+          const R th = (aqq - app) / ((R)2 * apq);
+          const R at = fabs(th);
+          // t = sign(th) / (|th| + sqrt(1 + th^2)), the smaller root
+          R t = at > (R)1e150 ? (R)0.5 / at : (R)1 / (at + sqrt((R)1 + th * th));
+          if (th < 0) t = -t;
+          c = (R)1 / sqrt((R)1 + t * t);
+          s = t * c;
+        }
+        pp[k] = p;
+        pq[k] = q;
+        rc[k] = c;
+        rs[k] = s;
+      }
+      __syncthreads();
+      // A <- G^T A G as 2x2 blocks (row pair k1, column pair k2)
+      for (int t = tid; t < h * h; t += nt) {
+        const int k1 = t / h, k2 = t - k1 * h;
+        const int p1 = pp[k1], q1 = pq[k1], p2 = pp[k2], q2 = pq[k2];
+        const R c1 = rc[k1], s1 = rs[k1], c2 = rc[k2], s2 = rs[k2];
+        const R a = A[p1 * n + p2], b = A[p1 * n + q2], dd = A[q1 * n + p2], e = A[q1 * n + q2];
+        const R a1 = c1 * a - s1 * dd, b1 = c1 * b - s1 * e;
+        const R d1 = s1 * a + c1 * dd, e1 = s1 * b + c1 * e;
+        R a2 = c2 * a1 - s2 * b1, b2 = s2 * a1 + c2 * b1;
+        R d2 = c2 * d1 - s2 * e1, e2 = s2 * d1 + c2 * e1;
+        if (k1 == k2 && s1 != (R)0) {
+          b2 = 0;
+          d2 = 0;
+        }
+        A[p1 * n + p2] = a2;
+        A[p1 * n + q2] = b2;
+        A[q1 * n + p2] = d2;
+        A[q1 * n + q2] = e2;
+      }
+      // Zt <- G^T Zt (rows p, q)
+      for (int t = tid; t < h * n; t += nt) {
+        const int k = t / n, col = t - k * n;
+        const R c = rc[k], s = rs[k];
+        if (s == (R)0) continue;
+        const int p = pp[k], q = pq[k];
+        const R zp = Zt[p * n + col], zq = Zt[q * n + col];
+        Zt[p * n + col] = c * zp - s * zq;
+        Zt[q * n + col] = s * zp + c * zq;
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = tid; t < n; t += nt) d[t] = A[t * n + t];
+  __syncthreads();
+  return sweeps < 40 ? sweeps : -1;
+}
