@@ -98,6 +98,10 @@ typedef struct {
   double t_solve_ms;      /* last msdd_solve */
   int32_t pcg_iters;      /* last msdd_solve */
   double pcg_relres;      /* last msdd_solve: recurrence ||r_m|| / ||r_0|| */
+  int64_t eig_iters_sum;  /* local eigensolver iterations summed over the finest-level
+                             subdomains and all their passes */
+  int32_t warm_started;   /* finest-level subdomains started from the network's block */
+  int32_t warm_fallbacks; /* of those, re-solved from the random start (not converged) */
 } msdd_stats_t;
 
 /* Fill *opt with defaults. */
@@ -222,7 +226,7 @@ int msdd_get_basis(const msdd_ctx* c, int32_t level, int32_t i, double* basis, i
  * compute; see each kernel's comment).  msdd_profile_name gives the class name
  * (NULL for an id out of range).
  */
-#define MSDD_NPROF 18
+#define MSDD_NPROF 19
 int msdd_profile(msdd_ctx* c, int enable);
 int msdd_profile_query(msdd_ctx* c, int id, double* total_ms, int64_t* launches,
                        double* alg_bytes, double* alg_flops);
@@ -233,6 +237,101 @@ const char* msdd_last_error(const msdd_ctx* c);
 
 /* Release all device memory owned by the context. */
 void msdd_destroy(msdd_ctx* c);
+
+/* Local eigensolver iterations of every finest-level subdomain in the last setup
+ * (summed over its passes): iters[n_sub] (host or device). */
+int msdd_get_eig_iters(const msdd_ctx* c, int32_t* iters);
+
+/*
+ * ---------------------------------------------------------------------------
+ * Learned warm start of the local eigensolver.
+ *
+ * An extension of the method: the paper solves each local GEVP of Sec. 2.3
+ * (abar w = lambda b w) from scratch.  A network msdd_net maps a subdomain's
+ * coefficient features x (n_in values) to n_vec vectors on a fixed frame of n_pos
+ * node positions, a three-layer perceptron with relu activations
+ *     y = relu(relu(x W1 + b1) W2 + b2) W3 + b3,   y[v*n_pos + q] = vector v at q.
+ * Attached with msdd_warm_start, it supplies the first n_vec columns of the start
+ * block of the finest-level eigensolver; the eigensolver's backward-error test
+ * judges the result exactly as for a random start, and a subdomain whose
+ * warm-started iteration stops without converging is solved again from the random
+ * start (cold-start fallback).  The eigenvalues and the coarse space therefore do
+ * not depend on the network beyond the eigensolver tolerance.
+ *
+ * Training: the targets are the method's own converged eigenvectors
+ * (msdd_warm_targets after a setup with collect > 0); the loss of a sample is the
+ * share of its unit-norm target vectors t_1..t_m outside the span of the masked
+ * output block Ys = diag(s) Y:
+ *     loss = 1 - tr(C^T G^{-1} C) / m,  G = Ys^T Ys + 1e-6 I,  C = Ys^T T,
+ * averaged over the batch; Adam (beta1 0.9, beta2 0.999, eps 1e-8) updates the
+ * parameters.  Training runs in FP32; inference in BF16 on the matrix cores with
+ * FP32 accumulation.
+ * ---------------------------------------------------------------------------
+ */
+typedef struct msdd_net msdd_net; /* opaque; owns its device memory */
+
+/* Create a network on `device`, launching on `stream` (hipStream_t; NULL = the legacy
+ * default stream).  Weights are Glorot-uniform draws of a counter-based generator
+ * seeded with `seed` (the splitmix64 finaliser of seed ^ index); biases are 0.
+ * Limits: n_in, n_hidden, n_pos >= 1; 1 <= n_vec <= 16.  MSDD_EINVAL otherwise. */
+int msdd_net_create(msdd_net** out, int32_t n_in, int32_t n_hidden, int32_t n_vec,
+                    int32_t n_pos, uint64_t seed, int32_t device, void* stream);
+
+/* Number of parameters: n_in*H + H + H*H + H + H*n_vec*n_pos + n_vec*n_pos (-1 for NULL). */
+int64_t msdd_net_param_count(const msdd_net* net);
+
+/* Flat FP32 parameter vector, in the order W1 (n_in x H, row-major), b1 (H),
+ * W2 (H x H), b2 (H), W3 (H x n_vec*n_pos), b3 (n_vec*n_pos); host or device
+ * pointer of msdd_net_param_count entries.  set also clears the Adam moments. */
+int msdd_net_set_params(msdd_net* net, const float* p);
+int msdd_net_get_params(const msdd_net* net, float* p);
+
+/* Forward pass of `batch` samples: x (batch x n_in), y (batch x n_vec*n_pos), FP32
+ * arrays on host or device.  mode 0: FP32 arithmetic (the training pass); mode 1:
+ * inputs, weights and hidden activations rounded to BF16 (nearest even), products on
+ * the matrix cores with FP32 accumulation, biases in FP32 (the pass the setup uses). */
+int msdd_net_forward(msdd_net* net, int32_t batch, const float* x, float* y, int32_t mode);
+
+/* Mean loss over the samples idx[0..batch) of a training set of n_samples samples:
+ *   x_all  (n_samples x n_in)       features,
+ *   tgt    (n_samples x m_cap x n_pos) target vectors (unit 2-norm on the mask),
+ *   mask   (n_samples x n_pos)      1 on the sample's frame positions, 0 elsewhere,
+ *   cnt    (n_samples)              targets used per sample (<= m_cap; 0 = none),
+ * all host or device; 1 <= m_cap <= 16; every idx must lie in [0, n_samples).
+ * loss (host, may be NULL) receives the mean loss and grad (host or device, may be
+ * NULL) its gradient with respect to the flat parameter vector.  FP32. */
+int msdd_net_grad(msdd_net* net, int32_t batch, const int32_t* idx, int32_t n_samples,
+                  const float* x_all, const float* tgt, const float* mask, const int32_t* cnt,
+                  int32_t m_cap, float* loss, float* grad);
+
+/* One Adam step with learning rate lr > 0 on the same loss (loss may be NULL). */
+int msdd_net_train_step(msdd_net* net, int32_t batch, const int32_t* idx, int32_t n_samples,
+                        const float* x_all, const float* tgt, const float* mask,
+                        const int32_t* cnt, int32_t m_cap, float lr, float* loss);
+
+const char* msdd_net_last_error(const msdd_net* net);
+void msdd_net_destroy(msdd_net* net);
+
+/* Attach a warm start to the next msdd_setup / msdd_setup_batch of c (n_sub = 0
+ * detaches).  n_sub must equal that setup's number of finest-level subdomains and
+ * n_entries its sub_dof_ptr[n_sub].
+ *   x (n_sub x n_in, host or device): features per subdomain (used when net != NULL);
+ *   sub_pos[n_entries]: for each entry of that setup's sub_dof array, the frame position
+ *     (0 <= pos < n_pos) of the dof, or -1 (no frame position: that row starts from
+ *     the random block);
+ *   net: the network (its n_in and n_pos must match; it must outlive the setup), or
+ *     NULL: no warm start, the frame layout only serves collect;
+ *   collect: m_cap > 0 keeps training targets, the first min(m_i + 1, m_cap) converged
+ *     eigenvectors of every subdomain (m_i selected ones plus the next), for
+ *     msdd_warm_targets; 1 <= m_cap <= 16.
+ * The arrays are copied.  MSDD_EINVAL on size or range errors (also at setup time if
+ * the setup's sizes differ). */
+int msdd_warm_start(msdd_ctx* c, msdd_net* net, int32_t n_sub, int32_t n_in, const float* x,
+                    int64_t n_entries, const int32_t* sub_pos, int32_t n_pos, int32_t collect);
+
+/* Training targets of the last setup (it must have had collect = m_cap > 0):
+ * tgt (n_sub x m_cap x n_pos), mask (n_sub x n_pos), cnt (n_sub); host or device. */
+int msdd_warm_targets(const msdd_ctx* c, float* tgt, float* mask, int32_t* cnt);
 
 #ifdef __cplusplus
 }

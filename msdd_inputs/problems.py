@@ -547,3 +547,65 @@ def free_dof_coords(prob: Problem):
             comp[dd[m]] = cc
     assert nn > 0 and k > 0
     return coords, comp
+
+
+# ----------------------------------------------------------------------------
+# Frame layout of the learned warm start (inputs only; no solver arithmetic)
+# ----------------------------------------------------------------------------
+
+def warm_frame(prob: Problem, delta: int, log_scale: float = 4.0):
+    """Features and frame positions of every finest-level box subdomain of a scalar
+    problem on the structured mesh.
+
+    The frame of box b is the element block [cut_b - delta, cut_b + core + delta) per
+    dimension (core = widest box), so that the box's own elements always sit at the same
+    frame place; elements of the frame outside the subdomain (at the domain boundary) are
+    absent.  Features per subdomain (float32):
+      [log10(k_e) / log_scale on the E^dim frame elements (0 where absent),
+       presence flag per frame element,
+       2*dim flags: the frame's low / high side reaches the domain boundary].
+    sub_pos (int32, aligned with prob.sub_dof): frame node index of each Neumann dof.
+    Returns feat [P, 2 E^dim + 2 dim], sub_pos, n_pos = (E+1)^dim.
+    """
+    if prob.ncomp != 1 or prob.box_shape is None:
+        raise ValueError("warm_frame needs a scalar problem on a box partition")
+    dim, N = prob.dim, prob.N
+    Pd = prob.box_shape[0]
+    cuts = _split(N, Pd)
+    core = int(np.max(np.diff(cuts)))
+    E = core + 2 * delta
+    M = E + 1
+    n_pos = M ** dim
+    ec = element_coords(dim, N)
+    logk = np.log10(np.asarray(prob.coeff, np.float64)) / log_scale
+    # integer node coordinates of each free dof
+    nn = (N + 1) ** dim
+    ncoord = np.stack(np.meshgrid(*([np.arange(N + 1)] * dim), indexing="ij"), -1).reshape(-1, dim)[:, ::-1]
+    nodes = element_nodes(dim, N)
+    dof_node = np.full(prob.n, -1, np.int64)
+    ed = prob.elem_dofs
+    valid = ed >= 0
+    dof_node[ed[valid]] = nodes[valid]
+    assert np.all(dof_node >= 0) and nn == ncoord.shape[0]
+    dof_xyz = ncoord[dof_node]
+    P = prob.n_sub
+    feat = np.zeros((P, 2 * E ** dim + 2 * dim), np.float32)
+    sub_pos = np.full(prob.sub_dof.shape[0], -1, np.int32)
+    strides_e = np.array([E ** d for d in range(dim)])
+    strides_n = np.array([M ** d for d in range(dim)])
+    for i, bidx in enumerate(itertools.product(range(Pd), repeat=dim)):
+        b = bidx[::-1]  # same box numbering as box_partition
+        origin = np.array([cuts[b[d]] - delta for d in range(dim)])
+        el = prob.sub_elems(i)
+        fe = ((ec[el] - origin) * strides_e).sum(1)
+        assert fe.min() >= 0 and fe.max() < E ** dim
+        feat[i, fe] = logk[el]
+        feat[i, E ** dim + fe] = 1.0
+        for d in range(dim):
+            feat[i, 2 * E ** dim + 2 * d] = float(origin[d] <= 0)
+            feat[i, 2 * E ** dim + 2 * d + 1] = float(origin[d] + E >= N)
+        lo, hi = prob.sub_dof_ptr[i], prob.sub_dof_ptr[i + 1]
+        fp = ((dof_xyz[prob.sub_dof[lo:hi]] - origin) * strides_n).sum(1)
+        assert fp.min() >= 0 and fp.max() < n_pos
+        sub_pos[lo:hi] = fp
+    return feat, sub_pos, n_pos

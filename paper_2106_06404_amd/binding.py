@@ -47,7 +47,8 @@ class MsddStats(ctypes.Structure):
                 ("t_local_ms", ctypes.c_double), ("t_gevp_ms", ctypes.c_double),
                 ("t_coarse_ms", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("pcg_iters", ctypes.c_int32),
-                ("pcg_relres", ctypes.c_double)]
+                ("pcg_relres", ctypes.c_double), ("eig_iters_sum", ctypes.c_int64),
+                ("warm_started", ctypes.c_int32), ("warm_fallbacks", ctypes.c_int32)]
 
     def as_dict(self):
         L = self.n_levels
@@ -61,8 +62,11 @@ EXPORTS = ["msdd_default_options", "msdd_create", "msdd_setup", "msdd_setup_batc
            "msdd_solve_batch", "msdd_solve_history", "msdd_apply",
            "msdd_stats", "msdd_get_level_counts", "msdd_get_eigs", "msdd_get_basis",
            "msdd_profile", "msdd_profile_query", "msdd_profile_name", "msdd_last_error",
-           "msdd_destroy"]
-MSDD_NPROF = 18
+           "msdd_destroy", "msdd_get_eig_iters", "msdd_warm_start", "msdd_warm_targets",
+           "msdd_net_create", "msdd_net_param_count", "msdd_net_set_params",
+           "msdd_net_get_params", "msdd_net_forward", "msdd_net_grad", "msdd_net_train_step",
+           "msdd_net_last_error", "msdd_net_destroy"]
+MSDD_NPROF = 19
 
 _lib = None
 
@@ -80,6 +84,14 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libmsdd.so not built ({LIB_PATH}); run paper_2106_06404_amd/build.py")
+    # torch ships its own HIP runtime; it is brought up before the library's own one
+    # (the order in which both have been seen to share the device)
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
@@ -120,6 +132,31 @@ def load():
     L.msdd_last_error.restype = ctypes.c_char_p
     L.msdd_destroy.argtypes = [vp]
     L.msdd_destroy.restype = None
+    L.msdd_get_eig_iters.argtypes = [vp, vp]
+    L.msdd_get_eig_iters.restype = ctypes.c_int
+    L.msdd_warm_start.argtypes = [vp, vp, i32, i32, vp, i64, vp, i32, i32]
+    L.msdd_warm_start.restype = ctypes.c_int
+    L.msdd_warm_targets.argtypes = [vp, vp, vp, vp]
+    L.msdd_warm_targets.restype = ctypes.c_int
+    L.msdd_net_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, ctypes.c_uint64, i32, vp]
+    L.msdd_net_create.restype = ctypes.c_int
+    L.msdd_net_param_count.argtypes = [vp]
+    L.msdd_net_param_count.restype = i64
+    L.msdd_net_set_params.argtypes = [vp, vp]
+    L.msdd_net_set_params.restype = ctypes.c_int
+    L.msdd_net_get_params.argtypes = [vp, vp]
+    L.msdd_net_get_params.restype = ctypes.c_int
+    L.msdd_net_forward.argtypes = [vp, i32, vp, vp, i32]
+    L.msdd_net_forward.restype = ctypes.c_int
+    L.msdd_net_grad.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float), vp]
+    L.msdd_net_grad.restype = ctypes.c_int
+    L.msdd_net_train_step.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, i32, ctypes.c_float,
+                                      ctypes.POINTER(ctypes.c_float)]
+    L.msdd_net_train_step.restype = ctypes.c_int
+    L.msdd_net_last_error.argtypes = [vp]
+    L.msdd_net_last_error.restype = ctypes.c_char_p
+    L.msdd_net_destroy.argtypes = [vp]
+    L.msdd_net_destroy.restype = None
     _lib = L
     return L
 
@@ -141,7 +178,7 @@ def _ptr(a, dtype):
         return ctypes.c_void_p(a.ctypes.data)
     import torch
     tmap = {np.dtype(np.float64): torch.float64, np.dtype(np.int32): torch.int32,
-            np.dtype(np.int64): torch.int64}
+            np.dtype(np.int64): torch.int64, np.dtype(np.float32): torch.float32}
     assert isinstance(a, torch.Tensor) and a.dtype == tmap[np.dtype(dtype)] and a.is_contiguous()
     return ctypes.c_void_p(a.data_ptr())
 
@@ -251,6 +288,32 @@ class Msdd:
                                                ctypes.byref(r), ctypes.byref(c)))
         return out.T.copy()
 
+    def eig_iters(self, nsub: int) -> np.ndarray:
+        """Local eigensolver iterations per finest-level subdomain of the last setup."""
+        it = np.zeros(nsub, np.int32)
+        self._check(self._L.msdd_get_eig_iters(self._h, ctypes.c_void_p(it.ctypes.data)))
+        return it
+
+    def warm_start(self, net, n_sub, sub_pos, n_pos, feat=None, collect=0):
+        """Attach a warm start to the next setup: net (or None: frame layout only, for
+        collect), n_sub finest-level subdomains, sub_pos int32 aligned with sub_dof,
+        feat n_sub x n_in float32 (needed with a network), collect = m_cap."""
+        n_in = int(feat.shape[1]) if feat is not None else 0
+        rc = self._L.msdd_warm_start(self._h, net._h if net is not None else None, int(n_sub),
+                                     n_in, _ptr(feat, np.float32) if feat is not None else None,
+                                     int(sub_pos.shape[0]), _ptr(sub_pos, np.int32), int(n_pos),
+                                     int(collect))
+        return self._check(rc)
+
+    def warm_detach(self):
+        return self._check(self._L.msdd_warm_start(self._h, None, 0, 0, None, 0, None, 1, 0))
+
+    def warm_targets(self, tgt, mask, cnt):
+        """Copy the collected training targets into tgt (n_sub x m_cap x n_pos float32),
+        mask (n_sub x n_pos float32) and cnt (n_sub int32)."""
+        return self._check(self._L.msdd_warm_targets(self._h, _ptr(tgt, np.float32),
+                                                     _ptr(mask, np.float32), _ptr(cnt, np.int32)))
+
     def profile(self, enable=True, reset=True):
         """enable=True: reset (unless reset=False) and enable; False: pause, keeping counts."""
         mode = (1 if reset else 2) if enable else 0
@@ -269,6 +332,75 @@ class Msdd:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._L.msdd_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MsddNet:
+    """The warm-start network of the local eigensolver (msdd_net_* of msdd.h)."""
+
+    def __init__(self, n_in, n_hidden, n_vec, n_pos, seed=0, device=0, stream=None):
+        L = load()
+        self._L = L
+        h = ctypes.c_void_p()
+        rc = L.msdd_net_create(ctypes.byref(h), int(n_in), int(n_hidden), int(n_vec), int(n_pos),
+                               ctypes.c_uint64(seed & (2 ** 64 - 1)), int(device), stream)
+        if rc != MSDD_OK:
+            raise MsddError(rc, "msdd_net_create failed")
+        self._h = h
+        self.n_in, self.n_hidden, self.n_vec, self.n_pos = int(n_in), int(n_hidden), int(n_vec), int(n_pos)
+
+    def _check(self, rc):
+        if rc != MSDD_OK:
+            raise MsddError(rc, self._L.msdd_net_last_error(self._h).decode())
+        return rc
+
+    @property
+    def n_params(self) -> int:
+        return int(self._L.msdd_net_param_count(self._h))
+
+    def set_params(self, p):
+        return self._check(self._L.msdd_net_set_params(self._h, _ptr(p, np.float32)))
+
+    def get_params(self, out=None):
+        if out is None:
+            out = np.zeros(self.n_params, np.float32)
+        self._check(self._L.msdd_net_get_params(self._h, _ptr(out, np.float32)))
+        return out
+
+    def forward(self, x, y, mode=1):
+        """y (batch x n_vec*n_pos) = network(x); mode 0 FP32, 1 BF16 matrix cores."""
+        return self._check(self._L.msdd_net_forward(self._h, int(x.shape[0]), _ptr(x, np.float32),
+                                                    _ptr(y, np.float32), int(mode)))
+
+    def grad(self, idx, x_all, tgt, mask, cnt, grad=None):
+        """Mean loss of samples idx and (into grad, if given) its parameter gradient."""
+        loss = ctypes.c_float()
+        self._check(self._L.msdd_net_grad(self._h, int(idx.shape[0]), _ptr(idx, np.int32),
+                                          int(x_all.shape[0]), _ptr(x_all, np.float32),
+                                          _ptr(tgt, np.float32), _ptr(mask, np.float32),
+                                          _ptr(cnt, np.int32), int(tgt.shape[1]),
+                                          ctypes.byref(loss),
+                                          _ptr(grad, np.float32) if grad is not None else None))
+        return float(loss.value)
+
+    def train_step(self, idx, x_all, tgt, mask, cnt, lr, want_loss=True):
+        loss = ctypes.c_float()
+        self._check(self._L.msdd_net_train_step(
+            self._h, int(idx.shape[0]), _ptr(idx, np.int32), int(x_all.shape[0]),
+            _ptr(x_all, np.float32), _ptr(tgt, np.float32), _ptr(mask, np.float32),
+            _ptr(cnt, np.int32), int(tgt.shape[1]), float(lr),
+            ctypes.byref(loss) if want_loss else None))
+        return float(loss.value) if want_loss else None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.msdd_net_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

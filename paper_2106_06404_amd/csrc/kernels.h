@@ -147,3 +147,33 @@ void launch_apply_fine_up(hipStream_t s, i64 n, const i64* dinc_ptr, const i32* 
                           const i32* dinc_q, const i64* doff, const i32* msub, const i64* moff,
                           const i64* phid_off, const double* PhiD, const double* u,
                           const double* zc, double* z);
+
+// mlp.hip (warm-start network of the local eigensolver)
+// C_z = opA(A) opB(B) over split z of K (row-major M x N partials); every split is
+// non-empty, so at most `splits` are launched: the count launched is returned
+int sgemm_splits(int K, int splits);
+int launch_sgemm(hipStream_t s, int ta, int tb, int M, int N, int K, int splits, const float* A,
+                 int lda, const float* B, int ldb, float* C);
+void launch_splitk_epi(hipStream_t s, int M, int N, int splits, const float* part, const float* bias,
+                       const float* h, int mode, float* out);
+void launch_colsum(hipStream_t s, int M, int N, const float* D, float* g);
+void launch_gather_rows(hipStream_t s, int B, int w, const int* idx, const float* src, float* dst);
+void launch_proj_loss(hipStream_t s, int B, int V, int n_pos, int m_cap, const int* idx,
+                      const float* y, const float* tgt, const float* mask, const int* cnt,
+                      double ridge, float* dy, float* loss_b);
+void launch_adam(hipStream_t s, i64 n, float* p, const float* g, float* m, float* v, float lr,
+                 int step);
+void launch_init_uniform(hipStream_t s, i64 lo, i64 hi, float a, unsigned long long seed, float* w);
+void launch_to_bf16(hipStream_t s, int rows, int cols, int ldd, const float* src, int lds,
+                    unsigned short* dst);
+void launch_to_bf16_t(hipStream_t s, int rows, int cols, int ldd, const float* src, int lds,
+                      unsigned short* dst);
+void launch_hgemm(hipStream_t s, int M, int N, int Kp, const unsigned short* A, const unsigned short* Bt,
+                  const float* bias, int relu, int out_bf16, void* C, int ldc);
+void launch_eig_init_warm(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
+                          const i32* nb, const i64* kvoff, int K, const double* dv, double* X,
+                          unsigned long long seed, const i32* seed_id, const int* warm,
+                          const float* yw, int n_vec, int n_pos, const i32* pos);
+void launch_warm_targets(hipStream_t s, int nsel, const int* sel, const i32* nb, const i64* voff,
+                         const i64* kvoff, int K, const double* X, const int* mcount, int m_cap,
+                         int n_pos, const i32* pos, float* tgt, float* mask, int* cnt);

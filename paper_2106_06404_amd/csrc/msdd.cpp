@@ -25,88 +25,13 @@
 #include <vector>
 
 #include "common.h"
+#include "host_util.h"
 #include "kernels.h"
+#include "net.h"
+
+using namespace msdd_host;
 
 namespace {
-
-struct MsddError {
-  int code;
-  std::string msg;
-};
-
-#define HIPCHK(x)                                                                       \
-  do {                                                                                  \
-    hipError_t e_ = (x);                                                                \
-    if (e_ != hipSuccess)                                                               \
-      throw MsddError{MSDD_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)};    \
-  } while (0)
-
-#define REQUIRE(cond, msg)                                     \
-  do {                                                         \
-    if (!(cond)) throw MsddError{MSDD_EINVAL, std::string(msg)}; \
-  } while (0)
-
-double now_ms() {
-  using namespace std::chrono;
-  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
-}
-
-template <class T>
-struct DVec {
-  T* p = nullptr;
-  size_t n = 0;
-  DVec() = default;
-  DVec(const DVec&) = delete;
-  DVec& operator=(const DVec&) = delete;
-  DVec(DVec&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
-  DVec& operator=(DVec&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
-    return *this;
-  }
-  ~DVec() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    n = 0;
-  }
-  void alloc(size_t cnt) {
-    release();
-    if (cnt == 0) return;
-    if (hipMalloc((void**)&p, cnt * sizeof(T)) != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      throw MsddError{MSDD_ENOMEM, "device allocation of " + std::to_string(cnt * sizeof(T)) + " bytes failed"};
-    }
-    n = cnt;
-  }
-  void zero(hipStream_t s) {
-    if (n) HIPCHK(hipMemsetAsync(p, 0, n * sizeof(T), s));
-  }
-  void upload(const std::vector<T>& v, hipStream_t s) {
-    alloc(v.size());
-    if (n) HIPCHK(hipMemcpyAsync(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
-  }
-  std::vector<T> download(hipStream_t s, size_t cnt = (size_t)-1) const {
-    if (cnt == (size_t)-1) cnt = n;
-    std::vector<T> v(cnt);
-    if (cnt) {
-      HIPCHK(hipMemcpyAsync(v.data(), p, cnt * sizeof(T), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-    }
-    return v;
-  }
-};
-
-bool is_device_ptr(const void* ptr) {
-  if (!ptr) return false;
-  hipPointerAttribute_t a;
-  hipError_t e = hipPointerGetAttributes(&a, ptr);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return a.type == hipMemoryTypeDevice || a.isManaged;
-}
 
 int host_threads(int work) {
   unsigned hc = std::thread::hardware_concurrency();
@@ -139,29 +64,6 @@ void parallel_for(int n, int nthr, F f) {
     });
   for (auto& x : th) x.join();
   if (!errs.empty()) throw errs.front();
-}
-
-template <class T>
-std::vector<T> to_host(const T* ptr, size_t cnt) {
-  std::vector<T> v(cnt);
-  if (cnt == 0) return v;
-  REQUIRE(ptr != nullptr, "null array argument");
-  if (is_device_ptr(ptr)) {
-    HIPCHK(hipMemcpy(v.data(), ptr, cnt * sizeof(T), hipMemcpyDeviceToHost));
-  } else {
-    std::memcpy(v.data(), ptr, cnt * sizeof(T));
-  }
-  return v;
-}
-
-// device copy owned by the context (from host or device source)
-template <class T>
-void to_device(DVec<T>& dst, const T* src, size_t cnt, hipStream_t s) {
-  dst.alloc(cnt);
-  if (!cnt) return;
-  REQUIRE(src != nullptr, "null array argument");
-  HIPCHK(hipMemcpyAsync(dst.p, src, cnt * sizeof(T),
-                        is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
 }
 
 // ---------------------------------------------------------------------------
@@ -320,6 +222,8 @@ struct FineLevel {
   DVec<double> Dband, LDc, LDr;
   DVec<float> LDc32, LDr32;  // single-precision mode: factor of diag(sc) A_i diag(sc)
   DVec<int32_t> seed_id;     // index of the subdomain within its problem (start blocks)
+  std::vector<int32_t> h_wpos;  // warm-start frame position per Neumann row (-1 = none)
+  DVec<int32_t> wpos;
   DVec<double> dscale;       // sc per Dirichlet dof (single-precision mode)
   int nd_max = 0, bd_max = 0, bw_max = 0, nb_max = 0;
   // sums used for the algorithmic byte / flop counts of the profiler
@@ -376,7 +280,8 @@ enum ProfId {
   PR_APPLY_COARSE,  // coarse-level solves, restriction, prolongation
   PR_APPLY_GATHER,  // finest-level prolongation + gather
   PR_APPLY_RESTRICT,  // finest-level gather of r + restriction to level L-1
-  PR_COARSE_GEVP,     // coarse-level GEVPs on the generating systems (Jacobi)
+  PR_COARSE_GEVP,     // coarse-level GEVPs on the generating systems
+  PR_WARM,            // warm-start network inference (BF16 matrix cores)
   PR_OTHER,
   PR_COUNT
 };
@@ -385,7 +290,7 @@ const char* kProfNames[PR_COUNT] = {
     "neumann_assemble", "dirichlet_extract", "band_cholesky", "eig_band_solve",
     "eig_bapply", "eig_gram", "eig_rayleigh_ritz", "eig_update", "patch", "coarse",
     "spmv", "pcg_vector", "apply_fine_solve", "apply_coarse", "apply_fine_gather",
-    "apply_fine_restrict", "coarse_gevp", "other"};
+    "apply_fine_restrict", "coarse_gevp", "warm_infer", "other"};
 
 struct Profiler {
   bool on = false;
@@ -484,6 +389,19 @@ struct msdd_ctx {
   std::vector<double> hist;  // ||r_k|| / ||r_0||, k = 0..iters, of the last solve
   Profiler prof;
   int eig_active = 0;  // subdomains running in the eigensolver (last status read)
+  // learned warm start (attached with msdd_warm_start for the next setup)
+  struct Warm {
+    msdd_net* net = nullptr;
+    int P = 0;  // 0 = detached
+    int n_in = 0, n_pos = 0, m_cap = 0;
+    int64_t n_entries = 0;
+    DVec<float> x;              // P x n_in features
+    std::vector<int32_t> pos;   // frame position per sub_dof entry
+    DVec<float> tgt, mask;      // collected training targets of the last setup
+    DVec<int> cnt;
+    bool have_targets = false;
+  } warm;
+  std::vector<int32_t> eig_iters;  // per finest-level subdomain, last setup
   ~msdd_ctx() {
     if (h_segI) (void)hipHostFree(h_segI);
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -556,6 +474,7 @@ struct ProfScope {
 struct SubPlan {
   std::vector<double> dv;            // PoU weight per Neumann dof (0 off the Dirichlet set)
   std::vector<int32_t> dpos, dglob;  // Dirichlet dofs: local Neumann index, global dof
+  std::vector<int32_t> wpos;         // warm-start frame position per Neumann dof
   std::vector<int32_t> ell_ptr, ell_col;  // local CSR of the Neumann matrix pattern
   int nD = 0, bd = 0, rankb = 0, ell_w = 0;
   std::string err;
@@ -564,7 +483,7 @@ struct SubPlan {
 void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
                const std::vector<int64_t>& sep, const std::vector<int32_t>& se,
                const std::vector<int64_t>& sdp, const std::vector<int32_t>& sd,
-               const std::vector<double>& sw) {
+               const std::vector<double>& sw, const std::vector<int32_t>* wp) {
   FineLevel& F = c->F;
   const int k = c->k;
   const int64_t n = c->n;
@@ -597,18 +516,28 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
       S.err = "sub_dof of subdomain " + std::to_string(i) + " is not the set of free dofs of its elements";
       return;
     }
-    std::vector<std::pair<int32_t, double>> dw((size_t)nd_in);
-    for (int64_t q = 0; q < nd_in; ++q) dw[q] = {sd[sdp[i] + q], sw[sdp[i] + q]};
-    std::sort(dw.begin(), dw.end());
+    struct DofW {
+      int32_t d;
+      double w;
+      int32_t p;
+    };
+    std::vector<DofW> dw((size_t)nd_in);
+    for (int64_t q = 0; q < nd_in; ++q)
+      dw[q] = {sd[sdp[i] + q], sw[sdp[i] + q], wp ? (*wp)[sdp[i] + q] : -1};
+    std::sort(dw.begin(), dw.end(), [](const DofW& a, const DofW& b) {
+      return a.d < b.d || (a.d == b.d && a.w < b.w);
+    });
     const int nb = (int)g.dofs.size();
     std::vector<int32_t> dloc(nb, -1);
     S.dv.resize(nb);
+    S.wpos.resize(nb);
     for (int r = 0; r < nb; ++r) {
-      if (dw[r].first != g.dofs[r]) {
+      S.wpos[r] = dw[r].p;
+      if (dw[r].d != g.dofs[r]) {
         S.err = "sub_dof of subdomain " + std::to_string(i) + " is not the set of free dofs of its elements";
         return;
       }
-      const double w = dw[r].second;
+      const double w = dw[r].w;
       if (!std::isfinite(w)) {
         S.err = "non-finite partition-of-unity weight";
         return;
@@ -662,6 +591,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   vlog(c, "plan: subdomain groups (parallel)", &tv);
   // merge in subdomain order
   F.h_dv.clear();
+  F.h_wpos.clear();
   F.h_nd.assign(P, 0);
   F.h_bd.assign(P, 0);
   F.h_rankb.assign(P, 0);
@@ -676,6 +606,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
     const GroupPlan& g = F.plans[i];
     const SubPlan& S = sp[i];
     F.h_dv.insert(F.h_dv.end(), S.dv.begin(), S.dv.end());
+    F.h_wpos.insert(F.h_wpos.end(), S.wpos.begin(), S.wpos.end());
     for (size_t r = 0; r < g.dofs.size(); ++r) pou_sum[g.dofs[r]] += S.dv[r];
     for (int32_t d : S.dglob) dcount[d]++;
     F.h_dpos.insert(F.h_dpos.end(), S.dpos.begin(), S.dpos.end());
@@ -720,6 +651,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   hipStream_t s = c->stream;
   build_groupset(F.plans, F.elems, k, F.gs, s);
   F.dv.upload(F.h_dv, s);
+  F.wpos.upload(F.h_wpos, s);
   F.h_boff.assign(P + 1, 0);
   for (int i = 0; i < P; ++i)
     F.h_boff[i + 1] = F.h_boff[i] + (int64_t)F.plans[i].dofs.size() * (F.plans[i].bw + 1);
@@ -851,6 +783,23 @@ void fine_eigensolve(msdd_ctx* c) {
   int restarts = 0, max_it = 0;
   double res_max = 0.0;
   F.lam.assign(P, {});
+  // learned warm start: the network's block for every subdomain (BF16 inference)
+  msdd_net* net = c->warm.P > 0 ? c->warm.net : nullptr;
+  const int n_vec = net ? msdd_net_internal::n_vec(net) : 0;
+  const int n_pos = c->warm.P > 0 ? c->warm.n_pos : 0;
+  DVec<float> yw;
+  std::vector<int> warm_ok(P, net ? 1 : 0);
+  if (net) {
+    yw.alloc((size_t)P * n_vec * n_pos);
+    const double ni = msdd_net_internal::n_in(net), nh = msdd_net_internal::n_hidden(net);
+    const double no = (double)n_vec * n_pos;
+    // bytes: BF16 weights once + features in + FP32 block out; flops: 2 per multiply-add
+    ProfScope ps(c, PR_WARM, 2.0 * (ni * nh + nh * nh + nh * no) + 4.0 * P * (ni + no),
+                 2.0 * P * (ni * nh + nh * nh + nh * no));
+    msdd_net_internal::infer(net, P, c->warm.x.p, yw.p, s);
+  }
+  std::vector<int> iters_tot(P, 0);
+  int fallbacks = 0;
   while (true) {
     int nwant = 0;
     for (int i = 0; i < P; ++i) nwant += want[i];
@@ -888,8 +837,16 @@ void fine_eigensolve(msdd_ctx* c) {
     status.upload(st0, s);
     iters.alloc(P);
     iters.zero(s);
-    launch_eig_init(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K, F.dv.p,
-                    E.X.p, 0x5eed5eedull + (unsigned long long)K, F.seed_id.p);
+    DVec<int> dwarm;
+    if (net) {
+      dwarm.upload(warm_ok, s);
+      launch_eig_init_warm(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K,
+                           F.dv.p, E.X.p, 0x5eed5eedull + (unsigned long long)K, F.seed_id.p,
+                           dwarm.p, yw.p, n_vec, n_pos, F.wpos.p);
+    } else {
+      launch_eig_init(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K,
+                      F.dv.p, E.X.p, 0x5eed5eedull + (unsigned long long)K, F.seed_id.p);
+    }
     launch_bapply_ell(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K,
                       F.dv.p, F.ell_w, F.ell_col.p, F.ell_val.p, E.X.p, BX.p, status.p);
     const int maxit = o.eig_maxit;
@@ -938,14 +895,24 @@ void fine_eigensolve(msdd_ctx* c) {
     std::vector<int> itv = iters.download(s);
     std::vector<double> lamv = E.lam.download(s);
     std::vector<double> resv = E.res.download(s);
-    bool grew = false;
+    bool grew = false, fell = false;
     for (int i = 0; i < P; ++i) {
       if (!want[i]) continue;
       max_it = std::max(max_it, itv[i]);
+      iters_tot[i] += itv[i];
       if (st[i] == ST_GROW && K < 64) {
         grew = true;
         ++restarts;
         continue;  // stays wanted for the next pass
+      }
+      if (warm_ok[i] && st[i] != ST_DONE) {
+        // the warm-started iteration did not converge: solve again from the random start
+        warm_ok[i] = 0;
+        fell = true;
+        ++fallbacks;
+        if (c->opt.verbose)
+          std::fprintf(stderr, "msdd: subdomain %d warm start not converged, cold restart\n", i);
+        continue;
       }
       if (st[i] == ST_RUNNING || st[i] == ST_NOCONV || st[i] == ST_GROW) {
         // iteration limit: accept the current Ritz pairs and report the residual
@@ -961,8 +928,8 @@ void fine_eigensolve(msdd_ctx* c) {
       for (int a = 0; a < std::min(K, mc[i] + 1); ++a) res_max = std::max(res_max, resv[(size_t)i * K + a]);
     }
     passes.push_back(std::move(ps));
-    if (!grew) break;
-    K *= 2;
+    if (!grew && !fell) break;
+    if (grew) K *= 2;
   }
   // pooled basis blocks
   F.m = final_m;
@@ -986,6 +953,15 @@ void fine_eigensolve(msdd_ctx* c) {
   F.phid_off.upload(F.h_phid_off, s);
   F.moff.upload(F.h_moff, s);
   F.dm.upload(F.m, s);
+  const int m_cap = c->warm.P > 0 ? c->warm.m_cap : 0;
+  if (m_cap > 0) {
+    c->warm.tgt.alloc((size_t)P * m_cap * n_pos);
+    c->warm.mask.alloc((size_t)P * n_pos);
+    c->warm.cnt.alloc(P);
+    c->warm.tgt.zero(s);
+    c->warm.mask.zero(s);
+    c->warm.cnt.zero(s);
+  }
   for (size_t pi = 0; pi < passes.size(); ++pi) {
     EigPass& E = *passes[pi];
     std::vector<int> mm(P, 0);
@@ -999,8 +975,23 @@ void fine_eigensolve(msdd_ctx* c) {
                         E.mcount.p, F.phi_off.p, F.Phi.p, F.nd.p, F.doff.p, F.dpos.p,
                         F.phid_off.p, F.PhiD.p);
     HIPCHK(hipGetLastError());
+    if (m_cap > 0 && !E.subs.empty()) {
+      DVec<int> sel;
+      sel.upload(E.subs, s);
+      launch_warm_targets(s, (int)E.subs.size(), sel.p, F.gs.n.p, F.gs.voff.p, dkvoff.p, E.K,
+                          E.X.p, E.mcount.p, m_cap, n_pos, F.wpos.p, c->warm.tgt.p,
+                          c->warm.mask.p, c->warm.cnt.p);
+      HIPCHK(hipGetLastError());
+    }
     HIPCHK(hipStreamSynchronize(s));
   }
+  c->warm.have_targets = m_cap > 0;
+  c->eig_iters = iters_tot;
+  int64_t isum = 0;
+  for (int v : iters_tot) isum += v;
+  c->stats.eig_iters_sum = isum;
+  c->stats.warm_started = net ? P : 0;
+  c->stats.warm_fallbacks = fallbacks;
   c->stats.eig_iters_max = max_it;
   c->stats.eig_restarts = restarts;
   c->stats.eig_resid_max = res_max;
@@ -1787,7 +1778,18 @@ int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     // finest level
     c->F = FineLevel();
     c->F.P = n_sub;
-    plan_fine(c, n_elem, ed, sep, se, sdp, sd, sw);
+    const std::vector<int32_t>* wp = nullptr;
+    if (c->warm.P > 0) {
+      REQUIRE(c->warm.P == n_sub, "warm start attached for " + std::to_string(c->warm.P) +
+                                      " subdomains, setup has " + std::to_string(n_sub));
+      REQUIRE(c->warm.n_entries == sdp[n_sub], "warm start frame positions do not match sub_dof");
+      if (c->warm.net)
+        REQUIRE(msdd_net_internal::device(c->warm.net) == c->opt.device,
+                "warm-start network lives on another device");
+      wp = &c->warm.pos;
+    }
+    c->warm.have_targets = false;
+    plan_fine(c, n_elem, ed, sep, se, sdp, sd, sw, wp);
     {
       std::vector<int32_t> sid(n_sub);
       for (int i = 0, first = 0; i < n_sub; ++i) {
@@ -2104,6 +2106,88 @@ int msdd_solve_history(const msdd_ctx* c, double* relres, int32_t cap, int32_t* 
 int msdd_stats(const msdd_ctx* c, msdd_stats_t* out) {
   if (!c || !out) return MSDD_EINVAL;
   *out = c->stats;
+  return MSDD_OK;
+}
+
+int msdd_get_eig_iters(const msdd_ctx* c, int32_t* iters) {
+  if (!c || !iters) return MSDD_EINVAL;
+  if (!c->ready) return MSDD_ESTATE;
+  msdd_ctx* cc = const_cast<msdd_ctx*>(c);
+  try {
+    HIPCHK(hipSetDevice(c->opt.device));
+    const size_t P = c->eig_iters.size();
+    HIPCHK(hipMemcpy(iters, c->eig_iters.data(), P * sizeof(int32_t),
+                     is_device_ptr(iters) ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+  } catch (const MsddError& e) {
+    return code_for(cc, e);
+  }
+  return MSDD_OK;
+}
+
+int msdd_warm_start(msdd_ctx* c, msdd_net* net, int32_t n_sub, int32_t n_in, const float* x,
+                    int64_t n_entries, const int32_t* sub_pos, int32_t n_pos, int32_t collect) {
+  if (!c) return MSDD_EINVAL;
+  try {
+    HIPCHK(hipSetDevice(c->opt.device));
+    auto& W = c->warm;
+    if (n_sub == 0) {  // detach
+      W.net = nullptr;
+      W.P = 0;
+      W.pos.clear();
+      W.x.release();
+      W.m_cap = 0;
+      return MSDD_OK;
+    }
+    REQUIRE(n_sub > 0 && n_entries >= 0 && n_pos >= 1, "bad warm-start sizes");
+    REQUIRE(collect >= 0 && collect <= 16, "collect must lie in [0, 16]");
+    REQUIRE(net || collect > 0, "a warm start needs a network or collect > 0");
+    if (net) {
+      REQUIRE(msdd_net_internal::n_in(net) == n_in, "feature count differs from the network's n_in");
+      REQUIRE(msdd_net_internal::n_pos(net) == n_pos, "frame size differs from the network's n_pos");
+    }
+    std::vector<int32_t> pos = to_host(sub_pos, (size_t)n_entries);
+    for (int32_t v : pos) REQUIRE(v >= -1 && v < n_pos, "frame position out of range");
+    if (net) {
+      REQUIRE(n_in >= 1, "n_in must be positive");
+      to_device(W.x, x, (size_t)n_sub * n_in, c->stream);
+      HIPCHK(hipStreamSynchronize(c->stream));
+    } else {
+      W.x.release();
+    }
+    W.net = net;
+    W.P = n_sub;
+    W.n_in = n_in;
+    W.n_pos = n_pos;
+    W.m_cap = collect;
+    W.n_entries = n_entries;
+    W.pos = std::move(pos);
+  } catch (const MsddError& e) {
+    return code_for(c, e);
+  }
+  return MSDD_OK;
+}
+
+int msdd_warm_targets(const msdd_ctx* c, float* tgt, float* mask, int32_t* cnt) {
+  if (!c) return MSDD_EINVAL;
+  msdd_ctx* cc = const_cast<msdd_ctx*>(c);
+  if (!c->ready || !c->warm.have_targets) {
+    set_err(cc, "no training targets: run a setup with collect > 0 first");
+    return MSDD_ESTATE;
+  }
+  try {
+    HIPCHK(hipSetDevice(c->opt.device));
+    REQUIRE(tgt && mask && cnt, "null output array");
+    const auto& W = c->warm;
+    auto cp = [&](void* dst, const void* src, size_t bytes) {
+      HIPCHK(hipMemcpy(dst, src, bytes,
+                       is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    };
+    cp(tgt, W.tgt.p, W.tgt.n * sizeof(float));
+    cp(mask, W.mask.p, W.mask.n * sizeof(float));
+    cp(cnt, W.cnt.p, W.cnt.n * sizeof(int));
+  } catch (const MsddError& e) {
+    return code_for(cc, e);
+  }
   return MSDD_OK;
 }
 
