@@ -124,11 +124,13 @@ template <typename V, int TR>
 __global__ void k_gram(const i32* __restrict__ nb, const i64* __restrict__ kvoff, int K,
                        const V* __restrict__ Y, const V* __restrict__ W, const V* __restrict__ Z,
                        double* __restrict__ GS, double* __restrict__ GB,
-                       const int* __restrict__ active) {
+                       const int* __restrict__ active, int S) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int i = blockIdx.x;
+  const int i = blockIdx.x, sp = blockIdx.y;  // subdomain, row split
   if (active && active[i] != ST_RUNNING) return;
   const int n = nb[i];
+  const int chunk = ((n + S - 1) / S + TR - 1) / TR * TR;
+  const int r_lo = sp * chunk, r_hi = min(n, r_lo + chunk);
   V* ty = reinterpret_cast<V*>(smem_raw);
   V* tw = ty + TR * K;
   V* tz = tw + TR * K;
@@ -139,8 +141,8 @@ __global__ void k_gram(const i32* __restrict__ nb, const i64* __restrict__ kvoff
   constexpr int MAXP = 16;  // K <= 64 -> K*K/256 <= 16 pairs per thread
   double as[MAXP], ab[MAXP];
   for (int u = 0; u < MAXP; ++u) as[u] = ab[u] = 0.0;
-  for (int r0 = 0; r0 < n; r0 += TR) {
-    const int rn = min(TR, n - r0);
+  for (int r0 = r_lo; r0 < r_hi; r0 += TR) {
+    const int rn = min(TR, r_hi - r0);
     __syncthreads();
     for (int t = threadIdx.x; t < TR * K; t += blockDim.x) {
       const int c = t / TR, rr = t % TR;
@@ -169,10 +171,12 @@ __global__ void k_gram(const i32* __restrict__ nb, const i64* __restrict__ kvoff
       ab[u] += s2;
     }
   }
+  // partial Gram matrices of this row split (an empty split writes zeros)
   int u = 0;
+  const i64 o = ((i64)i * S + sp) * KK;
   for (int t = threadIdx.x; t < KK; t += blockDim.x, ++u) {
-    GS[(i64)i * KK + t] = as[u];
-    GB[(i64)i * KK + t] = ab[u];
+    GS[o + t] = as[u];
+    GB[o + t] = ab[u];
   }
 }
 
@@ -182,7 +186,8 @@ __global__ void k_gram(const i32* __restrict__ nb, const i64* __restrict__ kvoff
 // column); the projected standard problem is solved by cyclic Jacobi.
 __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
                                 const double* __restrict__ GB, double* __restrict__ Cout,
-                                double* __restrict__ nu_out, const int* __restrict__ active) {
+                                double* __restrict__ nu_out, const int* __restrict__ active,
+                                int nsplit) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = blockIdx.x;
   if (active && active[i] != ST_RUNNING) return;
@@ -195,16 +200,27 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
   double* wsp = ev + K;                              // 4K (eigensolver workspace)
   int* ord = reinterpret_cast<int*>(wsp + 4 * K);    // K
   const int tid = threadIdx.x, nt = blockDim.x;
-  const double* gs = GS + (i64)i * KK;
-  const double* gb = GB + (i64)i * KK;
+  // G_S and G_B arrive as nsplit partial sums over row splits
+  const double* gs = GS + (i64)i * nsplit * KK;
+  const double* gb = GB + (i64)i * nsplit * KK;
+  for (int t = tid; t < KK; t += nt) {
+    double a = 0.0;
+    for (int q = 0; q < nsplit; ++q) a += gs[(i64)q * KK + t];
+    S[t] = a;
+  }
+  __syncthreads();
   for (int t = tid; t < K; t += nt) {
-    const double dgs = gs[t * K + t];
+    const double dgs = S[t * K + t];
     sc[t] = dgs > 0 ? 1.0 / sqrt(dgs) : 0.0;
   }
   __syncthreads();
-  for (int t = tid; t < KK; t += nt) {
+  for (int t = tid; t < KK; t += nt) {  // symmetrise and scale (each pair by one thread)
     const int a = t / K, b = t % K;
-    S[t] = 0.5 * (gs[a * K + b] + gs[b * K + a]) * sc[a] * sc[b];
+    if (a <= b) {
+      const double v = 0.5 * (S[a * K + b] + S[b * K + a]) * sc[a] * sc[b];
+      S[a * K + b] = v;
+      S[b * K + a] = v;
+    }
   }
   __syncthreads();
   // scaled G_S = L L^T by a Cholesky factorisation that drops dependent columns: a
@@ -247,11 +263,26 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
     U[t] = sc[r] * M[a * K + r];
   }
   __syncthreads();
-  // M = T^T GB T: first S <- GB_sym T (K x K), then M = T^T S
+  // M = T^T GB T: GB (summed, symmetrised) into M, then S <- GB T, then M = T^T S
+  for (int t = tid; t < KK; t += nt) {
+    double a = 0.0;
+    for (int q = 0; q < nsplit; ++q) a += gb[(i64)q * KK + t];
+    M[t] = a;
+  }
+  __syncthreads();
+  for (int t = tid; t < KK; t += nt) {
+    const int a = t / K, b = t % K;
+    if (a < b) {
+      const double v = 0.5 * (M[a * K + b] + M[b * K + a]);
+      M[a * K + b] = v;
+      M[b * K + a] = v;
+    }
+  }
+  __syncthreads();
   for (int t = tid; t < KK; t += nt) {
     const int r = t / K, a = t % K;
     double acc = 0;
-    for (int q = 0; q < K; ++q) acc += 0.5 * (gb[r * K + q] + gb[q * K + r]) * U[q * K + a];
+    for (int q = 0; q < K; ++q) acc += M[r * K + q] * U[q * K + a];
     S[t] = acc;
   }
   __syncthreads();
@@ -305,22 +336,19 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
                              const double* __restrict__ Cm, const double* __restrict__ nu,
                              const V* __restrict__ Y, const V* __restrict__ Z,
                              V* __restrict__ X, V* __restrict__ BX, V* __restrict__ SX,
-                             double sigma, double eta, int nev_max, double tol, int maxit,
-                             int* __restrict__ status, int* __restrict__ iters,
-                             int* __restrict__ mcount, double* __restrict__ lam_out,
-                             double* __restrict__ res_out, int Kmax_allowed,
-                             const i32* __restrict__ rankb, const double* __restrict__ normS,
-                             double* __restrict__ nu_prev) {
+                             const int* __restrict__ status, double* __restrict__ part, int S) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int i = blockIdx.x;
+  const int i = blockIdx.x, sp = blockIdx.y;  // subdomain, row split
   if (status[i] != ST_RUNNING) return;
   const int n = nb[i];
+  const int chunk = ((n + S - 1) / S + TR - 1) / TR * TR;
+  const int r_lo = sp * chunk, r_hi = min(n, r_lo + chunk);
   const int KK = K * K;
   double* C = reinterpret_cast<double*>(smem_raw);  // KK
   V* ty = reinterpret_cast<V*>(C + KK);             // TR*K
   V* tz = ty + TR * K;
   V* tb = tz + TR * K;
-  __shared__ double red_r[MSDD_WG], red_s[MSDD_WG], sh_res[64], sh_lam[64], sh_stag[64];
+  __shared__ double red_r[MSDD_WG], red_s[MSDD_WG];
   const int tid = threadIdx.x;
   for (int t = tid; t < KK; t += blockDim.x) C[t] = Cm[(i64)i * KK + t];
   const int c = tid % K;
@@ -333,8 +361,8 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
   V* Xi = X + kvoff[i];
   V* Bi = BX + kvoff[i];
   V* Si = SX + kvoff[i];
-  for (int r0 = 0; r0 < n; r0 += TR) {
-    const int rn = min(TR, n - r0);
+  for (int r0 = r_lo; r0 < r_hi; r0 += TR) {
+    const int rn = min(TR, r_hi - r0);
     __syncthreads();
     for (int t = tid; t < TR * K; t += blockDim.x) {
       const int cc = t / TR, rr = t % TR;
@@ -372,11 +400,37 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
   red_r[tid] = accr;
   red_s[tid] = accs;
   __syncthreads();
-  if (tid < K) {
+  if (tid < K) {  // partial residual^2 and ||x||^2 of this row split, per column
     double sr = 0, ss = 0;
     for (int l = 0; l < lanes; ++l) {
       sr += red_r[l * K + tid];
       ss += red_s[l * K + tid];
+    }
+    const i64 o = ((i64)i * S + sp) * 2 * K;
+    part[o + tid] = sr;
+    part[o + K + tid] = ss;
+  }
+}
+
+// Convergence decision of each running subdomain (one wavefront): sums the row-split
+// partials of k_eig_update, then the backward errors, Ritz values, count m and status.
+__global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* __restrict__ part,
+                            int S, double sigma, double eta, int nev_max, double tol, int maxit,
+                            int* __restrict__ status, int* __restrict__ iters,
+                            int* __restrict__ mcount, double* __restrict__ lam_out,
+                            double* __restrict__ res_out, int Kmax_allowed,
+                            const i32* __restrict__ rankb, const double* __restrict__ normS,
+                            double* __restrict__ nu_prev) {
+  const int i = blockIdx.x;
+  if (status[i] != ST_RUNNING) return;
+  __shared__ double sh_res[64], sh_lam[64], sh_stag[64];
+  const int tid = threadIdx.x;
+  if (tid < K) {
+    double sr = 0, ss = 0;
+    for (int q = 0; q < S; ++q) {
+      const i64 o = ((i64)i * S + q) * 2 * K;
+      sr += part[o + tid];
+      ss += part[o + K + tid];
     }
     const double nv = nu[(i64)i * K + tid];
     const double rel = (nv > 0 && ss > 0) ? sqrt(sr) / (nv * normS[i] * sqrt(ss)) : 0.0;
@@ -495,22 +549,23 @@ void launch_bapply_ell(hipStream_t s, i64 total_rows, const i32* row_sub, const 
 }
 
 void launch_gram(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K, const double* Y,
-                 const double* W, const double* Z, double* GS, double* GB, const int* active) {
+                 const double* W, const double* Z, double* GS, double* GB, const int* active,
+                 int nsplit) {
   constexpr int TR = 32;
   size_t lds = 3 * TR * K * sizeof(double);
-  hipLaunchKernelGGL((k_gram<double, TR>), dim3(P), dim3(MSDD_WG), lds, s, nb, kvoff, K, Y, W,
-                     Z, GS, GB, active);
+  hipLaunchKernelGGL((k_gram<double, TR>), dim3(P, nsplit), dim3(MSDD_WG), lds, s, nb, kvoff, K,
+                     Y, W, Z, GS, GB, active, nsplit);
 }
 
 void launch_rayleigh_ritz(hipStream_t s, int P, int K, const double* GS, const double* GB,
-                          double* C, double* nu, const int* active) {
+                          double* C, double* nu, const int* active, int nsplit) {
   size_t lds = (3 * (size_t)K * K + 6 * K) * sizeof(double) + K * sizeof(int) + 16;
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   // one wave per subdomain for K = 16 (the Jacobi rounds update K^2/4 blocks), four above
   const int nt = K <= 16 ? 64 : 256;
-  hipLaunchKernelGGL(k_rayleigh_ritz, dim3(P), dim3(nt), lds, s, K, GS, GB, C, nu, active);
+  hipLaunchKernelGGL(k_rayleigh_ritz, dim3(P), dim3(nt), lds, s, K, GS, GB, C, nu, active, nsplit);
 }
 
 void launch_row_norm(hipStream_t s, int P, const i64* voff, int ell_w, const i32* ell_col,
@@ -524,12 +579,14 @@ void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, in
                        double* X, double* BX, double* SX, double sigma, double eta, int nev_max,
                        double tol, int maxit, int* status, int* iters, int* mcount,
                        double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
-                       const double* normS, double* nu_prev) {
+                       const double* normS, double* nu_prev, double* part, int nsplit) {
   constexpr int TR = 16;
   size_t lds = (size_t)K * K * sizeof(double) + 3 * TR * K * sizeof(double);
-  hipLaunchKernelGGL((k_eig_update<double, TR>), dim3(P), dim3(MSDD_WG), lds, s, nb, kvoff, K, C,
-                     nu, Y, Z, X, BX, SX, sigma, eta, nev_max, tol, maxit, status, iters, mcount,
-                     lam_out, res_out, Kmax_allowed, rankb, normS, nu_prev);
+  hipLaunchKernelGGL((k_eig_update<double, TR>), dim3(P, nsplit), dim3(MSDD_WG), lds, s, nb, kvoff,
+                     K, C, nu, Y, Z, X, BX, SX, status, part, nsplit);
+  hipLaunchKernelGGL(k_eig_judge, dim3(P), dim3(64), 0, s, K, nu, part, nsplit, sigma, eta,
+                     nev_max, tol, maxit, status, iters, mcount, lam_out, res_out, Kmax_allowed,
+                     rankb, normS, nu_prev);
 }
 
 void launch_eig_finalize(hipStream_t s, int P, const i32* nb, const i64* voff, const i64* kvoff,

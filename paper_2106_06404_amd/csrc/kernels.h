@@ -47,16 +47,18 @@ void launch_bapply_ell(hipStream_t s, i64 total_rows, const i32* row_sub, const 
                        const i32* nb, const i64* kvoff, int K, const double* dv, int ell_w,
                        const i32* ell_col, const double* ell_val, const double* Y, double* Z,
                        const int* active);
+// Gram matrices as nsplit partial sums over row splits (GS, GB: P x nsplit x K x K)
 void launch_gram(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K, const double* Y,
-                 const double* W, const double* Z, double* GS, double* GB, const int* active);
+                 const double* W, const double* Z, double* GS, double* GB, const int* active,
+                 int nsplit);
 void launch_rayleigh_ritz(hipStream_t s, int P, int K, const double* GS, const double* GB,
-                          double* C, double* nu, const int* active);
+                          double* C, double* nu, const int* active, int nsplit);
 void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K,
                        const double* C, const double* nu, const double* Y, const double* Z,
                        double* X, double* BX, double* SX, double sigma, double eta, int nev_max,
                        double tol, int maxit, int* status, int* iters, int* mcount,
                        double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
-                       const double* normS, double* nu_prev);
+                       const double* normS, double* nu_prev, double* part, int nsplit);
 void launch_row_norm(hipStream_t s, int P, const i64* voff, int ell_w, const i32* ell_col,
                      const double* ell_val, const double* dv, double sigma, double* normS);
 void launch_eig_finalize(hipStream_t s, int P, const i32* nb, const i64* voff, const i64* kvoff,

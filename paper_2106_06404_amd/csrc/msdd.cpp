@@ -812,14 +812,17 @@ void fine_eigensolve(msdd_ctx* c) {
     DVec<int64_t> dkvoff;
     dkvoff.upload(kvoff, s);
     const size_t tot = kvoff.back();
-    DVec<double> BX, Y, Z, SX, GS, GB, Cm;
+    DVec<double> BX, Y, Z, SX, GS, GB, Cm, upart;
+    // row splits per subdomain of the Gram and update kernels (about 192 rows each)
+    const int nsplit = std::max(1, std::min(8, (F.nb_max + 191) / 192));
     E.X.alloc(tot);
     BX.alloc(tot);
     Y.alloc(tot);
     Z.alloc(tot);
     SX.alloc(tot);
-    GS.alloc((size_t)P * K * K);
-    GB.alloc((size_t)P * K * K);
+    GS.alloc((size_t)P * nsplit * K * K);
+    GB.alloc((size_t)P * nsplit * K * K);
+    upart.alloc((size_t)P * nsplit * 2 * K);
     Cm.alloc((size_t)P * K * K);
     E.nu.alloc((size_t)P * K);
     E.lam.alloc((size_t)P * K);
@@ -869,17 +872,18 @@ void fine_eigensolve(msdd_ctx* c) {
       }
       {
         ProfScope ps(c, PR_EIG_GRAM, f * 3.0 * F.s_nb * K * 8.0, f * 4.0 * F.s_nb * K * K);
-        launch_gram(s, P, F.gs.n.p, dkvoff.p, K, Y.p, BX.p, Z.p, GS.p, GB.p, status.p);
+        launch_gram(s, P, F.gs.n.p, dkvoff.p, K, Y.p, BX.p, Z.p, GS.p, GB.p, status.p, nsplit);
       }
       {
         ProfScope ps(c, PR_EIG_RR, c->eig_active * 3.0 * K * K * 8.0, 0.0);
-        launch_rayleigh_ritz(s, P, K, GS.p, GB.p, Cm.p, E.nu.p, status.p);
+        launch_rayleigh_ritz(s, P, K, GS.p, GB.p, Cm.p, E.nu.p, status.p, nsplit);
       }
       {
         ProfScope ps(c, PR_EIG_UPDATE, f * 6.0 * F.s_nb * K * 8.0, f * 6.0 * F.s_nb * K * K);
         launch_eig_update(s, P, F.gs.n.p, dkvoff.p, K, Cm.p, E.nu.p, Y.p, Z.p, E.X.p, BX.p, SX.p,
                           c->sigma, c->eta, o.nev_max, o.eig_tol, maxit, status.p, iters.p,
-                          E.mcount.p, E.lam.p, E.res.p, 64, F.rankb.p, normS.p, nu_prev.p);
+                          E.mcount.p, E.lam.p, E.res.p, 64, F.rankb.p, normS.p, nu_prev.p,
+                          upart.p, nsplit);
       }
       HIPCHK(hipGetLastError());
       if (it >= 3 && (it % 2 == 1 || it == maxit - 1)) {
