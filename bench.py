@@ -259,6 +259,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the launch shapes chosen by problem shape (no msdd_autotune)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start leg (training + warm-started steps)")
     ap.add_argument("--verbose", action="store_true")
@@ -311,6 +313,12 @@ def main():
 
         for _ in range(args.warmup):
             step(False)
+        tuning = None
+        if not args.no_autotune:
+            # launch shapes timed on this context's data (one-off, outside the timed steps),
+            # then one more untimed step so that the timed ones run the tuned shapes
+            tuning = ctx.autotune(reps=5)
+            step(False)
         torch.cuda.synchronize()
         ctx.profile(True)
         ctx.profile(False)
@@ -344,7 +352,7 @@ def main():
         xh = x.cpu().numpy()
         true_rel = float(np.linalg.norm(prob.b - prob.A @ xh) / np.linalg.norm(prob.b))
         return dict(ms_per_step=(t1 - t0) * 1e3 / args.steps, prof=prof, st=st, iters=iters,
-                    setup_ms=setup_ms, solve_ms=solve_ms, true_rel=true_rel)
+                    setup_ms=setup_ms, solve_ms=solve_ms, true_rel=true_rel, tuning=tuning)
 
     r64 = measure(B.MSDD_FP64)
     r32 = measure(B.MSDD_MIXED)
@@ -378,6 +386,7 @@ def main():
         "local_gevps_per_s": n_gevp / gevp_s,
         "coarse_sizes": st["n"],
         "roofline": dict(rl_all[dom], kernel=dom),
+        "tuning": r64["tuning"],
         "roofline_by_kernel": {k: {"ms_per_step": prof[k][0],
                                    "launches_per_step": prof[k][1],
                                    "bound": r["bound"], "achieved": r["achieved"],

@@ -333,6 +333,43 @@ int msdd_warm_start(msdd_ctx* c, msdd_net* net, int32_t n_sub, int32_t n_in, con
  * tgt (n_sub x m_cap x n_pos), mask (n_sub x n_pos), cnt (n_sub); host or device. */
 int msdd_warm_targets(const msdd_ctx* c, float* tgt, float* mask, int32_t* cnt);
 
+/*
+ * ---------------------------------------------------------------------------
+ * Autotuner of launch shapes.
+ *
+ * msdd_autotune times the candidate launch shapes of the hot kernels on the data of
+ * the context's last setup (its factors, block sizes and matrix; scratch vectors) and
+ * keeps the fastest: solve-phase choices apply to the next msdd_solve / msdd_apply,
+ * setup-phase choices to the next setup.  Results do not depend on the choices beyond
+ * rounding (every candidate computes the same quantity).
+ *   what: MSDD_TUNE_EIG (finest-level eigensolver: band-solve variant, row splits of
+ *         the Gram and update kernels) | MSDD_TUNE_SOLVE (preconditioner apply: fine
+ *         band-solve variant; CG: lanes per CSR row of the SpMV);
+ *   reps: timed launches per candidate (1..100), after one untimed launch.
+ * MSDD_ESTATE before a setup.  The measured times per launch are in msdd_tuning_t.
+ * ---------------------------------------------------------------------------
+ */
+#define MSDD_TUNE_EIG 1
+#define MSDD_TUNE_SOLVE 2
+
+typedef struct {
+  int32_t eig_solve;      /* 0 = by shape; 1 = rolling window, 8 columns per workgroup;
+                             2 = rolling window, 16 columns; 3 = one wavefront per column */
+  int32_t eig_splits;     /* row splits per subdomain of the Gram / update kernels:
+                             0 = by size, else 1..16 */
+  int32_t fine_solve;     /* 0 = by shape; 1 = rolling window; 2 = one wavefront per subdomain */
+  int32_t spmv_group;     /* lanes per CSR row: 0 = by average row length, else 4, 8, 16, 32 */
+  float eig_solve_ms[4];  /* [v] for eig_solve = v (v = 1..3; 0 = not run or not applicable) */
+  float eig_splits_ms[5]; /* for 1, 2, 4, 8, 16 splits */
+  float fine_solve_ms[3]; /* [v] for fine_solve = v (v = 1, 2) */
+  float spmv_ms[4];       /* for 4, 8, 16, 32 lanes */
+} msdd_tuning_t;
+
+int msdd_autotune(msdd_ctx* c, int32_t what, int32_t reps);
+int msdd_get_tuning(const msdd_ctx* c, msdd_tuning_t* t);
+/* Set the choices (the *_ms fields are ignored); MSDD_EINVAL for values out of range. */
+int msdd_set_tuning(msdd_ctx* c, const msdd_tuning_t* t);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,21 @@ class MsddStats(ctypes.Structure):
         return d
 
 
+MSDD_TUNE_EIG = 1
+MSDD_TUNE_SOLVE = 2
+
+
+class MsddTuning(ctypes.Structure):
+    _fields_ = [("eig_solve", ctypes.c_int32), ("eig_splits", ctypes.c_int32),
+                ("fine_solve", ctypes.c_int32), ("spmv_group", ctypes.c_int32),
+                ("eig_solve_ms", ctypes.c_float * 4), ("eig_splits_ms", ctypes.c_float * 5),
+                ("fine_solve_ms", ctypes.c_float * 3), ("spmv_ms", ctypes.c_float * 4)]
+
+    def as_dict(self):
+        return {f: (list(getattr(self, f)) if f.endswith("_ms") else getattr(self, f))
+                for f, _ in self._fields_}
+
+
 EXPORTS = ["msdd_default_options", "msdd_create", "msdd_setup", "msdd_setup_batch", "msdd_solve",
            "msdd_solve_batch", "msdd_solve_history", "msdd_apply",
            "msdd_stats", "msdd_get_level_counts", "msdd_get_eigs", "msdd_get_basis",
@@ -65,7 +80,8 @@ EXPORTS = ["msdd_default_options", "msdd_create", "msdd_setup", "msdd_setup_batc
            "msdd_destroy", "msdd_get_eig_iters", "msdd_warm_start", "msdd_warm_targets",
            "msdd_net_create", "msdd_net_param_count", "msdd_net_set_params",
            "msdd_net_get_params", "msdd_net_forward", "msdd_net_grad", "msdd_net_train_step",
-           "msdd_net_last_error", "msdd_net_destroy"]
+           "msdd_net_last_error", "msdd_net_destroy", "msdd_autotune", "msdd_get_tuning",
+           "msdd_set_tuning"]
 MSDD_NPROF = 19
 
 _lib = None
@@ -157,6 +173,12 @@ def load():
     L.msdd_net_last_error.restype = ctypes.c_char_p
     L.msdd_net_destroy.argtypes = [vp]
     L.msdd_net_destroy.restype = None
+    L.msdd_autotune.argtypes = [vp, i32, i32]
+    L.msdd_autotune.restype = ctypes.c_int
+    L.msdd_get_tuning.argtypes = [vp, ctypes.POINTER(MsddTuning)]
+    L.msdd_get_tuning.restype = ctypes.c_int
+    L.msdd_set_tuning.argtypes = [vp, ctypes.POINTER(MsddTuning)]
+    L.msdd_set_tuning.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -313,6 +335,21 @@ class Msdd:
         mask (n_sub x n_pos float32) and cnt (n_sub int32)."""
         return self._check(self._L.msdd_warm_targets(self._h, _ptr(tgt, np.float32),
                                                      _ptr(mask, np.float32), _ptr(cnt, np.int32)))
+
+    def autotune(self, what=MSDD_TUNE_EIG | MSDD_TUNE_SOLVE, reps=5) -> dict:
+        """Time the candidate launch shapes on the last setup's data; keep the fastest."""
+        self._check(self._L.msdd_autotune(self._h, int(what), int(reps)))
+        return self.tuning()
+
+    def tuning(self) -> dict:
+        t = MsddTuning()
+        self._check(self._L.msdd_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, eig_solve=0, eig_splits=0, fine_solve=0, spmv_group=0):
+        t = MsddTuning(eig_solve=eig_solve, eig_splits=eig_splits, fine_solve=fine_solve,
+                       spmv_group=spmv_group)
+        return self._check(self._L.msdd_set_tuning(self._h, ctypes.byref(t)))
 
     def profile(self, enable=True, reset=True):
         """enable=True: reset (unless reset=False) and enable; False: pause, keeping counts."""

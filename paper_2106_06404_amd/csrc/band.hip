@@ -441,11 +441,16 @@ template <typename T, typename V>
 void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax,
                              const i32* n_arr, const i32* b_arr, const i64* l_off, const T* Fc,
                              const T* Fr, const i64* v_off, int K, const V* W, V* Y,
-                             const int* active, int bmax) {
+                             const int* active, int bmax, int variant) {
+  // variant: 0 = by shape (rolling window with 16 or 8 columns per workgroup when the
+  // half-bandwidth is below 64, else one wavefront per column), 1 = rolling window with 8
+  // columns, 2 = rolling window with 16 columns, 3 = one wavefront per column
   if (nsubs == 0 || K == 0) return;
-  if (bmax < 64) {
+  if (variant == 0) variant = bmax < 64 ? (K >= 16 ? 2 : 1) : 3;
+  if (bmax >= 64) variant = 3;  // the rolling window needs a half-bandwidth below 64
+  if (variant != 3) {
     const size_t lds = 2 * (size_t)ROT_TILE * sizeof(V);
-    if (K >= 16) {
+    if (variant == 2) {
       (void)hipFuncSetAttribute((const void*)k_band_solve_rot<T, V, 16>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       hipLaunchKernelGGL((k_band_solve_rot<T, V, 16>), dim3(nsubs, (K + 15) / 16), dim3(1024), lds,
@@ -469,8 +474,8 @@ template void launch_band_solve_multi<double, double>(hipStream_t, int, const i3
                                                       const i32*, const i32*, const i64*,
                                                       const double*, const double*, const i64*,
                                                       int, const double*, double*, const int*,
-                                                      int);
+                                                      int, int);
 template void launch_band_solve_multi<float, float>(hipStream_t, int, const i32*, int,
                                                     const i32*, const i32*, const i64*,
                                                     const float*, const float*, const i64*, int,
-                                                    const float*, float*, const int*, int);
+                                                    const float*, float*, const int*, int, int);

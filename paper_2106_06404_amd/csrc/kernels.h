@@ -37,7 +37,7 @@ template <typename T, typename V>
 void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax,
                              const i32* n_arr, const i32* b_arr, const i64* l_off, const T* Fc,
                              const T* Fr, const i64* v_off, int K, const V* W, V* Y,
-                             const int* active, int bmax);
+                             const int* active, int bmax, int variant = 0);
 
 // eig.hip
 void launch_eig_init(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
@@ -134,7 +134,8 @@ void launch_apply_fine_restrict(hipStream_t s, int P, int nd_max, const i32* nd,
 // diag(scale) A_i diag(scale), scale given per Dirichlet dof).
 void launch_apply_fine_solve(hipStream_t s, int P, int nd_max, int bd_max, const i32* nd,
                              const i32* bd, const i64* doff, const i64* dboff, const void* Fc,
-                             const void* Fr, int fp32, const double* scale, double* u);
+                             const void* Fr, int fp32, const double* scale, double* u,
+                             int variant = 0);
 void launch_apply_coarse_down(hipStream_t s, int P, int no_max, const i32* nown,
                               const i64* own_ptr, const i32* own_idx, const i64* loff,
                               const double* Inv, const i32* msub, const i64* yoff,

@@ -402,6 +402,7 @@ struct msdd_ctx {
     bool have_targets = false;
   } warm;
   std::vector<int32_t> eig_iters;  // per finest-level subdomain, last setup
+  msdd_tuning_t tune{};            // launch-shape choices (0 = by shape)
   ~msdd_ctx() {
     if (h_segI) (void)hipHostFree(h_segI);
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -814,7 +815,8 @@ void fine_eigensolve(msdd_ctx* c) {
     const size_t tot = kvoff.back();
     DVec<double> BX, Y, Z, SX, GS, GB, Cm, upart;
     // row splits per subdomain of the Gram and update kernels (about 192 rows each)
-    const int nsplit = std::max(1, std::min(8, (F.nb_max + 191) / 192));
+    const int nsplit = c->tune.eig_splits > 0 ? c->tune.eig_splits
+                                              : std::max(1, std::min(8, (F.nb_max + 191) / 192));
     E.X.alloc(tot);
     BX.alloc(tot);
     Y.alloc(tot);
@@ -862,7 +864,7 @@ void fine_eigensolve(msdd_ctx* c) {
                      f * 4.0 * F.s_nbb * K);
         launch_band_solve_multi<double, double>(s, P, nullptr, F.nb_max, F.gs.n.p, F.gs.bw.p,
                                                 F.boff.p, F.LSc.p, F.LSr.p, dkvoff.p, K, BX.p,
-                                                Y.p, status.p, F.bw_max);
+                                                Y.p, status.p, F.bw_max, c->tune.eig_solve);
       }
       {
         ProfScope ps(c, PR_EIG_BAPPLY, f * (F.s_nb * F.ell_w * 12.0 + 2.0 * F.s_nb * K * 8.0),
@@ -1580,10 +1582,10 @@ void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
                  4.0 * F.s_ndbd + F.s_nd);
     if (f32)
       launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
-                              F.LDc32.p, F.LDr32.p, 1, F.dscale.p, c->u.p);
+                              F.LDc32.p, F.LDr32.p, 1, F.dscale.p, c->u.p, c->tune.fine_solve);
     else
       launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
-                              F.LDc.p, F.LDr.p, 0, nullptr, c->u.p);
+                              F.LDc.p, F.LDr.p, 0, nullptr, c->u.p, c->tune.fine_solve);
   }
   {
     ProfScope ps(c, PR_APPLY_COARSE);
@@ -1778,7 +1780,8 @@ int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     }
     vlog(c, "setup: input copies", &tv);
     const double avg = (double)c->nnz / (double)n;
-    c->spmv_sg = avg <= 6 ? 4 : (avg <= 14 ? 8 : (avg <= 40 ? 16 : 32));
+    c->spmv_sg = c->tune.spmv_group > 0 ? c->tune.spmv_group
+                                        : (avg <= 6 ? 4 : (avg <= 14 ? 8 : (avg <= 40 ? 16 : 32)));
     // finest level
     c->F = FineLevel();
     c->F.P = n_sub;
@@ -2124,6 +2127,153 @@ int msdd_get_eig_iters(const msdd_ctx* c, int32_t* iters) {
                      is_device_ptr(iters) ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
   } catch (const MsddError& e) {
     return code_for(cc, e);
+  }
+  return MSDD_OK;
+}
+
+int msdd_autotune(msdd_ctx* c, int32_t what, int32_t reps) {
+  if (!c) return MSDD_EINVAL;
+  if (!c->ready) {
+    set_err(c, "msdd_autotune needs a completed setup");
+    return MSDD_ESTATE;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  try {
+    HIPCHK(hipSetDevice(c->opt.device));
+    REQUIRE(reps >= 1 && reps <= 100, "reps must lie in [1, 100]");
+    REQUIRE((what & ~(MSDD_TUNE_EIG | MSDD_TUNE_SOLVE)) == 0 && what != 0, "bad tuning mask");
+    hipStream_t s = c->stream;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    // ms per launch of f: one untimed launch, then reps timed ones
+    auto time_it = [&](const auto& f) -> float {
+      f();
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) f();
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      return ms / reps;
+    };
+    FineLevel& F = c->F;
+    const int P = F.P;
+    msdd_tuning_t& T = c->tune;
+    if (what & MSDD_TUNE_EIG) {
+      const int K = c->opt.block <= 16 ? 16 : (c->opt.block <= 32 ? 32 : 64);
+      std::vector<int64_t> kvoff(P + 1, 0);
+      for (int i = 0; i < P; ++i) kvoff[i + 1] = kvoff[i] + (int64_t)F.gs.h_n[i] * K;
+      DVec<int64_t> dkvoff;
+      dkvoff.upload(kvoff, s);
+      DVec<double> W, Y, Z, GS, GB;
+      W.alloc(kvoff.back());
+      Y.alloc(kvoff.back());
+      Z.alloc(kvoff.back());
+      W.zero(s);
+      Y.zero(s);
+      Z.zero(s);
+      for (float& v : T.eig_solve_ms) v = 0.f;
+      int best = 0;
+      for (int v = 1; v <= 3; ++v) {
+        if (v != 3 && F.bw_max >= 64) continue;  // rolling window needs a band below 64
+        T.eig_solve_ms[v] = time_it([&] {
+          launch_band_solve_multi<double, double>(s, P, nullptr, F.nb_max, F.gs.n.p, F.gs.bw.p,
+                                                  F.boff.p, F.LSc.p, F.LSr.p, dkvoff.p, K, W.p,
+                                                  Y.p, nullptr, F.bw_max, v);
+        });
+        if (!best || T.eig_solve_ms[v] < T.eig_solve_ms[best]) best = v;
+      }
+      T.eig_solve = best;
+      const int cand[5] = {1, 2, 4, 8, 16};
+      GS.alloc((size_t)P * 16 * K * K);
+      GB.alloc((size_t)P * 16 * K * K);
+      int bs = 0;
+      for (int q = 0; q < 5; ++q) {
+        T.eig_splits_ms[q] = time_it([&] {
+          launch_gram(s, P, F.gs.n.p, dkvoff.p, K, Y.p, W.p, Z.p, GS.p, GB.p, nullptr, cand[q]);
+        });
+        if (T.eig_splits_ms[q] < T.eig_splits_ms[bs]) bs = q;
+      }
+      T.eig_splits = cand[bs];
+    }
+    if (what & MSDD_TUNE_SOLVE) {
+      const bool f32 = c->opt.precision == MSDD_MIXED;
+      DVec<double> u;
+      u.alloc(std::max<int64_t>(F.h_doff.back(), 1));
+      u.zero(s);
+      for (float& v : T.fine_solve_ms) v = 0.f;
+      int best = 0;
+      for (int v = 1; v <= 2; ++v) {
+        if (v == 1 && F.bd_max >= 64) continue;  // rolling window needs a band below 64
+        T.fine_solve_ms[v] = time_it([&] {
+          if (f32)
+            launch_apply_fine_solve(s, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
+                                    F.LDc32.p, F.LDr32.p, 1, F.dscale.p, u.p, v);
+          else
+            launch_apply_fine_solve(s, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
+                                    F.LDc.p, F.LDr.p, 0, nullptr, u.p, v);
+        });
+        if (!best || T.fine_solve_ms[v] < T.fine_solve_ms[best]) best = v;
+      }
+      T.fine_solve = best;
+      const int sgs[4] = {4, 8, 16, 32};
+      int bs = 0;
+      DVec<double> pv, qv;
+      pv.alloc(c->n);
+      qv.alloc(c->n);
+      pv.zero(s);
+      for (int q = 0; q < 4; ++q) {
+        T.spmv_ms[q] = time_it([&] {
+          launch_spmv_chunk(s, c->nch, sgs[q], c->ch_lo.p, c->ch_hi.p, c->rowptr.p, c->col.p,
+                            c->val.p, pv.p, qv.p, c->partial.p);
+        });
+        if (T.spmv_ms[q] < T.spmv_ms[bs]) bs = q;
+      }
+      T.spmv_group = sgs[bs];
+      c->spmv_sg = T.spmv_group;
+      if (c->gexec) (void)hipGraphExecDestroy(c->gexec);  // captured with the old shapes
+      c->gexec = nullptr;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+  } catch (const MsddError& e) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return code_for(c, e);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return MSDD_OK;
+}
+
+int msdd_get_tuning(const msdd_ctx* c, msdd_tuning_t* t) {
+  if (!c || !t) return MSDD_EINVAL;
+  *t = c->tune;
+  return MSDD_OK;
+}
+
+int msdd_set_tuning(msdd_ctx* c, const msdd_tuning_t* t) {
+  if (!c || !t) return MSDD_EINVAL;
+  const bool ok = t->eig_solve >= 0 && t->eig_solve <= 3 && t->eig_splits >= 0 &&
+                  t->eig_splits <= 16 && t->fine_solve >= 0 && t->fine_solve <= 2 &&
+                  (t->spmv_group == 0 || t->spmv_group == 4 || t->spmv_group == 8 ||
+                   t->spmv_group == 16 || t->spmv_group == 32);
+  if (!ok) {
+    set_err(c, "tuning value out of range");
+    return MSDD_EINVAL;
+  }
+  c->tune.eig_solve = t->eig_solve;
+  c->tune.eig_splits = t->eig_splits;
+  c->tune.fine_solve = t->fine_solve;
+  c->tune.spmv_group = t->spmv_group;
+  if (c->ready && t->spmv_group > 0 && c->spmv_sg != t->spmv_group) {
+    c->spmv_sg = t->spmv_group;
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  if (c->ready && c->gexec) {  // the fine-solve variant is part of the captured graph
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
   }
   return MSDD_OK;
 }

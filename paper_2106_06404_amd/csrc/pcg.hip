@@ -428,10 +428,14 @@ size_t apply_fine_rot_lds(int nd_max, size_t elem) {
 }
 void launch_apply_fine_solve(hipStream_t s, int P, int nd_max, int bd_max, const i32* nd,
                              const i32* bd, const i64* doff, const i64* dboff, const void* Fc,
-                             const void* Fr, int fp32, const double* scale, double* u) {
+                             const void* Fr, int fp32, const double* scale, double* u,
+                             int variant) {
+  // variant: 0 = by shape, 1 = rolling window (needs a half-bandwidth below 64 and the
+  // window in LDS), 2 = one wavefront per subdomain
   if (P == 0) return;
   const size_t lds = apply_fine_rot_lds(nd_max, fp32 ? sizeof(float) : sizeof(double));
-  if (bd_max < 64 && lds <= 160 * 1024) {
+  const bool rot_ok = bd_max < 64 && lds <= 160 * 1024;
+  if (rot_ok && variant != 2) {
     if (fp32) {
       (void)hipFuncSetAttribute((const void*)k_apply_fine_rot<float>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -1,0 +1,67 @@
+"""Autotuner of launch shapes (msdd_autotune) on the GPU, through the C ABI: every
+launch-shape variant computes the same preconditioner (checked against the oracle),
+and tuning picks valid shapes from measured times without changing results beyond
+rounding."""
+import numpy as np
+import pytest
+
+from msdd_inputs import problems as P
+from oracle.msdd_oracle import Oracle
+from test_gpu_parity import _apply_rel, _check_fine_level, _setup, _solve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("eig_solve,eig_splits,fine_solve,spmv_group",
+                         [(1, 1, 1, 4), (2, 3, 2, 8), (3, 16, 1, 32), (1, 8, 2, 16)])
+def test_every_variant_matches_oracle(eig_solve, eig_splits, fine_solve, spmv_group):
+    # the problem of the two-level parity test, where the default shapes meet these bounds
+    prob = P.small_problem(N=16, P=4, delta=1, contrast=1e6, seed=5)
+    o = Oracle(prob)
+    from paper_2106_06404_amd import binding as B
+    arrs = B.problem_arrays(prob, device="cuda:0")
+    m = B.Msdd()
+    m.set_tuning(eig_solve=eig_solve, eig_splits=eig_splits, fine_solve=fine_solve,
+                 spmv_group=spmv_group)
+    m.setup(**arrs)
+    _check_fine_level(m, o, prob, prob.eta)
+    assert _apply_rel(m, o, prob) < 1e-9
+    it, rel, x = _solve(m, prob)
+    ro = o.solve()
+    assert abs(it - ro.iters) <= 1
+    assert np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x) < 1e-8
+    m.close()
+
+
+def test_set_tuning_rejects_out_of_range():
+    from paper_2106_06404_amd import binding as B
+    m = B.Msdd()
+    for kw in ({"eig_solve": 4}, {"eig_splits": 17}, {"fine_solve": 3}, {"spmv_group": 12}):
+        with pytest.raises(B.MsddError):
+            m.set_tuning(**kw)
+    with pytest.raises(B.MsddError):
+        m.autotune()  # no setup yet
+    m.close()
+
+
+def test_autotune_picks_measured_shapes_and_keeps_results():
+    prob = P.small_problem(N=48, P=4, delta=2, contrast=1e4, seed=2)
+    m, arrs = _setup(prob)
+    it0, _, x0 = _solve(m, prob)
+    lam0 = [m.eigs(1, i, 1) for i in range(prob.n_sub)]
+    t = m.autotune(reps=3)
+    assert t["eig_solve"] in (1, 2, 3) and t["eig_splits"] in (1, 2, 4, 8, 16)
+    assert t["fine_solve"] in (1, 2) and t["spmv_group"] in (4, 8, 16, 32)
+    # the choice is the fastest measured candidate
+    assert t["eig_solve_ms"][t["eig_solve"]] == min(v for v in t["eig_solve_ms"][1:] if v > 0)
+    assert t["spmv_ms"][[4, 8, 16, 32].index(t["spmv_group"])] == min(t["spmv_ms"])
+    assert all(v > 0 for v in t["spmv_ms"]) and all(v > 0 for v in t["eig_splits_ms"])
+    # the solve with the tuned shapes, and a new setup with them
+    it1, _, x1 = _solve(m, prob)
+    assert abs(it1 - it0) <= 1 and np.linalg.norm(x1 - x0) / np.linalg.norm(x0) < 1e-8
+    m.setup(**arrs)
+    for i in range(prob.n_sub):
+        l1 = m.eigs(1, i, 1)
+        assert len(l1) == len(lam0[i])
+        assert np.all(np.abs(l1 - lam0[i]) <= 1e-10 * np.maximum(np.abs(lam0[i]), prob.eta))
+    m.close()
