@@ -286,12 +286,12 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   int* keep = reinterpret_cast<int*>(Yc + g2);
   __shared__ int sh_fail, sh_r, sh_m;
   __shared__ double sh_smax, red[32];
-  // dynamic LDS: eigenvalues d (ng_max), workspace (4 ng_max), then (in_lds) the matrix
+  // dynamic LDS: eigenvalues d (ng_max), workspace (6 ng_max), then (in_lds) the matrix
   // being diagonalised, later its eigenvector copy
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* d = reinterpret_cast<double*>(smem_raw);
   double* wsp = d + ng_max;
-  double* Alds = wsp + 4 * ng_max;
+  double* Alds = wsp + 6 * ng_max;
   const int tid = threadIdx.x, nt = blockDim.x;
   if (no == 0) {
     if (tid == 0) {
@@ -550,9 +550,9 @@ void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_
                         double eps_reg, double* lam_out, const i64* lamoff, int* m_out,
                         int* status, int* rank_out, int* sweeps_out, int ng_max) {
   if (!nt) return;
-  const size_t vecs = 5 * (size_t)ng_max * sizeof(double);
+  const size_t vecs = 7 * (size_t)ng_max * sizeof(double);
   const size_t full = vecs + (size_t)ng_max * ng_max * sizeof(double);
-  const int in_lds = full <= 150 * 1024;
+  const int in_lds = full <= 158 * 1024;  // 160 KB of LDS per workgroup, less the static part
   const size_t lds = in_lds ? full : vecs;
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_coarse_gevp,

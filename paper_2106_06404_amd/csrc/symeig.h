@@ -11,7 +11,7 @@
 //        If Zl is not null, the QL rotations run on the copy Zl (LDS, n x n) and the
 //        result is copied to Zt.
 //   d  : n eigenvalues (LDS), unsorted, d[a] belongs to eigenvector a.
-//   w  : LDS workspace of 4n entries.
+//   w  : LDS workspace of 6n entries.
 // All threads of the workgroup must call it.  Returns the number of QL steps, or -1
 // if some eigenvalue needed more than 60 QL steps.
 #pragma once
@@ -22,8 +22,8 @@ __device__ __forceinline__ int wg_syev(int n, R* A, R* Zt, R* Zl, R* d, R* w, R*
   const int tid = threadIdx.x, nt = blockDim.x;
   R* e = w;          // subdiagonal: e[i] = T(i+1, i)
   R* beta = w + n;   // Householder scalars
-  R* v = w + 2 * n;  // current Householder vector / rotation cosines
-  R* sn = w + 3 * n;  // rotation sines
+  R* v = w + 2 * n;   // current Householder vector / rotation cosines (buffer 0)
+  R* sn = w + 3 * n;  // rotation sines (buffer 0); w + 4n, w + 5n: buffer 1
   __shared__ R sh_alpha, sh_beta, sh_k;
   __shared__ int sh_state[5];  // l, m, lo, iterations at l, failed
   if (n == 1) {
@@ -122,106 +122,161 @@ __device__ __forceinline__ int wg_syev(int n, R* A, R* Zt, R* Zl, R* d, R* w, R*
     }
     __syncthreads();
   }
-  R* Z = Zl ? Zl : Zt;
+  // the QL rotations run on the LDS copy Zl when there is one
   if (Zl) {
     for (i64 t = tid; t < (i64)n * n; t += nt) Zl[t] = Zt[t];
     __syncthreads();
   }
-  // ---- 3. implicit QL on (d, e); each step's rotations are computed by one thread
-  // (they depend on each other) and applied by all threads to the rows of Z
-  // deflation test relative to the norm of T (absolute accuracy eps ||A|| for every
-  // eigenvalue; a test relative to the neighbouring diagonal entries can stall on
-  // clusters of eigenvalues near zero)
+  // ---- 3. implicit QL on (d, e).  Wavefront 0 runs the control: it finds the next
+  // unreduced block with a wave-wide scan of e (deflation test relative to the norm of
+  // T: absolute accuracy eps ||A|| for every eigenvalue; a test relative to the
+  // neighbouring diagonal entries can stall on clusters near zero) and one lane computes
+  // the step's rotations, a dependent chain, with its loads issued one rotation ahead.
+  // The other wavefronts apply the previous step's rotations to the rows of Z
+  // meanwhile (rotation arrays double buffered), so a step costs the longer of the two.
   const R eps = (R)2.220446049250313e-16;
   __shared__ R sh_tnorm;
+  __shared__ int q_m[2], q_lo[2], q_has[2];
+  // rotation buffer b: cosines at w + (2 + 2b) n, sines at w + (3 + 2b) n (offsets from w,
+  // so that the compiler keeps them in the LDS address space)
   if (tid == 0) {
-    sh_state[0] = 0;  // l
-    sh_state[3] = 0;  // iterations at this l
-    sh_state[4] = 0;  // failed
     R tn = 0;
     for (int i = 0; i < n; ++i) tn = fmax(tn, fabs(d[i]) + fabs(e[i]));
     sh_tnorm = tn;
+    sh_state[4] = 0;
   }
   __syncthreads();
-  int steps = 0;
-  while (true) {
-    if (tid == 0) {
-      int l = sh_state[0], it = sh_state[3];
-      int flag = 0, m = l, lo = 0;
-      while (l < n) {
-        m = l;
-        while (m < n - 1) {
-          if (fabs(e[m]) <= eps * sh_tnorm) break;
-          ++m;
-        }
-        if (m == l || it >= 60) {  // eigenvalue l converged (or gave up)
-          if (m != l) sh_state[4] = 1;
-          ++l;
-          it = 0;
-          continue;
-        }
-        break;
+  const R thr = eps * sh_tnorm;
+  const int lane = tid & 63;
+  // wavefront-0 state (uniform over its lanes)
+  int ql_l = 0, ql_it = 0, ql_failed = 0;
+  // one QL step into buffer b (wavefront 0 only); q_has[b] = 0 when all have converged
+  auto ql_step = [&](int b) {
+    int m = 0;
+    while (ql_l < n) {
+      // first m >= l with |e[m]| <= thr, or n - 1
+      m = -1;
+      for (int base = ql_l; base < n - 1 && m < 0; base += 64) {
+        const int idx = base + lane;
+        const bool hit = idx >= n - 1 || fabs(e[idx]) <= thr;
+        const unsigned long long mk = __ballot(hit);
+        if (mk) m = base + __ffsll((long long)mk) - 1;
       }
-      if (l >= n) {
-        flag = 2;
-      } else {
-        ++it;
-        R g = (d[l + 1] - d[l]) / ((R)2 * e[l]);
-        R r = sqrt(g * g + (R)1);
-        g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
-        R s = 1, c = 1, p = 0;
-        int i;
-        lo = l;
-        for (i = m - 1; i >= l; --i) {
-          const R f = s * e[i], bb = c * e[i];
-          r = sqrt(f * f + g * g);
-          e[i + 1] = r;
-          if (r == (R)0) {  // deflation inside the sweep
-            d[i + 1] -= p;
-            e[m] = 0;
-            lo = i + 1;
-            break;
-          }
-          s = f / r;
-          c = g / r;
-          g = d[i + 1] - p;
-          r = (d[i] - g) * s + (R)2 * c * bb;
-          p = s * r;
-          d[i + 1] = g + p;
-          g = c * r - bb;
-          v[i] = c;
-          sn[i] = s;
-        }
-        if (i < l) {
-          d[l] -= p;
-          e[l] = g;
+      if (m < 0 || m > n - 1) m = n - 1;
+      if (m == ql_l || ql_it >= 60) {  // eigenvalue l converged (or given up)
+        if (m != ql_l) ql_failed = 1;
+        ++ql_l;
+        ql_it = 0;
+        continue;
+      }
+      break;
+    }
+    if (ql_l >= n) {
+      if (lane == 0) q_has[b] = 0;
+      return;
+    }
+    ++ql_it;
+    const int l = ql_l;
+    if (lane == 0) {
+      R* cb = w + (2 + 2 * b) * n;
+      R* sb = cb + n;
+      R g = (d[l + 1] - d[l]) / ((R)2 * e[l]);
+      R r = sqrt(g * g + (R)1);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+      R s = 1, c = 1, p = 0;
+      int i = m - 1, lo = l;
+      R ei = e[i], di = d[i], di1 = d[i + 1];
+      for (; i >= l; --i) {
+        // values of the next rotation, loaded before this one's stores (they are not
+        // written by it)
+        const int ip = i > 0 ? i - 1 : 0;  // unconditional (clamped) loads, no branch
+        const R en = e[ip];
+        const R dn = d[ip];
+        const R f = s * ei, bb = c * ei;
+        // r = sqrt(f^2 + g^2), s = f / r, c = g / r through one reciprocal square root:
+        // the rotation chain is the critical path of the whole solver, and this halves
+        // its dependent latency against a square root and two divisions
+        const R q = f * f + g * g;
+        if (q == (R)0) {  // deflation inside the sweep
+          e[i + 1] = 0;
+          d[i + 1] = di1 - p;
           e[m] = 0;
+          lo = i + 1;
+          break;
         }
-        flag = 1;
+        const R ri = rsqrt(q);
+        r = q * ri;
+        e[i + 1] = r;
+        s = f * ri;
+        c = g * ri;
+        g = di1 - p;
+        r = (di - g) * s + (R)2 * c * bb;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - bb;
+        cb[i] = c;
+        sb[i] = s;
+        di1 = di;
+        ei = en;
+        di = dn;
       }
-      sh_state[0] = l;
-      sh_state[1] = m;
-      sh_state[2] = lo;
-      sh_state[3] = it;
-      sh_k = (R)flag;
+      if (i < l) {
+        d[l] -= p;
+        e[l] = g;
+        e[m] = 0;
+      }
+      q_m[b] = m;
+      q_lo[b] = lo;
+      q_has[b] = 1;
+    }
+  };
+  if (tid < 64) ql_step(0);
+  __syncthreads();
+  int steps = 0, cur = 0;
+  while (q_has[cur]) {
+    if (tid < 64) {
+      ql_step(cur ^ 1);
+    } else {
+      // rotations i = m-1 down to lo on eigenvector rows (i, i+1) of Z (transposed),
+      // eight at a time with their operands loaded first; Z is the LDS copy when there
+      // is one (two call sites, so that each keeps its address space)
+      const int m = q_m[cur], lo = q_lo[cur];
+      const R* cb = w + (2 + 2 * cur) * n;
+      const R* sb = cb + n;
+      auto apply = [&](R* Z) {
+        for (int k = tid - 64; k < n; k += nt - 64) {
+          R zi1 = Z[(i64)m * n + k];
+          for (int i0 = m - 1; i0 >= lo; i0 -= 8) {
+            const int cnt = min(8, i0 - lo + 1);
+            R zb[8], cv[8], sv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (u < cnt) {
+                zb[u] = Z[(i64)(i0 - u) * n + k];
+                cv[u] = cb[i0 - u];
+                sv[u] = sb[i0 - u];
+              }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (u < cnt) {
+                Z[(i64)(i0 - u + 1) * n + k] = sv[u] * zb[u] + cv[u] * zi1;
+                zi1 = cv[u] * zb[u] - sv[u] * zi1;
+              }
+          }
+          Z[(i64)lo * n + k] = zi1;
+        }
+      };
+      if (Zl)
+        apply(Zl);
+      else
+        apply(Zt);
     }
     __syncthreads();
-    if (sh_k == (R)2) break;
+    cur ^= 1;
     ++steps;
-    // rotations i = m-1 down to lo on eigenvector rows (i, i+1) of Z (transposed)
-    const int m = sh_state[1], lo = sh_state[2];
-    for (int k = tid; k < n; k += nt) {
-      R zi1 = Z[(i64)m * n + k];
-      for (int i = m - 1; i >= lo; --i) {
-        const R zi = Z[(i64)i * n + k];
-        const R c = v[i], s = sn[i];
-        Z[(i64)(i + 1) * n + k] = s * zi + c * zi1;
-        zi1 = c * zi - s * zi1;
-      }
-      Z[(i64)lo * n + k] = zi1;
-    }
-    __syncthreads();
   }
+  if (tid == 0) sh_state[4] = ql_failed;
+  __syncthreads();
   if (Zl) {
     for (i64 t = tid; t < (i64)n * n; t += nt) Zt[t] = Zl[t];
     __syncthreads();
