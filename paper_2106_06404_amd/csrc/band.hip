@@ -106,6 +106,9 @@ __global__ void k_dirichlet_extract(i64 total_rows, const i32* __restrict__ drow
 // column enters the window; sigma = 0 / dv = nullptr factorises A itself.
 // Writes L in both column (Lc) and row (Lr) band layouts.
 // ---------------------------------------------------------------------------
+constexpr int CHOL_RB = 32;    // columns per batch of global loads / stores
+constexpr int CHOL_MAXI = 8;   // trailing-update items per thread kept in registers
+
 template <typename T>
 __global__ void k_band_cholesky(const i32* __restrict__ subs, const i32* __restrict__ n_arr,
                                 const i32* __restrict__ b_arr, const i64* __restrict__ src_off,
@@ -113,70 +116,110 @@ __global__ void k_band_cholesky(const i32* __restrict__ subs, const i32* __restr
                                 const double* __restrict__ dv, double sigma,
                                 const i64* __restrict__ dst_off, T* __restrict__ Lc,
                                 T* __restrict__ Lr, int* __restrict__ status) {
+  // The (b+1) x (b+1) active window lives in LDS (column c in slot c mod (b+1)).  Global
+  // traffic is batched: the next CHOL_RB input columns are loaded into an LDS ring once
+  // every CHOL_RB steps and the factor columns are staged in a second ring and written
+  // out every CHOL_RB steps, so the two barriers of a step wait on LDS work only (a
+  // barrier also waits for the wavefront's outstanding global loads and stores).
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = subs ? subs[blockIdx.x] : blockIdx.x;
   const int n = n_arr[i];
   const int b = b_arr[i];
   const int w = b + 1;
-  T* W = reinterpret_cast<T*>(smem_raw);  // w*w
-  T* lcol = W + (size_t)w * w;            // w
-  __shared__ int fail;
+  T* W = reinterpret_cast<T*>(smem_raw);   // w*w
+  T* lcol = W + (size_t)w * w;             // w
+  T* ain = lcol + w;                       // CHOL_RB*w  upcoming input columns
+  T* lout = ain + (size_t)CHOL_RB * w;     // CHOL_RB*w  factor columns not yet written
   const double* A = src + src_off[i];
   const double* d = dv ? dv + dv_off[i] : nullptr;
   T* Lci = Lc + dst_off[i];
   T* Lri = Lr + dst_off[i];
-  if (threadIdx.x == 0) fail = 0;
-  auto load_col = [&](int c, int slot) {
-    for (int t = threadIdx.x; t < w; t += blockDim.x) {
-      T v = 0;
-      if (c + t < n) {
-        double a = A[(i64)c * w + t];
-        if (d) a *= 1.0 + sigma * d[c + t] * d[c];
-        v = (T)a;
-      }
-      W[slot * w + t] = v;
-    }
+  auto in_val = [&](int c, int t) -> T {
+    double a = A[(i64)c * w + t];
+    if (d) a *= 1.0 + sigma * d[c + t] * d[c];
+    return (T)a;
   };
-  for (int c = 0; c < w && c < n; ++c) load_col(c, c);
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const int slot = j % w;
+  for (int c = 0; c < w && c < n; ++c)
+    for (int t = threadIdx.x; t < w; t += blockDim.x) W[c * w + t] = (c + t < n) ? in_val(c, t) : (T)0;
+  int flushed = 0;  // columns < flushed are written to Lc / Lr
+  auto flush = [&](int upto) {  // write staged columns [flushed, upto)
+    const int cnt = upto - flushed;
+    for (int e = threadIdx.x; e < cnt * w; e += blockDim.x) {
+      const int jj = flushed + e / w, t = e % w;
+      const T l = lout[(jj % CHOL_RB) * w + t];
+      Lci[(i64)jj * w + t] = l;
+      if (jj + t < n) Lri[(i64)(jj + t) * w + t] = l;
+    }
+    flushed = upto;
+  };
+  // this thread's items (p, q), 1 <= q <= p <= b, of the lower triangle, enumerated once
+  // (row-wise index t = p (p - 1) / 2 + q - 1) when they fit in registers
+  const int nitems = b * (b + 1) / 2;
+  const bool fast = nitems <= CHOL_MAXI * (int)blockDim.x;
+  int ip[CHOL_MAXI], iq[CHOL_MAXI], ni = 0;
+  if (fast)
+    for (int t = threadIdx.x; t < nitems; t += blockDim.x) {
+      int p = (int)((1.0 + sqrt(1.0 + 8.0 * t)) * 0.5);
+      while (p * (p - 1) / 2 > t) --p;
+      while ((p + 1) * p / 2 <= t) ++p;
+      ip[ni] = p;
+      iq[ni] = t - p * (p - 1) / 2 + 1;
+      ++ni;
+    }
+  bool failed = false;
+  int slot = 0;
+  for (int j = 0; j < n; ++j, slot = (slot + 1 == w) ? 0 : slot + 1) {
+    if (j % CHOL_RB == 0) {
+      // factor columns of the previous batch out, input columns j+w .. j+w+RB-1 in (after
+      // every thread has consumed the previous batch's last input column)
+      if (j > 0) __syncthreads();
+      flush(j);
+      for (int e = threadIdx.x; e < CHOL_RB * w; e += blockDim.x) {
+        const int c = j + w + e / w, t = e % w;
+        ain[e] = (c < n && c + t < n) ? in_val(c, t) : (T)0;
+      }
+    }
+    __syncthreads();
     const T ajj = W[slot * w];
     if (!(ajj > (T)0)) {
-      if (threadIdx.x == 0) { fail = 1; status[i] = ST_NOTSPD; }
+      if (threadIdx.x == 0) status[i] = ST_NOTSPD;
+      failed = true;
       break;
     }
     const T ljj = sqrt(ajj);
+    const T rl = (T)1 / ljj;
     for (int t = threadIdx.x; t < w; t += blockDim.x) {
       T l = 0;
-      if (j + t < n) {
-        l = (t == 0) ? ljj : W[slot * w + t] / ljj;
-        Lri[(i64)(j + t) * w + t] = l;
-      }
+      if (j + t < n) l = (t == 0) ? ljj : W[slot * w + t] * rl;
       lcol[t] = l;
-      Lci[(i64)j * w + t] = l;
+      lout[(j % CHOL_RB) * w + t] = l;
     }
     __syncthreads();
     // trailing update of the window: A(j+p, j+q) -= L(j+p, j) L(j+q, j), 1 <= q <= p <= b
-    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
-      const int p = t / b + 1, q = t % b + 1;
-      if (q <= p && j + p < n) W[((j + q) % w) * w + (p - q)] -= lcol[p] * lcol[q];
-    }
-    if (j + w < n) {
-      for (int t = threadIdx.x; t < w; t += blockDim.x) {
-        T v = 0;
-        const int c = j + w;
-        if (c + t < n) {
-          double a = A[(i64)c * w + t];
-          if (d) a *= 1.0 + sigma * d[c + t] * d[c];
-          v = (T)a;
+    if (fast) {
+#pragma unroll
+      for (int u = 0; u < CHOL_MAXI; ++u) {
+        if (u >= ni) break;
+        const int pp = ip[u], qq = iq[u];
+        if (j + pp < n) {
+          int sl = slot + qq;
+          if (sl >= w) sl -= w;
+          W[sl * w + (pp - qq)] -= lcol[pp] * lcol[qq];
         }
-        W[slot * w + t] = v;
+      }
+    } else {
+      for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
+        const int p = t / b + 1, q = t % b + 1;
+        if (q <= p && j + p < n) W[((j + q) % w) * w + (p - q)] -= lcol[p] * lcol[q];
       }
     }
-    __syncthreads();
+    if (j + w < n)
+      for (int t = threadIdx.x; t < w; t += blockDim.x) W[slot * w + t] = ain[(j % CHOL_RB) * w + t];
   }
-  (void)fail;
+  if (!failed) {
+    __syncthreads();
+    flush(n);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -316,8 +359,11 @@ void launch_band_cholesky(hipStream_t s, int nsubs, const i32* subs, int bmax, c
                           T* Lc, T* Lr, int* status) {
   if (nsubs == 0) return;
   size_t w = (size_t)bmax + 1;
-  size_t lds = (w * w + w) * sizeof(T);
-  if (lds <= 64 * 1024) {
+  size_t lds = (w * w + w + 2 * CHOL_RB * w) * sizeof(T);
+  if (lds <= 160 * 1024) {
+    if (lds > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)k_band_cholesky<T>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_band_cholesky<T>, dim3(nsubs), dim3(MSDD_WG), lds, s, subs, n_arr,
                        b_arr, src_off, src, dv_off, dv, sigma, dst_off, Lc, Lr, status);
   } else {

@@ -74,18 +74,23 @@ __global__ void k_bapply_ell(i64 total_rows, const i32* __restrict__ row_sub,
   }
   const i32* ec = ell_col + g * ell_w;
   const double* ev = ell_val + g * ell_w;
-  constexpr int CB = 8;
+  // padding entries (column -1) are read as column 0 with coefficient 0, so the loop has
+  // no data-dependent exits and the loads of different entries can be issued together
+  constexpr int CB = 16;
   for (int c0 = 0; c0 < K; c0 += CB) {
     V acc[CB];
+#pragma unroll
     for (int u = 0; u < CB; ++u) acc[u] = 0;
     for (int t = 0; t < ell_w; ++t) {
-      const int cc = ec[t];
-      if (cc < 0) break;
-      const V a = (V)(ev[t] * d[cc]);
-      if (a == (V)0) continue;
+      const int c_raw = ec[t];
+      const int cc = c_raw < 0 ? 0 : c_raw;
+      const V a = c_raw < 0 ? (V)0 : (V)(ev[t] * d[cc]);
+      const V* yc = Yi + cc + (i64)c0 * n;
+#pragma unroll
       for (int u = 0; u < CB; ++u)
-        if (c0 + u < K) acc[u] += a * Yi[cc + (i64)(c0 + u) * n];
+        if (c0 + u < K) acc[u] += a * yc[(i64)u * n];
     }
+#pragma unroll
     for (int u = 0; u < CB; ++u)
       if (c0 + u < K) Zi[r + (i64)(c0 + u) * n] = (V)(dr * acc[u]);
   }
