@@ -380,6 +380,7 @@ struct msdd_ctx {
   std::vector<int> last_iters;
   std::vector<double> last_relres;
   hipStream_t gstream = nullptr;  // capture stream for the iteration graphs
+  hipStream_t ustream = nullptr;  // uploads of the patch planning that overlaps the eigensolves
   hipEvent_t gev0 = nullptr, gev1 = nullptr;
   hipGraphExec_t gexec = nullptr;
   const double* g_x = nullptr;  // pointers the cached graph was captured with
@@ -409,6 +410,7 @@ struct msdd_ctx {
     if (gev0) (void)hipEventDestroy(gev0);
     if (gev1) (void)hipEventDestroy(gev1);
     if (gstream) (void)hipStreamDestroy(gstream);
+    if (ustream) (void)hipStreamDestroy(ustream);
   }
 };
 
@@ -1006,10 +1008,20 @@ void fine_eigensolve(msdd_ctx* c) {
 // ---------------------------------------------------------------------------
 // Patches of the finest level and their projections (Sec. 4.1)
 // ---------------------------------------------------------------------------
-void fine_patches(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
-                  const double* d_elem_mat, PatchLevel& PL) {
+// Symbolic part of the finest-level patches (depends on the subdomain element sets only),
+// run on a host thread while the GPU factorises and solves the local eigenproblems; its
+// uploads go to the side stream us.
+struct PatchPlan {
+  std::vector<std::vector<int32_t>> pel;  // elements per patch
+  std::vector<GroupPlan> plans;
+  GroupSetDev gs;
+  std::vector<int64_t> ploc_off;
+  std::vector<int32_t> ploc;              // patch dof -> local index in each member
+};
+
+void fine_patches_plan(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
+                       PatchLevel& PL, PatchPlan& T, hipStream_t us) {
   FineLevel& F = c->F;
-  hipStream_t s = c->stream;
   const int k = c->k;
   double tv = now_ms();
   // element -> containing subdomains (CSR, ascending subdomain order)
@@ -1028,7 +1040,7 @@ void fine_patches(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
   }
   // group elements by their subdomain set; patches are numbered by first element
   std::unordered_map<uint64_t, std::vector<int>> key;
-  std::vector<std::vector<int32_t>> pel;
+  std::vector<std::vector<int32_t>>& pel = T.pel;
   for (int32_t e = 0; e < n_elem; ++e) {
     const int32_t* m0 = esub.data() + ecnt[e];
     const int cnt = ecnt[e + 1] - ecnt[e];
@@ -1055,38 +1067,22 @@ void fine_patches(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
   vlog(c, "patches: element keys", &tv);
   const int nthr = host_threads(PL.np);
   std::vector<std::vector<int>> maps(nthr);
-  std::vector<GroupPlan> plans(PL.np);
+  std::vector<GroupPlan>& plans = T.plans;
+  plans.assign(PL.np, GroupPlan());
   parallel_for(PL.np, nthr, [&](int p, int t) {
     if (maps[t].empty()) maps[t].assign(c->n, -1);
     plans[p] = plan_group(pel[p].data(), (int64_t)pel[p].size(), ed, k, maps[t]);
   });
   vlog(c, "patches: group plans", &tv);
-  GroupSetDev gs;
-  build_groupset(plans, pel, k, gs, s);
+  build_groupset(plans, pel, k, T.gs, us);
   vlog(c, "patches: groupset upload", &tv);
-  // member columns, loc maps
-  PL.M.assign(PL.np, 0);
-  PL.mcol.resize(PL.np);
-  std::vector<int64_t> mem_ptr(PL.np + 1, 0), ploc_off(PL.np + 1, 0), vpoff(PL.np + 1, 0);
-  std::vector<int32_t> mem_sub, mem_col;
-  PL.pmoff.assign(PL.np + 1, 0);
-  for (int p = 0; p < PL.np; ++p) {
-    int M = 0;
-    for (int32_t j : PL.members[p]) {
-      PL.mcol[p].push_back(M);
-      mem_sub.push_back(j);
-      mem_col.push_back(M);
-      M += F.m[j];
-    }
-    PL.M[p] = M;
-    mem_ptr[p + 1] = (int64_t)mem_sub.size();
-    const int64_t nd = (int64_t)plans[p].dofs.size();
-    ploc_off[p + 1] = ploc_off[p] + nd * (int64_t)PL.members[p].size();
-    vpoff[p + 1] = vpoff[p] + nd * M;
-    PL.pmoff[p + 1] = PL.pmoff[p] + (int64_t)M * M;
-  }
+  std::vector<int64_t>& ploc_off = T.ploc_off;
+  ploc_off.assign(PL.np + 1, 0);
+  for (int p = 0; p < PL.np; ++p)
+    ploc_off[p + 1] = ploc_off[p] + (int64_t)plans[p].dofs.size() * (int64_t)PL.members[p].size();
   // patch dof -> local index in each member subdomain (-1 outside it)
-  std::vector<int32_t> ploc(ploc_off.back());
+  std::vector<int32_t>& ploc = T.ploc;
+  ploc.assign(ploc_off.back(), -1);
   parallel_for(PL.np, nthr, [&](int p, int) {
     const int nm = (int)PL.members[p].size();
     const auto& pd = plans[p].dofs;
@@ -1102,6 +1098,38 @@ void fine_patches(msdd_ctx* c, const std::vector<int32_t>& ed, int32_t n_elem,
     }
   });
   vlog(c, "patches: member maps", &tv);
+}
+
+// Numeric part: member columns (from the selected counts m_j), uploads and the patch
+// projections of the coarse basis (Sec. 4.1)
+void fine_patches(msdd_ctx* c, const double* d_elem_mat, PatchLevel& PL, PatchPlan& T) {
+  FineLevel& F = c->F;
+  hipStream_t s = c->stream;
+  const int k = c->k;
+  double tv = now_ms();
+  const std::vector<GroupPlan>& plans = T.plans;
+  const GroupSetDev& gs = T.gs;
+  PL.M.assign(PL.np, 0);
+  PL.mcol.assign(PL.np, {});
+  std::vector<int64_t> mem_ptr(PL.np + 1, 0), vpoff(PL.np + 1, 0);
+  std::vector<int32_t> mem_sub, mem_col;
+  PL.pmoff.assign(PL.np + 1, 0);
+  for (int p = 0; p < PL.np; ++p) {
+    int M = 0;
+    for (int32_t j : PL.members[p]) {
+      PL.mcol[p].push_back(M);
+      mem_sub.push_back(j);
+      mem_col.push_back(M);
+      M += F.m[j];
+    }
+    PL.M[p] = M;
+    mem_ptr[p + 1] = (int64_t)mem_sub.size();
+    const int64_t nd = (int64_t)plans[p].dofs.size();
+    vpoff[p + 1] = vpoff[p] + nd * M;
+    PL.pmoff[p + 1] = PL.pmoff[p] + (int64_t)M * M;
+  }
+  const std::vector<int64_t>& ploc_off = T.ploc_off;
+  const std::vector<int32_t>& ploc = T.ploc;
   DVec<int64_t> dmem_ptr, dploc_off, dvpoff;
   DVec<int32_t> dmem_sub, dmem_col, dploc;
   dmem_ptr.upload(mem_ptr, s);
@@ -1807,18 +1835,40 @@ int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     }
     HIPCHK(hipStreamSynchronize(s));
     const double t1 = now_ms();
+    // the symbolic planning of the finest-level patches runs on a host thread (uploads on
+    // a side stream) while the GPU factorises and solves the local eigenproblems
+    if (!c->ustream) HIPCHK(hipStreamCreateWithFlags(&c->ustream, hipStreamNonBlocking));
+    PatchLevel PL;
+    PatchPlan PT;
+    MsddError plan_err{MSDD_OK, ""};
+    std::thread plan_thread([&] {
+      try {
+        HIPCHK(hipSetDevice(c->opt.device));
+        fine_patches_plan(c, ed, n_elem, PL, PT, c->ustream);
+        HIPCHK(hipStreamSynchronize(c->ustream));
+      } catch (const MsddError& e) {
+        plan_err = e;
+      }
+    });
+    struct Joiner {
+      std::thread& t;
+      ~Joiner() {
+        if (t.joinable()) t.join();
+      }
+    } joiner{plan_thread};
     fine_local_matrices(c, d_emat);
     HIPCHK(hipStreamSynchronize(s));
     const double t2 = now_ms();
     fine_eigensolve(c);
     HIPCHK(hipStreamSynchronize(s));
     const double t3 = now_ms();
+    plan_thread.join();
+    if (plan_err.code != MSDD_OK) throw plan_err;
     // coarse levels
     const int L = n_levels - 1;
     c->C.clear();
     c->C.resize(L - 1);
-    PatchLevel PL;
-    fine_patches(c, ed, n_elem, d_emat, PL);
+    fine_patches(c, d_emat, PL, PT);
     std::vector<int32_t> m_cur = c->F.m;
     std::vector<int64_t> moff_cur = c->F.h_moff;
     for (int t = 0; t < L - 1; ++t) {
