@@ -172,14 +172,14 @@ __global__ void k_band_cholesky(const i32* __restrict__ subs, const i32* __restr
     if (j % CHOL_RB == 0) {
       // factor columns of the previous batch out, input columns j+w .. j+w+RB-1 in (after
       // every thread has consumed the previous batch's last input column)
-      if (j > 0) __syncthreads();
+      if (j > 0) lds_barrier();
       flush(j);
       for (int e = threadIdx.x; e < CHOL_RB * w; e += blockDim.x) {
         const int c = j + w + e / w, t = e % w;
         ain[e] = (c < n && c + t < n) ? in_val(c, t) : (T)0;
       }
     }
-    __syncthreads();
+    lds_barrier();  // the window, factor column and rings are in LDS
     const T ajj = W[slot * w];
     if (!(ajj > (T)0)) {
       if (threadIdx.x == 0) status[i] = ST_NOTSPD;
@@ -194,7 +194,7 @@ __global__ void k_band_cholesky(const i32* __restrict__ subs, const i32* __restr
       lcol[t] = l;
       lout[(j % CHOL_RB) * w + t] = l;
     }
-    __syncthreads();
+    lds_barrier();
     // trailing update of the window: A(j+p, j+q) -= L(j+p, j) L(j+q, j), 1 <= q <= p <= b
     if (fast) {
 #pragma unroll
@@ -306,6 +306,66 @@ __global__ void __launch_bounds__(64 * NW) k_band_solve_rot(
   }
   wg_ldl_solve_rot_cols<T, V, NW>(n, b_arr[i], Fc + l_off[i], Fr + l_off[i], Y, ncol,
                                   reinterpret_cast<V*>(smem_raw));
+}
+
+// NW wavefronts of NC columns each: 16 columns per workgroup with one LDS table read
+// shared by NC chains (see rot_block_m)
+template <typename T, typename V, int NW, int NC>
+__global__ void __launch_bounds__(64 * NW) k_band_solve_rotm(
+    const i32* __restrict__ subs, const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
+    const i64* __restrict__ l_off, const T* __restrict__ Fc, const T* __restrict__ Fr,
+    const i64* __restrict__ v_off, int K, const V* __restrict__ Win, V* __restrict__ Yout,
+    const int* __restrict__ active) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = subs ? subs[blockIdx.x] : blockIdx.x;
+  if (active && active[i] != ST_RUNNING) return;
+  const int n = n_arr[i];
+  const int c0 = blockIdx.y * NW * NC;
+  const int ncol = min(NW * NC, K - c0);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  V* Y = Yout + v_off[i] + (i64)c0 * n;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const int col = wave * NC + q;
+    if (col < ncol) {
+      // each lane copies the rows it will own in the forward sweep
+      const V* Wc = Win + v_off[i] + (i64)(c0 + col) * n;
+      V* Yc = Y + (i64)col * n;
+      for (int r = lane; r < n; r += 64) Yc[r] = Wc[r];
+    }
+  }
+  wg_ldl_solve_rot_mcols<T, V, NW, NC>(n, b_arr[i], Fc + l_off[i], Fr + l_off[i], Y, ncol,
+                                       reinterpret_cast<V*>(smem_raw));
+}
+
+// NW computing wavefronts of NC columns plus NS staging wavefronts
+template <typename T, typename V, int NW, int NC, int NS>
+__global__ void __launch_bounds__(64 * (NW + NS)) k_band_solve_rotms(
+    const i32* __restrict__ subs, const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
+    const i64* __restrict__ l_off, const T* __restrict__ Fc, const T* __restrict__ Fr,
+    const i64* __restrict__ v_off, int K, const V* __restrict__ Win, V* __restrict__ Yout,
+    const int* __restrict__ active) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = subs ? subs[blockIdx.x] : blockIdx.x;
+  if (active && active[i] != ST_RUNNING) return;
+  const int n = n_arr[i];
+  const int c0 = blockIdx.y * NW * NC;
+  const int ncol = min(NW * NC, K - c0);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  V* Y = Yout + v_off[i] + (i64)c0 * n;
+  if (wave < NW) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int col = wave * NC + q;
+      if (col < ncol) {
+        const V* Wc = Win + v_off[i] + (i64)(c0 + col) * n;
+        V* Yc = Y + (i64)col * n;
+        for (int r = lane; r < n; r += 64) Yc[r] = Wc[r];
+      }
+    }
+  }
+  wg_ldl_solve_rot_mcols_st<T, V, NW, NC, NS>(n, b_arr[i], Fc + l_off[i], Fr + l_off[i], Y, ncol,
+                                              reinterpret_cast<V*>(smem_raw));
 }
 
 template <typename T, typename V>
@@ -490,10 +550,44 @@ void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax
                              const int* active, int bmax, int variant) {
   // variant: 0 = by shape (rolling window with 16 or 8 columns per workgroup when the
   // half-bandwidth is below 64, else one wavefront per column), 1 = rolling window with 8
-  // columns, 2 = rolling window with 16 columns, 3 = one wavefront per column
+  // columns, 2 = rolling window with 16 columns, 3 = one wavefront per column, 4 = rolling
+  // window, 4 wavefronts of 4 columns, 5 = rolling window, 8 wavefronts of 2 columns,
+  // 6 = as 5 with 4 staging wavefronts, 7 = as 4 with 4 staging wavefronts
   if (nsubs == 0 || K == 0) return;
   if (variant == 0) variant = bmax < 64 ? (K >= 16 ? 2 : 1) : 3;
   if (bmax >= 64) variant = 3;  // the rolling window needs a half-bandwidth below 64
+  if (variant == 6 || variant == 7) {
+    const size_t lds = 2 * (size_t)ROT_TILE * sizeof(V);
+    if (variant == 6) {
+      (void)hipFuncSetAttribute((const void*)k_band_solve_rotms<T, V, 8, 2, 4>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL((k_band_solve_rotms<T, V, 8, 2, 4>), dim3(nsubs, (K + 15) / 16),
+                         dim3(768), lds, s, subs, n_arr, b_arr, l_off, Fc, Fr, v_off, K, W, Y,
+                         active);
+    } else {
+      (void)hipFuncSetAttribute((const void*)k_band_solve_rotms<T, V, 4, 4, 4>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL((k_band_solve_rotms<T, V, 4, 4, 4>), dim3(nsubs, (K + 15) / 16),
+                         dim3(512), lds, s, subs, n_arr, b_arr, l_off, Fc, Fr, v_off, K, W, Y,
+                         active);
+    }
+    return;
+  }
+  if (variant == 4 || variant == 5) {
+    const size_t lds = 2 * (size_t)ROT_TILE * sizeof(V);
+    if (variant == 4) {
+      (void)hipFuncSetAttribute((const void*)k_band_solve_rotm<T, V, 4, 4>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL((k_band_solve_rotm<T, V, 4, 4>), dim3(nsubs, (K + 15) / 16), dim3(256),
+                         lds, s, subs, n_arr, b_arr, l_off, Fc, Fr, v_off, K, W, Y, active);
+    } else {
+      (void)hipFuncSetAttribute((const void*)k_band_solve_rotm<T, V, 8, 2>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL((k_band_solve_rotm<T, V, 8, 2>), dim3(nsubs, (K + 15) / 16), dim3(512),
+                         lds, s, subs, n_arr, b_arr, l_off, Fc, Fr, v_off, K, W, Y, active);
+    }
+    return;
+  }
   if (variant != 3) {
     const size_t lds = 2 * (size_t)ROT_TILE * sizeof(V);
     if (variant == 2) {

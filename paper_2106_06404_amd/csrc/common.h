@@ -19,6 +19,15 @@ enum : int {
   ST_NOCONV = 5,    // eigensolver iteration limit
 };
 
+// Workgroup barrier that orders LDS accesses only: the fences are limited to the local
+// address space, so global loads still in flight (prefetches held in registers) are
+// not waited for.  For use where threads communicate through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Sum over a workgroup of blockDim.x threads (blockDim.x a multiple of 64, <= 1024).
 template <typename T>
 __device__ inline T block_sum(T v, T* sh /* >= 16 entries */) {

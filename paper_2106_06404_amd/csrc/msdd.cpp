@@ -2225,7 +2225,7 @@ int msdd_autotune(msdd_ctx* c, int32_t what, int32_t reps) {
       Z.zero(s);
       for (float& v : T.eig_solve_ms) v = 0.f;
       int best = 0;
-      for (int v = 1; v <= 3; ++v) {
+      for (int v = 1; v <= 7; ++v) {
         if (v != 3 && F.bw_max >= 64) continue;  // rolling window needs a band below 64
         T.eig_solve_ms[v] = time_it([&] {
           launch_band_solve_multi<double, double>(s, P, nullptr, F.nb_max, F.gs.n.p, F.gs.bw.p,
@@ -2304,7 +2304,7 @@ int msdd_get_tuning(const msdd_ctx* c, msdd_tuning_t* t) {
 
 int msdd_set_tuning(msdd_ctx* c, const msdd_tuning_t* t) {
   if (!c || !t) return MSDD_EINVAL;
-  const bool ok = t->eig_solve >= 0 && t->eig_solve <= 3 && t->eig_splits >= 0 &&
+  const bool ok = t->eig_solve >= 0 && t->eig_solve <= 7 && t->eig_splits >= 0 &&
                   t->eig_splits <= 16 && t->fine_solve >= 0 && t->fine_solve <= 2 &&
                   (t->spmv_group == 0 || t->spmv_group == 4 || t->spmv_group == 8 ||
                    t->spmv_group == 16 || t->spmv_group == 32);

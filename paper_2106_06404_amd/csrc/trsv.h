@@ -256,7 +256,9 @@ __device__ __forceinline__ void wg_ldl_solve_rot(int n, int b, const T* __restri
       if (row < n) v[row] = a;
       a = a2;
     }
-    __syncthreads();
+    // the solution vector and the tables are in LDS; the staging loads of the block
+    // after next stay in flight across the barrier
+    lds_barrier();
   }
 }
 
@@ -362,6 +364,294 @@ __device__ __forceinline__ void wg_ldl_solve_rot_cols(int n, int b, const T* __r
       if (has && row < n) v[row] = a;
       a = a2;
     }
-    __syncthreads();
+    // tables in LDS; each lane's global rows are its own until the sweep changes
+    // direction (full barrier above), so prefetches stay in flight across this one
+    lds_barrier();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Rolling-window step for NC right-hand sides per wavefront: each table entry read
+// from LDS feeds NC independent chains (NC broadcasts and 2 NC FMAs per row), which
+// divides the LDS traffic per right-hand side by NC.  With one column per wavefront
+// and 16 wavefronts per workgroup the table reads (16 KB per row step) bound the solve.
+// ---------------------------------------------------------------------------
+template <typename V, int CH, int NC>
+__device__ __forceinline__ void rot_block_m(const V* buf, int lane, V (&a)[NC], V (&a2)[NC]) {
+  constexpr int NCH = 64 / CH;
+  const V* Tc = buf;
+  const V* Tn = buf + 4096;
+  V tc[2][CH], tn[2][CH];
+#pragma unroll
+  for (int t = 0; t < CH; ++t) {
+    tc[0][t] = Tc[t * 64 + lane];
+    tn[0][t] = Tn[t * 64 + lane];
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    if (c + 1 < NCH) {
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        tc[(c + 1) & 1][t] = Tc[(CH * (c + 1) + t) * 64 + lane];
+        tn[(c + 1) & 1][t] = Tn[(CH * (c + 1) + t) * 64 + lane];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const V y = wave_bcast(a[q], CH * c + t);
+        a[q] -= tc[c & 1][t] * y;
+        a2[q] -= tn[c & 1][t] * y;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) asm volatile("" : "+v"(a2[q]));
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// As wg_ldl_solve_rot_cols, with NW wavefronts of NC columns each (wavefront w owns
+// columns w*NC .. w*NC+NC-1 of X; columns >= ncol run on zeros).
+template <typename T, typename V, int NW, int NC>
+__device__ __forceinline__ void wg_ldl_solve_rot_mcols(int n, int b, const T* __restrict__ Fc,
+                                                       const T* __restrict__ Fr,
+                                                       V* __restrict__ X, int ncol, V* tiles) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  constexpr int NTH = 64 * NW;
+  constexpr int PER = (64 * 64 + NTH - 1) / NTH;
+  const int w = b + 1;
+  const int nblk = (n + 63) >> 6;
+  const int nsteps = 2 * nblk;
+  const int N = nblk * 64;
+  bool has[NC];
+  V* v[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const int col = wave * NC + q;
+    has[q] = col < ncol;
+    v[q] = X + (i64)(has[q] ? col : 0) * n;
+  }
+  T gv[PER];
+  int gpos[PER];
+  auto stage_load = [&](int s) {
+    const bool fwd = s < nblk;
+    const int qb = fwd ? s : nsteps - 1 - s;
+    const int j0 = qb * 64;
+    const T* src = (fwd ? Fc : Fr) + (i64)j0 * w;
+    const int cnt = min(64, n - j0) * w;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * NTH;
+      const int kk = e / w, d = e - kk * w;
+      int pos = 0;
+      if (e < cnt && d > 0) {
+        const int k = fwd ? kk : 63 - kk;
+        const int l = (k + d) & 63;
+        pos = (k * 64 + l + 1) | ((l > k) ? 0 : (1 << 30));
+      }
+      gpos[u] = pos;
+      gv[u] = src[min(e, cnt - 1)];
+    }
+  };
+  auto stage_store = [&](V* buf) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int pos = gpos[u];
+      if (pos) {
+        const int p = (pos & ((1 << 30) - 1)) - 1;
+        buf[(pos >> 30) ? 4096 + p : p] = (V)gv[u];
+      }
+    }
+  };
+  for (int t = tid; t < 2 * ROT_TILE; t += NTH) tiles[t] = (V)0;
+  __syncthreads();
+  stage_load(0);
+  stage_store(tiles);
+  if (nsteps > 1) stage_load(1);
+  V a[NC], a2[NC], nxt[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const int row = 64 + lane;
+    nxt[q] = (has[q] && row < n) ? v[q][row] : (V)0;
+    a[q] = (has[q] && lane < n) ? v[q][lane] : (V)0;
+    a2[q] = 0;
+  }
+  __syncthreads();
+  for (int s = 0; s < nsteps; ++s) {
+    V* buf = tiles + (s & 1) * ROT_TILE;
+    if (s + 1 < nsteps) {
+      stage_store(tiles + ((s + 1) & 1) * ROT_TILE);
+      if (s + 2 < nsteps) stage_load(s + 2);
+    }
+    if (s < nblk) {  // forward, row block s
+      const int row = s * 64 + lane;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        a2[q] = nxt[q];
+        nxt[q] = (has[q] && row + 128 < n) ? v[q][row + 128] : (V)0;
+      }
+      rot_block_m<V, 8, NC>(buf, lane, a, a2);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        if (has[q] && row < n) v[q][row] = a[q];
+        a[q] = a2[q];
+      }
+      if (s == nblk - 1) {
+        // forward done: make y visible, then start the reversed sweep
+        __threadfence_block();
+        __syncthreads();
+        const int r0 = N - 1 - lane;
+        const int r1 = r0 - 64;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          a[q] = (has[q] && r0 < n) ? v[q][r0] * (V)Fr[(i64)r0 * w] : (V)0;
+          nxt[q] = (has[q] && r1 >= 0 && r1 < n) ? v[q][r1] * (V)Fr[(i64)r1 * w] : (V)0;
+        }
+      }
+    } else {  // backward, reversed block s - nblk: lane l <-> row N-1-(64(s-nblk)+l)
+      const int row = N - 1 - (64 * (s - nblk) + lane);
+      const int r2 = row - 128;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        a2[q] = nxt[q];
+        nxt[q] = (has[q] && r2 >= 0 && r2 < n) ? v[q][r2] * (V)Fr[(i64)r2 * w] : (V)0;
+      }
+      rot_block_m<V, 8, NC>(buf, lane, a, a2);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        if (has[q] && row < n) v[q][row] = a[q];
+        a[q] = a2[q];
+      }
+    }
+    lds_barrier();  // as in wg_ldl_solve_rot_cols
+  }
+}
+
+// As wg_ldl_solve_rot_mcols with NS more wavefronts that only stage the tables, so
+// the NW computing wavefronts run nothing but the recurrence (workgroup of
+// 64 (NW + NS) threads).  The change of sweep direction is a full barrier that every
+// thread executes.
+template <typename T, typename V, int NW, int NC, int NS>
+__device__ __forceinline__ void wg_ldl_solve_rot_mcols_st(int n, int b, const T* __restrict__ Fc,
+                                                          const T* __restrict__ Fr,
+                                                          V* __restrict__ X, int ncol, V* tiles) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  constexpr int NST = 64 * NS;
+  constexpr int PER = (64 * 64 + NST - 1) / NST;
+  const bool stager = wave >= NW;
+  const int tl = tid - 64 * NW;  // staging thread index
+  const int w = b + 1;
+  const int nblk = (n + 63) >> 6;
+  const int nsteps = 2 * nblk;
+  const int N = nblk * 64;
+  bool has[NC];
+  V* v[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const int col = wave * NC + q;
+    has[q] = !stager && col < ncol;
+    v[q] = X + (i64)(has[q] ? col : 0) * n;
+  }
+  T gv[PER];
+  int gpos[PER];
+  auto stage_load = [&](int s) {
+    const bool fwd = s < nblk;
+    const int qb = fwd ? s : nsteps - 1 - s;
+    const int j0 = qb * 64;
+    const T* src = (fwd ? Fc : Fr) + (i64)j0 * w;
+    const int cnt = min(64, n - j0) * w;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tl + u * NST;
+      const int kk = e / w, d = e - kk * w;
+      int pos = 0;
+      if (e < cnt && d > 0) {
+        const int k = fwd ? kk : 63 - kk;
+        const int l = (k + d) & 63;
+        pos = (k * 64 + l + 1) | ((l > k) ? 0 : (1 << 30));
+      }
+      gpos[u] = pos;
+      gv[u] = src[min(e, cnt - 1)];
+    }
+  };
+  auto stage_store = [&](V* buf) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int pos = gpos[u];
+      if (pos) {
+        const int p = (pos & ((1 << 30) - 1)) - 1;
+        buf[(pos >> 30) ? 4096 + p : p] = (V)gv[u];
+      }
+    }
+  };
+  for (int t = tid; t < 2 * ROT_TILE; t += 64 * (NW + NS)) tiles[t] = (V)0;
+  __syncthreads();
+  if (stager) {
+    stage_load(0);
+    stage_store(tiles);
+    if (nsteps > 1) stage_load(1);
+  }
+  V a[NC], a2[NC], nxt[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const int row = 64 + lane;
+    nxt[q] = (has[q] && row < n) ? v[q][row] : (V)0;
+    a[q] = (has[q] && lane < n) ? v[q][lane] : (V)0;
+    a2[q] = 0;
+  }
+  __syncthreads();
+  for (int s = 0; s < nsteps; ++s) {
+    V* buf = tiles + (s & 1) * ROT_TILE;
+    if (stager) {
+      if (s + 1 < nsteps) {
+        stage_store(tiles + ((s + 1) & 1) * ROT_TILE);
+        if (s + 2 < nsteps) stage_load(s + 2);
+      }
+    } else if (s < nblk) {  // forward, row block s
+      const int row = s * 64 + lane;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        a2[q] = nxt[q];
+        nxt[q] = (has[q] && row + 128 < n) ? v[q][row + 128] : (V)0;
+      }
+      rot_block_m<V, 4, NC>(buf, lane, a, a2);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        if (has[q] && row < n) v[q][row] = a[q];
+        a[q] = a2[q];
+      }
+    } else {  // backward, reversed block s - nblk: lane l <-> row N-1-(64(s-nblk)+l)
+      const int row = N - 1 - (64 * (s - nblk) + lane);
+      const int r2 = row - 128;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        a2[q] = nxt[q];
+        nxt[q] = (has[q] && r2 >= 0 && r2 < n) ? v[q][r2] * (V)Fr[(i64)r2 * w] : (V)0;
+      }
+      rot_block_m<V, 4, NC>(buf, lane, a, a2);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        if (has[q] && row < n) v[q][row] = a[q];
+        a[q] = a2[q];
+      }
+    }
+    if (s == nblk - 1) {
+      // forward done (every thread takes this barrier): make y visible, then start the
+      // reversed sweep, which reads rows written by other lanes
+      __threadfence_block();
+      __syncthreads();
+      const int r0 = N - 1 - lane;
+      const int r1 = r0 - 64;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        a[q] = (has[q] && r0 < n) ? v[q][r0] * (V)Fr[(i64)r0 * w] : (V)0;
+        nxt[q] = (has[q] && r1 >= 0 && r1 < n) ? v[q][r1] * (V)Fr[(i64)r1 * w] : (V)0;
+      }
+    }
+    lds_barrier();
   }
 }
