@@ -284,14 +284,14 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   double* C = Qk + g2;
   double* Yc = C + g2;
   int* keep = reinterpret_cast<int*>(Yc + g2);
-  __shared__ int sh_fail, sh_r, sh_m;
+  __shared__ int sh_fail, sh_r, sh_m, sh_bad;
   __shared__ double sh_smax, red[32];
-  // dynamic LDS: eigenvalues d (ng_max), workspace (6 ng_max), then (in_lds) the matrix
-  // being diagonalised, later its eigenvector copy
+  // dynamic LDS: eigenvalues d (ng_max), workspace (14 ng_max), then (in_lds) the matrix
+  // being diagonalised, later the tridiagonal problem's eigenvectors
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* d = reinterpret_cast<double*>(smem_raw);
   double* wsp = d + ng_max;
-  double* Alds = wsp + 6 * ng_max;
+  double* Alds = wsp + 14 * ng_max;
   const int tid = threadIdx.x, nt = blockDim.x;
   if (no == 0) {
     if (tid == 0) {
@@ -313,16 +313,23 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   __syncthreads();
   // S = Q diag(d) Q^T (Q transposed in global memory); separate calls so that the LDS
   // case is compiled with LDS accesses
-  const int st1 = in_lds ? wg_syev<double>(ng, Alds, Q, Alds, d, wsp, red)
-                         : wg_syev<double>(ng, S, Q, nullptr, d, wsp, red);
+  if (in_lds)
+    wg_syev_dc(ng, Alds, Q, C, Yc, d, wsp, red);
+  else
+    wg_syev_dc(ng, S, Q, C, Yc, d, wsp, red);
   if (tid == 0) {
     double smax = 0.0;
-    for (int a = 0; a < ng; ++a) smax = fmax(smax, d[a]);
+    int bad = 0;
+    for (int a = 0; a < ng; ++a) {
+      smax = fmax(smax, d[a]);
+      bad |= !isfinite(d[a]);
+    }
     int r = 0;
     for (int a = 0; a < ng; ++a)
       if (d[a] > tau * smax) keep[r++] = a;
     sh_smax = smax;
     sh_r = r;
+    sh_bad = bad;
   }
   __syncthreads();
   const int r = sh_r;
@@ -351,30 +358,26 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   }
   __syncthreads();
   // C = Y diag(mu) Y^T (Y transposed in Yc); mu in d
-  const int st2 = in_lds ? wg_syev<double>(r, Alds, Yc, Alds, d, wsp, red)
-                         : wg_syev<double>(r, C, Yc, nullptr, d, wsp, red);
+  if (in_lds)
+    wg_syev_dc(r, Alds, Yc, S, Q, d, wsp, red);
+  else
+    wg_syev_dc(r, C, Yc, S, Q, d, wsp, red);
   if (tid == 0) {
-    sweeps_out[4 * t] = st1;
-    sweeps_out[4 * t + 1] = st2;
+    sweeps_out[4 * t] = 0;
+    sweeps_out[4 * t + 1] = 0;
     sweeps_out[4 * t + 2] = ng;
     sweeps_out[4 * t + 3] = r;
   }
-  const bool ql_failed = st1 < 0 || st2 < 0;
-  // sort mu descending, lambda = 1/mu - 1 ascending
+  // mu descending (the eigensolver returns them ascending), lambda = 1/mu - 1 ascending
   double* lam = lam_out + lamoff[t];
   int* ord = keep;  // reused (r entries)
   if (tid == 0) {
-    for (int a = 0; a < r; ++a) ord[a] = a;
-    for (int a = 1; a < r; ++a) {
-      const int v = ord[a];
-      const double mv = d[v];
-      int b = a - 1;
-      while (b >= 0 && d[ord[b]] < mv) {
-        ord[b + 1] = ord[b];
-        --b;
-      }
-      ord[b + 1] = v;
+    int bad = sh_bad;
+    for (int a = 0; a < r; ++a) {
+      ord[a] = r - 1 - a;
+      bad |= !isfinite(d[a]);
     }
+    sh_bad = bad;
     int m = 0, nl = 0;
     for (int a = 0; a < r && nl < no; ++a) {
       const double mu = d[ord[a]];
@@ -411,7 +414,7 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
     if (tid == 0) status[t] = ST_NOTSPD;
     return;
   }
-  if (tid == 0) status[t] = ql_failed ? ST_NOCONV : ST_DONE;
+  if (tid == 0) status[t] = sh_bad ? ST_NOCONV : ST_DONE;
 }
 
 // Dense lower factor (column-major, n x n) -> the row and column band layouts with
@@ -550,7 +553,7 @@ void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_
                         double eps_reg, double* lam_out, const i64* lamoff, int* m_out,
                         int* status, int* rank_out, int* sweeps_out, int ng_max) {
   if (!nt) return;
-  const size_t vecs = 7 * (size_t)ng_max * sizeof(double);
+  const size_t vecs = 15 * (size_t)ng_max * sizeof(double);
   const size_t full = vecs + (size_t)ng_max * ng_max * sizeof(double);
   const int in_lds = full <= 158 * 1024;  // 160 KB of LDS per workgroup, less the static part
   const size_t lds = in_lds ? full : vecs;

@@ -1297,8 +1297,9 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
   std::vector<int> rkh;
   {
     // flops of the two symmetric eigendecompositions (sizes ng and r): Householder
-    // tridiagonalisation and accumulation of Q, 8/3 n^3, and the QL rotations applied
-    // to the eigenvectors, counted as 3 n^2 per QL step (steps reported by the kernel)
+    // tridiagonalisation and accumulation of Q, 8/3 n^3; the divide-and-conquer merges'
+    // eigenvector products, 8/3 n^3 (2 s^2 k per merge of width s with k roots, summed
+    // over the levels with k = s); the back-transformation Q W, 2 n^3
     ProfScope pscope(c, PR_COARSE_GEVP);
     launch_coarse_gevp(s, Pc, dng.p, dno.p, aoff.p, Abar.p, CL.loff.p, CL.Lo.p, dsoff.p,
                        scratch.p, c->eta, c->opt.nev_max, c->opt.eps_reg_rel, CL.lam.p, dlamoff.p,
@@ -1311,22 +1312,20 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
     for (int i = 0; i < Pc; ++i)
       for (int q = 0; q < 2; ++q) {
         const double nn = sw[4 * i + 2 + q];
-        fl += 8.0 / 3.0 * nn * nn * nn + 3.0 * nn * nn * std::max(sw[4 * i + q], 0);
+        fl += 22.0 / 3.0 * nn * nn * nn;
       }
     pscope.flops = fl;
   }
   std::vector<int> stv = st.download(s);
   vlog(c, "coarse: GEVP kernel", &tv);
   if (c->opt.verbose) {
-    int ngm = 0, s1 = 0, s2 = 0, rmax = 0;
+    int ngm = 0, rmax = 0;
     for (int i = 0; i < Pc; ++i) {
       ngm = std::max(ngm, CL.ng[i]);
-      s1 = std::max(s1, sw[4 * i]);
-      s2 = std::max(s2, sw[4 * i + 1]);
       rmax = std::max(rmax, rkh[i]);
     }
-    fprintf(stderr, "msdd:   coarse level %d: %d subdomains, ng max %d, rank max %d, QL steps max %d / %d\n",
-            l, Pc, ngm, rmax, s1, s2);
+    fprintf(stderr, "msdd:   coarse level %d: %d subdomains, ng max %d, rank max %d\n", l, Pc,
+            ngm, rmax);
   }
   check_status(stv, "coarse GEVP (eigensolver or Cholesky of the owned block)");
   CL.m = mo.download(s);

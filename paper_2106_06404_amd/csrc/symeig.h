@@ -17,24 +17,19 @@
 #pragma once
 #include "common.h"
 
+// Householder reduction of the n x n symmetric A (row-major, LDS or global) to
+// tridiagonal form: d (diagonal), w[0..n) (subdiagonal, e[i] = T(i+1, i), e[n-1] = 0),
+// w[n..2n) the Householder scalars, w[2n..4n) scratch; the Householder vectors are left
+// in the strictly lower part of A.  n >= 2.  All threads must call it.
 template <typename R>
-__device__ __forceinline__ int wg_syev(int n, R* A, R* Zt, R* Zl, R* d, R* w, R* red) {
+__device__ __forceinline__ void wg_tridiagonalize(int n, R* A, R* d, R* w, R* red) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  R* e = w;          // subdiagonal: e[i] = T(i+1, i)
-  R* beta = w + n;   // Householder scalars
-  R* v = w + 2 * n;   // current Householder vector / rotation cosines (buffer 0)
-  R* sn = w + 3 * n;  // rotation sines (buffer 0); w + 4n, w + 5n: buffer 1
-  __shared__ R sh_alpha, sh_beta, sh_k;
-  __shared__ int sh_state[5];  // l, m, lo, iterations at l, failed
-  if (n == 1) {
-    if (tid == 0) {
-      d[0] = A[0];
-      Zt[0] = (R)1;
-    }
-    __syncthreads();
-    return 0;
-  }
-  // ---- 1. tridiagonalisation: for k = 0..n-3, H_k = I - beta v v^T zeroes A[k+2.., k]
+  R* e = w;
+  R* beta = w + n;
+  R* v = w + 2 * n;
+  R* sn = w + 3 * n;
+  __shared__ R sh_alpha, sh_beta;
+  // tridiagonalisation: for k = 0..n-3, H_k = I - beta v v^T zeroes A[k+2.., k]
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;  // length of the vector (rows k+1..n-1)
     R part = 0;
@@ -95,7 +90,17 @@ __device__ __forceinline__ int wg_syev(int n, R* A, R* Zt, R* Zl, R* d, R* w, R*
     e[n - 1] = 0;
   }
   __syncthreads();
-  // ---- 2. Q = H_0 H_1 ... H_{n-3}, accumulated backwards, stored transposed in Zt
+}
+
+// Q = H_0 H_1 ... H_{n-3} from the reflectors left by wg_tridiagonalize, stored
+// transposed in Zt (Zt[a*n + k] = Q(k, a)).  All threads must call it.
+template <typename R>
+__device__ __forceinline__ void wg_accumulate_q(int n, const R* A, R* Zt, R* w) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const R* beta = w + n;
+  R* v = w + 2 * n;
+  R* sn = w + 3 * n;
+  // accumulated backwards
   for (i64 t = tid; t < (i64)n * n; t += nt) Zt[t] = (t / n == t % n) ? (R)1 : (R)0;
   __syncthreads();
   for (int k = n - 3; k >= 0; --k) {
@@ -122,6 +127,23 @@ __device__ __forceinline__ int wg_syev(int n, R* A, R* Zt, R* Zl, R* d, R* w, R*
     }
     __syncthreads();
   }
+}
+
+template <typename R>
+__device__ __forceinline__ int wg_syev(int n, R* A, R* Zt, R* Zl, R* d, R* w, R* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  R* e = w;          // subdiagonal: e[i] = T(i+1, i)
+  __shared__ int sh_state[5];  // l, m, lo, iterations at l, failed
+  if (n == 1) {
+    if (tid == 0) {
+      d[0] = A[0];
+      Zt[0] = (R)1;
+    }
+    __syncthreads();
+    return 0;
+  }
+  wg_tridiagonalize(n, A, d, w, red);
+  wg_accumulate_q(n, A, Zt, w);
   // the QL rotations run on the LDS copy Zl when there is one
   if (Zl) {
     for (i64 t = tid; t < (i64)n * n; t += nt) Zl[t] = Zt[t];
@@ -388,4 +410,64 @@ __device__ __forceinline__ int wg_jacobi(int n, R* A, R* Zt, R* d) {
   for (int t = tid; t < n; t += nt) d[t] = A[t * n + t];
   __syncthreads();
   return sweeps < 40 ? sweeps : -1;
+}
+
+#include "tridiag_dc.h"
+
+// Dense symmetric eigensolver through the tridiagonal divide-and-conquer method:
+// Householder reduction (wg_tridiagonalize), Q accumulated (wg_accumulate_q), the
+// tridiagonal problem solved by wg_tridiag_dc with its eigenvector matrix W kept in A's
+// storage (free once Q is formed), and Zt = (Q W)^T.
+//   A  : n x n symmetric, row-major (LDS or global); destroyed.
+//   Zt : n x n output (global), Zt[a*n + k] = component k of eigenvector a.
+//   U, Wn : n x n global workspace (distinct from A and Zt).
+//   d  : n eigenvalues (LDS), ascending, d[a] belongs to eigenvector a.
+//   w  : LDS workspace of 14n doubles.
+// All threads of the workgroup must call it.
+__device__ __forceinline__ void wg_syev_dc(int n, double* A, double* Zt, double* U, double* Wn,
+                                           double* d, double* w, double* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (n <= 0) return;
+  if (n == 1) {
+    if (tid == 0) {
+      d[0] = A[0];
+      Zt[0] = 1.0;
+    }
+    __syncthreads();
+    return;
+  }
+  wg_tridiagonalize(n, A, d, w, red);
+  wg_accumulate_q(n, A, Zt, w);
+  wg_tridiag_dc(n, d, w, A, U, Wn, w + n);
+  // Wn[a*n + k] = sum_b Q(k, b) W(b, a) = sum_b Zt[b*n + k] A[b*n + a], 4 x 4 tiles
+  const int tp = (n + 3) / 4;
+  for (int it = tid; it < tp * tp; it += nt) {
+    const int a0 = 4 * (it / tp), k0 = 4 * (it % tp);
+    const int amax = min(4, n - a0), kmax = min(4, n - k0);
+    double acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    for (int b = 0; b < n; ++b) {
+      double wv[4], qv[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) wv[x] = x < amax ? A[(i64)b * n + a0 + x] : 0.0;
+#pragma unroll
+      for (int y = 0; y < 4; ++y) qv[y] = y < kmax ? Zt[(i64)b * n + k0 + y] : 0.0;
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] += wv[x] * qv[y];
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+      if (x < amax)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          if (y < kmax) Wn[(i64)(a0 + x) * n + k0 + y] = acc[x][y];
+  }
+  __syncthreads();
+  for (i64 t = tid; t < (i64)n * n; t += nt) Zt[t] = Wn[t];
+  __syncthreads();
 }

@@ -1,0 +1,454 @@
+// Workgroup-parallel divide-and-conquer eigensolver for a symmetric tridiagonal matrix
+// (Cuppen's method with the Gu-Eisenstat eigenvector formula; Golub and Van Loan,
+// "Matrix Computations", Sec. 8.4).  The matrix is torn into 1 x 1 leaves by rank-one
+// tears at every off-diagonal entry, and the leaves are merged pairwise, level by
+// level, all merges of a level side by side:
+//
+//   T = diag(T1, T2) + rho v v^T,  v = (last row of Q1, +-first row of Q2) / sqrt(2),
+//
+// where T1 = Q1 D1 Q1^T and T2 = Q2 D2 Q2^T are the halves' eigendecompositions and a
+// coupling beta gives rho = 2 |beta| (the tear takes |beta| off both adjacent diagonal
+// entries, the sign of beta goes into v).  A merge
+//   1. deflates: components with rho |z_i| <= tol, and pairs of nearly equal poles
+//      (a plane rotation zeroes one z component when the off-diagonal entry it creates
+//      is <= tol), tol = 8 eps max(|D|, rho); the eigenvector columns take the rotations;
+//   2. solves the secular equation 1/rho + sum_i z_i^2 / (d_i - lambda) = 0 for each
+//      root between consecutive poles (one small group of lanes per root), each root
+//      kept as (origin pole, offset) so that every difference lambda - d_i is accurate;
+//   3. recomputes z from the roots (the Gu-Eisenstat product formula), so that the
+//      vectors z_i / (d_i - lambda_j) are orthogonal to working precision;
+//   4. multiplies the block's eigenvector columns by those vectors and sorts.
+//
+// Secular iteration (per root): the origin is the nearer end pole of the root's
+// interval (decided by the sign of f at the midpoint).  Each step models f as the
+// origin's own term w_o / (d_o - x) (exact weight) plus the rest of f replaced by one
+// pole matching its value, slope and curvature at the current point (a linear function
+// if the rest has no curvature, the fallback when the first model has no root in the
+// bracket); the model's root is solved for the offset from the origin directly.  A
+// bracket on the root is kept from the signs of f and a step leaving it becomes a
+// (geometric, across many orders of magnitude) bisection.  The iteration stops at the
+// rounding level of f, when the step is below 2 eps of the offset, or when the bracket
+// is exhausted.
+#pragma once
+#include "common.h"
+
+// LDS doubles used by wg_tridiag_dc for a matrix of order n.
+__host__ __device__ constexpr int dc_lds_doubles(int n) { return 13 * n; }
+
+namespace dcimpl {
+
+constexpr double kEps = 2.220446049250313e-16;
+
+__device__ __forceinline__ double grp_sum(double x, int G) {
+  for (int o = G >> 1; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
+  return x;
+}
+
+// root of a x^2 + b x + c0 = 0 strictly inside (lo, hi) closest to t; false if none
+__device__ __forceinline__ bool quad_pick(double a, double b, double c0, double t, double lo,
+                                          double hi, double* x) {
+  double x1, x2;
+  if (a == 0.0) {
+    if (b == 0.0) return false;
+    x1 = -c0 / b;
+    x2 = x1;
+  } else {
+    const double disc = fmax(b * b - 4.0 * a * c0, 0.0);
+    const double q = -0.5 * (b + copysign(sqrt(disc), b));
+    if (q == 0.0) return false;
+    x1 = q / a;
+    x2 = c0 / q;
+  }
+  const bool in1 = lo < x1 && x1 < hi, in2 = lo < x2 && x2 < hi;
+  if (in1 && in2) {
+    *x = fabs(x1 - t) <= fabs(x2 - t) ? x1 : x2;
+    return true;
+  }
+  if (in1) {
+    *x = x1;
+    return true;
+  }
+  if (in2) {
+    *x = x2;
+    return true;
+  }
+  return false;
+}
+
+// Root j (of k) of 1/rho + sum_i zK_i^2 / (dK_i - lambda) = 0, dK strictly increasing,
+// computed by the G lanes of a group (lane g); lambda = dK[org] + tau.  All lanes of the
+// group take the same path (butterfly sums are bitwise equal on every lane).
+__device__ __forceinline__ void secular_root(int j, int k, const double* dK, const double* zK,
+                                             double rho, int g, int G, int* org_out,
+                                             double* tau_out) {
+  const double irho = 1.0 / rho;
+  if (k == 1) {
+    *org_out = 0;
+    *tau_out = rho * zK[0] * zK[0];
+    return;
+  }
+  int org;
+  double lo, hi, tau;
+  if (j < k - 1) {
+    const double dj = dK[j];
+    const double mid = 0.5 * (dK[j + 1] - dj);
+    double s = 0.0;
+    for (int i = g; i < k; i += G) s += zK[i] * zK[i] / ((dK[i] - dj) - mid);
+    s = grp_sum(s, G);
+    if (irho + s >= 0.0) {
+      org = j;
+      lo = 0.0;
+      hi = mid;
+    } else {
+      org = j + 1;
+      lo = (dj - dK[j + 1]) + mid;
+      hi = 0.0;
+    }
+    tau = 0.5 * (lo + hi);
+  } else {
+    org = k - 1;
+    double zz = 0.0;
+    for (int i = g; i < k; i += G) zz += zK[i] * zK[i];
+    zz = grp_sum(zz, G);
+    const double dl = dK[org];
+    lo = 0.0;
+    hi = rho * zz;
+    for (int t = 0; t < 8; ++t) {  // f(hi) >= 0 up to rounding; widen if not
+      double s = 0.0;
+      for (int i = g; i < k; i += G) s += zK[i] * zK[i] / ((dK[i] - dl) - hi);
+      s = grp_sum(s, G);
+      if (irho + s >= 0.0) break;
+      hi *= 2.0;
+    }
+    tau = 0.5 * hi;
+  }
+  const double dorg = dK[org];
+  const double wo = zK[org] * zK[org];
+  for (int it = 0; it < 64; ++it) {
+    double f = 0.0, fa = 0.0, r1 = 0.0, r2 = 0.0;
+    for (int i = g; i < k; i += G) {
+      const double rr = 1.0 / ((dK[i] - dorg) - tau);
+      const double t = zK[i] * rr;
+      const double term = zK[i] * t;
+      f += term;
+      fa += fabs(term);
+      if (i != org) {
+        r1 += t * t;
+        r2 += t * t * rr;
+      }
+    }
+    f = grp_sum(f, G);
+    fa = grp_sum(fa, G);
+    r1 = grp_sum(r1, G);
+    r2 = 2.0 * grp_sum(r2, G);
+    const double F = irho + f;
+    if (!(fabs(F) > 8.0 * kEps * (irho + fa))) break;  // rounding level (or NaN)
+    if (F < 0.0)
+      lo = tau;
+    else
+      hi = tau;
+    const double R = F + wo / tau;  // f without the origin's term -wo / x, at x = tau
+    double tn = 0.0;
+    bool ok = false;
+    if (r2 != 0.0) {
+      const double ap = 2.0 * r1 / r2;  // osculating pole, offset from tau
+      const double ds = tau + ap;
+      const double S = r1 * ap * ap;
+      const double c = R - S / ap;
+      ok = quad_pick(-c, wo + S + c * ds, -wo * ds, tau, lo, hi, &tn);
+    }
+    if (!ok) ok = quad_pick(r1, R - r1 * tau, -wo, tau, lo, hi, &tn);
+    if (!ok) {
+      tn = 0.5 * (lo + hi);
+      if (lo > 0.0 && hi > 1e3 * lo)
+        tn = sqrt(lo * hi);
+      else if (hi < 0.0 && lo < 1e3 * hi)
+        tn = -sqrt(lo * hi);
+    }
+    const bool small_step = fabs(tn - tau) <= 2.0 * kEps * fabs(tn);
+    tau = tn;
+    if (small_step || hi - lo <= 2.0 * kEps * fmax(fabs(lo), fabs(hi))) break;
+  }
+  *org_out = org;
+  *tau_out = tau;
+}
+
+}  // namespace dcimpl
+
+// Eigen-decomposition of the symmetric tridiagonal matrix with diagonal d[0..n) and
+// off-diagonal e[i] = T(i+1, i), i < n-1 (e[n-1] is not read), by all threads of the
+// workgroup.
+//   d  : in: diagonal; out: eigenvalues in ascending order (LDS).
+//   W  : n x n output, row-major, W[r*n + a] = component r of eigenvector a (LDS or
+//        global; may not alias U or Wn).
+//   U, Wn : n x n global workspace.
+//   v  : LDS workspace of dc_lds_doubles(n) doubles.
+// All threads must call it.
+__device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e, double* W,
+                                              double* U, double* Wn, double* v) {
+  using namespace dcimpl;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* zs = v;           // z in sorted order; later the merged values
+  double* Ds = v + n;       // poles in sorted order
+  double* dK = v + 2 * n;   // non-deflated poles (compacted)
+  double* zK = v + 3 * n;   // their z (later the recomputed z)
+  double* tau = v + 4 * n;  // root offsets
+  double* Dd = v + 5 * n;   // deflated values
+  double* rc = v + 6 * n;   // deflation rotations: cosines, sines
+  double* rs = v + 7 * n;
+  int* ps = reinterpret_cast<int*>(v + 8 * n);  // sorted order; later new positions
+  int* K = ps + n;     // non-deflated columns (local index in the block)
+  int* Kd = K + n;     // deflated columns
+  int* org = Kd + n;   // root origins (index into the compacted poles)
+  int* rp = org + n;   // rotation column pairs
+  int* ri = rp + n;
+  int* kc = ri + n;    // per block (at the block's first index): non-deflated count,
+  int* dcn = kc + n;   // deflated count, rotation count
+  int* rcn = dcn + n;
+  // leaves: each coupling is torn out of both adjacent diagonal entries
+  for (int i = tid; i < n; i += nt) {
+    double di = d[i];
+    if (i > 0) di -= fabs(e[i - 1]);
+    if (i < n - 1) di -= fabs(e[i]);
+    d[i] = di;
+  }
+  for (i64 t = tid; t < (i64)n * n; t += nt) W[t] = (t / n == t % n) ? 1.0 : 0.0;
+  __syncthreads();
+  const double r2 = 0.70710678118654752440;
+  // lanes per secular root: as many as let one pass cover n roots
+  int G = 1;
+  while (G < 16 && 2 * G * n <= nt) G *= 2;
+  for (int bs = 1; bs < n; bs *= 2) {
+    const int bw = 2 * bs;  // merged block width
+    // ---- z (from the boundary rows of W) and the sorted order of the poles, scattered
+    // by rank (ties by index)
+    for (int gc = tid; gc < n; gc += nt) {
+      const int s0 = gc - gc % bw, c = gc - s0;
+      const int s = min(bw, n - s0), n1 = min(bs, s);
+      if (s == n1) continue;  // no partner: carried
+      const double beta = e[s0 + n1 - 1];
+      const double z = c < n1 ? W[(i64)(s0 + n1 - 1) * n + gc] * r2
+                              : (beta >= 0.0 ? r2 : -r2) * W[(i64)(s0 + n1) * n + gc];
+      const double da = d[gc];
+      int rank = 0;
+      for (int b = 0; b < s; ++b) {
+        const double db = d[s0 + b];
+        rank += (db < da || (db == da && b < c)) ? 1 : 0;
+      }
+      zs[s0 + rank] = z;
+      Ds[s0 + rank] = da;
+      ps[s0 + rank] = c;
+    }
+    __syncthreads();
+    // ---- deflation scan, one thread per merging block
+    for (int s0 = tid * bw; s0 < n; s0 += nt * bw) {
+      const int s = min(bw, n - s0), n1 = min(bs, s);
+      if (s == n1) continue;
+      const double rho = 2.0 * fabs(e[s0 + n1 - 1]);
+      double dmax = rho;
+      for (int p = 0; p < s; ++p) dmax = fmax(dmax, fabs(Ds[s0 + p]));
+      const double tol = 8.0 * kEps * dmax;
+      int k = 0, nd = 0, nr = 0, prev = -1;
+      double dp = 0.0, zp = 0.0;
+      for (int p = 0; p < s; ++p) {
+        const int i = ps[s0 + p];
+        double zi = zs[s0 + p], di = Ds[s0 + p];
+        if (rho * fabs(zi) <= tol) {
+          Kd[s0 + nd] = i;
+          Dd[s0 + nd] = di;
+          ++nd;
+          continue;
+        }
+        if (prev >= 0) {
+          const double t = sqrt(zp * zp + zi * zi);
+          const double c = zi / t, sn = zp / t;
+          if (fabs((di - dp) * c * sn) <= tol) {
+            // rotate (prev, i) so that prev's z vanishes; prev is deflated
+            rp[s0 + nr] = prev;
+            ri[s0 + nr] = i;
+            rc[s0 + nr] = c;
+            rs[s0 + nr] = sn;
+            ++nr;
+            Kd[s0 + nd] = prev;
+            Dd[s0 + nd] = c * c * dp + sn * sn * di;
+            ++nd;
+            di = sn * sn * dp + c * c * di;
+            zi = t;
+            --k;  // prev was the last non-deflated entry
+          }
+        }
+        K[s0 + k] = i;
+        dK[s0 + k] = di;
+        zK[s0 + k] = zi;
+        ++k;
+        prev = i;
+        dp = di;
+        zp = zi;
+      }
+      kc[s0] = k;
+      dcn[s0] = nd;
+      rcn[s0] = nr;
+    }
+    __syncthreads();
+    // ---- deflation rotations on the block's eigenvector columns (one thread per row,
+    // in order), and the secular roots (one group of G lanes per root)
+    for (int gr = tid; gr < n; gr += nt) {
+      const int s0 = gr - gr % bw;
+      const int s = min(bw, n - s0), n1 = min(bs, s);
+      if (s == n1) continue;
+      const int nr = rcn[s0];
+      double* Wr = W + (i64)gr * n + s0;
+      for (int q = 0; q < nr; ++q) {
+        const int a = rp[s0 + q], b = ri[s0 + q];
+        const double c = rc[s0 + q], sn = rs[s0 + q];
+        const double wa = Wr[a], wb = Wr[b];
+        Wr[a] = c * wa - sn * wb;
+        Wr[b] = sn * wa + c * wb;
+      }
+    }
+    {
+      const int g = tid % G;
+      for (int gj = tid / G; gj < n; gj += nt / G) {
+        const int s0 = gj - gj % bw, j = gj - s0;
+        const int s = min(bw, n - s0), n1 = min(bs, s);
+        if (s == n1 || j >= kc[s0]) continue;
+        int o;
+        double t;
+        secular_root(j, kc[s0], dK + s0, zK + s0, 2.0 * fabs(e[s0 + n1 - 1]), g, G, &o, &t);
+        if (g == 0) {
+          org[s0 + j] = o;
+          tau[s0 + j] = t;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- z recomputed from the roots: z_i^2 = prod_j (lambda_j - d_i) /
+    // (rho prod_{j != i} (d_j - d_i)), factors paired so that each is at most one
+    for (int gi = tid; gi < n; gi += nt) {
+      const int s0 = gi - gi % bw, i = gi - s0;
+      const int s = min(bw, n - s0), n1 = min(bs, s);
+      if (s == n1) continue;
+      const int k = kc[s0];
+      if (i >= k) continue;
+      const double* dk = dK + s0;
+      const double* tk = tau + s0;
+      const int* ok = org + s0;
+      const double di = dk[i];
+      const double rho = 2.0 * fabs(e[s0 + n1 - 1]);
+      double pr = ((dk[ok[k - 1]] - di) + tk[k - 1]) / rho;
+      for (int jj = 0; jj < i; ++jj) pr *= ((dk[ok[jj]] - di) + tk[jj]) / (dk[jj] - di);
+      for (int jj = i; jj < k - 1; ++jj) pr *= ((dk[ok[jj]] - di) + tk[jj]) / (dk[jj + 1] - di);
+      // own element only: no other thread reads zK in this phase
+      zK[gi] = copysign(sqrt(fmax(pr, 0.0)), zK[gi]);
+    }
+    __syncthreads();
+    // ---- eigenvectors of the rank-one problem, normalised, as the columns j < k of
+    // U (rows: the block's columns; deflated rows zero); merged values into zs
+    {
+      const int g = tid % G;
+      for (int gj = tid / G; gj < n; gj += nt / G) {
+        const int s0 = gj - gj % bw, j = gj - s0;
+        const int s = min(bw, n - s0), n1 = min(bs, s);
+        if (s == n1) continue;
+        const int k = kc[s0];
+        if (j >= k) {
+          const int q = j - k;  // deflated value q goes after the k roots
+          if (g == 0) zs[gj] = Dd[s0 + q];
+          continue;
+        }
+        const double dl = dK[s0 + org[s0 + j]], tj = tau[s0 + j];
+        double nrm = 0.0;
+        for (int i = g; i < k; i += G) {
+          const double u = zK[s0 + i] / ((dK[s0 + i] - dl) - tj);
+          nrm += u * u;
+        }
+        const double inv = 1.0 / sqrt(grp_sum(nrm, G));
+        for (int i = g; i < k; i += G) {
+          const double u = zK[s0 + i] / ((dK[s0 + i] - dl) - tj);
+          U[(i64)(s0 + K[s0 + i]) * n + s0 + j] = u * inv;
+        }
+        const int nd = s - k;
+        for (int q = g; q < nd; q += G) U[(i64)(s0 + Kd[s0 + q]) * n + s0 + j] = 0.0;
+        if (g == 0) zs[gj] = dl + tj;
+      }
+    }
+    __syncthreads();
+    // ---- positions in ascending order (rank, ties by index) and the new values
+    for (int ga = tid; ga < n; ga += nt) {
+      const int s0 = ga - ga % bw, a = ga - s0;
+      const int s = min(bw, n - s0), n1 = min(bs, s);
+      if (s == n1) continue;
+      const double va = zs[ga];
+      int rank = 0;
+      for (int b = 0; b < s; ++b) {
+        const double vb = zs[s0 + b];
+        rank += (vb < va || (vb == va && b < a)) ? 1 : 0;
+      }
+      ps[ga] = rank;
+      d[s0 + rank] = va;
+    }
+    __syncthreads();
+    // ---- new eigenvector columns: Wn(block rows, pos_j) = W(block) U(:, j) for the
+    // roots (4 x 4 output tiles per thread), deflated columns copied
+    {
+      const int tpb = (bw + 3) / 4;  // tiles per block side
+      const i64 items = (i64)((n + bw - 1) / bw) * tpb * tpb;
+      for (i64 it = tid; it < items; it += nt) {
+        const int b = (int)(it / ((i64)tpb * tpb));
+        const int rem = (int)(it - (i64)b * tpb * tpb);
+        const int rt = rem / tpb, ct = rem - rt * tpb;
+        const int s0 = b * bw;
+        const int s = min(bw, n - s0), n1 = min(bs, s);
+        if (s == n1) continue;
+        const int k = kc[s0];
+        const int r0 = 4 * rt, a0 = 4 * ct;
+        if (r0 >= s || a0 >= k) continue;
+        double acc[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+        const int rmax = min(4, s - r0), amax = min(4, k - a0);
+        for (int c = 0; c < s; ++c) {
+          double wv[4], uv[4];
+#pragma unroll
+          for (int x = 0; x < 4; ++x) wv[x] = x < rmax ? W[(i64)(s0 + r0 + x) * n + s0 + c] : 0.0;
+          const double* Ur = U + (i64)(s0 + c) * n + s0 + a0;
+#pragma unroll
+          for (int y = 0; y < 4; ++y) uv[y] = y < amax ? Ur[y] : 0.0;
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] += wv[x] * uv[y];
+        }
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          if (y < amax) {
+            const int col = s0 + ps[s0 + a0 + y];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+              if (x < rmax) Wn[(i64)(s0 + r0 + x) * n + col] = acc[x][y];
+          }
+      }
+      for (i64 it = tid; it < (i64)n * bw; it += nt) {
+        const int gr = (int)(it / bw), q = (int)(it - (i64)gr * bw);
+        const int s0 = gr - gr % bw;
+        const int s = min(bw, n - s0), n1 = min(bs, s);
+        if (s == n1) continue;
+        const int k = kc[s0];
+        if (q >= s - k) continue;
+        Wn[(i64)gr * n + s0 + ps[s0 + k + q]] = W[(i64)gr * n + s0 + Kd[s0 + q]];
+      }
+    }
+    __syncthreads();
+    // ---- merged blocks back into W
+    for (i64 it = tid; it < (i64)n * bw; it += nt) {
+      const int gr = (int)(it / bw), c = (int)(it - (i64)gr * bw);
+      const int s0 = gr - gr % bw;
+      const int s = min(bw, n - s0), n1 = min(bs, s);
+      if (s == n1 || c >= s) continue;
+      W[(i64)gr * n + s0 + c] = Wn[(i64)gr * n + s0 + c];
+    }
+    __syncthreads();
+  }
+}
