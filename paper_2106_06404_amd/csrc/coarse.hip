@@ -285,7 +285,7 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   double* Yc = C + g2;
   int* keep = reinterpret_cast<int*>(Yc + g2);
   __shared__ int sh_fail, sh_r, sh_m, sh_bad;
-  __shared__ double sh_smax, red[32];
+  __shared__ double sh_smax, red[64];
   // dynamic LDS: eigenvalues d (ng_max), workspace (14 ng_max), then (in_lds) the matrix
   // being diagonalised, later the tridiagonal problem's eigenvectors
   extern __shared__ __align__(16) unsigned char smem_raw[];

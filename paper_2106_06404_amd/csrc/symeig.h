@@ -19,69 +19,95 @@
 
 // Householder reduction of the n x n symmetric A (row-major, LDS or global) to
 // tridiagonal form: d (diagonal), w[0..n) (subdiagonal, e[i] = T(i+1, i), e[n-1] = 0),
-// w[n..2n) the Householder scalars, w[2n..4n) scratch; the Householder vectors are left
-// in the strictly lower part of A.  n >= 2.  All threads must call it.
+// w[n..2n) the Householder scalars (H_k = I - beta_k v_k v_k^T), w[2n..3n) scratch; the
+// Householder vectors are left in the strictly lower part of A (v_k in column k, rows
+// k+1..n-1).  n >= 2.  red: LDS, >= 48 entries.  Two barriers per column: the
+// reflector's norm comes from per-wavefront partial sums taken during the previous
+// column's update, and every thread derives the reflector from them itself.
 template <typename R>
 __device__ __forceinline__ void wg_tridiagonalize(int n, R* A, R* d, R* w, R* red) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6;
+  const int nw = (nt + 63) >> 6;
   R* e = w;
   R* beta = w + n;
-  R* v = w + 2 * n;
-  R* sn = w + 3 * n;
-  __shared__ R sh_alpha, sh_beta;
-  // tridiagonalisation: for k = 0..n-3, H_k = I - beta v v^T zeroes A[k+2.., k]
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;  // length of the vector (rows k+1..n-1)
+  R* p = w + 2 * n;
+  // norm partials of column 0 below the subdiagonal
+  {
     R part = 0;
-    for (int i = k + 2 + tid; i < n; i += nt) part += A[(i64)i * n + k] * A[(i64)i * n + k];
-    const R sig = block_sum(part, red);
+    for (int i = 2 + tid; i < n; i += nt) part += A[(i64)i * n] * A[(i64)i * n];
+    part = wave_sum(part);
+    if (lane == 0) red[wv] = part;
+  }
+  __syncthreads();
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;  // reflector length (rows k+1..n-1)
+    const int pb = (k & 1) * 16, pn = 16 - pb;  // norm partials: this column's, the next's
+    R sig = 0;
+    for (int q = 0; q < nw; ++q) sig += red[pb + q];
+    const R x0 = A[(i64)(k + 1) * n + k];
+    R bt = 0, alpha = x0, v0 = x0;
+    if (sig != (R)0) {
+      const R nx = sqrt(x0 * x0 + sig);
+      alpha = x0 >= 0 ? -nx : nx;
+      v0 = x0 - alpha;
+      bt = (R)2 / (v0 * v0 + sig);
+    }
     if (tid == 0) {
-      const R x0 = A[(i64)(k + 1) * n + k];
-      if (sig == (R)0) {  // already reduced: no reflection
-        sh_alpha = x0;
-        sh_beta = 0;
-      } else {
-        const R nx = sqrt(x0 * x0 + sig);
-        const R alpha = x0 >= 0 ? -nx : nx;
-        const R v0 = x0 - alpha;
-        sh_alpha = alpha;
-        sh_beta = (R)2 / (v0 * v0 + sig);
-        A[(i64)(k + 1) * n + k] = v0;  // v stored in column k below the diagonal
-      }
-      e[k] = sh_alpha;
-      beta[k] = sh_beta;
+      e[k] = alpha;
+      beta[k] = bt;
     }
+    const R* vc = A + (i64)(k + 1) * n + k;  // v_i = vc[i n] for i >= 1, v_0 = v0
+    if (bt == (R)0) {  // already reduced: only the next column's partials
+      R part = 0;
+      for (int i = k + 3 + tid; i < n; i += nt) part += A[(i64)i * n + k + 1] * A[(i64)i * n + k + 1];
+      part = wave_sum(part);
+      if (lane == 0) red[pn + wv] = part;
+      __syncthreads();
+      continue;
+    }
+    // p = bt A_sub v, tpr threads per row; partials of v . p
+    int tpr = 1;
+    while (tpr < 16 && 2 * tpr * m <= nt) tpr *= 2;
+    R vp = 0;
+    for (int i0 = 0; i0 < m; i0 += nt / tpr) {
+      const int i = i0 + tid / tpr, l = tid & (tpr - 1);
+      R acc = 0;
+      if (i < m) {
+        const R* Ar = A + (i64)(k + 1 + i) * n + (k + 1);
+        for (int j = l; j < m; j += tpr) acc += Ar[j] * (j == 0 ? v0 : vc[(i64)j * n]);
+      }
+      for (int o = tpr >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, tpr);
+      if (i < m && l == 0) {
+        const R pi = bt * acc;
+        p[i] = pi;
+        vp += (i == 0 ? v0 : vc[(i64)i * n]) * pi;
+      }
+    }
+    vp = wave_sum(vp);
+    if (lane == 0) red[32 + wv] = vp;
     __syncthreads();
-    const R bt = sh_beta;
-    if (bt != (R)0) {
-      for (int i = tid; i < m; i += nt) v[i] = A[(i64)(k + 1 + i) * n + k];
-      __syncthreads();
-      // p = bt * A_sub v  (rows k+1..n-1), 8 threads per row
-      for (int i0 = 0; i0 < m; i0 += nt / 8) {
-        const int i = i0 + tid / 8, l8 = tid & 7;
-        R acc = 0;
-        if (i < m) {
-          const R* Ar = A + (i64)(k + 1 + i) * n + (k + 1);
-          for (int j = l8; j < m; j += 8) acc += Ar[j] * v[j];
-        }
-        for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 8);
-        if (i < m && l8 == 0) sn[i] = bt * acc;
+    R kp = 0;
+    for (int q = 0; q < nw; ++q) kp += red[32 + q];
+    const R Kc = (R)0.5 * bt * kp;
+    // A_sub -= v q^T + q v^T with q = p - Kc v; 32 columns per row group; the next
+    // column's norm partials from the updated values
+    R part = 0;
+    const int tr = tid >> 5, tc = tid & 31, ng = nt >> 5;
+    for (int i = tr; i < m; i += ng) {
+      const R vi = i == 0 ? v0 : vc[(i64)i * n];
+      const R qi = p[i] - Kc * vi;
+      R* Ar = A + (i64)(k + 1 + i) * n + (k + 1);
+      for (int j = tc; j < m; j += 32) {
+        const R vj = j == 0 ? v0 : vc[(i64)j * n];
+        const R nv = Ar[j] - (vi * (p[j] - Kc * vj) + qi * vj);
+        Ar[j] = nv;
+        if (j == 0 && i >= 2) part += nv * nv;
       }
-      __syncthreads();
-      // K = bt/2 v^T p ; q = p - K v (in sn)
-      R kp = 0;
-      for (int i = tid; i < m; i += nt) kp += v[i] * sn[i];
-      kp = block_sum(kp, red);
-      const R Kc = (R)0.5 * bt * kp;
-      for (int i = tid; i < m; i += nt) sn[i] -= Kc * v[i];
-      __syncthreads();
-      // A_sub -= v q^T + q v^T
-      for (i64 t = tid; t < (i64)m * m; t += nt) {
-        const int i = (int)(t / m), j = (int)(t - (i64)i * m);
-        A[(i64)(k + 1 + i) * n + (k + 1 + j)] -= v[i] * sn[j] + sn[i] * v[j];
-      }
-      __syncthreads();
     }
+    part = wave_sum(part);
+    if (lane == 0) red[pn + wv] = part;
+    if (tid == 0) A[(i64)(k + 1) * n + k] = v0;  // v stored in column k below the diagonal
+    __syncthreads();
   }
   for (int i = tid; i < n; i += nt) d[i] = A[(i64)i * n + i];
   if (tid == 0) {
@@ -93,37 +119,39 @@ __device__ __forceinline__ void wg_tridiagonalize(int n, R* A, R* d, R* w, R* re
 }
 
 // Q = H_0 H_1 ... H_{n-3} from the reflectors left by wg_tridiagonalize, stored
-// transposed in Zt (Zt[a*n + k] = Q(k, a)).  All threads must call it.
+// transposed in Zt (Zt[a*n + k] = Q(k, a)); applied backwards, two barriers per
+// reflector.  All threads must call it.
 template <typename R>
 __device__ __forceinline__ void wg_accumulate_q(int n, const R* A, R* Zt, R* w) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const R* beta = w + n;
-  R* v = w + 2 * n;
-  R* sn = w + 3 * n;
-  // accumulated backwards
+  R* sn = w + 2 * n;
   for (i64 t = tid; t < (i64)n * n; t += nt) Zt[t] = (t / n == t % n) ? (R)1 : (R)0;
   __syncthreads();
   for (int k = n - 3; k >= 0; --k) {
     const R bt = beta[k];
     if (bt == (R)0) continue;
     const int m = n - k - 1;
-    for (int i = tid; i < m; i += nt) v[i] = A[(i64)(k + 1 + i) * n + k];
-    __syncthreads();
-    // Q[k+1:, k+1:] -= bt v (v^T Q[k+1:, k+1:]):  wq_c = v . Zt[c][k+1:], 8 threads per c
-    for (int c0 = 0; c0 < m; c0 += nt / 8) {
-      const int c = c0 + tid / 8, l8 = tid & 7;
+    const R* vc = A + (i64)(k + 1) * n + k;  // v_r = vc[r n]
+    // Q[k+1:, k+1:] -= bt v (v^T Q[k+1:, k+1:]):  sn_c = bt v . Zt[c][k+1:]
+    int tpr = 1;
+    while (tpr < 16 && 2 * tpr * m <= nt) tpr *= 2;
+    for (int c0 = 0; c0 < m; c0 += nt / tpr) {
+      const int c = c0 + tid / tpr, l = tid & (tpr - 1);
       R acc = 0;
       if (c < m) {
         const R* Zr = Zt + (i64)(k + 1 + c) * n + (k + 1);
-        for (int r = l8; r < m; r += 8) acc += Zr[r] * v[r];
+        for (int r = l; r < m; r += tpr) acc += Zr[r] * vc[(i64)r * n];
       }
-      for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 8);
-      if (c < m && l8 == 0) sn[c] = bt * acc;
+      for (int o = tpr >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, tpr);
+      if (c < m && l == 0) sn[c] = bt * acc;
     }
     __syncthreads();
-    for (i64 t = tid; t < (i64)m * m; t += nt) {
-      const int c = (int)(t / m), r = (int)(t - (i64)c * m);
-      Zt[(i64)(k + 1 + c) * n + (k + 1 + r)] -= sn[c] * v[r];
+    const int tr = tid >> 5, tc = tid & 31, ng = nt >> 5;
+    for (int c = tr; c < m; c += ng) {
+      const R sc = sn[c];
+      R* Zr = Zt + (i64)(k + 1 + c) * n + (k + 1);
+      for (int r = tc; r < m; r += 32) Zr[r] -= sc * vc[(i64)r * n];
     }
     __syncthreads();
   }
@@ -422,7 +450,7 @@ __device__ __forceinline__ int wg_jacobi(int n, R* A, R* Zt, R* d) {
 //   Zt : n x n output (global), Zt[a*n + k] = component k of eigenvector a.
 //   U, Wn : n x n global workspace (distinct from A and Zt).
 //   d  : n eigenvalues (LDS), ascending, d[a] belongs to eigenvector a.
-//   w  : LDS workspace of 14n doubles.
+//   w  : LDS workspace of 14n doubles; red: LDS, >= 48 entries.
 // All threads of the workgroup must call it.
 __device__ __forceinline__ void wg_syev_dc(int n, double* A, double* Zt, double* U, double* Wn,
                                            double* d, double* w, double* red) {
@@ -449,6 +477,7 @@ __device__ __forceinline__ void wg_syev_dc(int n, double* A, double* Zt, double*
     for (int x = 0; x < 4; ++x)
 #pragma unroll
       for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+#pragma unroll 2
     for (int b = 0; b < n; ++b) {
       double wv[4], qv[4];
 #pragma unroll

@@ -260,9 +260,11 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
           continue;
         }
         if (prev >= 0) {
-          const double t = sqrt(zp * zp + zi * zi);
-          const double c = zi / t, sn = zp / t;
-          if (fabs((di - dp) * c * sn) <= tol) {
+          // the rotation's off-diagonal entry is (di - dp) c s with c s = zi zp / t^2
+          const double t2 = zp * zp + zi * zi;
+          if (fabs((di - dp) * zi * zp) <= tol * t2) {
+            const double t = sqrt(t2);
+            const double c = zi / t, sn = zp / t;
             // rotate (prev, i) so that prev's z vanishes; prev is deflated
             rp[s0 + nr] = prev;
             ri[s0 + nr] = i;
@@ -409,6 +411,7 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
         const int rmax = min(4, s - r0), amax = min(4, k - a0);
+#pragma unroll 2
         for (int c = 0; c < s; ++c) {
           double wv[4], uv[4];
 #pragma unroll
