@@ -286,12 +286,12 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   int* keep = reinterpret_cast<int*>(Yc + g2);
   __shared__ int sh_fail, sh_r, sh_m, sh_bad;
   __shared__ double sh_smax, red[64];
-  // dynamic LDS: eigenvalues d (ng_max), workspace (14 ng_max), then (in_lds) the matrix
+  // dynamic LDS: eigenvalues d (ng_max), workspace (syev_dc_ws), then (in_lds) the matrix
   // being diagonalised, later the tridiagonal problem's eigenvectors
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* d = reinterpret_cast<double*>(smem_raw);
   double* wsp = d + ng_max;
-  double* Alds = wsp + 14 * ng_max;
+  double* Alds = wsp + syev_dc_ws(ng_max);
   const int tid = threadIdx.x, nt = blockDim.x;
   if (no == 0) {
     if (tid == 0) {
@@ -553,9 +553,12 @@ void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_
                         double eps_reg, double* lam_out, const i64* lamoff, int* m_out,
                         int* status, int* rank_out, int* sweeps_out, int ng_max) {
   if (!nt) return;
-  const size_t vecs = 15 * (size_t)ng_max * sizeof(double);
+  const size_t vecs = ((size_t)ng_max + syev_dc_ws(ng_max)) * sizeof(double);
   const size_t full = vecs + (size_t)ng_max * ng_max * sizeof(double);
-  const int in_lds = full <= 158 * 1024;  // 160 KB of LDS per workgroup, less the static part
+  hipFuncAttributes fa;
+  size_t stat = 4096;
+  if (hipFuncGetAttributes(&fa, (const void*)k_coarse_gevp) == hipSuccess) stat = fa.sharedSizeBytes;
+  const int in_lds = full + stat <= 160 * 1024;  // LDS per workgroup, with the static part
   const size_t lds = in_lds ? full : vecs;
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_coarse_gevp,

@@ -1,19 +1,7 @@
-// Workgroup-parallel symmetric eigensolver for one dense n x n matrix:
-// Householder reduction to tridiagonal form, then implicit QL iteration with
-// Wilkinson-type shifts on the tridiagonal matrix (the textbook symmetric QR/QL
-// algorithm, Golub and Van Loan, "Matrix Computations", Sec. 8.3), with the
-// orthogonal transformations accumulated into the eigenvector matrix.
-//
-//   A  : n x n symmetric, row-major (LDS or global); overwritten (the Householder
-//        vectors are kept in its strictly lower part).
-//   Zt : n x n output, eigenvectors stored transposed: Zt[a*n + k] = component k of
-//        eigenvector a (so rotations of eigenvector pairs touch two contiguous rows).
-//        If Zl is not null, the QL rotations run on the copy Zl (LDS, n x n) and the
-//        result is copied to Zt.
-//   d  : n eigenvalues (LDS), unsorted, d[a] belongs to eigenvector a.
-//   w  : LDS workspace of 6n entries.
-// All threads of the workgroup must call it.  Returns the number of QL steps, or -1
-// if some eigenvalue needed more than 60 QL steps.
+// Workgroup-parallel dense symmetric eigensolvers: Householder reduction to
+// tridiagonal form followed by divide and conquer (wg_syev_dc, for the coarse
+// generating systems), and a parallel cyclic Jacobi method for small, nearly diagonal
+// matrices (wg_jacobi, for the Rayleigh-Ritz problems of the subspace iteration).
 #pragma once
 #include "common.h"
 
@@ -118,222 +106,6 @@ __device__ __forceinline__ void wg_tridiagonalize(int n, R* A, R* d, R* w, R* re
   __syncthreads();
 }
 
-// Q = H_0 H_1 ... H_{n-3} from the reflectors left by wg_tridiagonalize, stored
-// transposed in Zt (Zt[a*n + k] = Q(k, a)); applied backwards, two barriers per
-// reflector.  All threads must call it.
-template <typename R>
-__device__ __forceinline__ void wg_accumulate_q(int n, const R* A, R* Zt, R* w) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const R* beta = w + n;
-  R* sn = w + 2 * n;
-  for (i64 t = tid; t < (i64)n * n; t += nt) Zt[t] = (t / n == t % n) ? (R)1 : (R)0;
-  __syncthreads();
-  for (int k = n - 3; k >= 0; --k) {
-    const R bt = beta[k];
-    if (bt == (R)0) continue;
-    const int m = n - k - 1;
-    const R* vc = A + (i64)(k + 1) * n + k;  // v_r = vc[r n]
-    // Q[k+1:, k+1:] -= bt v (v^T Q[k+1:, k+1:]):  sn_c = bt v . Zt[c][k+1:]
-    int tpr = 1;
-    while (tpr < 16 && 2 * tpr * m <= nt) tpr *= 2;
-    for (int c0 = 0; c0 < m; c0 += nt / tpr) {
-      const int c = c0 + tid / tpr, l = tid & (tpr - 1);
-      R acc = 0;
-      if (c < m) {
-        const R* Zr = Zt + (i64)(k + 1 + c) * n + (k + 1);
-        for (int r = l; r < m; r += tpr) acc += Zr[r] * vc[(i64)r * n];
-      }
-      for (int o = tpr >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, tpr);
-      if (c < m && l == 0) sn[c] = bt * acc;
-    }
-    __syncthreads();
-    const int tr = tid >> 5, tc = tid & 31, ng = nt >> 5;
-    for (int c = tr; c < m; c += ng) {
-      const R sc = sn[c];
-      R* Zr = Zt + (i64)(k + 1 + c) * n + (k + 1);
-      for (int r = tc; r < m; r += 32) Zr[r] -= sc * vc[(i64)r * n];
-    }
-    __syncthreads();
-  }
-}
-
-template <typename R>
-__device__ __forceinline__ int wg_syev(int n, R* A, R* Zt, R* Zl, R* d, R* w, R* red) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  R* e = w;          // subdiagonal: e[i] = T(i+1, i)
-  __shared__ int sh_state[5];  // l, m, lo, iterations at l, failed
-  if (n == 1) {
-    if (tid == 0) {
-      d[0] = A[0];
-      Zt[0] = (R)1;
-    }
-    __syncthreads();
-    return 0;
-  }
-  wg_tridiagonalize(n, A, d, w, red);
-  wg_accumulate_q(n, A, Zt, w);
-  // the QL rotations run on the LDS copy Zl when there is one
-  if (Zl) {
-    for (i64 t = tid; t < (i64)n * n; t += nt) Zl[t] = Zt[t];
-    __syncthreads();
-  }
-  // ---- 3. implicit QL on (d, e).  Wavefront 0 runs the control: it finds the next
-  // unreduced block with a wave-wide scan of e (deflation test relative to the norm of
-  // T: absolute accuracy eps ||A|| for every eigenvalue; a test relative to the
-  // neighbouring diagonal entries can stall on clusters near zero) and one lane computes
-  // the step's rotations, a dependent chain, with its loads issued one rotation ahead.
-  // The other wavefronts apply the previous step's rotations to the rows of Z
-  // meanwhile (rotation arrays double buffered), so a step costs the longer of the two.
-  const R eps = (R)2.220446049250313e-16;
-  __shared__ R sh_tnorm;
-  __shared__ int q_m[2], q_lo[2], q_has[2];
-  // rotation buffer b: cosines at w + (2 + 2b) n, sines at w + (3 + 2b) n (offsets from w,
-  // so that the compiler keeps them in the LDS address space)
-  if (tid == 0) {
-    R tn = 0;
-    for (int i = 0; i < n; ++i) tn = fmax(tn, fabs(d[i]) + fabs(e[i]));
-    sh_tnorm = tn;
-    sh_state[4] = 0;
-  }
-  __syncthreads();
-  const R thr = eps * sh_tnorm;
-  const int lane = tid & 63;
-  // wavefront-0 state (uniform over its lanes)
-  int ql_l = 0, ql_it = 0, ql_failed = 0;
-  // one QL step into buffer b (wavefront 0 only); q_has[b] = 0 when all have converged
-  auto ql_step = [&](int b) {
-    int m = 0;
-    while (ql_l < n) {
-      // first m >= l with |e[m]| <= thr, or n - 1
-      m = -1;
-      for (int base = ql_l; base < n - 1 && m < 0; base += 64) {
-        const int idx = base + lane;
-        const bool hit = idx >= n - 1 || fabs(e[idx]) <= thr;
-        const unsigned long long mk = __ballot(hit);
-        if (mk) m = base + __ffsll((long long)mk) - 1;
-      }
-      if (m < 0 || m > n - 1) m = n - 1;
-      if (m == ql_l || ql_it >= 60) {  // eigenvalue l converged (or given up)
-        if (m != ql_l) ql_failed = 1;
-        ++ql_l;
-        ql_it = 0;
-        continue;
-      }
-      break;
-    }
-    if (ql_l >= n) {
-      if (lane == 0) q_has[b] = 0;
-      return;
-    }
-    ++ql_it;
-    const int l = ql_l;
-    if (lane == 0) {
-      R* cb = w + (2 + 2 * b) * n;
-      R* sb = cb + n;
-      R g = (d[l + 1] - d[l]) / ((R)2 * e[l]);
-      R r = sqrt(g * g + (R)1);
-      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
-      R s = 1, c = 1, p = 0;
-      int i = m - 1, lo = l;
-      R ei = e[i], di = d[i], di1 = d[i + 1];
-      for (; i >= l; --i) {
-        // values of the next rotation, loaded before this one's stores (they are not
-        // written by it)
-        const int ip = i > 0 ? i - 1 : 0;  // unconditional (clamped) loads, no branch
-        const R en = e[ip];
-        const R dn = d[ip];
-        const R f = s * ei, bb = c * ei;
-        // r = sqrt(f^2 + g^2), s = f / r, c = g / r through one reciprocal square root:
-        // the rotation chain is the critical path of the whole solver, and this halves
-        // its dependent latency against a square root and two divisions
-        const R q = f * f + g * g;
-        if (q == (R)0) {  // deflation inside the sweep
-          e[i + 1] = 0;
-          d[i + 1] = di1 - p;
-          e[m] = 0;
-          lo = i + 1;
-          break;
-        }
-        const R ri = rsqrt(q);
-        r = q * ri;
-        e[i + 1] = r;
-        s = f * ri;
-        c = g * ri;
-        g = di1 - p;
-        r = (di - g) * s + (R)2 * c * bb;
-        p = s * r;
-        d[i + 1] = g + p;
-        g = c * r - bb;
-        cb[i] = c;
-        sb[i] = s;
-        di1 = di;
-        ei = en;
-        di = dn;
-      }
-      if (i < l) {
-        d[l] -= p;
-        e[l] = g;
-        e[m] = 0;
-      }
-      q_m[b] = m;
-      q_lo[b] = lo;
-      q_has[b] = 1;
-    }
-  };
-  if (tid < 64) ql_step(0);
-  __syncthreads();
-  int steps = 0, cur = 0;
-  while (q_has[cur]) {
-    if (tid < 64) {
-      ql_step(cur ^ 1);
-    } else {
-      // rotations i = m-1 down to lo on eigenvector rows (i, i+1) of Z (transposed),
-      // eight at a time with their operands loaded first; Z is the LDS copy when there
-      // is one (two call sites, so that each keeps its address space)
-      const int m = q_m[cur], lo = q_lo[cur];
-      const R* cb = w + (2 + 2 * cur) * n;
-      const R* sb = cb + n;
-      auto apply = [&](R* Z) {
-        for (int k = tid - 64; k < n; k += nt - 64) {
-          R zi1 = Z[(i64)m * n + k];
-          for (int i0 = m - 1; i0 >= lo; i0 -= 8) {
-            const int cnt = min(8, i0 - lo + 1);
-            R zb[8], cv[8], sv[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-              if (u < cnt) {
-                zb[u] = Z[(i64)(i0 - u) * n + k];
-                cv[u] = cb[i0 - u];
-                sv[u] = sb[i0 - u];
-              }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-              if (u < cnt) {
-                Z[(i64)(i0 - u + 1) * n + k] = sv[u] * zb[u] + cv[u] * zi1;
-                zi1 = cv[u] * zb[u] - sv[u] * zi1;
-              }
-          }
-          Z[(i64)lo * n + k] = zi1;
-        }
-      };
-      if (Zl)
-        apply(Zl);
-      else
-        apply(Zt);
-    }
-    __syncthreads();
-    cur ^= 1;
-    ++steps;
-  }
-  if (tid == 0) sh_state[4] = ql_failed;
-  __syncthreads();
-  if (Zl) {
-    for (i64 t = tid; t < (i64)n * n; t += nt) Zt[t] = Zl[t];
-    __syncthreads();
-  }
-  return sh_state[4] ? -1 : steps;
-}
-
 // Workgroup-parallel cyclic Jacobi eigensolver for one small symmetric matrix
 // (n even, n <= 64): the round-robin ("tournament") ordering gives n/2 disjoint
 // rotation planes per round, each annihilating one off-diagonal pair with the
@@ -345,7 +117,7 @@ __device__ __forceinline__ int wg_syev(int n, R* A, R* Zt, R* Zl, R* d, R* w, R*
 //   A  : n x n symmetric, row-major (LDS); overwritten, its diagonal holds the
 //        eigenvalues on return.
 //   Zt : n x n output (LDS), eigenvectors stored transposed (Zt[a*n + k] = component k
-//        of eigenvector a), as in wg_syev.
+//        of eigenvector a), as in wg_syev_dc.
 //   d  : n eigenvalues, unsorted.
 // A rotation is skipped when |a_pq| <= 1e-16 sqrt(|a_pp a_qq|) (relative test:
 // graded eigenvalues keep their relative accuracy).  All threads must call it.
@@ -442,19 +214,29 @@ __device__ __forceinline__ int wg_jacobi(int n, R* A, R* Zt, R* d) {
 
 #include "tridiag_dc.h"
 
+// LDS doubles of wg_syev_dc's workspace for a matrix of order up to n: the
+// tridiagonal solver's (e, then 13 n) and the back-transformation's panel data.
+__host__ __device__ constexpr int syev_dc_ws(int n) { return 14 * n > n + 528 ? 14 * n : n + 528; }
+
 // Dense symmetric eigensolver through the tridiagonal divide-and-conquer method:
-// Householder reduction (wg_tridiagonalize), Q accumulated (wg_accumulate_q), the
-// tridiagonal problem solved by wg_tridiag_dc with its eigenvector matrix W kept in A's
-// storage (free once Q is formed), and Zt = (Q W)^T.
+// Householder reduction (wg_tridiagonalize); the reflectors are moved to Zt's storage;
+// the tridiagonal problem is solved by wg_tridiag_dc with its eigenvector matrix W in
+// A's storage; then Z = H_0 H_1 ... H_{n-3} W is formed in place, sixteen reflectors at
+// a time in compact WY form (Golub and Van Loan, Sec. 5.1.7): for a panel V_b of
+// reflectors H_k = I - beta_k v_k v_k^T, H_k0 ... H_k1-1 = I - V_b T V_b^T with
+// T^{-1} = S = strict_upper(V_b^T V_b) + diag(1 / beta) (T by one wavefront), so
+//   Z <- Z - V_b (T (V_b^T Z)),
+// the products on the matrix cores.  Zt = Z^T at the end.
 //   A  : n x n symmetric, row-major (LDS or global); destroyed.
 //   Zt : n x n output (global), Zt[a*n + k] = component k of eigenvector a.
 //   U, Wn : n x n global workspace (distinct from A and Zt).
 //   d  : n eigenvalues (LDS), ascending, d[a] belongs to eigenvector a.
-//   w  : LDS workspace of 14n doubles; red: LDS, >= 48 entries.
+//   w  : LDS workspace of syev_dc_ws(n) doubles; red: LDS, >= 48 entries.
 // All threads of the workgroup must call it.
 __device__ __forceinline__ void wg_syev_dc(int n, double* A, double* Zt, double* U, double* Wn,
                                            double* d, double* w, double* red) {
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int wave = tid >> 6, nwv = nt >> 6, lane = tid & 63;
   if (n <= 0) return;
   if (n == 1) {
     if (tid == 0) {
@@ -465,38 +247,77 @@ __device__ __forceinline__ void wg_syev_dc(int n, double* A, double* Zt, double*
     return;
   }
   wg_tridiagonalize(n, A, d, w, red);
-  wg_accumulate_q(n, A, Zt, w);
-  wg_tridiag_dc(n, d, w, A, U, Wn, w + n);
-  // Wn[a*n + k] = sum_b Q(k, b) W(b, a) = sum_b Zt[b*n + k] A[b*n + a], 4 x 4 tiles
-  const int tp = (n + 3) / 4;
-  for (int it = tid; it < tp * tp; it += nt) {
-    const int a0 = 4 * (it / tp), k0 = 4 * (it % tp);
-    const int amax = min(4, n - a0), kmax = min(4, n - k0);
-    double acc[4][4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-#pragma unroll 2
-    for (int b = 0; b < n; ++b) {
-      double wv[4], qv[4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x) wv[x] = x < amax ? A[(i64)b * n + a0 + x] : 0.0;
-#pragma unroll
-      for (int y = 0; y < 4; ++y) qv[y] = y < kmax ? Zt[(i64)b * n + k0 + y] : 0.0;
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] += wv[x] * qv[y];
+  // reflectors: V[k*n + r] = v_k(r) for r > k, V[k*n + k] = beta_k (zero reflector when
+  // beta_k = 0); rows k >= n-2 and entries r < k are not read
+  double* V = Zt;
+  {
+    const double* beta = w + n;
+    for (i64 t = tid; t < (i64)(n - 2) * n; t += nt) {
+      const int k = (int)(t / n), r = (int)(t - (i64)k * n);
+      const double bk = beta[k];
+      V[t] = r > k ? (bk != 0.0 ? A[(i64)r * n + k] : 0.0) : (r == k ? bk : 0.0);
     }
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-      if (x < amax)
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-          if (y < kmax) Wn[(i64)(a0 + x) * n + k0 + y] = acc[x][y];
   }
   __syncthreads();
-  for (i64 t = tid; t < (i64)n * n; t += nt) Zt[t] = Wn[t];
+  wg_tridiag_dc(n, d, w, A, U, Wn, w + n);
+  // W (in A) <- H_0 ... H_{n-3} W, panels from the last
+  // the panel's S, T = S^{-1} and beta, in the workspace the tridiagonal solver used
+  double* Sl = w + n;
+  double* Tl = Sl + 256;
+  double* bl = Tl + 256;
+  for (int k1 = n - 2; k1 > 0; k1 -= 16) {
+    const int k0 = k1 > 16 ? k1 - 16 : 0, nb = k1 - k0;
+    const int r0 = k0 + 1, m0 = n - r0;  // rows touched: r0..n-1
+    auto vb = [&](int i, int kk) {       // V_b(row r0 + i, reflector k0 + kk)
+      const int k = k0 + kk, r = r0 + i;
+      return r > k ? V[(i64)k * n + r] : 0.0;
+    };
+    // wavefront 0: S = V_b^T V_b and T = S^{-1}; the others: Y = V_b^T W(r0:, :) into
+    // U (nb x n)
+    const int tn = (n + 15) / 16;
+    if (wave == 0) {
+      wave_gemm_tiles(
+          nb, nb, m0, 1, 0, 1, 1, [&](int i, int r) { return vb(r, i); },
+          [&](int r, int j) { return vb(r, j); }, [&](int i, int j, double v) { Sl[i * 16 + j] = v; });
+      if (lane < nb) bl[lane] = V[(i64)(k0 + lane) * n + k0 + lane];
+      // upper triangular inverse, column j by lane j: T(j, j) = beta_j,
+      // T(i, j) = -beta_i sum_{i < l <= j} S(i, l) T(l, j)
+      if (lane < nb) {
+        const int j = lane;
+        Tl[j * 16 + j] = bl[j];
+#pragma unroll 1
+        for (int i = j - 1; i >= 0; --i) {
+          double acc = 0.0;
+          for (int l = i + 1; l <= j; ++l) acc += Sl[i * 16 + l] * Tl[l * 16 + j];
+          Tl[i * 16 + j] = -bl[i] * acc;
+        }
+      }
+    } else {
+      wave_gemm_tiles(
+          nb, n, m0, tn, wave - 1, tn, nwv - 1, [&](int i, int r) { return vb(r, i); },
+          [&](int r, int a) { return A[(i64)(r0 + r) * n + a]; },
+          [&](int i, int a, double v) { U[(i64)i * n + a] = v; });
+    }
+    __syncthreads();
+    // X = T Y in place (each tile reads its columns of Y before writing them)
+    wave_gemm_tiles(
+        nb, n, nb, tn, wave, tn, nwv, [&](int i, int l) { return l >= i ? Tl[i * 16 + l] : 0.0; },
+        [&](int l, int a) { return U[(i64)l * n + a]; },
+        [&](int i, int a, double v) { U[(i64)i * n + a] = v; });
+    __syncthreads();
+    // W(r0:, :) -= V_b X
+    {
+      const int tm = (m0 + 15) / 16;
+      wave_gemm_tiles(
+          m0, n, nb, tn, wave, tm * tn, nwv, [&](int i, int kk) { return vb(i, kk); },
+          [&](int kk, int a) { return U[(i64)kk * n + a]; },
+          [&](int i, int a, double v) { A[(i64)(r0 + i) * n + a] -= v; });
+    }
+    __syncthreads();
+  }
+  for (i64 t = tid; t < (i64)n * n; t += nt) {
+    const int a = (int)(t / n), k = (int)(t - (i64)a * n);
+    Zt[t] = A[(i64)k * n + a];
+  }
   __syncthreads();
 }

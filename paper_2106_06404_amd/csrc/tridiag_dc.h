@@ -31,6 +31,7 @@
 // is exhausted.
 #pragma once
 #include "common.h"
+#include "wg_gemm.h"
 
 // LDS doubles used by wg_tridiag_dc for a matrix of order n.
 __host__ __device__ constexpr int dc_lds_doubles(int n) { return 13 * n; }
@@ -391,47 +392,26 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
     }
     __syncthreads();
     // ---- new eigenvector columns: Wn(block rows, pos_j) = W(block) U(:, j) for the
-    // roots (4 x 4 output tiles per thread), deflated columns copied
+    // roots (16 x 16 matrix-core tiles, one wavefront each), deflated columns copied
     {
-      const int tpb = (bw + 3) / 4;  // tiles per block side
-      const i64 items = (i64)((n + bw - 1) / bw) * tpb * tpb;
-      for (i64 it = tid; it < items; it += nt) {
-        const int b = (int)(it / ((i64)tpb * tpb));
-        const int rem = (int)(it - (i64)b * tpb * tpb);
-        const int rt = rem / tpb, ct = rem - rt * tpb;
+      const int tpb = (bw + 15) / 16;  // tiles per block side
+      const int tiles = ((n + bw - 1) / bw) * tpb * tpb;
+      const int wave = tid >> 6, nwv = nt >> 6;
+      for (int T = wave; T < tiles; T += nwv) {
+        const int b = T / (tpb * tpb), t = T - b * tpb * tpb;
         const int s0 = b * bw;
         const int s = min(bw, n - s0), n1 = min(bs, s);
         if (s == n1) continue;
         const int k = kc[s0];
-        const int r0 = 4 * rt, a0 = 4 * ct;
-        if (r0 >= s || a0 >= k) continue;
-        double acc[4][4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-        const int rmax = min(4, s - r0), amax = min(4, k - a0);
-#pragma unroll 2
-        for (int c = 0; c < s; ++c) {
-          double wv[4], uv[4];
-#pragma unroll
-          for (int x = 0; x < 4; ++x) wv[x] = x < rmax ? W[(i64)(s0 + r0 + x) * n + s0 + c] : 0.0;
-          const double* Ur = U + (i64)(s0 + c) * n + s0 + a0;
-#pragma unroll
-          for (int y = 0; y < 4; ++y) uv[y] = y < amax ? Ur[y] : 0.0;
-#pragma unroll
-          for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y] += wv[x] * uv[y];
-        }
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-          if (y < amax) {
-            const int col = s0 + ps[s0 + a0 + y];
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-              if (x < rmax) Wn[(i64)(s0 + r0 + x) * n + col] = acc[x][y];
-          }
+        if (16 * (t / tpb) >= s || 16 * (t % tpb) >= k) continue;
+        const double* Wb = W + (i64)s0 * n + s0;
+        const double* Ub = U + (i64)s0 * n + s0;
+        double* Wnb = Wn + (i64)s0 * n + s0;
+        const int* pb = ps + s0;
+        wave_gemm_tiles(
+            s, k, s, tpb, t, t + 1, 1, [&](int i, int c) { return Wb[(i64)i * n + c]; },
+            [&](int c, int j) { return Ub[(i64)c * n + j]; },
+            [&](int i, int j, double v) { Wnb[(i64)i * n + pb[j]] = v; });
       }
       for (i64 it = tid; it < (i64)n * bw; it += nt) {
         const int gr = (int)(it / bw), q = (int)(it - (i64)gr * bw);
