@@ -81,15 +81,43 @@ __device__ __forceinline__ void wg_tridiagonalize(int n, R* A, R* d, R* w, R* re
     // column's norm partials from the updated values
     R part = 0;
     const int tr = tid >> 5, tc = tid & 31, ng = nt >> 5;
-    for (int i = tr; i < m; i += ng) {
-      const R vi = i == 0 ? v0 : vc[(i64)i * n];
-      const R qi = p[i] - Kc * vi;
-      R* Ar = A + (i64)(k + 1 + i) * n + (k + 1);
-      for (int j = tc; j < m; j += 32) {
-        const R vj = j == 0 ? v0 : vc[(i64)j * n];
-        const R nv = Ar[j] - (vi * (p[j] - Kc * vj) + qi * vj);
-        Ar[j] = nv;
-        if (j == 0 && i >= 2) part += nv * nv;
+    constexpr int NQ = 5;
+    if (m <= 32 * NQ) {
+      // the thread's columns j = tc + 32 q: v_j and q_j in registers, each row's
+      // elements loaded together before the stores
+      R vj[NQ], qj[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int j = tc + 32 * q;
+        vj[q] = j < m ? (j == 0 ? v0 : vc[(i64)j * n]) : (R)0;
+        qj[q] = j < m ? p[j] - Kc * vj[q] : (R)0;
+      }
+      for (int i = tr; i < m; i += ng) {
+        const R vi = i == 0 ? v0 : vc[(i64)i * n];
+        const R qi = p[i] - Kc * vi;
+        R* Ar = A + (i64)(k + 1 + i) * n + (k + 1);
+        R a[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a[q] = tc + 32 * q < m ? Ar[tc + 32 * q] : (R)0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          if (tc + 32 * q < m) {
+            const R nv = a[q] - (vi * qj[q] + qi * vj[q]);
+            Ar[tc + 32 * q] = nv;
+            if (q == 0 && tc == 0 && i >= 2) part += nv * nv;
+          }
+      }
+    } else {
+      for (int i = tr; i < m; i += ng) {
+        const R vi = i == 0 ? v0 : vc[(i64)i * n];
+        const R qi = p[i] - Kc * vi;
+        R* Ar = A + (i64)(k + 1 + i) * n + (k + 1);
+        for (int j = tc; j < m; j += 32) {
+          const R vj = j == 0 ? v0 : vc[(i64)j * n];
+          const R nv = Ar[j] - (vi * (p[j] - Kc * vj) + qi * vj);
+          Ar[j] = nv;
+          if (j == 0 && i >= 2) part += nv * nv;
+        }
       }
     }
     part = wave_sum(part);
@@ -259,7 +287,7 @@ __device__ __forceinline__ void wg_syev_dc(int n, double* A, double* Zt, double*
     }
   }
   __syncthreads();
-  wg_tridiag_dc(n, d, w, A, U, Wn, w + n);
+  wg_tridiag_dc(n, d, w, A, Wn, w + n);
   // W (in A) <- H_0 ... H_{n-3} W, panels from the last
   // the panel's S, T = S^{-1} and beta, in the workspace the tridiagonal solver used
   double* Sl = w + n;

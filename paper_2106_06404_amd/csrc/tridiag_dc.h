@@ -40,6 +40,21 @@ namespace dcimpl {
 
 constexpr double kEps = 2.220446049250313e-16;
 
+// 1 / x from the hardware reciprocal refined by two Newton steps (error below one ulp
+// beyond rounding; x finite and nonzero)
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ __forceinline__ double grp_prod(double x, int G) {
+  for (int o = G >> 1; o > 0; o >>= 1) x *= __shfl_xor(x, o, G);
+  return x;
+}
+
 __device__ __forceinline__ double grp_sum(double x, int G) {
   for (int o = G >> 1; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
   return x;
@@ -94,7 +109,7 @@ __device__ __forceinline__ void secular_root(int j, int k, const double* dK, con
     const double dj = dK[j];
     const double mid = 0.5 * (dK[j + 1] - dj);
     double s = 0.0;
-    for (int i = g; i < k; i += G) s += zK[i] * zK[i] / ((dK[i] - dj) - mid);
+    for (int i = g; i < k; i += G) s += zK[i] * zK[i] * rcp_nr((dK[i] - dj) - mid);
     s = grp_sum(s, G);
     if (irho + s >= 0.0) {
       org = j;
@@ -116,7 +131,7 @@ __device__ __forceinline__ void secular_root(int j, int k, const double* dK, con
     hi = rho * zz;
     for (int t = 0; t < 8; ++t) {  // f(hi) >= 0 up to rounding; widen if not
       double s = 0.0;
-      for (int i = g; i < k; i += G) s += zK[i] * zK[i] / ((dK[i] - dl) - hi);
+      for (int i = g; i < k; i += G) s += zK[i] * zK[i] * rcp_nr((dK[i] - dl) - hi);
       s = grp_sum(s, G);
       if (irho + s >= 0.0) break;
       hi *= 2.0;
@@ -128,7 +143,7 @@ __device__ __forceinline__ void secular_root(int j, int k, const double* dK, con
   for (int it = 0; it < 64; ++it) {
     double f = 0.0, fa = 0.0, r1 = 0.0, r2 = 0.0;
     for (int i = g; i < k; i += G) {
-      const double rr = 1.0 / ((dK[i] - dorg) - tau);
+      const double rr = rcp_nr((dK[i] - dorg) - tau);
       const double t = zK[i] * rr;
       const double term = zK[i] * t;
       f += term;
@@ -181,12 +196,12 @@ __device__ __forceinline__ void secular_root(int j, int k, const double* dK, con
 // workgroup.
 //   d  : in: diagonal; out: eigenvalues in ascending order (LDS).
 //   W  : n x n output, row-major, W[r*n + a] = component r of eigenvector a (LDS or
-//        global; may not alias U or Wn).
-//   U, Wn : n x n global workspace.
+//        global; may not alias Wn).
+//   Wn : n x n global workspace.
 //   v  : LDS workspace of dc_lds_doubles(n) doubles.
 // All threads must call it.
 __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e, double* W,
-                                              double* U, double* Wn, double* v) {
+                                              double* Wn, double* v) {
   using namespace dcimpl;
   const int tid = threadIdx.x, nt = blockDim.x;
   double* zs = v;           // z in sorted order; later the merged values
@@ -206,6 +221,8 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
   int* kc = ri + n;    // per block (at the block's first index): non-deflated count,
   int* dcn = kc + n;   // deflated count, rotation count
   int* rcn = dcn + n;
+  double* dorg = Ds;  // after the scan: the roots' origin poles
+  double* invn = rc;  // after the rotations: 1 / |u_j|
   // leaves: each coupling is torn out of both adjacent diagonal entries
   for (int i = tid; i < n; i += nt) {
     double di = d[i];
@@ -251,9 +268,17 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
       const double tol = 8.0 * kEps * dmax;
       int k = 0, nd = 0, nr = 0, prev = -1;
       double dp = 0.0, zp = 0.0;
+      // the next element is loaded before this one's stores (the loads are not held
+      // back behind them)
+      int i_n = ps[s0];
+      double z_n = zs[s0], d_n = Ds[s0];
       for (int p = 0; p < s; ++p) {
-        const int i = ps[s0 + p];
-        double zi = zs[s0 + p], di = Ds[s0 + p];
+        const int i = i_n;
+        double zi = z_n, di = d_n;
+        const int pn = p + 1 < s ? p + 1 : p;
+        i_n = ps[s0 + pn];
+        z_n = zs[s0 + pn];
+        d_n = Ds[s0 + pn];
         if (rho * fabs(zi) <= tol) {
           Kd[s0 + nd] = i;
           Dd[s0 + nd] = di;
@@ -321,32 +346,38 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
         if (g == 0) {
           org[s0 + j] = o;
           tau[s0 + j] = t;
+          dorg[s0 + j] = dK[s0 + o];
         }
       }
     }
     __syncthreads();
     // ---- z recomputed from the roots: z_i^2 = prod_j (lambda_j - d_i) /
-    // (rho prod_{j != i} (d_j - d_i)), factors paired so that each is at most one
-    for (int gi = tid; gi < n; gi += nt) {
-      const int s0 = gi - gi % bw, i = gi - s0;
-      const int s = min(bw, n - s0), n1 = min(bs, s);
-      if (s == n1) continue;
-      const int k = kc[s0];
-      if (i >= k) continue;
-      const double* dk = dK + s0;
-      const double* tk = tau + s0;
-      const int* ok = org + s0;
-      const double di = dk[i];
-      const double rho = 2.0 * fabs(e[s0 + n1 - 1]);
-      double pr = ((dk[ok[k - 1]] - di) + tk[k - 1]) / rho;
-      for (int jj = 0; jj < i; ++jj) pr *= ((dk[ok[jj]] - di) + tk[jj]) / (dk[jj] - di);
-      for (int jj = i; jj < k - 1; ++jj) pr *= ((dk[ok[jj]] - di) + tk[jj]) / (dk[jj + 1] - di);
-      // own element only: no other thread reads zK in this phase
-      zK[gi] = copysign(sqrt(fmax(pr, 0.0)), zK[gi]);
+    // (rho prod_{j != i} (d_j - d_i)), factors paired so that each is at most one in
+    // magnitude; the G lanes of a group take every G-th factor
+    {
+      const int g = tid % G;
+      for (int gi = tid / G; gi < n; gi += nt / G) {
+        const int s0 = gi - gi % bw, i = gi - s0;
+        const int s = min(bw, n - s0), n1 = min(bs, s);
+        if (s == n1) continue;
+        const int k = kc[s0];
+        if (i >= k) continue;
+        const double* dk = dK + s0;
+        const double* tk = tau + s0;
+        const double* ok = dorg + s0;
+        const double di = dk[i];
+        const double rho = 2.0 * fabs(e[s0 + n1 - 1]);
+        double pr = g == 0 ? ((ok[k - 1] - di) + tk[k - 1]) * rcp_nr(rho) : 1.0;
+        for (int jj = g; jj < i; jj += G) pr *= ((ok[jj] - di) + tk[jj]) * rcp_nr(dk[jj] - di);
+        for (int jj = i + g; jj < k - 1; jj += G) pr *= ((ok[jj] - di) + tk[jj]) * rcp_nr(dk[jj + 1] - di);
+        pr = grp_prod(pr, G);
+        // own element only: no other group reads zK in this phase
+        if (g == 0) zK[gi] = copysign(sqrt(fmax(pr, 0.0)), zK[gi]);
+      }
     }
     __syncthreads();
-    // ---- eigenvectors of the rank-one problem, normalised, as the columns j < k of
-    // U (rows: the block's columns; deflated rows zero); merged values into zs
+    // ---- norms of the rank-one problem's eigenvectors u_j = (z_i / (d_i - lambda_j))_i
+    // (their entries are formed again inside the product below); merged values into zs
     {
       const int g = tid % G;
       for (int gj = tid / G; gj < n; gj += nt / G) {
@@ -359,20 +390,17 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
           if (g == 0) zs[gj] = Dd[s0 + q];
           continue;
         }
-        const double dl = dK[s0 + org[s0 + j]], tj = tau[s0 + j];
+        const double dl = dorg[gj], tj = tau[gj];
         double nrm = 0.0;
         for (int i = g; i < k; i += G) {
-          const double u = zK[s0 + i] / ((dK[s0 + i] - dl) - tj);
+          const double u = zK[s0 + i] * rcp_nr((dK[s0 + i] - dl) - tj);
           nrm += u * u;
         }
-        const double inv = 1.0 / sqrt(grp_sum(nrm, G));
-        for (int i = g; i < k; i += G) {
-          const double u = zK[s0 + i] / ((dK[s0 + i] - dl) - tj);
-          U[(i64)(s0 + K[s0 + i]) * n + s0 + j] = u * inv;
+        nrm = grp_sum(nrm, G);
+        if (g == 0) {
+          invn[gj] = 1.0 / sqrt(nrm);
+          zs[gj] = dl + tj;
         }
-        const int nd = s - k;
-        for (int q = g; q < nd; q += G) U[(i64)(s0 + Kd[s0 + q]) * n + s0 + j] = 0.0;
-        if (g == 0) zs[gj] = dl + tj;
       }
     }
     __syncthreads();
@@ -405,13 +433,15 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
         const int k = kc[s0];
         if (16 * (t / tpb) >= s || 16 * (t % tpb) >= k) continue;
         const double* Wb = W + (i64)s0 * n + s0;
-        const double* Ub = U + (i64)s0 * n + s0;
         double* Wnb = Wn + (i64)s0 * n + s0;
         const int* pb = ps + s0;
+        const int* Kb = K + s0;
+        const double *zb = zK + s0, *db = dK + s0, *ob = dorg + s0, *tb = tau + s0, *nb = invn + s0;
+        // A = the block's non-deflated columns of W, B(i, j) = z_i / (d_i - lambda_j) / |u_j|
         wave_gemm_tiles(
-            s, k, s, tpb, t, t + 1, 1, [&](int i, int c) { return Wb[(i64)i * n + c]; },
-            [&](int c, int j) { return Ub[(i64)c * n + j]; },
-            [&](int i, int j, double v) { Wnb[(i64)i * n + pb[j]] = v; });
+            s, k, k, tpb, t, t + 1, 1, [&](int r, int i) { return Wb[(i64)r * n + Kb[i]]; },
+            [&](int i, int j) { return zb[i] * rcp_nr((db[i] - ob[j]) - tb[j]) * nb[j]; },
+            [&](int r, int j, double v) { Wnb[(i64)r * n + pb[j]] = v; });
       }
       for (i64 it = tid; it < (i64)n * bw; it += nt) {
         const int gr = (int)(it / bw), q = (int)(it - (i64)gr * bw);
