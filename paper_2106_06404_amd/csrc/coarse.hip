@@ -18,6 +18,7 @@
 // the rest.
 #include "common.h"
 #include "symeig.h"
+#include "wg_gemm.h"
 #include "kernels.h"
 
 // V[p] (npd x M, column-major): values of the patch's coarse functions at the patch dofs
@@ -218,27 +219,37 @@ __global__ void k_coarse_assemble(const i64* __restrict__ tp_ptr, const i32* __r
 
 // In-place dense Cholesky of an n x n column-major matrix held in global memory
 // (lower triangle); one workgroup.  Returns false on a non-positive pivot.
-__device__ bool dense_cholesky_block(int n, double* A, int lda, int* fail_sh) {
-  if (threadIdx.x == 0) *fail_sh = 0;
+// In-place Cholesky factorisation A = L L^T of one n x n SPD block (column-major,
+// leading dimension lda) by the whole workgroup; L is left in the lower triangle, the
+// upper triangle is zeroed.  One barrier per column: the trailing update subtracts
+// a_rj a_cj / a_jj with the unscaled column, whose scaled copy goes to the upper
+// triangle (not touched by the update) and is moved down at the end.  Returns false
+// for a non-positive pivot.
+__device__ __forceinline__ bool dense_cholesky_block(int n, double* A, int lda, int* fail_sh) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tr = tid >> 5, tc = tid & 31, ng = nt >> 5;
+  if (tid == 0) *fail_sh = 0;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
     const double ajj = A[j + (i64)j * lda];
     if (!(ajj > 0.0)) return false;
-    const double l = sqrt(ajj);
-    __syncthreads();
-    for (int r = j + threadIdx.x; r < n; r += blockDim.x)
-      A[r + (i64)j * lda] = (r == j) ? l : A[r + (i64)j * lda] / l;
-    __syncthreads();
-    const int rem = n - j - 1;
-    for (i64 t = threadIdx.x; t < (i64)rem * rem; t += blockDim.x) {
-      const int r = j + 1 + (int)(t % rem), c = j + 1 + (int)(t / rem);
-      if (c <= r) A[r + (i64)c * lda] -= A[r + (i64)j * lda] * A[c + (i64)j * lda];
+    const double il = 1.0 / sqrt(ajj), ia = 1.0 / ajj;
+    for (int r = j + 1 + tid; r < n; r += nt) A[j + (i64)r * lda] = A[r + (i64)j * lda] * il;
+    for (int r = j + 1 + tr; r < n; r += ng) {
+      const double arj = A[r + (i64)j * lda] * ia;
+      for (int c = j + 1 + tc; c <= r; c += 32) A[r + (i64)c * lda] -= arj * A[c + (i64)j * lda];
     }
     __syncthreads();
   }
-  for (i64 t = threadIdx.x; t < (i64)n * n; t += blockDim.x) {
+  for (i64 t = tid; t < (i64)n * n; t += nt) {
+    const int r = (int)(t % n), c = (int)(t / n);
+    if (r > c) A[r + (i64)c * lda] = A[c + (i64)r * lda];
+  }
+  __syncthreads();
+  for (i64 t = tid; t < (i64)n * n; t += nt) {
     const int r = (int)(t % n), c = (int)(t / n);
     if (r < c) A[r + (i64)c * lda] = 0.0;
+    if (r == c) A[r + (i64)c * lda] = sqrt(A[r + (i64)c * lda]);
   }
   __syncthreads();
   return true;
@@ -257,10 +268,10 @@ __global__ void k_dense_cholesky(const i64* __restrict__ off, const i32* __restr
 // Coarse GEVP of one level-(l-1) subdomain per workgroup, on its generating system
 // (owned functions first, no of them; Abar is ng x ng column-major):
 //   S = Abar + B with B = D Abar D, D the 0/1 owned mask;
-//   S = Q diag(s) Q^T (Jacobi, Q and Y stored transposed); keep s > tau * max(s) (the rest is the numerical
-//   kernel of abar and b, their common kernel in exact arithmetic);
-//   Qk = Q_keep diag(s_keep)^{-1/2};  C = Qk^T B Qk = Qk_o^T A_oo Qk_o;
-//   C = Y diag(mu) Y^T (Jacobi);  lambda = 1/mu - 1;  select lambda < eta;
+//   S = Q diag(s) Q^T (wg_syev_dc; Q and Y stored transposed); keep s > tau * max(s) (the
+//   rest is the numerical kernel of abar and b, their common kernel in exact arithmetic);
+//   Qk = Q_keep diag(s_keep)^{-1/2};  C = Qk^T B Qk = Qk_o^T A_oo Qk_o (matrix cores);
+//   C = Y diag(mu) Y^T (wg_syev_dc);  lambda = 1/mu - 1;  select lambda < eta;
 //   x = Qk y / sqrt(mu) (b-normalised); the coarse basis block is x on the owned rows.
 // The owned block A_oo is the level's Dirichlet matrix; its Cholesky factor is kept.
 // Scratch layout per target (doubles): S ng^2 | Q ng^2 | Qk ng^2 | C ng^2 | Yc ng^2 | ints ng.
@@ -340,21 +351,30 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
     Qk[e] = Q[(i64)a * ng + row] / sqrt(d[a]);  // Q stored transposed
   }
   __syncthreads();
-  // C = Qk_o^T A_oo Qk_o: first Q <- A_oo Qk_o (no x r), then C (r x r, row-major)
-  for (i64 e = tid; e < (i64)no * r; e += nt) {
-    const int row = (int)(e / r), k = (int)(e % r);
-    double acc = 0.0;
-    for (int q = 0; q < no; ++q) acc += 0.5 * (A[row + (i64)q * ng] + A[q + (i64)row * ng]) * Qk[(i64)q * r + k];
-    Q[e] = acc;
-  }
-  __syncthreads();
-  for (i64 e = tid; e < (i64)r * r; e += nt) {
-    const int a = (int)(e / r), b = (int)(e % r);
-    if (a > b) continue;
-    double acc = 0.0;
-    for (int q = 0; q < no; ++q) acc += Qk[(i64)q * r + a] * Q[(i64)q * r + b];
-    Cx[(i64)a * r + b] = acc;
-    Cx[(i64)b * r + a] = acc;
+  // C = Qk_o^T A_oo Qk_o on the matrix cores: first Q <- A_oo Qk_o (no x r), then C
+  // (r x r, row-major), made exactly symmetric
+  const int wave = tid >> 6, nwv = nt >> 6;
+  {
+    const int tnr = (r + 15) / 16, tmo = (no + 15) / 16;
+    wave_gemm_tiles(
+        no, r, no, tnr, wave, tmo * tnr, nwv,
+        [&](int row, int q) { return 0.5 * (A[row + (i64)q * ng] + A[q + (i64)row * ng]); },
+        [&](int q, int k) { return Qk[(i64)q * r + k]; },
+        [&](int row, int k, double v) { Q[(i64)row * r + k] = v; });
+    __syncthreads();
+    wave_gemm_tiles(
+        r, r, no, tnr, wave, tnr * tnr, nwv, [&](int a, int q) { return Qk[(i64)q * r + a]; },
+        [&](int q, int b) { return Q[(i64)q * r + b]; },
+        [&](int a, int b, double v) { Cx[(i64)a * r + b] = v; });
+    __syncthreads();
+    for (i64 e = tid; e < (i64)r * r; e += nt) {
+      const int a = (int)(e / r), b = (int)(e % r);
+      if (a < b) {
+        const double v = 0.5 * (Cx[(i64)a * r + b] + Cx[(i64)b * r + a]);
+        Cx[(i64)a * r + b] = v;
+        Cx[(i64)b * r + a] = v;
+      }
+    }
   }
   __syncthreads();
   // C = Y diag(mu) Y^T (Y transposed in Yc); mu in d
@@ -396,23 +416,26 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   const int m = sh_m;
   // selected b-normalised eigenvectors, owned rows: Xo[row, c] = (Qk_o y_c)[row] / sqrt(mu_c)
   double* Xo = S;  // reuse S as no x m column-major output
-  for (i64 e = tid; e < (i64)no * m; e += nt) {
-    const int row = (int)(e % no), c = (int)(e / no);
-    const int src = ord[c];
-    const double mu = d[src];
-    double acc = 0.0;
-    for (int k = 0; k < r; ++k) acc += Qk[(i64)row * r + k] * Yc[(i64)src * r + k];  // Yc transposed
-    Xo[row + (i64)c * no] = acc / sqrt(mu);
-  }
-  // Dirichlet factor of the owned block
+  wave_gemm_tiles(
+      no, m, r, (m + 15) / 16, wave, ((no + 15) / 16) * ((m + 15) / 16), nwv,
+      [&](int row, int k) { return Qk[(i64)row * r + k]; },
+      [&](int k, int c) { return Yc[(i64)ord[c] * r + k]; },  // Yc transposed
+      [&](int row, int c, double v) { Xo[row + (i64)c * no] = v / sqrt(d[ord[c]]); });
+  // Dirichlet factor of the owned block (in LDS when the generating system was there)
+  double* Lw = in_lds ? Alds : L;
   for (i64 e = tid; e < (i64)no * no; e += nt) {
     const int rr = (int)(e % no), cc = (int)(e / no);
-    L[e] = 0.5 * (A[rr + (i64)cc * ng] + A[cc + (i64)rr * ng]);
+    Lw[e] = 0.5 * (A[rr + (i64)cc * ng] + A[cc + (i64)rr * ng]);
   }
   __syncthreads();
-  if (!dense_cholesky_block(no, L, no, &sh_fail)) {
+  const bool spd = in_lds ? dense_cholesky_block(no, Alds, no, &sh_fail)
+                          : dense_cholesky_block(no, L, no, &sh_fail);
+  if (!spd) {
     if (tid == 0) status[t] = ST_NOTSPD;
     return;
+  }
+  if (in_lds) {
+    for (i64 e = tid; e < (i64)no * no; e += nt) L[e] = Alds[e];
   }
   if (tid == 0) status[t] = sh_bad ? ST_NOCONV : ST_DONE;
 }

@@ -5,7 +5,10 @@
 
 #include <chrono>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "msdd.h"
@@ -34,6 +37,100 @@ inline double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Device memory cache shared by all contexts of the process.  A setup allocates and
+// frees hundreds of buffers; hipMalloc and hipFree are slow and hipFree waits for the
+// device, so freed blocks are kept for reuse.  A freed block is quarantined until the
+// next safe point (a device-wide synchronisation, taken at the start of every setup and
+// when a context is destroyed): until then a kernel still in flight may read it, and
+// another stream or host thread must not receive it.  Blocks are matched by size,
+// rounded up to 256 bytes below 64 KiB and to eighths of a power of two above.
+class DevicePool {
+ public:
+  static DevicePool& get() {
+    static DevicePool pool;
+    return pool;
+  }
+  void* alloc(size_t bytes) {
+    const size_t sz = round(bytes);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto it = free_.find(Key{dev, sz});
+      if (it != free_.end()) {
+        void* p = it->second;
+        free_.erase(it);
+        live_[p] = Key{dev, sz};
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, sz) != hipSuccess) {
+      (void)hipGetLastError();
+      drop_free(dev);  // give the cached blocks back and try once more
+      if (hipMalloc(&p, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    live_[p] = Key{dev, sz};
+    return p;
+  }
+  void release(void* p) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    quarantine_.push_back({it->second, p});
+    live_.erase(it);
+  }
+  // the device has no work in flight: the current device's quarantined blocks become
+  // reusable
+  void safe_point() {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> lk(mu_);
+    std::vector<std::pair<Key, void*>> keep;
+    for (auto& q : quarantine_) {
+      if (q.first.dev == dev)
+        free_.emplace(q.first, q.second);
+      else
+        keep.push_back(q);
+    }
+    quarantine_.swap(keep);
+  }
+
+ private:
+  struct Key {
+    int dev;
+    size_t bytes;
+    bool operator<(const Key& o) const { return dev != o.dev ? dev < o.dev : bytes < o.bytes; }
+  };
+  static size_t round(size_t b) {
+    if (b < 65536) return (b + 255) & ~(size_t)255;
+    size_t p = 65536;
+    while (p * 2 <= b) p *= 2;
+    const size_t step = p / 8;
+    return (b + step - 1) / step * step;
+  }
+  void drop_free(int dev) {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto it = free_.begin(); it != free_.end();) {
+      if (it->first.dev == dev) {
+        (void)hipFree(it->second);
+        it = free_.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  std::mutex mu_;
+  std::multimap<Key, void*> free_;
+  std::unordered_map<void*, Key> live_;
+  std::vector<std::pair<Key, void*>> quarantine_;
+};
+
 template <class T>
 struct DVec {
   T* p = nullptr;
@@ -48,18 +145,16 @@ struct DVec {
   }
   ~DVec() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) DevicePool::get().release(p);
     p = nullptr;
     n = 0;
   }
   void alloc(size_t cnt) {
     release();
     if (cnt == 0) return;
-    if (hipMalloc((void**)&p, cnt * sizeof(T)) != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
+    p = static_cast<T*>(DevicePool::get().alloc(cnt * sizeof(T)));
+    if (!p)
       throw MsddError{MSDD_ENOMEM, "device allocation of " + std::to_string(cnt * sizeof(T)) + " bytes failed"};
-    }
     n = cnt;
   }
   void zero(hipStream_t s) {

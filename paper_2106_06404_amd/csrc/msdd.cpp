@@ -1706,6 +1706,7 @@ int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
   try {
     REQUIRE(nprob >= 1, "nprob must be positive");
     HIPCHK(hipSetDevice(c->opt.device));
+    DevicePool::get().safe_point();  // the previous setup's freed buffers become reusable
     const double t0 = now_ms();
     REQUIRE(n > 0 && n < (int64_t)1 << 31, "n out of range");
     REQUIRE(n_elem > 0 && k > 0 && k <= 81, "bad element count or size");
@@ -2499,6 +2500,7 @@ void msdd_destroy(msdd_ctx* c) {
   (void)hipSetDevice(c->opt.device);
   (void)hipDeviceSynchronize();
   delete c;
+  DevicePool::get().safe_point();
 }
 
 }  // extern "C"

@@ -235,13 +235,18 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
   const double r2 = 0.70710678118654752440;
   // lanes per secular root: as many as let one pass cover n roots
   int G = 1;
-  while (G < 16 && 2 * G * n <= nt) G *= 2;
-  for (int bs = 1; bs < n; bs *= 2) {
-    const int bw = 2 * bs;  // merged block width
+  int lg = 0;
+  while (G < 16 && 2 * G * n <= nt) {
+    G *= 2;
+    ++lg;
+  }
+  for (int lb = 0; (1 << lb) < n; ++lb) {
+    const int bs = 1 << lb, bw = 2 * bs;  // half and merged block width (bw = 2^(lb+1))
+    const int bm = bw - 1, lw = lb + 1;
     // ---- z (from the boundary rows of W) and the sorted order of the poles, scattered
     // by rank (ties by index)
     for (int gc = tid; gc < n; gc += nt) {
-      const int s0 = gc - gc % bw, c = gc - s0;
+      const int s0 = gc & ~bm, c = gc - s0;
       const int s = min(bw, n - s0), n1 = min(bs, s);
       if (s == n1) continue;  // no partner: carried
       const double beta = e[s0 + n1 - 1];
@@ -321,7 +326,7 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
     // ---- deflation rotations on the block's eigenvector columns (one thread per row,
     // in order), and the secular roots (one group of G lanes per root)
     for (int gr = tid; gr < n; gr += nt) {
-      const int s0 = gr - gr % bw;
+      const int s0 = gr & ~bm;
       const int s = min(bw, n - s0), n1 = min(bs, s);
       if (s == n1) continue;
       const int nr = rcn[s0];
@@ -335,9 +340,9 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
       }
     }
     {
-      const int g = tid % G;
-      for (int gj = tid / G; gj < n; gj += nt / G) {
-        const int s0 = gj - gj % bw, j = gj - s0;
+      const int g = tid & (G - 1);
+      for (int gj = tid >> lg; gj < n; gj += nt >> lg) {
+        const int s0 = gj & ~bm, j = gj - s0;
         const int s = min(bw, n - s0), n1 = min(bs, s);
         if (s == n1 || j >= kc[s0]) continue;
         int o;
@@ -355,9 +360,9 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
     // (rho prod_{j != i} (d_j - d_i)), factors paired so that each is at most one in
     // magnitude; the G lanes of a group take every G-th factor
     {
-      const int g = tid % G;
-      for (int gi = tid / G; gi < n; gi += nt / G) {
-        const int s0 = gi - gi % bw, i = gi - s0;
+      const int g = tid & (G - 1);
+      for (int gi = tid >> lg; gi < n; gi += nt >> lg) {
+        const int s0 = gi & ~bm, i = gi - s0;
         const int s = min(bw, n - s0), n1 = min(bs, s);
         if (s == n1) continue;
         const int k = kc[s0];
@@ -379,9 +384,9 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
     // ---- norms of the rank-one problem's eigenvectors u_j = (z_i / (d_i - lambda_j))_i
     // (their entries are formed again inside the product below); merged values into zs
     {
-      const int g = tid % G;
-      for (int gj = tid / G; gj < n; gj += nt / G) {
-        const int s0 = gj - gj % bw, j = gj - s0;
+      const int g = tid & (G - 1);
+      for (int gj = tid >> lg; gj < n; gj += nt >> lg) {
+        const int s0 = gj & ~bm, j = gj - s0;
         const int s = min(bw, n - s0), n1 = min(bs, s);
         if (s == n1) continue;
         const int k = kc[s0];
@@ -406,7 +411,7 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
     __syncthreads();
     // ---- positions in ascending order (rank, ties by index) and the new values
     for (int ga = tid; ga < n; ga += nt) {
-      const int s0 = ga - ga % bw, a = ga - s0;
+      const int s0 = ga & ~bm, a = ga - s0;
       const int s = min(bw, n - s0), n1 = min(bs, s);
       if (s == n1) continue;
       const double va = zs[ga];
@@ -423,7 +428,7 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
     // roots (16 x 16 matrix-core tiles, one wavefront each), deflated columns copied
     {
       const int tpb = (bw + 15) / 16;  // tiles per block side
-      const int tiles = ((n + bw - 1) / bw) * tpb * tpb;
+      const int tiles = ((n + bm) >> lw) * tpb * tpb;
       const int wave = tid >> 6, nwv = nt >> 6;
       for (int T = wave; T < tiles; T += nwv) {
         const int b = T / (tpb * tpb), t = T - b * tpb * tpb;
@@ -443,9 +448,9 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
             [&](int i, int j) { return zb[i] * rcp_nr((db[i] - ob[j]) - tb[j]) * nb[j]; },
             [&](int r, int j, double v) { Wnb[(i64)r * n + pb[j]] = v; });
       }
-      for (i64 it = tid; it < (i64)n * bw; it += nt) {
-        const int gr = (int)(it / bw), q = (int)(it - (i64)gr * bw);
-        const int s0 = gr - gr % bw;
+      for (int it = tid; it < n * bw; it += nt) {
+        const int gr = it >> lw, q = it & bm;
+        const int s0 = gr & ~bm;
         const int s = min(bw, n - s0), n1 = min(bs, s);
         if (s == n1) continue;
         const int k = kc[s0];
@@ -455,9 +460,9 @@ __device__ __forceinline__ void wg_tridiag_dc(int n, double* d, const double* e,
     }
     __syncthreads();
     // ---- merged blocks back into W
-    for (i64 it = tid; it < (i64)n * bw; it += nt) {
-      const int gr = (int)(it / bw), c = (int)(it - (i64)gr * bw);
-      const int s0 = gr - gr % bw;
+    for (int it = tid; it < n * bw; it += nt) {
+      const int gr = it >> lw, c = it & bm;
+      const int s0 = gr & ~bm;
       const int s = min(bw, n - s0), n1 = min(bs, s);
       if (s == n1 || c >= s) continue;
       W[(i64)gr * n + s0 + c] = Wn[(i64)gr * n + s0 + c];

@@ -13,24 +13,45 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // C(i, j) = sum_k A(i, k) B(k, j) over the tiles t = first, first + stride, ... of a
 // grid of tm x tn tiles; tile t covers rows 16 (t / tn) + 0..15 and columns
-// 16 (t % tn) + 0..15, clipped to M x N.  a(i, k), b(k, j) load the operands (only
-// called in range), c(i, j, value) stores a result.  Called by whole wavefronts.
+// 16 (t % tn) + 0..15, clipped to M x N.  a(i, k), b(k, j) load the operands and are
+// called with indices clamped into range (out-of-range operands are then replaced by
+// zeros, without branches, so that the loads of four steps are issued together);
+// c(i, j, value) stores a result.  Called by whole wavefronts.
 template <class FA, class FB, class FC>
 __device__ __forceinline__ void wave_gemm_tiles(int M, int N, int K, int tn, int t0, int tcount,
                                                 int tstride, FA a, FB b, FC c) {
+  if (M <= 0 || N <= 0 || K <= 0) return;
   const int lane = threadIdx.x & 63;
   const int r16 = lane & 15, k4 = lane >> 4;
+  const int nsteps = (K + 3) >> 2;
   for (int t = t0; t < tcount; t += tstride) {
     const int i0 = 16 * (t / tn), j0 = 16 * (t % tn);
     const int ia = i0 + r16, jb = j0 + r16;
     const bool ai = ia < M, bj = jb < N;
+    const int iac = ai ? ia : M - 1, jbc = bj ? jb : N - 1;
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int kk = k0 + k4;
-      const double av = (ai && kk < K) ? a(ia, kk) : 0.0;
-      const double bv = (bj && kk < K) ? b(kk, jb) : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    int st = 0;
+    for (; st + 4 <= nsteps; st += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kk = 4 * (st + u) + k4;
+        const bool in = kk < K;
+        const int kc = in ? kk : K - 1;
+        const double x = a(iac, kc), y = b(kc, jbc);
+        av[u] = (ai && in) ? x : 0.0;
+        bv[u] = (bj && in) ? y : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+    }
+    for (; st < nsteps; ++st) {
+      const int kk = 4 * st + k4;
+      const bool in = kk < K;
+      const int kc = in ? kk : K - 1;
+      const double x = a(iac, kc), y = b(kc, jbc);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64((ai && in) ? x : 0.0, (bj && in) ? y : 0.0, acc,
+                                                 0, 0, 0);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
