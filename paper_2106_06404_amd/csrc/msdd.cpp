@@ -381,6 +381,8 @@ struct msdd_ctx {
   std::vector<double> last_relres;
   hipStream_t gstream = nullptr;  // capture stream for the iteration graphs
   hipStream_t ustream = nullptr;  // uploads of the patch planning that overlaps the eigensolves
+  hipStream_t cstream = nullptr;  // coarse levels of the preconditioner, beside the fine solve
+  hipEvent_t cev0 = nullptr, cev1 = nullptr;
   hipEvent_t gev0 = nullptr, gev1 = nullptr;
   hipGraphExec_t gexec = nullptr;
   const double* g_x = nullptr;  // pointers the cached graph was captured with
@@ -411,6 +413,9 @@ struct msdd_ctx {
     if (gev1) (void)hipEventDestroy(gev1);
     if (gstream) (void)hipStreamDestroy(gstream);
     if (ustream) (void)hipStreamDestroy(ustream);
+    if (cev0) (void)hipEventDestroy(cev0);
+    if (cev1) (void)hipEventDestroy(cev1);
+    if (cstream) (void)hipStreamDestroy(cstream);
   }
 };
 
@@ -1588,17 +1593,32 @@ void alloc_solve_work(msdd_ctx* c) {
   HIPCHK(hipStreamSynchronize(s));
 }
 
-// z = B r (Sec. 2.1, additive over all levels), launched on stream s
+// z = B r (Sec. 2.1, additive over all levels), launched on stream s.  After the
+// restriction the coarse levels (a chain of small launches) and the finest-level solves
+// are independent: without profiling the coarse chain runs on a second stream, forked
+// and joined with events (inside a captured iteration graph these become graph edges),
+// so that it overlaps the solves.
 void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
   FineLevel& F = c->F;
   const int L = c->n_levels - 1;
   double* rc_top = c->rlev[L - 1].p;  // level L-1 vector
+  const bool fork = !c->prof.on;
+  if (fork && !c->cstream) {
+    HIPCHK(hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->cev0, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->cev1, hipEventDisableTiming));
+  }
+  const hipStream_t cs = fork ? c->cstream : s;
   {
     // gather (index + value) and u write, PhiD read, rc write
     ProfScope ps(c, PR_APPLY_RESTRICT, F.s_nd * (4.0 + 8.0 + 8.0) + F.s_ndm * 8.0 + F.s_m * 8.0,
                  2.0 * F.s_ndm);
     launch_apply_fine_restrict(s, F.P, F.nd_max, F.nd.p, F.doff.p, F.dglob.p, F.dm.p, F.moff.p,
                                F.phid_off.p, F.PhiD.p, r, rc_top, c->u.p);
+  }
+  if (fork) {
+    HIPCHK(hipEventRecord(c->cev0, s));
+    HIPCHK(hipStreamWaitEvent(cs, c->cev0, 0));
   }
   {
     // both sweeps read the band factor once; u is read and written (and the scaling
@@ -1620,18 +1640,22 @@ void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
     for (int t = 0; t < (int)c->C.size(); ++t) {
       CoarseLevel& CL = c->C[t];
       const int l = CL.level;
-      launch_apply_coarse_down(s, CL.P, CL.no_max, CL.dno.p, CL.own_ptr.p, CL.own_idx.p,
+      launch_apply_coarse_down(cs, CL.P, CL.no_max, CL.dno.p, CL.own_ptr.p, CL.own_idx.p,
                                CL.loff.p, CL.Inv.p, CL.dm.p, CL.yoff.p, CL.Y.p, CL.moff.p,
                                c->rlev[l].p, c->zlev[l].p, c->rlev[l - 1].p);
     }
-    launch_apply_coarsest(s, c->n0_blocks, c->n0_max, c->z0off.p, c->a0off.p, c->n0blk.p,
+    launch_apply_coarsest(cs, c->n0_blocks, c->n0_max, c->z0off.p, c->a0off.p, c->n0blk.p,
                           c->A0inv.p, c->rlev[0].p, c->zlev[0].p);
     for (int t = (int)c->C.size() - 1; t >= 0; --t) {
       CoarseLevel& CL = c->C[t];
       const int l = CL.level;
-      launch_apply_coarse_up(s, CL.P, CL.dno.p, CL.own_ptr.p, CL.own_idx.p, CL.dm.p, CL.yoff.p,
+      launch_apply_coarse_up(cs, CL.P, CL.dno.p, CL.own_ptr.p, CL.own_idx.p, CL.dm.p, CL.yoff.p,
                              CL.Y.p, CL.moff.p, c->zlev[l - 1].p, c->zlev[l].p);
     }
+  }
+  if (fork) {
+    HIPCHK(hipEventRecord(c->cev1, cs));
+    HIPCHK(hipStreamWaitEvent(s, c->cev1, 0));
   }
   {
     ProfScope ps(c, PR_APPLY_GATHER,
