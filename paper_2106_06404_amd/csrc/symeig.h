@@ -320,9 +320,11 @@ __device__ __forceinline__ void wg_syev_dc(int n, double* A, double* Zt, double*
           Tl[i * 16 + j] = -bl[i] * acc;
         }
       }
-    } else {
+    }
+    if (wave > 0 || nwv == 1) {  // a lone wavefront does both
+      const int w0 = nwv > 1 ? wave - 1 : 0, ws = nwv > 1 ? nwv - 1 : 1;
       wave_gemm_tiles(
-          nb, n, m0, tn, wave - 1, tn, nwv - 1, [&](int i, int r) { return vb(r, i); },
+          nb, n, m0, tn, w0, tn, ws, [&](int i, int r) { return vb(r, i); },
           [&](int r, int a) { return A[(i64)(r0 + r) * n + a]; },
           [&](int i, int a, double v) { U[(i64)i * n + a] = v; });
     }
