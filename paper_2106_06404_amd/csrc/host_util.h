@@ -37,6 +37,60 @@ inline double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Pinned host staging for uploads.  hipMemcpyAsync from pageable memory blocks the
+// host until the runtime has copied the data through its own bounce buffers; copied
+// into pinned memory first, an upload becomes an asynchronous DMA that overlaps the
+// host work after it.  The staged copies stay valid (chunks are only handed out
+// again) until the next reset, taken at the same device-wide safe points as the
+// device memory cache, when no copy can still be in flight; one arena per device.
+class PinnedArena {
+ public:
+  static PinnedArena& get() {
+    static PinnedArena arenas[kMaxDev];
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return arenas[dev >= 0 && dev < kMaxDev ? dev : 0];
+  }
+  // a pinned copy of [src, src + bytes), or nullptr (then the caller copies directly)
+  void* stage(const void* src, size_t bytes) {
+    char* dst = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      const size_t need = (bytes + 255) & ~(size_t)255;
+      while (cur_ < chunks_.size() && off_ + need > chunks_[cur_].second) {
+        ++cur_;
+        off_ = 0;
+      }
+      if (cur_ == chunks_.size()) {
+        const size_t sz = need > kChunk ? need : kChunk;
+        void* p = nullptr;
+        if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) {
+          (void)hipGetLastError();
+          return nullptr;
+        }
+        chunks_.push_back({static_cast<char*>(p), sz});
+        off_ = 0;
+      }
+      dst = chunks_[cur_].first + off_;
+      off_ += need;
+    }
+    std::memcpy(dst, src, bytes);
+    return dst;
+  }
+  void reset() {
+    std::lock_guard<std::mutex> lk(mu_);
+    cur_ = 0;
+    off_ = 0;
+  }
+
+ private:
+  static constexpr int kMaxDev = 64;
+  static constexpr size_t kChunk = (size_t)64 << 20;
+  std::mutex mu_;
+  std::vector<std::pair<char*, size_t>> chunks_;
+  size_t cur_ = 0, off_ = 0;
+};
+
 // Device memory cache shared by all contexts of the process.  A setup allocates and
 // frees hundreds of buffers; hipMalloc and hipFree are slow and hipFree waits for the
 // device, so freed blocks are kept for reuse.  A freed block is quarantined until the
@@ -90,6 +144,7 @@ class DevicePool {
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceSynchronize();
+    PinnedArena::get().reset();
     std::lock_guard<std::mutex> lk(mu_);
     std::vector<std::pair<Key, void*>> keep;
     for (auto& q : quarantine_) {
@@ -162,7 +217,10 @@ struct DVec {
   }
   void upload(const std::vector<T>& v, hipStream_t s) {
     alloc(v.size());
-    if (n) HIPCHK(hipMemcpyAsync(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
+    if (!n) return;
+    const size_t bytes = n * sizeof(T);
+    const void* src = bytes >= ((size_t)64 << 10) ? PinnedArena::get().stage(v.data(), bytes) : nullptr;
+    HIPCHK(hipMemcpyAsync(p, src ? src : v.data(), bytes, hipMemcpyHostToDevice, s));
   }
   std::vector<T> download(hipStream_t s, size_t cnt = (size_t)-1) const {
     if (cnt == (size_t)-1) cnt = n;

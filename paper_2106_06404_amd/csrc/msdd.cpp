@@ -152,12 +152,14 @@ void build_groupset(const std::vector<GroupPlan>& G, const std::vector<std::vect
   out.total_rows = out.h_voff.back();
   std::vector<int32_t> row_grp(out.total_rows), slot_elem(soff.back()), slot_loc(soff.back() * k);
   std::vector<int64_t> inc_ptr(out.total_rows + 1, 0);
-  size_t ninc = 0;
-  for (auto& g : G) ninc += g.inc_t.size();
-  std::vector<int32_t> inc_slot(ninc), inc_a(ninc);
-  size_t q = 0;
-  for (size_t i = 0; i < G.size(); ++i) {
+  // incidence offsets per group, then every group fills its own ranges (in parallel)
+  std::vector<int64_t> qoff(G.size() + 1, 0);
+  for (size_t i = 0; i < G.size(); ++i) qoff[i + 1] = qoff[i] + (int64_t)G[i].inc_t.size();
+  std::vector<int32_t> inc_slot(qoff.back()), inc_a(qoff.back());
+  const int ng = (int)G.size();
+  parallel_for(ng, host_threads(ng), [&](int i, int) {
     const auto& g = G[i];
+    int64_t q = qoff[i];
     for (size_t r = 0; r < g.dofs.size(); ++r) {
       const int64_t gr = out.h_voff[i] + (int64_t)r;
       row_grp[gr] = (int32_t)i;
@@ -166,11 +168,11 @@ void build_groupset(const std::vector<GroupPlan>& G, const std::vector<std::vect
         inc_a[q] = g.inc_a[e];
         ++q;
       }
-      inc_ptr[gr + 1] = (int64_t)q;
+      inc_ptr[gr + 1] = q;
     }
     for (size_t t = 0; t < elems[i].size(); ++t) slot_elem[soff[i] + t] = elems[i][t];
     std::copy(g.eloc.begin(), g.eloc.end(), slot_loc.begin() + soff[i] * k);
-  }
+  });
   out.row_grp.upload(row_grp, s);
   out.slot_elem.upload(slot_elem, s);
   out.slot_loc.upload(slot_loc, s);
@@ -180,7 +182,8 @@ void build_groupset(const std::vector<GroupPlan>& G, const std::vector<std::vect
   out.voff.upload(out.h_voff, s);
   out.n.upload(out.h_n, s);
   out.bw.upload(out.h_bw, s);
-  HIPCHK(hipStreamSynchronize(s));
+  // no wait: the uploads' sources are staged (pinned) or already copied, and the
+  // kernels that read them follow on the same stream
 }
 
 // ---------------------------------------------------------------------------
@@ -689,8 +692,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   F.dinc_ptr.upload(dptr, s);
   F.dinc_sub.upload(dsub, s);
   F.dinc_q.upload(dq, s);
-  HIPCHK(hipStreamSynchronize(s));
-  vlog(c, "plan: uploads", &tv);
+  vlog(c, "plan: uploads (queued)", &tv);
 }
 
 void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
@@ -1857,8 +1859,7 @@ int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
       }
       c->F.seed_id.upload(sid, s);
     }
-    HIPCHK(hipStreamSynchronize(s));
-    const double t1 = now_ms();
+    const double t1 = now_ms();  // host planning done; its uploads may still be in flight
     // the symbolic planning of the finest-level patches runs on a host thread (uploads on
     // a side stream) while the GPU factorises and solves the local eigenproblems
     if (!c->ustream) HIPCHK(hipStreamCreateWithFlags(&c->ustream, hipStreamNonBlocking));
