@@ -308,7 +308,10 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
   }
   __syncthreads();
   // M = Q diag(ev) Q^T, eigenvectors transposed into S (S[a*K + q] = Q(q, a))
-  wg_jacobi<double>(K, M, S, ev);
+  if (K == 16 && nt == 64)
+    wave_jacobi16(M, S, ev, wsp);
+  else
+    wg_jacobi<double>(K, M, S, ev);
   if (tid == 0) {  // sort descending (insertion sort, K <= 64)
     for (int a = 0; a < K; ++a) ord[a] = a;
     for (int a = 1; a < K; ++a) {

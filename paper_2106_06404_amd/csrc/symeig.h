@@ -240,6 +240,114 @@ __device__ __forceinline__ int wg_jacobi(int n, R* A, R* Zt, R* d) {
   return sweeps < 40 ? sweeps : -1;
 }
 
+// wg_jacobi for n = 16 on a single wavefront (the Rayleigh-Ritz problems of the
+// 16-column subspace iteration): the same rotations, ordering, skip test and output as
+// wg_jacobi, with the round's pairs computed from constants, the rotation from refined
+// hardware reciprocals and reciprocal square roots (two Newton steps each), the
+// convergence vote taken with a wavefront ballot, and the 64 2x2 block updates and
+// 128 eigenvector-row updates of a round spread one and two per lane.
+//   A, Zt: 16 x 16 (LDS), as for wg_jacobi; prm: 16 doubles of LDS.  blockDim.x == 64.
+__device__ __forceinline__ double rcp_refined(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  // r <- r (3 - x r^2) / 2, twice
+  r = r * fma(-0.5 * x, r * r, 1.5);
+  return r * fma(-0.5 * x, r * r, 1.5);
+}
+__device__ __forceinline__ int wave_jacobi16(double* A, double* Zt, double* d, double* prm) {
+  constexpr int n = 16, h = 8;
+  const int lane = threadIdx.x & 63;
+  const double tol = 1e-16;
+  for (int t = lane; t < n * n; t += 64) Zt[t] = ((t >> 4) == (t & 15)) ? 1.0 : 0.0;
+  __syncthreads();
+  // round r pairs k: k = 0 -> (15, r); else ((r + k) mod 15, (r - k) mod 15)
+  auto pair = [](int r, int k, int& p, int& q) {
+    if (k == 0) {
+      p = n - 1;
+      q = r;
+    } else {
+      p = r + k;
+      if (p >= n - 1) p -= n - 1;
+      q = r - k;
+      if (q < 0) q += n - 1;
+    }
+  };
+  int sweeps = 0;
+  for (; sweeps < 40; ++sweeps) {
+    bool big = false;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = lane + 64 * u, p = t >> 4, q = t & 15;
+      if (p < q) {
+        const double apq = A[t];
+        if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(A[p * (n + 1)] * A[q * (n + 1)]))) big = true;
+      }
+    }
+    if (!__any(big)) break;
+    for (int r = 0; r < n - 1; ++r) {
+      if (lane < h) {
+        int p, q;
+        pair(r, lane, p, q);
+        const double apq = A[p * n + q], app = A[p * (n + 1)], aqq = A[q * (n + 1)];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+          const double th = (aqq - app) * rcp_refined(2.0 * apq);
+          const double at = fabs(th);
+          double t = at > 1e150 ? 0.5 * rcp_refined(at) : rcp_refined(at + sqrt(1.0 + th * th));
+          if (th < 0) t = -t;
+          c = rsqrt_refined(1.0 + t * t);
+          s = t * c;
+        }
+        prm[2 * lane] = c;
+        prm[2 * lane + 1] = s;
+      }
+      __syncthreads();
+      {
+        const int k1 = lane >> 3, k2 = lane & 7;
+        int p1, q1, p2, q2;
+        pair(r, k1, p1, q1);
+        pair(r, k2, p2, q2);
+        const double c1 = prm[2 * k1], s1 = prm[2 * k1 + 1], c2 = prm[2 * k2], s2 = prm[2 * k2 + 1];
+        const double a = A[p1 * n + p2], b = A[p1 * n + q2], dd = A[q1 * n + p2], e = A[q1 * n + q2];
+        const double a1 = c1 * a - s1 * dd, b1 = c1 * b - s1 * e;
+        const double d1 = s1 * a + c1 * dd, e1 = s1 * b + c1 * e;
+        double a2 = c2 * a1 - s2 * b1, b2 = s2 * a1 + c2 * b1;
+        double d2 = c2 * d1 - s2 * e1, e2 = s2 * d1 + c2 * e1;
+        if (k1 == k2 && s1 != 0.0) {
+          b2 = 0.0;
+          d2 = 0.0;
+        }
+        A[p1 * n + p2] = a2;
+        A[p1 * n + q2] = b2;
+        A[q1 * n + p2] = d2;
+        A[q1 * n + q2] = e2;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int t = lane + 64 * u, k = t >> 4, col = t & 15;
+          const double c = prm[2 * k], s = prm[2 * k + 1];
+          if (s != 0.0) {
+            int p, q;
+            pair(r, k, p, q);
+            const double zp = Zt[p * n + col], zq = Zt[q * n + col];
+            Zt[p * n + col] = c * zp - s * zq;
+            Zt[q * n + col] = s * zp + c * zq;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = lane; t < n; t += 64) d[t] = A[t * (n + 1)];
+  __syncthreads();
+  return sweeps < 40 ? sweeps : -1;
+}
+
 #include "tridiag_dc.h"
 
 // LDS doubles of wg_syev_dc's workspace for a matrix of order up to n: the
