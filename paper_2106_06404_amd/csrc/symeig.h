@@ -241,10 +241,10 @@ __device__ __forceinline__ int wg_jacobi(int n, R* A, R* Zt, R* d) {
 }
 
 // wg_jacobi for n = 16 on a single wavefront (the Rayleigh-Ritz problems of the
-// 16-column subspace iteration): the same rotations, ordering, skip test and output as
-// wg_jacobi, with the round's pairs computed from constants, the rotation from refined
-// hardware reciprocals and reciprocal square roots (two Newton steps each), the
-// convergence vote taken with a wavefront ballot, and the 64 2x2 block updates and
+// 16-column subspace iteration): the same rotations, ordering, skip test (compared in
+// squares) and output as wg_jacobi, with the round's pairs computed from constants, the
+// rotation from refined hardware reciprocals and reciprocal square roots (two Newton
+// steps each), the convergence vote taken with a wavefront ballot, and the 64 2x2 block updates and
 // 128 eigenvector-row updates of a round spread one and two per lane.
 //   A, Zt: 16 x 16 (LDS), as for wg_jacobi; prm: 16 doubles of LDS.  blockDim.x == 64.
 __device__ __forceinline__ double rcp_refined(double x) {
@@ -263,7 +263,7 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
 __device__ __forceinline__ int wave_jacobi16(double* A, double* Zt, double* d, double* prm) {
   constexpr int n = 16, h = 8;
   const int lane = threadIdx.x & 63;
-  const double tol = 1e-16;
+  const double tol2 = 1e-32;  // the skip test of wg_jacobi, |a_pq| > 1e-16 sqrt(|a_pp a_qq|), squared
   for (int t = lane; t < n * n; t += 64) Zt[t] = ((t >> 4) == (t & 15)) ? 1.0 : 0.0;
   __syncthreads();
   // round r pairs k: k = 0 -> (15, r); else ((r + k) mod 15, (r - k) mod 15)
@@ -286,7 +286,7 @@ __device__ __forceinline__ int wave_jacobi16(double* A, double* Zt, double* d, d
       const int t = lane + 64 * u, p = t >> 4, q = t & 15;
       if (p < q) {
         const double apq = A[t];
-        if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(A[p * (n + 1)] * A[q * (n + 1)]))) big = true;
+        if (apq != 0.0 && apq * apq > tol2 * fabs(A[p * (n + 1)] * A[q * (n + 1)])) big = true;
       }
     }
     if (!__any(big)) break;
@@ -296,10 +296,11 @@ __device__ __forceinline__ int wave_jacobi16(double* A, double* Zt, double* d, d
         pair(r, lane, p, q);
         const double apq = A[p * n + q], app = A[p * (n + 1)], aqq = A[q * (n + 1)];
         double c = 1.0, s = 0.0;
-        if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+        if (apq != 0.0 && apq * apq > tol2 * fabs(app * aqq)) {
           const double th = (aqq - app) * rcp_refined(2.0 * apq);
           const double at = fabs(th);
-          double t = at > 1e150 ? 0.5 * rcp_refined(at) : rcp_refined(at + sqrt(1.0 + th * th));
+          const double w = 1.0 + th * th;
+          double t = at > 1e150 ? 0.5 * rcp_refined(at) : rcp_refined(at + w * rsqrt_refined(w));
           if (th < 0) t = -t;
           c = rsqrt_refined(1.0 + t * t);
           s = t * c;
