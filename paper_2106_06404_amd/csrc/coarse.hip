@@ -265,6 +265,49 @@ __global__ void k_dense_cholesky(const i64* __restrict__ off, const i32* __restr
   if (threadIdx.x == 0) status[t] = ok ? ST_DONE : ST_NOTSPD;
 }
 
+// The same factorisation with the trailing matrix in LDS, packed lower triangle
+// (column c at c n - c (c - 1) / 2): the right-looking update a_rc -= a_rj a_cj / a_jj
+// reads column j unscaled while its scaled copy goes to the output; one barrier per
+// column.  For blocks whose packed triangle fits in LDS (dynamic size n (n + 1) / 2).
+__global__ void k_dense_cholesky_lds(const i64* __restrict__ off, const i32* __restrict__ n_arr,
+                                     double* __restrict__ A, int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* P = reinterpret_cast<double*>(smem_raw);
+  __shared__ int fail;
+  const int t = blockIdx.x;
+  const int n = n_arr[t];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tr = tid >> 5, tc = tid & 31, ng = nt >> 5;
+  double* Ag = A + off[t];
+  auto idx = [n](int r, int c) { return c * n - (c * (c - 1)) / 2 + (r - c); };
+  if (tid == 0) fail = 0;
+  for (int c = 0; c < n; ++c)
+    for (int r = c + tid; r < n; r += nt) P[idx(r, c)] = Ag[r + (i64)c * n];
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double ajj = P[idx(j, j)];
+    if (!(ajj > 0.0)) {
+      if (tid == 0) status[t] = ST_NOTSPD;
+      return;
+    }
+    const double il = 1.0 / sqrt(ajj), ia = 1.0 / ajj;
+    const double* Pj = P + idx(j, j);  // column j from its diagonal
+    for (int r = j + 1 + tid; r < n; r += nt) Ag[r + (i64)j * n] = Pj[r - j] * il;
+    for (int c = j + 1 + tc; c < n; c += 32) {
+      const double acj = Pj[c - j] * ia;
+      double* Pc = P + idx(c, c);
+      for (int r = c + tr; r < n; r += ng) Pc[r - c] -= Pj[r - j] * acj;
+    }
+    __syncthreads();
+  }
+  for (i64 e = tid; e < (i64)n * n; e += nt) {
+    const int r = (int)(e % n), c = (int)(e / n);
+    if (r < c) Ag[e] = 0.0;
+    if (r == c) Ag[e] = sqrt(P[idx(r, r)]);
+  }
+  if (tid == 0) status[t] = ST_DONE;
+}
+
 // Coarse GEVP of one level-(l-1) subdomain per workgroup, on its generating system
 // (owned functions first, no of them; Abar is ng x ng column-major):
 //   S = Abar + B with B = D Abar D, D the 0/1 owned mask;
@@ -462,8 +505,52 @@ __global__ void k_dense_to_layouts(const i64* __restrict__ off, const i32* __res
 // sequential triangular sweeps.  Step 1: Linv = L^{-1} (one thread per column,
 // forward substitution); step 2: Inv = Linv^T Linv (one thread per entry).
 // grid: (ceil(nmax / 256), targets); L, Linv, Inv column-major n x n at off[t].
-__global__ void k_tri_inverse(const i64* __restrict__ off, const i32* __restrict__ n_arr,
-                              const double* __restrict__ L, double* __restrict__ Linv) {
+// Inverse of a lower triangular block (column-major, n x n), one wavefront per column:
+// L x = e_c by column-oriented forward substitution, x held in registers (lane l owns
+// rows l, l + 64, ...); each step finishes x_q and subtracts L(r, q) x_q from the rows
+// below it, the same operations in the same order as a row-oriented substitution.
+template <int NR>
+__global__ void __launch_bounds__(64) k_tri_inverse(const i64* __restrict__ off,
+                                                    const i32* __restrict__ n_arr,
+                                                    const double* __restrict__ L,
+                                                    double* __restrict__ Linv) {
+  const int t = blockIdx.y;
+  const int n = n_arr[t];
+  const int c = blockIdx.x;
+  if (c >= n) return;
+  const double* Lt = L + off[t];
+  double* X = Linv + off[t];
+  const int lane = threadIdx.x;
+  double x[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) x[k] = (lane + 64 * k == c) ? 1.0 : 0.0;
+  for (int q = c; q < n; ++q) {
+    const double* Lq = Lt + (i64)q * n;  // column q
+    const int kq = q >> 6;
+    double xq = 0.0;
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if (k == kq) xq = x[k];
+    xq = __shfl(xq, q & 63) / Lq[q];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int r = lane + 64 * k;
+      if (r == q)
+        x[k] = xq;
+      else if (r > q && r < n)
+        x[k] -= Lq[r] * xq;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    const int r = lane + 64 * k;
+    if (r < n) X[r + (i64)c * n] = r >= c ? x[k] : 0.0;
+  }
+}
+
+// Larger blocks (up to 8192): one thread per column, row-oriented substitution.
+__global__ void k_tri_inverse_rows(const i64* __restrict__ off, const i32* __restrict__ n_arr,
+                                   const double* __restrict__ L, double* __restrict__ Linv) {
   const int t = blockIdx.y;
   const int n = n_arr[t];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -565,10 +652,18 @@ void launch_coarse_assemble(hipStream_t s, int nt, const i64* tp_ptr, const i32*
   hipLaunchKernelGGL(k_coarse_assemble, dim3(nt), dim3(MSDD_WG), 0, s, tp_ptr, tp_patch,
                      tp_map_off, tp_map, pM, pmoff, Pm, ng_arr, aoff, Aout);
 }
-void launch_dense_cholesky(hipStream_t s, int nt, const i64* off, const i32* n_arr, double* A,
-                           int* status) {
+void launch_dense_cholesky(hipStream_t s, int nt, int nmax, const i64* off, const i32* n_arr,
+                           double* A, int* status) {
   if (nt == 0) return;
-  hipLaunchKernelGGL(k_dense_cholesky, dim3(nt), dim3(1024), 0, s, off, n_arr, A, status);
+  const size_t lds = (size_t)nmax * (nmax + 1) / 2 * sizeof(double);
+  if (lds <= 150 * 1024) {
+    if (lds > 65536)
+      (void)hipFuncSetAttribute((const void*)k_dense_cholesky_lds,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_dense_cholesky_lds, dim3(nt), dim3(1024), lds, s, off, n_arr, A, status);
+  } else {
+    hipLaunchKernelGGL(k_dense_cholesky, dim3(nt), dim3(1024), 0, s, off, n_arr, A, status);
+  }
 }
 void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_arr,
                         const i64* aoff, double* Abar, const i64* loff, double* Lo,
@@ -598,8 +693,14 @@ void launch_dense_to_layouts(hipStream_t s, int nt, const i64* off, const i32* n
 void launch_spd_inverse(hipStream_t s, int nt, int nmax, const i64* off, const i32* n_arr,
                         const double* L, double* Linv, double* Inv) {
   if (!nt || nmax <= 0) return;
-  hipLaunchKernelGGL(k_tri_inverse, dim3((nmax + 255) / 256, nt), dim3(256), 0, s, off, n_arr, L,
-                     Linv);
+  // one wavefront per column, rows in registers, up to 1024 x 1024 blocks
+  if (nmax <= 256)
+    hipLaunchKernelGGL(k_tri_inverse<4>, dim3(nmax, nt), dim3(64), 0, s, off, n_arr, L, Linv);
+  else if (nmax <= 1024)
+    hipLaunchKernelGGL(k_tri_inverse<16>, dim3(nmax, nt), dim3(64), 0, s, off, n_arr, L, Linv);
+  else
+    hipLaunchKernelGGL(k_tri_inverse_rows, dim3((nmax + 255) / 256, nt), dim3(256), 0, s, off,
+                       n_arr, L, Linv);
   const i64 nn = (i64)nmax * nmax;
   hipLaunchKernelGGL(k_gram_lower, dim3((unsigned)((nn + 255) / 256), nt), dim3(256), 0, s, off,
                      n_arr, Linv, Inv);

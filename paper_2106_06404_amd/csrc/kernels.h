@@ -89,8 +89,8 @@ void launch_coarse_assemble(hipStream_t s, int nt, const i64* tp_ptr, const i32*
                             const i64* tp_map_off, const i32* tp_map, const i32* pM,
                             const i64* pmoff, const double* Pm, const i32* ng_arr,
                             const i64* aoff, double* Aout);
-void launch_dense_cholesky(hipStream_t s, int nt, const i64* off, const i32* n_arr, double* A,
-                           int* status);
+void launch_dense_cholesky(hipStream_t s, int nt, int nmax, const i64* off, const i32* n_arr,
+                           double* A, int* status);
 void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_arr,
                         const i64* aoff, double* Abar, const i64* loff, double* Lo,
                         const i64* soff, double* scratch, double eta, int nev_max,

@@ -1529,7 +1529,7 @@ void coarsest(msdd_ctx* c, const PatchLevel& PL, const std::vector<int32_t>& m_l
   }
   {
     ProfScope ps(c, PR_COARSE, by, fl);
-    launch_dense_cholesky(s, nprob, c->a0off.p, c->n0blk.p, c->A0.p, st.p);
+    launch_dense_cholesky(s, nprob, nmax, c->a0off.p, c->n0blk.p, c->A0.p, st.p);
   }
   HIPCHK(hipGetLastError());
   std::vector<int> v = st.download(s);
