@@ -357,12 +357,15 @@ typedef struct {
                              2 = rolling window, 16 columns; 3 = one wavefront per column;
                              4 = rolling window, 4 wavefronts of 4 columns; 5 = rolling
                              window, 8 wavefronts of 2 columns; 6 = as 5 plus 4 staging
-                             wavefronts; 7 = as 4 plus 4 staging wavefronts */
+                             wavefronts; 7 = as 4 plus 4 staging wavefronts; 8 = blocked
+                             solve with per-block inverses of 64-row blocks on the
+                             matrix cores (half-bandwidths up to 64; by shape when
+                             available) */
   int32_t eig_splits;     /* row splits per subdomain of the Gram / update kernels:
                              0 = by size, else 1..16 */
   int32_t fine_solve;     /* 0 = by shape; 1 = rolling window; 2 = one wavefront per subdomain */
   int32_t spmv_group;     /* lanes per CSR row: 0 = by average row length, else 4, 8, 16, 32 */
-  float eig_solve_ms[8];  /* [v] for eig_solve = v (v = 1..7; 0 = not run or not applicable) */
+  float eig_solve_ms[9];  /* [v] for eig_solve = v (v = 1..8; 0 = not run or not applicable) */
   float eig_splits_ms[5]; /* for 1, 2, 4, 8, 16 splits */
   float fine_solve_ms[3]; /* [v] for fine_solve = v (v = 1, 2) */
   float spmv_ms[4];       /* for 4, 8, 16, 32 lanes */

@@ -25,6 +25,15 @@ void launch_band_cholesky(hipStream_t s, int nsubs, const i32* subs, int bmax, c
                           T* Lc, T* Lr, int* status);
 // Cholesky factor (column layout) -> LDL^T factor in row layout F and, in place,
 // in column layout Lc (both with 1/D on the diagonal slot).
+// band_blocked.hip: blocked solves with per-block inverses (half-bandwidth <= 64)
+int64_t band_block_doubles(int n);  // storage of one subdomain's blocked factor
+void launch_band_block_build(hipStream_t s, int nsubs, int nmax, int bmax, const i32* n_arr,
+                             const i32* b_arr, const i64* l_off, const double* Fr,
+                             const i64* blk_off, double* out);
+void launch_band_solve_blk(hipStream_t s, int nsubs, const i32* subs, const i32* n_arr,
+                           const i32* b_arr, const i64* blk_off, const double* LB,
+                           const i64* v_off, int K, const double* W, double* Y,
+                           const int* active);
 template <typename T>
 void launch_band_to_ldl(hipStream_t s, int nsubs, int nmax, int bmax, const i32* n_arr,
                         const i32* b_arr, const i64* off, T* Lc, T* F);

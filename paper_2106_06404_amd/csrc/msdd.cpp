@@ -217,6 +217,12 @@ struct FineLevel {
   DVec<int32_t> ell_col;
   DVec<double> ell_val;
   DVec<double> LSc, LSr;                // LDL^T factor of S = abar + sigma*b (column, row layouts)
+  // blocked form of the same factor (per 64-row block: inverse of the diagonal block and
+  // the couplings multiplied by it); built when every half-bandwidth is at most 64
+  std::vector<int64_t> h_lbo;
+  DVec<int64_t> lbo;
+  DVec<double> LB;
+  bool has_lb = false;
   // Dirichlet
   std::vector<int32_t> h_nd, h_bd, h_dpos, h_dglob, h_rankb;
   std::vector<int64_t> h_doff, h_dboff;
@@ -739,6 +745,18 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   launch_band_to_ldl<double>(s, P, F.nb_max, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.LSc.p,
                              F.LSr.p);
   HIPCHK(hipGetLastError());
+  F.has_lb = F.bw_max <= 64;
+  if (F.has_lb) {
+    F.h_lbo.assign(P + 1, 0);
+    for (int i = 0; i < P; ++i) F.h_lbo[i + 1] = F.h_lbo[i] + band_block_doubles(F.gs.h_n[i]);
+    F.lbo.upload(F.h_lbo, s);
+    F.LB.alloc(F.h_lbo.back());
+    ProfScope ps(c, PR_CHOL, F.s_band * 8.0 + (double)F.h_lbo.back() * 8.0,
+                 (double)F.h_lbo.back() * 1.25 * F.bw_max);
+    launch_band_block_build(s, P, F.nb_max, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.LSr.p,
+                            F.lbo.p, F.LB.p);
+    HIPCHK(hipGetLastError());
+  }
   if (c->opt.precision == MSDD_MIXED) {
     // single precision: factor diag(sc) A_i diag(sc), sc = diag(A_i)^{-1/2}
     F.dscale.alloc(std::max<int64_t>(F.h_doff.back(), 1));
@@ -778,6 +796,24 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   launch_band_to_ldl<double>(s, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.LDc.p, F.LDr.p);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
+}
+
+// Band solves Y = S^{-1} W of the eigensolver (K columns per subdomain, skipped where
+// status is not running).  variant: 0 = by shape (blocked with per-block inverses when
+// the blocked factor exists), 1..7 = rolling-window / per-column shapes, 8 = blocked.
+void eig_band_solve(msdd_ctx* c, hipStream_t s, const int64_t* kvoff, int K, const double* W,
+                    double* Y, const int* status, int variant) {
+  FineLevel& F = c->F;
+  if (variant == 0) variant = F.has_lb ? 8 : 0;
+  if (variant == 8 && F.has_lb) {
+    REQUIRE(W != Y, "blocked band solve: right-hand side and solution must be distinct");
+    launch_band_solve_blk(s, F.P, nullptr, F.gs.n.p, F.gs.bw.p, F.lbo.p, F.LB.p, kvoff, K, W, Y,
+                          status);
+    return;
+  }
+  launch_band_solve_multi<double, double>(s, F.P, nullptr, F.nb_max, F.gs.n.p, F.gs.bw.p,
+                                          F.boff.p, F.LSc.p, F.LSr.p, kvoff, K, W, Y, status,
+                                          F.bw_max, variant == 8 ? 0 : variant);
 }
 
 void fine_eigensolve(msdd_ctx* c) {
@@ -871,9 +907,7 @@ void fine_eigensolve(msdd_ctx* c) {
       {
         ProfScope ps(c, PR_EIG_SOLVE, f * (2.0 * F.s_band * 8.0 + 4.0 * F.s_nb * K * 8.0),
                      f * 4.0 * F.s_nbb * K);
-        launch_band_solve_multi<double, double>(s, P, nullptr, F.nb_max, F.gs.n.p, F.gs.bw.p,
-                                                F.boff.p, F.LSc.p, F.LSr.p, dkvoff.p, K, BX.p,
-                                                Y.p, status.p, F.bw_max, c->tune.eig_solve);
+        eig_band_solve(c, s, dkvoff.p, K, BX.p, Y.p, status.p, c->tune.eig_solve);
       }
       {
         ProfScope ps(c, PR_EIG_BAPPLY, f * (F.s_nb * F.ell_w * 12.0 + 2.0 * F.s_nb * K * 8.0),
@@ -2250,12 +2284,11 @@ int msdd_autotune(msdd_ctx* c, int32_t what, int32_t reps) {
       Z.zero(s);
       for (float& v : T.eig_solve_ms) v = 0.f;
       int best = 0;
-      for (int v = 1; v <= 7; ++v) {
-        if (v != 3 && F.bw_max >= 64) continue;  // rolling window needs a band below 64
+      for (int v = 1; v <= 8; ++v) {
+        if (v != 3 && v != 8 && F.bw_max >= 64) continue;  // rolling window: band below 64
+        if (v == 8 && !F.has_lb) continue;                   // blocked: band at most 64
         T.eig_solve_ms[v] = time_it([&] {
-          launch_band_solve_multi<double, double>(s, P, nullptr, F.nb_max, F.gs.n.p, F.gs.bw.p,
-                                                  F.boff.p, F.LSc.p, F.LSr.p, dkvoff.p, K, W.p,
-                                                  Y.p, nullptr, F.bw_max, v);
+          eig_band_solve(c, s, dkvoff.p, K, W.p, Y.p, nullptr, v);
         });
         if (!best || T.eig_solve_ms[v] < T.eig_solve_ms[best]) best = v;
       }
@@ -2329,7 +2362,7 @@ int msdd_get_tuning(const msdd_ctx* c, msdd_tuning_t* t) {
 
 int msdd_set_tuning(msdd_ctx* c, const msdd_tuning_t* t) {
   if (!c || !t) return MSDD_EINVAL;
-  const bool ok = t->eig_solve >= 0 && t->eig_solve <= 7 && t->eig_splits >= 0 &&
+  const bool ok = t->eig_solve >= 0 && t->eig_solve <= 8 && t->eig_splits >= 0 &&
                   t->eig_splits <= 16 && t->fine_solve >= 0 && t->fine_solve <= 2 &&
                   (t->spmv_group == 0 || t->spmv_group == 4 || t->spmv_group == 8 ||
                    t->spmv_group == 16 || t->spmv_group == 32);
