@@ -360,12 +360,16 @@ typedef struct {
                              wavefronts; 7 = as 4 plus 4 staging wavefronts; 8 = blocked
                              solve with per-block inverses of 64-row blocks on the
                              matrix cores (half-bandwidths up to 64; by shape when
-                             available) */
+                             available); 9 = as 8 in four launches, the block-diagonal
+                             products apart from the block-to-block chain */
   int32_t eig_splits;     /* row splits per subdomain of the Gram / update kernels:
                              0 = by size, else 1..16 */
   int32_t fine_solve;     /* 0 = by shape; 1 = rolling window; 2 = one wavefront per subdomain */
   int32_t spmv_group;     /* lanes per CSR row: 0 = by average row length, else 4, 8, 16, 32 */
-  float eig_solve_ms[9];  /* [v] for eig_solve = v (v = 1..8; 0 = not run or not applicable) */
+  float eig_solve_ms[10]; /* [v] for eig_solve = v (v = 1..9; 0 = not run or not
+                             applicable): time per eigensolver iteration, from launches
+                             with all subdomains active and with the longest-iterating
+                             one alone, weighed by the last setup's iteration counts */
   float eig_splits_ms[5]; /* for 1, 2, 4, 8, 16 splits */
   float fine_solve_ms[3]; /* [v] for fine_solve = v (v = 1, 2) */
   float spmv_ms[4];       /* for 4, 8, 16, 32 lanes */

@@ -65,7 +65,7 @@ MSDD_TUNE_SOLVE = 2
 class MsddTuning(ctypes.Structure):
     _fields_ = [("eig_solve", ctypes.c_int32), ("eig_splits", ctypes.c_int32),
                 ("fine_solve", ctypes.c_int32), ("spmv_group", ctypes.c_int32),
-                ("eig_solve_ms", ctypes.c_float * 9), ("eig_splits_ms", ctypes.c_float * 5),
+                ("eig_solve_ms", ctypes.c_float * 10), ("eig_splits_ms", ctypes.c_float * 5),
                 ("fine_solve_ms", ctypes.c_float * 3), ("spmv_ms", ctypes.c_float * 4)]
 
     def as_dict(self):

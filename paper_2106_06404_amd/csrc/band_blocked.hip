@@ -123,6 +123,17 @@ void launch_band_block_build(hipStream_t s, int nsubs, int nmax, int bmax, const
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
+// 16 inner steps of a 16 x 16 product tile in four independent accumulator chains
+// (step s into chain s % 4), summed at the end: a chain of dependent products waits
+// the full latency of each, four chains keep the matrix core issuing.
+__device__ __forceinline__ dbl4 mfma16(const double (&a)[16], const double (&b)[16], dbl4 init) {
+  dbl4 c[4] = {init, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+  for (int s = 0; s < 16; ++s)
+    c[s & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c[s & 3], 0, 0, 0);
+  return (c[0] + c[1]) + (c[2] + c[3]);
+}
+
 // Buffer loads and stores with the hardware range check: an offset at or past the
 // buffer's size reads 0 and drops the store, without a branch.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t dbuf(const double* p, unsigned bytes) {
@@ -192,15 +203,17 @@ __global__ void __launch_bounds__(256) k_band_solve_blk(
     }
   };
   auto fstep = [&](int q, const double (&m)[16], const double (&p)[16], const double (&v)[16]) {
-    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    double a[16], y[16];
 #pragma unroll
-    for (int s = 0; s < 16; ++s)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s <= mhi ? m[s] : 0.0, v[s], acc, 0, 0, 0);
+    for (int s = 0; s < 16; ++s) a[s] = s <= mhi ? m[s] : 0.0;
+    dbl4 acc = mfma16(a, v, dbl4{0.0, 0.0, 0.0, 0.0});
     const double* yp = ybuf[(q + 1) & 1];  // y_{q-1}; zeros for q = 0 (P_0 is zero too)
 #pragma unroll
-    for (int s = 0; s < 16; ++s)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s >= plo ? p[s] : 0.0,
-                                                 yp[(4 * s + kr) * 16 + cl], acc, 0, 0, 0);
+    for (int s = 0; s < 16; ++s) {
+      a[s] = s >= plo ? p[s] : 0.0;
+      y[s] = yp[(4 * s + kr) * 16 + cl];
+    }
+    acc = mfma16(a, y, acc);
     double* yc = ybuf[q & 1];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -240,16 +253,18 @@ __global__ void __launch_bounds__(256) k_band_solve_blk(
     }
   };
   auto bstep = [&](int q, const double (&nf)[16], const double (&qf)[16], const double (&v)[16]) {
-    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    double a[16], y[16];
 #pragma unroll
-    for (int s = 0; s < 16; ++s)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s >= nlo ? nf[s] : 0.0, v[s], acc, 0, 0, 0);
+    for (int s = 0; s < 16; ++s) a[s] = s >= nlo ? nf[s] : 0.0;
+    dbl4 acc = mfma16(a, v, dbl4{0.0, 0.0, 0.0, 0.0});
     // x_{q+1}; for the last block Q is zero and the buffer holds finite forward values
     const double* xp = ybuf[(q + 1) & 1];
 #pragma unroll
-    for (int s = 0; s < 16; ++s)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s <= qhi ? qf[s] : 0.0,
-                                                 xp[(4 * s + kr) * 16 + cl], acc, 0, 0, 0);
+    for (int s = 0; s < 16; ++s) {
+      a[s] = s <= qhi ? qf[s] : 0.0;
+      y[s] = xp[(4 * s + kr) * 16 + cl];
+    }
+    acc = mfma16(a, y, acc);
     double* xc = ybuf[q & 1];
 #pragma unroll
     for (int r = 0; r < 4; ++r) xc[(16 * t + kr + 4 * r) * 16 + cl] = acc[r];
@@ -272,6 +287,164 @@ __global__ void __launch_bounds__(256) k_band_solve_blk(
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// The same solve in four launches, so that only the couplings stay on the chain:
+//   1. u_q = M_q v_q for all blocks at once          (k_blk_diag, into Y)
+//   2. y_q = u_q - P_q y_{q-1}, block after block     (k_blk_chain<true>, in place)
+//   3. w_q = N_q y_q for all blocks at once          (k_blk_diag, in place)
+//   4. x_q = w_q - Q_q x_{q+1}, block after block     (k_blk_chain<false>, in place)
+// Steps 1 and 3 spread over (subdomain, block, 16 columns) workgroups; a chain step
+// is the coupling product alone and its operands are loaded two blocks ahead.  When few subdomains remain this keeps
+// one compute unit per subdomain from carrying all the products.
+// ---------------------------------------------------------------------------
+
+// Grid (subdomains, blocks, ceil(K / 16)), 256 threads; wavefront t computes rows
+// 16t..16t+15 of the block.  which = 0: Y = M W (block-diagonal part of the forward
+// sweep); which = 2: Y = N Y in place.
+__global__ void __launch_bounds__(256) k_blk_diag(
+    const i32* __restrict__ subs, const i32* __restrict__ n_arr,
+    const i64* __restrict__ blk_off, const double* __restrict__ LB,
+    const i64* __restrict__ v_off, int K, const double* Win, double* Yout,
+    const int* __restrict__ active, int which) {
+  const int i = subs ? subs[blockIdx.x] : blockIdx.x;
+  if (active && active[i] != ST_RUNNING) return;
+  const int n = n_arr[i];
+  const int q = blockIdx.y;
+  if (q * 64 >= n) return;
+  const int c0 = blockIdx.z * 16;
+  const int ncol = min(16, K - c0);
+  const int t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int kr = lane >> 4, cl = lane & 15;
+  const bool colok = cl < ncol;
+  const i64 cb = v_off[i] + (i64)c0 * n;
+  const unsigned bytes = (unsigned)ncol * (unsigned)n * 8u;
+  const __amdgpu_buffer_rsrc_t rx = dbuf((which == 0 ? Win : Yout) + cb, bytes);
+  const __amdgpu_buffer_rsrc_t ry = dbuf(Yout + cb, bytes);
+  auto offs = [&](int row) -> unsigned {
+    return (row < n && colok) ? ((unsigned)cl * (unsigned)n + (unsigned)row) * 8u : 0xfffffff0u;
+  };
+  // M is lower triangular (row tile t: inner steps 0..4t+3), N upper (4t..15)
+  const int lo = which == 0 ? 0 : 4 * t, hi = which == 0 ? 4 * t + 3 : 15;
+  const double* base = LB + blk_off[i] + (i64)q * BSTRIDE + which * BMAT + (t * 16) * 64 + lane;
+  double a[16], v[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    a[s] = base[(s >= lo && s <= hi ? s : lo) * 64];
+    v[s] = dbuf_load(rx, offs(q * 64 + 4 * s + kr));
+  }
+#pragma unroll
+  for (int s = 0; s < 16; ++s) a[s] = s >= lo && s <= hi ? a[s] : 0.0;
+  const dbl4 acc = mfma16(a, v, dbl4{0.0, 0.0, 0.0, 0.0});
+  if (which != 0) __syncthreads();  // in place: every wavefront has read the block
+#pragma unroll
+  for (int r = 0; r < 4; ++r) dbuf_store(ry, offs(q * 64 + 16 * t + kr + 4 * r), acc[r]);
+}
+
+// Grid (subdomains, ceil(K / 16)), 256 threads.  Forward: Y_q <- Y_q - P_q y_{q-1} for
+// q = 0, 1, ...; backward: Y_q <- Y_q - Q_q x_{q+1} for q = last, ..., 0.  Each lane
+// reads and writes only its own rows of Y (the result layout of the products), so the
+// update is in place without a race; the chain value goes through LDS.
+template <bool FWD>
+__global__ void __launch_bounds__(256) k_blk_chain(
+    const i32* __restrict__ subs, const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
+    const i64* __restrict__ blk_off, const double* __restrict__ LB,
+    const i64* __restrict__ v_off, int K, double* __restrict__ Yout,
+    const int* __restrict__ active) {
+  __shared__ double ybuf[2][64 * 16];
+  const int i = subs ? subs[blockIdx.x] : blockIdx.x;
+  if (active && active[i] != ST_RUNNING) return;
+  const int n = n_arr[i], b = b_arr[i];
+  const int nblk = (n + 63) >> 6;
+  const int c0 = blockIdx.y * 16;
+  const int ncol = min(16, K - c0);
+  const int t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int kr = lane >> 4, cl = lane & 15;
+  const bool colok = cl < ncol;
+  const i64 cb = v_off[i] + (i64)c0 * n;
+  const unsigned bytes = (unsigned)ncol * (unsigned)n * 8u;
+  const __amdgpu_buffer_rsrc_t ry = dbuf(Yout + cb, bytes);
+  auto offs = [&](int row) -> unsigned {
+    return (row >= 0 && row < n && colok) ? ((unsigned)cl * (unsigned)n + (unsigned)row) * 8u
+                                          : 0xfffffff0u;
+  };
+  // P: nonzero inner steps plo..15 (last b columns); Q: 0..qhi (first b columns)
+  const int lo = FWD ? max(0, (64 - b) >> 2) : 0;
+  const int hi = FWD ? 15 : min(15, (b - 1) >> 2);
+  const double* Lb = LB + blk_off[i] + (FWD ? BMAT : 3 * BMAT) + (t * 16) * 64 + lane;
+  for (int e = threadIdx.x; e < 2 * 64 * 16; e += 256) (&ybuf[0][0])[e] = 0.0;
+  __syncthreads();
+  // step j processes block q(j) = j (forward) or nblk-1-j (backward); steps past the
+  // last block read a valid block's fragments and store nothing
+  auto blk = [&](int j) { return FWD ? j : nblk - 1 - j; };
+  auto load = [&](int j, double (&f)[16], double (&u)[4]) {
+    const int q = blk(j);
+    const double* base = Lb + (i64)min(max(q, 0), nblk - 1) * BSTRIDE;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) f[s] = base[(s >= lo && s <= hi ? s : lo) * 64];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) u[r] = dbuf_load(ry, offs(q * 64 + 16 * t + kr + 4 * r));
+  };
+  auto step = [&](int j, const double (&f)[16], const double (&u)[4]) {
+    const int q = blk(j);
+    dbl4 acc = {u[0], u[1], u[2], u[3]};
+    const double* yp = ybuf[(j + 1) & 1];  // the previous step's chain value (zeros at j = 0)
+    // all LDS reads first, then the products with zeros for the empty inner steps: no
+    // branches, so the reads are issued together and waited for once
+    double a[16], y[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      a[s] = s >= lo && s <= hi ? f[s] : 0.0;
+      y[s] = yp[(4 * s + kr) * 16 + cl];
+    }
+    acc = mfma16(a, y, acc);
+    double* yc = ybuf[j & 1];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int lr = 16 * t + kr + 4 * r;
+      yc[lr * 16 + cl] = acc[r];
+      dbuf_store(ry, offs(q * 64 + lr), acc[r]);
+    }
+    lds_barrier();
+  };
+  double f0[16], f1[16], f2[16], u0[4], u1[4], u2[4];
+  load(0, f0, u0);
+  load(1, f1, u1);
+  for (int j = 0; j < nblk; j += 3) {
+    // operands two steps ahead; scheduling barriers keep each group of loads together
+    load(j + 2, f2, u2);
+    __builtin_amdgcn_sched_barrier(0);
+    step(j, f0, u0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(j + 3, f0, u0);
+    __builtin_amdgcn_sched_barrier(0);
+    step(j + 1, f1, u1);
+    __builtin_amdgcn_sched_barrier(0);
+    load(j + 4, f1, u1);
+    __builtin_amdgcn_sched_barrier(0);
+    step(j + 2, f2, u2);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+void launch_band_solve_blk4(hipStream_t s, int nsubs, const i32* subs, int nmax,
+                            const i32* n_arr, const i32* b_arr, const i64* blk_off,
+                            const double* LB, const i64* v_off, int K, const double* W,
+                            double* Y, const int* active) {
+  // the caller guarantees W != Y and a blocked factor built from half-bandwidths <= 64
+  if (nsubs == 0 || K == 0 || nmax == 0) return;
+  const dim3 gd(nsubs, (nmax + 63) / 64, (K + 15) / 16), gc(nsubs, (K + 15) / 16);
+  hipLaunchKernelGGL(k_blk_diag, gd, dim3(256), 0, s, subs, n_arr, blk_off, LB, v_off, K, W, Y,
+                     active, 0);
+  hipLaunchKernelGGL(k_blk_chain<true>, gc, dim3(256), 0, s, subs, n_arr, b_arr, blk_off, LB,
+                     v_off, K, Y, active);
+  hipLaunchKernelGGL(k_blk_diag, gd, dim3(256), 0, s, subs, n_arr, blk_off, LB, v_off, K, Y, Y,
+                     active, 2);
+  hipLaunchKernelGGL(k_blk_chain<false>, gc, dim3(256), 0, s, subs, n_arr, b_arr, blk_off, LB,
+                     v_off, K, Y, active);
 }
 
 void launch_band_solve_blk(hipStream_t s, int nsubs, const i32* subs, const i32* n_arr,

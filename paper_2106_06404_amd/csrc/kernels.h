@@ -30,6 +30,10 @@ int64_t band_block_doubles(int n);  // storage of one subdomain's blocked factor
 void launch_band_block_build(hipStream_t s, int nsubs, int nmax, int bmax, const i32* n_arr,
                              const i32* b_arr, const i64* l_off, const double* Fr,
                              const i64* blk_off, double* out);
+void launch_band_solve_blk4(hipStream_t s, int nsubs, const i32* subs, int nmax,
+                            const i32* n_arr, const i32* b_arr, const i64* blk_off,
+                            const double* LB, const i64* v_off, int K, const double* W,
+                            double* Y, const int* active);
 void launch_band_solve_blk(hipStream_t s, int nsubs, const i32* subs, const i32* n_arr,
                            const i32* b_arr, const i64* blk_off, const double* LB,
                            const i64* v_off, int K, const double* W, double* Y,

@@ -800,20 +800,25 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
 
 // Band solves Y = S^{-1} W of the eigensolver (K columns per subdomain, skipped where
 // status is not running).  variant: 0 = by shape (blocked with per-block inverses when
-// the blocked factor exists), 1..7 = rolling-window / per-column shapes, 8 = blocked.
+// the blocked factor exists), 1..7 = rolling-window / per-column shapes, 8 = blocked in
+// one launch, 9 = blocked in four launches (block-diagonal products apart from the chain).
 void eig_band_solve(msdd_ctx* c, hipStream_t s, const int64_t* kvoff, int K, const double* W,
                     double* Y, const int* status, int variant) {
   FineLevel& F = c->F;
   if (variant == 0) variant = F.has_lb ? 8 : 0;
-  if (variant == 8 && F.has_lb) {
+  if ((variant == 8 || variant == 9) && F.has_lb) {
     REQUIRE(W != Y, "blocked band solve: right-hand side and solution must be distinct");
-    launch_band_solve_blk(s, F.P, nullptr, F.gs.n.p, F.gs.bw.p, F.lbo.p, F.LB.p, kvoff, K, W, Y,
-                          status);
+    if (variant == 8)
+      launch_band_solve_blk(s, F.P, nullptr, F.gs.n.p, F.gs.bw.p, F.lbo.p, F.LB.p, kvoff, K, W,
+                            Y, status);
+    else
+      launch_band_solve_blk4(s, F.P, nullptr, F.nb_max, F.gs.n.p, F.gs.bw.p, F.lbo.p, F.LB.p,
+                             kvoff, K, W, Y, status);
     return;
   }
   launch_band_solve_multi<double, double>(s, F.P, nullptr, F.nb_max, F.gs.n.p, F.gs.bw.p,
                                           F.boff.p, F.LSc.p, F.LSr.p, kvoff, K, W, Y, status,
-                                          F.bw_max, variant == 8 ? 0 : variant);
+                                          F.bw_max, variant >= 8 ? 0 : variant);
 }
 
 void fine_eigensolve(msdd_ctx* c) {
@@ -2284,12 +2289,36 @@ int msdd_autotune(msdd_ctx* c, int32_t what, int32_t reps) {
       Z.zero(s);
       for (float& v : T.eig_solve_ms) v = 0.f;
       int best = 0;
-      for (int v = 1; v <= 8; ++v) {
-        if (v != 3 && v != 8 && F.bw_max >= 64) continue;  // rolling window: band below 64
-        if (v == 8 && !F.has_lb) continue;                   // blocked: band at most 64
-        T.eig_solve_ms[v] = time_it([&] {
+      // The eigensolver's launches run with every subdomain active at first and with few
+      // at the end.  Each candidate is timed with all active (t_all) and with only the
+      // subdomain that iterated longest (t_one, the latency of a lone subdomain); the
+      // estimate per iteration weighs the two by the last setup's iteration counts,
+      // sum over iterations k of t_one + (t_all - t_one) active(k) / P, over max_k.
+      int i_long = 0;
+      double it_sum = 0.0;
+      for (int i = 0; i < (int)c->eig_iters.size() && i < P; ++i) {
+        it_sum += c->eig_iters[i];
+        if (c->eig_iters[i] > c->eig_iters[i_long]) i_long = i;
+      }
+      const double it_max = c->eig_iters.empty() ? 0.0 : (double)c->eig_iters[i_long];
+      std::vector<int> st_one(P, ST_DONE);
+      st_one[i_long] = ST_RUNNING;
+      DVec<int> one;
+      one.upload(st_one, s);
+      for (int v = 1; v <= 9; ++v) {
+        if ((v < 3 || (v > 3 && v < 8)) && F.bw_max >= 64) continue;  // rolling window: b < 64
+        if (v >= 8 && !F.has_lb) continue;                              // blocked: b <= 64
+        const float t_all = time_it([&] {
           eig_band_solve(c, s, dkvoff.p, K, W.p, Y.p, nullptr, v);
         });
+        T.eig_solve_ms[v] = t_all;
+        if (it_max > 0) {
+          const float t_one = time_it([&] {
+            eig_band_solve(c, s, dkvoff.p, K, W.p, Y.p, one.p, v);
+          });
+          T.eig_solve_ms[v] =
+              (float)((it_max * t_one + (t_all - t_one) * it_sum / P) / it_max);
+        }
         if (!best || T.eig_solve_ms[v] < T.eig_solve_ms[best]) best = v;
       }
       T.eig_solve = best;
@@ -2362,7 +2391,7 @@ int msdd_get_tuning(const msdd_ctx* c, msdd_tuning_t* t) {
 
 int msdd_set_tuning(msdd_ctx* c, const msdd_tuning_t* t) {
   if (!c || !t) return MSDD_EINVAL;
-  const bool ok = t->eig_solve >= 0 && t->eig_solve <= 8 && t->eig_splits >= 0 &&
+  const bool ok = t->eig_solve >= 0 && t->eig_solve <= 9 && t->eig_splits >= 0 &&
                   t->eig_splits <= 16 && t->fine_solve >= 0 && t->fine_solve <= 2 &&
                   (t->spmv_group == 0 || t->spmv_group == 4 || t->spmv_group == 8 ||
                    t->spmv_group == 16 || t->spmv_group == 32);

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("eig_solve,eig_splits,fine_solve,spmv_group",
                          [(1, 1, 1, 4), (2, 3, 2, 8), (3, 16, 1, 32), (4, 8, 2, 16),
                           (5, 2, 1, 8), (6, 4, 2, 4), (7, 1, 1, 16),
-                          (8, 2, 2, 8)])
+                          (8, 2, 2, 8), (9, 4, 1, 16)])
 def test_every_variant_matches_oracle(eig_solve, eig_splits, fine_solve, spmv_group):
     # the problem of the two-level parity test, where the default shapes meet these bounds
     prob = P.small_problem(N=16, P=4, delta=1, contrast=1e6, seed=5)
@@ -38,7 +38,7 @@ def test_every_variant_matches_oracle(eig_solve, eig_splits, fine_solve, spmv_gr
 def test_set_tuning_rejects_out_of_range():
     from paper_2106_06404_amd import binding as B
     m = B.Msdd()
-    for kw in ({"eig_solve": 9}, {"eig_splits": 17}, {"fine_solve": 3}, {"spmv_group": 12}):
+    for kw in ({"eig_solve": 10}, {"eig_splits": 17}, {"fine_solve": 3}, {"spmv_group": 12}):
         with pytest.raises(B.MsddError):
             m.set_tuning(**kw)
     with pytest.raises(B.MsddError):
@@ -52,7 +52,7 @@ def test_autotune_picks_measured_shapes_and_keeps_results():
     it0, _, x0 = _solve(m, prob)
     lam0 = [m.eigs(1, i, 1) for i in range(prob.n_sub)]
     t = m.autotune(reps=3)
-    assert t["eig_solve"] in (1, 2, 3, 4, 5, 6, 7, 8) and t["eig_splits"] in (1, 2, 4, 8, 16)
+    assert t["eig_solve"] in (1, 2, 3, 4, 5, 6, 7, 8, 9) and t["eig_splits"] in (1, 2, 4, 8, 16)
     assert t["fine_solve"] in (1, 2) and t["spmv_group"] in (4, 8, 16, 32)
     # the choice is the fastest measured candidate
     assert t["eig_solve_ms"][t["eig_solve"]] == min(v for v in t["eig_solve_ms"][1:] if v > 0)
