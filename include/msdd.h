@@ -359,9 +359,9 @@ typedef struct {
                              window, 8 wavefronts of 2 columns; 6 = as 5 plus 4 staging
                              wavefronts; 7 = as 4 plus 4 staging wavefronts; 8 = blocked
                              solve with per-block inverses of 64-row blocks on the
-                             matrix cores (half-bandwidths up to 64; by shape when
-                             available); 9 = as 8 in four launches, the block-diagonal
-                             products apart from the block-to-block chain */
+                             matrix cores (half-bandwidths up to 64); 9 = as 8 in four
+                             launches, the block-diagonal products apart from the
+                             block-to-block chain (by shape when available) */
   int32_t eig_splits;     /* row splits per subdomain of the Gram / update kernels:
                              0 = by size, else 1..16 */
   int32_t fine_solve;     /* 0 = by shape; 1 = rolling window; 2 = one wavefront per subdomain */

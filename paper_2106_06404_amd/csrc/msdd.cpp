@@ -799,13 +799,13 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
 }
 
 // Band solves Y = S^{-1} W of the eigensolver (K columns per subdomain, skipped where
-// status is not running).  variant: 0 = by shape (blocked with per-block inverses when
-// the blocked factor exists), 1..7 = rolling-window / per-column shapes, 8 = blocked in
+// status is not running).  variant: 0 = by shape (blocked in four launches when the
+// blocked factor exists), 1..7 = rolling-window / per-column shapes, 8 = blocked in
 // one launch, 9 = blocked in four launches (block-diagonal products apart from the chain).
 void eig_band_solve(msdd_ctx* c, hipStream_t s, const int64_t* kvoff, int K, const double* W,
                     double* Y, const int* status, int variant) {
   FineLevel& F = c->F;
-  if (variant == 0) variant = F.has_lb ? 8 : 0;
+  if (variant == 0) variant = F.has_lb ? 9 : 0;
   if ((variant == 8 || variant == 9) && F.has_lb) {
     REQUIRE(W != Y, "blocked band solve: right-hand side and solution must be distinct");
     if (variant == 8)
