@@ -422,6 +422,10 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
 
 // Convergence decision of each running subdomain (one wavefront): sums the row-split
 // partials of k_eig_update, then the backward errors, Ritz values, count m and status.
+// backward error at which the pair that certifies the count is accepted (its relative
+// eigenvalue error then stays near 1e-11)
+constexpr double CERT_TOL = 1e-11;
+
 __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* __restrict__ part,
                             int S, double sigma, double eta, int nev_max, double tol, int maxit,
                             int* __restrict__ status, int* __restrict__ iters,
@@ -463,7 +467,13 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
     bool grow = (m + 1 + guard > kb) && (kb < rankb[i]) && (K < Kmax_allowed);
     int need = min(m + 1, kb);
     bool ok = true;
-    for (int a = 0; a < need; ++a) ok = ok && (sh_res[a] <= tol || sh_stag[a] > 0.0);
+    // the pair after the selected ones only certifies the count (its eigenvalue is at
+    // least eta); its Ritz value is accurate to about its backward error, so it is
+    // accepted at CERT_TOL, below the accuracy asked of reported eigenvalues
+    for (int a = 0; a < need; ++a) {
+      const double ta = (a == m && sh_lam[a] >= eta) ? fmax(tol, CERT_TOL) : tol;
+      ok = ok && (sh_res[a] <= ta || sh_stag[a] > 0.0);
+    }
     mcount[i] = m;
     if (grow) status[i] = ST_GROW;
     else if (ok) status[i] = ST_DONE;
