@@ -84,7 +84,7 @@ def bench_batch(args):
     ctx.profile(False)
     prof = ctx.profile_query()
     ctx.close()
-    rl_all = {k: roofline_entry(k, v) for k, v in prof.items() if v[1] > 0}
+    rl_all = {k: roofline_entry(k, v, counters=False) for k, v in prof.items() if v[1] > 0}
     dom = max(rl_all, key=lambda k: prof[k][0])
     xh = x.cpu().numpy()
     true_rel, base = [], 0
@@ -198,20 +198,23 @@ def cpu_baseline(prob, budget_s=20.0):
             "local_gevps_per_s": 1.0 / per}
 
 
-def roofline_entry(name, rec):
+def roofline_entry(name, rec, counters=True):
     """Achieved = algorithmic work per launch / average launch duration (HIP events on
-    the launching stream), against the MI355X peak of the resource that bounds it."""
+    the launching stream), against the MI355X peak of the resource that bounds it.
+    counters: attach the rocprofv3 traffic per launch, which was measured on the 512x512
+    inclusions workload only (False for any other workload)."""
     tot_ms, launches, byts, flops = rec
     avg_ms = tot_ms / launches
     if name in ALU_CLASSES:
         ach = (flops / launches) / (avg_ms * 1e-3) / 1e12
         return {"bound": "alu", "achieved": ach, "peak": FP64_VALU_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": ach / FP64_VALU_PEAK_TFS, "traffic": traffic_for(name),
+                "frac": ach / FP64_VALU_PEAK_TFS,
+                "traffic": traffic_for(name) if counters else None,
                 "alg_flops_per_launch": flops / launches, "avg_launch_ms": avg_ms,
                 "launches": launches}
     ach = (byts / launches) / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(name),
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(name) if counters else None,
             "alg_bytes_per_launch": byts / launches, "avg_launch_ms": avg_ms, "launches": launches}
 
 
@@ -364,7 +367,8 @@ def main():
     n_gevp = sum(st["n_sub"][1:])
     gevp_s = (st["t_gevp_ms"] + st["t_coarse_ms"]) * 1e-3
     # roofline of every kernel class, and of the dominant one (largest time per step)
-    rl_all = {k: roofline_entry(k, v) for k, v in prof.items() if v[1] > 0}
+    rl_all = {k: roofline_entry(k, v, counters=args.workload == "c2")
+              for k, v in prof.items() if v[1] > 0}
     dom = max(rl_all, key=lambda k: prof[k][0])
     out = {
         "metric": METRIC,
