@@ -745,12 +745,22 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   launch_band_to_ldl<double>(s, P, F.nb_max, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.LSc.p,
                              F.LSr.p);
   HIPCHK(hipGetLastError());
+  // the blocked form (about 3.4 times the band factor for half-bandwidths near 40) is
+  // built when the band allows it; if its memory cannot be had, the eigensolver uses
+  // the band-factor solves instead
   F.has_lb = F.bw_max <= 64;
   if (F.has_lb) {
     F.h_lbo.assign(P + 1, 0);
     for (int i = 0; i < P; ++i) F.h_lbo[i + 1] = F.h_lbo[i] + band_block_doubles(F.gs.h_n[i]);
+    try {
+      F.LB.alloc(F.h_lbo.back());
+    } catch (const MsddError&) {
+      F.has_lb = false;
+      F.LB.release();
+    }
+  }
+  if (F.has_lb) {
     F.lbo.upload(F.h_lbo, s);
-    F.LB.alloc(F.h_lbo.back());
     ProfScope ps(c, PR_CHOL, F.s_band * 8.0 + (double)F.h_lbo.back() * 8.0,
                  (double)F.h_lbo.back() * 1.25 * F.bw_max);
     launch_band_block_build(s, P, F.nb_max, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.LSr.p,
