@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -74,7 +75,22 @@ class PinnedArena {
       dst = chunks_[cur_].first + off_;
       off_ += need;
     }
-    std::memcpy(dst, src, bytes);
+    // large arrays are copied by several threads (a single thread moves only a few GB/s)
+    constexpr size_t kPar = (size_t)4 << 20;
+    if (bytes >= kPar) {
+      constexpr int kThr = 8;
+      const size_t part = ((bytes + kThr - 1) / kThr + 255) & ~(size_t)255;
+      const char* s = static_cast<const char*>(src);
+      std::vector<std::thread> th;
+      for (size_t a = part; a < bytes; a += part) {
+        const size_t len = a + part < bytes ? part : bytes - a;
+        th.emplace_back([dst, s, a, len] { std::memcpy(dst + a, s + a, len); });
+      }
+      std::memcpy(dst, s, part < bytes ? part : bytes);
+      for (auto& t : th) t.join();
+    } else {
+      std::memcpy(dst, src, bytes);
+    }
     return dst;
   }
   void reset() {
