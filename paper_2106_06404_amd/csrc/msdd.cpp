@@ -468,18 +468,20 @@ struct ProfScope {
   msdd_ctx* c;
   int id;
   double bytes, flops;
+  hipStream_t st;  // the stream the scope's kernels are launched on
   hipEvent_t a = nullptr;
-  ProfScope(msdd_ctx* c_, int id_, double bytes_ = 0, double flops_ = 0)
-      : c(c_), id(id_), bytes(bytes_), flops(flops_) {
+  ProfScope(msdd_ctx* c_, int id_, double bytes_ = 0, double flops_ = 0,
+            hipStream_t st_ = nullptr)
+      : c(c_), id(id_), bytes(bytes_), flops(flops_), st(st_ ? st_ : c_->stream) {
     if (c->prof.on) {
       a = c->prof.get();
-      HIPCHK(hipEventRecord(a, c->stream));
+      HIPCHK(hipEventRecord(a, st));
     }
   }
   ~ProfScope() {
     if (c->prof.on && a) {
       hipEvent_t b = c->prof.get();
-      if (hipEventRecord(b, c->stream) == hipSuccess) c->prof.recs.push_back({id, a, b, bytes, flops});
+      if (hipEventRecord(b, st) == hipSuccess) c->prof.recs.push_back({id, a, b, bytes, flops});
     }
   }
 };
@@ -701,6 +703,15 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   vlog(c, "plan: uploads (queued)", &tv);
 }
 
+// The side stream (default priority, non-blocking) and the two events that fork work
+// onto it and join it back, created on first use.
+void ensure_side_stream(msdd_ctx* c) {
+  if (c->cstream) return;
+  HIPCHK(hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&c->cev0, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c->cev1, hipEventDisableTiming));
+}
+
 void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   FineLevel& F = c->F;
   hipStream_t s = c->stream;
@@ -728,7 +739,56 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   }
   HIPCHK(hipGetLastError());
   check_status(status.download(s), "local matrix extraction");
-  // factorisations: S = abar + sigma * D abar D, and the Dirichlet matrices
+  // factorisations: S = abar + sigma * D abar D (eigensolver) and the Dirichlet matrices
+  // (preconditioner) are independent and each is latency bound (one workgroup per
+  // subdomain): the Dirichlet one runs on the side stream beside the other, joined
+  // before the statuses are read (its profile events are recorded on that stream)
+  ensure_side_stream(c);
+  const hipStream_t s2 = c->cstream;
+  DVec<int> st_scale, st_dchol;  // statuses of the Dirichlet path
+  st_scale.alloc(P);
+  st_dchol.alloc(P);
+  st_scale.zero(s);
+  st_dchol.zero(s);
+  HIPCHK(hipEventRecord(c->cev0, s));
+  HIPCHK(hipStreamWaitEvent(s2, c->cev0, 0));
+  const bool mixed = c->opt.precision == MSDD_MIXED;
+  if (mixed) {
+    // single precision: factor diag(sc) A_i diag(sc), sc = diag(A_i)^{-1/2}
+    F.dscale.alloc(std::max<int64_t>(F.h_doff.back(), 1));
+    launch_band_scale(s2, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.doff.p, F.Dband.p,
+                      F.dscale.p, st_scale.p);
+    HIPCHK(hipGetLastError());
+    F.LDc32.alloc(F.h_dboff.back());
+    F.LDr32.alloc(F.h_dboff.back());
+    F.LDc32.zero(s2);
+    F.LDr32.zero(s2);
+    {
+    ProfScope ps(c, PR_CHOL, F.s_dband * (8.0 + 2.0 * 4.0), F.s_ndbd * (F.bd_max + 2.0), s2);
+    launch_band_cholesky<float>(s2, P, nullptr, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.Dband.p,
+                                nullptr, nullptr, 0.0, F.dboff.p, F.LDc32.p, F.LDr32.p,
+                                st_dchol.p);
+    }
+    HIPCHK(hipGetLastError());
+    launch_band_to_ldl<float>(s2, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.LDc32.p,
+                              F.LDr32.p);
+    HIPCHK(hipGetLastError());
+  } else {
+    F.LDc.alloc(F.h_dboff.back());
+    F.LDr.alloc(F.h_dboff.back());
+    F.LDc.zero(s2);
+    F.LDr.zero(s2);
+    {
+    ProfScope ps(c, PR_CHOL, F.s_dband * 8.0 * 3.0, F.s_ndbd * (F.bd_max + 2.0), s2);
+    launch_band_cholesky<double>(s2, P, nullptr, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.Dband.p,
+                                 nullptr, nullptr, 0.0, F.dboff.p, F.LDc.p, F.LDr.p, st_dchol.p);
+    }
+    HIPCHK(hipGetLastError());
+    // the apply uses the LDL^T form: row layout in LDr, column layout in place in LDc
+    launch_band_to_ldl<double>(s2, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.LDc.p,
+                               F.LDr.p);
+    HIPCHK(hipGetLastError());
+  }
   F.LSc.alloc(F.h_boff.back());
   F.LSr.alloc(F.h_boff.back());
   F.LSc.zero(s);
@@ -740,7 +800,6 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
                                status.p);
   }
   HIPCHK(hipGetLastError());
-  check_status(status.download(s), "Cholesky of abar + sigma*b");
   // the eigensolver's solves use the LDL^T form: row layout in LSr, column layout in LSc
   launch_band_to_ldl<double>(s, P, F.nb_max, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.LSc.p,
                              F.LSr.p);
@@ -767,44 +826,15 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
                             F.lbo.p, F.LB.p);
     HIPCHK(hipGetLastError());
   }
-  if (c->opt.precision == MSDD_MIXED) {
-    // single precision: factor diag(sc) A_i diag(sc), sc = diag(A_i)^{-1/2}
-    F.dscale.alloc(std::max<int64_t>(F.h_doff.back(), 1));
-    launch_band_scale(s, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.doff.p, F.Dband.p,
-                      F.dscale.p, status.p);
-    HIPCHK(hipGetLastError());
-    check_status(status.download(s), "Dirichlet matrix diagonal");
-    F.LDc32.alloc(F.h_dboff.back());
-    F.LDr32.alloc(F.h_dboff.back());
-    F.LDc32.zero(s);
-    F.LDr32.zero(s);
-    {
-    ProfScope ps(c, PR_CHOL, F.s_dband * (8.0 + 2.0 * 4.0), F.s_ndbd * (F.bd_max + 2.0));
-    launch_band_cholesky<float>(s, P, nullptr, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.Dband.p,
-                                nullptr, nullptr, 0.0, F.dboff.p, F.LDc32.p, F.LDr32.p, status.p);
-    }
-    HIPCHK(hipGetLastError());
-    check_status(status.download(s), "single-precision Cholesky of the scaled Dirichlet matrices");
-    launch_band_to_ldl<float>(s, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.LDc32.p,
-                              F.LDr32.p);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
-    return;
+  HIPCHK(hipEventRecord(c->cev1, s2));
+  HIPCHK(hipStreamWaitEvent(s, c->cev1, 0));
+  check_status(status.download(s), "Cholesky of abar + sigma*b");
+  if (mixed) {
+    check_status(st_scale.download(s), "Dirichlet matrix diagonal");
+    check_status(st_dchol.download(s), "single-precision Cholesky of the scaled Dirichlet matrices");
+  } else {
+    check_status(st_dchol.download(s), "Cholesky of the Dirichlet matrices");
   }
-  F.LDc.alloc(F.h_dboff.back());
-  F.LDr.alloc(F.h_dboff.back());
-  F.LDc.zero(s);
-  F.LDr.zero(s);
-  {
-  ProfScope ps(c, PR_CHOL, F.s_dband * 8.0 * 3.0, F.s_ndbd * (F.bd_max + 2.0));
-  launch_band_cholesky<double>(s, P, nullptr, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.Dband.p,
-                               nullptr, nullptr, 0.0, F.dboff.p, F.LDc.p, F.LDr.p, status.p);
-  }
-  HIPCHK(hipGetLastError());
-  check_status(status.download(s), "Cholesky of the Dirichlet matrices");
-  // the apply uses the LDL^T form: row layout in LDr, column layout in place in LDc
-  launch_band_to_ldl<double>(s, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.LDc.p, F.LDr.p);
-  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
 }
 
@@ -1654,11 +1684,7 @@ void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
   const int L = c->n_levels - 1;
   double* rc_top = c->rlev[L - 1].p;  // level L-1 vector
   const bool fork = !c->prof.on;
-  if (fork && !c->cstream) {
-    HIPCHK(hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&c->cev0, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&c->cev1, hipEventDisableTiming));
-  }
+  if (fork) ensure_side_stream(c);
   const hipStream_t cs = fork ? c->cstream : s;
   {
     // gather (index + value) and u write, PhiD read, rc write
