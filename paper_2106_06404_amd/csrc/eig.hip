@@ -96,6 +96,64 @@ __global__ void k_bapply_ell(i64 total_rows, const i32* __restrict__ row_sub,
   }
 }
 
+// The same product with the columns staged in LDS: workgroup (i, j) computes rows
+// 256 j .. 256 j + 255 of subdomain i; the rows it reads (those within the
+// half-bandwidth b of its own) are loaded once per group of 16 columns, coalesced, into
+// LDS (column-major, tile[u * rows + row - lo]), instead of every row fetching its
+// neighbours' values from L2 (each value is read by about nine rows).
+__global__ void __launch_bounds__(256) k_bapply_tile(
+    const i64* __restrict__ voff, const i32* __restrict__ nb, const i32* __restrict__ bw,
+    const i64* __restrict__ kvoff, int K, const double* __restrict__ dv, int ell_w,
+    const i32* __restrict__ ell_col, const double* __restrict__ ell_val,
+    const double* __restrict__ Y, double* __restrict__ Z, const int* __restrict__ active) {
+  extern __shared__ double tile[];
+  const int i = blockIdx.x;
+  if (active && active[i] != ST_RUNNING) return;
+  const int n = nb[i];
+  const int r0 = blockIdx.y * 256;
+  if (r0 >= n) return;
+  const int b = bw[i];
+  const int lo = max(0, r0 - b), hi = min(n, r0 + 256 + b);
+  const int rows = hi - lo;
+  const double* Yi = Y + kvoff[i];
+  double* Zi = Z + kvoff[i];
+  const double* d = dv + voff[i];
+  const int r = r0 + threadIdx.x;
+  const bool own = r < n;
+  const i64 g = voff[i] + (own ? r : 0);
+  const i32* ec = ell_col + g * ell_w;
+  const double* ev = ell_val + g * ell_w;
+  const double dr = own ? d[r] : 0.0;
+  for (int c0 = 0; c0 < K; c0 += 16) {
+    const int kc = min(16, K - c0);
+    __syncthreads();  // the previous group's reads of the tile are done
+    for (int e = threadIdx.x; e < kc * rows; e += 256) {
+      const int u = e / rows, rr = e - u * rows;
+      tile[u * rows + rr] = Yi[(i64)(c0 + u) * n + lo + rr];
+    }
+    __syncthreads();
+    if (!own) continue;
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    if (dr != 0.0) {
+      // padding entries (column -1) read this row's own values with coefficient 0
+      for (int t = 0; t < ell_w; ++t) {
+        const int c_raw = ec[t];
+        const int cc = c_raw < 0 ? r : c_raw;
+        const double a = c_raw < 0 ? 0.0 : ev[t] * d[cc];
+        const double* tc = tile + (cc - lo);
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (u < kc) acc[u] += a * tc[u * rows];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (u < kc) Zi[r + (i64)(c0 + u) * n] = dr * acc[u];
+  }
+}
+
 // ||S||_inf estimate per subdomain: max row sum of |abar| (1 + sigma d_r d_c)
 __global__ void k_row_norm(const i64* __restrict__ voff, int ell_w, const i32* __restrict__ ell_col,
                            const double* __restrict__ ell_val, const double* __restrict__ dv,
@@ -564,6 +622,18 @@ void launch_bapply_ell(hipStream_t s, i64 total_rows, const i32* row_sub, const 
   dim3 g((unsigned)((total_rows + MSDD_WG - 1) / MSDD_WG));
   hipLaunchKernelGGL(k_bapply_ell<double>, g, dim3(MSDD_WG), 0, s, total_rows, row_sub, voff, nb,
                      kvoff, K, dv, ell_w, ell_col, ell_val, Y, Z, active);
+}
+
+bool launch_bapply_tile(hipStream_t s, int P, int nmax, int bmax, const i64* voff, const i32* nb,
+                        const i32* bw, const i64* kvoff, int K, const double* dv, int ell_w,
+                        const i32* ell_col, const double* ell_val, const double* Y, double* Z,
+                        const int* active) {
+  const size_t lds = (size_t)16 * (256 + 2 * (size_t)bmax) * sizeof(double);
+  if (lds > 64 * 1024) return false;  // wider bands: the untiled kernel
+  if (P == 0 || nmax == 0 || K == 0) return true;
+  hipLaunchKernelGGL(k_bapply_tile, dim3(P, (nmax + 255) / 256), dim3(256), lds, s, voff, nb, bw,
+                     kvoff, K, dv, ell_w, ell_col, ell_val, Y, Z, active);
+  return true;
 }
 
 void launch_gram(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K, const double* Y,

@@ -56,6 +56,12 @@ void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax
 void launch_eig_init(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
                      const i32* nb, const i64* kvoff, int K, const double* dv, double* X,
                      unsigned long long seed, const i32* seed_id);
+// Z = b Y with the columns staged in LDS per 256-row tile (band halo included); false
+// (nothing launched) when the half-bandwidth makes the tile too large.
+bool launch_bapply_tile(hipStream_t s, int P, int nmax, int bmax, const i64* voff, const i32* nb,
+                        const i32* bw, const i64* kvoff, int K, const double* dv, int ell_w,
+                        const i32* ell_col, const double* ell_val, const double* Y, double* Z,
+                        const int* active);
 void launch_bapply_ell(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
                        const i32* nb, const i64* kvoff, int K, const double* dv, int ell_w,
                        const i32* ell_col, const double* ell_val, const double* Y, double* Z,

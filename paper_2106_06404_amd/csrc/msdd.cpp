@@ -838,6 +838,18 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   HIPCHK(hipStreamSynchronize(s));
 }
 
+// Z = b Y for the eigensolver's K columns per subdomain (skipped where status is not
+// running): LDS-tiled when the band allows it, else one thread per row from L2.
+void eig_bapply(msdd_ctx* c, hipStream_t s, const int64_t* kvoff, int K, const double* Y,
+                double* Z, const int* status) {
+  FineLevel& F = c->F;
+  if (launch_bapply_tile(s, F.P, F.nb_max, F.bw_max, F.gs.voff.p, F.gs.n.p, F.gs.bw.p, kvoff, K,
+                         F.dv.p, F.ell_w, F.ell_col.p, F.ell_val.p, Y, Z, status))
+    return;
+  launch_bapply_ell(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, kvoff, K, F.dv.p,
+                    F.ell_w, F.ell_col.p, F.ell_val.p, Y, Z, status);
+}
+
 // Band solves Y = S^{-1} W of the eigensolver (K columns per subdomain, skipped where
 // status is not running).  variant: 0 = by shape (blocked in four launches when the
 // blocked factor exists), 1..7 = rolling-window / per-column shapes, 8 = blocked in
@@ -942,8 +954,7 @@ void fine_eigensolve(msdd_ctx* c) {
       launch_eig_init(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K,
                       F.dv.p, E.X.p, 0x5eed5eedull + (unsigned long long)K, F.seed_id.p);
     }
-    launch_bapply_ell(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K,
-                      F.dv.p, F.ell_w, F.ell_col.p, F.ell_val.p, E.X.p, BX.p, status.p);
+    eig_bapply(c, s, dkvoff.p, K, E.X.p, BX.p, status.p);
     const int maxit = o.eig_maxit;
     std::vector<int> st;
     c->eig_active = nwant;
@@ -957,8 +968,7 @@ void fine_eigensolve(msdd_ctx* c) {
       {
         ProfScope ps(c, PR_EIG_BAPPLY, f * (F.s_nb * F.ell_w * 12.0 + 2.0 * F.s_nb * K * 8.0),
                      f * 2.0 * F.s_nb * F.ell_w * K);
-        launch_bapply_ell(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K,
-                          F.dv.p, F.ell_w, F.ell_col.p, F.ell_val.p, Y.p, Z.p, status.p);
+        eig_bapply(c, s, dkvoff.p, K, Y.p, Z.p, status.p);
       }
       {
         ProfScope ps(c, PR_EIG_GRAM, f * 3.0 * F.s_nb * K * 8.0, f * 4.0 * F.s_nb * K * K);
