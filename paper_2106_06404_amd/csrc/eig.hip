@@ -366,9 +366,11 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
   }
   __syncthreads();
   // M = Q diag(ev) Q^T, eigenvectors transposed into S (S[a*K + q] = Q(q, a))
-  if (K == 16 && nt == 64)
-    wave_jacobi16(M, S, ev, wsp);
-  else
+  if (K == 16 && nt >= 64) {
+    // the 16 x 16 Jacobi runs in wavefront 0 (it synchronises within the wavefront only)
+    if (tid < 64) wave_jacobi16(M, S, ev, wsp);
+    __syncthreads();
+  } else
     wg_jacobi<double>(K, M, S, ev);
   if (tid == 0) {  // sort descending (insertion sort, K <= 64)
     for (int a = 0; a < K; ++a) ord[a] = a;
@@ -651,8 +653,8 @@ void launch_rayleigh_ritz(hipStream_t s, int P, int K, const double* GS, const d
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  // one wave per subdomain for K = 16 (the Jacobi rounds update K^2/4 blocks), four above
-  const int nt = K <= 16 ? 64 : 256;
+  // four wavefronts per subdomain (for K = 16 the Jacobi itself runs in one of them)
+  const int nt = 256;
   hipLaunchKernelGGL(k_rayleigh_ritz, dim3(P), dim3(nt), lds, s, K, GS, GB, C, nu, active, nsplit);
 }
 

@@ -245,8 +245,10 @@ __device__ __forceinline__ int wg_jacobi(int n, R* A, R* Zt, R* d) {
 // squares) and output as wg_jacobi, with the round's pairs computed from constants, the
 // rotation from refined hardware reciprocals and reciprocal square roots (two Newton
 // steps each), the convergence vote taken with a wavefront ballot, and the 64 2x2 block updates and
-// 128 eigenvector-row updates of a round spread one and two per lane.
-//   A, Zt: 16 x 16 (LDS), as for wg_jacobi; prm: 16 doubles of LDS.  blockDim.x == 64.
+// 128 eigenvector-row updates of a round spread one and two per lane.  It synchronises
+// within its wavefront only (wave_lds_sync), so it is called by exactly one wavefront
+// (lanes threadIdx.x & 63) while the workgroup's other wavefronts wait at a barrier.
+//   A, Zt: 16 x 16 (LDS), as for wg_jacobi; prm: 16 doubles of LDS.
 __device__ __forceinline__ double rcp_refined(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
@@ -254,6 +256,11 @@ __device__ __forceinline__ double rcp_refined(double x) {
   e = fma(-x, r, 1.0);
   return fma(r, e, r);
 }
+// LDS hand-off inside one wavefront: its LDS operations complete in order, so waiting
+// for its own outstanding ones (and keeping the compiler from moving memory operations
+// across) makes every lane's earlier writes visible to every lane's later reads; the
+// other wavefronts of the workgroup are not involved.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ double rsqrt_refined(double x) {
   double r = __builtin_amdgcn_rsq(x);
   // r <- r (3 - x r^2) / 2, twice
@@ -265,7 +272,7 @@ __device__ __forceinline__ int wave_jacobi16(double* A, double* Zt, double* d, d
   const int lane = threadIdx.x & 63;
   const double tol2 = 1e-32;  // the skip test of wg_jacobi, |a_pq| > 1e-16 sqrt(|a_pp a_qq|), squared
   for (int t = lane; t < n * n; t += 64) Zt[t] = ((t >> 4) == (t & 15)) ? 1.0 : 0.0;
-  __syncthreads();
+  wave_lds_sync();
   // round r pairs k: k = 0 -> (15, r); else ((r + k) mod 15, (r - k) mod 15)
   auto pair = [](int r, int k, int& p, int& q) {
     if (k == 0) {
@@ -308,7 +315,7 @@ __device__ __forceinline__ int wave_jacobi16(double* A, double* Zt, double* d, d
         prm[2 * lane] = c;
         prm[2 * lane + 1] = s;
       }
-      __syncthreads();
+      wave_lds_sync();
       {
         const int k1 = lane >> 3, k2 = lane & 7;
         int p1, q1, p2, q2;
@@ -341,11 +348,11 @@ __device__ __forceinline__ int wave_jacobi16(double* A, double* Zt, double* d, d
           }
         }
       }
-      __syncthreads();
+      wave_lds_sync();
     }
   }
   for (int t = lane; t < n; t += 64) d[t] = A[t * (n + 1)];
-  __syncthreads();
+  wave_lds_sync();
   return sweeps < 40 ? sweeps : -1;
 }
 
