@@ -480,12 +480,12 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
   }
 }
 
-// Convergence decision of each running subdomain (one wavefront): sums the row-split
-// partials of k_eig_update, then the backward errors, Ritz values, count m and status.
 // backward error at which the pair that certifies the count is accepted (its relative
 // eigenvalue error then stays near 1e-11)
 constexpr double CERT_TOL = 1e-11;
 
+// Convergence decision of each running subdomain (one wavefront): sums the row-split
+// partials of k_eig_update, then the backward errors, Ritz values, count m and status.
 __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* __restrict__ part,
                             int S, double sigma, double eta, int nev_max, double tol, int maxit,
                             int* __restrict__ status, int* __restrict__ iters,
