@@ -52,29 +52,32 @@ class PinnedArena {
     (void)hipGetDevice(&dev);
     return arenas[dev >= 0 && dev < kMaxDev ? dev : 0];
   }
+  // uninitialised pinned space for bytes (valid until the next reset), or nullptr
+  void* alloc(size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu_);
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    while (cur_ < chunks_.size() && off_ + need > chunks_[cur_].second) {
+      ++cur_;
+      off_ = 0;
+    }
+    if (cur_ == chunks_.size()) {
+      const size_t sz = need > kChunk ? need : kChunk;
+      void* p = nullptr;
+      if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      chunks_.push_back({static_cast<char*>(p), sz});
+      off_ = 0;
+    }
+    char* dst = chunks_[cur_].first + off_;
+    off_ += need;
+    return dst;
+  }
   // a pinned copy of [src, src + bytes), or nullptr (then the caller copies directly)
   void* stage(const void* src, size_t bytes) {
-    char* dst = nullptr;
-    {
-      std::lock_guard<std::mutex> lk(mu_);
-      const size_t need = (bytes + 255) & ~(size_t)255;
-      while (cur_ < chunks_.size() && off_ + need > chunks_[cur_].second) {
-        ++cur_;
-        off_ = 0;
-      }
-      if (cur_ == chunks_.size()) {
-        const size_t sz = need > kChunk ? need : kChunk;
-        void* p = nullptr;
-        if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) {
-          (void)hipGetLastError();
-          return nullptr;
-        }
-        chunks_.push_back({static_cast<char*>(p), sz});
-        off_ = 0;
-      }
-      dst = chunks_[cur_].first + off_;
-      off_ += need;
-    }
+    char* dst = static_cast<char*>(alloc(bytes));
+    if (!dst) return nullptr;
     // large arrays are copied by several threads (a single thread moves only a few GB/s)
     constexpr size_t kPar = (size_t)4 << 20;
     if (bytes >= kPar) {
@@ -238,6 +241,12 @@ struct DVec {
     const void* src = bytes >= ((size_t)64 << 10) ? PinnedArena::get().stage(v.data(), bytes) : nullptr;
     HIPCHK(hipMemcpyAsync(p, src ? src : v.data(), bytes, hipMemcpyHostToDevice, s));
   }
+  // upload from host memory that stays valid until the copy has run (pinned staging
+  // space, or pageable memory, which the runtime copies before returning)
+  void upload_raw(const T* src, size_t cnt, hipStream_t s) {
+    alloc(cnt);
+    if (n) HIPCHK(hipMemcpyAsync(p, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+  }
   std::vector<T> download(hipStream_t s, size_t cnt = (size_t)-1) const {
     if (cnt == (size_t)-1) cnt = n;
     std::vector<T> v(cnt);
@@ -282,5 +291,24 @@ void to_device(DVec<T>& dst, const T* src, size_t cnt, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(dst.p, src, cnt * sizeof(T),
                         is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
 }
+
+// Host array built only to be uploaded: placed in the pinned staging arena (no zeroing,
+// no first-touch page faults, asynchronous upload), or in an owned vector when pinned
+// memory is not available.  Contents start uninitialised.
+template <class T>
+struct HostBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  std::vector<T> fallback;
+  explicit HostBuf(size_t cnt) : n(cnt) {
+    p = cnt ? static_cast<T*>(PinnedArena::get().alloc(cnt * sizeof(T))) : nullptr;
+    if (!p && cnt) {
+      fallback.resize(cnt);
+      p = fallback.data();
+    }
+  }
+  T& operator[](size_t i) { return p[i]; }
+  T* begin() { return p; }
+};
 
 }  // namespace msdd_host

@@ -150,12 +150,14 @@ void build_groupset(const std::vector<GroupPlan>& G, const std::vector<std::vect
     out.h_bw[i] = G[i].bw;
   }
   out.total_rows = out.h_voff.back();
-  std::vector<int32_t> row_grp(out.total_rows), slot_elem(soff.back()), slot_loc(soff.back() * k);
-  std::vector<int64_t> inc_ptr(out.total_rows + 1, 0);
+  // every entry of these arrays is written below (they live only until uploaded)
+  HostBuf<int32_t> row_grp(out.total_rows), slot_elem(soff.back()), slot_loc(soff.back() * k);
+  HostBuf<int64_t> inc_ptr(out.total_rows + 1);
+  inc_ptr[0] = 0;
   // incidence offsets per group, then every group fills its own ranges (in parallel)
   std::vector<int64_t> qoff(G.size() + 1, 0);
   for (size_t i = 0; i < G.size(); ++i) qoff[i + 1] = qoff[i] + (int64_t)G[i].inc_t.size();
-  std::vector<int32_t> inc_slot(qoff.back()), inc_a(qoff.back());
+  HostBuf<int32_t> inc_slot(qoff.back()), inc_a(qoff.back());
   const int ng = (int)G.size();
   parallel_for(ng, host_threads(ng), [&](int i, int) {
     const auto& g = G[i];
@@ -173,12 +175,12 @@ void build_groupset(const std::vector<GroupPlan>& G, const std::vector<std::vect
     for (size_t t = 0; t < elems[i].size(); ++t) slot_elem[soff[i] + t] = elems[i][t];
     std::copy(g.eloc.begin(), g.eloc.end(), slot_loc.begin() + soff[i] * k);
   });
-  out.row_grp.upload(row_grp, s);
-  out.slot_elem.upload(slot_elem, s);
-  out.slot_loc.upload(slot_loc, s);
-  out.inc_slot.upload(inc_slot, s);
-  out.inc_a.upload(inc_a, s);
-  out.inc_ptr.upload(inc_ptr, s);
+  out.row_grp.upload_raw(row_grp.p, row_grp.n, s);
+  out.slot_elem.upload_raw(slot_elem.p, slot_elem.n, s);
+  out.slot_loc.upload_raw(slot_loc.p, slot_loc.n, s);
+  out.inc_slot.upload_raw(inc_slot.p, inc_slot.n, s);
+  out.inc_a.upload_raw(inc_a.p, inc_a.n, s);
+  out.inc_ptr.upload_raw(inc_ptr.p, inc_ptr.n, s);
   out.voff.upload(out.h_voff, s);
   out.n.upload(out.h_n, s);
   out.bw.upload(out.h_bw, s);
@@ -674,17 +676,21 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   F.h_boff.assign(P + 1, 0);
   for (int i = 0; i < P; ++i)
     F.h_boff[i + 1] = F.h_boff[i] + (int64_t)F.plans[i].dofs.size() * (F.plans[i].bw + 1);
-  std::vector<int32_t> ell((size_t)F.gs.total_rows * F.ell_w, -1);
+  // ELL columns, rows padded with -1 (every entry written here; uploaded from the
+  // pinned staging space)
+  HostBuf<int32_t> ell((size_t)F.gs.total_rows * F.ell_w);
   parallel_for(P, nthr, [&](int i, int) {
     const SubPlan& S = sp[i];
     const int nb = (int)S.ell_ptr.size() - 1;
     for (int r = 0; r < nb; ++r) {
       const int64_t gr = F.gs.h_voff[i] + r;
-      std::copy(S.ell_col.begin() + S.ell_ptr[r], S.ell_col.begin() + S.ell_ptr[r + 1],
-                ell.begin() + gr * F.ell_w);
+      int32_t* row = ell.begin() + gr * F.ell_w;
+      const int len = S.ell_ptr[r + 1] - S.ell_ptr[r];
+      std::copy(S.ell_col.begin() + S.ell_ptr[r], S.ell_col.begin() + S.ell_ptr[r + 1], row);
+      std::fill(row + len, row + F.ell_w, -1);
     }
   });
-  F.ell_col.upload(ell, s);
+  F.ell_col.upload_raw(ell.p, ell.n, s);
   F.boff.upload(F.h_boff, s);
   std::vector<int32_t> drow_sub(F.h_doff.back());
   for (int i = 0; i < P; ++i)
