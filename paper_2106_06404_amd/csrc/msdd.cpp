@@ -416,6 +416,10 @@ struct msdd_ctx {
     bool have_targets = false;
   } warm;
   std::vector<int32_t> eig_iters;  // per finest-level subdomain, last setup
+  // host scratch of the planning, kept between setups (no fresh pages each time)
+  std::vector<double> scr_pou;
+  std::vector<int32_t> scr_cnt;
+  std::vector<int64_t> scr_pos;
   msdd_tuning_t tune{};            // launch-shape choices (0 = by shape)
   ~msdd_ctx() {
     if (h_segI) (void)hipHostFree(h_segI);
@@ -621,8 +625,10 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   F.h_dpos.clear();
   F.h_dglob.clear();
   F.ell_w = 0;
-  std::vector<double> pou_sum(n, 0.0);
-  std::vector<int32_t> dcount(n, 0);
+  std::vector<double>& pou_sum = c->scr_pou;
+  std::vector<int32_t>& dcount = c->scr_cnt;
+  pou_sum.assign(n, 0.0);
+  dcount.assign(n, 0);
   for (int i = 0; i < P; ++i) {
     const GroupPlan& g = F.plans[i];
     const SubPlan& S = sp[i];
@@ -655,11 +661,14 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
     REQUIRE(dcount[d] > 0, "dof " + std::to_string(d) + " lies in no subdomain's Dirichlet space");
   }
   // fine dof -> (subdomain, Dirichlet position), in subdomain order
-  std::vector<int64_t> dptr(n + 1, 0);
+  // (upload-only arrays in the pinned staging arena; every entry is written)
+  HostBuf<int64_t> dptr(n + 1);
+  dptr[0] = 0;
   for (int64_t d = 0; d < n; ++d) dptr[d + 1] = dptr[d] + dcount[d];
-  std::vector<int32_t> dsub(dptr[n]), dq(dptr[n]);
+  HostBuf<int32_t> dsub(dptr[n]), dq(dptr[n]);
   {
-    std::vector<int64_t> pos(dptr.begin(), dptr.end() - 1);
+    std::vector<int64_t>& pos = c->scr_pos;
+    pos.assign(dptr.p, dptr.p + n);
     for (int i = 0; i < P; ++i)
       for (int q = 0; q < sp[i].nD; ++q) {
         const int32_t d = sp[i].dglob[q];
@@ -703,9 +712,9 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   F.dpos.upload(F.h_dpos, s);
   F.dglob.upload(F.h_dglob, s);
   F.rankb.upload(F.h_rankb, s);
-  F.dinc_ptr.upload(dptr, s);
-  F.dinc_sub.upload(dsub, s);
-  F.dinc_q.upload(dq, s);
+  F.dinc_ptr.upload_raw(dptr.p, dptr.n, s);
+  F.dinc_sub.upload_raw(dsub.p, dsub.n, s);
+  F.dinc_q.upload_raw(dq.p, dq.n, s);
   vlog(c, "plan: uploads (queued)", &tv);
 }
 
