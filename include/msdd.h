@@ -17,7 +17,7 @@
  *   - Sec. 2.3: local Neumann spaces, the partition of unity chi_{l,i}, the
  *     GEVP abar_{l,i}(w,v) = lambda b_{l,i}(w,v), the coarse space
  *     V_{h,l-1} = span{ e chi w : lambda < eta } and the Dirichlet subspaces.
- *   - Sec. 3.5: abar_{l,i} = sum over the subdomain's elements of a_tau;
+ *   - Sec. 3.4: abar_{l,i} = sum over the subdomain's elements of a_tau;
  *     b_{l,i}(u,v) = abar_{l,i}(chi u, chi v).
  *   - Sec. 4.1/4.2: coarse levels work from patch matrices and a generating
  *     system whose pencil has a common kernel.
@@ -102,6 +102,11 @@ typedef struct {
                              subdomains and all their passes */
   int32_t warm_started;   /* finest-level subdomains started from the network's block */
   int32_t warm_fallbacks; /* of those, re-solved from the random start (not converged) */
+  int32_t eig_unconverged; /* finest-level subdomains whose eigensolver stopped without
+                              certifying its count (the setup then fails with MSDD_EEIG) */
+  int32_t eig_stagnated;  /* finest-level pairs (selected or certifying) accepted at the
+                             rounding floor: Ritz value fixed to 1e-14 between iterations and
+                             backward error within 1e6 * eig_tol, but above eig_tol */
 } msdd_stats_t;
 
 /* Fill *opt with defaults. */
@@ -117,7 +122,7 @@ int msdd_create(msdd_ctx** out, const msdd_options* opt);
  *      A on the free dofs, CSR, symmetric positive definite.
  *  n_elem, k, elem_dofs[n_elem*k] (int32, -1 = eliminated),
  *  elem_mat[n_elem*k*k] (double, row-major per element):
- *      the element matrices a_tau (Sec. 3.5); sum_tau a_tau must equal A.
+ *      the element matrices a_tau (Sec. 3.4); sum_tau a_tau must equal A.
  *  n_sub, sub_elem_ptr[n_sub+1] (int64), sub_elem[] (int32):
  *      the finest-level element sets T_{h,L,i} (overlap included).
  *  sub_dof_ptr[n_sub+1] (int64), sub_dof[] (int32), sub_pou[] (double):

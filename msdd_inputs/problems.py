@@ -13,7 +13,7 @@ eigenproblems, no coarse spaces, no Krylov solver).  Both the CPU oracle
 and the GPU library consume exactly these arrays.
 
 Paper sections followed:
-  * Sec. 3.3 (continuous Galerkin): a_tau(u,v) = int_tau (K grad u).grad v,
+  * Sec. 3.4 (continuous Galerkin): a_tau(u,v) = int_tau (K grad u).grad v,
     l(v) = int f v; element-wise stiffness matrices.
   * Sec. 2.2 (hierarchical domain decomposition): finest level = element
     partition plus delta layers of overlap; coarser levels group subdomain

@@ -4,7 +4,7 @@
  *
  *  - oracle_cholesky: textbook Cholesky-Crout, A = L L^T (row-major, in place).
  *    Used for the shifted pencil (a + b) that the spectral transformation of
- *    the GEVP lemma (Sec. 3.4) makes SPD, for the subdomain Dirichlet matrices
+ *    the GEVP lemma (Sec. 3.3) makes SPD, for the subdomain Dirichlet matrices
  *    A_i = R_i A R_i^T of the additive Schwarz preconditioner (Sec. 2.1), and
  *    for the coarsest-level matrix A_0.
  *  - oracle_jacobi: cyclic two-sided Jacobi rotations for a dense symmetric

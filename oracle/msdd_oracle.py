@@ -16,10 +16,10 @@ dense matrices and no blocking or fusion:
   * Sec. 2.3  local Neumann spaces, partition of unity, the recursive
               spectral coarse space (GEVP "theGEVP", selection lambda < eta,
               phi = e chi w) and the Dirichlet subspaces V_{h,l,i}.
-  * Sec. 3.4  GEVP lemma: with b(.,.) positive semi-definite and
+  * Sec. 3.3  GEVP lemma: with b(.,.) positive semi-definite and
               ker a cap ker b = {0}, b(p,v) = mu (a+b)(p,v), mu = 1/(1+lambda);
               eigenvectors b-orthonormal.
-  * Sec. 3.5  CG bilinear forms: abar_{l,i} = sum over the subdomain's
+  * Sec. 3.4  CG bilinear forms: abar_{l,i} = sum over the subdomain's
               elements of a_tau; right-hand side b^1(u,v) = abar(chi u, chi v).
   * Sec. 4.2  coarse-level GEVPs on a generating system have
               ker A cap ker B != {0}; we use compression: eigenvectors of
@@ -76,7 +76,7 @@ def dirichlet_mask(elem_dofs: np.ndarray, elems: np.ndarray, dofs: np.ndarray) -
 
 def neumann_matrix(elem_dofs: np.ndarray, elem_mat: np.ndarray, elems: np.ndarray,
                    dofs: np.ndarray) -> np.ndarray:
-    """abar_i = sum_{tau in T_i} a_tau on the local Neumann space (Sec. 3.5), dense."""
+    """abar_i = sum_{tau in T_i} a_tau on the local Neumann space (Sec. 3.4), dense."""
     n = int(elem_dofs.max()) + 1
     loc = -np.ones(n, np.int64)
     loc[dofs] = np.arange(len(dofs))
@@ -107,7 +107,7 @@ def elements_matrix(n: int, elem_dofs: np.ndarray, elem_mat: np.ndarray,
 
 
 # ----------------------------------------------------------------------------
-# Sec. 3.4: the GEVP through the spectral transformation mu = 1/(1+lambda)
+# Sec. 3.3: the GEVP through the spectral transformation mu = 1/(1+lambda)
 # ----------------------------------------------------------------------------
 
 @dataclasses.dataclass

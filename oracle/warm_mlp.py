@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: imported by tests/ (and nothing else); it shares no
 code with the GPU library.
 
 The paper solves the local generalized eigenproblems of Sec. 2.3 (the GEVP
-abar w = lambda b w, b = b^1 of Sec. 3.5) from scratch in every subdomain.
+abar w = lambda b w, b = b^1 of Sec. 3.4) from scratch in every subdomain.
 This module is the reference of an extension: a multilayer perceptron that maps
 a subdomain's coefficient features to a start block for that eigensolver.  The
 network and its training objective are not in the paper; they are defined here

@@ -48,7 +48,8 @@ class MsddStats(ctypes.Structure):
                 ("t_coarse_ms", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("pcg_iters", ctypes.c_int32),
                 ("pcg_relres", ctypes.c_double), ("eig_iters_sum", ctypes.c_int64),
-                ("warm_started", ctypes.c_int32), ("warm_fallbacks", ctypes.c_int32)]
+                ("warm_started", ctypes.c_int32), ("warm_fallbacks", ctypes.c_int32),
+                ("eig_unconverged", ctypes.c_int32), ("eig_stagnated", ctypes.c_int32)]
 
     def as_dict(self):
         L = self.n_levels

@@ -6,9 +6,9 @@
 // Padding entries (j+d >= n, or j-d < 0) are zero.
 //
 // Paper: the local Neumann matrix abar_{l,i} is the sum of the element
-// matrices a_tau over the subdomain's elements (Sec. 3.5); the Dirichlet
+// matrices a_tau over the subdomain's elements (Sec. 3.4); the Dirichlet
 // matrix is A_i = R_i A R_i^T (Sec. 2.1); the shifted pencil matrix
-// abar + sigma*b, b = D abar D (Sec. 3.4 lemma, b^1 of Sec. 3.5) is SPD.
+// abar + sigma*b, b = D abar D (Sec. 3.3 lemma, b^1 of Sec. 3.4) is SPD.
 #include "common.h"
 #include <algorithm>
 #include "kernels.h"

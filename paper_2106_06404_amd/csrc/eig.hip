@@ -1,8 +1,8 @@
 // Finest-level local generalized eigenproblems (Sec. 2.3 "theGEVP", b^1 of
-// Sec. 3.5), batched over subdomains.
+// Sec. 3.4), batched over subdomains.
 //
 // abar x = lambda b x,  b = D abar D  (D = partition-of-unity weights).
-// The lemma of Sec. 3.4 (ker abar cap ker b = {0}) makes S = abar + sigma*b SPD
+// The lemma of Sec. 3.3 (ker abar cap ker b = {0}) makes S = abar + sigma*b SPD
 // for every sigma > 0, and the wanted smallest lambda are the largest
 //   nu = 1/(lambda + sigma)  of  b x = nu S x.
 // Block subspace iteration with the exact factor of S (shift-invert) and a
@@ -483,6 +483,10 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
 // backward error at which the pair that certifies the count is accepted (its relative
 // eigenvalue error then stays near 1e-11)
 constexpr double CERT_TOL = 1e-11;
+// A pair whose Ritz value no longer moves (1e-14 relative between iterations) is at the
+// rounding floor of its pencil; it is accepted if its backward error is within 1e6 times
+// the tolerance (1e-8 at the default 1e-14).  The host counts such pairs.
+constexpr double STAG_FACTOR = 1e6;
 
 // Convergence decision of each running subdomain (one wavefront): sums the row-split
 // partials of k_eig_update, then the backward errors, Ritz values, count m and status.
@@ -513,7 +517,7 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
     nu_prev[(i64)i * K + tid] = nv;
     sh_res[tid] = rel;
     sh_lam[tid] = lv;
-    sh_stag[tid] = (rel <= 1e-8 && fabs(nv - np) <= 1e-14 * fabs(nv)) ? 1.0 : 0.0;
+    sh_stag[tid] = (rel <= fmax(STAG_FACTOR * tol, CERT_TOL) && fabs(nv - np) <= 1e-14 * fabs(nv)) ? 1.0 : 0.0;
   }
   __syncthreads();
   if (tid == 0) {

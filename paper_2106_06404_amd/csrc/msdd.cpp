@@ -386,7 +386,7 @@ struct msdd_ctx {
   DVec<int32_t> ch_seg;
   DVec<double> segD, hist_d;  // per-segment CG scalars; residual history
   DVec<int> segI;
-  int hist_cap = 0;
+  size_t hist_cap = 0;        // entries allocated in hist_d
   int* h_segI = nullptr;      // pinned
   std::vector<int> last_iters;
   std::vector<double> last_relres;
@@ -899,6 +899,7 @@ void fine_eigensolve(msdd_ctx* c) {
   std::vector<int> final_m(P, 0);
   std::vector<std::unique_ptr<EigPass>> passes;
   int restarts = 0, max_it = 0;
+  int unconverged = 0, stagnated = 0, first_unconv = -1;
   double res_max = 0.0;
   F.lam.assign(P, {});
   // learned warm start: the network's block for every subdomain (BF16 inference)
@@ -1034,9 +1035,18 @@ void fine_eigensolve(msdd_ctx* c) {
         continue;
       }
       if (st[i] == ST_RUNNING || st[i] == ST_NOCONV || st[i] == ST_GROW) {
-        // iteration limit: accept the current Ritz pairs and report the residual
-        if (c->opt.verbose)
-          std::fprintf(stderr, "msdd: subdomain %d eigensolver stopped at maxit (status %d)\n", i, st[i]);
+        // iteration limit (or a block that cannot grow past 64 columns): the count m is
+        // not certified, so the coarse space may miss eigenvectors below eta
+        ++unconverged;
+        if (first_unconv < 0) first_unconv = i;
+      } else {
+        // selected pairs (and the certifying one) accepted at the rounding floor rather
+        // than at the tolerance
+        for (int a = 0; a < std::min(K, mc[i] + 1); ++a) {
+          const double la = lamv[(size_t)i * K + a];
+          const double ta = (a == mc[i] && la >= c->eta) ? std::max(o.eig_tol, 1e-11) : o.eig_tol;
+          if (resv[(size_t)i * K + a] > ta) ++stagnated;
+        }
       }
       want[i] = 0;
       final_pass[i] = (int)passes.size();
@@ -1050,6 +1060,10 @@ void fine_eigensolve(msdd_ctx* c) {
     if (!grew && !fell) break;
     if (grew) K *= 2;
   }
+  if (unconverged > 0)
+    throw MsddError{MSDD_EEIG, "local eigensolver: " + std::to_string(unconverged) +
+                                   " finest-level subdomain(s) not converged within eig_maxit "
+                                   "(first: subdomain " + std::to_string(first_unconv) + ")"};
   // pooled basis blocks
   F.m = final_m;
   F.s_ndm = 0;
@@ -1114,6 +1128,8 @@ void fine_eigensolve(msdd_ctx* c) {
   c->stats.eig_iters_max = max_it;
   c->stats.eig_restarts = restarts;
   c->stats.eig_resid_max = res_max;
+  c->stats.eig_unconverged = unconverged;
+  c->stats.eig_stagnated = stagnated;
 }
 
 // ---------------------------------------------------------------------------
@@ -1696,6 +1712,8 @@ void alloc_solve_work(msdd_ctx* c) {
   HIPCHK(hipHostMalloc((void**)&c->h_segI, (size_t)c->nseg * PCG_SI * sizeof(int), hipHostMallocDefault));
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   c->gexec = nullptr;
+  c->hist_d.release();
+  c->hist_cap = 0;
   HIPCHK(hipStreamSynchronize(s));
 }
 
@@ -2191,9 +2209,10 @@ int solve_all(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxi
   }
   double* xx = xdev ? x : c->x.p;
   if (!xdev) HIPCHK(hipMemcpyAsync(xx, x, n * sizeof(double), hipMemcpyHostToDevice, s));
-  if (c->hist_cap < maxit + 1) {
+  // the history holds (maxit + 1) entries per segment; a later setup may have more segments
+  if (c->hist_cap < (size_t)(maxit + 1) * ns) {
     c->hist_d.alloc((size_t)(maxit + 1) * ns);
-    c->hist_cap = maxit + 1;
+    c->hist_cap = (size_t)(maxit + 1) * ns;
     if (c->gexec) HIPCHK(hipGraphExecDestroy(c->gexec));
     c->gexec = nullptr;
   }

@@ -82,3 +82,42 @@ def test_batch_rules_are_checked():
     assert e.value.code == B.MSDD_EINVAL
     m.setup_batch(**arrs)   # the context is still usable
     m.close()
+
+
+def test_context_reused_from_single_to_batch():
+    """One context: a single-problem setup and solve, then a batch of three on the same
+    context with the same and then a smaller iteration limit.  The residual history is
+    kept per problem, so the batch needs a larger history buffer than the single run;
+    results must equal a fresh batch context's bitwise."""
+    import torch
+    from paper_2106_06404_amd import binding as B
+    probs = _members(2)
+    arrs = B.batch_arrays(probs, device="cuda:0")
+    b = torch.from_numpy(np.concatenate([p.b for p in probs])).cuda()
+
+    fresh = B.Msdd()
+    fresh.setup_batch(**arrs)
+    x_ref = torch.zeros_like(b)
+    its_ref, _, _ = fresh.solve_batch(b, x_ref, 1e-8, 200)
+    h_ref = fresh.history()
+    torch.cuda.synchronize()
+    fresh.close()
+
+    m = B.Msdd()
+    m.setup(**B.problem_arrays(probs[0], device="cuda:0"))
+    b0 = torch.from_numpy(probs[0].b).cuda()
+    x0 = torch.zeros_like(b0)
+    it0, _, _ = m.solve(b0, x0, 1e-8, 200)
+    h0 = m.history()
+    assert len(h0) == it0 + 1
+    for maxit in (200, 100):
+        m.setup_batch(**arrs)
+        x = torch.zeros_like(b)
+        its, rels, _ = m.solve_batch(b, x, 1e-8, maxit)
+        torch.cuda.synchronize()
+        assert list(its) == list(its_ref)
+        assert np.array_equal(x.cpu().numpy(), x_ref.cpu().numpy())
+        h = m.history()
+        assert np.array_equal(h, h_ref)
+        assert np.array_equal(h, h0)   # problem 0 of the batch is the single problem
+    m.close()

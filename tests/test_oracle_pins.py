@@ -171,7 +171,7 @@ def test_pin7_brute_force_lapack(contrast, seed, tol):
             assert np.allclose(X.T @ Bm @ X, np.eye(g.m), atol=1e-10)
             G = X.T @ Ab @ X
             assert np.allclose(G - np.diag(np.diag(G)), 0.0, atol=1e-9 * max(1, abs(G).max()))
-        # Pi_m stability (Sec. 3.4 lemma): |Pi v|_a <= |v|_a, |v - Pi v|_a <= |v|_a,
+        # Pi_m stability (Sec. 3.3 lemma): |Pi v|_a <= |v|_a, |v - Pi v|_a <= |v|_a,
         # |v - Pi v|_b^2 <= |v - Pi v|_a^2 / lambda_{m+1}  for m >= dim ker a
         lam_next = g.lam[g.m] if g.m < len(g.lam) else np.inf
         for _ in range(5):
