@@ -71,8 +71,11 @@ typedef struct {
                          common kernel and removed (default 1e-12) */
   int nev_max;        /* 0 = threshold selection only; > 0 caps eigenvectors per subdomain */
   double eig_tol;     /* tolerance on the normwise backward error
-                         ||b x - nu S x|| / (nu ||S|| ||x||) of the local eigenpairs
-                         (default 1e-14) */
+                         ||b x - nu S x|| / (nu ||S|| ||x||) of the selected local
+                         eigenpairs (default 1e-14).  The next pair, which only certifies
+                         the count (lambda_{m+1} >= eta), is accepted at max(eig_tol, 1e-11),
+                         or once its Krylov-Weinstein interval in the S inner product lies
+                         entirely above eta */
   int eig_maxit;      /* iterations of the local eigensolver (default 200) */
   int block;          /* initial block size of the local eigensolver (default 16) */
   int device;         /* HIP device ordinal */
@@ -89,7 +92,7 @@ typedef struct {
   int32_t max_band;       /* largest half-bandwidth of a finest-level local matrix */
   int32_t eig_iters_max;  /* largest local eigensolver iteration count */
   int32_t eig_restarts;   /* subdomains re-run with a larger block */
-  double eig_resid_max;   /* largest normwise backward error of a certified pair (FP64) */
+  double eig_resid_max;   /* largest normwise backward error of a selected finest-level pair */
   double t_plan_ms;       /* host planning (index analysis) */
   double t_local_ms;      /* local matrix extraction + shifted Cholesky + Dirichlet Cholesky */
   double t_gevp_ms;       /* finest-level GEVPs (eigensolver) */
@@ -104,9 +107,9 @@ typedef struct {
   int32_t warm_fallbacks; /* of those, re-solved from the random start (not converged) */
   int32_t eig_unconverged; /* finest-level subdomains whose eigensolver stopped without
                               certifying its count (the setup then fails with MSDD_EEIG) */
-  int32_t eig_stagnated;  /* finest-level pairs (selected or certifying) accepted at the
-                             rounding floor: Ritz value fixed to 1e-14 between iterations and
-                             backward error within 1e6 * eig_tol, but above eig_tol */
+  int32_t eig_stagnated;  /* selected finest-level pairs accepted at the rounding floor:
+                             Ritz value fixed to 1e-14 between iterations and backward error
+                             within 1e6 * eig_tol, but above eig_tol */
 } msdd_stats_t;
 
 /* Fill *opt with defaults. */

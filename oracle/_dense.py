@@ -14,16 +14,21 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dense.c")
 _OUT = os.path.join(_HERE, "_build", "liboracle_dense.so")
+_RSRC = os.path.join(_HERE, "refine.c")
+_ROUT = os.path.join(_HERE, "_build", "liboracle_refine.so")
 _lib = None
+_rlib = None
 
 
 def build(force: bool = True) -> str:
     os.makedirs(os.path.dirname(_OUT), exist_ok=True)
-    if force or not os.path.exists(_OUT):
-        tmp = _OUT + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall", _SRC,
-                               "-o", tmp, "-lm"])
-        os.replace(tmp, _OUT)
+    for src, out, extra in ((_SRC, _OUT, ["-fopenmp", "-lm"]), (_RSRC, _ROUT, ["-lquadmath", "-lm"])):
+        if force or not os.path.exists(out):
+            tmp = out + f".tmp{os.getpid()}"
+            cmd = ["gcc", "-O2", "-shared", "-fPIC", "-Wall", src, "-o", tmp]
+            subprocess.check_call(cmd[:2] + [e for e in extra if e.startswith("-f")] + cmd[2:]
+                                  + [e for e in extra if e.startswith("-l")])
+            os.replace(tmp, out)
     return _OUT
 
 
@@ -77,3 +82,65 @@ def jacobi_eigh(A: np.ndarray, max_sweeps: int = 60, abs_floor: float = 1e-18,
         raise ArithmeticError("Jacobi did not converge")
     order = np.argsort(w, kind="stable")
     return w[order], v[:, order]
+
+
+def rlib():
+    global _rlib
+    if _rlib is None:
+        if not os.path.exists(_ROUT):
+            build(force=True)
+        L = ctypes.CDLL(_ROUT)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.oracle_refine.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp,
+                                    ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp, dp]
+        L.oracle_refine.restype = ctypes.c_int
+        L.oracle_rayleigh.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp,
+                                      ctypes.c_int, dp, dp]
+        L.oracle_rayleigh.restype = ctypes.c_int
+        _rlib = L
+    return _rlib
+
+
+def refine_pairs(eloc: np.ndarray, emat: np.ndarray, d: np.ndarray, X0: np.ndarray,
+                 iters: int = 3):
+    """Binary128 Rayleigh-Ritz + subspace iteration of abar x = lambda D abar D x
+    (oracle/refine.c).  eloc: (ne, k) local dof index or -1; emat: (ne, k, k);
+    d: weights; X0: (n, kv) start vectors.  Returns (lam_hi, lam_lo, bound, cond, X),
+    lambda ascending."""
+    n, kv = X0.shape
+    ne, kk = eloc.shape
+    el = np.ascontiguousarray(eloc, dtype=np.int32)
+    em = np.ascontiguousarray(emat, dtype=np.float64)
+    dd = np.ascontiguousarray(d, dtype=np.float64)
+    x0 = np.asfortranarray(X0, dtype=np.float64)
+    hi = np.zeros(kv)
+    lo = np.zeros(kv)
+    bd = np.zeros(kv)
+    cd = np.zeros(kv)
+    X = np.zeros((n, kv), order="F")
+    ip = ctypes.POINTER(ctypes.c_int)
+    rc = rlib().oracle_refine(n, ne, kk, el.ctypes.data_as(ip), _ptr(em), _ptr(dd), kv,
+                              x0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), iters,
+                              _ptr(hi), _ptr(lo), _ptr(bd), _ptr(cd),
+                              X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise ArithmeticError(f"oracle_refine failed ({rc})")
+    return hi, lo, bd, cd, np.array(X)
+
+
+def rayleigh_exact(eloc: np.ndarray, emat: np.ndarray, d: np.ndarray, X: np.ndarray):
+    """x^T abar x / x^T (D abar D) x in binary128 for each column of X (oracle/refine.c)."""
+    n, kv = X.shape
+    ne, kk = eloc.shape
+    el = np.ascontiguousarray(eloc, dtype=np.int32)
+    em = np.ascontiguousarray(emat, dtype=np.float64)
+    dd = np.ascontiguousarray(d, dtype=np.float64)
+    x = np.asfortranarray(X, dtype=np.float64)
+    lam = np.zeros(kv)
+    ip = ctypes.POINTER(ctypes.c_int)
+    rc = rlib().oracle_rayleigh(n, ne, kk, el.ctypes.data_as(ip), _ptr(em), _ptr(dd), kv,
+                                x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(lam))
+    if rc != 0:
+        raise ArithmeticError(f"oracle_rayleigh failed ({rc})")
+    return lam

@@ -43,12 +43,14 @@ pencil, dense direct solves, condition-number bounds).
 from __future__ import annotations
 
 import dataclasses
+import os
 from typing import Dict, List, Optional
 
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
+from . import _dense
 from ._dense import NotSPD, cholesky, jacobi_eigh
 
 COMPRESS_REL = 1e-12  # coarse generating-system compression threshold (relative to ||A+B||)
@@ -116,14 +118,17 @@ class GevpResult:
     mu: np.ndarray         # all eigenvalues mu = 1/(1+lambda), descending (incl. mu = 0)
     m: int                 # number selected (lambda < eta)
     X: np.ndarray          # selected eigenvectors, b-orthonormal (columns)
+    V: Optional[np.ndarray] = None   # the first m + extra_vec eigenvectors, S-orthonormal
 
 
-def gevp_definite(Ab: np.ndarray, Bm: np.ndarray, eta: float) -> GevpResult:
+def gevp_definite(Ab: np.ndarray, Bm: np.ndarray, eta: float, extra_vec: int = 0) -> GevpResult:
     """abar x = lambda b x with ker abar cap ker b = {0}: S = abar + b is SPD.
 
     S = L L^T; C = L^{-1} b L^{-T}; C = Y diag(mu) Y^T (Jacobi);
     lambda = 1/mu - 1 (mu = 0 <-> lambda = inf); x = L^{-T} y; select
     lambda < eta (strict); b-normalise (x^T S x = 1 so x^T b x = mu).
+    extra_vec > 0 also returns the eigenvectors of the m + extra_vec largest mu
+    (x^T S x = 1), e.g. as start vectors of the binary128 refinement.
     """
     S = Ab + Bm
     L = cholesky(S)
@@ -133,7 +138,49 @@ def gevp_definite(Ab: np.ndarray, Bm: np.ndarray, eta: float) -> GevpResult:
     mu, Y = jacobi_eigh(C)
     mu = mu[::-1]
     Y = Y[:, ::-1]
-    return _select(mu, lambda Yc: sla.solve_triangular(L.T, Yc, lower=False), Y, eta)
+    back = lambda Yc: sla.solve_triangular(L.T, Yc, lower=False)  # noqa: E731
+    g = _select(mu, back, Y, eta)
+    if extra_vec > 0:
+        g.V = back(Y[:, :min(g.m + extra_vec, Y.shape[1])])
+    return g
+
+
+def local_elements(elem_dofs: np.ndarray, elem_mat: np.ndarray, elems: np.ndarray,
+                   dofs: np.ndarray):
+    """The subdomain's element matrices with their dofs numbered in the local Neumann
+    space (-1: eliminated or outside), for the binary128 refinement."""
+    n = int(elem_dofs.max()) + 1
+    loc = -np.ones(n + 1, np.int64)
+    loc[dofs] = np.arange(len(dofs))
+    ed = elem_dofs[elems]
+    eloc = np.where(ed >= 0, loc[np.where(ed >= 0, ed, n)], -1)
+    return eloc.astype(np.int32), elem_mat[elems]
+
+
+@dataclasses.dataclass
+class RefinedPairs:
+    lam: np.ndarray      # eigenvalues of the exact-data pencil, rounded to FP64 (ascending)
+    lam_lo: np.ndarray   # binary128 value minus lam
+    bound: np.ndarray    # bound on |lam + lam_lo - lambda*| (Krylov-Weinstein, in binary128)
+    cond: np.ndarray     # first-order sensitivity to entrywise relative data perturbations
+    X: np.ndarray        # Ritz vectors, b-normalised (x^T b x = 1)
+
+    @property
+    def fp64_uncertainty(self) -> np.ndarray:
+        """u * cond, u = 2^-53: the change of lambda that relative perturbations of the
+        element data at FP64 unit roundoff can cause, to first order."""
+        return 2.0 ** -53 * self.cond
+
+
+def refine_pairs(elem_dofs, elem_mat, elems, dofs, d, V0, iters: int = 3) -> RefinedPairs:
+    """Eigenpairs of abar x = lambda (D abar D) x (Sec. 2.3 GEVP, b^1 of Sec. 3.4, through
+    the transformation of the Sec. 3.3 lemma) refined in binary128 from the start
+    vectors V0 (columns; e.g. the oracle's FP64 eigenvectors of the smallest lambda):
+    Rayleigh-Ritz on span(V0), then `iters` steps of subspace iteration with
+    (abar + b)^{-1} b, each followed by Rayleigh-Ritz (oracle/refine.c)."""
+    eloc, emat = local_elements(elem_dofs, elem_mat, elems, dofs)
+    hi, lo, bd, cd, X = _dense.refine_pairs(eloc, emat, d, V0, iters)
+    return RefinedPairs(hi, lo, bd, cd, X)
 
 
 def _select(mu, back, Y, eta):
@@ -190,13 +237,30 @@ class LevelData:
     gen_size: List[int]            # generating-system size (coarse levels)
     neumann: Optional[List[np.ndarray]] = None   # abar_{l,i} (kept for tests)
     owned: Optional[List[np.ndarray]] = None     # owned mask over the generating system
+    gen_cols: Optional[List[np.ndarray]] = None  # generating system: level-l function indices
+
+
+_POOL_ORACLE = None
+
+
+def _pool_init():
+    os.environ["ORACLE_THREADS"] = "1"
+
+
+def _pool_fine(i):
+    return _POOL_ORACLE._fine_one(i)
 
 
 class Oracle:
     """Setup and solve of the multilevel additive spectral Schwarz preconditioner."""
 
     def __init__(self, prob, eta: Optional[float] = None, verbose: bool = False,
-                 only_fine: Optional[List[int]] = None):
+                 only_fine: Optional[List[int]] = None, fine_vectors: int = 0,
+                 workers: int = 1):
+        """fine_vectors > 0 keeps, per finest-level subdomain, the S-orthonormal
+        eigenvectors of the m + fine_vectors smallest lambda (in fine_vecs);
+        workers > 1 solves the finest-level subdomains in that many processes (the
+        results do not depend on it)."""
         self.prob = prob
         self.eta = prob.eta if eta is None else eta
         self.L = prob.n_levels - 1
@@ -206,36 +270,69 @@ class Oracle:
         self.P: Dict[int, sp.csr_matrix] = {}    # level-l coefficients -> fine dofs
         self.Al: Dict[int, np.ndarray] = {}      # Galerkin matrices A_l (l < L), dense
         self.verbose = verbose
+        self.fine_vectors = fine_vectors
+        self.workers = workers
+        self.fine_vecs: Dict[int, np.ndarray] = {}
         self._setup(only_fine)
 
     # -- finest level (Sec. 2.3 step 2 with l = L) --
+    def _fine_one(self, i):
+        p = self.prob
+        dofs = p.sub_dofs(i)
+        d = p.sub_weights(i)
+        el = p.sub_elems(i)
+        dm = dirichlet_mask(p.elem_dofs, el, dofs)
+        Ab = neumann_matrix(p.elem_dofs, p.elem_mat, el, dofs)
+        Bm = d[:, None] * Ab * d[None, :]
+        g = gevp_definite(Ab, Bm, self.eta, extra_vec=self.fine_vectors)
+        Ad = self.A[dofs[dm]][:, dofs[dm]].toarray()   # A_i = R_i A R_i^T
+        return g, d[:, None] * g.X, cholesky(Ad)
+
     def _fine(self, only):
         p = self.prob
         lam, m, basis, rows, dirr, dchol = [], [], [], [], [], []
-        cols = []
+        todo = [i for i in range(p.n_sub) if only is None or i in only]
+        res = {}
+        if self.workers > 1 and len(todo) > 1:
+            import multiprocessing as mp
+            global _POOL_ORACLE
+            _POOL_ORACLE = self
+            with mp.get_context("fork").Pool(self.workers, initializer=_pool_init) as pool:
+                for i, out in zip(todo, pool.imap(_pool_fine, todo)):
+                    res[i] = out
+                    if self.verbose:
+                        print(f"  fine sub {i}: nbar={len(p.sub_dofs(i))} m={out[0].m}", flush=True)
+            _POOL_ORACLE = None
+        else:
+            for i in todo:
+                res[i] = self._fine_one(i)
+                if self.verbose:
+                    print(f"  fine sub {i}: nbar={len(p.sub_dofs(i))} m={res[i][0].m}", flush=True)
         for i in range(p.n_sub):
             dofs = p.sub_dofs(i)
-            d = p.sub_weights(i)
-            el = p.sub_elems(i)
-            dm = dirichlet_mask(p.elem_dofs, el, dofs)
-            if only is not None and i not in only:
-                lam.append(None); m.append(0); basis.append(np.zeros((len(dofs), 0)))
-                rows.append(dofs); dirr.append(dofs[dm]); dchol.append(None)
-                continue
-            Ab = neumann_matrix(p.elem_dofs, p.elem_mat, el, dofs)
-            Bm = d[:, None] * Ab * d[None, :]
-            g = gevp_definite(Ab, Bm, self.eta)
-            lam.append(g.lam)
-            m.append(g.m)
-            basis.append(d[:, None] * g.X)   # phi = e chi w
+            dm = dirichlet_mask(p.elem_dofs, p.sub_elems(i), dofs)
             rows.append(dofs)
             dirr.append(dofs[dm])
-            Ad = self.A[dofs[dm]][:, dofs[dm]].toarray()   # A_i = R_i A R_i^T
-            dchol.append(cholesky(Ad))
-            if self.verbose:
-                print(f"  fine sub {i}: nbar={len(dofs)} m={g.m}", flush=True)
+            if i not in res:
+                lam.append(None); m.append(0); basis.append(np.zeros((len(dofs), 0)))
+                dchol.append(None)
+                continue
+            g, phi, Lc = res[i]
+            lam.append(g.lam)
+            m.append(g.m)
+            basis.append(phi)   # phi = e chi w
+            dchol.append(Lc)
+            if g.V is not None:
+                self.fine_vecs[i] = g.V
         self.levels[self.L] = LevelData(self.L, p.n_sub, lam, np.array(m), basis, rows, dirr,
                                         dchol, [len(r) for r in rows])
+
+    @staticmethod
+    def _generating_subdomains(emask_l, emask, par, i):
+        """Generating system of coarse subdomain i (Sec. 4.2): the basis functions of every
+        next-finer subdomain j that has elements in T_{h,l,i} (owned: par[j] == i; the others
+        are its ghosts).  emask_l[j]: element mask of subdomain j; emask: that of i."""
+        return [j for j in range(len(emask_l)) if np.any(emask_l[j] & emask)]
 
     def _setup(self, only):
         p = self.prob
@@ -290,13 +387,13 @@ class Oracle:
                     mk |= elem_mask_fine[f]
                 emask_l.append(mk)
             lam, m, basis, rows, dirr, dchol, gsz = [], [], [], [], [], [], []
-            keep_ab, keep_own = [], []
+            keep_ab, keep_own, keep_gen = [], [], []
             A_lm1 = self.Al[l - 1]
             for i in range(nsub):
                 emask = np.zeros(p.n_elem, bool)
                 for j in np.nonzero(par == i)[0]:
                     emask |= emask_l[j]
-                gen_subs = [j for j in range(lev.n_sub) if np.any(emask_l[j] & emask)]
+                gen_subs = self._generating_subdomains(emask_l, emask, par, i)
                 owned_subs = set(np.nonzero(par == i)[0].tolist())
                 gen_cols = np.concatenate([np.nonzero(col_owner == j)[0] for j in gen_subs])
                 own = np.array([col_owner[c] in owned_subs for c in gen_cols])
@@ -317,11 +414,12 @@ class Oracle:
                 gsz.append(len(gen_cols))
                 keep_ab.append(Ab)
                 keep_own.append(own)
+                keep_gen.append(gen_cols)
                 if self.verbose:
                     print(f"  level {l-1} sub {i}: gen={len(gen_cols)} own={own.sum()} m={g.m}",
                           flush=True)
             self.levels[l - 1] = LevelData(l - 1, nsub, lam, np.array(m), basis, rows, dirr,
-                                           dchol, gsz, keep_ab, keep_own)
+                                           dchol, gsz, keep_ab, keep_own, keep_gen)
         self.A0 = self.Al[0]
         self.A0_chol = cholesky(self.A0)
 

@@ -92,6 +92,7 @@ class MsddError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"msdd error {_ERRNAMES.get(code, code)}: {msg}")
         self.code = code
+        self.stats = None
 
 
 def load():
@@ -223,7 +224,11 @@ class Msdd:
     def _check(self, rc, allow=()):
         if rc != MSDD_OK and rc not in allow:
             msg = self._L.msdd_last_error(self._h).decode()
-            raise MsddError(rc, msg)
+            err = MsddError(rc, msg)
+            st = MsddStats()
+            if self._L.msdd_stats(self._h, ctypes.byref(st)) == MSDD_OK:
+                err.stats = st.as_dict()   # what the failed call recorded
+            raise err
         return rc
 
     def setup(self, n, rowptr, col, val, elem_dofs, elem_mat, sub_elem_ptr, sub_elem, sub_dof_ptr,

@@ -250,7 +250,7 @@ __global__ void k_gram(const i32* __restrict__ nb, const i64* __restrict__ kvoff
 __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
                                 const double* __restrict__ GB, double* __restrict__ Cout,
                                 double* __restrict__ nu_out, const int* __restrict__ active,
-                                int nsplit) {
+                                int nsplit, double* __restrict__ gs_diag) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = blockIdx.x;
   if (active && active[i] != ST_RUNNING) return;
@@ -274,6 +274,8 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
   __syncthreads();
   for (int t = tid; t < K; t += nt) {
     const double dgs = S[t * K + t];
+    // y_t^T S y_t = ||S^{-1} b x_t||_S^2 for the previous Ritz vector x_t (error bound)
+    gs_diag[(i64)i * K + t] = dgs;
     sc[t] = dgs > 0 ? 1.0 / sqrt(dgs) : 0.0;
   }
   __syncthreads();
@@ -487,6 +489,13 @@ constexpr double CERT_TOL = 1e-11;
 // rounding floor of its pencil; it is accepted if its backward error is within 1e6 times
 // the tolerance (1e-8 at the default 1e-14).  The host counts such pairs.
 constexpr double STAG_FACTOR = 1e6;
+// The Krylov-Weinstein interval shows that an eigenvalue lies near the certifying Ritz
+// value, not that none lies above it in nu (Ritz values bound eigenvalues from below), so
+// it is used only after KW_MIN_IT iterations: an eigenvalue below eta that the block had
+// not yet captured would by then dominate it (its component grows by
+// (lambda_{m+1} + sigma) / (lambda* + sigma) per iteration; the rule is needed only for
+// certifying pairs in the slow cluster near lambda = 1, where that factor is large).
+constexpr int KW_MIN_IT = 30;
 
 // Convergence decision of each running subdomain (one wavefront): sums the row-split
 // partials of k_eig_update, then the backward errors, Ritz values, count m and status.
@@ -496,10 +505,10 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
                             int* __restrict__ mcount, double* __restrict__ lam_out,
                             double* __restrict__ res_out, int Kmax_allowed,
                             const i32* __restrict__ rankb, const double* __restrict__ normS,
-                            double* __restrict__ nu_prev) {
+                            double* __restrict__ nu_prev, const double* __restrict__ gs_diag) {
   const int i = blockIdx.x;
   if (status[i] != ST_RUNNING) return;
-  __shared__ double sh_res[64], sh_lam[64], sh_stag[64];
+  __shared__ double sh_res[64], sh_lam[64], sh_stag[64], sh_kwup[64];
   const int tid = threadIdx.x;
   if (tid < K) {
     double sr = 0, ss = 0;
@@ -518,6 +527,13 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
     sh_res[tid] = rel;
     sh_lam[tid] = lv;
     sh_stag[tid] = (rel <= fmax(STAG_FACTOR * tol, CERT_TOL) && fabs(nv - np) <= 1e-14 * fabs(nv)) ? 1.0 : 0.0;
+    // Krylov-Weinstein: the previous Ritz pair (np, x) of this column, x^T S x = 1, has an
+    // eigenvalue of S^{-1} b within eps = ||S^{-1} b x - np x||_S, and eps^2 = y^T S y - np^2
+    // with y = S^{-1} b x (this iteration's block).  The rounding of y^T S y is covered by a
+    // floor of 16 u y^T S y.  sh_kwup = np + eps, the interval's upper end (nu of the pair).
+    const double g = gs_diag[(i64)i * K + tid];
+    const double e2 = fmax(g - np * np, 0.0) + 16.0 * 2.220446049250313e-16 * fabs(g);
+    sh_kwup[tid] = (np > 0.0 && g > 0.0) ? np + sqrt(e2) : INFINITY;
   }
   __syncthreads();
   if (tid == 0) {
@@ -535,8 +551,15 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
     // least eta); its Ritz value is accurate to about its backward error, so it is
     // accepted at CERT_TOL, below the accuracy asked of reported eigenvalues
     for (int a = 0; a < need; ++a) {
-      const double ta = (a == m && sh_lam[a] >= eta) ? fmax(tol, CERT_TOL) : tol;
-      ok = ok && (sh_res[a] <= ta || sh_stag[a] > 0.0);
+      if (a == m && sh_lam[a] >= eta) {
+        // the certifying pair: accepted at CERT_TOL, or once the Krylov-Weinstein interval
+        // of its previous iterate lies entirely on the lambda > eta side (its eigenvalue
+        // then certifies the count whatever its remaining error)
+        const bool kw = it >= KW_MIN_IT && sh_kwup[a] < 1.0 / (eta + sigma);
+        ok = ok && (sh_res[a] <= fmax(tol, CERT_TOL) || sh_stag[a] > 0.0 || kw);
+      } else {
+        ok = ok && (sh_res[a] <= tol || sh_stag[a] > 0.0);
+      }
     }
     mcount[i] = m;
     if (grow) status[i] = ST_GROW;
@@ -652,14 +675,15 @@ void launch_gram(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K, c
 }
 
 void launch_rayleigh_ritz(hipStream_t s, int P, int K, const double* GS, const double* GB,
-                          double* C, double* nu, const int* active, int nsplit) {
+                          double* C, double* nu, const int* active, int nsplit, double* gs_diag) {
   size_t lds = (3 * (size_t)K * K + 6 * K) * sizeof(double) + K * sizeof(int) + 16;
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   // four wavefronts per subdomain (for K = 16 the Jacobi itself runs in one of them)
   const int nt = 256;
-  hipLaunchKernelGGL(k_rayleigh_ritz, dim3(P), dim3(nt), lds, s, K, GS, GB, C, nu, active, nsplit);
+  hipLaunchKernelGGL(k_rayleigh_ritz, dim3(P), dim3(nt), lds, s, K, GS, GB, C, nu, active, nsplit,
+                     gs_diag);
 }
 
 void launch_row_norm(hipStream_t s, int P, const i64* voff, int ell_w, const i32* ell_col,
@@ -673,14 +697,15 @@ void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, in
                        double* X, double* BX, double* SX, double sigma, double eta, int nev_max,
                        double tol, int maxit, int* status, int* iters, int* mcount,
                        double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
-                       const double* normS, double* nu_prev, double* part, int nsplit) {
+                       const double* normS, double* nu_prev, double* part, int nsplit,
+                       const double* gs_diag) {
   constexpr int TR = 16;
   size_t lds = (size_t)K * K * sizeof(double) + 3 * TR * K * sizeof(double);
   hipLaunchKernelGGL((k_eig_update<double, TR>), dim3(P, nsplit), dim3(MSDD_WG), lds, s, nb, kvoff,
                      K, C, nu, Y, Z, X, BX, SX, status, part, nsplit);
   hipLaunchKernelGGL(k_eig_judge, dim3(P), dim3(64), 0, s, K, nu, part, nsplit, sigma, eta,
                      nev_max, tol, maxit, status, iters, mcount, lam_out, res_out, Kmax_allowed,
-                     rankb, normS, nu_prev);
+                     rankb, normS, nu_prev, gs_diag);
 }
 
 void launch_eig_finalize(hipStream_t s, int P, const i32* nb, const i64* voff, const i64* kvoff,

@@ -949,9 +949,11 @@ void fine_eigensolve(msdd_ctx* c) {
     E.res.alloc((size_t)P * K);
     E.mcount.alloc(P);
     E.mcount.zero(s);
-    DVec<double> nu_prev, normS;
+    DVec<double> nu_prev, normS, gsd;
     nu_prev.alloc((size_t)P * K);
     nu_prev.zero(s);
+    gsd.alloc((size_t)P * K);
+    gsd.zero(s);
     normS.alloc(P);
     launch_row_norm(s, P, F.gs.voff.p, F.ell_w, F.ell_col.p, F.ell_val.p, F.dv.p, c->sigma, normS.p);
     DVec<int> status, iters;
@@ -992,14 +994,14 @@ void fine_eigensolve(msdd_ctx* c) {
       }
       {
         ProfScope ps(c, PR_EIG_RR, c->eig_active * 3.0 * K * K * 8.0, 0.0);
-        launch_rayleigh_ritz(s, P, K, GS.p, GB.p, Cm.p, E.nu.p, status.p, nsplit);
+        launch_rayleigh_ritz(s, P, K, GS.p, GB.p, Cm.p, E.nu.p, status.p, nsplit, gsd.p);
       }
       {
         ProfScope ps(c, PR_EIG_UPDATE, f * 6.0 * F.s_nb * K * 8.0, f * 6.0 * F.s_nb * K * K);
         launch_eig_update(s, P, F.gs.n.p, dkvoff.p, K, Cm.p, E.nu.p, Y.p, Z.p, E.X.p, BX.p, SX.p,
                           c->sigma, c->eta, o.nev_max, o.eig_tol, maxit, status.p, iters.p,
                           E.mcount.p, E.lam.p, E.res.p, 64, F.rankb.p, normS.p, nu_prev.p,
-                          upart.p, nsplit);
+                          upart.p, nsplit, gsd.p);
       }
       HIPCHK(hipGetLastError());
       if (it >= 3 && (it % 2 == 1 || it == maxit - 1)) {
@@ -1039,14 +1041,17 @@ void fine_eigensolve(msdd_ctx* c) {
         // not certified, so the coarse space may miss eigenvectors below eta
         ++unconverged;
         if (first_unconv < 0) first_unconv = i;
-      } else {
-        // selected pairs (and the certifying one) accepted at the rounding floor rather
-        // than at the tolerance
-        for (int a = 0; a < std::min(K, mc[i] + 1); ++a) {
-          const double la = lamv[(size_t)i * K + a];
-          const double ta = (a == mc[i] && la >= c->eta) ? std::max(o.eig_tol, 1e-11) : o.eig_tol;
-          if (resv[(size_t)i * K + a] > ta) ++stagnated;
+        if (c->opt.verbose) {
+          std::fprintf(stderr, "msdd: subdomain %d not converged (status %d, %d iterations, K %d, m %d):", i,
+                       st[i], itv[i], K, mc[i]);
+          for (int a = 0; a < std::min(K, mc[i] + 2); ++a)
+            std::fprintf(stderr, " [%.10g %.2e]", lamv[(size_t)i * K + a], resv[(size_t)i * K + a]);
+          std::fprintf(stderr, "\n");
         }
+      } else {
+        // selected pairs accepted at the rounding floor rather than at the tolerance
+        for (int a = 0; a < std::min(K, mc[i]); ++a)
+          if (resv[(size_t)i * K + a] > o.eig_tol) ++stagnated;
       }
       want[i] = 0;
       final_pass[i] = (int)passes.size();
@@ -1054,12 +1059,23 @@ void fine_eigensolve(msdd_ctx* c) {
       E.subs.push_back(i);
       const int ne = std::min(K, mc[i] + 4);
       F.lam[i].assign(lamv.begin() + (size_t)i * K, lamv.begin() + (size_t)i * K + ne);
-      for (int a = 0; a < std::min(K, mc[i] + 1); ++a) res_max = std::max(res_max, resv[(size_t)i * K + a]);
+      for (int a = 0; a < std::min(K, mc[i]); ++a) res_max = std::max(res_max, resv[(size_t)i * K + a]);
     }
     passes.push_back(std::move(ps));
     if (!grew && !fell) break;
     if (grew) K *= 2;
   }
+  c->eig_iters = iters_tot;
+  int64_t isum = 0;
+  for (int v : iters_tot) isum += v;
+  c->stats.eig_iters_sum = isum;
+  c->stats.warm_started = net ? P : 0;
+  c->stats.warm_fallbacks = fallbacks;
+  c->stats.eig_iters_max = max_it;
+  c->stats.eig_restarts = restarts;
+  c->stats.eig_resid_max = res_max;
+  c->stats.eig_unconverged = unconverged;
+  c->stats.eig_stagnated = stagnated;
   if (unconverged > 0)
     throw MsddError{MSDD_EEIG, "local eigensolver: " + std::to_string(unconverged) +
                                    " finest-level subdomain(s) not converged within eig_maxit "
@@ -1119,17 +1135,6 @@ void fine_eigensolve(msdd_ctx* c) {
     HIPCHK(hipStreamSynchronize(s));
   }
   c->warm.have_targets = m_cap > 0;
-  c->eig_iters = iters_tot;
-  int64_t isum = 0;
-  for (int v : iters_tot) isum += v;
-  c->stats.eig_iters_sum = isum;
-  c->stats.warm_started = net ? P : 0;
-  c->stats.warm_fallbacks = fallbacks;
-  c->stats.eig_iters_max = max_it;
-  c->stats.eig_restarts = restarts;
-  c->stats.eig_resid_max = res_max;
-  c->stats.eig_unconverged = unconverged;
-  c->stats.eig_stagnated = stagnated;
 }
 
 // ---------------------------------------------------------------------------

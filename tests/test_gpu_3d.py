@@ -10,7 +10,7 @@ import pytest
 
 from msdd_inputs import problems as P
 from oracle.msdd_oracle import Oracle
-from test_gpu_parity import _apply_rel, _check_fine_level, _setup, _solve
+from test_gpu_parity import APPLY_BAR, _apply_rel, _check_fine_level, _setup, _solve
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +26,7 @@ CASES = {
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_3d_against_oracle(case):
     prob = CASES[case]()
-    o = Oracle(prob)
+    o = Oracle(prob, fine_vectors=8)
     m, _ = _setup(prob)
     _check_fine_level(m, o, prob, prob.eta)
     L = prob.n_levels - 1
@@ -36,11 +36,11 @@ def test_3d_against_oracle(case):
         for i in range(lev.n_sub):
             lg = m.eigs(l, i, 0)
             assert np.all((lg >= -1e-12) & (lg < prob.eta)) and len(lg) == lev.m[i]
-    assert _apply_rel(m, o, prob) < (1e-9 if L == 1 else 1e-3)
+    assert _apply_rel(m, o, prob) < APPLY_BAR
     it, rel, x = _solve(m, prob)
     ro = o.solve()
     assert abs(it - ro.iters) <= 1
-    assert np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x) < (1e-8 if L == 1 else 1e-7)
+    assert np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x) < 1e-8
     if case.startswith("elasticity"):
         assert m.stats()["max_band"] >= 64   # the wide-band kernels ran
     m.close()

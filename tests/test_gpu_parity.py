@@ -1,16 +1,18 @@
 """GPU parity: the HIP library (through its C ABI) against the CPU oracle.
 
-Tolerances (derived in the design doc):
-  * finest-level eigenvalues: |d lambda| <= 1e-10 * max(lambda, eta) (below eta the
-    eigenvalues of a high-contrast pencil are fixed in double precision only to an
-    absolute ~1e-11: see the 40-digit pin of the oracle);
-  * finest-level coarse-space blocks: largest principal angle <= 1e-7;
-  * counts m: exact (subdomains with an eigenvalue within 1e-8 eta of eta excepted);
-  * coarse levels (generating systems): counts exact, the preconditioner apply
-    within 1e-3 relative (the generating system is numerically rank deficient, and
-    two valid reductions of it differ at that level);
-  * PCG: iteration count within +-1 and solution within 1e-8 relative (2 levels)
-    or within the CG attainable-accuracy bound (3 levels).
+Tolerances (derived in tests/gpu_common.py and the design notes):
+  * finest-level eigenvalues of the selected pairs: within 128 u cond (the first-order
+    effect of the FP64 evaluation of the pencil) or 1e-10 max(lambda, 1e-3 eta), whichever
+    is larger, of the oracle's pair refined in binary128 on the exactly summed element data;
+    the pair that certifies the count must lie at or above eta on both sides;
+  * finest-level coarse-space blocks: sin of the largest principal angle to the refined
+    subspace D X within 1e-8;
+  * counts m: exact;
+  * coarse levels (generating systems): counts exact, eigenvalues in [0, eta); the
+    preconditioner apply within 1e-8 relative (a sum of A-orthogonal projections moves by
+    O(theta) when its subspaces turn by theta; 1e-8 is the subspace bar);
+  * PCG: iteration count within +-1, solution and the iterates at fixed counts within 1e-8
+    relative.
 """
 import json
 import os
@@ -24,6 +26,8 @@ from oracle.msdd_oracle import Oracle, neumann_matrix
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+ANGLE_BAR = 1e-8
+APPLY_BAR = 1e-8
 
 
 def _torch():
@@ -37,28 +41,27 @@ def _setup(prob, **opts):
     return gpu_setup(prob, **opts)
 
 
-def _sin_angle(U, V):
-    """sin of the largest principal angle between span(U) and span(V)."""
-    if U.shape[1] != V.shape[1]:
-        return 1.0
-    if U.shape[1] == 0:
-        return 0.0
-    Qu, _ = np.linalg.qr(U)
-    Qv, _ = np.linalg.qr(V)
-    return float(np.linalg.norm(Qv - Qu @ (Qu.T @ Qv), 2))
-
-
-def _check_fine_level(m, o, prob, eta, rel=1e-10, angle=1e-7):
+def _check_fine_level(m, o, prob, eta):
+    """Counts, selected eigenvalues, certifying pairs and coarse-space blocks of the finest
+    level against the binary128 references (o built with fine_vectors > 0)."""
+    from gpu_common import check_selected_and_certifying, refined_fine_level, sin_angle
     L = prob.n_levels - 1
     lev = o.levels[L]
     mg = m.level_counts(L, prob.n_sub)
     assert list(mg) == list(lev.m)
-    for i in range(prob.n_sub):
-        lg = m.eigs(L, i, 0)
-        lo = lev.lam[i][:len(lg)]
-        scale = np.maximum(np.abs(lo), eta)
-        assert np.all(np.abs(lg - lo) <= rel * scale), (i, lg, lo)
-        assert _sin_angle(m.basis(L, i), lev.basis[i]) <= angle, i
+    st = m.stats()
+    assert st["eig_unconverged"] == 0
+    refs = refined_fine_level(o, prob)
+    worst = 0.0
+    for i, r in enumerate(refs):
+        mi = int(lev.m[i])
+        lg = m.eigs(L, i, 1)
+        worst = max(worst, check_selected_and_certifying(lg, mi, r.lam, r.fp64_uncertainty,
+                                                         r.bound, eta, where=i))
+        if mi:
+            Dx = prob.sub_weights(i)[:, None] * r.X[:, :mi]
+            assert sin_angle(m.basis(L, i), Dx) <= ANGLE_BAR, i
+    return worst
 
 
 def _apply_rel(m, o, prob, seed=0):
@@ -81,17 +84,33 @@ def _solve(m, prob, rtol=1e-8, maxit=2000):
     return it, rel, x.cpu().numpy()
 
 
+def _iterate(m, prob, k):
+    """The PCG iterate after exactly k iterations (x0 = 0)."""
+    torch = _torch()
+    b = torch.from_numpy(prob.b).cuda()
+    x = torch.zeros_like(b)
+    m.solve(b, x, 1e-30, k, allow_noconv=True)
+    torch.cuda.synchronize()
+    return x.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
 @pytest.mark.parametrize("contrast,seed", [(1.0, 0), (1e4, 3), (1e6, 5)])
 def test_two_level_small(contrast, seed):
     prob = P.small_problem(N=16, P=4, delta=1, contrast=contrast, seed=seed)
-    o = Oracle(prob)
+    o = Oracle(prob, fine_vectors=8)
     m, _ = _setup(prob)
     _check_fine_level(m, o, prob, prob.eta)
-    assert _apply_rel(m, o, prob) < 1e-9
+    assert _apply_rel(m, o, prob) < APPLY_BAR
     it, rel, x = _solve(m, prob)
-    ro = o.solve()
+    ro = o.solve(record=True)
     assert abs(it - ro.iters) <= 1
-    assert np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x) < 1e-8
+    assert _rel(x, ro.x) < 1e-8
+    for k in (3, 8):
+        assert _rel(_iterate(m, prob, k), ro.iterates[k]) < 1e-8, k
     m.close()
 
 
@@ -101,7 +120,7 @@ def test_three_level_small(N, Pn, delta, seed):
     counts m exactly (they are stable under the truncation of the numerically
     dependent ghost functions), the preconditioner and the PCG (iterations +-1)."""
     prob = P.small_problem(N=N, P=Pn, delta=delta, contrast=1e4, n_levels=3, groups=(2,), seed=seed)
-    o = Oracle(prob)
+    o = Oracle(prob, fine_vectors=8)
     m, _ = _setup(prob)
     _check_fine_level(m, o, prob, prob.eta)
     lev = o.levels[1]
@@ -109,34 +128,53 @@ def test_three_level_small(N, Pn, delta, seed):
     for i in range(lev.n_sub):
         lg = m.eigs(1, i, 0)
         assert np.all((lg >= -1e-12) & (lg < prob.eta)) and len(lg) == lev.m[i]
-    assert _apply_rel(m, o, prob) < 1e-3
+    assert _apply_rel(m, o, prob) < APPLY_BAR
     it, rel, x = _solve(m, prob)
-    ro = o.solve()
+    ro = o.solve(record=True)
     assert abs(it - ro.iters) <= 1
-    assert np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x) < 1e-7
+    assert _rel(x, ro.x) < 1e-8
+    for k in (3, 8):
+        assert _rel(_iterate(m, prob, k), ro.iterates[k]) < 1e-8, k
     m.close()
+
+
+def _golden(name):
+    with open(os.path.join(HERE, "golden", f"{name}_oracle.json")) as f:
+        g = json.load(f)
+    arr = np.load(os.path.join(HERE, "golden", f"{name}_oracle.npz"), allow_pickle=False)
+    return g, arr
+
+
+def _check_golden_fine_level(m, prob, g, arr):
+    from gpu_common import check_selected_and_certifying, sin_angle
+    L = prob.n_levels - 1
+    lev = g["levels"][str(L)]
+    ref = lev["lam_ref"]
+    assert list(m.level_counts(L, prob.n_sub)) == lev["m"]
+    worst = 0.0
+    for i in range(prob.n_sub):
+        lg = m.eigs(L, i, 1)   # the m selected pairs and the next one, which certifies m
+        worst = max(worst, check_selected_and_certifying(
+            lg, lev["m"][i], np.array(ref["lam"][i]), np.array(ref["unc"][i]),
+            np.array(ref["bound"][i]), prob.eta, where=i))
+    for i in g["basis_subdomains"]:
+        Bo = arr[f"basis_{L}_{i}"]
+        assert sin_angle(m.basis(L, i), Bo) <= ANGLE_BAR, i
+    return worst
 
 
 def test_c1_full_against_golden():
     """64x64 channels workload, 2 levels: every subdomain and the PCG against the oracle."""
-    with open(os.path.join(HERE, "golden", "c1_oracle.json")) as f:
-        g = json.load(f)
+    g, arr = _golden("c1")
     prob = P.config1()
     m, _ = _setup(prob)
-    L = prob.n_levels - 1
-    lev = g["levels"][str(L)]
-    assert list(m.level_counts(L, prob.n_sub)) == lev["m"]
-    for i in range(prob.n_sub):
-        lg = m.eigs(L, i, 1)   # the m selected pairs and the next one, which certifies m
-        lo = np.array(lev["lam"][i][:len(lg)])
-        scale = np.maximum(np.abs(lo), prob.eta)
-        assert np.all(np.abs(lg - lo) <= 1e-10 * scale), (i, lg, lo)
-    st = m.stats()
-    assert st["n"] == g["level_sizes"]
+    assert m.stats()["n"] == g["level_sizes"]
+    _check_golden_fine_level(m, prob, g, arr)
     it, rel, x = _solve(m, prob)
     assert abs(it - g["pcg"]["iters"]) <= 1
-    xo = np.array(g["pcg"]["x"])
-    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8
+    assert _rel(x, arr["x"]) < 1e-8
+    for k in g["iterates"]:
+        assert _rel(_iterate(m, prob, k), arr[f"x_it{k}"]) < 1e-8, k
     m.close()
 
 
@@ -147,54 +185,51 @@ def _first_below(h, tau):
 
 def test_c2_full_against_golden():
     """512x512 inclusions workload, 3 levels (the benchmark workload), against the oracle's
-    full run (tests/golden/c2_oracle.json).
+    full run (tests/golden/c2_oracle.json, .npz).
 
-    Tolerances, from the arithmetic of this workload:
-      * finest-level eigenvalues: 2.5e-8 * max(lambda, eta).  The oracle itself differs
-        from LAPACK (scipy.linalg.eigh on the same pencils, all 256 subdomains) by up to
-        1.26e-8 * max(lambda, eta) here (contrast 1e6, 1369 dofs per subdomain), so the
-        bar is twice the reference's own uncertainty;
-      * level-1 eigenvalues (generating systems, numerically rank deficient): 1e-6 *
-        max(lambda, eta);
-      * PCG: the 2-norm residual of this high-contrast system is erratic (it first grows
-        to 3e3, later has isolated spikes), and the attainable accuracy of the residual is
-        ~eps ||A|| ||x|| / ||b|| = 3e-6.  GPU and oracle histories agree to 4 digits for
-        the first 60 iterations and stay within a factor 1.85 afterwards, but a spike
-        (iteration 95: 4.9e-6 against 8.3e-6) moves the crossing of 1e-5 by two
-        iterations.  Below the attainable accuracy the recurrence residual is dominated
-        by rounding: it contracts by about 0.77 per iteration near 1e-8 (oracle history,
-        iterations 115-120), so the history bound below (a factor 10^0.5) allows the
-        crossing of 1e-8 to move by log(10^0.5)/log(1/0.77) = 4.4 iterations; the oracle's
-        last step lands at 0.98e-8.  So crossings of 1e-2 ... 1e-7 are compared within +-2
-        (the +-1 bar holds on the other workloads), the final count within +-4, the whole
-        history within a factor 10^0.5, the solution at sampled dofs within 1e-7 and the
-        true residual below 1e-5."""
-    with open(os.path.join(HERE, "golden", "c2_oracle.json")) as f:
-        g = json.load(f)
+      * finest level: every count; every selected eigenvalue to the per-pair bar against the
+        binary128 references; coarse-space blocks of 16 sampled subdomains within 1e-8;
+      * level 1 (generating systems): counts exact, eigenvalues within 1e-6 max(lambda, eta).
+        These pencils are numerically rank deficient (the singular values of abar + b run
+        continuously down to the compression threshold); two independent reductions of the
+        same pencil (compression and the Schur complement with a pseudo-inverse) agree only
+        to 2e-6 at contrast 1e4 (the oracle's coarse-pencil pin), so that is the accuracy to
+        which these eigenvalues are defined in FP64;
+      * PCG: the iterates after 5 and 20 iterations and the final solution within 1e-8.
+        The attainable accuracy of the residual of this contrast-1e6 system is
+        eps ||A|| ||x|| / ||b|| = 3e-6 (the true residual of both runs at exit); crossings
+        of thresholds at least 100 times above it (1e-2, 1e-3, 1e-4) agree within +-1.  Below
+        the floor the recurrence residual is driven by rounding and contracts by about 0.77
+        per iteration near 1e-8 (oracle history), so a factor 10^0.5 between the histories
+        (the history bound below) moves the crossing of 1e-8 by up to
+        log(10^0.5) / log(1/0.77) = 4.4 iterations: the final count is compared within +-4."""
+    if not os.path.exists(os.path.join(HERE, "golden", "c2_oracle.npz")):
+        pytest.skip("c2 golden (refined references, solution) not generated yet")
+    g, arr = _golden("c2")
     prob = P.config2()
     m, _ = _setup(prob)
     assert m.stats()["n"] == g["level_sizes"]
-    for L, tol in ((2, 2.5e-8), (1, 1e-6)):
-        lev = g["levels"][str(L)]
-        assert list(m.level_counts(L, len(lev["m"]))) == lev["m"], L
-        for i in range(len(lev["m"])):
-            lg = m.eigs(L, i, 1 if L == 2 else 0)
-            lo = np.array(lev["lam"][i][:len(lg)])
-            assert len(lo) == len(lg)
-            scale = np.maximum(np.abs(lo), prob.eta)
-            assert np.all(np.abs(lg - lo) <= tol * scale), (L, i, lg, lo)
+    _check_golden_fine_level(m, prob, g, arr)
+    lev1 = g["levels"]["1"]
+    assert list(m.level_counts(1, len(lev1["m"]))) == lev1["m"]
+    for i in range(len(lev1["m"])):
+        lg = m.eigs(1, i, 0)
+        lo = np.array(lev1["lam"][i][:len(lg)])
+        assert len(lo) == len(lg)
+        assert np.all(np.abs(lg - lo) <= 1e-6 * np.maximum(np.abs(lo), prob.eta)), (i, lg, lo)
+    for k in g["iterates"]:
+        if k <= 20:
+            assert _rel(_iterate(m, prob, k), arr[f"x_it{k}"]) < 1e-8, k
     it, rel, x = _solve(m, prob)
     h = m.history()
     ho = np.array(g["pcg"]["resnorms"])
     ho = ho / ho[0]
-    for tau in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7):
-        assert abs(_first_below(h, tau) - _first_below(ho, tau)) <= 2, tau
+    for tau in (1e-2, 1e-3, 1e-4):
+        assert abs(_first_below(h, tau) - _first_below(ho, tau)) <= 1, tau
     assert abs(it - g["pcg"]["iters"]) <= 4
     k = min(len(h), len(ho))
     assert np.max(np.abs(np.log10(h[:k] / ho[:k]))) <= 0.5
-    idx = np.array(g["pcg"]["x_sample_idx"])
-    xs = np.array(g["pcg"]["x_sample"])
-    assert np.linalg.norm(x[idx] - xs) / np.linalg.norm(xs) < 1e-7
+    assert _rel(x, arr["x"]) < 1e-8
     assert np.linalg.norm(prob.b - prob.A @ x) / np.linalg.norm(prob.b) < 1e-5
     m.close()
 
@@ -219,30 +254,36 @@ def test_c1_local_eigenpairs_residual():
 
 
 @pytest.mark.parametrize("case", ["c1", "three_level"])
-def test_mixed_precision_apply(case):
-    """Single-precision Dirichlet factors and fine-level solves (MSDD_MIXED): the coarse
-    spaces are those of double precision (bitwise), PCG reaches the same recurrence
-    tolerance in at most 3 more iterations, and the true residual stays within 10x of
-    the double-precision run's (its error against the oracle is stated, not bounded)."""
+def test_mixed_precision_against_oracle(case):
+    """Single-precision Dirichlet factors and fine-level solves (MSDD_MIXED) against the
+    oracle: the coarse spaces come from the FP64 eigensolver, so counts and eigenvalues meet
+    the FP64 bars (and equal the FP64 GPU run bitwise); PCG reaches the recurrence tolerance
+    within 3 iterations of the oracle's count, and its solution error against the oracle is
+    stated (printed), with the true residual within 10x of the oracle's."""
     from paper_2106_06404_amd import binding as B
     prob = (P.config1() if case == "c1" else
             P.small_problem(N=20, P=4, delta=2, contrast=1e4, n_levels=3, groups=(2,), seed=12))
+    o = Oracle(prob, fine_vectors=8)
+    ro = o.solve()
+    tr_o = np.linalg.norm(prob.b - prob.A @ ro.x) / np.linalg.norm(prob.b)
     out = {}
     for prec in (B.MSDD_FP64, B.MSDD_MIXED):
         m, _ = _setup(prob, precision=prec)
         L = prob.n_levels - 1
-        counts = m.level_counts(L, prob.n_sub)
+        if prec == B.MSDD_MIXED:
+            _check_fine_level(m, o, prob, prob.eta)
         eigs = [m.eigs(L, i, 0) for i in range(prob.n_sub)]
         it, rel, x = _solve(m, prob)
         tr = np.linalg.norm(prob.b - prob.A @ x) / np.linalg.norm(prob.b)
-        out[prec] = (counts, eigs, it, rel, x, tr)
+        out[prec] = (eigs, it, rel, x, tr)
         m.close()
-    c64, e64, it64, _, x64, tr64 = out[B.MSDD_FP64]
-    c32, e32, it32, rel32, x32, tr32 = out[B.MSDD_MIXED]
-    assert np.array_equal(c64, c32)
+    e64 = out[B.MSDD_FP64][0]
+    e32, it32, rel32, x32, tr32 = out[B.MSDD_MIXED]
     assert all(np.array_equal(a, b) for a, b in zip(e64, e32))
-    assert rel32 < 1e-8 and it32 <= it64 + 3
-    assert tr32 <= 10 * tr64 + 1e-12
+    assert rel32 < 1e-8 and abs(it32 - ro.iters) <= 3
+    assert tr32 <= 10 * tr_o + 1e-12
+    print(f"mixed {case}: iterations {it32} (oracle {ro.iters}), solution error against the "
+          f"oracle {_rel(x32, ro.x):.2e}, true residual {tr32:.2e} (oracle {tr_o:.2e})")
 
 
 def test_single_subdomain_empty_coarse_space():
@@ -259,7 +300,7 @@ def test_ragged_boxes_and_block_growth():
     """Boxes of uneven size (N not divisible by P) and a threshold that selects many
     eigenvectors (forces the eigensolver to grow its block)."""
     prob = P.small_problem(N=23, P=3, delta=2, contrast=1e4, seed=21, eta=1.1)
-    o = Oracle(prob)
+    o = Oracle(prob, fine_vectors=8)
     m, _ = _setup(prob, block=16)
     _check_fine_level(m, o, prob, prob.eta)
     st = m.stats()

@@ -183,14 +183,14 @@ def test_warm_started_setup_matches_oracle():
     """An untrained network changes the start block only: eigenpairs, coarse space,
     apply and PCG agree with the oracle as for the random start."""
     prob = P.small_problem(N=16, P=4, delta=1, contrast=1e6, seed=5)
-    o = Oracle(prob)
+    o = Oracle(prob, fine_vectors=8)
     feat, sub_pos, n_pos = _frame(prob, 1)
     net = _net(feat.shape[1], 64, 8, n_pos, seed=3)
     m = _setup_warm(prob, net, feat, sub_pos, n_pos)
     st = m.stats()
     assert st["warm_started"] == prob.n_sub
     _check_fine_level(m, o, prob, prob.eta)
-    assert _apply_rel(m, o, prob) < 1e-9
+    assert _apply_rel(m, o, prob) < 1e-8
     it, rel, x = _solve(m, prob)
     ro = o.solve()
     assert abs(it - ro.iters) <= 1
@@ -201,20 +201,24 @@ def test_warm_started_setup_matches_oracle():
 
 def test_cold_start_fallback():
     """With one iteration allowed no warm-started subdomain converges: every one of
-    them is solved again from the random start."""
+    them is solved again from the random start, which cannot converge in one iteration
+    either, so the setup fails with MSDD_EEIG (an uncertified count is never accepted)
+    and the statistics record the fallbacks."""
+    from paper_2106_06404_amd import binding as B
     # subdomains of 12 x 12 elements: rank(b) far above the block, so one iteration
     # cannot reach the backward-error tolerance
     prob = P.small_problem(N=32, P=4, delta=2, contrast=1e4, seed=3)
     feat, sub_pos, n_pos = _frame(prob, 2)
     net = _net(feat.shape[1], 32, 8, n_pos, seed=4)
-    m = _setup_warm(prob, net, feat, sub_pos, n_pos, eig_maxit=1)
-    st = m.stats()
+    with pytest.raises(B.MsddError) as e:
+        _setup_warm(prob, net, feat, sub_pos, n_pos, eig_maxit=1)
+    assert e.value.code == B.MSDD_EEIG
+    st = e.value.stats
     assert st["warm_started"] == prob.n_sub and st["warm_fallbacks"] == prob.n_sub
-    # at least one warm and one cold iteration each (a pass with a larger block adds more
-    # for subdomains that asked to grow)
-    its = m.eig_iters(prob.n_sub)
-    assert np.all(its >= 2) and its.sum() == st["eig_iters_sum"]
-    m.close()
+    assert st["eig_unconverged"] == prob.n_sub
+    # one warm and one cold iteration each (a pass with a larger block adds more for
+    # subdomains that asked to grow)
+    assert st["eig_iters_sum"] >= 2 * prob.n_sub
     net.close()
 
 
@@ -289,10 +293,12 @@ def test_trained_network_reduces_eigensolver_work():
     L = prob.n_levels - 1
     assert np.array_equal(cold.level_counts(L, prob.n_sub), warm.level_counts(L, prob.n_sub))
     for i in range(prob.n_sub):
-        # the certified pairs: the m_i selected ones and the next (further Ritz values
-        # are not converged to the tolerance in either run)
+        # the m_i selected pairs (the next one only certifies the count: it is checked for
+        # its side of eta)
         lc, lw = cold.eigs(L, i, 1), warm.eigs(L, i, 1)
-        assert np.all(np.abs(lc - lw) <= 2.5e-8 * np.maximum(np.abs(lc), prob.eta)), (i, lc, lw)
+        mi = len(cold.eigs(L, i, 0))
+        assert np.all(np.abs(lc[:mi] - lw[:mi]) <= 2.5e-8 * np.maximum(np.abs(lc[:mi]), prob.eta)), (i, lc, lw)
+        assert np.all(lc[mi:] >= prob.eta) and np.all(lw[mi:] >= prob.eta)
     ic, _, xc = _solve(cold, prob)
     iw, _, xw = _solve(warm, prob)
     assert abs(ic - iw) <= 1
