@@ -197,6 +197,25 @@ int msdd_solve_batch(msdd_ctx* c, const double* b, double* x, double rtol, int32
  */
 int msdd_solve_history(const msdd_ctx* c, double* relres, int32_t cap, int32_t* count);
 
+/*
+ * msdd_solve without allocating: for callers that cannot allocate device memory during
+ * the call (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same computation, arguments, results and errors as msdd_solve, except:
+ *  - b and x must be device pointers (MSDD_EINVAL otherwise);
+ *  - the PCG work vectors (4 n doubles), chunk partial sums, per-problem CG scalars and
+ *    the residual history ((maxit + 1) doubles per problem) live in a fixed device array of
+ *    MSDD_NOALLOC_SCRATCH_BYTES per device (each device the library runs on holds it until
+ *    the process ends); a call that needs more fails with MSDD_EINVAL (n up to about
+ *    2 million dofs for one problem at maxit 1000);
+ *  - the iterations are launched one by one on the context's stream (no graph is built).
+ * It calls no hipMalloc or hipFree; the preconditioner's own buffers are the ones the
+ * setup allocated.  Every call on a device shares that device's array: calls that overlap
+ * in time on one device (from any context or thread) race and must not be made.
+ */
+#define MSDD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int msdd_solve_noalloc(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit,
+                       int32_t* iters, double* relres);
+
 /* z = B r: one application of the multilevel additive preconditioner. */
 int msdd_apply(msdd_ctx* c, const double* r, double* z);
 

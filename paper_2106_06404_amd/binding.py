@@ -82,7 +82,7 @@ EXPORTS = ["msdd_default_options", "msdd_create", "msdd_setup", "msdd_setup_batc
            "msdd_net_create", "msdd_net_param_count", "msdd_net_set_params",
            "msdd_net_get_params", "msdd_net_forward", "msdd_net_grad", "msdd_net_train_step",
            "msdd_net_last_error", "msdd_net_destroy", "msdd_autotune", "msdd_get_tuning",
-           "msdd_set_tuning"]
+           "msdd_set_tuning", "msdd_solve_noalloc"]
 MSDD_NPROF = 19
 
 _lib = None
@@ -125,6 +125,9 @@ def load():
     L.msdd_setup_batch.restype = ctypes.c_int
     L.msdd_solve.argtypes = [vp, vp, vp, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]
     L.msdd_solve.restype = ctypes.c_int
+    L.msdd_solve_noalloc.argtypes = [vp, vp, vp, f64, i32, ctypes.POINTER(i32),
+                                     ctypes.POINTER(f64)]
+    L.msdd_solve_noalloc.restype = ctypes.c_int
     L.msdd_solve_batch.argtypes = [vp, vp, vp, f64, i32, vp, vp]
     L.msdd_solve_batch.restype = ctypes.c_int
     L.msdd_solve_history.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
@@ -275,6 +278,16 @@ class Msdd:
         rel = ctypes.c_double()
         rc = self._L.msdd_solve(self._h, _ptr(b, np.float64), _ptr(x, np.float64), float(rtol),
                                 int(maxit), ctypes.byref(it), ctypes.byref(rel))
+        self._check(rc, allow=(MSDD_ENOCONV,) if allow_noconv else ())
+        return int(it.value), float(rel.value), rc
+
+    def solve_noalloc(self, b, x, rtol=1e-8, maxit=1000, allow_noconv=False):
+        """msdd_solve_noalloc: b, x must be device tensors."""
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        rc = self._L.msdd_solve_noalloc(self._h, _ptr(b, np.float64), _ptr(x, np.float64),
+                                        float(rtol), int(maxit), ctypes.byref(it),
+                                        ctypes.byref(rel))
         self._check(rc, allow=(MSDD_ENOCONV,) if allow_noconv else ())
         return int(it.value), float(rel.value), rc
 

@@ -166,6 +166,11 @@ void launch_apply_coarsest(hipStream_t s, int nt, int nmax, const i64* zoff, con
 void launch_apply_coarse_up(hipStream_t s, int P, const i32* nown, const i64* own_ptr,
                             const i32* own_idx, const i32* msub, const i64* yoff, const double* Y,
                             const i64* moff, const double* zc, double* zl);
+// Scratch array of msdd_solve_noalloc (pcg.hip): noalloc_scratch_init looks up its
+// device address for `device` (which must be current), once; noalloc_scratch returns it
+// (nullptr before the lookup).  Returns 0 or -1.
+int noalloc_scratch_init(int device);
+void* noalloc_scratch(int device);
 void launch_apply_fine_up(hipStream_t s, i64 n, const i64* dinc_ptr, const i32* dinc_sub,
                           const i32* dinc_q, const i64* doff, const i32* msub, const i64* moff,
                           const i64* phid_off, const double* PhiD, const double* u,

@@ -1838,6 +1838,11 @@ int msdd_create(msdd_ctx** out, const msdd_options* opt) {
     return MSDD_EINVAL;
   }
   c->stream = (hipStream_t)c->opt.stream;
+  // device address of msdd_solve_noalloc's scratch array on this device (once per device)
+  if (noalloc_scratch_init(c->opt.device) != 0) {
+    delete c;
+    return MSDD_EDEVICE;
+  }
   *out = c;
   return MSDD_OK;
 }
@@ -2123,32 +2128,40 @@ int msdd_apply(msdd_ctx* c, const double* r, double* z) {
 
 namespace {
 
+// Device buffers of one PCG run: work vectors, chunk partial sums, per-segment scalars
+// and states, residual history ((maxit + 1) entries per segment).
+struct PcgBufs {
+  double *r, *z, *p, *q, *partial, *segD, *hist;
+  int* segI;
+};
+
+PcgBufs ctx_bufs(msdd_ctx* c) {
+  return PcgBufs{c->r.p, c->z.p, c->p.p, c->q.p, c->partial.p, c->segD.p, c->hist_d.p, c->segI.p};
+}
+
 // One PCG iteration on every segment (Sec. 5), launched on stream s.
-void pcg_iteration(msdd_ctx* c, hipStream_t s, double* xx, int maxit) {
+void pcg_iteration(msdd_ctx* c, hipStream_t s, double* xx, int maxit, const PcgBufs& w) {
   const int64_t n = c->n;
   const int nch = c->nch, ns = c->nseg;
   const double spmv_bytes = (double)c->nnz * 12.0 + (double)(n + 1) * 8.0 + 2.0 * n * 8.0;
   {
     ProfScope ps(c, PR_SPMV, spmv_bytes, 2.0 * c->nnz);
     launch_spmv_chunk(s, nch, c->spmv_sg, c->ch_lo.p, c->ch_hi.p, c->rowptr.p, c->col.p, c->val.p,
-                      c->p.p, c->q.p, c->partial.p);
+                      w.p, w.q, w.partial);
   }
   {
     ProfScope ps(c, PR_VEC, 6.0 * n * 8.0, 6.0 * n);
-    launch_seg_reduce(s, ns, c->seg_ch.p, c->partial.p, c->segD.p, c->segI.p, PCG_R_PQ, 0.0, maxit,
-                      c->hist_d.p);
-    launch_update_xr_chunk(s, nch, c->ch_lo.p, c->ch_hi.p, c->ch_seg.p, xx, c->r.p, c->p.p, c->q.p,
-                           c->segD.p, c->partial.p);
-    launch_seg_reduce(s, ns, c->seg_ch.p, c->partial.p, c->segD.p, c->segI.p, PCG_R_RR, 0.0, maxit,
-                      c->hist_d.p);
+    launch_seg_reduce(s, ns, c->seg_ch.p, w.partial, w.segD, w.segI, PCG_R_PQ, 0.0, maxit, w.hist);
+    launch_update_xr_chunk(s, nch, c->ch_lo.p, c->ch_hi.p, c->ch_seg.p, xx, w.r, w.p, w.q, w.segD,
+                           w.partial);
+    launch_seg_reduce(s, ns, c->seg_ch.p, w.partial, w.segD, w.segI, PCG_R_RR, 0.0, maxit, w.hist);
   }
-  apply_prec(c, c->r.p, c->z.p, s);
+  apply_prec(c, w.r, w.z, s);
   {
     ProfScope ps(c, PR_VEC, 5.0 * n * 8.0, 4.0 * n);
-    launch_dot_chunk(s, nch, c->ch_lo.p, c->ch_hi.p, c->r.p, c->z.p, c->partial.p);
-    launch_seg_reduce(s, ns, c->seg_ch.p, c->partial.p, c->segD.p, c->segI.p, PCG_R_RZ, 0.0, maxit,
-                      c->hist_d.p);
-    launch_update_p_chunk(s, nch, c->ch_lo.p, c->ch_hi.p, c->ch_seg.p, c->z.p, c->p.p, c->segD.p, 0);
+    launch_dot_chunk(s, nch, c->ch_lo.p, c->ch_hi.p, w.r, w.z, w.partial);
+    launch_seg_reduce(s, ns, c->seg_ch.p, w.partial, w.segD, w.segI, PCG_R_RZ, 0.0, maxit, w.hist);
+    launch_update_p_chunk(s, nch, c->ch_lo.p, c->ch_hi.p, c->ch_seg.p, w.z, w.p, w.segD, 0);
   }
 }
 
@@ -2157,8 +2170,8 @@ void pcg_iteration(msdd_ctx* c, hipStream_t s, double* xx, int maxit) {
 // captured once as a HIP graph (per x pointer and maxit) and replayed.
 constexpr int PCG_CHUNK = 8;
 
-bool any_running(msdd_ctx* c) {
-  HIPCHK(hipMemcpyAsync(c->h_segI, c->segI.p, (size_t)c->nseg * PCG_SI * sizeof(int),
+bool any_running(msdd_ctx* c, const PcgBufs& w) {
+  HIPCHK(hipMemcpyAsync(c->h_segI, w.segI, (size_t)c->nseg * PCG_SI * sizeof(int),
                         hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   for (int q = 0; q < c->nseg; ++q)
@@ -2166,9 +2179,9 @@ bool any_running(msdd_ctx* c) {
   return false;
 }
 
-void run_chunk(msdd_ctx* c, double* xx, const double* bb, int maxit) {
-  if (c->prof.on) {
-    for (int k = 0; k < PCG_CHUNK; ++k) pcg_iteration(c, c->stream, xx, maxit);
+void run_chunk(msdd_ctx* c, double* xx, const double* bb, int maxit, const PcgBufs& w, bool graph) {
+  if (c->prof.on || !graph) {
+    for (int k = 0; k < PCG_CHUNK; ++k) pcg_iteration(c, c->stream, xx, maxit, w);
     return;
   }
   if (!c->gstream) {
@@ -2181,7 +2194,7 @@ void run_chunk(msdd_ctx* c, double* xx, const double* bb, int maxit) {
     c->gexec = nullptr;
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < PCG_CHUNK; ++k) pcg_iteration(c, c->gstream, xx, maxit);
+    for (int k = 0; k < PCG_CHUNK; ++k) pcg_iteration(c, c->gstream, xx, maxit, w);
     HIPCHK(hipStreamEndCapture(c->gstream, &g));
     const hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -2197,8 +2210,59 @@ void run_chunk(msdd_ctx* c, double* xx, const double* bb, int maxit) {
   HIPCHK(hipStreamWaitEvent(c->stream, c->gev1, 0));
 }
 
-// PCG on all segments from the initial guess in x; per-segment iteration counts and
-// final recurrence residuals in c->last_iters / c->last_relres.  Returns the status.
+// PCG on all segments from the initial guess in xx (device), right-hand side bb (device),
+// with the buffers w; per-segment iteration counts and final recurrence residuals in
+// c->last_iters / c->last_relres, the history of segment 0 in c->hist.  Returns the status.
+int pcg_run(msdd_ctx* c, const double* bb, double* xx, double rtol, int32_t maxit,
+            const PcgBufs& w, bool graph, double t0) {
+  hipStream_t s = c->stream;
+  const int ns = c->nseg;
+  // r = b - A x, rr0 per segment
+  launch_spmv_chunk(s, c->nch, c->spmv_sg, c->ch_lo.p, c->ch_hi.p, c->rowptr.p, c->col.p, c->val.p,
+                    xx, w.q, w.partial);
+  launch_residual_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, bb, w.q, w.r, w.partial);
+  launch_seg_reduce(s, ns, c->seg_ch.p, w.partial, w.segD, w.segI, PCG_R_RR0, rtol, maxit, w.hist);
+  apply_prec(c, w.r, w.z, s);
+  launch_dot_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, w.r, w.z, w.partial);
+  launch_seg_reduce(s, ns, c->seg_ch.p, w.partial, w.segD, w.segI, PCG_R_RZ0, 0.0, maxit, w.hist);
+  launch_update_p_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, c->ch_seg.p, w.z, w.p, w.segD, 1);
+  HIPCHK(hipGetLastError());
+  int done_its = 0;
+  while (any_running(c, w) && done_its < maxit) {
+    run_chunk(c, xx, bb, maxit, w, graph);
+    HIPCHK(hipGetLastError());
+    done_its += PCG_CHUNK;
+  }
+  std::vector<double> D((size_t)ns * PCG_SD);
+  std::vector<int> I((size_t)ns * PCG_SI);
+  HIPCHK(hipMemcpyAsync(D.data(), w.segD, D.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(I.data(), w.segI, I.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->last_iters.assign(ns, 0);
+  c->last_relres.assign(ns, 0.0);
+  int status = MSDD_OK;
+  bool bad = false;
+  for (int q = 0; q < ns; ++q) {
+    const int act = I[q * PCG_SI + PCG_ACTIVE];
+    c->last_iters[q] = act == PCG_RUNNING ? I[q * PCG_SI + PCG_IT] : I[q * PCG_SI + PCG_ITERS];
+    const double rr0 = D[q * PCG_SD + PCG_RR0];
+    c->last_relres[q] = rr0 > 0 ? std::sqrt(D[q * PCG_SD + PCG_RR] / rr0) : 0.0;
+    if (act == PCG_BREAKDOWN) bad = true;
+    else if (act != PCG_CONVERGED) status = MSDD_ENOCONV;
+  }
+  REQUIRE(!bad, "PCG produced a non-finite value (breakdown or non-finite input)");
+  // residual history of segment 0 (entry k of segment q at k * ns + q)
+  const int it0 = c->last_iters[0];
+  c->hist.assign(it0 + 1, 0.0);
+  HIPCHK(hipMemcpy2DAsync(c->hist.data(), sizeof(double), w.hist, (size_t)ns * sizeof(double),
+                          sizeof(double), (size_t)it0 + 1, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->stats.pcg_iters = *std::max_element(c->last_iters.begin(), c->last_iters.end());
+  c->stats.pcg_relres = *std::max_element(c->last_relres.begin(), c->last_relres.end());
+  c->stats.t_solve_ms = now_ms() - t0;
+  return status;
+}
+
 int solve_all(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit) {
   HIPCHK(hipSetDevice(c->opt.device));
   REQUIRE(b && x && rtol > 0 && maxit >= 0, "bad solve arguments");
@@ -2221,52 +2285,64 @@ int solve_all(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxi
     if (c->gexec) HIPCHK(hipGraphExecDestroy(c->gexec));
     c->gexec = nullptr;
   }
-  // r = b - A x, rr0 per segment
-  launch_spmv_chunk(s, c->nch, c->spmv_sg, c->ch_lo.p, c->ch_hi.p, c->rowptr.p, c->col.p, c->val.p,
-                    xx, c->q.p, c->partial.p);
-  launch_residual_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, bb, c->q.p, c->r.p, c->partial.p);
-  launch_seg_reduce(s, ns, c->seg_ch.p, c->partial.p, c->segD.p, c->segI.p, PCG_R_RR0, rtol, maxit,
-                    c->hist_d.p);
-  apply_prec(c, c->r.p, c->z.p, s);
-  launch_dot_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, c->r.p, c->z.p, c->partial.p);
-  launch_seg_reduce(s, ns, c->seg_ch.p, c->partial.p, c->segD.p, c->segI.p, PCG_R_RZ0, 0.0, maxit,
-                    c->hist_d.p);
-  launch_update_p_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, c->ch_seg.p, c->z.p, c->p.p, c->segD.p, 1);
-  HIPCHK(hipGetLastError());
-  int done_its = 0;
-  while (any_running(c) && done_its < maxit) {
-    run_chunk(c, xx, bb, maxit);
-    HIPCHK(hipGetLastError());
-    done_its += PCG_CHUNK;
+  const int status = pcg_run(c, bb, xx, rtol, maxit, ctx_bufs(c), true, t0);
+  if (!xdev) {
+    HIPCHK(hipMemcpyAsync(x, xx, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
   }
-  if (!xdev) HIPCHK(hipMemcpyAsync(x, xx, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  std::vector<double> D = c->segD.download(s);
-  std::vector<int> I = c->segI.download(s);
-  c->last_iters.assign(ns, 0);
-  c->last_relres.assign(ns, 0.0);
-  int status = MSDD_OK;
-  bool bad = false;
-  for (int q = 0; q < ns; ++q) {
-    const int act = I[q * PCG_SI + PCG_ACTIVE];
-    c->last_iters[q] = act == PCG_RUNNING ? I[q * PCG_SI + PCG_IT] : I[q * PCG_SI + PCG_ITERS];
-    const double rr0 = D[q * PCG_SD + PCG_RR0];
-    c->last_relres[q] = rr0 > 0 ? std::sqrt(D[q * PCG_SD + PCG_RR] / rr0) : 0.0;
-    if (act == PCG_BREAKDOWN) bad = true;
-    else if (act != PCG_CONVERGED) status = MSDD_ENOCONV;
-  }
-  REQUIRE(!bad, "PCG produced a non-finite value (breakdown or non-finite input)");
-  // residual history of segment 0
-  const int it0 = c->last_iters[0];
-  std::vector<double> hd = c->hist_d.download(s);
-  c->hist.assign(it0 + 1, 0.0);
-  for (int k = 0; k <= it0; ++k) c->hist[k] = hd[(size_t)k * ns];
-  c->stats.pcg_iters = *std::max_element(c->last_iters.begin(), c->last_iters.end());
-  c->stats.pcg_relres = *std::max_element(c->last_relres.begin(), c->last_relres.end());
-  c->stats.t_solve_ms = now_ms() - t0;
   return status;
 }
 
 }  // namespace
+
+int msdd_solve_noalloc(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit,
+                       int32_t* iters, double* relres) {
+  if (!c) return MSDD_EINVAL;
+  if (!c->ready)
+    return code_for(c, MsddError{MSDD_ESTATE, "msdd_solve_noalloc before a successful setup"});
+  try {
+    HIPCHK(hipSetDevice(c->opt.device));
+    REQUIRE(b && x && rtol > 0 && maxit >= 0, "bad solve arguments");
+    REQUIRE(is_device_ptr(b) && is_device_ptr(x), "msdd_solve_noalloc needs device pointers for b and x");
+    const double t0 = now_ms();
+    const int64_t n = c->n;
+    const int ns = c->nseg;
+    // carve the buffers from the device's scratch array, each 256-byte aligned
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t b_vec = up((size_t)n * sizeof(double));
+    const size_t b_part = up((size_t)std::max(c->nch, 1) * sizeof(double));
+    const size_t b_sd = up((size_t)ns * PCG_SD * sizeof(double));
+    const size_t b_hist = up((size_t)(maxit + 1) * ns * sizeof(double));
+    const size_t b_si = up((size_t)ns * PCG_SI * sizeof(int));
+    const size_t need = 4 * b_vec + b_part + b_sd + b_hist + b_si;
+    if (need > MSDD_NOALLOC_SCRATCH_BYTES)
+      throw MsddError{MSDD_EINVAL, "msdd_solve_noalloc: needs " + std::to_string(need) +
+                                       " bytes of scratch, the limit is " +
+                                       std::to_string((size_t)MSDD_NOALLOC_SCRATCH_BYTES)};
+    unsigned char* base = static_cast<unsigned char*>(noalloc_scratch(c->opt.device));
+    REQUIRE(base, "scratch memory of this device not initialised");
+    PcgBufs w;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { unsigned char* q = base + off; off += bytes; return q; };
+    w.r = reinterpret_cast<double*>(take(b_vec));
+    w.z = reinterpret_cast<double*>(take(b_vec));
+    w.p = reinterpret_cast<double*>(take(b_vec));
+    w.q = reinterpret_cast<double*>(take(b_vec));
+    w.partial = reinterpret_cast<double*>(take(b_part));
+    w.segD = reinterpret_cast<double*>(take(b_sd));
+    w.hist = reinterpret_cast<double*>(take(b_hist));
+    w.segI = reinterpret_cast<int*>(take(b_si));
+    // every buffer is written before it is read (the first reductions set the CG scalars
+    // and states of each problem), so nothing needs clearing
+    const int st = pcg_run(c, b, x, rtol, maxit, w, false, t0);
+    if (iters) *iters = c->stats.pcg_iters;
+    if (relres) *relres = c->stats.pcg_relres;
+    if (st == MSDD_ENOCONV) return code_for(c, MsddError{MSDD_ENOCONV, "PCG reached maxit"});
+    return st;
+  } catch (const MsddError& e) {
+    return code_for(c, e);
+  }
+}
 
 int msdd_solve(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit,
                int32_t* iters, double* relres) {

@@ -4,8 +4,11 @@
 //   P_L = I, P_{l-1} = P_l Phi_l.
 // Reductions are two-pass (fixed grid of partial sums, then one workgroup in a
 // fixed order), so results are bitwise repeatable.
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
+#include "msdd.h"
 #include "trsv.h"
 
 // ---------------------------------------------------------------------------
@@ -490,4 +493,37 @@ void launch_apply_fine_up(hipStream_t s, i64 n, const i64* dinc_ptr, const i32* 
                           const double* zc, double* z) {
   hipLaunchKernelGGL(k_apply_fine_up, dim3(grid_for(n)), dim3(MSDD_WG), 0, s, n, dinc_ptr,
                      dinc_sub, dinc_q, doff, msub, moff, phid_off, PhiD, u, zc, z);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch memory of msdd_solve_noalloc: a file-scope device array of fixed size, one copy
+// per device (resident while the library is loaded).  Host code never names the array: its
+// device address is looked up once per device (with that device current) and kept here.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[MSDD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+
+int noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return -1;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return 0;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return -1;
+  }
+  g_scratch_ptr[device] = ptr;
+  return 0;
+}
+
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
