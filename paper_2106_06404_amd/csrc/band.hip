@@ -222,6 +222,119 @@ __global__ void k_band_cholesky(const i32* __restrict__ subs, const i32* __restr
   }
 }
 
+__global__ void k_fill_int(int* __restrict__ p, int n, int v) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Sylvester inertia of M = A + sigma * D A D (with sigma = -eta: abar - eta b), one
+// workgroup per subdomain: the number of negative pivots of its LDL^T factorisation
+// without pivoting, which equals the number of eigenvalues of abar x = lambda b x below
+// eta (congruence; the eigenvalues of b's kernel are infinite).  Same sliding window as
+// k_band_cholesky, with the column scaled by 1/sqrt|pivot| and the trailing update signed.
+// A pivot at or below 1e-13 times the column's original diagonal makes the count unreliable
+// (rounding could flip its sign): neg[i] = -1 then, else the count.  Nothing is stored.
+// ---------------------------------------------------------------------------
+__global__ void k_band_inertia(const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
+                               const i64* __restrict__ src_off, const double* __restrict__ src,
+                               const i64* __restrict__ dv_off, const double* __restrict__ dv,
+                               double sigma, int* __restrict__ neg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = blockIdx.x;
+  const int n = n_arr[i];
+  const int b = b_arr[i];
+  const int w = b + 1;
+  double* W = reinterpret_cast<double*>(smem_raw);  // w*w
+  double* lcol = W + (size_t)w * w;                 // w
+  double* ain = lcol + w;                           // CHOL_RB*w  upcoming input columns
+  double* dgi = ain + (size_t)CHOL_RB * w;          // CHOL_RB    original diagonals
+  const double* A = src + src_off[i];
+  const double* d = dv + dv_off[i];
+  auto in_val = [&](int c, int t) -> double {
+    return A[(i64)c * w + t] * (1.0 + sigma * d[c + t] * d[c]);
+  };
+  for (int c = 0; c < w && c < n; ++c)
+    for (int t = threadIdx.x; t < w; t += blockDim.x) W[c * w + t] = (c + t < n) ? in_val(c, t) : 0.0;
+  // this thread's items (p, q), 1 <= q <= p <= b, of the trailing triangle (as in
+  // k_band_cholesky)
+  const int nitems = b * (b + 1) / 2;
+  const bool fast = nitems <= CHOL_MAXI * (int)blockDim.x;
+  int ip[CHOL_MAXI], iq[CHOL_MAXI], ni = 0;
+  if (fast)
+    for (int t = threadIdx.x; t < nitems; t += blockDim.x) {
+      int p = (int)((1.0 + sqrt(1.0 + 8.0 * t)) * 0.5);
+      while (p * (p - 1) / 2 > t) --p;
+      while ((p + 1) * p / 2 <= t) ++p;
+      ip[ni] = p;
+      iq[ni] = t - p * (p - 1) / 2 + 1;
+      ++ni;
+    }
+  int count = 0;
+  bool unreliable = false;
+  int slot = 0;
+  for (int j = 0; j < n; ++j, slot = (slot + 1 == w) ? 0 : slot + 1) {
+    if (j % CHOL_RB == 0) {
+      if (j > 0) lds_barrier();
+      for (int e = threadIdx.x; e < CHOL_RB * w; e += blockDim.x) {
+        const int c = j + w + e / w, t = e % w;
+        ain[e] = (c < n && c + t < n) ? in_val(c, t) : 0.0;
+      }
+      for (int t = threadIdx.x; t < CHOL_RB; t += blockDim.x) dgi[t] = (j + t < n) ? in_val(j + t, 0) : 0.0;
+    }
+    lds_barrier();
+    const double ajj = W[slot * w];
+    if (!(fabs(ajj) > 1e-13 * fabs(dgi[j % CHOL_RB]))) {
+      unreliable = true;
+      break;
+    }
+    if (ajj < 0.0) ++count;
+    const double sg = ajj < 0.0 ? -1.0 : 1.0;
+    const double rl = 1.0 / sqrt(fabs(ajj));
+    for (int t = threadIdx.x; t < w; t += blockDim.x) lcol[t] = (j + t < n && t > 0) ? W[slot * w + t] * rl : 0.0;
+    lds_barrier();
+    if (fast) {
+#pragma unroll
+      for (int u = 0; u < CHOL_MAXI; ++u) {
+        if (u >= ni) break;
+        const int pp = ip[u], qq = iq[u];
+        if (j + pp < n) {
+          int sl = slot + qq;
+          if (sl >= w) sl -= w;
+          W[sl * w + (pp - qq)] -= sg * lcol[pp] * lcol[qq];
+        }
+      }
+    } else {
+      for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
+        const int p = t / b + 1, q = t % b + 1;
+        if (q <= p && j + p < n) W[((slot + q) % w) * w + (p - q)] -= sg * lcol[p] * lcol[q];
+      }
+    }
+    if (j + w < n)
+      for (int t = threadIdx.x; t < w; t += blockDim.x) W[slot * w + t] = ain[(j % CHOL_RB) * w + t];
+  }
+  if (threadIdx.x == 0) neg[i] = unreliable ? -1 : count;
+}
+
+// Inertia counts of every subdomain (k_band_inertia); subdomains whose window does not fit
+// in LDS get -1 (no count).
+void launch_band_inertia(hipStream_t s, int nsubs, int bmax, const i32* n_arr, const i32* b_arr,
+                         const i64* src_off, const double* src, const i64* dv_off,
+                         const double* dv, double sigma, int* neg) {
+  if (nsubs == 0) return;
+  const size_t w = (size_t)bmax + 1;
+  const size_t lds = (w * w + w + CHOL_RB * w + CHOL_RB) * sizeof(double);
+  if (lds > 160 * 1024) {
+    hipLaunchKernelGGL(k_fill_int, dim3((nsubs + 255) / 256), dim3(256), 0, s, neg, nsubs, -1);
+    return;
+  }
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_band_inertia,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_band_inertia, dim3(nsubs), dim3(MSDD_WG), lds, s, n_arr, b_arr, src_off, src,
+                     dv_off, dv, sigma, neg);
+}
+
 // ---------------------------------------------------------------------------
 // Same factorisation for half-bandwidths whose window does not fit in LDS:
 // S is first written to Lc (lower band) and factorised in place, right-looking,

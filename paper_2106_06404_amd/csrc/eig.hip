@@ -485,9 +485,10 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
 // backward error at which the pair that certifies the count is accepted (its relative
 // eigenvalue error then stays near 1e-11)
 constexpr double CERT_TOL = 1e-11;
-// A pair whose Ritz value no longer moves (1e-14 relative between iterations) is at the
-// rounding floor of its pencil; it is accepted if its backward error is within 1e6 times
-// the tolerance (1e-8 at the default 1e-14).  The host counts such pairs.
+// A pair whose Ritz value no longer moves (1e-14 relative between iterations) and whose
+// backward error no longer falls (by more than half per iteration) is at the rounding floor
+// of its pencil; it is accepted if that backward error is within 1e6 times the tolerance
+// (1e-8 at the default 1e-14).  The host counts such pairs.
 constexpr double STAG_FACTOR = 1e6;
 // The Krylov-Weinstein interval shows that an eigenvalue lies near the certifying Ritz
 // value, not that none lies above it in nu (Ritz values bound eigenvalues from below), so
@@ -505,7 +506,8 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
                             int* __restrict__ mcount, double* __restrict__ lam_out,
                             double* __restrict__ res_out, int Kmax_allowed,
                             const i32* __restrict__ rankb, const double* __restrict__ normS,
-                            double* __restrict__ nu_prev, const double* __restrict__ gs_diag) {
+                            double* __restrict__ nu_prev, const double* __restrict__ gs_diag,
+                            const int* __restrict__ inertia) {
   const int i = blockIdx.x;
   if (status[i] != ST_RUNNING) return;
   __shared__ double sh_res[64], sh_lam[64], sh_stag[64], sh_kwup[64];
@@ -521,12 +523,17 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
     const double rel = (nv > 0 && ss > 0) ? sqrt(sr) / (nv * normS[i] * sqrt(ss)) : 0.0;
     const double lv = nv > 0 ? 1.0 / nv - sigma : INFINITY;
     const double np = nu_prev[(i64)i * K + tid];
+    const double rp = res_out[(i64)i * K + tid];  // this column's backward error last time
     res_out[(i64)i * K + tid] = rel;
     lam_out[(i64)i * K + tid] = lv;
     nu_prev[(i64)i * K + tid] = nv;
     sh_res[tid] = rel;
     sh_lam[tid] = lv;
-    sh_stag[tid] = (rel <= fmax(STAG_FACTOR * tol, CERT_TOL) && fabs(nv - np) <= 1e-14 * fabs(nv)) ? 1.0 : 0.0;
+    // at the rounding floor: the Ritz value has stopped moving (its error is about the
+    // square of the vector's) and so has the backward error (while the vector still
+    // converges it falls by the convergence factor every iteration)
+    sh_stag[tid] = (rel <= fmax(STAG_FACTOR * tol, CERT_TOL) && fabs(nv - np) <= 1e-14 * fabs(nv) &&
+                    rel >= 0.5 * rp) ? 1.0 : 0.0;
     // Krylov-Weinstein: the previous Ritz pair (np, x) of this column, x^T S x = 1, has an
     // eigenvalue of S^{-1} b within eps = ||S^{-1} b x - np x||_S, and eps^2 = y^T S y - np^2
     // with y = S^{-1} b x (this iteration's block).  The rounding of y^T S y is covered by a
@@ -542,6 +549,10 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
     const int kb = min(K, rankb[i]);  // usable columns
     int m = 0;
     while (m < kb && sh_lam[m] < eta) ++m;
+    // Ritz values bound the eigenvalues from above in lambda, so m never exceeds the true
+    // count; when it equals the inertia count of abar - eta b, no eigenvalue below eta is
+    // missing and the next pair need not converge
+    const bool by_inertia = inertia != nullptr && inertia[i] >= 0 && inertia[i] == m && m < kb;
     if (nev_max > 0 && m > nev_max) m = nev_max;
     const int guard = 2;
     bool grow = (m + 1 + guard > kb) && (kb < rankb[i]) && (K < Kmax_allowed);
@@ -552,11 +563,12 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
     // accepted at CERT_TOL, below the accuracy asked of reported eigenvalues
     for (int a = 0; a < need; ++a) {
       if (a == m && sh_lam[a] >= eta) {
-        // the certifying pair: accepted at CERT_TOL, or once the Krylov-Weinstein interval
-        // of its previous iterate lies entirely on the lambda > eta side (its eigenvalue
-        // then certifies the count whatever its remaining error)
+        // the certifying pair: not needed when the inertia certifies the count; else
+        // accepted at CERT_TOL, or once the Krylov-Weinstein interval of its previous
+        // iterate lies entirely on the lambda > eta side (its eigenvalue then certifies
+        // the count whatever its remaining error)
         const bool kw = it >= KW_MIN_IT && sh_kwup[a] < 1.0 / (eta + sigma);
-        ok = ok && (sh_res[a] <= fmax(tol, CERT_TOL) || sh_stag[a] > 0.0 || kw);
+        ok = ok && (by_inertia || sh_res[a] <= fmax(tol, CERT_TOL) || sh_stag[a] > 0.0 || kw);
       } else {
         ok = ok && (sh_res[a] <= tol || sh_stag[a] > 0.0);
       }
@@ -698,14 +710,14 @@ void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, in
                        double tol, int maxit, int* status, int* iters, int* mcount,
                        double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
                        const double* normS, double* nu_prev, double* part, int nsplit,
-                       const double* gs_diag) {
+                       const double* gs_diag, const int* inertia) {
   constexpr int TR = 16;
   size_t lds = (size_t)K * K * sizeof(double) + 3 * TR * K * sizeof(double);
   hipLaunchKernelGGL((k_eig_update<double, TR>), dim3(P, nsplit), dim3(MSDD_WG), lds, s, nb, kvoff,
                      K, C, nu, Y, Z, X, BX, SX, status, part, nsplit);
   hipLaunchKernelGGL(k_eig_judge, dim3(P), dim3(64), 0, s, K, nu, part, nsplit, sigma, eta,
                      nev_max, tol, maxit, status, iters, mcount, lam_out, res_out, Kmax_allowed,
-                     rankb, normS, nu_prev, gs_diag);
+                     rankb, normS, nu_prev, gs_diag, inertia);
 }
 
 void launch_eig_finalize(hipStream_t s, int P, const i32* nb, const i64* voff, const i64* kvoff,

@@ -78,7 +78,7 @@ void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, in
                        double tol, int maxit, int* status, int* iters, int* mcount,
                        double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
                        const double* normS, double* nu_prev, double* part, int nsplit,
-                       const double* gs_diag);
+                       const double* gs_diag, const int* inertia);
 void launch_row_norm(hipStream_t s, int P, const i64* voff, int ell_w, const i32* ell_col,
                      const double* ell_val, const double* dv, double sigma, double* normS);
 void launch_eig_finalize(hipStream_t s, int P, const i32* nb, const i64* voff, const i64* kvoff,
@@ -166,6 +166,11 @@ void launch_apply_coarsest(hipStream_t s, int nt, int nmax, const i64* zoff, con
 void launch_apply_coarse_up(hipStream_t s, int P, const i32* nown, const i64* own_ptr,
                             const i32* own_idx, const i32* msub, const i64* yoff, const double* Y,
                             const i64* moff, const double* zc, double* zl);
+// Number of eigenvalues below eta of each subdomain's pencil, by the inertia of
+// abar + sigma D abar D (sigma = -eta); -1 where it could not be determined.
+void launch_band_inertia(hipStream_t s, int nsubs, int bmax, const i32* n_arr, const i32* b_arr,
+                         const i64* src_off, const double* src, const i64* dv_off,
+                         const double* dv, double sigma, int* neg);
 // Scratch array of msdd_solve_noalloc (pcg.hip): noalloc_scratch_init looks up its
 // device address for `device` (which must be current), once; noalloc_scratch returns it
 // (nullptr before the lookup).  Returns 0 or -1.

@@ -229,6 +229,7 @@ struct FineLevel {
   std::vector<int32_t> h_nd, h_bd, h_dpos, h_dglob, h_rankb;
   std::vector<int64_t> h_doff, h_dboff;
   DVec<int32_t> nd, bd, dpos, dglob, drow_sub, rankb;
+  DVec<int> inertia;  // eigenvalues below eta per subdomain (-1: unknown)
   DVec<int64_t> doff, dboff;
   DVec<double> Dband, LDc, LDr;
   DVec<float> LDc32, LDr32;  // single-precision mode: factor of diag(sc) A_i diag(sc)
@@ -393,6 +394,8 @@ struct msdd_ctx {
   hipStream_t gstream = nullptr;  // capture stream for the iteration graphs
   hipStream_t ustream = nullptr;  // uploads of the patch planning that overlaps the eigensolves
   hipStream_t cstream = nullptr;  // coarse levels of the preconditioner, beside the fine solve
+  hipStream_t istream = nullptr;  // inertia counts, beside the setup's factorisations
+  hipEvent_t iev = nullptr;
   hipEvent_t cev0 = nullptr, cev1 = nullptr;
   hipEvent_t gev0 = nullptr, gev1 = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -431,6 +434,8 @@ struct msdd_ctx {
     if (cev0) (void)hipEventDestroy(cev0);
     if (cev1) (void)hipEventDestroy(cev1);
     if (cstream) (void)hipStreamDestroy(cstream);
+    if (istream) (void)hipStreamDestroy(istream);
+    if (iev) (void)hipEventDestroy(iev);
   }
 };
 
@@ -725,6 +730,8 @@ void ensure_side_stream(msdd_ctx* c) {
   HIPCHK(hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&c->cev0, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&c->cev1, hipEventDisableTiming));
+  HIPCHK(hipStreamCreateWithFlags(&c->istream, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&c->iev, hipEventDisableTiming));
 }
 
 void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
@@ -767,6 +774,18 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   st_dchol.zero(s);
   HIPCHK(hipEventRecord(c->cev0, s));
   HIPCHK(hipStreamWaitEvent(s2, c->cev0, 0));
+  // the number of eigenvalues below eta of every pencil (Sylvester inertia of
+  // abar - eta b), on a third stream beside both factorisations; the eigensolver stops
+  // once its selected pairs converge and their count equals it
+  HIPCHK(hipStreamWaitEvent(c->istream, c->cev0, 0));
+  F.inertia.alloc(P);
+  {
+  ProfScope ps(c, PR_CHOL, F.s_band * 8.0, F.s_nbb * (F.bw_max + 2.0), c->istream);
+  launch_band_inertia(c->istream, P, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.band.p,
+                      F.gs.voff.p, F.dv.p, -c->eta, F.inertia.p);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(c->iev, c->istream));
   const bool mixed = c->opt.precision == MSDD_MIXED;
   if (mixed) {
     // single precision: factor diag(sc) A_i diag(sc), sc = diag(A_i)^{-1/2}
@@ -843,6 +862,7 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   }
   HIPCHK(hipEventRecord(c->cev1, s2));
   HIPCHK(hipStreamWaitEvent(s, c->cev1, 0));
+  HIPCHK(hipStreamWaitEvent(s, c->iev, 0));
   check_status(status.download(s), "Cholesky of abar + sigma*b");
   if (mixed) {
     check_status(st_scale.download(s), "Dirichlet matrix diagonal");
@@ -947,6 +967,7 @@ void fine_eigensolve(msdd_ctx* c) {
     E.nu.alloc((size_t)P * K);
     E.lam.alloc((size_t)P * K);
     E.res.alloc((size_t)P * K);
+    E.res.zero(s);
     E.mcount.alloc(P);
     E.mcount.zero(s);
     DVec<double> nu_prev, normS, gsd;
@@ -1001,7 +1022,7 @@ void fine_eigensolve(msdd_ctx* c) {
         launch_eig_update(s, P, F.gs.n.p, dkvoff.p, K, Cm.p, E.nu.p, Y.p, Z.p, E.X.p, BX.p, SX.p,
                           c->sigma, c->eta, o.nev_max, o.eig_tol, maxit, status.p, iters.p,
                           E.mcount.p, E.lam.p, E.res.p, 64, F.rankb.p, normS.p, nu_prev.p,
-                          upart.p, nsplit, gsd.p);
+                          upart.p, nsplit, gsd.p, F.inertia.p);
       }
       HIPCHK(hipGetLastError());
       if (it >= 3 && (it % 2 == 1 || it == maxit - 1)) {
