@@ -92,7 +92,7 @@ def rlib():
         L = ctypes.CDLL(_ROUT)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
-        L.oracle_refine.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp,
+        L.oracle_refine.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip,
                                     ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp, dp]
         L.oracle_refine.restype = ctypes.c_int
         L.oracle_rayleigh.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp,
@@ -103,7 +103,7 @@ def rlib():
 
 
 def refine_pairs(eloc: np.ndarray, emat: np.ndarray, d: np.ndarray, X0: np.ndarray,
-                 iters: int = 3):
+                 iters: int = 3, bmask: np.ndarray = None):
     """Binary128 Rayleigh-Ritz + subspace iteration of abar x = lambda D abar D x
     (oracle/refine.c).  eloc: (ne, k) local dof index or -1; emat: (ne, k, k);
     d: weights; X0: (n, kv) start vectors.  Returns (lam_hi, lam_lo, bound, cond, X),
@@ -120,7 +120,9 @@ def refine_pairs(eloc: np.ndarray, emat: np.ndarray, d: np.ndarray, X0: np.ndarr
     cd = np.zeros(kv)
     X = np.zeros((n, kv), order="F")
     ip = ctypes.POINTER(ctypes.c_int)
-    rc = rlib().oracle_refine(n, ne, kk, el.ctypes.data_as(ip), _ptr(em), _ptr(dd), kv,
+    bm = None if bmask is None else np.ascontiguousarray(bmask, dtype=np.int32)
+    rc = rlib().oracle_refine(n, ne, kk, el.ctypes.data_as(ip), _ptr(em), _ptr(dd),
+                              None if bm is None else bm.ctypes.data_as(ip), kv,
                               x0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), iters,
                               _ptr(hi), _ptr(lo), _ptr(bd), _ptr(cd),
                               X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))

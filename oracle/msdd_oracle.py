@@ -96,6 +96,33 @@ def neumann_matrix(elem_dofs: np.ndarray, elem_mat: np.ndarray, elems: np.ndarra
     return Ab
 
 
+def overlap_elements(sub_elems: List[np.ndarray], i: int) -> np.ndarray:
+    """The elements of T_{h,i} that also belong to some other subdomain's T_{h,j}
+    (the set on which the original GenEO right-hand side b^2 is assembled, Sec. 3.4)."""
+    n_elem = int(max(int(e.max()) for e in sub_elems if len(e))) + 1
+    cnt = np.zeros(n_elem, np.int64)
+    for e in sub_elems:
+        cnt[e] += 1
+    el = sub_elems[i]
+    return el[cnt[el] >= 2]
+
+
+def gevp_rhs(alpha: int, Ab: np.ndarray, d: np.ndarray, Ao: Optional[np.ndarray] = None):
+    """The GEVP right-hand side matrix b^alpha on the local Neumann space (Sec. 3.4):
+    alpha = 1: abar(chi u, chi v)            -> D abar D;
+    alpha = 2: a-ring(chi u, chi v)          -> D Ao D, Ao = sum of a_tau over the overlap
+                                                elements (the original GenEO choice);
+    alpha = 3: abar(u - chi u, v - chi v)    -> (I - D) abar (I - D)."""
+    if alpha == 1:
+        return d[:, None] * Ab * d[None, :]
+    if alpha == 2:
+        return d[:, None] * Ao * d[None, :]
+    if alpha == 3:
+        e = 1.0 - d
+        return e[:, None] * Ab * e[None, :]
+    raise ValueError(alpha)
+
+
 def elements_matrix(n: int, elem_dofs: np.ndarray, elem_mat: np.ndarray,
                     elems: np.ndarray) -> sp.csr_matrix:
     """sum_{tau in elems} a_tau as a sparse n x n matrix on the free dofs."""
@@ -121,14 +148,16 @@ class GevpResult:
     V: Optional[np.ndarray] = None   # the first m + extra_vec eigenvectors, S-orthonormal
 
 
-def gevp_definite(Ab: np.ndarray, Bm: np.ndarray, eta: float, extra_vec: int = 0) -> GevpResult:
+def gevp_definite(Ab: np.ndarray, Bm: np.ndarray, eta: float, extra_vec: int = 0,
+                  nev: int = 0) -> GevpResult:
     """abar x = lambda b x with ker abar cap ker b = {0}: S = abar + b is SPD.
 
     S = L L^T; C = L^{-1} b L^{-T}; C = Y diag(mu) Y^T (Jacobi);
     lambda = 1/mu - 1 (mu = 0 <-> lambda = inf); x = L^{-T} y; select
     lambda < eta (strict); b-normalise (x^T S x = 1 so x^T b x = mu).
     extra_vec > 0 also returns the eigenvectors of the m + extra_vec largest mu
-    (x^T S x = 1), e.g. as start vectors of the binary128 refinement.
+    (x^T S x = 1), e.g. as start vectors of the binary128 refinement.  nev > 0 selects
+    the nev smallest finite eigenvalues instead of those below eta (fixed n_ev, Sec. 5).
     """
     S = Ab + Bm
     L = cholesky(S)
@@ -139,7 +168,7 @@ def gevp_definite(Ab: np.ndarray, Bm: np.ndarray, eta: float, extra_vec: int = 0
     mu = mu[::-1]
     Y = Y[:, ::-1]
     back = lambda Yc: sla.solve_triangular(L.T, Yc, lower=False)  # noqa: E731
-    g = _select(mu, back, Y, eta)
+    g = _select(mu, back, Y, eta, nev)
     if extra_vec > 0:
         g.V = back(Y[:, :min(g.m + extra_vec, Y.shape[1])])
     return g
@@ -172,25 +201,35 @@ class RefinedPairs:
         return 2.0 ** -53 * self.cond
 
 
-def refine_pairs(elem_dofs, elem_mat, elems, dofs, d, V0, iters: int = 3) -> RefinedPairs:
+def refine_pairs(elem_dofs, elem_mat, elems, dofs, d, V0, iters: int = 3,
+                 geneo_rhs: int = 1, overlap: Optional[np.ndarray] = None) -> RefinedPairs:
     """Eigenpairs of abar x = lambda (D abar D) x (Sec. 2.3 GEVP, b^1 of Sec. 3.4, through
     the transformation of the Sec. 3.3 lemma) refined in binary128 from the start
     vectors V0 (columns; e.g. the oracle's FP64 eigenvectors of the smallest lambda):
     Rayleigh-Ritz on span(V0), then `iters` steps of subspace iteration with
-    (abar + b)^{-1} b, each followed by Rayleigh-Ritz (oracle/refine.c)."""
+    (abar + b)^{-1} b, each followed by Rayleigh-Ritz (oracle/refine.c).  geneo_rhs
+    selects b^alpha (alpha = 2 needs `overlap`, the subdomain's overlap elements)."""
     eloc, emat = local_elements(elem_dofs, elem_mat, elems, dofs)
-    hi, lo, bd, cd, X = _dense.refine_pairs(eloc, emat, d, V0, iters)
+    bmask = None
+    dd = d
+    if geneo_rhs == 2:
+        bmask = np.isin(elems, overlap).astype(np.int32)
+    elif geneo_rhs == 3:
+        dd = 1.0 - d
+    hi, lo, bd, cd, X = _dense.refine_pairs(eloc, emat, dd, V0, iters, bmask)
     return RefinedPairs(hi, lo, bd, cd, X)
 
 
-def _select(mu, back, Y, eta):
+def _select(mu, back, Y, eta, nev=0):
     mu = np.where(mu > MU_ZERO, mu, 0.0)
     pos = mu > 0
     lam_all = np.full(mu.shape, np.inf)
     lam_all[pos] = 1.0 / mu[pos] - 1.0
     lam_all = np.maximum(lam_all, 0.0)
-    sel = lam_all < eta
-    m = int(sel.sum())
+    if nev > 0:
+        m = int(min(nev, np.sum(np.isfinite(lam_all))))
+    else:
+        m = int(np.sum(lam_all < eta))
     X = back(Y[:, :m]) if m else np.zeros((Y.shape[0], 0))
     if m:
         X = X / np.sqrt(mu[:m])[None, :]
@@ -256,11 +295,13 @@ class Oracle:
 
     def __init__(self, prob, eta: Optional[float] = None, verbose: bool = False,
                  only_fine: Optional[List[int]] = None, fine_vectors: int = 0,
-                 workers: int = 1):
+                 workers: int = 1, geneo_rhs: int = 1, nev_fixed: int = 0):
         """fine_vectors > 0 keeps, per finest-level subdomain, the S-orthonormal
         eigenvectors of the m + fine_vectors smallest lambda (in fine_vecs);
         workers > 1 solves the finest-level subdomains in that many processes (the
-        results do not depend on it)."""
+        results do not depend on it).  geneo_rhs (1, 2, 3) is the finest level's GEVP
+        right-hand side b^alpha (Sec. 3.4); nev_fixed > 0 selects that many eigenvectors per
+        finest-level subdomain instead of those below eta.  Coarse levels use b^1 and eta."""
         self.prob = prob
         self.eta = prob.eta if eta is None else eta
         self.L = prob.n_levels - 1
@@ -272,6 +313,8 @@ class Oracle:
         self.verbose = verbose
         self.fine_vectors = fine_vectors
         self.workers = workers
+        self.geneo_rhs = geneo_rhs
+        self.nev_fixed = nev_fixed
         self.fine_vecs: Dict[int, np.ndarray] = {}
         self._setup(only_fine)
 
@@ -283,8 +326,12 @@ class Oracle:
         el = p.sub_elems(i)
         dm = dirichlet_mask(p.elem_dofs, el, dofs)
         Ab = neumann_matrix(p.elem_dofs, p.elem_mat, el, dofs)
-        Bm = d[:, None] * Ab * d[None, :]
-        g = gevp_definite(Ab, Bm, self.eta, extra_vec=self.fine_vectors)
+        Ao = None
+        if self.geneo_rhs == 2:
+            subs = [p.sub_elems(j) for j in range(p.n_sub)]
+            Ao = neumann_matrix(p.elem_dofs, p.elem_mat, overlap_elements(subs, i), dofs)
+        Bm = gevp_rhs(self.geneo_rhs, Ab, d, Ao)
+        g = gevp_definite(Ab, Bm, self.eta, extra_vec=self.fine_vectors, nev=self.nev_fixed)
         Ad = self.A[dofs[dm]][:, dofs[dm]].toarray()   # A_i = R_i A R_i^T
         return g, d[:, None] * g.X, cholesky(Ad)
 

@@ -22,8 +22,8 @@
  *     operator S^{-1} b is self-adjoint, and this is ||S^{-1} b v - mu v||_S, so
  *     some eigenvalue mu* lies within it (Krylov-Weinstein); for lambda the
  *     bound is bound / (mu (mu - bound)).
- *   - cond: with x = v / sqrt(mu) (x^T b x = 1), |x|^T E |x| + lambda |Dx|^T E |Dx|,
- *     E = sum over the elements of |a_tau| entrywise.  To first order, entrywise
+ *   - cond: with x = v / sqrt(mu) (x^T b x = 1), |x|^T E |x| + lambda |Dx|^T Eb |Dx|,
+ *     E = sum over the elements of |a_tau| entrywise, Eb the same over b's elements.  To first order, entrywise
  *     relative perturbations of the element matrices of size eps move lambda by at
  *     most eps * cond (lambda = x^T abar x / x^T b x at the eigenvector).  With
  *     eps = 2^-53 this is the part of lambda that FP64 input data already leaves
@@ -139,13 +139,14 @@ static int small_jacobi(int k, q* a, q* V, q* w) {
 
 typedef struct {
   band_t A, L; /* abar; Cholesky factor of S = abar + b */
+  band_t Bo;   /* the matrix inside b = D Bo D (abar itself, or the overlap elements' sum) */
   const q* d;
   int n;
 } pencil_t;
 
 static void apply_b(const pencil_t* P, const q* x, q* y, q* tmp) {
   for (int i = 0; i < P->n; ++i) tmp[i] = P->d[i] * x[i];
-  band_symv(&P->A, tmp, y);
+  band_symv(&P->Bo, tmp, y);
   for (int i = 0; i < P->n; ++i) y[i] *= P->d[i];
 }
 
@@ -254,6 +255,9 @@ static int rayleigh_ritz(const pencil_t* P, int k, q* V, q* mu, q* work) {
 /*
  * n: local dofs; ne elements with kk local dofs each: eloc[ne*kk] (local index or
  * -1 for an eliminated dof), emat[ne*kk*kk] (row-major per element); d[n] weights.
+ * bmask[ne] (may be NULL): the elements whose matrices form the matrix inside
+ * b = D (sum a_tau) D (NULL: all, b = D abar D; the b^2 right-hand side passes the
+ * overlap elements, b^3 passes d = 1 - chi).
  * X0[n*k] (column-major): FP64 start vectors, k >= 1.  iters: subspace steps after
  * the first Rayleigh-Ritz.
  * Outputs (k each, mu descending = lambda ascending): lam_hi + lam_lo = lambda
@@ -262,8 +266,8 @@ static int rayleigh_ritz(const pencil_t* P, int k, q* V, q* mu, q* work) {
  * Returns 0, -1 (S not positive definite), -2 (Rayleigh-Ritz failed), -3 (bad input).
  */
 int oracle_refine(int n, int ne, int kk, const int* eloc, const double* emat, const double* d,
-                  int k, const double* X0, int iters, double* lam_hi, double* lam_lo,
-                  double* lam_bound, double* cond, double* Xout) {
+                  const int* bmask, int k, const double* X0, int iters, double* lam_hi,
+                  double* lam_lo, double* lam_bound, double* cond, double* Xout) {
   if (n <= 0 || k <= 0 || k > n || ne < 0 || kk <= 0) return -3;
   int b = 0;
   for (int e = 0; e < ne; ++e)
@@ -280,7 +284,12 @@ int oracle_refine(int n, int ne, int kk, const int* eloc, const double* emat, co
   const size_t bs = (size_t)n * (b + 1);
   P.A.v = (q*)calloc(bs, sizeof(q));
   P.L.v = (q*)calloc(bs, sizeof(q));
-  q* E = (q*)calloc(bs, sizeof(q)); /* sum of |a_tau| */
+  P.Bo = P.A;
+  if (bmask) {
+    P.Bo.v = (q*)calloc(bs, sizeof(q));
+  }
+  q* E = (q*)calloc(bs, sizeof(q));  /* sum of |a_tau| */
+  q* Eb = bmask ? (q*)calloc(bs, sizeof(q)) : E;  /* the same over b's elements */
   q* dq = (q*)malloc(sizeof(q) * n);
   for (int i = 0; i < n; ++i) dq[i] = d[i];
   P.d = dq;
@@ -293,12 +302,16 @@ int oracle_refine(int n, int ne, int kk, const int* eloc, const double* emat, co
         const size_t o = (size_t)s * (b + 1) + (p - s);
         P.A.v[o] += (q)a;
         E[o] += (q)fabs(a);
+        if (bmask && bmask[e]) {
+          P.Bo.v[o] += (q)a;
+          Eb[o] += (q)fabs(a);
+        }
       }
-  /* S = abar + D abar D */
+  /* S = abar + D Bo D */
   for (int j = 0; j < n; ++j)
     for (int t = 0; t <= b && j + t < n; ++t) {
       const size_t o = (size_t)j * (b + 1) + t;
-      P.L.v[o] = P.A.v[o] + dq[j + t] * P.A.v[o] * dq[j];
+      P.L.v[o] = P.A.v[o] + dq[j + t] * P.Bo.v[o] * dq[j];
     }
   int rc = band_chol(&P.L);
   q* V = NULL;
@@ -347,10 +360,10 @@ int oracle_refine(int n, int ne, int kk, const int* eloc, const double* emat, co
       q c1 = 0, c2 = 0;
       for (int jj = 0; jj < n; ++jj)
         for (int t = 0; t <= b && jj + t < n; ++t) {
-          const q e = E[(size_t)jj * (b + 1) + t];
+          const q e = E[(size_t)jj * (b + 1) + t], eb = Eb[(size_t)jj * (b + 1) + t];
           const q x1 = t1[jj + t] * t1[jj], x2 = dq[jj + t] * t1[jj + t] * dq[jj] * t1[jj];
           c1 += (t == 0 ? 1 : 2) * e * x1;
-          c2 += (t == 0 ? 1 : 2) * e * x2;
+          c2 += (t == 0 ? 1 : 2) * eb * x2;
         }
       cond[j] = (double)(c1 + lam * c2);
       if (Xout)
@@ -359,6 +372,10 @@ int oracle_refine(int n, int ne, int kk, const int* eloc, const double* emat, co
   }
   rc = 0;
 done:
+  if (bmask) {
+    free(P.Bo.v);
+    free(Eb);
+  }
   free(P.A.v);
   free(P.L.v);
   free(E);
