@@ -81,6 +81,15 @@ typedef struct {
   int device;         /* HIP device ordinal */
   void* stream;       /* hipStream_t to launch on; NULL = the legacy default stream */
   int verbose;        /* 1 = print phase timings to stderr */
+  int geneo_rhs;      /* right-hand side of the finest-level GEVP (Sec. 3.4, eq. of the
+                         three forms): 1 = b^1(u,v) = abar(chi u, chi v) (default);
+                         2 = b^2 = the overlap elements' sum a-ring(chi u, chi v) (the
+                         original GenEO choice; overlap elements are those that belong to
+                         another subdomain too); 3 = b^3 = abar(u - chi u, v - chi v).
+                         Coarse levels always use b^1 with their 0/1 masks. */
+  int nev_fixed;      /* 0 = select lambda < eta on the finest level (default); > 0 = select
+                         the nev_fixed smallest eigenvalues per finest-level subdomain (the
+                         fixed-count form of the paper's runs); coarse levels use eta */
 } msdd_options;
 
 typedef struct {

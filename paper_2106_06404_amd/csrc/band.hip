@@ -18,7 +18,9 @@
 // abar_i = sum_{tau in T_i} a_tau, gathered row by row: the thread that owns
 // local row r adds every element contribution (r, c), c <= r, in the fixed
 // order of r's incidence list, so the result is deterministic without atomics.
-// The same pass fills the symmetric ELL copy (full rows) used by b = D abar D.
+// The same pass fills the symmetric ELL copy (full rows) used by b = D abar D, and, when
+// elem_ov is given, the band and ELL copies of the overlap elements' sum (the matrix of the
+// b^2 right-hand side, Sec. 3.4) in band2 / ell_val2.
 // ---------------------------------------------------------------------------
 __global__ void k_neumann_assemble(i64 total_rows, const i32* __restrict__ row_sub,
                                    const i64* __restrict__ voff, const i32* __restrict__ bw,
@@ -28,19 +30,23 @@ __global__ void k_neumann_assemble(i64 total_rows, const i32* __restrict__ row_s
                                    int k, const double* __restrict__ elem_mat,
                                    double* __restrict__ band, int ell_w,
                                    const i32* __restrict__ ell_col, double* __restrict__ ell_val,
-                                   int* __restrict__ status) {
+                                   int* __restrict__ status, const i32* __restrict__ elem_ov,
+                                   double* __restrict__ band2, double* __restrict__ ell_val2) {
   i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total_rows) return;
   const int i = row_sub[g];
   const int r = (int)(g - voff[i]);
   const int b = bw[i];
   double* B = band + boff[i];
+  double* B2 = band2 ? band2 + boff[i] : nullptr;
   const i32* ec = ell_col + g * ell_w;
   double* ev = ell_val + g * ell_w;
+  double* ev2 = ell_val2 ? ell_val2 + g * ell_w : nullptr;
   for (i64 q = inc_ptr[g]; q < inc_ptr[g + 1]; ++q) {
     const i64 slot = inc_slot[q];
     const int a = inc_a[q];
     const int e = slot_elem[slot];
+    const bool ov = elem_ov && elem_ov[e];  // an overlap element (also in the b^2 sum)
     const double* Krow = elem_mat + (i64)e * k * k + (i64)a * k;
     const i32* loc = slot_loc + slot * k;
     for (int bb = 0; bb < k; ++bb) {
@@ -53,11 +59,17 @@ __global__ void k_neumann_assemble(i64 total_rows, const i32* __restrict__ row_s
           status[i] = ST_BADINPUT;
         } else {
           B[(i64)c * (b + 1) + (r - c)] += v;
+          if (ov) B2[(i64)c * (b + 1) + (r - c)] += v;
         }
       }
       int t = 0;
       while (t < ell_w && ec[t] != c) ++t;
-      if (t < ell_w) ev[t] += v; else status[i] = ST_BADINPUT;
+      if (t < ell_w) {
+        ev[t] += v;
+        if (ov) ev2[t] += v;
+      } else {
+        status[i] = ST_BADINPUT;
+      }
     }
   }
 }
@@ -115,7 +127,8 @@ __global__ void k_band_cholesky(const i32* __restrict__ subs, const i32* __restr
                                 const double* __restrict__ src, const i64* __restrict__ dv_off,
                                 const double* __restrict__ dv, double sigma,
                                 const i64* __restrict__ dst_off, T* __restrict__ Lc,
-                                T* __restrict__ Lr, int* __restrict__ status) {
+                                T* __restrict__ Lr, int* __restrict__ status,
+                                const double* __restrict__ src2) {
   // The (b+1) x (b+1) active window lives in LDS (column c in slot c mod (b+1)).  Global
   // traffic is batched: the next CHOL_RB input columns are loaded into an LDS ring once
   // every CHOL_RB steps and the factor columns are staged in a second ring and written
@@ -131,12 +144,13 @@ __global__ void k_band_cholesky(const i32* __restrict__ subs, const i32* __restr
   T* ain = lcol + w;                       // CHOL_RB*w  upcoming input columns
   T* lout = ain + (size_t)CHOL_RB * w;     // CHOL_RB*w  factor columns not yet written
   const double* A = src + src_off[i];
+  const double* A2 = src2 ? src2 + src_off[i] : nullptr;
   const double* d = dv ? dv + dv_off[i] : nullptr;
   T* Lci = Lc + dst_off[i];
   T* Lri = Lr + dst_off[i];
   auto in_val = [&](int c, int t) -> T {
     double a = A[(i64)c * w + t];
-    if (d) a *= 1.0 + sigma * d[c + t] * d[c];
+    if (d) a = A2 ? a + sigma * d[c + t] * d[c] * A2[(i64)c * w + t] : a * (1.0 + sigma * d[c + t] * d[c]);
     return (T)a;
   };
   for (int c = 0; c < w && c < n; ++c)
@@ -239,7 +253,8 @@ __global__ void k_fill_int(int* __restrict__ p, int n, int v) {
 __global__ void k_band_inertia(const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
                                const i64* __restrict__ src_off, const double* __restrict__ src,
                                const i64* __restrict__ dv_off, const double* __restrict__ dv,
-                               double sigma, int* __restrict__ neg) {
+                               double sigma, int* __restrict__ neg,
+                               const double* __restrict__ src2) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = blockIdx.x;
   const int n = n_arr[i];
@@ -251,8 +266,10 @@ __global__ void k_band_inertia(const i32* __restrict__ n_arr, const i32* __restr
   double* dgi = ain + (size_t)CHOL_RB * w;          // CHOL_RB    original diagonals
   const double* A = src + src_off[i];
   const double* d = dv + dv_off[i];
+  const double* A2 = src2 ? src2 + src_off[i] : nullptr;
   auto in_val = [&](int c, int t) -> double {
-    return A[(i64)c * w + t] * (1.0 + sigma * d[c + t] * d[c]);
+    const double a = A[(i64)c * w + t];
+    return A2 ? a + sigma * d[c + t] * d[c] * A2[(i64)c * w + t] : a * (1.0 + sigma * d[c + t] * d[c]);
   };
   for (int c = 0; c < w && c < n; ++c)
     for (int t = threadIdx.x; t < w; t += blockDim.x) W[c * w + t] = (c + t < n) ? in_val(c, t) : 0.0;
@@ -320,7 +337,7 @@ __global__ void k_band_inertia(const i32* __restrict__ n_arr, const i32* __restr
 // in LDS get -1 (no count).
 void launch_band_inertia(hipStream_t s, int nsubs, int bmax, const i32* n_arr, const i32* b_arr,
                          const i64* src_off, const double* src, const i64* dv_off,
-                         const double* dv, double sigma, int* neg) {
+                         const double* dv, double sigma, int* neg, const double* src2) {
   if (nsubs == 0) return;
   const size_t w = (size_t)bmax + 1;
   const size_t lds = (w * w + w + CHOL_RB * w + CHOL_RB) * sizeof(double);
@@ -332,7 +349,7 @@ void launch_band_inertia(hipStream_t s, int nsubs, int bmax, const i32* n_arr, c
     (void)hipFuncSetAttribute((const void*)k_band_inertia,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_band_inertia, dim3(nsubs), dim3(MSDD_WG), lds, s, n_arr, b_arr, src_off, src,
-                     dv_off, dv, sigma, neg);
+                     dv_off, dv, sigma, neg, src2);
 }
 
 // ---------------------------------------------------------------------------
@@ -348,7 +365,8 @@ __global__ void k_band_cholesky_global(const i32* __restrict__ subs, const i32* 
                                        const i64* __restrict__ dv_off,
                                        const double* __restrict__ dv, double sigma,
                                        const i64* __restrict__ dst_off, T* __restrict__ Lc,
-                                       T* __restrict__ Lr, int* __restrict__ status) {
+                                       T* __restrict__ Lr, int* __restrict__ status,
+                                       const double* __restrict__ src2) {
   const int i = subs ? subs[blockIdx.x] : blockIdx.x;
   const int n = n_arr[i];
   const int b = b_arr[i];
@@ -362,7 +380,7 @@ __global__ void k_band_cholesky_global(const i32* __restrict__ subs, const i32* 
     double a = 0.0;
     if (c + dd < n) {
       a = A[t];
-      if (d) a *= 1.0 + sigma * d[c + dd] * d[c];
+      if (d) a = src2 ? a + sigma * d[c + dd] * d[c] * src2[src_off[i] + t] : a * (1.0 + sigma * d[c + dd] * d[c]);
     }
     Li[t] = (T)a;
   }
@@ -507,12 +525,13 @@ void launch_neumann_assemble(hipStream_t s, i64 total_rows, const i32* row_sub, 
                              const i32* bw, const i64* boff, const i64* inc_ptr,
                              const i32* inc_slot, const i32* inc_a, const i32* slot_elem,
                              const i32* slot_loc, int k, const double* elem_mat, double* band,
-                             int ell_w, const i32* ell_col, double* ell_val, int* status) {
+                             int ell_w, const i32* ell_col, double* ell_val, int* status,
+                             const i32* elem_ov, double* band2, double* ell_val2) {
   if (total_rows == 0) return;
   dim3 g((unsigned)((total_rows + MSDD_WG - 1) / MSDD_WG));
   hipLaunchKernelGGL(k_neumann_assemble, g, dim3(MSDD_WG), 0, s, total_rows, row_sub, voff, bw,
                      boff, inc_ptr, inc_slot, inc_a, slot_elem, slot_loc, k, elem_mat, band,
-                     ell_w, ell_col, ell_val, status);
+                     ell_w, ell_col, ell_val, status, elem_ov, band2, ell_val2);
 }
 
 void launch_dirichlet_extract(hipStream_t s, i64 total_rows, const i32* drow_sub,
@@ -529,7 +548,7 @@ template <typename T>
 void launch_band_cholesky(hipStream_t s, int nsubs, const i32* subs, int bmax, const i32* n_arr,
                           const i32* b_arr, const i64* src_off, const double* src,
                           const i64* dv_off, const double* dv, double sigma, const i64* dst_off,
-                          T* Lc, T* Lr, int* status) {
+                          T* Lc, T* Lr, int* status, const double* src2) {
   if (nsubs == 0) return;
   size_t w = (size_t)bmax + 1;
   size_t lds = (w * w + w + 2 * CHOL_RB * w) * sizeof(T);
@@ -538,20 +557,20 @@ void launch_band_cholesky(hipStream_t s, int nsubs, const i32* subs, int bmax, c
       (void)hipFuncSetAttribute((const void*)k_band_cholesky<T>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_band_cholesky<T>, dim3(nsubs), dim3(MSDD_WG), lds, s, subs, n_arr,
-                       b_arr, src_off, src, dv_off, dv, sigma, dst_off, Lc, Lr, status);
+                       b_arr, src_off, src, dv_off, dv, sigma, dst_off, Lc, Lr, status, src2);
   } else {
     hipLaunchKernelGGL(k_band_cholesky_global<T>, dim3(nsubs), dim3(MSDD_WG), 0, s, subs, n_arr,
-                       b_arr, src_off, src, dv_off, dv, sigma, dst_off, Lc, Lr, status);
+                       b_arr, src_off, src, dv_off, dv, sigma, dst_off, Lc, Lr, status, src2);
   }
 }
 template void launch_band_cholesky<double>(hipStream_t, int, const i32*, int, const i32*,
                                            const i32*, const i64*, const double*, const i64*,
                                            const double*, double, const i64*, double*, double*,
-                                           int*);
+                                           int*, const double*);
 template void launch_band_cholesky<float>(hipStream_t, int, const i32*, int, const i32*,
                                           const i32*, const i64*, const double*, const i64*,
                                           const double*, double, const i64*, float*, float*,
-                                          int*);
+                                          int*, const double*);
 
 // Cholesky factor L (column layout Lc[j*w + d] = L(j+d, j)) -> LDL^T factor A =
 // Lt D Lt^T.  Row layout F[j*w + d] = L(j, j-d) / L(j-d, j-d) (d >= 1, 0 before

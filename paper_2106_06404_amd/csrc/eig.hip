@@ -157,7 +157,8 @@ __global__ void __launch_bounds__(256) k_bapply_tile(
 // ||S||_inf estimate per subdomain: max row sum of |abar| (1 + sigma d_r d_c)
 __global__ void k_row_norm(const i64* __restrict__ voff, int ell_w, const i32* __restrict__ ell_col,
                            const double* __restrict__ ell_val, const double* __restrict__ dv,
-                           double sigma, double* __restrict__ normS) {
+                           double sigma, double* __restrict__ normS,
+                           const double* __restrict__ ell_val2) {
   const int i = blockIdx.x;
   const i64 r0 = voff[i], r1 = voff[i + 1];
   double mx = 0.0;
@@ -167,7 +168,8 @@ __global__ void k_row_norm(const i64* __restrict__ voff, int ell_w, const i32* _
     for (int t = 0; t < ell_w; ++t) {
       const int c = ell_col[g * ell_w + t];
       if (c < 0) break;
-      s += fabs(ell_val[g * ell_w + t]) * (1.0 + sigma * dr * dv[r0 + c]);
+      s += ell_val2 ? fabs(ell_val[g * ell_w + t] + sigma * dr * dv[r0 + c] * ell_val2[g * ell_w + t])
+                    : fabs(ell_val[g * ell_w + t]) * (1.0 + sigma * dr * dv[r0 + c]);
     }
     mx = fmax(mx, s);
   }
@@ -507,7 +509,7 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
                             double* __restrict__ res_out, int Kmax_allowed,
                             const i32* __restrict__ rankb, const double* __restrict__ normS,
                             double* __restrict__ nu_prev, const double* __restrict__ gs_diag,
-                            const int* __restrict__ inertia) {
+                            const int* __restrict__ inertia, int nev_fixed) {
   const int i = blockIdx.x;
   if (status[i] != ST_RUNNING) return;
   __shared__ double sh_res[64], sh_lam[64], sh_stag[64], sh_kwup[64];
@@ -548,11 +550,17 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
     iters[i] = it;
     const int kb = min(K, rankb[i]);  // usable columns
     int m = 0;
-    while (m < kb && sh_lam[m] < eta) ++m;
+    if (nev_fixed > 0) {
+      // fixed count: the nev_fixed smallest finite eigenvalues
+      while (m < kb && m < nev_fixed && sh_lam[m] < INFINITY) ++m;
+    } else {
+      while (m < kb && sh_lam[m] < eta) ++m;
+    }
     // Ritz values bound the eigenvalues from above in lambda, so m never exceeds the true
     // count; when it equals the inertia count of abar - eta b, no eigenvalue below eta is
     // missing and the next pair need not converge
-    const bool by_inertia = inertia != nullptr && inertia[i] >= 0 && inertia[i] == m && m < kb;
+    const bool by_inertia = nev_fixed == 0 && inertia != nullptr && inertia[i] >= 0 &&
+                            inertia[i] == m && m < kb;
     if (nev_max > 0 && m > nev_max) m = nev_max;
     const int guard = 2;
     bool grow = (m + 1 + guard > kb) && (kb < rankb[i]) && (K < Kmax_allowed);
@@ -561,13 +569,17 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
     // the pair after the selected ones only certifies the count (its eigenvalue is at
     // least eta); its Ritz value is accurate to about its backward error, so it is
     // accepted at CERT_TOL, below the accuracy asked of reported eigenvalues
+    // with a fixed count the next pair shows that the selected ones are the smallest: its
+    // Krylov-Weinstein interval must clear the largest selected Ritz value
+    const double nu_sep = nev_fixed > 0 ? (m > 0 ? 1.0 / (sh_lam[m - 1] + sigma) : INFINITY)
+                                        : 1.0 / (eta + sigma);
     for (int a = 0; a < need; ++a) {
-      if (a == m && sh_lam[a] >= eta) {
+      if (a == m && (nev_fixed > 0 || sh_lam[a] >= eta)) {
         // the certifying pair: not needed when the inertia certifies the count; else
         // accepted at CERT_TOL, or once the Krylov-Weinstein interval of its previous
         // iterate lies entirely on the lambda > eta side (its eigenvalue then certifies
         // the count whatever its remaining error)
-        const bool kw = it >= KW_MIN_IT && sh_kwup[a] < 1.0 / (eta + sigma);
+        const bool kw = it >= KW_MIN_IT && sh_kwup[a] < nu_sep;
         ok = ok && (by_inertia || sh_res[a] <= fmax(tol, CERT_TOL) || sh_stag[a] > 0.0 || kw);
       } else {
         ok = ok && (sh_res[a] <= tol || sh_stag[a] > 0.0);
@@ -699,9 +711,10 @@ void launch_rayleigh_ritz(hipStream_t s, int P, int K, const double* GS, const d
 }
 
 void launch_row_norm(hipStream_t s, int P, const i64* voff, int ell_w, const i32* ell_col,
-                     const double* ell_val, const double* dv, double sigma, double* normS) {
+                     const double* ell_val, const double* dv, double sigma, double* normS,
+                     const double* ell_val2) {
   hipLaunchKernelGGL(k_row_norm, dim3(P), dim3(MSDD_WG), 0, s, voff, ell_w, ell_col, ell_val, dv,
-                     sigma, normS);
+                     sigma, normS, ell_val2);
 }
 
 void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K,
@@ -710,14 +723,14 @@ void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, in
                        double tol, int maxit, int* status, int* iters, int* mcount,
                        double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
                        const double* normS, double* nu_prev, double* part, int nsplit,
-                       const double* gs_diag, const int* inertia) {
+                       const double* gs_diag, const int* inertia, int nev_fixed) {
   constexpr int TR = 16;
   size_t lds = (size_t)K * K * sizeof(double) + 3 * TR * K * sizeof(double);
   hipLaunchKernelGGL((k_eig_update<double, TR>), dim3(P, nsplit), dim3(MSDD_WG), lds, s, nb, kvoff,
                      K, C, nu, Y, Z, X, BX, SX, status, part, nsplit);
   hipLaunchKernelGGL(k_eig_judge, dim3(P), dim3(64), 0, s, K, nu, part, nsplit, sigma, eta,
                      nev_max, tol, maxit, status, iters, mcount, lam_out, res_out, Kmax_allowed,
-                     rankb, normS, nu_prev, gs_diag, inertia);
+                     rankb, normS, nu_prev, gs_diag, inertia, nev_fixed);
 }
 
 void launch_eig_finalize(hipStream_t s, int P, const i32* nb, const i64* voff, const i64* kvoff,

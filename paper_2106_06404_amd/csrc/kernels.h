@@ -13,7 +13,9 @@ void launch_neumann_assemble(hipStream_t s, i64 total_rows, const i32* row_sub, 
                              const i32* bw, const i64* boff, const i64* inc_ptr,
                              const i32* inc_slot, const i32* inc_a, const i32* slot_elem,
                              const i32* slot_loc, int k, const double* elem_mat, double* band,
-                             int ell_w, const i32* ell_col, double* ell_val, int* status);
+                             int ell_w, const i32* ell_col, double* ell_val, int* status,
+                             const i32* elem_ov = nullptr, double* band2 = nullptr,
+                             double* ell_val2 = nullptr);
 void launch_dirichlet_extract(hipStream_t s, i64 total_rows, const i32* drow_sub,
                               const i64* doff, const i32* nd, const i32* bd, const i64* dboff,
                               const i32* dglob, const i64* rowptr, const i32* col,
@@ -22,7 +24,7 @@ template <typename T>
 void launch_band_cholesky(hipStream_t s, int nsubs, const i32* subs, int bmax, const i32* n_arr,
                           const i32* b_arr, const i64* src_off, const double* src,
                           const i64* dv_off, const double* dv, double sigma, const i64* dst_off,
-                          T* Lc, T* Lr, int* status);
+                          T* Lc, T* Lr, int* status, const double* src2 = nullptr);
 // Cholesky factor (column layout) -> LDL^T factor in row layout F and, in place,
 // in column layout Lc (both with 1/D on the diagonal slot).
 // band_blocked.hip: blocked solves with per-block inverses (half-bandwidth <= 64)
@@ -78,9 +80,10 @@ void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, in
                        double tol, int maxit, int* status, int* iters, int* mcount,
                        double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
                        const double* normS, double* nu_prev, double* part, int nsplit,
-                       const double* gs_diag, const int* inertia);
+                       const double* gs_diag, const int* inertia, int nev_fixed = 0);
 void launch_row_norm(hipStream_t s, int P, const i64* voff, int ell_w, const i32* ell_col,
-                     const double* ell_val, const double* dv, double sigma, double* normS);
+                     const double* ell_val, const double* dv, double sigma, double* normS,
+                     const double* ell_val2 = nullptr);
 void launch_eig_finalize(hipStream_t s, int P, const i32* nb, const i64* voff, const i64* kvoff,
                          int K, const double* dv, const double* X, const double* nu,
                          const int* mcount, const i64* phi_off, double* Phi, const i32* nd,
@@ -170,7 +173,7 @@ void launch_apply_coarse_up(hipStream_t s, int P, const i32* nown, const i64* ow
 // abar + sigma D abar D (sigma = -eta); -1 where it could not be determined.
 void launch_band_inertia(hipStream_t s, int nsubs, int bmax, const i32* n_arr, const i32* b_arr,
                          const i64* src_off, const double* src, const i64* dv_off,
-                         const double* dv, double sigma, int* neg);
+                         const double* dv, double sigma, int* neg, const double* src2 = nullptr);
 // Scratch array of msdd_solve_noalloc (pcg.hip): noalloc_scratch_init looks up its
 // device address for `device` (which must be current), once; noalloc_scratch returns it
 // (nullptr before the lookup).  Returns 0 or -1.

@@ -211,6 +211,12 @@ struct FineLevel {
   std::vector<GroupPlan> plans;
   std::vector<double> h_dv;             // PoU weights (sorted order)
   DVec<double> dv;
+  std::vector<double> h_dg;             // b^3: weights 1 - dv of the GEVP right-hand side
+  DVec<double> dg;                      // (empty for b^1 and b^2, which use dv)
+  DVec<int32_t> elem_ov;                // b^2: 1 for overlap elements (else empty)
+  DVec<double> band2, ell_val2;         // b^2: the overlap elements' sum, band and ELL
+  // weights of the GEVP right-hand side b = D_g M D_g (M = abar, or band2 / ell_val2)
+  const double* gw() const { return dg.p ? dg.p : dv.p; }
   // band storage
   std::vector<int64_t> h_boff;
   DVec<int64_t> boff;
@@ -422,6 +428,7 @@ struct msdd_ctx {
   // host scratch of the planning, kept between setups (no fresh pages each time)
   std::vector<double> scr_pou;
   std::vector<int32_t> scr_cnt;
+  std::vector<int32_t> scr_ecnt;
   std::vector<int64_t> scr_pos;
   msdd_tuning_t tune{};            // launch-shape choices (0 = by shape)
   ~msdd_ctx() {
@@ -503,6 +510,7 @@ struct ProfScope {
 // Per-subdomain planning results (computed in parallel, merged in subdomain order).
 struct SubPlan {
   std::vector<double> dv;            // PoU weight per Neumann dof (0 off the Dirichlet set)
+  std::vector<double> dg;            // weights of the GEVP right-hand side (b^3: 1 - dv)
   std::vector<int32_t> dpos, dglob;  // Dirichlet dofs: local Neumann index, global dof
   std::vector<int32_t> wpos;         // warm-start frame position per Neumann dof
   std::vector<int32_t> ell_ptr, ell_col;  // local CSR of the Neumann matrix pattern
@@ -529,6 +537,13 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   for (int32_t e : se) REQUIRE(e >= 0 && e < n_elem, "sub_elem entry out of range");
   F.elems.assign(P, {});
   F.plans.assign(P, {});
+  // b^2: elements that belong to more than one subdomain (the overlap elements)
+  const int rhs = c->opt.geneo_rhs;
+  std::vector<int32_t>& ecount = c->scr_ecnt;
+  if (rhs == 2) {
+    ecount.assign(n_elem, 0);
+    for (int32_t e : se) ecount[e]++;
+  }
   std::vector<SubPlan> sp(P);
   const int nthr = host_threads(P);
   std::vector<std::vector<int>> maps(nthr);
@@ -583,8 +598,26 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
         dloc[r] = S.nD++;
         S.dpos.push_back(r);
         S.dglob.push_back(g.dofs[r]);
-        if (w != 0.0) S.rankb++;
+        if (w != 0.0 && rhs == 1) S.rankb++;
       }
+    }
+    // weights of the GEVP right-hand side and the rank of b (an upper bound for b^2)
+    if (rhs == 3) {
+      S.dg.resize(nb);
+      for (int r = 0; r < nb; ++r) {
+        S.dg[r] = 1.0 - S.dv[r];
+        if (S.dg[r] != 0.0) S.rankb++;
+      }
+    } else if (rhs == 2) {
+      std::vector<char> touch(nb, 0);  // the dof lies on an overlap element
+      for (size_t q = 0; q < els.size(); ++q)
+        if (ecount[els[q]] >= 2)
+          for (int a = 0; a < k; ++a) {
+            const int l = g.eloc[q * k + a];
+            if (l >= 0) touch[l] = 1;
+          }
+      for (int r = 0; r < nb; ++r)
+        if (touch[r] && S.dv[r] != 0.0) S.rankb++;
     }
     for (size_t q = 0; q < els.size(); ++q) {
       int lo = 1 << 30, hi = -1;
@@ -621,6 +654,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   vlog(c, "plan: subdomain groups (parallel)", &tv);
   // merge in subdomain order
   F.h_dv.clear();
+  F.h_dg.clear();
   F.h_wpos.clear();
   F.h_nd.assign(P, 0);
   F.h_bd.assign(P, 0);
@@ -638,6 +672,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
     const GroupPlan& g = F.plans[i];
     const SubPlan& S = sp[i];
     F.h_dv.insert(F.h_dv.end(), S.dv.begin(), S.dv.end());
+    if (rhs == 3) F.h_dg.insert(F.h_dg.end(), S.dg.begin(), S.dg.end());
     F.h_wpos.insert(F.h_wpos.end(), S.wpos.begin(), S.wpos.end());
     for (size_t r = 0; r < g.dofs.size(); ++r) pou_sum[g.dofs[r]] += S.dv[r];
     for (int32_t d : S.dglob) dcount[d]++;
@@ -686,6 +721,15 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   hipStream_t s = c->stream;
   build_groupset(F.plans, F.elems, k, F.gs, s);
   F.dv.upload(F.h_dv, s);
+  if (rhs == 3) F.dg.upload(F.h_dg, s);
+  else F.dg.release();
+  if (rhs == 2) {
+    std::vector<int32_t> ov(n_elem);
+    for (int32_t e = 0; e < n_elem; ++e) ov[e] = ecount[e] >= 2;
+    F.elem_ov.upload(ov, s);
+  } else {
+    F.elem_ov.release();
+  }
   F.wpos.upload(F.h_wpos, s);
   F.h_boff.assign(P + 1, 0);
   for (int i = 0; i < P; ++i)
@@ -747,10 +791,19 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   F.ell_val.zero(s);
   {
   ProfScope ps(c, PR_NEUMANN, F.s_nb * (8.0 + F.ell_w * 12.0) + F.s_band * 8.0);
+  if (F.elem_ov.p) {
+    F.band2.alloc(F.h_boff.back());
+    F.band2.zero(s);
+    F.ell_val2.alloc((size_t)F.gs.total_rows * F.ell_w);
+    F.ell_val2.zero(s);
+  } else {
+    F.band2.release();
+    F.ell_val2.release();
+  }
   launch_neumann_assemble(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.bw.p, F.boff.p,
                           F.gs.inc_ptr.p, F.gs.inc_slot.p, F.gs.inc_a.p, F.gs.slot_elem.p,
                           F.gs.slot_loc.p, c->k, d_elem_mat, F.band.p, F.ell_w, F.ell_col.p,
-                          F.ell_val.p, status.p);
+                          F.ell_val.p, status.p, F.elem_ov.p, F.band2.p, F.ell_val2.p);
   }
   F.Dband.alloc(F.h_dboff.back());
   F.Dband.zero(s);
@@ -781,8 +834,13 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   F.inertia.alloc(P);
   {
   ProfScope ps(c, PR_CHOL, F.s_band * 8.0, F.s_nbb * (F.bw_max + 2.0), c->istream);
-  launch_band_inertia(c->istream, P, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.band.p,
-                      F.gs.voff.p, F.dv.p, -c->eta, F.inertia.p);
+  if (c->opt.nev_fixed > 0) {  // a fixed count has no threshold to certify
+    std::vector<int> none(P, -1);
+    F.inertia.upload(none, c->istream);
+  } else {
+    launch_band_inertia(c->istream, P, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.band.p,
+                        F.gs.voff.p, F.gw(), -c->eta, F.inertia.p, F.band2.p);
+  }
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(c->iev, c->istream));
@@ -830,8 +888,8 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   {
   ProfScope ps(c, PR_CHOL, F.s_band * 8.0 * 3.0, F.s_nbb * (F.bw_max + 2.0));
   launch_band_cholesky<double>(s, P, nullptr, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.band.p,
-                               F.gs.voff.p, F.dv.p, c->sigma, F.boff.p, F.LSc.p, F.LSr.p,
-                               status.p);
+                               F.gs.voff.p, F.gw(), c->sigma, F.boff.p, F.LSc.p, F.LSr.p,
+                               status.p, F.band2.p);
   }
   HIPCHK(hipGetLastError());
   // the eigensolver's solves use the LDL^T form: row layout in LSr, column layout in LSc
@@ -878,11 +936,12 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
 void eig_bapply(msdd_ctx* c, hipStream_t s, const int64_t* kvoff, int K, const double* Y,
                 double* Z, const int* status) {
   FineLevel& F = c->F;
+  const double* ev = F.ell_val2.p ? F.ell_val2.p : F.ell_val.p;  // the matrix inside b
   if (launch_bapply_tile(s, F.P, F.nb_max, F.bw_max, F.gs.voff.p, F.gs.n.p, F.gs.bw.p, kvoff, K,
-                         F.dv.p, F.ell_w, F.ell_col.p, F.ell_val.p, Y, Z, status))
+                         F.gw(), F.ell_w, F.ell_col.p, ev, Y, Z, status))
     return;
-  launch_bapply_ell(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, kvoff, K, F.dv.p,
-                    F.ell_w, F.ell_col.p, F.ell_val.p, Y, Z, status);
+  launch_bapply_ell(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, kvoff, K, F.gw(),
+                    F.ell_w, F.ell_col.p, ev, Y, Z, status);
 }
 
 // Band solves Y = S^{-1} W of the eigensolver (K columns per subdomain, skipped where
@@ -976,7 +1035,8 @@ void fine_eigensolve(msdd_ctx* c) {
     gsd.alloc((size_t)P * K);
     gsd.zero(s);
     normS.alloc(P);
-    launch_row_norm(s, P, F.gs.voff.p, F.ell_w, F.ell_col.p, F.ell_val.p, F.dv.p, c->sigma, normS.p);
+    launch_row_norm(s, P, F.gs.voff.p, F.ell_w, F.ell_col.p, F.ell_val.p, F.gw(), c->sigma, normS.p,
+                    F.ell_val2.p);
     DVec<int> status, iters;
     std::vector<int> st0(P);
     for (int i = 0; i < P; ++i) st0[i] = want[i] ? ST_RUNNING : ST_DONE;
@@ -987,11 +1047,11 @@ void fine_eigensolve(msdd_ctx* c) {
     if (net) {
       dwarm.upload(warm_ok, s);
       launch_eig_init_warm(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K,
-                           F.dv.p, E.X.p, 0x5eed5eedull + (unsigned long long)K, F.seed_id.p,
+                           F.gw(), E.X.p, 0x5eed5eedull + (unsigned long long)K, F.seed_id.p,
                            dwarm.p, yw.p, n_vec, n_pos, F.wpos.p);
     } else {
       launch_eig_init(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, dkvoff.p, K,
-                      F.dv.p, E.X.p, 0x5eed5eedull + (unsigned long long)K, F.seed_id.p);
+                      F.gw(), E.X.p, 0x5eed5eedull + (unsigned long long)K, F.seed_id.p);
     }
     eig_bapply(c, s, dkvoff.p, K, E.X.p, BX.p, status.p);
     const int maxit = o.eig_maxit;
@@ -1022,7 +1082,7 @@ void fine_eigensolve(msdd_ctx* c) {
         launch_eig_update(s, P, F.gs.n.p, dkvoff.p, K, Cm.p, E.nu.p, Y.p, Z.p, E.X.p, BX.p, SX.p,
                           c->sigma, c->eta, o.nev_max, o.eig_tol, maxit, status.p, iters.p,
                           E.mcount.p, E.lam.p, E.res.p, 64, F.rankb.p, normS.p, nu_prev.p,
-                          upart.p, nsplit, gsd.p, F.inertia.p);
+                          upart.p, nsplit, gsd.p, F.inertia.p, o.nev_fixed);
       }
       HIPCHK(hipGetLastError());
       if (it >= 3 && (it % 2 == 1 || it == maxit - 1)) {
@@ -1834,6 +1894,8 @@ void msdd_default_options(msdd_options* o) {
   o->device = 0;
   o->stream = nullptr;
   o->verbose = 0;
+  o->geneo_rhs = 1;
+  o->nev_fixed = 0;
 }
 
 int msdd_create(msdd_ctx** out, const msdd_options* opt) {
@@ -1854,7 +1916,8 @@ int msdd_create(msdd_ctx** out, const msdd_options* opt) {
     delete c;
     return MSDD_EDEVICE;
   }
-  if (c->opt.precision != MSDD_FP64 && c->opt.precision != MSDD_MIXED) {
+  if ((c->opt.precision != MSDD_FP64 && c->opt.precision != MSDD_MIXED) ||
+      c->opt.geneo_rhs < 1 || c->opt.geneo_rhs > 3 || c->opt.nev_fixed < 0) {
     delete c;
     return MSDD_EINVAL;
   }

@@ -63,29 +63,37 @@ def eig_bar(lam_ref, unc, bound, eta):
                        U_FACTOR * np.asarray(unc)) + np.asarray(bound))
 
 
-def check_selected_and_certifying(lg, m_i, lam_ref, unc, bound, eta, where=""):
+def check_selected_and_certifying(lg, m_i, lam_ref, unc, bound, eta, where="", fixed=False):
     """lg: GPU eigenvalues (m_i selected and at least the certifying one when computed);
-    lam_ref/unc/bound: binary128 references of the first m_i + 1 or more pairs."""
+    lam_ref/unc/bound: binary128 references of the first m_i + 1 or more pairs.  With a
+    fixed count (no threshold) the next pair must lie at or above the selected ones."""
     lg = np.asarray(lg)
     sel = lg[:m_i]
     assert len(sel) == m_i, where
     bar = eig_bar(lam_ref[:m_i], unc[:m_i], bound[:m_i], eta)
     err = np.abs(sel - np.asarray(lam_ref[:m_i]))
     assert np.all(err <= bar), (where, sel, lam_ref[:m_i], err / bar)
-    assert np.all(sel < eta), where
+    if not fixed:
+        assert np.all(sel < eta), where
     if len(lg) > m_i and len(lam_ref) > m_i:
-        assert lg[m_i] >= eta and lam_ref[m_i] >= eta, (where, lg[m_i], lam_ref[m_i])
+        if fixed:
+            assert m_i == 0 or lg[m_i] >= lam_ref[m_i - 1], (where, lg[m_i], lam_ref[m_i - 1])
+        else:
+            assert lg[m_i] >= eta and lam_ref[m_i] >= eta, (where, lg[m_i], lam_ref[m_i])
     return float(np.max(err / bar)) if m_i else 0.0
 
 
 def refined_fine_level(o, prob):
     """Binary128 references of every finest-level subdomain of an oracle built with
-    fine_vectors > 0."""
-    from oracle.msdd_oracle import refine_pairs
+    fine_vectors > 0 (with the oracle's GEVP right-hand side)."""
+    from oracle.msdd_oracle import overlap_elements, refine_pairs
+    alpha = getattr(o, "geneo_rhs", 1)
+    subs = [prob.sub_elems(j) for j in range(prob.n_sub)] if alpha == 2 else None
     out = []
     for i in range(prob.n_sub):
         out.append(refine_pairs(prob.elem_dofs, prob.elem_mat, prob.sub_elems(i), prob.sub_dofs(i),
-                                prob.sub_weights(i), o.fine_vecs[i], iters=8))
+                                prob.sub_weights(i), o.fine_vecs[i], iters=8, geneo_rhs=alpha,
+                                overlap=overlap_elements(subs, i) if alpha == 2 else None))
     return out
 
 

@@ -41,9 +41,10 @@ def _setup(prob, **opts):
     return gpu_setup(prob, **opts)
 
 
-def _check_fine_level(m, o, prob, eta):
+def _check_fine_level(m, o, prob, eta, angle_bar=None):
     """Counts, selected eigenvalues, certifying pairs and coarse-space blocks of the finest
     level against the binary128 references (o built with fine_vectors > 0)."""
+    angle_bar = ANGLE_BAR if angle_bar is None else angle_bar
     from gpu_common import check_selected_and_certifying, refined_fine_level, sin_angle
     L = prob.n_levels - 1
     lev = o.levels[L]
@@ -53,14 +54,15 @@ def _check_fine_level(m, o, prob, eta):
     assert st["eig_unconverged"] == 0
     refs = refined_fine_level(o, prob)
     worst = 0.0
+    fixed = getattr(o, "nev_fixed", 0) > 0
     for i, r in enumerate(refs):
         mi = int(lev.m[i])
         lg = m.eigs(L, i, 1)
         worst = max(worst, check_selected_and_certifying(lg, mi, r.lam, r.fp64_uncertainty,
-                                                         r.bound, eta, where=i))
+                                                         r.bound, eta, where=i, fixed=fixed))
         if mi:
             Dx = prob.sub_weights(i)[:, None] * r.X[:, :mi]
-            assert sin_angle(m.basis(L, i), Dx) <= ANGLE_BAR, i
+            assert sin_angle(m.basis(L, i), Dx) <= angle_bar, i
     return worst
 
 
