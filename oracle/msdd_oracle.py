@@ -490,6 +490,46 @@ class Oracle:
         z += self.P[0] @ sla.solve_triangular(self.A0_chol.T, y, lower=False)
         return z
 
+    # -- Sec. 2.1 / Sec. 5: hybrid form -- restricted additive Schwarz within a level
+    # (prolongation weighted by the partition of unity), multiplicative over the levels,
+    # finest first: z = B_L r; then for l = L-1, ..., 0: z += P_l B_l P_l^T (r - A z)
+    def apply_hybrid(self, r: np.ndarray) -> np.ndarray:
+        p = self.prob
+        L = self.L
+        lev = self.levels[L]
+        z = np.zeros_like(r)
+        for i in range(lev.n_sub):
+            idx = lev.dir_rows[i]
+            if len(idx) == 0:
+                continue
+            Lc = lev.dir_chol[i]
+            y = sla.solve_triangular(Lc, r[idx], lower=True)
+            ui = sla.solve_triangular(Lc.T, y, lower=False)
+            dofs = p.sub_dofs(i)
+            dm = dirichlet_mask(p.elem_dofs, p.sub_elems(i), dofs)
+            z[idx] += p.sub_weights(i)[dm] * ui          # restricted: chi_i on Dir_i
+        for l in range(L - 1, -1, -1):
+            t = self.P[l].T @ (r - self.A @ z)
+            if l == 0:
+                y = sla.solve_triangular(self.A0_chol, t, lower=True)
+                zl = sla.solve_triangular(self.A0_chol.T, y, lower=False)
+            else:
+                cl = self.levels[l]
+                zl = np.zeros_like(t)
+                for i in range(cl.n_sub):
+                    idx = cl.dir_rows[i]
+                    if len(idx) == 0:
+                        continue
+                    Lc = cl.dir_chol[i]
+                    y = sla.solve_triangular(Lc, t[idx], lower=True)
+                    zl[idx] += sla.solve_triangular(Lc.T, y, lower=False)
+            z = z + self.P[l] @ zl
+        return z
+
+    def solve_gmres(self, b=None, rtol=1e-8, restart=200, maxit=1000):
+        b = self.prob.b if b is None else b
+        return gmres(self.A, b, self.apply_hybrid, rtol=rtol, restart=restart, maxit=maxit)
+
     def level_sizes(self):
         return [self.P[l].shape[1] for l in range(self.L + 1)]
 
@@ -563,3 +603,73 @@ def lanczos_kappa(alphas, betas) -> float:
             T[j, j + 1] = T[j + 1, j] = np.sqrt(betas[j]) / alphas[j]
     w, _ = jacobi_eigh(T)
     return float(w[-1] / w[0])
+
+
+# ----------------------------------------------------------------------------
+# GMRES with right preconditioning (the Krylov method of the hybrid form, Sec. 5)
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class GmresResult:
+    x: np.ndarray
+    iters: int
+    converged: bool
+    resnorms: List[float]      # ||r_k|| estimates from the least-squares problem, k = 0..iters
+
+
+def gmres(A, b, M, rtol=1e-8, restart=200, maxit=1000) -> GmresResult:
+    """Textbook restarted GMRES from x^0 = 0 with right preconditioning: Arnoldi (modified
+    Gram-Schmidt) on A M, the small least-squares problem by Givens rotations; x = x^0 +
+    M V y; stops when ||b - A x^m|| < rtol ||b - A x^0||: the cycle ends when the
+    least-squares residual (equal to the true one in exact arithmetic) meets it, and the
+    true residual is then checked; if rounding left it above (the operator A M of the
+    hybrid form can be ill conditioned), GMRES restarts from x^m."""
+    n = len(b)
+    x = np.zeros(n)
+    r = b - A @ x
+    r0 = float(np.linalg.norm(r))
+    res = [r0]
+    if r0 == 0.0:
+        return GmresResult(x, 0, True, res)
+    its = 0
+    while its < maxit:
+        beta = float(np.linalg.norm(r))
+        m = min(restart, maxit - its)
+        V = np.zeros((n, m + 1))
+        H = np.zeros((m + 1, m))
+        cs, sn = np.zeros(m), np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[:, 0] = r / beta
+        k_done = 0
+        conv = False
+        for k in range(m):
+            w = A @ M(V[:, k])
+            for j in range(k + 1):
+                H[j, k] = float(V[:, j] @ w)
+                w = w - H[j, k] * V[:, j]
+            H[k + 1, k] = float(np.linalg.norm(w))
+            if H[k + 1, k] > 0.0:
+                V[:, k + 1] = w / H[k + 1, k]
+            for j in range(k):   # earlier rotations on the new column
+                t = cs[j] * H[j, k] + sn[j] * H[j + 1, k]
+                H[j + 1, k] = -sn[j] * H[j, k] + cs[j] * H[j + 1, k]
+                H[j, k] = t
+            d = np.hypot(H[k, k], H[k + 1, k])
+            cs[k], sn[k] = H[k, k] / d, H[k + 1, k] / d
+            H[k, k] = d
+            H[k + 1, k] = 0.0
+            g[k + 1] = -sn[k] * g[k]
+            g[k] = cs[k] * g[k]
+            its += 1
+            k_done = k + 1
+            res.append(abs(g[k + 1]))
+            if abs(g[k + 1]) < rtol * r0 or H[k, k] == 0.0:
+                conv = abs(g[k + 1]) < rtol * r0
+                break
+        y = sla.solve_triangular(H[:k_done, :k_done], g[:k_done], lower=False)
+        x = x + M(V[:, :k_done] @ y)
+        r = b - A @ x
+        if conv and float(np.linalg.norm(r)) < rtol * r0:
+            return GmresResult(x, its, True, res)
+    return GmresResult(x, its, False, res)
