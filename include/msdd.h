@@ -225,6 +225,32 @@ int msdd_solve_history(const msdd_ctx* c, double* relres, int32_t cap, int32_t* 
 int msdd_solve_noalloc(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t* iters, double* relres);
 
+/*
+ * Hybrid form of the preconditioner (Sec. 2.1 subspace correction; the form the paper uses
+ * with GMRES in Sec. 5): restricted additive Schwarz on the finest level (each local
+ * solution weighted by the partition of unity chi before it is added), multiplicative over
+ * the levels from the finest to the coarsest:
+ *     z = sum_i R_i^T D_i A_i^{-1} R_i r;
+ *     for l = L-1, ..., 0:  z += P_l (sum_i R_{l,i}^T A_{l,i}^{-1} R_{l,i}) P_l^T (r - A z)
+ * (coarse levels: the owned blocks, which partition the level, so no weights; level 0: the
+ * coarsest matrix).  Not symmetric: use it with GMRES.  Single-problem setups only
+ * (MSDD_EINVAL after msdd_setup_batch).  r, z host or device, length n.
+ */
+int msdd_apply_hybrid(msdd_ctx* c, const double* r, double* z);
+
+/*
+ * Solve A x = b by restarted GMRES (restart >= 1 basis vectors per cycle) with the hybrid
+ * form as right preconditioner, from the initial guess in x.  Stops when the true residual
+ * satisfies ||b - A x^m|| < rtol ||b - A x^0|| (Sec. 5): a cycle ends when GMRES's
+ * least-squares residual meets it, the true residual is then computed, and the solve
+ * restarts from x^m if rounding left it above.  maxit counts iterations over all cycles;
+ * iters, relres (may be NULL) receive the count and the true ||r|| / ||r_0||;
+ * msdd_solve_history returns the least-squares residuals.  MSDD_ENOCONV at maxit.
+ * Single-problem setups only.
+ */
+int msdd_solve_gmres(msdd_ctx* c, const double* b, double* x, double rtol, int32_t restart,
+                     int32_t maxit, int32_t* iters, double* relres);
+
 /* z = B r: one application of the multilevel additive preconditioner. */
 int msdd_apply(msdd_ctx* c, const double* r, double* z);
 

@@ -247,6 +247,8 @@ def gevp_generating(Ab: np.ndarray, Bm: np.ndarray, eta: float,
     """Coarse-level GEVP on a generating system (Sec. 4.2): ker abar cap ker b may be
     nonzero.  Compress: S = abar + b = Q diag(s) Q^T (Jacobi); drop s <= rel*max(s)
     (that is ker abar cap ker b); on the kept span solve the definite pencil."""
+    if Ab.shape[0] == 0:   # no function on the next finer level: nothing to select
+        return GevpResult(lam=np.zeros(0), mu=np.zeros(0), m=0, X=np.zeros((0, 0)))
     S = 0.5 * ((Ab + Bm) + (Ab + Bm).T)
     s, Q = jacobi_eigh(S)
     keep = s > rel * max(s.max(), 0.0)
@@ -443,7 +445,7 @@ class Oracle:
                 gen_subs = self._generating_subdomains(emask_l, emask, par, i)
                 owned_subs = set(np.nonzero(par == i)[0].tolist())
                 gen_cols = np.concatenate([np.nonzero(col_owner == j)[0] for j in gen_subs])
-                own = np.array([col_owner[c] in owned_subs for c in gen_cols])
+                own = np.array([col_owner[c] in owned_subs for c in gen_cols], dtype=bool)
                 AT = elements_matrix(n, p.elem_dofs, p.elem_mat, np.nonzero(emask)[0])
                 G = Pl1[:, gen_cols]
                 Ab = (G.T @ (AT @ G)).toarray()

@@ -82,7 +82,8 @@ EXPORTS = ["msdd_default_options", "msdd_create", "msdd_setup", "msdd_setup_batc
            "msdd_net_create", "msdd_net_param_count", "msdd_net_set_params",
            "msdd_net_get_params", "msdd_net_forward", "msdd_net_grad", "msdd_net_train_step",
            "msdd_net_last_error", "msdd_net_destroy", "msdd_autotune", "msdd_get_tuning",
-           "msdd_set_tuning", "msdd_solve_noalloc"]
+           "msdd_set_tuning", "msdd_solve_noalloc",
+           "msdd_apply_hybrid", "msdd_solve_gmres"]
 MSDD_NPROF = 19
 
 _lib = None
@@ -128,6 +129,11 @@ def load():
     L.msdd_solve_noalloc.argtypes = [vp, vp, vp, f64, i32, ctypes.POINTER(i32),
                                      ctypes.POINTER(f64)]
     L.msdd_solve_noalloc.restype = ctypes.c_int
+    L.msdd_apply_hybrid.argtypes = [vp, vp, vp]
+    L.msdd_apply_hybrid.restype = ctypes.c_int
+    L.msdd_solve_gmres.argtypes = [vp, vp, vp, f64, i32, i32, ctypes.POINTER(i32),
+                                   ctypes.POINTER(f64)]
+    L.msdd_solve_gmres.restype = ctypes.c_int
     L.msdd_solve_batch.argtypes = [vp, vp, vp, f64, i32, vp, vp]
     L.msdd_solve_batch.restype = ctypes.c_int
     L.msdd_solve_history.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
@@ -288,6 +294,18 @@ class Msdd:
         rc = self._L.msdd_solve_noalloc(self._h, _ptr(b, np.float64), _ptr(x, np.float64),
                                         float(rtol), int(maxit), ctypes.byref(it),
                                         ctypes.byref(rel))
+        self._check(rc, allow=(MSDD_ENOCONV,) if allow_noconv else ())
+        return int(it.value), float(rel.value), rc
+
+    def apply_hybrid(self, r, z):
+        self._check(self._L.msdd_apply_hybrid(self._h, _ptr(r, np.float64), _ptr(z, np.float64)))
+
+    def solve_gmres(self, b, x, rtol=1e-8, restart=200, maxit=1000, allow_noconv=False):
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        rc = self._L.msdd_solve_gmres(self._h, _ptr(b, np.float64), _ptr(x, np.float64),
+                                      float(rtol), int(restart), int(maxit), ctypes.byref(it),
+                                      ctypes.byref(rel))
         self._check(rc, allow=(MSDD_ENOCONV,) if allow_noconv else ())
         return int(it.value), float(rel.value), rc
 

@@ -174,6 +174,23 @@ void launch_apply_coarse_up(hipStream_t s, int P, const i32* nown, const i64* ow
 void launch_band_inertia(hipStream_t s, int nsubs, int bmax, const i32* n_arr, const i32* b_arr,
                          const i64* src_off, const double* src, const i64* dv_off,
                          const double* dv, double sigma, int* neg, const double* src2 = nullptr);
+// gmres.hip: dense vector kernels of GMRES (x, y, V column-major with leading dimension n)
+// h[c] = V(:, c) . w for c < k (partial sums per block, then a fixed-order reduction)
+void launch_multi_dot(hipStream_t s, i64 n, int k, const double* V, const double* w,
+                      double* partial, double* h);
+// w -= V(:, 0:k) h
+void launch_multi_axpy(hipStream_t s, i64 n, int k, const double* V, const double* h, double* w);
+// y = V(:, 0:k) c   (acc: y += ...)
+void launch_gemv_cols(hipStream_t s, i64 n, int k, const double* V, const double* c, double* y,
+                      int acc);
+// y = a * x, a read from the device scalar: a = ap[0] (inv 0), 1 / ap[0] (1), 1 / sqrt(ap[0]) (2)
+void launch_scale_dev(hipStream_t s, i64 n, const double* ap, int inv, const double* x, double* y);
+// y += a x (host scalar)
+void launch_axpy(hipStream_t s, i64 n, double a, const double* x, double* y);
+void launch_fill(hipStream_t s, i64 n, double v, double* y);
+// number of blocks multi_dot uses for n rows (its partial array holds k * blocks)
+int multi_dot_blocks(i64 n);
+
 // Scratch array of msdd_solve_noalloc (pcg.hip): noalloc_scratch_init looks up its
 // device address for `device` (which must be current), once; noalloc_scratch returns it
 // (nullptr before the lookup).  Returns 0 or -1.
@@ -182,7 +199,8 @@ void* noalloc_scratch(int device);
 void launch_apply_fine_up(hipStream_t s, i64 n, const i64* dinc_ptr, const i32* dinc_sub,
                           const i32* dinc_q, const i64* doff, const i32* msub, const i64* moff,
                           const i64* phid_off, const double* PhiD, const double* u,
-                          const double* zc, double* z);
+                          const double* zc, double* z,
+                          const double* w = nullptr, int acc = 0);
 
 // mlp.hip (warm-start network of the local eigensolver)
 // C_z = opA(A) opB(B) over split z of K (row-major M x N partials); every split is

@@ -211,6 +211,8 @@ struct FineLevel {
   std::vector<GroupPlan> plans;
   std::vector<double> h_dv;             // PoU weights (sorted order)
   DVec<double> dv;
+  std::vector<double> h_dw;             // PoU weight per Dirichlet entry (doff order)
+  DVec<double> dw;                      // (the restricted additive Schwarz weights)
   std::vector<double> h_dg;             // b^3: weights 1 - dv of the GEVP right-hand side
   DVec<double> dg;                      // (empty for b^1 and b^2, which use dv)
   DVec<int32_t> elem_ov;                // b^2: 1 for overlap elements (else empty)
@@ -386,6 +388,7 @@ struct msdd_ctx {
   // solve work
   std::vector<DVec<double>> rlev, zlev;  // index l = 0..L-1
   DVec<double> u, r, z, p, q, x, bvec, partial;
+  DVec<double> hyb_t, hyb_q;  // hybrid form: residual of the current correction, A z
   // PCG segments (one per problem) and chunks (row ranges inside one segment)
   std::vector<int64_t> h_seg_row;        // nseg+1
   int nseg = 1, nch = 0;
@@ -654,6 +657,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   vlog(c, "plan: subdomain groups (parallel)", &tv);
   // merge in subdomain order
   F.h_dv.clear();
+  F.h_dw.clear();
   F.h_dg.clear();
   F.h_wpos.clear();
   F.h_nd.assign(P, 0);
@@ -677,6 +681,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
     for (size_t r = 0; r < g.dofs.size(); ++r) pou_sum[g.dofs[r]] += S.dv[r];
     for (int32_t d : S.dglob) dcount[d]++;
     F.h_dpos.insert(F.h_dpos.end(), S.dpos.begin(), S.dpos.end());
+    for (int32_t q : S.dpos) F.h_dw.push_back(S.dv[q]);
     F.h_dglob.insert(F.h_dglob.end(), S.dglob.begin(), S.dglob.end());
     F.h_nd[i] = S.nD;
     F.h_bd[i] = S.bd;
@@ -721,6 +726,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   hipStream_t s = c->stream;
   build_groupset(F.plans, F.elems, k, F.gs, s);
   F.dv.upload(F.h_dv, s);
+  F.dw.upload(F.h_dw, s);
   if (rhs == 3) F.dg.upload(F.h_dg, s);
   else F.dg.release();
   if (rhs == 2) {
@@ -1772,6 +1778,8 @@ void alloc_solve_work(msdd_ctx* c) {
   c->q.alloc(n);
   c->x.alloc(n);
   c->bvec.alloc(n);
+  c->hyb_t.alloc(n);
+  c->hyb_q.alloc(n);
   // chunks of at most 256 rows, never crossing a segment boundary
   const int64_t CH = 256;
   std::vector<int64_t> lo, hi, sch(c->nseg + 1, 0);
@@ -1869,6 +1877,79 @@ void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
                  2.0 * F.s_ndm + F.s_nd);
     launch_apply_fine_up(s, c->n, F.dinc_ptr.p, F.dinc_sub.p, F.dinc_q.p, F.doff.p, F.dm.p,
                          F.moff.p, F.phid_off.p, F.PhiD.p, c->u.p, c->zlev[L - 1].p, z);
+  }
+}
+
+// Hybrid form (Sec. 2.1; the form used with GMRES in Sec. 5): restricted additive Schwarz
+// on the finest level (local solutions weighted by the partition of unity), then, finest to
+// coarsest, each level's additive correction of the updated residual:
+//   z = sum_i R_i^T D_i A_i^{-1} R_i r;   for l = L-1, ..., 0:  z += P_l B_l P_l^T (r - A z)
+// (B_l: the owned blocks' inverses, level 0 the coarsest inverse).  On one stream.
+void apply_hybrid(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
+  FineLevel& F = c->F;
+  const int L = c->n_levels - 1;
+  const int64_t n = c->n;
+  double* rc_top = c->rlev[L - 1].p;
+  const bool f32 = c->opt.precision == MSDD_MIXED;
+  auto fine_restrict = [&](const double* v) {
+    ProfScope ps(c, PR_APPLY_RESTRICT, F.s_nd * (4.0 + 8.0 + 8.0) + F.s_ndm * 8.0 + F.s_m * 8.0,
+                 2.0 * F.s_ndm);
+    launch_apply_fine_restrict(s, F.P, F.nd_max, F.nd.p, F.doff.p, F.dglob.p, F.dm.p, F.moff.p,
+                               F.phid_off.p, F.PhiD.p, v, rc_top, c->u.p);
+  };
+  fine_restrict(r);
+  {
+    ProfScope ps(c, PR_APPLY_FINE,
+                 2.0 * F.s_dband * (f32 ? 4.0 : 8.0) + 2.0 * F.s_nd * 8.0 + (f32 ? 2.0 * F.s_nd * 8.0 : 0.0),
+                 4.0 * F.s_ndbd + F.s_nd);
+    if (f32)
+      launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
+                              F.LDc32.p, F.LDr32.p, 1, F.dscale.p, c->u.p, c->tune.fine_solve);
+    else
+      launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
+                              F.LDc.p, F.LDr.p, 0, nullptr, c->u.p, c->tune.fine_solve);
+  }
+  {
+    ProfScope ps(c, PR_APPLY_GATHER, (double)(n + 1) * 8.0 + F.s_nd * 24.0 + n * 8.0, 2.0 * F.s_nd);
+    launch_apply_fine_up(s, n, F.dinc_ptr.p, F.dinc_sub.p, F.dinc_q.p, F.doff.p, F.dm.p, F.moff.p,
+                         F.phid_off.p, F.PhiD.p, c->u.p, nullptr, z, F.dw.p, 0);
+  }
+  double* t = c->hyb_t.p;
+  double* q = c->hyb_q.p;
+  for (int l = L - 1; l >= 0; --l) {
+    {
+      ProfScope ps(c, PR_SPMV, (double)c->nnz * 12.0 + (double)(n + 1) * 8.0 + 3.0 * n * 8.0,
+                   2.0 * c->nnz);
+      launch_spmv_chunk(s, c->nch, c->spmv_sg, c->ch_lo.p, c->ch_hi.p, c->rowptr.p, c->col.p,
+                        c->val.p, z, q, c->partial.p);
+      launch_residual_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, r, q, t, c->partial.p);
+    }
+    fine_restrict(t);  // rc_top = P_{L-1}^T t (the local copies in u are not used)
+    ProfScope ps(c, PR_APPLY_COARSE);
+    // restriction down to level l (owned solves of the levels passed are not used), then the
+    // solve on level l
+    for (int tt = 0; tt < (int)c->C.size(); ++tt) {
+      CoarseLevel& CL = c->C[tt];
+      const int lv = CL.level;
+      if (lv < l) break;
+      launch_apply_coarse_down(s, CL.P, CL.no_max, CL.dno.p, CL.own_ptr.p, CL.own_idx.p,
+                               CL.loff.p, CL.Inv.p, CL.dm.p, CL.yoff.p, CL.Y.p, CL.moff.p,
+                               c->rlev[lv].p, c->zlev[lv].p, c->rlev[lv - 1].p);
+    }
+    if (l == 0)
+      launch_apply_coarsest(s, c->n0_blocks, c->n0_max, c->z0off.p, c->a0off.p, c->n0blk.p,
+                            c->A0inv.p, c->rlev[0].p, c->zlev[0].p);
+    // prolongation of the level-l correction alone up to level L-1, then to the fine level
+    for (int lv = l + 1; lv <= L - 1; ++lv) launch_fill(s, c->nlev[lv], 0.0, c->zlev[lv].p);
+    for (int tt = (int)c->C.size() - 1; tt >= 0; --tt) {
+      CoarseLevel& CL = c->C[tt];
+      const int lv = CL.level;
+      if (lv <= l) continue;
+      launch_apply_coarse_up(s, CL.P, CL.dno.p, CL.own_ptr.p, CL.own_idx.p, CL.dm.p, CL.yoff.p,
+                             CL.Y.p, CL.moff.p, c->zlev[lv - 1].p, c->zlev[lv].p);
+    }
+    launch_apply_fine_up(s, n, F.dinc_ptr.p, F.dinc_sub.p, F.dinc_q.p, F.doff.p, F.dm.p, F.moff.p,
+                         F.phid_off.p, F.PhiD.p, nullptr, c->zlev[L - 1].p, z, nullptr, 1);
   }
 }
 
@@ -2377,7 +2458,172 @@ int solve_all(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxi
   return status;
 }
 
+// Restarted GMRES with the hybrid form as right preconditioner (Sec. 5): Arnoldi by
+// classical Gram-Schmidt applied twice (the projections of a step in two passes over the
+// basis), the Hessenberg least-squares problem by Givens rotations on the host (one small
+// read-back per iteration), x = x0 + M V y at the end of a cycle.  A cycle ends when the
+// least-squares residual meets rtol ||r_0||; the true residual is then computed, and the
+// solve stops only if it meets the tolerance too (else it restarts from x).
+int gmres_run(msdd_ctx* c, const double* bb, double* xx, double rtol, int restart, int maxit) {
+  hipStream_t s = c->stream;
+  const double t0 = now_ms();
+  const int64_t n = c->n;
+  const int mr = std::max(1, std::min(restart, std::max(maxit, 1)));
+  DVec<double> V, w, zt, hd, part;
+  V.alloc((size_t)(mr + 1) * n);
+  w.alloc(n);
+  zt.alloc(n);
+  hd.alloc((size_t)2 * (mr + 2));
+  part.alloc((size_t)multi_dot_blocks(n) * (mr + 1));
+  double* r = c->r.p;
+  auto true_residual = [&]() {  // r = b - A x; returns ||r||
+    launch_spmv_chunk(s, c->nch, c->spmv_sg, c->ch_lo.p, c->ch_hi.p, c->rowptr.p, c->col.p,
+                      c->val.p, xx, c->q.p, c->partial.p);
+    launch_residual_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, bb, c->q.p, r, c->partial.p);
+    launch_multi_dot(s, n, 1, r, r, part.p, hd.p);
+    double rr = 0.0;
+    HIPCHK(hipMemcpyAsync(&rr, hd.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return std::sqrt(rr);
+  };
+  double beta = true_residual();
+  REQUIRE(std::isfinite(beta), "non-finite right-hand side or initial guess");
+  const double r0 = beta;
+  c->hist.assign(1, r0 > 0 ? 1.0 : 0.0);
+  int its = 0;
+  int status = MSDD_ENOCONV;
+  if (r0 == 0.0) status = MSDD_OK;
+  std::vector<double> H((size_t)(mr + 1) * mr), cs(mr), sn(mr), g(mr + 1), hv(2 * (mr + 2));
+  while (status != MSDD_OK && its < maxit) {
+    const int m = std::min(mr, maxit - its);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    // v_0 = r / beta (beta^2 is still in hd[0])
+    launch_scale_dev(s, n, hd.p, 2, r, V.p);
+    int k_done = 0;
+    bool conv = false;
+    for (int k = 0; k < m; ++k) {
+      double* vk = V.p + (size_t)k * n;
+      apply_hybrid(c, vk, zt.p, s);
+      launch_spmv_chunk(s, c->nch, c->spmv_sg, c->ch_lo.p, c->ch_hi.p, c->rowptr.p, c->col.p,
+                        c->val.p, zt.p, w.p, c->partial.p);
+      // two passes of classical Gram-Schmidt, then the norm
+      launch_multi_dot(s, n, k + 1, V.p, w.p, part.p, hd.p);
+      launch_multi_axpy(s, n, k + 1, V.p, hd.p, w.p);
+      launch_multi_dot(s, n, k + 1, V.p, w.p, part.p, hd.p + (mr + 2));
+      launch_multi_axpy(s, n, k + 1, V.p, hd.p + (mr + 2), w.p);
+      launch_multi_dot(s, n, 1, w.p, w.p, part.p, hd.p + (mr + 1));
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(hv.data(), hd.p, hv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double* Hk = &H[(size_t)k * (mr + 1)];  // column k
+      for (int j = 0; j <= k; ++j) Hk[j] = hv[j] + hv[(mr + 2) + j];
+      const double hn = std::sqrt(std::max(hv[mr + 1], 0.0));
+      REQUIRE(std::isfinite(hn), "GMRES produced a non-finite value");
+      Hk[k + 1] = hn;
+      if (hn > 0.0) launch_scale_dev(s, n, hd.p + (mr + 1), 2, w.p, V.p + (size_t)(k + 1) * n);
+      for (int j = 0; j < k; ++j) {  // earlier rotations on the new column
+        const double a = cs[j] * Hk[j] + sn[j] * Hk[j + 1];
+        Hk[j + 1] = -sn[j] * Hk[j] + cs[j] * Hk[j + 1];
+        Hk[j] = a;
+      }
+      const double d = std::hypot(Hk[k], Hk[k + 1]);
+      cs[k] = Hk[k] / d;
+      sn[k] = Hk[k + 1] / d;
+      Hk[k] = d;
+      Hk[k + 1] = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      ++its;
+      k_done = k + 1;
+      c->hist.push_back(std::fabs(g[k + 1]) / r0);
+      if (std::fabs(g[k + 1]) < rtol * r0 || hn == 0.0) {
+        conv = std::fabs(g[k + 1]) < rtol * r0;
+        break;
+      }
+    }
+    // y = R^{-1} g (upper triangular, column-major in H with ld mr + 1), x += M V y
+    std::vector<double> y(k_done);
+    for (int i = k_done - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int j = i + 1; j < k_done; ++j) t -= H[(size_t)j * (mr + 1) + i] * y[j];
+      y[i] = t / H[(size_t)i * (mr + 1) + i];
+    }
+    HIPCHK(hipMemcpyAsync(hd.p, y.data(), k_done * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_gemv_cols(s, n, k_done, V.p, hd.p, w.p, 0);
+    apply_hybrid(c, w.p, zt.p, s);
+    launch_axpy(s, n, 1.0, zt.p, xx);
+    beta = true_residual();
+    REQUIRE(std::isfinite(beta), "GMRES produced a non-finite value");
+    if (conv && beta < rtol * r0) status = MSDD_OK;
+  }
+  c->last_iters.assign(1, its);
+  c->last_relres.assign(1, r0 > 0 ? beta / r0 : 0.0);
+  c->stats.pcg_iters = its;
+  c->stats.pcg_relres = r0 > 0 ? beta / r0 : 0.0;
+  c->stats.t_solve_ms = now_ms() - t0;
+  return status;
+}
+
 }  // namespace
+
+int msdd_apply_hybrid(msdd_ctx* c, const double* r, double* z) {
+  if (!c) return MSDD_EINVAL;
+  if (!c->ready) return code_for(c, MsddError{MSDD_ESTATE, "msdd_apply_hybrid before a successful setup"});
+  try {
+    HIPCHK(hipSetDevice(c->opt.device));
+    REQUIRE(c->nseg == 1, "the hybrid form is available for single-problem setups");
+    hipStream_t s = c->stream;
+    const int64_t n = c->n;
+    const bool rdev = is_device_ptr(r), zdev = is_device_ptr(z);
+    const double* rin = r;
+    if (!rdev) {
+      HIPCHK(hipMemcpyAsync(c->bvec.p, r, n * sizeof(double), hipMemcpyHostToDevice, s));
+      rin = c->bvec.p;
+    }
+    double* zout = zdev ? z : c->z.p;
+    apply_hybrid(c, rin, zout, s);
+    HIPCHK(hipGetLastError());
+    if (!zdev) HIPCHK(hipMemcpyAsync(z, zout, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MSDD_OK;
+  } catch (const MsddError& e) {
+    return code_for(c, e);
+  }
+}
+
+int msdd_solve_gmres(msdd_ctx* c, const double* b, double* x, double rtol, int32_t restart,
+                     int32_t maxit, int32_t* iters, double* relres) {
+  if (!c) return MSDD_EINVAL;
+  if (!c->ready) return code_for(c, MsddError{MSDD_ESTATE, "msdd_solve_gmres before a successful setup"});
+  try {
+    HIPCHK(hipSetDevice(c->opt.device));
+    REQUIRE(b && x && rtol > 0 && maxit >= 0 && restart >= 1, "bad solve arguments");
+    REQUIRE(c->nseg == 1, "GMRES with the hybrid form is available for single-problem setups");
+    hipStream_t s = c->stream;
+    const int64_t n = c->n;
+    const bool bdev = is_device_ptr(b), xdev = is_device_ptr(x);
+    const double* bb = b;
+    if (!bdev) {
+      HIPCHK(hipMemcpyAsync(c->bvec.p, b, n * sizeof(double), hipMemcpyHostToDevice, s));
+      bb = c->bvec.p;
+    }
+    double* xx = xdev ? x : c->x.p;
+    if (!xdev) HIPCHK(hipMemcpyAsync(xx, x, n * sizeof(double), hipMemcpyHostToDevice, s));
+    const int st = gmres_run(c, bb, xx, rtol, restart, maxit);
+    if (!xdev) {
+      HIPCHK(hipMemcpyAsync(x, xx, n * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    if (iters) *iters = c->stats.pcg_iters;
+    if (relres) *relres = c->stats.pcg_relres;
+    if (st == MSDD_ENOCONV) return code_for(c, MsddError{MSDD_ENOCONV, "GMRES reached maxit"});
+    return st;
+  } catch (const MsddError& e) {
+    return code_for(c, e);
+  }
+}
 
 int msdd_solve_noalloc(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxit,
                        int32_t* iters, double* relres) {

@@ -346,26 +346,32 @@ __global__ void k_apply_coarse_up(const i32* __restrict__ nown, const i64* __res
 }
 
 // finest level, upward and gather: z[p] = sum over subdomains whose Dirichlet space
-// contains p of (u_i + PhiD_i zc_i)[local index of p]
+// contains p of (u_i + PhiD_i zc_i)[local index of p].  Variants for the hybrid form:
+// w (per Dirichlet entry, may be null) weights u_i (restricted additive Schwarz: the
+// partition of unity), u or zc null drops that term, acc adds to z instead of writing it.
 __global__ void k_apply_fine_up(i64 n, const i64* __restrict__ dinc_ptr,
                                 const i32* __restrict__ dinc_sub, const i32* __restrict__ dinc_q,
                                 const i64* __restrict__ doff, const i32* __restrict__ msub,
                                 const i64* __restrict__ moff, const i64* __restrict__ phid_off,
                                 const double* __restrict__ PhiD, const double* __restrict__ u,
-                                const double* __restrict__ zc, double* __restrict__ z) {
+                                const double* __restrict__ zc, double* __restrict__ z,
+                                const double* __restrict__ w, int acc) {
   for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (i64)gridDim.x * blockDim.x) {
     double s = 0.0;
     for (i64 e = dinc_ptr[p]; e < dinc_ptr[p + 1]; ++e) {
       const int i = dinc_sub[e];
       const int q = dinc_q[e];
-      double v = u[doff[i] + q];
-      const int m = msub[i];
-      const double* row = PhiD + phid_off[i] + (i64)q * m;
-      const double* zz = zc + moff[i];
-      for (int c = 0; c < m; ++c) v += row[c] * zz[c];
+      double v = 0.0;
+      if (u) v = w ? w[doff[i] + q] * u[doff[i] + q] : u[doff[i] + q];
+      if (zc) {
+        const int m = msub[i];
+        const double* row = PhiD + phid_off[i] + (i64)q * m;
+        const double* zz = zc + moff[i];
+        for (int c = 0; c < m; ++c) v += row[c] * zz[c];
+      }
       s += v;
     }
-    z[p] = s;
+    z[p] = acc ? z[p] + s : s;
   }
 }
 
@@ -490,9 +496,9 @@ void launch_apply_coarse_up(hipStream_t s, int P, const i32* nown, const i64* ow
 void launch_apply_fine_up(hipStream_t s, i64 n, const i64* dinc_ptr, const i32* dinc_sub,
                           const i32* dinc_q, const i64* doff, const i32* msub, const i64* moff,
                           const i64* phid_off, const double* PhiD, const double* u,
-                          const double* zc, double* z) {
+                          const double* zc, double* z, const double* w, int acc) {
   hipLaunchKernelGGL(k_apply_fine_up, dim3(grid_for(n)), dim3(MSDD_WG), 0, s, n, dinc_ptr,
-                     dinc_sub, dinc_q, doff, msub, moff, phid_off, PhiD, u, zc, z);
+                     dinc_sub, dinc_q, doff, msub, moff, phid_off, PhiD, u, zc, z, w, acc);
 }
 
 // ---------------------------------------------------------------------------
