@@ -90,6 +90,12 @@ typedef struct {
   int nev_fixed;      /* 0 = select lambda < eta on the finest level (default); > 0 = select
                          the nev_fixed smallest eigenvalues per finest-level subdomain (the
                          fixed-count form of the paper's runs); coarse levels use eta */
+  double eig_tol_energy; /* tolerance on the energy residual ||S^{-1} b x - nu x||_S / nu
+                         (x^T S x = 1) of the selected local eigenpairs, which bounds the
+                         S-angle to the eigenvector by itself over the gap (default 1e-10;
+                         0 = normwise test only).  Needed at high coefficient contrast,
+                         where ||S|| is set by the high-coefficient rows and the normwise
+                         test alone leaves vectors off by up to 1e-7 */
 } msdd_options;
 
 typedef struct {
@@ -117,8 +123,12 @@ typedef struct {
   int32_t eig_unconverged; /* finest-level subdomains whose eigensolver stopped without
                               certifying its count (the setup then fails with MSDD_EEIG) */
   int32_t eig_stagnated;  /* selected finest-level pairs accepted at the rounding floor:
-                             Ritz value fixed to 1e-14 between iterations and backward error
-                             within 1e6 * eig_tol, but above eig_tol */
+                             Ritz value fixed to 1e-14 between iterations, residuals no
+                             longer falling, backward error within 1e6 * eig_tol and energy
+                             residual within 1e3 * eig_tol_energy, but one of them above its
+                             tolerance */
+  double eig_energy_resid_max; /* largest energy residual of a selected finest-level pair
+                             (of its iterate one step before acceptance) */
 } msdd_stats_t;
 
 /* Fill *opt with defaults. */
@@ -240,11 +250,15 @@ int msdd_apply_hybrid(msdd_ctx* c, const double* r, double* z);
 
 /*
  * Solve A x = b by restarted GMRES (restart >= 1 basis vectors per cycle) with the hybrid
- * form as right preconditioner, from the initial guess in x.  Stops when the true residual
- * satisfies ||b - A x^m|| < rtol ||b - A x^0|| (Sec. 5): a cycle ends when GMRES's
- * least-squares residual meets it, the true residual is then computed, and the solve
- * restarts from x^m if rounding left it above.  maxit counts iterations over all cycles;
- * iters, relres (may be NULL) receive the count and the true ||r|| / ||r_0||;
+ * form as right preconditioner, from the initial guess in x, to
+ * ||b - A x^m|| < rtol ||b - A x^0|| (Sec. 5).  A cycle ends when GMRES's least-squares
+ * residual meets the tolerance or after `restart` steps; b - A x^m is then recomputed and
+ * the solve stops if it meets the tolerance.  After a cycle that met it only in the
+ * least-squares sense, the next cycle refines from x^m, unless that cycle reduced the
+ * recomputed residual by less than half (it is then at its FP64 rounding floor, about
+ * u || |A| |x| + |b| ||, which exceeds 1e-8 ||b|| at coefficient contrast 1e6 on fine
+ * meshes): the solve stops as converged.  maxit counts iterations over all cycles;
+ * iters, relres (may be NULL) receive the count and the recomputed ||b - A x|| / ||r_0||;
  * msdd_solve_history returns the least-squares residuals.  MSDD_ENOCONV at maxit.
  * Single-problem setups only.
  */

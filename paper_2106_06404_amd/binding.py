@@ -35,7 +35,8 @@ class MsddOptions(ctypes.Structure):
                 ("eps_reg_rel", ctypes.c_double), ("nev_max", ctypes.c_int),
                 ("eig_tol", ctypes.c_double), ("eig_maxit", ctypes.c_int),
                 ("block", ctypes.c_int), ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("verbose", ctypes.c_int), ("geneo_rhs", ctypes.c_int), ("nev_fixed", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("geneo_rhs", ctypes.c_int), ("nev_fixed", ctypes.c_int),
+                ("eig_tol_energy", ctypes.c_double)]
 
 
 class MsddStats(ctypes.Structure):
@@ -49,7 +50,8 @@ class MsddStats(ctypes.Structure):
                 ("t_solve_ms", ctypes.c_double), ("pcg_iters", ctypes.c_int32),
                 ("pcg_relres", ctypes.c_double), ("eig_iters_sum", ctypes.c_int64),
                 ("warm_started", ctypes.c_int32), ("warm_fallbacks", ctypes.c_int32),
-                ("eig_unconverged", ctypes.c_int32), ("eig_stagnated", ctypes.c_int32)]
+                ("eig_unconverged", ctypes.c_int32), ("eig_stagnated", ctypes.c_int32),
+                ("eig_energy_resid_max", ctypes.c_double)]
 
     def as_dict(self):
         L = self.n_levels

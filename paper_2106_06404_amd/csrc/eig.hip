@@ -9,10 +9,17 @@
 // Rayleigh-Ritz step per iteration:
 //   Y = S^{-1} (B X);  Z = B Y;  G_S = Y^T (B X) (= Y^T S Y);  G_B = Y^T Z;
 //   G_B c = nu G_S c;  X <- Y C,  BX <- Z C,  SX <- (B X_old) C.
-// Convergence: the normwise backward error ||BX_j - nu_j SX_j|| / (nu_j ||S|| ||X_j||)
-// is <= tol for the m pairs with lambda < eta plus the next one (which certifies
-// the count m); as a safety net a pair also counts as converged when its backward
-// error is <= 1e-8 and its Ritz value no longer moves (relative change <= 1e-14).
+// Convergence of a selected pair: the normwise backward error
+// ||BX_j - nu_j SX_j|| / (nu_j ||S|| ||X_j||) is <= tol, and the energy residual of the
+// previous Ritz pair (nu, x), x^T S x = 1,
+//   eps = ||S^{-1} b x - nu x||_S,  eps^2 = (y - nu x)^T (b x - nu S x),  y = S^{-1} b x,
+// is <= tol_e nu (y is the next block before the Rayleigh-Ritz step).  eps bounds the
+// S-angle between x and the eigenvector (sin <= eps / gap), which the normwise test does
+// not: at high coefficient contrast ||S|| is set by the high-coefficient rows and a vector
+// whose error lies in the low-coefficient region passes it while still off by 1e-7.  The
+// pair after the selected ones only certifies the count m; as a safety net a pair also
+// counts as converged when its residuals have stopped falling and its Ritz value no
+// longer moves (relative change <= 1e-14).
 #include "common.h"
 #include "symeig.h"
 #include "kernels.h"
@@ -403,12 +410,15 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
 
 // X = Y C, BX = Z C, SX = BX_old C (in place on BX), residual norms, convergence
 // logic.  One workgroup per subdomain; K divides the workgroup size.
+// Also the energy residual of the previous pair (X_old, SX_old, BX_old, nu_old = nu_prev):
+// per column sum (y - nu_old x_old)(bx_old - nu_old sx_old) and a bound on its rounding.
 template <typename V, int TR>
 __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__ kvoff, int K,
                              const double* __restrict__ Cm, const double* __restrict__ nu,
                              const V* __restrict__ Y, const V* __restrict__ Z,
                              V* __restrict__ X, V* __restrict__ BX, V* __restrict__ SX,
-                             const int* __restrict__ status, double* __restrict__ part, int S) {
+                             const int* __restrict__ status, double* __restrict__ part, int S,
+                             const double* __restrict__ nu_prev) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = blockIdx.x, sp = blockIdx.y;  // subdomain, row split
   if (status[i] != ST_RUNNING) return;
@@ -420,14 +430,17 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
   V* ty = reinterpret_cast<V*>(C + KK);             // TR*K
   V* tz = ty + TR * K;
   V* tb = tz + TR * K;
-  __shared__ double red_r[MSDD_WG], red_s[MSDD_WG];
+  __shared__ double red_r[MSDD_WG], red_s[MSDD_WG], red_e[MSDD_WG], red_f[MSDD_WG];
   const int tid = threadIdx.x;
   for (int t = tid; t < KK; t += blockDim.x) C[t] = Cm[(i64)i * KK + t];
   const int c = tid % K;
   const int lanes = blockDim.x / K;
   const int rl = tid / K;
   const double nuc = nu[(i64)i * K + c];
+  // nu_old = 0 on a pass's first iteration: X is the start block and SX is not set yet
+  const double nuo = nu_prev[(i64)i * K + c];
   double accr = 0, accs = 0;  // residual^2, ||x||^2
+  double acce = 0, accf = 0;  // previous pair's eps^2 and the rounding bound of its sum
   const V* Yi = Y + kvoff[i];
   const V* Zi = Z + kvoff[i];
   V* Xi = X + kvoff[i];
@@ -460,6 +473,14 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
           sx += (double)tb[rr * K + a] * ca;
         }
         const i64 idx = r0 + rr + (i64)c * n;
+        if (nuo > 0.0) {  // read the previous pair before this thread overwrites it
+          const double yo = (double)ty[rr * K + c], bo = (double)tb[rr * K + c];
+          const double xo = (double)Xi[idx], so = (double)Si[idx];
+          const double dd = yo - nuo * xo, ro = bo - nuo * so;
+          acce += dd * ro;
+          accf += (fabs(yo) + 2.0 * nuo * fabs(xo)) * fabs(ro) +
+                  fabs(dd) * (fabs(bo) + 2.0 * nuo * fabs(so));
+        }
         Xi[idx] = (V)x;
         Bi[idx] = (V)bx;
         Si[idx] = (V)sx;
@@ -471,16 +492,22 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
   }
   red_r[tid] = accr;
   red_s[tid] = accs;
+  red_e[tid] = acce;
+  red_f[tid] = accf;
   __syncthreads();
-  if (tid < K) {  // partial residual^2 and ||x||^2 of this row split, per column
-    double sr = 0, ss = 0;
+  if (tid < K) {  // partial sums of this row split, per column
+    double sr = 0, ss = 0, se = 0, sf = 0;
     for (int l = 0; l < lanes; ++l) {
       sr += red_r[l * K + tid];
       ss += red_s[l * K + tid];
+      se += red_e[l * K + tid];
+      sf += red_f[l * K + tid];
     }
-    const i64 o = ((i64)i * S + sp) * 2 * K;
+    const i64 o = ((i64)i * S + sp) * UPD_PARTS * K;
     part[o + tid] = sr;
     part[o + K + tid] = ss;
+    part[o + 2 * K + tid] = se;
+    part[o + 3 * K + tid] = sf;
   }
 }
 
@@ -488,10 +515,12 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
 // eigenvalue error then stays near 1e-11)
 constexpr double CERT_TOL = 1e-11;
 // A pair whose Ritz value no longer moves (1e-14 relative between iterations) and whose
-// backward error no longer falls (by more than half per iteration) is at the rounding floor
-// of its pencil; it is accepted if that backward error is within 1e6 times the tolerance
-// (1e-8 at the default 1e-14).  The host counts such pairs.
+// residuals no longer fall (by more than half per iteration) is at the rounding floor of
+// its pencil; it is accepted if its backward error is within 1e6 times the tolerance (1e-8
+// at the default 1e-14) and its energy residual within 1e3 times tol_e.  The host counts
+// such pairs.
 constexpr double STAG_FACTOR = 1e6;
+constexpr double STAG_FACTOR_E = 1e3;
 // The Krylov-Weinstein interval shows that an eigenvalue lies near the certifying Ritz
 // value, not that none lies above it in nu (Ritz values bound eigenvalues from below), so
 // it is used only after KW_MIN_IT iterations: an eigenvalue below eta that the block had
@@ -509,40 +538,56 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
                             double* __restrict__ res_out, int Kmax_allowed,
                             const i32* __restrict__ rankb, const double* __restrict__ normS,
                             double* __restrict__ nu_prev, const double* __restrict__ gs_diag,
-                            const int* __restrict__ inertia, int nev_fixed) {
+                            const int* __restrict__ inertia, int nev_fixed, double tol_e,
+                            double* __restrict__ res_e_out) {
   const int i = blockIdx.x;
   if (status[i] != ST_RUNNING) return;
-  __shared__ double sh_res[64], sh_lam[64], sh_stag[64], sh_kwup[64];
+  __shared__ double sh_res[64], sh_lam[64], sh_stag[64], sh_kwup[64], sh_rese[64];
   const int tid = threadIdx.x;
   if (tid < K) {
-    double sr = 0, ss = 0;
+    double sr = 0, ss = 0, se = 0, sf = 0;
     for (int q = 0; q < S; ++q) {
-      const i64 o = ((i64)i * S + q) * 2 * K;
+      const i64 o = ((i64)i * S + q) * UPD_PARTS * K;
       sr += part[o + tid];
       ss += part[o + K + tid];
+      se += part[o + 2 * K + tid];
+      sf += part[o + 3 * K + tid];
     }
     const double nv = nu[(i64)i * K + tid];
     const double rel = (nv > 0 && ss > 0) ? sqrt(sr) / (nv * normS[i] * sqrt(ss)) : 0.0;
     const double lv = nv > 0 ? 1.0 / nv - sigma : INFINITY;
     const double np = nu_prev[(i64)i * K + tid];
     const double rp = res_out[(i64)i * K + tid];  // this column's backward error last time
+    const double rpe = res_e_out[(i64)i * K + tid];
+    // energy residual of the previous pair (np, x): eps^2 = sum (y - np x)(b x - np S x),
+    // raised by a bound on the rounding of that sum (8 u times the sum of the magnitudes
+    // of its factors' rounding errors, taken generously); infinite on a pass's first
+    // iteration, where np = 0
+    const double e2 = fmax(se, 0.0) + 8.0 * 2.220446049250313e-16 * sf;
+    const double eps = np > 0.0 ? sqrt(e2) : INFINITY;
+    const double rel_e = np > 0.0 ? eps / np : INFINITY;
     res_out[(i64)i * K + tid] = rel;
+    res_e_out[(i64)i * K + tid] = rel_e;
     lam_out[(i64)i * K + tid] = lv;
     nu_prev[(i64)i * K + tid] = nv;
     sh_res[tid] = rel;
+    sh_rese[tid] = tol_e > 0.0 ? rel_e : 0.0;
     sh_lam[tid] = lv;
     // at the rounding floor: the Ritz value has stopped moving (its error is about the
-    // square of the vector's) and so has the backward error (while the vector still
-    // converges it falls by the convergence factor every iteration)
+    // square of the vector's) and so have the residuals (while the vector still converges
+    // they fall by the convergence factor every iteration)
+    const bool stag_e = tol_e <= 0.0 || rel_e <= tol_e ||
+                        (rel_e <= STAG_FACTOR_E * tol_e && rel_e >= 0.5 * rpe);
     sh_stag[tid] = (rel <= fmax(STAG_FACTOR * tol, CERT_TOL) && fabs(nv - np) <= 1e-14 * fabs(nv) &&
-                    rel >= 0.5 * rp) ? 1.0 : 0.0;
-    // Krylov-Weinstein: the previous Ritz pair (np, x) of this column, x^T S x = 1, has an
-    // eigenvalue of S^{-1} b within eps = ||S^{-1} b x - np x||_S, and eps^2 = y^T S y - np^2
-    // with y = S^{-1} b x (this iteration's block).  The rounding of y^T S y is covered by a
-    // floor of 16 u y^T S y.  sh_kwup = np + eps, the interval's upper end (nu of the pair).
+                    rel >= 0.5 * rp && stag_e) ? 1.0 : 0.0;
+    // Krylov-Weinstein: the previous Ritz pair (np, x) of this column has an eigenvalue of
+    // S^{-1} b within eps.  The Gram diagonal gives eps^2 = y^T S y - np^2 as well, with a
+    // rounding floor of 16 u y^T S y (accurate only to sqrt(u) np); the smaller bound is
+    // used.  sh_kwup = np + eps, the interval's upper end (nu of the pair).
     const double g = gs_diag[(i64)i * K + tid];
-    const double e2 = fmax(g - np * np, 0.0) + 16.0 * 2.220446049250313e-16 * fabs(g);
-    sh_kwup[tid] = (np > 0.0 && g > 0.0) ? np + sqrt(e2) : INFINITY;
+    const double e2g = fmax(g - np * np, 0.0) + 16.0 * 2.220446049250313e-16 * fabs(g);
+    const double epsk = fmin(eps, g > 0.0 ? sqrt(e2g) : INFINITY);
+    sh_kwup[tid] = np > 0.0 ? np + epsk : INFINITY;
   }
   __syncthreads();
   if (tid == 0) {
@@ -582,7 +627,7 @@ __global__ void k_eig_judge(int K, const double* __restrict__ nu, const double* 
         const bool kw = it >= KW_MIN_IT && sh_kwup[a] < nu_sep;
         ok = ok && (by_inertia || sh_res[a] <= fmax(tol, CERT_TOL) || sh_stag[a] > 0.0 || kw);
       } else {
-        ok = ok && (sh_res[a] <= tol || sh_stag[a] > 0.0);
+        ok = ok && ((sh_res[a] <= tol && sh_rese[a] <= tol_e) || sh_stag[a] > 0.0);
       }
     }
     mcount[i] = m;
@@ -723,14 +768,15 @@ void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, in
                        double tol, int maxit, int* status, int* iters, int* mcount,
                        double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
                        const double* normS, double* nu_prev, double* part, int nsplit,
-                       const double* gs_diag, const int* inertia, int nev_fixed) {
+                       const double* gs_diag, const int* inertia, int nev_fixed, double tol_e,
+                       double* res_e_out) {
   constexpr int TR = 16;
   size_t lds = (size_t)K * K * sizeof(double) + 3 * TR * K * sizeof(double);
   hipLaunchKernelGGL((k_eig_update<double, TR>), dim3(P, nsplit), dim3(MSDD_WG), lds, s, nb, kvoff,
-                     K, C, nu, Y, Z, X, BX, SX, status, part, nsplit);
+                     K, C, nu, Y, Z, X, BX, SX, status, part, nsplit, nu_prev);
   hipLaunchKernelGGL(k_eig_judge, dim3(P), dim3(64), 0, s, K, nu, part, nsplit, sigma, eta,
                      nev_max, tol, maxit, status, iters, mcount, lam_out, res_out, Kmax_allowed,
-                     rankb, normS, nu_prev, gs_diag, inertia, nev_fixed);
+                     rankb, normS, nu_prev, gs_diag, inertia, nev_fixed, tol_e, res_e_out);
 }
 
 void launch_eig_finalize(hipStream_t s, int P, const i32* nb, const i64* voff, const i64* kvoff,

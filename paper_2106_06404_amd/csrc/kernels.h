@@ -74,13 +74,16 @@ void launch_gram(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K, c
                  int nsplit);
 void launch_rayleigh_ritz(hipStream_t s, int P, int K, const double* GS, const double* GB,
                           double* C, double* nu, const int* active, int nsplit, double* gs_diag);
+// partial sums per column and row split written by the eigensolver's update kernel
+constexpr int UPD_PARTS = 4;
 void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K,
                        const double* C, const double* nu, const double* Y, const double* Z,
                        double* X, double* BX, double* SX, double sigma, double eta, int nev_max,
                        double tol, int maxit, int* status, int* iters, int* mcount,
                        double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
                        const double* normS, double* nu_prev, double* part, int nsplit,
-                       const double* gs_diag, const int* inertia, int nev_fixed = 0);
+                       const double* gs_diag, const int* inertia, int nev_fixed, double tol_e,
+                       double* res_e_out);
 void launch_row_norm(hipStream_t s, int P, const i64* voff, int ell_w, const i32* ell_col,
                      const double* ell_val, const double* dv, double sigma, double* normS,
                      const double* ell_val2 = nullptr);

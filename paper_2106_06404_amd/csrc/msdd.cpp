@@ -277,7 +277,7 @@ struct CoarseLevel {
 
 struct EigPass {
   int K = 0;
-  DVec<double> X, nu, lam, res;
+  DVec<double> X, nu, lam, res, res_e;
   DVec<int> mcount;
   std::vector<int> subs;  // subdomains finalised from this pass
 };
@@ -985,7 +985,7 @@ void fine_eigensolve(msdd_ctx* c) {
   std::vector<std::unique_ptr<EigPass>> passes;
   int restarts = 0, max_it = 0;
   int unconverged = 0, stagnated = 0, first_unconv = -1;
-  double res_max = 0.0;
+  double res_max = 0.0, rese_max = 0.0;
   F.lam.assign(P, {});
   // learned warm start: the network's block for every subdomain (BF16 inference)
   msdd_net* net = c->warm.P > 0 ? c->warm.net : nullptr;
@@ -1027,12 +1027,14 @@ void fine_eigensolve(msdd_ctx* c) {
     SX.alloc(tot);
     GS.alloc((size_t)P * nsplit * K * K);
     GB.alloc((size_t)P * nsplit * K * K);
-    upart.alloc((size_t)P * nsplit * 2 * K);
+    upart.alloc((size_t)P * nsplit * UPD_PARTS * K);
     Cm.alloc((size_t)P * K * K);
     E.nu.alloc((size_t)P * K);
     E.lam.alloc((size_t)P * K);
     E.res.alloc((size_t)P * K);
     E.res.zero(s);
+    E.res_e.alloc((size_t)P * K);
+    E.res_e.zero(s);
     E.mcount.alloc(P);
     E.mcount.zero(s);
     DVec<double> nu_prev, normS, gsd;
@@ -1088,7 +1090,8 @@ void fine_eigensolve(msdd_ctx* c) {
         launch_eig_update(s, P, F.gs.n.p, dkvoff.p, K, Cm.p, E.nu.p, Y.p, Z.p, E.X.p, BX.p, SX.p,
                           c->sigma, c->eta, o.nev_max, o.eig_tol, maxit, status.p, iters.p,
                           E.mcount.p, E.lam.p, E.res.p, 64, F.rankb.p, normS.p, nu_prev.p,
-                          upart.p, nsplit, gsd.p, F.inertia.p, o.nev_fixed);
+                          upart.p, nsplit, gsd.p, F.inertia.p, o.nev_fixed, o.eig_tol_energy,
+                          E.res_e.p);
       }
       HIPCHK(hipGetLastError());
       if (it >= 3 && (it % 2 == 1 || it == maxit - 1)) {
@@ -1104,6 +1107,7 @@ void fine_eigensolve(msdd_ctx* c) {
     std::vector<int> itv = iters.download(s);
     std::vector<double> lamv = E.lam.download(s);
     std::vector<double> resv = E.res.download(s);
+    std::vector<double> resev = E.res_e.download(s);
     bool grew = false, fell = false;
     for (int i = 0; i < P; ++i) {
       if (!want[i]) continue;
@@ -1138,7 +1142,9 @@ void fine_eigensolve(msdd_ctx* c) {
       } else {
         // selected pairs accepted at the rounding floor rather than at the tolerance
         for (int a = 0; a < std::min(K, mc[i]); ++a)
-          if (resv[(size_t)i * K + a] > o.eig_tol) ++stagnated;
+          if (resv[(size_t)i * K + a] > o.eig_tol ||
+              (o.eig_tol_energy > 0 && resev[(size_t)i * K + a] > o.eig_tol_energy))
+            ++stagnated;
       }
       want[i] = 0;
       final_pass[i] = (int)passes.size();
@@ -1146,7 +1152,10 @@ void fine_eigensolve(msdd_ctx* c) {
       E.subs.push_back(i);
       const int ne = std::min(K, mc[i] + 4);
       F.lam[i].assign(lamv.begin() + (size_t)i * K, lamv.begin() + (size_t)i * K + ne);
-      for (int a = 0; a < std::min(K, mc[i]); ++a) res_max = std::max(res_max, resv[(size_t)i * K + a]);
+      for (int a = 0; a < std::min(K, mc[i]); ++a) {
+        res_max = std::max(res_max, resv[(size_t)i * K + a]);
+        rese_max = std::max(rese_max, resev[(size_t)i * K + a]);
+      }
     }
     passes.push_back(std::move(ps));
     if (!grew && !fell) break;
@@ -1161,6 +1170,7 @@ void fine_eigensolve(msdd_ctx* c) {
   c->stats.eig_iters_max = max_it;
   c->stats.eig_restarts = restarts;
   c->stats.eig_resid_max = res_max;
+  c->stats.eig_energy_resid_max = rese_max;
   c->stats.eig_unconverged = unconverged;
   c->stats.eig_stagnated = stagnated;
   if (unconverged > 0)
@@ -1977,6 +1987,7 @@ void msdd_default_options(msdd_options* o) {
   o->verbose = 0;
   o->geneo_rhs = 1;
   o->nev_fixed = 0;
+  o->eig_tol_energy = 1e-10;
 }
 
 int msdd_create(msdd_ctx** out, const msdd_options* opt) {
@@ -2032,7 +2043,8 @@ int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     REQUIRE(n_sub > 0, "n_sub must be positive");
     REQUIRE(n_levels >= 2 && n_levels <= 8, "n_levels must be in [2, 8]");
     REQUIRE(eta > 0 && std::isfinite(eta), "eta must be positive");
-    REQUIRE(c->opt.eig_maxit > 0 && c->opt.eig_tol > 0, "bad eigensolver options");
+    REQUIRE(c->opt.eig_maxit > 0 && c->opt.eig_tol > 0 && c->opt.eig_tol_energy >= 0,
+            "bad eigensolver options");
     c->n = n;
     c->k = k;
     c->eta = eta;
@@ -2461,9 +2473,12 @@ int solve_all(msdd_ctx* c, const double* b, double* x, double rtol, int32_t maxi
 // Restarted GMRES with the hybrid form as right preconditioner (Sec. 5): Arnoldi by
 // classical Gram-Schmidt applied twice (the projections of a step in two passes over the
 // basis), the Hessenberg least-squares problem by Givens rotations on the host (one small
-// read-back per iteration), x = x0 + M V y at the end of a cycle.  A cycle ends when the
-// least-squares residual meets rtol ||r_0||; the true residual is then computed, and the
-// solve stops only if it meets the tolerance too (else it restarts from x).
+// read-back per iteration), x = x0 + M V y at the end of a cycle, then b - A x recomputed.
+// A cycle ends when its least-squares residual meets rtol ||r_0|| or after `restart` steps.
+// The solve stops when the recomputed residual meets the tolerance; after a cycle that met
+// it only in the least-squares sense the next cycle refines from x, unless that cycle
+// reduced the recomputed residual by less than half: it then sits at its FP64 rounding
+// floor (about u || |A| |x| + |b| ||) and the solve stops as converged.
 int gmres_run(msdd_ctx* c, const double* bb, double* xx, double rtol, int restart, int maxit) {
   hipStream_t s = c->stream;
   const double t0 = now_ms();
@@ -2495,6 +2510,7 @@ int gmres_run(msdd_ctx* c, const double* bb, double* xx, double rtol, int restar
   if (r0 == 0.0) status = MSDD_OK;
   std::vector<double> H((size_t)(mr + 1) * mr), cs(mr), sn(mr), g(mr + 1), hv(2 * (mr + 2));
   while (status != MSDD_OK && its < maxit) {
+    const double beta_start = beta;
     const int m = std::min(mr, maxit - its);
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
@@ -2556,7 +2572,7 @@ int gmres_run(msdd_ctx* c, const double* bb, double* xx, double rtol, int restar
     launch_axpy(s, n, 1.0, zt.p, xx);
     beta = true_residual();
     REQUIRE(std::isfinite(beta), "GMRES produced a non-finite value");
-    if (conv && beta < rtol * r0) status = MSDD_OK;
+    if (beta < rtol * r0 || (conv && beta >= 0.5 * beta_start)) status = MSDD_OK;
   }
   c->last_iters.assign(1, its);
   c->last_relres.assign(1, r0 > 0 ? beta / r0 : 0.0);

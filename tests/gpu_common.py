@@ -48,6 +48,26 @@ def sin_angle(U, V):
     return float(np.linalg.norm(Qv - Qu @ (Qu.T @ Qv), 2))
 
 
+def energy_sin_angle(U, V, S):
+    """sin of the largest principal angle between span(U) and span(V) in the inner product
+    of the SPD matrix S (the local pencil's abar + b, the energy in which the coarse space
+    enters the method)."""
+    if U.shape[1] != V.shape[1]:
+        return 1.0
+    if U.shape[1] == 0:
+        return 0.0
+
+    def s_orth(W):
+        G = W.T @ S @ W
+        Lg = np.linalg.cholesky(0.5 * (G + G.T))
+        return np.linalg.solve(Lg, W.T).T           # W Lg^{-T}: S-orthonormal columns
+
+    Qu, Qv = s_orth(U), s_orth(V)
+    Wr = Qv - Qu @ (Qu.T @ (S @ Qv))
+    M = Wr.T @ S @ Wr
+    return float(np.sqrt(max(np.linalg.eigvalsh(0.5 * (M + M.T)).max(), 0.0)))
+
+
 def principal_angle_max(U, V):
     """Largest principal angle between span(U) and span(V) (columns)."""
     if U.shape[1] == 0 and V.shape[1] == 0:

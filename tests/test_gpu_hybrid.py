@@ -13,12 +13,14 @@ rounding -- two levels (level 0 is the Galerkin matrix of the finest spaces), an
 four levels at contrast 1 -- within
     64 u (|| |A| |z| || / || r ||) + 1e-12
 relative (z the oracle's result: the first-order effect of relative rounding of a few tens of
-u in the products A z of every level's correction).  Every case is compared through GMRES:
-the true residual below the tolerance, the solution within the accuracy the true-residual
-stopping rule fixes, ||x - x*||_A / ||x*||_A <= sqrt(kappa) 1e-8 against a dense direct solve,
-and, where the applies agree elementwise, the iteration count within +-2 of the oracle's (the
-true-residual check after a cycle can add a short second cycle on one side only: its margin
-is at the rounding level); where the two operators differ by up to ~1e-6 the Krylov
+u in the products A z of every level's correction).  Every case is compared through GMRES,
+which stops on its least-squares residual: the recomputed residual below the tolerance plus
+64 times its FP64 rounding floor u || |A| |x| + |b| ||, the solution within the accuracy that
+fixes, ||x - x*||_A / ||x*||_A <= sqrt(kappa) 1e-8 against a dense direct solve, and, where the
+applies agree elementwise, the iteration at which the least-squares residual first meets
+the tolerance within +-1 of the oracle's (the refinement cycle that may follow is decided by
+the recomputed residual against the tolerance, a comparison at the rounding level, so it
+can be taken on one side only); where the two operators differ by up to ~1e-6 the Krylov
 iterations are not comparable step by step and only the converged solutions are."""
 import numpy as np
 import pytest
@@ -73,17 +75,24 @@ def test_hybrid_apply_and_gmres_against_oracle(case):
     ro = o.solve_gmres(rtol=1e-8)
     print(f"{case}: GMRES iterations {it} (oracle {ro.iters}), true relres {rel:.2e}")
     assert ro.converged
+    h = m.history()
+    assert len(h) == it + 1
+    first_g = int(np.argmax(h < 1e-8))
+    first_o = int(np.argmax(np.array(ro.resnorms) < 1e-8 * ro.resnorms[0]))
+    print(f"{case}: least-squares residual below the tolerance at {first_g} (oracle {first_o})")
+    assert first_g > 0 and first_o > 0
     if elementwise:
-        assert abs(it - ro.iters) <= 2
+        assert abs(first_g - first_o) <= 1
     Ad = A.toarray()
-    assert np.linalg.norm(prob.b - Ad @ xg) < 1e-8 * np.linalg.norm(prob.b)
-    assert rel < 1e-8
+    bn = np.linalg.norm(prob.b)
+    floor = u * np.linalg.norm(abs(A) @ np.abs(xg) + np.abs(prob.b)) / bn
+    assert np.linalg.norm(prob.b - Ad @ xg) / bn < 1e-8 + 64 * floor
+    assert rel < 1e-8 + 64 * floor
     xs = np.linalg.solve(Ad, prob.b)
     kap = np.linalg.cond(Ad)
     e = xg - xs
     assert np.sqrt(e @ Ad @ e) <= np.sqrt(kap) * 1e-8 * np.sqrt(xs @ Ad @ xs)
-    h = m.history()
-    assert len(h) == it + 1 and h[-1] < 1e-8
+    assert h[-1] < 1e-8
     m.close()
 
 
