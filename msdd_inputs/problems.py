@@ -458,6 +458,34 @@ def config2(seed: int = 2) -> Problem:
                          groups=(4,))
 
 
+def islands_levels(P: int, n_levels: int, factor: int = 4):
+    """Coarse groupings for a P x P box partition: each coarser level groups factor x factor
+    boxes of the next finer one (fewer where P runs out), level 0 being one subdomain."""
+    groups, cur = [], P
+    for _ in range(n_levels - 2):
+        nxt = max(1, cur // factor)
+        if nxt == cur:
+            raise ValueError("too many levels for this partition")
+        groups.append(nxt)
+        cur = nxt
+    return tuple(groups)
+
+
+def table3_islands(P: int, n_levels: int, seed: int = 3, elems_per_sub: int = 80,
+                   delta: int = 3, eta: float = 0.3, factor: int = 4) -> Problem:
+    """Weak-scaling workload of the Islands problem's shape (Table 3 of the paper): P x P
+    subdomains of elems_per_sub^2 Q1 elements each (N = P * elems_per_sub), overlap delta = 3
+    element layers, eta = 0.3, Dirichlet on the two planes x = 0 and x = 1 and homogeneous
+    Neumann elsewhere.  The paper's island field is given only as a figure; the stand-in is
+    the seeded square-inclusion field (k = 1e6 on squares of 2-8 elements covering 10% of the
+    domain, 1 elsewhere), whose islands per subdomain stay statistically fixed as P grows."""
+    N = P * elems_per_sub
+    k = inclusions_2d(N, seed)
+    return build_problem(f"t3_islands_{P}x{P}_L{n_levels}", 2, N, k, P=P, delta=delta,
+                         n_levels=n_levels, eta=eta, groups=islands_levels(P, n_levels, factor),
+                         bc="x01")
+
+
 def config3(E_fibre: float = 1e3, nu: float = 0.3) -> Problem:
     """48^3 trilinear elasticity, 16 plies 3 elements thick (fibre 0/90 deg alternating with
     resin), clamped at x=0, body force -z; 6^3 boxes, overlap 1, 3 levels (216 -> 27 -> 1)."""
