@@ -74,6 +74,12 @@ void launch_gram(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K, c
                  int nsplit);
 void launch_rayleigh_ritz(hipStream_t s, int P, int K, const double* GS, const double* GB,
                           double* C, double* nu, const int* active, int nsplit, double* gs_diag);
+// Cholesky factorisation of one large SPD matrix A (n x n, column-major, overwritten by L
+// with the upper triangle zeroed), Linv = L^{-1} and Inv = A^{-1} (full, symmetric), in
+// 64 x 64 tiles over the whole device; status[0] is set to ST_NOTSPD on a non-positive
+// pivot (left untouched otherwise).  Linv and Inv: n x n each.
+void launch_blocked_spd_inverse(hipStream_t s, int n, double* A, double* Linv, double* Inv,
+                                int* status);
 // partial sums per column and row split written by the eigensolver's update kernel
 constexpr int UPD_PARTS = 4;
 void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, int K,

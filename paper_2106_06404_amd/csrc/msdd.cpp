@@ -1690,6 +1690,10 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
 // Level 0: one dense block per problem (a single problem: A_0 itself), assembled from
 // the patches of level 1 (Sec. 4.1), factorised and inverted.  prob[i] = problem of
 // level-1 subdomain i (nondecreasing).
+// above this size the coarsest space of a single problem is factorised by tiles over the
+// whole device instead of by one workgroup
+constexpr int kBlockedCoarsest = 384;
+
 void coarsest(msdd_ctx* c, const PatchLevel& PL, const std::vector<int32_t>& m_lvl1,
               const std::vector<int32_t>& prob, int nprob) {
   hipStream_t s = c->stream;
@@ -1710,7 +1714,11 @@ void coarsest(msdd_ctx* c, const PatchLevel& PL, const std::vector<int32_t>& m_l
   int nmax = 0;
   for (int t = 0; t < nprob; ++t) {
     J.ng[t] = (int32_t)(zoff[t + 1] - zoff[t]);
-    REQUIRE(J.ng[t] <= 8192, "coarsest space of a problem larger than 8192 (add a level)");
+    // one problem: tiled factorisation over the whole device (three n_0^2 matrices);
+    // a batch: one workgroup per problem
+    REQUIRE(J.ng[t] <= (nprob == 1 ? 32768 : 8192),
+            nprob == 1 ? "coarsest space larger than 32768 (add a level)"
+                       : "coarsest space of a batch member larger than 8192 (add a level)");
     J.aoff[t + 1] = J.aoff[t] + (int64_t)J.ng[t] * J.ng[t];
     nmax = std::max(nmax, J.ng[t]);
   }
@@ -1742,6 +1750,25 @@ void coarsest(msdd_ctx* c, const PatchLevel& PL, const std::vector<int32_t>& m_l
     return;
   }
   run_assemble(c, J, PL, c->A0);
+  if (nprob == 1 && nmax > kBlockedCoarsest) {
+    // factor, L^{-1} and the explicit inverse by 64 x 64 tiles over every compute unit
+    std::vector<int> ok(1, ST_DONE);
+    DVec<int> st;
+    st.upload(ok, s);
+    DVec<double> Linv;
+    Linv.alloc((size_t)nmax * nmax);
+    c->A0inv.alloc((size_t)nmax * nmax);
+    const double nn = (double)nmax;
+    {
+      ProfScope ps(c, PR_COARSE, 6.0 * nn * nn * 8.0, nn * nn * nn);
+      launch_blocked_spd_inverse(s, nmax, c->A0.p, Linv.p, c->A0inv.p, st.p);
+    }
+    HIPCHK(hipGetLastError());
+    if (st.download(s)[0] != ST_DONE)
+      throw MsddError{MSDD_ENOTSPD, "coarsest matrix A_0 is not positive definite"};
+    HIPCHK(hipStreamSynchronize(s));
+    return;
+  }
   DVec<int> st;
   st.alloc(nprob);
   double fl = 0.0, by = 0.0;

@@ -288,6 +288,26 @@ def test_mixed_precision_against_oracle(case):
           f"oracle {_rel(x32, ro.x):.2e}, true residual {tr32:.2e} (oracle {tr_o:.2e})")
 
 
+@pytest.mark.parametrize("N,Pn", [(64, 16), (96, 24)])
+def test_large_coarsest_tiled(N, Pn):
+    """Two levels with 256 and 576 subdomains: the coarsest spaces (781 and 1883 functions,
+    neither a multiple of the 64-row tile) are factorised and inverted by the tiled
+    whole-device kernels.  The apply, PCG and solution against the oracle."""
+    prob = P.small_problem(N=N, P=Pn, delta=1, contrast=1e4, seed=5)
+    o = Oracle(prob, fine_vectors=8)
+    m, _ = _setup(prob)
+    assert m.stats()["n"] == o.level_sizes()
+    assert o.level_sizes()[0] > 384 and o.level_sizes()[0] % 64
+    _check_fine_level(m, o, prob, prob.eta)
+    for seed in (0, 1):
+        assert _apply_rel(m, o, prob, seed) < APPLY_BAR
+    it, rel, x = _solve(m, prob)
+    ro = o.solve()
+    assert abs(it - ro.iters) <= 1
+    assert _rel(x, ro.x) < 1e-8
+    m.close()
+
+
 def test_single_subdomain_empty_coarse_space():
     prob = P.small_problem(N=10, P=1, delta=0, contrast=1e3, seed=3)
     m, _ = _setup(prob)
