@@ -161,16 +161,116 @@ def train_warm_start(members, t_gen, verbose=False):
     return net, info
 
 
+# Table 3 of the paper (Q1, overlap 3h, eta = 0.3, CG): coarsest-space size n_0 and CG
+# iterations per subdomain count and level count, quoted beside the measured ones.
+TABLE3 = {64: {"dofs": 410881, 2: (306, 25)},
+          256: {"dofs": 1640961, 2: (1348, 26), 3: (130, 32)},
+          1024: {"dofs": 6558721, 2: (5523, 27), 3: (431, 31), 4: (207, 40)}}
+
+
+def bench_islands(args):
+    """Weak scaling on the islands shape of Table 3: P x P subdomains of 80 x 80 Q1 elements,
+    overlap 3, eta 0.3, Dirichlet on x = 0 and x = 1; one setup + PCG (to 1e-8) per case, and
+    GMRES with the hybrid form on the same setup.  Cases 'P:L[:factor]' (coarse levels group
+    factor x factor subdomains)."""
+    import torch
+    from msdd_inputs import problems as P
+    from paper_2106_06404_amd import binding as B
+    cases = [tuple(int(v) for v in c.split(":")) for c in args.islands.split(",")]
+    u = 2.0 ** -53
+    rows = []
+    for cs in cases:
+        Ps, L = cs[0], cs[1]
+        fac = cs[2] if len(cs) > 2 else 4
+        prob = P.table3_islands(Ps, L, factor=fac)
+        print(f"islands P={Ps}x{Ps} L={L} factor={fac}: n={prob.n}", file=sys.stderr, flush=True)
+        arrs = B.problem_arrays(prob, device="cuda:0")
+        b = torch.from_numpy(prob.b).cuda()
+        torch.cuda.synchronize()
+        m = B.Msdd(verbose=1 if args.verbose else 0)
+        rec = {}
+        for rep in range(max(1, args.steps)):
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m.setup(**arrs)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            it, rel, _ = m.solve(b, x, 1e-8, 2000)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            rec.setdefault("setup", []).append(t1 - t0)
+            rec.setdefault("solve", []).append(t2 - t1)
+        st = m.stats()
+        xg = torch.zeros_like(b)
+        t3 = time.perf_counter()
+        itg, relg, _ = m.solve_gmres(b, xg, 1e-8, 300, 600, allow_noconv=True)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t3
+        xc = x.cpu().numpy()
+        bn = float(np.linalg.norm(prob.b))
+        paper = TABLE3.get(Ps * Ps, {})
+        rows.append({
+            "subdomains": Ps * Ps, "levels": L, "group_factor": fac, "dofs": prob.n,
+            "setup_s": float(np.median(rec["setup"])), "solve_s": float(np.median(rec["solve"])),
+            "cg_iters": it, "n0": st["n"][0], "level_sizes": st["n"],
+            "cg_true_relres": float(np.linalg.norm(prob.b - prob.A @ xc) / bn),
+            "fp64_residual_floor": float(u * np.linalg.norm(abs(prob.A) @ np.abs(xc)
+                                                             + np.abs(prob.b)) / bn),
+            "hybrid_gmres_iters": itg, "hybrid_gmres_s": tg,
+            "eig_iters_max": st["eig_iters_max"], "t_gevp_ms": st["t_gevp_ms"],
+            "t_coarse_ms": st["t_coarse_ms"], "t_local_ms": st["t_local_ms"],
+            "t_plan_ms": st["t_plan_ms"],
+            "paper": ({"dofs": paper["dofs"], "n0": paper[L][0], "cg_iters": paper[L][1]}
+                      if L in paper else None)})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        m.close()
+        del arrs, b, x, xg
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "islands weak scaling (Table 3 shape)", "steps": args.steps,
+                      "data": "synthetic (seeded inclusion field standing in for the paper's "
+                              "island field)", "cases": rows}))
+
+
 def make_problem(name):
     from msdd_inputs import problems as P
     return {"c1": P.config1, "c2": P.config2}[name]()
 
 
-def cpu_baseline(prob, budget_s=20.0):
+def host_cores():
+    """(cores the oracle may use, logical CPUs the process may run on, CPUs the host has).
+    A one-GPU share of the GPU hosts is 16 cores, whatever the machine has in all."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return min(16, avail), avail, os.cpu_count() or 1
+
+
+def full_oracle_run(name):
+    """The full oracle run (setup and PCG) of the workload as measured when its stored
+    expected values were written (tests/golden/<name>_oracle.json), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    t = g.get("oracle_seconds")
+    if not t:
+        return None
+    return {"setup_s": t["setup"], "solve_s": t["solve"], "total_s": t["setup"] + t["solve"],
+            "pcg_iters": g["pcg"]["iters"], "workers": t.get("workers"),
+            "host_cpus": t.get("host_cpus"),
+            "where": "the build host (8 CPUs), not the GPU host: measured once, when the "
+                     "stored expected values were written"}
+
+
+def cpu_baseline(prob, name, budget_s=20.0):
     """The oracle (plain CPU FP64) on a bounded sample of the same workload: the finest-level
     per-subdomain work (Neumann matrix, GEVP, Dirichlet Cholesky) for interior subdomains,
-    until the time budget is spent; extrapolated linearly to all subdomains."""
-    cores = min(16, os.cpu_count() or 1)
+    until the time budget is spent; extrapolated linearly to all subdomains.  The full
+    oracle run of the workload, where one was recorded, is attached beside it."""
+    cores, avail, ncpu = host_cores()
     os.environ["ORACLE_THREADS"] = str(cores)
     from oracle import msdd_oracle as O
     P = prob.n_sub
@@ -195,7 +295,8 @@ def cpu_baseline(prob, budget_s=20.0):
             "sample": (f"{done} of {P} finest-level subdomains (Neumann matrix + GEVP by Cholesky "
                        f"and Jacobi + Dirichlet Cholesky), {per:.2f} s each, extrapolated x{P}; "
                        f"coarse levels and PCG not timed"),
-            "local_gevps_per_s": 1.0 / per}
+            "local_gevps_per_s": 1.0 / per, "cpus_available": avail, "cpus_host": ncpu,
+            "full_oracle_run": full_oracle_run(name)}
 
 
 def roofline_entry(name, rec, counters=True):
@@ -260,7 +361,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4", "islands"])
+    ap.add_argument("--islands", default="8:2,16:2,16:3,32:3,32:4:2",
+                    help="islands cases P:L[:factor], comma separated (--workload islands)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the launch shapes chosen by problem shape (no msdd_autotune)")
@@ -279,6 +382,9 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         bench_batch(args)
+        return
+    if args.workload == "islands":
+        bench_islands(args)
         return
     import torch
     from paper_2106_06404_amd import binding as B
@@ -451,7 +557,7 @@ def main():
         }
         net.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob)
+        out["cpu_baseline"] = cpu_baseline(prob, args.workload)
     if args.verbose:
         for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0]):
             if v[1]:
