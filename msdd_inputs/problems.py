@@ -200,6 +200,10 @@ class Problem:
     eta: float
     coeff: Optional[np.ndarray] = None  # per-element scalar coefficient (diffusion) or material id
     box_shape: Optional[tuple] = None   # subdomains per dimension on the finest level
+    # Dirichlet subspace of a finest subdomain: "support" = the dofs all of whose elements lie
+    # in the subdomain (conforming elements); "all" = every dof of the subdomain (DG and
+    # finite volumes, whose basis functions live on one cell while face terms couple cells)
+    dirichlet_rule: str = "support"
 
     @property
     def n_elem(self):
@@ -358,6 +362,227 @@ def build_problem(name: str, dim: int, N: int, coeff: np.ndarray, P: int, delta:
                    elem_mat=np.ascontiguousarray(elem_mat), A=A, b=b, sub_elem_ptr=sep,
                    sub_elem=se, sub_dof_ptr=sdp, sub_dof=sd, sub_pou=sw, n_levels=n_levels,
                    parents=parents, eta=eta, coeff=coeff, box_shape=(P,) * dim)
+
+
+# ----------------------------------------------------------------------------
+# Cell-centred finite volumes and WSIP discontinuous Galerkin (2D, uniform grid)
+# ----------------------------------------------------------------------------
+#
+# Both are written as sums of "element" matrices in the sense of the solver's input: one per
+# cell (DG volume term) and one per face.  An interior face's matrix couples the dofs of its
+# two cells, a Dirichlet boundary face's matrix those of its one cell.  A subdomain's element
+# set is its cells' volume terms, the interior faces whose two cells both lie in it and the
+# Dirichlet faces of its cells: their sum is the local matrix with Neumann conditions on the
+# subdomain boundary inside the domain (the DG local form of Sec. 3.5, which for cell-centred
+# finite volumes with two-point fluxes is the same construction).
+
+
+def _cell_faces(N: int, bc: str):
+    """Interior faces (cell_minus, cell_plus, axis) and Dirichlet boundary faces
+    (cell, axis, side: -1 lower, +1 upper) of an N x N cell grid (cell id x + N y)."""
+    inter, bnd = [], []
+    for y in range(N):
+        for x in range(N):
+            c = x + N * y
+            if x + 1 < N:
+                inter.append((c, c + 1, 0))
+            if y + 1 < N:
+                inter.append((c, c + N, 1))
+    dir_axes = (0, 1) if bc == "all" else (0,) if bc == "x01" else ()
+    for ax in dir_axes:
+        for t in range(N):
+            lo = (0 + N * t) if ax == 0 else (t + 0)
+            hi = ((N - 1) + N * t) if ax == 0 else (t + N * (N - 1))
+            bnd.append((lo, ax, -1))
+            bnd.append((hi, ax, +1))
+    return inter, bnd
+
+
+def _skeleton_subdomains(N: int, P: int, delta: int, inter, bnd, vol: bool):
+    """Element sets of the overlapping cell boxes: element ids are [volume terms (cells) if
+    vol] + interior faces + boundary faces, in that order."""
+    cptr, cells = box_partition(2, N, P, delta)
+    nvol = N * N if vol else 0
+    fi = np.array([(a, b) for a, b, _ in inter], np.int64).reshape(-1, 2)
+    fb = np.array([c for c, _, _ in bnd], np.int64)
+    ptr, lists = [0], []
+    for i in range(len(cptr) - 1):
+        inside = np.zeros(N * N, bool)
+        inside[cells[cptr[i]:cptr[i + 1]]] = True
+        el = []
+        if vol:
+            el.append(np.nonzero(inside)[0])
+        el.append(nvol + np.nonzero(inside[fi[:, 0]] & inside[fi[:, 1]])[0])
+        el.append(nvol + len(fi) + np.nonzero(inside[fb])[0])
+        el = np.concatenate(el).astype(np.int32)
+        lists.append(el)
+        ptr.append(ptr[-1] + len(el))
+    return np.array(ptr, np.int64), np.concatenate(lists), cptr, cells
+
+
+def _cell_pou(N: int, cptr, cells, dofs_per_cell: int):
+    """Neumann dofs (all dofs of the box's cells) and the partition of unity: on a cell whose
+    neighbours all lie in the box, 1 / #boxes in which it is such an interior cell; 0 on the
+    box's boundary layer (cells with a neighbour outside the box inside the domain).  chi u
+    then has no jump across the faces that leave the subdomain, so that
+    abar(chi u, chi v) = a(chi u, chi v) as the DG right-hand side b^1 requires (Sec. 3.5)."""
+    P = len(cptr) - 1
+    interior = []
+    mult = np.zeros(N * N)
+    for i in range(P):
+        inside = np.zeros(N * N, bool)
+        c = np.sort(cells[cptr[i]:cptr[i + 1]])
+        inside[c] = True
+        x, y = c % N, c // N
+        ok = np.ones(len(c), bool)
+        for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+            xx, yy = x + dx, y + dy
+            valid = (xx >= 0) & (xx < N) & (yy >= 0) & (yy < N)
+            nb = np.where(valid, xx + N * yy, 0)
+            ok &= ~valid | inside[nb]
+        interior.append(ok)
+        mult[c[ok]] += 1
+    if np.any(mult == 0):
+        raise ValueError("some cell is interior to no subdomain (overlap too small)")
+    ptr, dofs, w = [0], [], []
+    for i in range(P):
+        c = np.sort(cells[cptr[i]:cptr[i + 1]])
+        d = (dofs_per_cell * c[:, None] + np.arange(dofs_per_cell)[None, :]).reshape(-1)
+        dofs.append(d.astype(np.int32))
+        w.append(np.repeat(np.where(interior[i], 1.0 / mult[c], 0.0), dofs_per_cell))
+        ptr.append(ptr[-1] + len(d))
+    return np.array(ptr, np.int64), np.concatenate(dofs), np.concatenate(w)
+
+
+def fv_problem(N: int, coeff: np.ndarray, P: int, delta: int, n_levels: int = 2,
+               groups: Sequence[int] = (), eta: float = 0.3, bc: str = "all",
+               name: str = "fv") -> Problem:
+    """Cell-centred finite volumes with two-point fluxes for -div(k grad u) = 1 on the unit
+    square, N x N cells (one dof per cell): interior face between cells a, b with
+    transmissibility t = 2 k_a k_b / (k_a + k_b) (face length h over centre distance h),
+    matrix t [[1, -1], [-1, 1]]; Dirichlet face of cell c (u = 0 on it, centre distance h/2)
+    t = 2 k_c on the cell's diagonal; right-hand side h^2 per cell.  Overlapping boxes of cells
+    (delta >= 1 cell layers), PoU as in _cell_pou."""
+    h = 1.0 / N
+    inter, bnd = _cell_faces(N, bc)
+    k = np.asarray(coeff, float)
+    ne = len(inter) + len(bnd)
+    ed = -np.ones((ne, 2), np.int32)
+    em = np.zeros((ne, 2, 2))
+    for f, (a, b, _) in enumerate(inter):
+        t = 2.0 * k[a] * k[b] / (k[a] + k[b])
+        ed[f] = (a, b)
+        em[f] = t * np.array([[1.0, -1.0], [-1.0, 1.0]])
+    for q, (c, _, _) in enumerate(bnd):
+        f = len(inter) + q
+        ed[f, 0] = c
+        em[f, 0, 0] = 2.0 * k[c]
+    n = N * N
+    A = assemble(n, ed, em)
+    b = np.full(n, h * h)
+    sep, se, cptr, cells = _skeleton_subdomains(N, P, delta, inter, bnd, vol=False)
+    sdp, sd, sw = _cell_pou(N, cptr, cells, 1)
+    parents, cur = [], P
+    for G in groups:
+        parents.append(group_parents(2, cur, G))
+        cur = G
+    assert len(parents) == n_levels - 2
+    return Problem(name=f"{name}_{N}", dim=2, ncomp=1, N=N, n=n, elem_dofs=ed, elem_mat=em,
+                   A=A, b=b, sub_elem_ptr=sep, sub_elem=se, sub_dof_ptr=sdp, sub_dof=sd,
+                   sub_pou=sw, n_levels=n_levels, parents=parents, eta=eta, coeff=k,
+                   box_shape=(P, P), dirichlet_rule="all")
+
+
+def _dg_face_matrix(h: float, km: float, kp: float, axis: int, alpha: float) -> np.ndarray:
+    """WSIP interior-face matrix (8 x 8 over the Q1 dofs of the cell below/left, then the
+    cell above/right; normal from the first to the second along `axis`):
+      sigma ([u],[v]) - ({k grad u}_w . n, [v]) - ({k grad v}_w . n, [u]),
+    [v] = v- - v+, {q}_w = w- q- + w+ q+ with w- = k+ / (k- + k+), w+ = k- / (k- + k+)
+    (weights of Ern, Stephansen and Zunino for scalar k), sigma = alpha k_h / h with the
+    harmonic mean k_h = 2 k- k+ / (k- + k+); two Gauss points on the face (exact here)."""
+    pts, wts = _gauss2()
+    sig = alpha * (2.0 * km * kp / (km + kp)) / h
+    wm, wp = kp / (km + kp), km / (km + kp)
+    M = np.zeros((8, 8))
+    for s, w in zip(pts, wts):
+        xm = np.zeros(2)
+        xp = np.zeros(2)
+        xm[axis], xp[axis] = 1.0, 0.0          # the face is the upper side of the first cell
+        xm[1 - axis] = xp[1 - axis] = s
+        vm, gm = q1_shape(2, xm)
+        vp, gp = q1_shape(2, xp)
+        jump = np.concatenate([vm, -vp])
+        flux = np.concatenate([wm * km * gm[:, axis] / h, wp * kp * gp[:, axis] / h])
+        M += w * h * (sig * np.outer(jump, jump) - np.outer(jump, flux) - np.outer(flux, jump))
+    return 0.5 * (M + M.T)
+
+
+def _dg_boundary_matrix(h: float, kc: float, axis: int, side: int, alpha: float) -> np.ndarray:
+    """WSIP Dirichlet-face matrix (4 x 4 over the cell's Q1 dofs, outward normal side e_axis):
+    sigma (u, v) - (k grad u . n, v) - (k grad v . n, u), sigma = alpha k / h."""
+    pts, wts = _gauss2()
+    sig = alpha * kc / h
+    M = np.zeros((4, 4))
+    for s, w in zip(pts, wts):
+        x = np.zeros(2)
+        x[axis] = 1.0 if side > 0 else 0.0
+        x[1 - axis] = s
+        v, g = q1_shape(2, x)
+        dn = side * kc * g[:, axis] / h
+        M += w * h * (sig * np.outer(v, v) - np.outer(v, dn) - np.outer(dn, v))
+    return 0.5 * (M + M.T)
+
+
+def dg_problem(N: int, coeff: np.ndarray, P: int, delta: int, n_levels: int = 2,
+               groups: Sequence[int] = (), eta: float = 0.3, bc: str = "all",
+               alpha: float = 8.0, name: str = "dg") -> Problem:
+    """WSIP discontinuous Galerkin with Q1 on N x N square cells (Sec. 3.5; four dofs per
+    cell, the nodal basis at the cell's corners, dof 4 c + a): volume terms k_c times the Q1
+    stiffness, interior-face and Dirichlet-face terms as in _dg_face_matrix and
+    _dg_boundary_matrix (penalty alpha = 8), load int f v with f = 1.  Elements: cells (4
+    dofs), interior faces (8), Dirichlet faces (4), padded to 8 with -1.  Overlapping boxes of
+    cells (delta >= 1), PoU as in _cell_pou."""
+    h = 1.0 / N
+    inter, bnd = _cell_faces(N, bc)
+    k = np.asarray(coeff, float)
+    nc = N * N
+    ne = nc + len(inter) + len(bnd)
+    ed = -np.ones((ne, 8), np.int32)
+    em = np.zeros((ne, 8, 8))
+    Kq = q1_laplace_element(2, h)
+    for c in range(nc):
+        ed[c, :4] = 4 * c + np.arange(4)
+        em[c, :4, :4] = k[c] * Kq
+    for f, (a, b, ax) in enumerate(inter):
+        e = nc + f
+        ed[e, :4] = 4 * a + np.arange(4)
+        ed[e, 4:] = 4 * b + np.arange(4)
+        em[e] = _dg_face_matrix(h, k[a], k[b], ax, alpha)
+    for q, (c, ax, side) in enumerate(bnd):
+        e = nc + len(inter) + q
+        ed[e, :4] = 4 * c + np.arange(4)
+        em[e, :4, :4] = _dg_boundary_matrix(h, k[c], ax, side, alpha)
+    n = 4 * nc
+    A = assemble(n, ed, em)
+    fe = q1_load_element(2, h)
+    b = np.tile(fe, nc)
+    sep, se, cptr, cells = _skeleton_subdomains(N, P, delta, inter, bnd, vol=True)
+    sdp, sd, sw = _cell_pou(N, cptr, cells, 4)
+    parents, cur = [], P
+    for G in groups:
+        parents.append(group_parents(2, cur, G))
+        cur = G
+    assert len(parents) == n_levels - 2
+    return Problem(name=f"{name}_{N}", dim=2, ncomp=1, N=N, n=n, elem_dofs=ed, elem_mat=em,
+                   A=A, b=b, sub_elem_ptr=sep, sub_elem=se, sub_dof_ptr=sdp, sub_dof=sd,
+                   sub_pou=sw, n_levels=n_levels, parents=parents, eta=eta, coeff=k,
+                   box_shape=(P, P), dirichlet_rule="all")
+
+
+def skeleton_field(N: int, seed: int, contrast: float = 1e4) -> np.ndarray:
+    """Per-cell coefficient for the finite-volume and DG test problems: the seeded inclusion
+    field (k = contrast on squares of 1-3 cells covering 10%, 1 elsewhere)."""
+    return inclusions_2d(N, seed, smin=1, smax=3, k_hi=contrast)
 
 
 # ----------------------------------------------------------------------------

@@ -76,6 +76,17 @@ def dirichlet_mask(elem_dofs: np.ndarray, elems: np.ndarray, dofs: np.ndarray) -
     return cnt[dofs] == deg[dofs]
 
 
+def dirichlet_set(prob, i: int, dofs: np.ndarray) -> np.ndarray:
+    """Mask of the Dirichlet subspace V_{h,L,i} among the Neumann dofs of subdomain i: for
+    conforming elements the dofs whose basis functions are supported in the subdomain
+    (dirichlet_mask); for DG and cell-centred finite volumes (Sec. 3.5) every dof, since each
+    basis function lives on one cell of the subdomain while the face terms that couple it to
+    a neighbour outside are not part of the subdomain's element set."""
+    if getattr(prob, "dirichlet_rule", "support") == "all":
+        return np.ones(len(dofs), bool)
+    return dirichlet_mask(prob.elem_dofs, prob.sub_elems(i), dofs)
+
+
 def neumann_matrix(elem_dofs: np.ndarray, elem_mat: np.ndarray, elems: np.ndarray,
                    dofs: np.ndarray) -> np.ndarray:
     """abar_i = sum_{tau in T_i} a_tau on the local Neumann space (Sec. 3.4), dense."""
@@ -326,7 +337,7 @@ class Oracle:
         dofs = p.sub_dofs(i)
         d = p.sub_weights(i)
         el = p.sub_elems(i)
-        dm = dirichlet_mask(p.elem_dofs, el, dofs)
+        dm = dirichlet_set(p, i, dofs)
         Ab = neumann_matrix(p.elem_dofs, p.elem_mat, el, dofs)
         Ao = None
         if self.geneo_rhs == 2:
@@ -359,7 +370,7 @@ class Oracle:
                     print(f"  fine sub {i}: nbar={len(p.sub_dofs(i))} m={res[i][0].m}", flush=True)
         for i in range(p.n_sub):
             dofs = p.sub_dofs(i)
-            dm = dirichlet_mask(p.elem_dofs, p.sub_elems(i), dofs)
+            dm = dirichlet_set(p, i, dofs)
             rows.append(dofs)
             dirr.append(dofs[dm])
             if i not in res:
@@ -508,7 +519,7 @@ class Oracle:
             y = sla.solve_triangular(Lc, r[idx], lower=True)
             ui = sla.solve_triangular(Lc.T, y, lower=False)
             dofs = p.sub_dofs(i)
-            dm = dirichlet_mask(p.elem_dofs, p.sub_elems(i), dofs)
+            dm = dirichlet_set(p, i, dofs)
             z[idx] += p.sub_weights(i)[dm] * ui          # restricted: chi_i on Dir_i
         for l in range(L - 1, -1, -1):
             t = self.P[l].T @ (r - self.A @ z)
