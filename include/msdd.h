@@ -96,6 +96,13 @@ typedef struct {
                          0 = normwise test only).  Needed at high coefficient contrast,
                          where ||S|| is set by the high-coefficient rows and the normwise
                          test alone leaves vectors off by up to 1e-7 */
+  int dirichlet_rule; /* Dirichlet subspace V_{h,L,i} of a finest subdomain among its Neumann
+                         dofs: 0 = the dofs all of whose elements lie in the subdomain
+                         (conforming elements; default); 1 = every Neumann dof (DG and
+                         cell-centred finite volumes, Sec. 3.5: there the input's "elements"
+                         are cells and faces, a basis function lives on one cell, and the
+                         subdomain's element set holds only the faces interior to it, so a
+                         face to a neighbour outside must not exclude the cell's dofs) */
 } msdd_options;
 
 typedef struct {

@@ -36,7 +36,7 @@ class MsddOptions(ctypes.Structure):
                 ("eig_tol", ctypes.c_double), ("eig_maxit", ctypes.c_int),
                 ("block", ctypes.c_int), ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("verbose", ctypes.c_int), ("geneo_rhs", ctypes.c_int), ("nev_fixed", ctypes.c_int),
-                ("eig_tol_energy", ctypes.c_double)]
+                ("eig_tol_energy", ctypes.c_double), ("dirichlet_rule", ctypes.c_int)]
 
 
 class MsddStats(ctypes.Structure):

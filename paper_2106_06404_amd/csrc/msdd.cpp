@@ -591,7 +591,8 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
         return;
       }
       const int64_t ninc = g.inc_ptr[r + 1] - g.inc_ptr[r];
-      const bool dir = ninc == deg[g.dofs[r]];  // every adjacent element lies in the subdomain
+      // every adjacent element lies in the subdomain, or (cells and faces) every dof
+      const bool dir = c->opt.dirichlet_rule == 1 || ninc == deg[g.dofs[r]];
       if (!dir && std::fabs(w) > 1e-14) {
         S.err = "partition of unity does not vanish on the boundary of subdomain " + std::to_string(i);
         return;
@@ -2015,6 +2016,7 @@ void msdd_default_options(msdd_options* o) {
   o->geneo_rhs = 1;
   o->nev_fixed = 0;
   o->eig_tol_energy = 1e-10;
+  o->dirichlet_rule = 0;
 }
 
 int msdd_create(msdd_ctx** out, const msdd_options* opt) {
@@ -2036,7 +2038,8 @@ int msdd_create(msdd_ctx** out, const msdd_options* opt) {
     return MSDD_EDEVICE;
   }
   if ((c->opt.precision != MSDD_FP64 && c->opt.precision != MSDD_MIXED) ||
-      c->opt.geneo_rhs < 1 || c->opt.geneo_rhs > 3 || c->opt.nev_fixed < 0) {
+      c->opt.geneo_rhs < 1 || c->opt.geneo_rhs > 3 || c->opt.nev_fixed < 0 ||
+      (c->opt.dirichlet_rule != 0 && c->opt.dirichlet_rule != 1)) {
     delete c;
     return MSDD_EINVAL;
   }
@@ -2072,6 +2075,8 @@ int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     REQUIRE(eta > 0 && std::isfinite(eta), "eta must be positive");
     REQUIRE(c->opt.eig_maxit > 0 && c->opt.eig_tol > 0 && c->opt.eig_tol_energy >= 0,
             "bad eigensolver options");
+    REQUIRE(c->opt.dirichlet_rule == 0 || c->opt.dirichlet_rule == 1,
+            "dirichlet_rule must be 0 or 1");
     c->n = n;
     c->k = k;
     c->eta = eta;

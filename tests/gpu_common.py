@@ -29,6 +29,8 @@ REL_FLOOR = 1e-10
 
 def gpu_setup(prob, device="cuda:0", **opts):
     import torch
+    if getattr(prob, "dirichlet_rule", "support") == "all":
+        opts.setdefault("dirichlet_rule", 1)
     arrs = B.problem_arrays(prob, device=device)
     torch.cuda.synchronize()
     m = B.Msdd(**opts)
