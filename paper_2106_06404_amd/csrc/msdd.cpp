@@ -1087,7 +1087,8 @@ void fine_eigensolve(msdd_ctx* c) {
         launch_rayleigh_ritz(s, P, K, GS.p, GB.p, Cm.p, E.nu.p, status.p, nsplit, gsd.p);
       }
       {
-        ProfScope ps(c, PR_EIG_UPDATE, f * 6.0 * F.s_nb * K * 8.0, f * 6.0 * F.s_nb * K * K);
+        // reads Y, Z, BX and the previous X, SX; writes X, BX, SX
+        ProfScope ps(c, PR_EIG_UPDATE, f * 8.0 * F.s_nb * K * 8.0, f * 6.0 * F.s_nb * K * K);
         launch_eig_update(s, P, F.gs.n.p, dkvoff.p, K, Cm.p, E.nu.p, Y.p, Z.p, E.X.p, BX.p, SX.p,
                           c->sigma, c->eta, o.nev_max, o.eig_tol, maxit, status.p, iters.p,
                           E.mcount.p, E.lam.p, E.res.p, 64, F.rankb.p, normS.p, nu_prev.p,
