@@ -232,6 +232,50 @@ def bench_islands(args):
                               "island field)", "cases": rows}))
 
 
+# Table 1 of the paper (Laplace, Q1, 16 subdomains, eta = 0.15, CG): #IT and n_0 per mesh
+# size for overlap ~ h and overlap ~ H
+TABLE1 = {320: {"h": (30, 56), "H": (30, 56)}, 640: {"h": (29, 114), "H": (32, 50)},
+          1280: {"h": (27, 236), "H": (25, 54)}, 2560: {"h": (26, 488), "H": (26, 54)}}
+
+
+def bench_table1(args):
+    """The Laplace column of Table 1: cases 'N:delta:kind' (kind h = overlap of a fixed number
+    of element layers, H = overlap a fixed fraction of the subdomain); one setup + CG each."""
+    import torch
+    from msdd_inputs import problems as P
+    from paper_2106_06404_amd import binding as B
+    rows = []
+    for c in args.table1.split(","):
+        N, delta, kind = c.split(":")
+        N, delta = int(N), int(delta)
+        prob = P.table1_laplace(N, delta)
+        print(f"table1 N={N} delta={delta} ({kind}): n={prob.n}", file=sys.stderr, flush=True)
+        arrs = B.problem_arrays(prob, device="cuda:0")
+        b = torch.from_numpy(prob.b).cuda()
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        m = B.Msdd()
+        t0 = time.perf_counter()
+        m.setup(**arrs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        it, rel, _ = m.solve(b, x, 1e-8, 2000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st = m.stats()
+        ref = TABLE1.get(N, {}).get(kind)
+        rows.append({"h_inv": N, "delta": delta, "overlap": kind, "dofs": prob.n,
+                     "cg_iters": it, "n0": st["n"][0], "setup_s": t1 - t0, "solve_s": t2 - t1,
+                     "eig_iters_max": st["eig_iters_max"], "max_band": st["max_band"],
+                     "paper": {"cg_iters": ref[0], "n0": ref[1]} if ref else None})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        m.close()
+        del arrs, b, x
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "Laplace two-level (Table 1 shape)", "data": "synthetic",
+                      "cases": rows}))
+
+
 def make_problem(name):
     from msdd_inputs import problems as P
     return {"c1": P.config1, "c2": P.config2}[name]()
@@ -361,7 +405,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4", "islands"])
+    ap.add_argument("--workload", default="c2",
+                    choices=sorted(WORKLOADS) + ["c4", "islands", "table1"])
+    ap.add_argument("--table1", default="320:2:h,640:2:h,320:5:H,640:10:H",
+                    help="Table 1 cases N:delta:kind (kind h or H), comma separated")
     ap.add_argument("--islands", default="8:2,16:2,16:3,32:3,32:4:2",
                     help="islands cases P:L[:factor], comma separated (--workload islands)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -385,6 +432,9 @@ def main():
         return
     if args.workload == "islands":
         bench_islands(args)
+        return
+    if args.workload == "table1":
+        bench_table1(args)
         return
     import torch
     from paper_2106_06404_amd import binding as B

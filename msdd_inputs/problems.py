@@ -711,6 +711,14 @@ def table3_islands(P: int, n_levels: int, seed: int = 3, elems_per_sub: int = 80
                          bc="x01")
 
 
+def table1_laplace(N: int, delta: int, P: int = 4, eta: float = 0.15) -> Problem:
+    """The Laplace column of Table 1 of the paper: Q1 on N x N elements, k = 1, P x P
+    subdomains (16), overlap delta element layers, two levels, eta = 0.15, Dirichlet on x = 0
+    and x = 1 and homogeneous Neumann elsewhere (the islands problem's boundary conditions)."""
+    return build_problem(f"t1_laplace_{N}_d{delta}", 2, N, np.ones(N * N), P=P, delta=delta,
+                         n_levels=2, eta=eta, bc="x01")
+
+
 def config3(E_fibre: float = 1e3, nu: float = 0.3) -> Problem:
     """48^3 trilinear elasticity, 16 plies 3 elements thick (fibre 0/90 deg alternating with
     resin), clamped at x=0, body force -z; 6^3 boxes, overlap 1, 3 levels (216 -> 27 -> 1)."""

@@ -521,6 +521,9 @@ struct SubPlan {
   std::string err;
 };
 
+// largest finest subdomain (Neumann dofs): its vector in double precision fills the LDS
+constexpr int kMaxLocalDofs = 20480;
+
 void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
                const std::vector<int64_t>& sep, const std::vector<int32_t>& se,
                const std::vector<int64_t>& sdp, const std::vector<int32_t>& sd,
@@ -701,6 +704,11 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
     F.s_dband += (double)S.nD * (S.bd + 1);
     F.s_ndbd += (double)S.nD * S.bd;
   }
+  // the local solves and the restriction hold one subdomain's vector in LDS
+  REQUIRE(F.nb_max <= kMaxLocalDofs,
+          "a finest subdomain has " + std::to_string(F.nb_max) + " dofs; the local solves hold "
+          "a subdomain's vector in LDS (160 KiB), at most " + std::to_string(kMaxLocalDofs) +
+          " dofs (use more subdomains)");
   for (int64_t d = 0; d < n; ++d) {
     REQUIRE(std::fabs(pou_sum[d] - 1.0) <= 1e-12,
             "partition-of-unity weights do not sum to 1 at dof " + std::to_string(d));

@@ -308,6 +308,16 @@ def test_large_coarsest_tiled(N, Pn):
     m.close()
 
 
+def test_subdomain_too_large_is_rejected():
+    """A finest subdomain above the 20480 dofs whose vector the local solves hold in LDS is
+    rejected at setup with MSDD_EINVAL (no kernel is launched)."""
+    from paper_2106_06404_amd import binding as B
+    prob = P.small_problem(N=160, P=1, delta=0, contrast=1.0, seed=1)   # 159^2 = 25281 dofs
+    with pytest.raises(B.MsddError) as e:
+        _setup(prob)
+    assert e.value.code == B.MSDD_EINVAL and "LDS" in str(e.value)
+
+
 def test_single_subdomain_empty_coarse_space():
     prob = P.small_problem(N=10, P=1, delta=0, contrast=1e3, seed=3)
     m, _ = _setup(prob)
