@@ -276,6 +276,64 @@ def bench_table1(args):
                       "cases": rows}))
 
 
+def bench_skeleton(args):
+    """Conforming Q1 (CG), cell-centred finite volumes (FV) and WSIP-DG-Q1 (DG) on one
+    log-normal field at about 1M dofs each (the discretisation comparison of the paper's
+    SPE10 runs, with a synthetic field): 16 x 16 subdomains, overlap 2, eta = 0.3, 2 or 3
+    levels (256 -> 16 -> 1); setup + CG, and GMRES with the hybrid form on the same setup.
+    Cases 'kind:levels', comma separated."""
+    import torch
+    from msdd_inputs import problems as P
+    from paper_2106_06404_amd import binding as B
+    N = 1024
+    field = np.exp(P.gaussian_field(2, N, 11, sigma2=args.skeleton_sigma2))
+    coarse = np.exp(np.log(field).reshape(N // 2, 2, N // 2, 2).mean(axis=(1, 3))).reshape(-1)
+    rows = []
+    for c in args.skeleton.split(","):
+        kind, L = c.split(":")
+        L = int(L)
+        groups = (4,) if L == 3 else ()
+        t0 = time.perf_counter()
+        if kind == "cg":
+            prob = P.build_problem("cg", 2, N, field, P=16, delta=2, n_levels=L, eta=0.3,
+                                   groups=groups)
+        elif kind == "fv":
+            prob = P.fv_problem(N, field, 16, 2, n_levels=L, groups=groups, eta=0.3)
+        else:
+            prob = P.dg_problem(N // 2, coarse, 16, 2, n_levels=L, groups=groups, eta=0.3)
+        tgen = time.perf_counter() - t0
+        print(f"skeleton {kind} L={L}: n={prob.n} (generated in {tgen:.0f} s)", file=sys.stderr,
+              flush=True)
+        opts = {"dirichlet_rule": 1} if prob.dirichlet_rule == "all" else {}
+        arrs = B.problem_arrays(prob, device="cuda:0")
+        b = torch.from_numpy(prob.b).cuda()
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        m = B.Msdd(**opts)
+        t0 = time.perf_counter()
+        m.setup(**arrs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        it, rel, _ = m.solve(b, x, 1e-8, 2000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        xg = torch.zeros_like(b)
+        itg, relg, _ = m.solve_gmres(b, xg, 1e-8, 300, 600, allow_noconv=True)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        st = m.stats()
+        rows.append({"discretisation": kind, "levels": L, "dofs": prob.n, "n0": st["n"][0],
+                     "level_sizes": st["n"], "cg_iters": it, "hybrid_gmres_iters": itg,
+                     "setup_s": t1 - t0, "cg_solve_s": t2 - t1, "gmres_solve_s": t3 - t2,
+                     "max_band": st["max_band"], "eig_iters_max": st["eig_iters_max"]})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        m.close()
+        del arrs, b, x, xg
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "CG / FV / DG on one log-normal field (SPE10-style comparison)",
+                      "data": "synthetic", "sigma2": args.skeleton_sigma2, "cases": rows}))
+
+
 def make_problem(name):
     from msdd_inputs import problems as P
     return {"c1": P.config1, "c2": P.config2}[name]()
@@ -406,7 +464,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2",
-                    choices=sorted(WORKLOADS) + ["c4", "islands", "table1"])
+                    choices=sorted(WORKLOADS) + ["c4", "islands", "table1", "skeleton"])
+    ap.add_argument("--skeleton", default="cg:2,fv:2,dg:2,cg:3,fv:3,dg:3",
+                    help="discretisation:levels cases (--workload skeleton)")
+    ap.add_argument("--skeleton-sigma2", type=float, default=4.0)
     ap.add_argument("--table1", default="320:2:h,640:2:h,320:5:H,640:10:H",
                     help="Table 1 cases N:delta:kind (kind h or H), comma separated")
     ap.add_argument("--islands", default="8:2,16:2,16:3,32:3,32:4:2",
@@ -435,6 +496,9 @@ def main():
         return
     if args.workload == "table1":
         bench_table1(args)
+        return
+    if args.workload == "skeleton":
+        bench_skeleton(args)
         return
     import torch
     from paper_2106_06404_amd import binding as B

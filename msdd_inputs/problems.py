@@ -466,17 +466,17 @@ def fv_problem(N: int, coeff: np.ndarray, P: int, delta: int, n_levels: int = 2,
     h = 1.0 / N
     inter, bnd = _cell_faces(N, bc)
     k = np.asarray(coeff, float)
-    ne = len(inter) + len(bnd)
+    fi = np.array([(a, b) for a, b, _ in inter], np.int64).reshape(-1, 2)
+    fb = np.array([c for c, _, _ in bnd], np.int64)
+    ne = len(fi) + len(fb)
     ed = -np.ones((ne, 2), np.int32)
     em = np.zeros((ne, 2, 2))
-    for f, (a, b, _) in enumerate(inter):
-        t = 2.0 * k[a] * k[b] / (k[a] + k[b])
-        ed[f] = (a, b)
-        em[f] = t * np.array([[1.0, -1.0], [-1.0, 1.0]])
-    for q, (c, _, _) in enumerate(bnd):
-        f = len(inter) + q
-        ed[f, 0] = c
-        em[f, 0, 0] = 2.0 * k[c]
+    ka, kb = k[fi[:, 0]], k[fi[:, 1]]
+    t = 2.0 * ka * kb / (ka + kb)
+    ed[:len(fi)] = fi
+    em[:len(fi)] = t[:, None, None] * np.array([[1.0, -1.0], [-1.0, 1.0]])[None]
+    ed[len(fi):, 0] = fb
+    em[len(fi):, 0, 0] = 2.0 * k[fb]
     n = N * N
     A = assemble(n, ed, em)
     b = np.full(n, h * h)
@@ -493,13 +493,16 @@ def fv_problem(N: int, coeff: np.ndarray, P: int, delta: int, n_levels: int = 2,
                    box_shape=(P, P), dirichlet_rule="all")
 
 
-def _dg_face_matrix(h: float, km: float, kp: float, axis: int, alpha: float) -> np.ndarray:
+def _dg_face_matrix(h: float, km: float, kp: float, axis: int, alpha: float,
+                    part: str = "all") -> np.ndarray:
     """WSIP interior-face matrix (8 x 8 over the Q1 dofs of the cell below/left, then the
     cell above/right; normal from the first to the second along `axis`):
       sigma ([u],[v]) - ({k grad u}_w . n, [v]) - ({k grad v}_w . n, [u]),
     [v] = v- - v+, {q}_w = w- q- + w+ q+ with w- = k+ / (k- + k+), w+ = k- / (k- + k+)
     (weights of Ern, Stephansen and Zunino for scalar k), sigma = alpha k_h / h with the
-    harmonic mean k_h = 2 k- k+ / (k- + k+); two Gauss points on the face (exact here)."""
+    harmonic mean k_h = 2 k- k+ / (k- + k+); two Gauss points on the face (exact here).
+    part: "all", or one of the parts the matrix is linear in: "jump" (the penalty term per
+    unit sigma), "minus" / "plus" (the consistency terms per unit w- k- / w+ k+)."""
     pts, wts = _gauss2()
     sig = alpha * (2.0 * km * kp / (km + kp)) / h
     wm, wp = kp / (km + kp), km / (km + kp)
@@ -512,8 +515,16 @@ def _dg_face_matrix(h: float, km: float, kp: float, axis: int, alpha: float) -> 
         vm, gm = q1_shape(2, xm)
         vp, gp = q1_shape(2, xp)
         jump = np.concatenate([vm, -vp])
-        flux = np.concatenate([wm * km * gm[:, axis] / h, wp * kp * gp[:, axis] / h])
-        M += w * h * (sig * np.outer(jump, jump) - np.outer(jump, flux) - np.outer(flux, jump))
+        zero = np.zeros(4)
+        if part == "all":
+            flux = np.concatenate([wm * km * gm[:, axis] / h, wp * kp * gp[:, axis] / h])
+            M += w * h * (sig * np.outer(jump, jump) - np.outer(jump, flux) - np.outer(flux, jump))
+        elif part == "jump":
+            M += w * h * np.outer(jump, jump)
+        else:
+            flux = (np.concatenate([gm[:, axis] / h, zero]) if part == "minus"
+                    else np.concatenate([zero, gp[:, axis] / h]))
+            M -= w * h * (np.outer(jump, flux) + np.outer(flux, jump))
     return 0.5 * (M + M.T)
 
 
@@ -553,11 +564,23 @@ def dg_problem(N: int, coeff: np.ndarray, P: int, delta: int, n_levels: int = 2,
     for c in range(nc):
         ed[c, :4] = 4 * c + np.arange(4)
         em[c, :4, :4] = k[c] * Kq
-    for f, (a, b, ax) in enumerate(inter):
-        e = nc + f
-        ed[e, :4] = 4 * a + np.arange(4)
-        ed[e, 4:] = 4 * b + np.arange(4)
-        em[e] = _dg_face_matrix(h, k[a], k[b], ax, alpha)
+    # the face matrices are linear in (sigma, w- k-, w+ k+) (interior) and (sigma, k)
+    # (Dirichlet): build the unit parts once per axis and side, then combine per face
+    fa = np.array([(a, b, ax) for a, b, ax in inter], np.int64).reshape(-1, 3)
+    for ax in (0, 1):
+        sel = np.nonzero(fa[:, 2] == ax)[0]
+        if not len(sel):
+            continue
+        J0 = _dg_face_matrix(h, 1.0, 1.0, ax, 0.0, part="jump")
+        Fm = _dg_face_matrix(h, 1.0, 1.0, ax, 0.0, part="minus")
+        Fp = _dg_face_matrix(h, 1.0, 1.0, ax, 0.0, part="plus")
+        km, kp = k[fa[sel, 0]], k[fa[sel, 1]]
+        sig = alpha * (2.0 * km * kp / (km + kp)) / h
+        cm, cp = kp / (km + kp) * km, km / (km + kp) * kp
+        e = nc + sel
+        ed[e, :4] = 4 * fa[sel, 0:1] + np.arange(4)[None]
+        ed[e, 4:] = 4 * fa[sel, 1:2] + np.arange(4)[None]
+        em[e] = sig[:, None, None] * J0 + cm[:, None, None] * Fm + cp[:, None, None] * Fp
     for q, (c, ax, side) in enumerate(bnd):
         e = nc + len(inter) + q
         ed[e, :4] = 4 * c + np.arange(4)
