@@ -503,12 +503,15 @@ template <typename T, typename V>
 __global__ void __launch_bounds__(64) k_band_solve_wave(
     const i32* __restrict__ subs, const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
     const i64* __restrict__ l_off, const T* __restrict__ Fr, const i64* __restrict__ v_off,
-    const V* __restrict__ Win, V* __restrict__ Yout, const int* __restrict__ active) {
+    const V* __restrict__ Win, V* __restrict__ Yout, const int* __restrict__ active, int K) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int i = subs ? subs[blockIdx.x] : blockIdx.x;
+  // columns run fastest over the grid, so the K waves of one subdomain run side by side
+  // and read its factor from L2 rather than each from HBM
+  const int c = (int)(blockIdx.x % (unsigned)K);
+  const int q = (int)(blockIdx.x / (unsigned)K);
+  const int i = subs ? subs[q] : q;
   if (active && active[i] != ST_RUNNING) return;
   const int n = n_arr[i];
-  const int c = blockIdx.y;
   V* v = reinterpret_cast<V*>(smem_raw);
   const V* Wc = Win + v_off[i] + (i64)c * n;
   V* Yc = Yout + v_off[i] + (i64)c * n;
@@ -739,8 +742,8 @@ void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_band_solve_wave<T, V>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_band_solve_wave<T, V>), dim3(nsubs, K), dim3(64), lds, s, subs, n_arr,
-                     b_arr, l_off, Fr, v_off, W, Y, active);
+  hipLaunchKernelGGL((k_band_solve_wave<T, V>), dim3((unsigned)((i64)K * nsubs)), dim3(64), lds, s,
+                     subs, n_arr, b_arr, l_off, Fr, v_off, W, Y, active, K);
 }
 template void launch_band_solve_multi<double, double>(hipStream_t, int, const i32*, int,
                                                       const i32*, const i32*, const i64*,

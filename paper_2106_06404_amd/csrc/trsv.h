@@ -29,6 +29,7 @@ __device__ inline float wave_bcast(float v, int lane) {
 // ---------------------------------------------------------------------------
 
 // Unstaged variant for any b (factor read from global memory).
+constexpr int WV_CH = 16;  // steps per prefetched chunk of the in-block chains
 template <typename T, typename V>
 __device__ __forceinline__ void wave_ldl_solve(int n, int b, const T* __restrict__ F, V* v) {
   const int lane = threadIdx.x & 63;
@@ -54,12 +55,36 @@ __device__ __forceinline__ void wave_ldl_solve(int n, int b, const T* __restrict
         a -= acc;
       }
     }
-    for (int k = 0; k < nb; ++k) {
-      const int dd = lane - k;
-      const bool ok = act && dd > 0 && dd <= b;
-      const V lv = ok ? (V)F[(i64)row * w + dd] : (V)0;
-      const V yk = wave_bcast(a, k);
-      a -= lv * yk;
+    // in-block chain: step k subtracts Lt(row, j0+k) y_k; lane l's entries are
+    // Lt(row, row-d), d = l-k, read into registers a 16-step chunk ahead of their use
+    // (unconditional loads, masked afterwards)
+    {
+      const int nch = (nb + WV_CH - 1) / WV_CH;
+      auto load = [&](int c, V* buf) {
+#pragma unroll
+        for (int t = 0; t < WV_CH; ++t) {
+          const int dd = lane - (WV_CH * c + t);
+          const bool ok = act && dd > 0 && dd <= b;
+          const V val = (V)F[ok ? (i64)row * w + dd : (i64)0];
+          buf[t] = ok ? val : (V)0;
+        }
+      };
+      auto run = [&](int c, const V* buf) {
+#pragma unroll
+        for (int t = 0; t < WV_CH; ++t) {
+          const V yk = wave_bcast(a, WV_CH * c + t);
+          a -= buf[t] * yk;
+        }
+      };
+      V l0[WV_CH], l1[WV_CH];
+      load(0, l0);
+      if (nch > 1) load(1, l1);
+      run(0, l0);
+      if (nch > 2) load(2, l0);
+      if (nch > 1) run(1, l1);
+      if (nch > 3) load(3, l1);
+      if (nch > 2) run(2, l0);
+      if (nch > 3) run(3, l1);
     }
     if (act) v[row] = a;
     __syncthreads();
@@ -86,12 +111,38 @@ __device__ __forceinline__ void wave_ldl_solve(int n, int b, const T* __restrict
         a -= acc;
       }
     }
-    for (int k = nb - 1; k >= 0; --k) {
-      const int dd = k - lane;
-      const bool ok = act && dd > 0 && dd <= b;
-      const V lv = ok ? (V)F[(i64)(j0 + k) * w + dd] : (V)0;
-      const V xk = wave_bcast(a, k);
-      a -= lv * xk;
+    // in-block chain, rows j0+k for k = nb-1 .. 0: step k subtracts Lt(j0+k, row) x_k,
+    // the entries read a chunk ahead as in the forward sweep (steps past the block's first
+    // row use k = 0 with a zero entry)
+    {
+      const int nch = (nb + WV_CH - 1) / WV_CH;
+      auto load = [&](int c, V* buf) {
+#pragma unroll
+        for (int t = 0; t < WV_CH; ++t) {
+          const int k = nb - 1 - (WV_CH * c + t);
+          const int dd = k - lane;
+          const bool ok = act && k >= 0 && dd > 0 && dd <= b;
+          const V val = (V)F[ok ? (i64)(j0 + k) * w + dd : (i64)0];
+          buf[t] = ok ? val : (V)0;
+        }
+      };
+      auto run = [&](int c, const V* buf) {
+#pragma unroll
+        for (int t = 0; t < WV_CH; ++t) {
+          const int k = max(nb - 1 - (WV_CH * c + t), 0);
+          const V xk = wave_bcast(a, k);
+          a -= buf[t] * xk;
+        }
+      };
+      V l0[WV_CH], l1[WV_CH];
+      load(0, l0);
+      if (nch > 1) load(1, l1);
+      run(0, l0);
+      if (nch > 2) load(2, l0);
+      if (nch > 1) run(1, l1);
+      if (nch > 3) load(3, l1);
+      if (nch > 2) run(2, l0);
+      if (nch > 3) run(3, l1);
     }
     if (act) v[row] = a;
     __syncthreads();
