@@ -156,8 +156,8 @@ int msdd_create(msdd_ctx** out, const msdd_options* opt);
  *      the finest-level element sets T_{h,L,i} (overlap included).
  *  sub_dof_ptr[n_sub+1] (int64), sub_dof[] (int32), sub_pou[] (double):
  *      for each subdomain the free dofs of its elements (the Neumann space
- *      V-bar_{L,i}, any order, at most 20480 per subdomain: the local solves hold a
- *      subdomain's vector in LDS) and the partition-of-unity weight chi of each;
+ *      V-bar_{L,i}, any order, at most 2^24 per subdomain) and the partition-of-unity
+ *      weight chi of each;
  *      chi must vanish off the subdomain's Dirichlet space (options.dirichlet_rule)
  *      and the weights must sum to 1 at every dof.
  *  n_levels (>= 2), parent[]: n_levels-2 concatenated maps; the first n_sub

@@ -512,13 +512,12 @@ __global__ void __launch_bounds__(64) k_band_solve_wave(
   const int i = subs ? subs[q] : q;
   if (active && active[i] != ST_RUNNING) return;
   const int n = n_arr[i];
-  V* v = reinterpret_cast<V*>(smem_raw);
+  V* ring = reinterpret_cast<V*>(smem_raw);
+  const int b = b_arr[i];
   const V* Wc = Win + v_off[i] + (i64)c * n;
   V* Yc = Yout + v_off[i] + (i64)c * n;
-  for (int q = threadIdx.x; q < n; q += 64) v[q] = Wc[q];
-  __syncthreads();
-  wave_ldl_solve<T, V>(n, b_arr[i], Fr + l_off[i], v);
-  for (int q = threadIdx.x; q < n; q += 64) Yc[q] = v[q];
+  wave_ldl_solve_ring<T, V, V>(n, b, Fr + l_off[i], Wc, Yc, nullptr, ring,
+                               wave_ring_size(b) - 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -738,7 +737,8 @@ void launch_band_solve_multi(hipStream_t s, int nsubs, const i32* subs, int nmax
     }
     return;
   }
-  const size_t lds = (size_t)nmax * sizeof(V);
+  (void)nmax;
+  const size_t lds = (size_t)wave_ring_size(bmax) * sizeof(V);
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_band_solve_wave<T, V>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

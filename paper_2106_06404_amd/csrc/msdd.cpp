@@ -521,8 +521,8 @@ struct SubPlan {
   std::string err;
 };
 
-// largest finest subdomain (Neumann dofs): its vector in double precision fills the LDS
-constexpr int kMaxLocalDofs = 20480;
+// largest finest subdomain (Neumann dofs)
+constexpr int kMaxLocalDofs = 1 << 24;
 
 void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
                const std::vector<int64_t>& sep, const std::vector<int32_t>& se,
@@ -704,11 +704,10 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
     F.s_dband += (double)S.nD * (S.bd + 1);
     F.s_ndbd += (double)S.nD * S.bd;
   }
-  // the local solves and the restriction hold one subdomain's vector in LDS
+  // local index arithmetic of the eigensolver blocks (n_i x K, K <= 64) stays in 32 bits
   REQUIRE(F.nb_max <= kMaxLocalDofs,
-          "a finest subdomain has " + std::to_string(F.nb_max) + " dofs; the local solves hold "
-          "a subdomain's vector in LDS (160 KiB), at most " + std::to_string(kMaxLocalDofs) +
-          " dofs (use more subdomains)");
+          "a finest subdomain has " + std::to_string(F.nb_max) + " dofs; at most " +
+          std::to_string(kMaxLocalDofs) + " are supported (use more subdomains)");
   for (int64_t d = 0; d < n; ++d) {
     REQUIRE(std::fabs(pou_sum[d] - 1.0) <= 1e-12,
             "partition-of-unity weights do not sum to 1 at dof " + std::to_string(d));

@@ -180,13 +180,15 @@ __global__ void __launch_bounds__(256) k_apply_fine_restrict(
     const i32* __restrict__ nd, const i64* __restrict__ doff, const i32* __restrict__ dglob,
     const i32* __restrict__ msub, const i64* __restrict__ moff, const i64* __restrict__ phid_off,
     const double* __restrict__ PhiD, const double* __restrict__ r, double* __restrict__ rc,
-    double* __restrict__ u) {
+    double* __restrict__ u, int in_lds) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16 * 8];
   const int i = blockIdx.x;
   const int n = nd[i];
   const int tid = threadIdx.x;
-  double* rl = reinterpret_cast<double*>(smem_raw);  // n
+  // the gathered residual in LDS, or (subdomains too large for it) read back from u after
+  // the barrier below
+  double* rl = in_lds ? reinterpret_cast<double*>(smem_raw) : u + doff[i];
   const i32* dg = dglob + doff[i];
   double* ui = u + doff[i];
   for (int q0 = tid; q0 < n; q0 += 4 * 256) {
@@ -200,7 +202,7 @@ __global__ void __launch_bounds__(256) k_apply_fine_restrict(
     for (int t = 0; t < 4; ++t) {
       const int q = q0 + t * 256;
       if (q < n) {
-        rl[q] = x[t];
+        if (in_lds) rl[q] = x[t];
         ui[q] = x[t];
       }
     }
@@ -267,13 +269,11 @@ __global__ void __launch_bounds__(64) k_apply_fine_wave(
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = blockIdx.x;
   const int n = nd[i];
-  T* rl = reinterpret_cast<T*>(smem_raw);
+  T* ring = reinterpret_cast<T*>(smem_raw);
   double* ui = u + doff[i];
   const double* si = scale ? scale + doff[i] : nullptr;
-  for (int q = threadIdx.x; q < n; q += 64) rl[q] = (T)(si ? ui[q] * si[q] : ui[q]);
-  __syncthreads();
-  wave_ldl_solve<T, T>(n, bd[i], Fr + dboff[i], rl);
-  for (int q = threadIdx.x; q < n; q += 64) ui[q] = si ? (double)rl[q] * si[q] : (double)rl[q];
+  wave_ldl_solve_ring<T, T, double>(n, bd[i], Fr + dboff[i], ui, ui, si, ring,
+                                    wave_ring_size(bd[i]) - 1);
 }
 
 // coarse level l: per subdomain, r_o = r_l[own]; rc = Y^T r_o; z_l[own] = A_oo^{-1} r_o
@@ -425,12 +425,13 @@ void launch_apply_fine_restrict(hipStream_t s, int P, int nd_max, const i32* nd,
                                 const i64* phid_off, const double* PhiD, const double* r,
                                 double* rc, double* u) {
   if (P == 0) return;
-  const size_t lds = (size_t)nd_max * sizeof(double);
+  const int in_lds = (size_t)nd_max * sizeof(double) <= 150 * 1024;
+  const size_t lds = in_lds ? (size_t)nd_max * sizeof(double) : 0;
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_apply_fine_restrict,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_apply_fine_restrict, dim3(P), dim3(256), lds, s, nd, doff, dglob, msub,
-                     moff, phid_off, PhiD, r, rc, u);
+                     moff, phid_off, PhiD, r, rc, u, in_lds);
 }
 size_t apply_fine_rot_lds(int nd_max, size_t elem) {
   return ((size_t)((nd_max + 3) & ~3) + 2 * (size_t)ROT_TILE) * elem;
@@ -457,7 +458,7 @@ void launch_apply_fine_solve(hipStream_t s, int P, int nd_max, int bd_max, const
                          dboff, (const double*)Fc, (const double*)Fr, scale, u, nd_max);
     }
   } else {
-    const size_t l2 = (size_t)nd_max * sizeof(double);
+    const size_t l2 = (size_t)wave_ring_size(bd_max) * sizeof(double);
     if (fp32) {
       if (l2 > 65536)
         (void)hipFuncSetAttribute((const void*)k_apply_fine_wave<float>,

@@ -19,8 +19,7 @@ __device__ inline float wave_bcast(float v, int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// Solves with an LDL^T band factor, right-hand side v in LDS (overwritten by the
-// solution).
+// Solves with an LDL^T band factor (one or many right-hand sides).
 //   F (row layout, ld w = b+1): F[j*w + d] = Lt(j, j-d) for 1 <= d <= b, where
 //   Lt is the unit lower triangular factor of A = Lt D Lt^T, and F[j*w] = 1/D_jj.
 // Forward sweep Lt y = v (unit diagonal: the diagonal-block chain is one
@@ -28,10 +27,25 @@ __device__ inline float wave_bcast(float v, int lane) {
 // touch of each row in the backward sweep Lt^T x = y.
 // ---------------------------------------------------------------------------
 
-// Unstaged variant for any b (factor read from global memory).
+// Unstaged variant for any b (factor read from global memory), one wavefront.  Forward:
+// for each 64-row block, lane l owns row j0 + l; it first subtracts the contributions of
+// the rows before the block (up to b back), then the block's own rows by a chain of
+// broadcasts, the factor entries of the chain read a 16-step chunk ahead into registers
+// (unconditional loads, masked afterwards).  Backward: the same on the reversed order with
+// the column entries Lt(j0 + k, row), 1/D folded into each row's first touch.
 constexpr int WV_CH = 16;  // steps per prefetched chunk of the in-block chains
-template <typename T, typename V>
-__device__ __forceinline__ void wave_ldl_solve(int n, int b, const T* __restrict__ F, V* v) {
+
+// The vector lives in global memory and only a ring of the last (forward) or next
+// (backward) M >= b + 64 values in LDS (M a power of two, rmask = M - 1), so that
+// LDS no longer bounds the subdomain size or the number of resident wavefronts.  vin is
+// read once (times scale, if given) by the forward sweep, which writes y = Lt^{-1} v to
+// vout; the backward sweep reads y back from vout (made visible by the barrier between
+// the sweeps) and overwrites it with x (times scale).  vin may equal vout.  One wavefront.
+template <typename T, typename V, typename G>
+__device__ __forceinline__ void wave_ldl_solve_ring(int n, int b, const T* __restrict__ F,
+                                                    const G* vin, G* vout,
+                                                    const double* __restrict__ scale, V* ring,
+                                                    int rmask) {
   const int lane = threadIdx.x & 63;
   const int w = b + 1;
   for (int j0 = 0; j0 < n; j0 += 64) {
@@ -41,7 +55,7 @@ __device__ __forceinline__ void wave_ldl_solve(int n, int b, const T* __restrict
     V a = 0;
     if (act) {
       const T* Fr = F + (i64)row * w;
-      a = v[row];
+      a = scale ? (V)((double)vin[row] * scale[row]) : (V)vin[row];
       for (int d0 = lane + 1; d0 <= b && row - d0 >= 0; d0 += 16) {
         V acc = 0;
 #pragma unroll
@@ -49,15 +63,12 @@ __device__ __forceinline__ void wave_ldl_solve(int n, int b, const T* __restrict
           const int dd = d0 + t;
           const bool ok = dd <= b && row - dd >= 0;
           const V lv = (V)Fr[ok ? dd : 0];
-          const V xv = v[ok ? row - dd : row];
+          const V xv = ring[(ok ? row - dd : row) & rmask];
           acc += ok ? lv * xv : (V)0;
         }
         a -= acc;
       }
     }
-    // in-block chain: step k subtracts Lt(row, j0+k) y_k; lane l's entries are
-    // Lt(row, row-d), d = l-k, read into registers a 16-step chunk ahead of their use
-    // (unconditional loads, masked afterwards)
     {
       const int nch = (nb + WV_CH - 1) / WV_CH;
       auto load = [&](int c, V* buf) {
@@ -86,7 +97,10 @@ __device__ __forceinline__ void wave_ldl_solve(int n, int b, const T* __restrict
       if (nch > 2) run(2, l0);
       if (nch > 3) run(3, l1);
     }
-    if (act) v[row] = a;
+    if (act) {
+      ring[row & rmask] = a;
+      vout[row] = (G)a;
+    }
     __syncthreads();
   }
   for (int j1 = n; j1 > 0; j1 -= 64) {
@@ -96,7 +110,7 @@ __device__ __forceinline__ void wave_ldl_solve(int n, int b, const T* __restrict
     const bool act = lane < nb;
     V a = 0;
     if (act) {
-      a = v[row] * (V)F[(i64)row * w];
+      a = (V)vout[row] * (V)F[(i64)row * w];
       const int imax = min(n - 1, row + b);
       for (int i0 = j1; i0 <= imax; i0 += 16) {
         V acc = 0;
@@ -106,14 +120,11 @@ __device__ __forceinline__ void wave_ldl_solve(int n, int b, const T* __restrict
           const bool ok = i <= imax;
           const int ic = ok ? i : row;
           const V lv = ok ? (V)F[(i64)ic * w + (ic - row)] : (V)0;
-          acc += lv * v[ic];
+          acc += lv * ring[ic & rmask];
         }
         a -= acc;
       }
     }
-    // in-block chain, rows j0+k for k = nb-1 .. 0: step k subtracts Lt(j0+k, row) x_k,
-    // the entries read a chunk ahead as in the forward sweep (steps past the block's first
-    // row use k = 0 with a zero entry)
     {
       const int nch = (nb + WV_CH - 1) / WV_CH;
       auto load = [&](int c, V* buf) {
@@ -144,9 +155,19 @@ __device__ __forceinline__ void wave_ldl_solve(int n, int b, const T* __restrict
       if (nch > 2) run(2, l0);
       if (nch > 3) run(3, l1);
     }
-    if (act) v[row] = a;
+    if (act) {
+      ring[row & rmask] = a;
+      vout[row] = scale ? (G)((double)a * scale[row]) : (G)a;
+    }
     __syncthreads();
   }
+}
+
+// ring size for wave_ldl_solve_ring: the power of two at or above b + 64
+__host__ __device__ inline int wave_ring_size(int b) {
+  int m = 64;
+  while (m < b + 64) m <<= 1;
+  return m;
 }
 
 // ---------------------------------------------------------------------------
