@@ -353,9 +353,131 @@ void launch_band_inertia(hipStream_t s, int nsubs, int bmax, const i32* n_arr, c
 }
 
 // ---------------------------------------------------------------------------
-// Same factorisation for half-bandwidths whose window does not fit in LDS:
-// S is first written to Lc (lower band) and factorised in place, right-looking,
-// with the trailing b x b triangle updated in global memory (L2 resident).
+// Same factorisation for half-bandwidths whose window does not fit in LDS: S is first
+// written to Lc (lower band, column layout) and factorised in place, right-looking, in
+// panels of CHB_P columns.  A panel (its columns' band entries, zero-padded) is factorised
+// in LDS; the trailing window it touches (columns j0+p .. j0+p+b-1, rows up to j0+p-1+b)
+// is then updated once by the rank-p product, each thread owning 4 x 4 tiles of the window
+// with the panel rows in registers, so the window is read and written once per panel
+// instead of once per column.
+// ---------------------------------------------------------------------------
+constexpr int CHB_P = 16;  // panel width
+
+template <typename T>
+__global__ void __launch_bounds__(MSDD_WG) k_band_cholesky_blocked(
+    const i32* __restrict__ subs, const i32* __restrict__ n_arr, const i32* __restrict__ b_arr,
+    const i64* __restrict__ src_off, const double* __restrict__ src,
+    const i64* __restrict__ dv_off, const double* __restrict__ dv, double sigma,
+    const i64* __restrict__ dst_off, T* __restrict__ Lc, T* __restrict__ Lr,
+    int* __restrict__ status, const double* __restrict__ src2, int pw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Pn = reinterpret_cast<T*>(smem_raw);  // CHB_P x pw: column c of the panel, offsets d
+  __shared__ int bad;
+  const int i = subs ? subs[blockIdx.x] : blockIdx.x;
+  const int n = n_arr[i];
+  const int b = b_arr[i];
+  const int w = b + 1;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double* A = src + src_off[i];
+  const double* d = dv ? dv + dv_off[i] : nullptr;
+  T* Li = Lc + dst_off[i];
+  T* Ri = Lr + dst_off[i];
+  for (i64 t = tid; t < (i64)n * w; t += nt) {
+    const int c = (int)(t / w), dd = (int)(t % w);
+    double a = 0.0;
+    if (c + dd < n) {
+      a = A[t];
+      if (d) a = src2 ? a + sigma * d[c + dd] * d[c] * src2[src_off[i] + t] : a * (1.0 + sigma * d[c + dd] * d[c]);
+    }
+    Li[t] = (T)a;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  const int tb = (b + 3) / 4;  // 4 x 4 tiles per window side
+  for (int j0 = 0; j0 < n; j0 += CHB_P) {
+    const int pc = min(CHB_P, n - j0);
+    // panel: Pn[c * pw + dd] = entry (j0 + c + dd, j0 + c), zero outside the band/matrix
+    for (int t = tid; t < CHB_P * pw; t += nt) {
+      const int c = t / pw, dd = t % pw;
+      Pn[t] = (c < pc && dd < w && j0 + c + dd < n) ? Li[(i64)(j0 + c) * w + dd] : (T)0;
+    }
+    __syncthreads();
+    for (int c = 0; c < pc; ++c) {
+      const T ajj = Pn[c * pw];
+      if (!(ajj > (T)0)) {
+        if (tid == 0) bad = 1;
+        break;
+      }
+      const T ljj = sqrt(ajj);
+      __syncthreads();
+      for (int dd = tid; dd < w; dd += nt) Pn[c * pw + dd] = dd == 0 ? ljj : Pn[c * pw + dd] / ljj;
+      __syncthreads();
+      // columns c2 > c of the panel: entry (j0+c2+d2, j0+c2) -= L(j0+c2+d2, j0+c) L(j0+c2, j0+c)
+      for (int t = tid; t < (pc - 1 - c) * w; t += nt) {
+        const int c2 = c + 1 + t / w, d2 = t % w;
+        const int o = c2 - c + d2;  // offset of row j0+c2+d2 in column j0+c
+        if (o <= b) Pn[c2 * pw + d2] -= Pn[c * pw + o] * Pn[c * pw + (c2 - c)];
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (bad) {
+      if (tid == 0) status[i] = ST_NOTSPD;
+      return;
+    }
+    for (int t = tid; t < pc * w; t += nt) {
+      const int c = t / w, dd = t % w;
+      if (j0 + c + dd < n) Li[(i64)(j0 + c) * w + dd] = Pn[c * pw + dd];
+    }
+    // trailing window: column k = kb + kk, row r = kb + rr, 0 <= kk <= rr < b, where
+    // kb = j0 + pc; L(x, j0+c) = Pn[c * pw + (x - j0 - c)] (zero beyond the band)
+    const int kb = j0 + pc;
+    if (kb < n) {
+      // row tiles run fastest over the threads, so the rows a wavefront writes in one
+      // column are contiguous
+      for (int t = tid; t < tb * tb; t += nt) {
+        const int tk = t / tb, tr = t % tb;
+        if (tk > tr) continue;
+        const int rr0 = 4 * tr, kk0 = 4 * tk;
+        T acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[a][e] = (T)0;
+        for (int c = 0; c < pc; ++c) {
+          const T* col = Pn + c * pw + (pc - c);
+          T lr[4], lk[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            lr[q] = col[rr0 + q];
+            lk[q] = col[kk0 + q];
+          }
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[a][e] += lr[a] * lk[e];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int rr = rr0 + a, kk = kk0 + e;
+            const int r = kb + rr, k = kb + kk;
+            if (kk <= rr && rr < b && r < n) Li[(i64)k * w + (rr - kk)] -= acc[a][e];
+          }
+      }
+    }
+    __syncthreads();
+  }
+  for (i64 t = tid; t < (i64)n * w; t += nt) {
+    const int c = (int)(t / w), dd = (int)(t % w);
+    if (c + dd < n) Ri[(i64)(c + dd) * w + dd] = Li[t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column-by-column variant for half-bandwidths whose panel does not fit in LDS either
+// (b above about 1250): the trailing b x b triangle updated in global memory each column.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_band_cholesky_global(const i32* __restrict__ subs, const i32* __restrict__ n_arr,
@@ -561,8 +683,20 @@ void launch_band_cholesky(hipStream_t s, int nsubs, const i32* subs, int bmax, c
     hipLaunchKernelGGL(k_band_cholesky<T>, dim3(nsubs), dim3(MSDD_WG), lds, s, subs, n_arr,
                        b_arr, src_off, src, dv_off, dv, sigma, dst_off, Lc, Lr, status, src2);
   } else {
-    hipLaunchKernelGGL(k_band_cholesky_global<T>, dim3(nsubs), dim3(MSDD_WG), 0, s, subs, n_arr,
-                       b_arr, src_off, src, dv_off, dv, sigma, dst_off, Lc, Lr, status, src2);
+    // panel rows padded so that the window's 4 x 4 tiles read zeros past the band
+    const int pw = (int)w + CHB_P + 4;
+    const size_t plds = (size_t)CHB_P * pw * sizeof(T);
+    if (plds > 150 * 1024) {
+      hipLaunchKernelGGL(k_band_cholesky_global<T>, dim3(nsubs), dim3(MSDD_WG), 0, s, subs, n_arr,
+                         b_arr, src_off, src, dv_off, dv, sigma, dst_off, Lc, Lr, status, src2);
+      return;
+    }
+    if (plds > 65536)
+      (void)hipFuncSetAttribute((const void*)k_band_cholesky_blocked<T>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds);
+    hipLaunchKernelGGL(k_band_cholesky_blocked<T>, dim3(nsubs), dim3(MSDD_WG), plds, s, subs,
+                       n_arr, b_arr, src_off, src, dv_off, dv, sigma, dst_off, Lc, Lr, status,
+                       src2, pw);
   }
 }
 template void launch_band_cholesky<double>(hipStream_t, int, const i32*, int, const i32*,
