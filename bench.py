@@ -31,6 +31,9 @@ WORKLOADS = {
            "16x16 subdomains overlap 2, 3 levels (256->16->1), eta=0.1, FP64, PCG to 1e-8"),
     "c1": ("2D scalar diffusion, Q1 64x64, 4 channels k=1e6, 4x4 subdomains overlap 2, 2 levels, "
            "eta=0.1, FP64, PCG to 1e-8"),
+    "c3": ("3D linear elasticity, trilinear Q1 48^3 (3 dofs/node), 16 plies 3 elements thick "
+           "(fibre E=1e3 0/90 deg, resin E=1, nu=0.3), clamped x=0, body force -z, 6x6x6 "
+           "subdomains overlap 1, 3 levels (216->27->1), eta=0.1, PCG to 1e-8"),
     "c5": ("3D scalar diffusion, Q1 96^3, seeded bars (k=1e6) over a log-normal field "
            "(sigma^2=4), 8x8x8 subdomains overlap 1, 3 levels (512->64->1), eta=0.1, PCG to 1e-8"),
 }
@@ -338,7 +341,7 @@ def bench_skeleton(args):
 
 def make_problem(name):
     from msdd_inputs import problems as P
-    return {"c1": P.config1, "c2": P.config2, "c5": P.config5}[name]()
+    return {"c1": P.config1, "c2": P.config2, "c3": P.config3, "c5": P.config5}[name]()
 
 
 def host_cores():

@@ -326,7 +326,7 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
                               double* __restrict__ lam_out, const i64* __restrict__ lamoff,
                               int* __restrict__ m_out, int* __restrict__ status,
                               int* __restrict__ rank_out, int* __restrict__ sweeps_out,
-                              int ng_max, int in_lds) {
+                              int ng_max, int in_lds, int vec_in_lds) {
   const int t = blockIdx.x;
   const int ng = ng_arr[t], no = no_arr[t];
   const double* A = Abar + aoff[t];
@@ -341,10 +341,13 @@ __global__ void k_coarse_gevp(const i32* __restrict__ ng_arr, const i32* __restr
   __shared__ int sh_fail, sh_r, sh_m, sh_bad;
   __shared__ double sh_smax, red[64];
   // dynamic LDS: eigenvalues d (ng_max), workspace (syev_dc_ws), then (in_lds) the matrix
-  // being diagonalised, later the tridiagonal problem's eigenvectors
+  // being diagonalised, later the tridiagonal problem's eigenvectors.  Generating systems
+  // too large for that (vec_in_lds = 0) keep d and the workspace in the target's scratch,
+  // after its matrices (the kernels address them through generic pointers, and their
+  // barriers order the global accesses within the workgroup).
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* d = reinterpret_cast<double*>(smem_raw);
-  double* wsp = d + ng_max;
+  double* d = vec_in_lds ? reinterpret_cast<double*>(smem_raw) : S + 5 * g2 + ng + 2;
+  double* wsp = d + (vec_in_lds ? ng_max : ng);
   double* Alds = wsp + syev_dc_ws(ng_max);
   const int tid = threadIdx.x, nt = blockDim.x;
   if (no == 0) {
@@ -665,6 +668,8 @@ void launch_dense_cholesky(hipStream_t s, int nt, int nmax, const i64* off, cons
     hipLaunchKernelGGL(k_dense_cholesky, dim3(nt), dim3(1024), 0, s, off, n_arr, A, status);
   }
 }
+int64_t coarse_gevp_vec_doubles(int ng) { return (int64_t)ng + syev_dc_ws(ng); }
+
 void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_arr,
                         const i64* aoff, double* Abar, const i64* loff, double* Lo,
                         const i64* soff, double* scratch, double eta, int nev_max,
@@ -677,13 +682,14 @@ void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_
   size_t stat = 4096;
   if (hipFuncGetAttributes(&fa, (const void*)k_coarse_gevp) == hipSuccess) stat = fa.sharedSizeBytes;
   const int in_lds = full + stat <= 160 * 1024;  // LDS per workgroup, with the static part
-  const size_t lds = in_lds ? full : vecs;
+  const int vec_in_lds = vecs + stat <= 160 * 1024;
+  const size_t lds = in_lds ? full : vec_in_lds ? vecs : 0;
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_coarse_gevp,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_coarse_gevp, dim3(nt), dim3(1024), lds, s, ng_arr, no_arr, aoff, Abar,
                      loff, Lo, soff, scratch, eta, nev_max, eps_reg, lam_out, lamoff, m_out,
-                     status, rank_out, sweeps_out, ng_max, in_lds);
+                     status, rank_out, sweeps_out, ng_max, in_lds, vec_in_lds);
 }
 void launch_dense_to_layouts(hipStream_t s, int nt, const i64* off, const i32* n_arr,
                              const double* L, double* R, double* C) {

@@ -123,6 +123,9 @@ void launch_coarse_assemble(hipStream_t s, int nt, const i64* tp_ptr, const i32*
                             const i64* aoff, double* Aout);
 void launch_dense_cholesky(hipStream_t s, int nt, int nmax, const i64* off, const i32* n_arr,
                            double* A, int* status);
+// doubles of eigenvalues and eigensolver workspace of one coarse GEVP target of size ng
+// (kept in its scratch when they do not fit in LDS)
+int64_t coarse_gevp_vec_doubles(int ng);
 void launch_coarse_gevp(hipStream_t s, int nt, const i32* ng_arr, const i32* no_arr,
                         const i64* aoff, double* Abar, const i64* loff, double* Lo,
                         const i64* soff, double* scratch, double eta, int nev_max,

@@ -1496,7 +1496,7 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
   J.ng = CL.ng;
   int ng_max = 0;
   for (int v : CL.ng) ng_max = std::max(ng_max, v);
-  REQUIRE(ng_max <= 1024, "coarse generating system with more than 1024 functions");
+  REQUIRE(ng_max <= 4096, "coarse generating system with more than 4096 functions");
   vlog(c, "coarse: generating-system plan", &tv);
   DVec<double> Abar;
   run_assemble(c, J, PL, Abar);
@@ -1506,7 +1506,9 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
   CL.h_loff.assign(Pc + 1, 0);
   for (int i = 0; i < Pc; ++i) {
     const int64_t ng = CL.ng[i], no = CL.no[i], ngh = ng - no;
-    soff[i + 1] = soff[i] + 5 * ng * ng + ng + 2;
+    // S, Q, Qk, C, Yc (ng^2 each), ints, then d and the eigensolver workspace for
+    // generating systems whose workspace does not fit in LDS
+    soff[i + 1] = soff[i] + 5 * ng * ng + ng + 2 + coarse_gevp_vec_doubles((int)ng);
     (void)ngh;
     CL.h_loff[i + 1] = CL.h_loff[i] + no * no;
     lamoff[i + 1] = lamoff[i] + no;
