@@ -676,17 +676,13 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   std::vector<int32_t>& dcount = c->scr_cnt;
   pou_sum.assign(n, 0.0);
   dcount.assign(n, 0);
+  // offsets of each subdomain's entries, sizes and maxima (serial, per subdomain)
+  std::vector<int64_t> nbo(P + 1, 0), ndo(P + 1, 0);
   for (int i = 0; i < P; ++i) {
     const GroupPlan& g = F.plans[i];
     const SubPlan& S = sp[i];
-    F.h_dv.insert(F.h_dv.end(), S.dv.begin(), S.dv.end());
-    if (rhs == 3) F.h_dg.insert(F.h_dg.end(), S.dg.begin(), S.dg.end());
-    F.h_wpos.insert(F.h_wpos.end(), S.wpos.begin(), S.wpos.end());
-    for (size_t r = 0; r < g.dofs.size(); ++r) pou_sum[g.dofs[r]] += S.dv[r];
-    for (int32_t d : S.dglob) dcount[d]++;
-    F.h_dpos.insert(F.h_dpos.end(), S.dpos.begin(), S.dpos.end());
-    for (int32_t q : S.dpos) F.h_dw.push_back(S.dv[q]);
-    F.h_dglob.insert(F.h_dglob.end(), S.dglob.begin(), S.dglob.end());
+    nbo[i + 1] = nbo[i] + (int64_t)g.dofs.size();
+    ndo[i + 1] = ndo[i] + S.nD;
     F.h_nd[i] = S.nD;
     F.h_bd[i] = S.bd;
     F.h_rankb[i] = S.rankb;
@@ -708,11 +704,43 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   REQUIRE(F.nb_max <= kMaxLocalDofs,
           "a finest subdomain has " + std::to_string(F.nb_max) + " dofs; at most " +
           std::to_string(kMaxLocalDofs) + " are supported (use more subdomains)");
-  for (int64_t d = 0; d < n; ++d) {
-    REQUIRE(std::fabs(pou_sum[d] - 1.0) <= 1e-12,
-            "partition-of-unity weights do not sum to 1 at dof " + std::to_string(d));
-    REQUIRE(dcount[d] > 0, "dof " + std::to_string(d) + " lies in no subdomain's Dirichlet space");
-  }
+  F.h_dv.resize(nbo[P]);
+  F.h_wpos.resize(nbo[P]);
+  if (rhs == 3) F.h_dg.resize(nbo[P]);
+  F.h_dpos.resize(ndo[P]);
+  F.h_dw.resize(ndo[P]);
+  F.h_dglob.resize(ndo[P]);
+  parallel_for(P, nthr, [&](int i, int) {
+    const SubPlan& S = sp[i];
+    std::copy(S.dv.begin(), S.dv.end(), F.h_dv.begin() + nbo[i]);
+    std::copy(S.wpos.begin(), S.wpos.end(), F.h_wpos.begin() + nbo[i]);
+    if (rhs == 3) std::copy(S.dg.begin(), S.dg.end(), F.h_dg.begin() + nbo[i]);
+    std::copy(S.dpos.begin(), S.dpos.end(), F.h_dpos.begin() + ndo[i]);
+    std::copy(S.dglob.begin(), S.dglob.end(), F.h_dglob.begin() + ndo[i]);
+    for (int q = 0; q < S.nD; ++q) F.h_dw[ndo[i] + q] = S.dv[S.dpos[q]];
+  });
+  // PoU sums and Dirichlet multiplicities, each thread over a range of dofs and all
+  // subdomains in order (each subdomain's dofs are sorted), so every sum runs in subdomain
+  // order as a serial loop would
+  const int nrange = std::max(1, (int)std::min<int64_t>(nthr, (n + 65535) / 65536));
+  auto range_lo = [&](int t) { return (int32_t)((n * (int64_t)t) / nrange); };
+  parallel_for(nrange, nrange, [&](int t, int) {
+    const int32_t lo = range_lo(t), hi = range_lo(t + 1);
+    for (int i = 0; i < P; ++i) {
+      const GroupPlan& g = F.plans[i];
+      const SubPlan& S = sp[i];
+      auto b0 = std::lower_bound(g.dofs.begin(), g.dofs.end(), lo);
+      for (auto it = b0; it != g.dofs.end() && *it < hi; ++it)
+        pou_sum[*it] += S.dv[it - g.dofs.begin()];
+      auto d0 = std::lower_bound(S.dglob.begin(), S.dglob.end(), lo);
+      for (auto it = d0; it != S.dglob.end() && *it < hi; ++it) dcount[*it]++;
+    }
+    for (int32_t d = lo; d < hi; ++d) {
+      REQUIRE(std::fabs(pou_sum[d] - 1.0) <= 1e-12,
+              "partition-of-unity weights do not sum to 1 at dof " + std::to_string(d));
+      REQUIRE(dcount[d] > 0, "dof " + std::to_string(d) + " lies in no subdomain's Dirichlet space");
+    }
+  });
   // fine dof -> (subdomain, Dirichlet position), in subdomain order
   // (upload-only arrays in the pinned staging arena; every entry is written)
   HostBuf<int64_t> dptr(n + 1);
@@ -722,13 +750,19 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   {
     std::vector<int64_t>& pos = c->scr_pos;
     pos.assign(dptr.p, dptr.p + n);
-    for (int i = 0; i < P; ++i)
-      for (int q = 0; q < sp[i].nD; ++q) {
-        const int32_t d = sp[i].dglob[q];
-        dsub[pos[d]] = i;
-        dq[pos[d]] = q;
-        pos[d]++;
+    parallel_for(nrange, nrange, [&](int t, int) {
+      const int32_t lo = range_lo(t), hi = range_lo(t + 1);
+      for (int i = 0; i < P; ++i) {
+        const SubPlan& S = sp[i];
+        auto d0 = std::lower_bound(S.dglob.begin(), S.dglob.end(), lo);
+        for (auto it = d0; it != S.dglob.end() && *it < hi; ++it) {
+          const int32_t d = *it;
+          dsub[pos[d]] = i;
+          dq[pos[d]] = (int32_t)(it - S.dglob.begin());
+          pos[d]++;
+        }
       }
+    });
   }
   vlog(c, "plan: merge + PoU check", &tv);
   hipStream_t s = c->stream;
