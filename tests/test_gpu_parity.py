@@ -197,14 +197,20 @@ def test_c2_full_against_golden():
         same pencil (compression and the Schur complement with a pseudo-inverse) agree only
         to 2e-6 at contrast 1e4 (the oracle's coarse-pencil pin), so that is the accuracy to
         which these eigenvalues are defined in FP64;
-      * PCG: the iterates after 5 and 20 iterations and the final solution within 1e-8.
-        The attainable accuracy of the residual of this contrast-1e6 system is
+      * PCG: the iterate after 20 iterations and the final solution within 1e-8, the one
+        after 5 within 5e-8.  The first iterations mostly resolve the coarse components, and
+        the level-1 coarse spaces are defined only to the accuracy stated above (rank
+        deficient generating systems), so the two preconditioners' coarse corrections
+        differ at the 1e-8 level, which the early iterate carries with a factor of a few
+        (measured: 1.8e-8 after 5 iterations, 3.3e-9 after 20, 9.4e-10 after 60 and at the
+        end).  The attainable accuracy of the residual of this contrast-1e6 system is
         eps ||A|| ||x|| / ||b|| = 3e-6 (the true residual of both runs at exit); crossings
         of thresholds at least 100 times above it (1e-2, 1e-3, 1e-4) agree within +-1.  Below
         the floor the recurrence residual is driven by rounding and contracts by about 0.77
-        per iteration near 1e-8 (oracle history), so a factor 10^0.5 between the histories
-        (the history bound below) moves the crossing of 1e-8 by up to
-        log(10^0.5) / log(1/0.77) = 4.4 iterations: the final count is compared within +-4."""
+        per iteration near 1e-8 (oracle history), so a factor 10^0.3 between the histories
+        (the history bound below; measured 10^0.23) moves the crossing of 1e-8 by up to
+        log(10^0.3) / log(1/0.77) = 2.6 iterations: the final count is compared within +-3
+        (measured: equal, 120)."""
     if not os.path.exists(os.path.join(HERE, "golden", "c2_oracle.npz")):
         pytest.skip("c2 golden (refined references, solution) not generated yet")
     g, arr = _golden("c2")
@@ -221,16 +227,16 @@ def test_c2_full_against_golden():
         assert np.all(np.abs(lg - lo) <= 1e-6 * np.maximum(np.abs(lo), prob.eta)), (i, lg, lo)
     for k in g["iterates"]:
         if k <= 20:
-            assert _rel(_iterate(m, prob, k), arr[f"x_it{k}"]) < 1e-8, k
+            assert _rel(_iterate(m, prob, k), arr[f"x_it{k}"]) < (5e-8 if k < 20 else 1e-8), k
     it, rel, x = _solve(m, prob)
     h = m.history()
     ho = np.array(g["pcg"]["resnorms"])
     ho = ho / ho[0]
     for tau in (1e-2, 1e-3, 1e-4):
         assert abs(_first_below(h, tau) - _first_below(ho, tau)) <= 1, tau
-    assert abs(it - g["pcg"]["iters"]) <= 4
+    assert abs(it - g["pcg"]["iters"]) <= 3
     k = min(len(h), len(ho))
-    assert np.max(np.abs(np.log10(h[:k] / ho[:k]))) <= 0.5
+    assert np.max(np.abs(np.log10(h[:k] / ho[:k]))) <= 0.3
     assert _rel(x, arr["x"]) < 1e-8
     assert np.linalg.norm(prob.b - prob.A @ x) / np.linalg.norm(prob.b) < 1e-5
     m.close()
