@@ -448,14 +448,22 @@ typedef struct {
                              block-to-block chain (by shape when available) */
   int32_t eig_splits;     /* row splits per subdomain of the Gram / update kernels:
                              0 = by size, else 1..16 */
-  int32_t fine_solve;     /* 0 = by shape; 1 = rolling window; 2 = one wavefront per subdomain */
+  int32_t fine_solve;     /* 0 = by shape (1 for half-bandwidths below 64, else 2);
+                             1 = rolling window; 2 = one wavefront per subdomain;
+                             3 = two-sided: the rows before and after a separator of b rows
+                             solved as two chains side by side, the separator through the
+                             explicit inverse of its Schur complement.  Its factors are
+                             built by a setup made with this choice set (every subdomain
+                             must have a half-bandwidth below 64 and at least b + 65 rows,
+                             and the workgroup's data must fit in LDS); otherwise the
+                             by-shape choice runs */
   int32_t spmv_group;     /* lanes per CSR row: 0 = by average row length, else 4, 8, 16, 32 */
   float eig_solve_ms[10]; /* [v] for eig_solve = v (v = 1..9; 0 = not run or not
                              applicable): time per eigensolver iteration, from launches
                              with all subdomains active and with the longest-iterating
                              one alone, weighed by the last setup's iteration counts */
   float eig_splits_ms[5]; /* for 1, 2, 4, 8, 16 splits */
-  float fine_solve_ms[3]; /* [v] for fine_solve = v (v = 1, 2) */
+  float fine_solve_ms[4]; /* [v] for fine_solve = v (v = 1, 2, 3; 0 = not applicable) */
   float spmv_ms[4];       /* for 4, 8, 16, 32 lanes */
 } msdd_tuning_t;
 

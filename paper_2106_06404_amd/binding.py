@@ -69,7 +69,7 @@ class MsddTuning(ctypes.Structure):
     _fields_ = [("eig_solve", ctypes.c_int32), ("eig_splits", ctypes.c_int32),
                 ("fine_solve", ctypes.c_int32), ("spmv_group", ctypes.c_int32),
                 ("eig_solve_ms", ctypes.c_float * 10), ("eig_splits_ms", ctypes.c_float * 5),
-                ("fine_solve_ms", ctypes.c_float * 3), ("spmv_ms", ctypes.c_float * 4)]
+                ("fine_solve_ms", ctypes.c_float * 4), ("spmv_ms", ctypes.c_float * 4)]
 
     def as_dict(self):
         return {f: (list(getattr(self, f)) if f.endswith("_ms") else getattr(self, f))

@@ -171,6 +171,22 @@ void launch_apply_fine_solve(hipStream_t s, int P, int nd_max, int bd_max, const
                              const i32* bd, const i64* doff, const i64* dboff, const void* Fc,
                              const void* Fr, int fp32, const double* scale, double* u,
                              int variant = 0);
+// twist.hip: two-sided Dirichlet solves (top and bottom parts as two chains, explicit
+// inverse of the separator's Schur complement)
+void twist_split(int n, int b, int* nbt, int* nbb);  // nbt = 0: no split
+size_t apply_fine_twist_lds(int nd_max, int bd_max, size_t elem, bool cinv_lds);
+void launch_twist_extract(hipStream_t s, int P, int nB_max, int bd_max, const i32* nd,
+                          const i32* bd, const i32* nbt, const i32* nbb, const i64* dboff,
+                          const double* Dband, const i64* toff, double* Bt);
+template <typename T>
+void launch_twist_schur(hipStream_t s, int P, const i32* nd, const i32* bd, const i32* nbt,
+                        const i32* nbb, const i64* dboff, const double* Dband, const T* Fr,
+                        const i64* toff, const T* Gr, const i64* coff, T* Cinv, int* status);
+bool launch_apply_fine_twist(hipStream_t s, int P, int nd_max, int bd_max, const i32* nd,
+                             const i32* bd, const i64* doff, const i64* dboff, const void* Fc,
+                             const void* Fr, const i32* nbt, const i32* nbb, const i64* toff,
+                             const void* Gc, const void* Gr, const i64* coff, const void* Cinv,
+                             int fp32, const double* scale, double* u);
 void launch_apply_coarse_down(hipStream_t s, int P, int no_max, const i32* nown,
                               const i64* own_ptr, const i32* own_idx, const i64* loff,
                               const double* Inv, const i32* msub, const i64* yoff,

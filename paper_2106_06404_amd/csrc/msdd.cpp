@@ -245,6 +245,18 @@ struct FineLevel {
   std::vector<int32_t> h_wpos;  // warm-start frame position per Neumann row (-1 = none)
   DVec<int32_t> wpos;
   DVec<double> dscale;       // sc per Dirichlet dof (single-precision mode)
+  // two-sided form of the Dirichlet solves (twist.hip): blocks before the separator of
+  // the top and bottom parts, the bottom part's reversed band and LDL^T factor (nB rows
+  // per subdomain at toff), and the separator's C^{-1} (b x b at coff)
+  bool has_twist = false;    // every subdomain splits (planned at every setup)
+  bool twist_built = false;  // factors built (when the tuning asks for the form)
+  std::vector<int32_t> h_tnbt, h_tnbb, h_tnB;
+  std::vector<int64_t> h_toff, h_coff;
+  DVec<int32_t> tnbt, tnbb, tnB;
+  DVec<int64_t> toff, coff;
+  int tnB_max = 0;
+  DVec<double> Tband, TGc, TGr, TCinv;
+  DVec<float> TGc32, TGr32, TCinv32;
   int nd_max = 0, bd_max = 0, bw_max = 0, nb_max = 0;
   // sums used for the algorithmic byte / flop counts of the profiler
   double s_nb = 0, s_band = 0, s_nbb = 0, s_nd = 0, s_dband = 0, s_ndbd = 0, s_ndm = 0, s_m = 0;
@@ -700,6 +712,33 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
     F.s_dband += (double)S.nD * (S.bd + 1);
     F.s_ndbd += (double)S.nD * S.bd;
   }
+  // two-sided Dirichlet solves when every subdomain splits (half-bandwidth below 64 and
+  // at least 65 rows past it) and the workgroup's vector and tables fit in LDS
+  {
+    F.h_tnbt.assign(P, 0);
+    F.h_tnbb.assign(P, 0);
+    F.h_tnB.assign(P, 0);
+    F.h_toff.assign(P + 1, 0);
+    F.h_coff.assign(P + 1, 0);
+    F.tnB_max = 0;
+    bool ok = P > 0 && F.bd_max < 64;
+    for (int i = 0; i < P && ok; ++i) {
+      int nbt = 0, nbb = 0;
+      twist_split(F.h_nd[i], F.h_bd[i], &nbt, &nbb);
+      if (nbt <= 0) {
+        ok = false;
+        break;
+      }
+      F.h_tnbt[i] = nbt;
+      F.h_tnbb[i] = nbb;
+      F.h_tnB[i] = 64 * nbb + F.h_bd[i];
+      F.tnB_max = std::max(F.tnB_max, F.h_tnB[i]);
+      F.h_toff[i + 1] = F.h_toff[i] + (int64_t)F.h_tnB[i] * (F.h_bd[i] + 1);
+      F.h_coff[i + 1] = F.h_coff[i] + (int64_t)F.h_bd[i] * F.h_bd[i];
+    }
+    const size_t elem = c->opt.precision == MSDD_MIXED ? sizeof(float) : sizeof(double);
+    F.has_twist = ok && apply_fine_twist_lds(F.nd_max, F.bd_max, elem, false) <= 160 * 1024;
+  }
   // local index arithmetic of the eigensolver blocks (n_i x K, K <= 64) stays in 32 bits
   REQUIRE(F.nb_max <= kMaxLocalDofs,
           "a finest subdomain has " + std::to_string(F.nb_max) + " dofs; at most " +
@@ -806,6 +845,13 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   F.bd.upload(F.h_bd, s);
   F.doff.upload(F.h_doff, s);
   F.dboff.upload(F.h_dboff, s);
+  if (F.has_twist) {
+    F.tnbt.upload(F.h_tnbt, s);
+    F.tnbb.upload(F.h_tnbb, s);
+    F.tnB.upload(F.h_tnB, s);
+    F.toff.upload(F.h_toff, s);
+    F.coff.upload(F.h_coff, s);
+  }
   F.dpos.upload(F.h_dpos, s);
   F.dglob.upload(F.h_dglob, s);
   F.rankb.upload(F.h_rankb, s);
@@ -927,6 +973,44 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
     // the apply uses the LDL^T form: row layout in LDr, column layout in place in LDc
     launch_band_to_ldl<double>(s2, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.dboff.p, F.LDc.p,
                                F.LDr.p);
+    HIPCHK(hipGetLastError());
+  }
+  F.twist_built = F.has_twist && c->tune.fine_solve == 3;
+  if (F.twist_built) {
+    // two-sided solves: the bottom part's reversed band (from the scaled band in single
+    // precision), its factor and the separator's C^{-1}
+    ProfScope ps(c, PR_CHOL, F.s_dband * (mixed ? 4.0 : 8.0) * 4.0, F.s_ndbd * (F.bd_max + 2.0) * 0.5,
+                 s2);
+    const int64_t tn = std::max<int64_t>(F.h_toff.back(), 1);
+    F.Tband.alloc(tn);
+    launch_twist_extract(s2, P, F.tnB_max, F.bd_max, F.nd.p, F.bd.p, F.tnbt.p, F.tnbb.p, F.dboff.p,
+                         F.Dband.p, F.toff.p, F.Tband.p);
+    const int64_t cn = std::max<int64_t>(F.h_coff.back(), 1);
+    if (mixed) {
+      F.TGc32.alloc(tn);
+      F.TGr32.alloc(tn);
+      F.TGc32.zero(s2);
+      F.TGr32.zero(s2);
+      F.TCinv32.alloc(cn);
+      launch_band_cholesky<float>(s2, P, nullptr, F.bd_max, F.tnB.p, F.bd.p, F.toff.p, F.Tband.p,
+                                  nullptr, nullptr, 0.0, F.toff.p, F.TGc32.p, F.TGr32.p, st_dchol.p);
+      launch_band_to_ldl<float>(s2, P, F.tnB_max, F.bd_max, F.tnB.p, F.bd.p, F.toff.p, F.TGc32.p,
+                                F.TGr32.p);
+      launch_twist_schur<float>(s2, P, F.nd.p, F.bd.p, F.tnbt.p, F.tnbb.p, F.dboff.p, F.Dband.p,
+                                F.LDr32.p, F.toff.p, F.TGr32.p, F.coff.p, F.TCinv32.p, st_dchol.p);
+    } else {
+      F.TGc.alloc(tn);
+      F.TGr.alloc(tn);
+      F.TGc.zero(s2);
+      F.TGr.zero(s2);
+      F.TCinv.alloc(cn);
+      launch_band_cholesky<double>(s2, P, nullptr, F.bd_max, F.tnB.p, F.bd.p, F.toff.p, F.Tband.p,
+                                   nullptr, nullptr, 0.0, F.toff.p, F.TGc.p, F.TGr.p, st_dchol.p);
+      launch_band_to_ldl<double>(s2, P, F.tnB_max, F.bd_max, F.tnB.p, F.bd.p, F.toff.p, F.TGc.p,
+                                 F.TGr.p);
+      launch_twist_schur<double>(s2, P, F.nd.p, F.bd.p, F.tnbt.p, F.tnbb.p, F.dboff.p, F.Dband.p,
+                                 F.LDr.p, F.toff.p, F.TGr.p, F.coff.p, F.TCinv.p, st_dchol.p);
+    }
     HIPCHK(hipGetLastError());
   }
   F.LSc.alloc(F.h_boff.back());
@@ -1898,6 +1982,34 @@ void alloc_solve_work(msdd_ctx* c) {
 // are independent: without profiling the coarse chain runs on a second stream, forked
 // and joined with events (inside a captured iteration graph these become graph edges),
 // so that it overlaps the solves.
+// The finest-level local solves u_i = A_i^{-1} u_i.  variant: 0 = by shape (the rolling
+// window for half-bandwidths below 64, else one wavefront), 1 = rolling window, 2 = one
+// wavefront per subdomain, 3 = two-sided (when its factors were built at the setup, else
+// by shape).
+static void fine_local_solve(msdd_ctx* c, hipStream_t s, double* u, int variant) {
+  FineLevel& F = c->F;
+  const bool f32 = c->opt.precision == MSDD_MIXED;
+  if (F.twist_built && variant == 3) {
+    const bool ok =
+        f32 ? launch_apply_fine_twist(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p,
+                                      F.dboff.p, F.LDc32.p, F.LDr32.p, F.tnbt.p, F.tnbb.p,
+                                      F.toff.p, F.TGc32.p, F.TGr32.p, F.coff.p, F.TCinv32.p, 1,
+                                      F.dscale.p, u)
+            : launch_apply_fine_twist(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p,
+                                      F.dboff.p, F.LDc.p, F.LDr.p, F.tnbt.p, F.tnbb.p, F.toff.p,
+                                      F.TGc.p, F.TGr.p, F.coff.p, F.TCinv.p, 0, nullptr, u);
+    REQUIRE(ok, "two-sided Dirichlet solves planned for a shape that does not fit");
+    return;
+  }
+  const int v = variant == 3 ? 0 : variant;
+  if (f32)
+    launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
+                            F.LDc32.p, F.LDr32.p, 1, F.dscale.p, u, v);
+  else
+    launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
+                            F.LDc.p, F.LDr.p, 0, nullptr, u, v);
+}
+
 void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
   FineLevel& F = c->F;
   const int L = c->n_levels - 1;
@@ -1923,12 +2035,7 @@ void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
     ProfScope ps(c, PR_APPLY_FINE,
                  2.0 * F.s_dband * (f32 ? 4.0 : 8.0) + 2.0 * F.s_nd * 8.0 + (f32 ? 2.0 * F.s_nd * 8.0 : 0.0),
                  4.0 * F.s_ndbd + F.s_nd);
-    if (f32)
-      launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
-                              F.LDc32.p, F.LDr32.p, 1, F.dscale.p, c->u.p, c->tune.fine_solve);
-    else
-      launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
-                              F.LDc.p, F.LDr.p, 0, nullptr, c->u.p, c->tune.fine_solve);
+    fine_local_solve(c, s, c->u.p, c->tune.fine_solve);
   }
   {
     ProfScope ps(c, PR_APPLY_COARSE);
@@ -1984,12 +2091,7 @@ void apply_hybrid(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
     ProfScope ps(c, PR_APPLY_FINE,
                  2.0 * F.s_dband * (f32 ? 4.0 : 8.0) + 2.0 * F.s_nd * 8.0 + (f32 ? 2.0 * F.s_nd * 8.0 : 0.0),
                  4.0 * F.s_ndbd + F.s_nd);
-    if (f32)
-      launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
-                              F.LDc32.p, F.LDr32.p, 1, F.dscale.p, c->u.p, c->tune.fine_solve);
-    else
-      launch_apply_fine_solve(s, F.P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
-                              F.LDc.p, F.LDr.p, 0, nullptr, c->u.p, c->tune.fine_solve);
+    fine_local_solve(c, s, c->u.p, c->tune.fine_solve);
   }
   {
     ProfScope ps(c, PR_APPLY_GATHER, (double)(n + 1) * 8.0 + F.s_nd * 24.0 + n * 8.0, 2.0 * F.s_nd);
@@ -2924,16 +3026,10 @@ int msdd_autotune(msdd_ctx* c, int32_t what, int32_t reps) {
       u.zero(s);
       for (float& v : T.fine_solve_ms) v = 0.f;
       int best = 0;
-      for (int v = 1; v <= 2; ++v) {
+      for (int v = 1; v <= 3; ++v) {
         if (v == 1 && F.bd_max >= 64) continue;  // rolling window needs a band below 64
-        T.fine_solve_ms[v] = time_it([&] {
-          if (f32)
-            launch_apply_fine_solve(s, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
-                                    F.LDc32.p, F.LDr32.p, 1, F.dscale.p, u.p, v);
-          else
-            launch_apply_fine_solve(s, P, F.nd_max, F.bd_max, F.nd.p, F.bd.p, F.doff.p, F.dboff.p,
-                                    F.LDc.p, F.LDr.p, 0, nullptr, u.p, v);
-        });
+        if (v == 3 && !F.twist_built) continue;  // two-sided factors built at the setup
+        T.fine_solve_ms[v] = time_it([&] { fine_local_solve(c, s, u.p, v); });
         if (!best || T.fine_solve_ms[v] < T.fine_solve_ms[best]) best = v;
       }
       T.fine_solve = best;
@@ -2975,7 +3071,7 @@ int msdd_get_tuning(const msdd_ctx* c, msdd_tuning_t* t) {
 int msdd_set_tuning(msdd_ctx* c, const msdd_tuning_t* t) {
   if (!c || !t) return MSDD_EINVAL;
   const bool ok = t->eig_solve >= 0 && t->eig_solve <= 9 && t->eig_splits >= 0 &&
-                  t->eig_splits <= 16 && t->fine_solve >= 0 && t->fine_solve <= 2 &&
+                  t->eig_splits <= 16 && t->fine_solve >= 0 && t->fine_solve <= 3 &&
                   (t->spmv_group == 0 || t->spmv_group == 4 || t->spmv_group == 8 ||
                    t->spmv_group == 16 || t->spmv_group == 32);
   if (!ok) {
