@@ -1501,7 +1501,8 @@ void fine_patches(msdd_ctx* c, const double* d_elem_mat, PatchLevel& PL, PatchPl
   U.alloc(std::max<int64_t>(vpoff.back(), 1));
   PL.Pm.alloc(std::max<int64_t>(PL.pmoff.back(), 1));
   {
-  ProfScope pscope(c, PR_PATCH);
+  // algorithmic bytes: the members' basis blocks read, the patch matrices written
+  ProfScope pscope(c, PR_PATCH, 8.0 * ((double)F.h_phi_off.back() + (double)PL.pmoff.back()));
   launch_patch_gather(s, PL.np, gs.voff.p, PL.dM.p, dmem_ptr.p, dmem_sub.p, dmem_col.p,
                       dploc_off.p, dploc.p, F.gs.n.p, F.dm.p, F.phi_off.p, F.Phi.p, dvpoff.p, V.p);
   launch_patch_av(s, gs.total_rows, gs.row_grp.p, gs.voff.p, PL.dM.p, gs.inc_ptr.p, gs.inc_slot.p,
@@ -1534,7 +1535,8 @@ void run_assemble(msdd_ctx* c, const AssembleJob& J, const PatchLevel& PL, DVec<
   tp_map.upload(J.tp_map, s);
   A.alloc(std::max<int64_t>(J.aoff.back(), 1));
   {
-  ProfScope ps(c, PR_COARSE);
+  // algorithmic bytes: the patch matrices read, the dense coarse matrices written
+  ProfScope ps(c, PR_COARSE, 8.0 * ((double)PL.pmoff.back() + (double)J.aoff.back()));
   launch_coarse_assemble(s, (int)J.ng.size(), tp_ptr.p, tp_patch.p, tp_map_off.p, tp_map.p,
                          PL.dM.p, PL.dpmoff.p, PL.Pm.p, ng.p, aoff.p, A.p);
   }
@@ -1804,7 +1806,10 @@ void coarse_level(msdd_ctx* c, int l, const std::vector<int32_t>& par,
   DVec<double> Wsc;
   Wsc.alloc(std::max<int64_t>(wsoff.back(), 1));
   {
-  ProfScope pscope2(c, PR_PATCH);
+  // algorithmic bytes: this level's patch matrices and owned bases read, the next level's
+  // patch matrices written
+  ProfScope pscope2(c, PR_PATCH, 8.0 * ((double)PL.pmoff.back() + (double)CL.h_yoff.back() +
+                                        (double)PLnext.pmoff.back()));
   vlog(c, "coarse: next-level patch plan", &tv);
   launch_patch_project(s, PLnext.np, dch_ptr.p, dch_patch.p, PL.dM.p, PL.dpmoff.p, PL.Pm.p,
                        dcmem_ptr.p, dcmem_pslot.p, dcmem_ownbase.p, dcmem_m.p, dcmem_col.p,
@@ -1982,6 +1987,26 @@ void alloc_solve_work(msdd_ctx* c) {
 // are independent: without profiling the coarse chain runs on a second stream, forked
 // and joined with events (inside a captured iteration graph these become graph edges),
 // so that it overlaps the solves.
+// Algorithmic work of the coarse part of one preconditioner apply: per coarse level the
+// owned blocks' inverses (no_i^2) and the basis blocks (no_i m_i, read on the way down and
+// up), the vectors they touch, and the coarsest inverse (n_0^2 per problem).
+static void apply_coarse_work(const msdd_ctx* c, double* bytes, double* flops) {
+  double by = 0, fl = 0;
+  for (const CoarseLevel& CL : c->C) {
+    const double inv = CL.h_loff.empty() ? 0.0 : (double)CL.h_loff.back();
+    const double y = CL.h_yoff.empty() ? 0.0 : (double)CL.h_yoff.back();
+    const double no = CL.h_own_ptr.empty() ? 0.0 : (double)CL.h_own_ptr.back();
+    const double m = CL.h_moff.empty() ? 0.0 : (double)CL.h_moff.back();
+    by += 8.0 * (inv + 2.0 * y + 4.0 * no + 2.0 * m) + 8.0 * no;  // + the owned indices
+    fl += 2.0 * inv + 4.0 * y;
+  }
+  const double a0 = c->h_a0off.empty() ? 0.0 : (double)c->h_a0off.back();
+  by += 8.0 * a0;
+  fl += 2.0 * a0;
+  *bytes = by;
+  *flops = fl;
+}
+
 // The finest-level local solves u_i = A_i^{-1} u_i.  variant: 0 = by shape (the rolling
 // window for half-bandwidths below 64, else one wavefront), 1 = rolling window, 2 = one
 // wavefront per subdomain, 3 = two-sided (when its factors were built at the setup, else
@@ -2038,7 +2063,9 @@ void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
     fine_local_solve(c, s, c->u.p, c->tune.fine_solve);
   }
   {
-    ProfScope ps(c, PR_APPLY_COARSE);
+    double acb = 0, acf = 0;
+    apply_coarse_work(c, &acb, &acf);
+    ProfScope ps(c, PR_APPLY_COARSE, acb, acf);
     // coarse levels, downward: C[t] is level L-1-t
     for (int t = 0; t < (int)c->C.size(); ++t) {
       CoarseLevel& CL = c->C[t];
@@ -2109,7 +2136,9 @@ void apply_hybrid(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
       launch_residual_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, r, q, t, c->partial.p);
     }
     fine_restrict(t);  // rc_top = P_{L-1}^T t (the local copies in u are not used)
-    ProfScope ps(c, PR_APPLY_COARSE);
+    double acb = 0, acf = 0;
+    apply_coarse_work(c, &acb, &acf);
+    ProfScope ps(c, PR_APPLY_COARSE, acb, acf);
     // restriction down to level l (owned solves of the levels passed are not used), then the
     // solve on level l
     for (int tt = 0; tt < (int)c->C.size(); ++tt) {
