@@ -13,7 +13,9 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_build", "libmsdd.so")
+# the in-tree build; MSDD_LIB may name another build of the same sources (the host-code
+# sanitizer build under _build_ubsan/)
+LIB_PATH = os.environ.get("MSDD_LIB") or os.path.join(_HERE, "_build", "libmsdd.so")
 
 MSDD_OK = 0
 MSDD_EINVAL = -1

@@ -29,14 +29,26 @@ def compile_flags():
     ]
 
 
-def build(verbose: bool = False) -> str:
+# Host-code sanitizer build (undefined-behaviour checks on the host planner, the runtime
+# around the kernels and the C ABI; device code is built as usual): a separate library
+# under _build_ubsan/, loaded instead of the regular one when MSDD_LIB names it.  Any
+# undefined behaviour aborts the process with a report.
+UBSAN_DIR = os.path.join(HERE, "_build_ubsan")
+UBSAN_FLAGS = ["-Xarch_host", "-fsanitize=undefined", "-Xarch_host", "-fno-sanitize-recover=all",
+               "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
     """Compile every source to an object, then link the shared library (always rebuilds)."""
-    os.makedirs(OUT_DIR, exist_ok=True)
+    out_dir = UBSAN_DIR if sanitize else OUT_DIR
+    lib = os.path.join(out_dir, "libmsdd.so")
+    extra = UBSAN_FLAGS if sanitize else []
+    os.makedirs(out_dir, exist_ok=True)
     objs = []
     procs = []
     for src in SOURCES:
-        obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC] + compile_flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC] + compile_flags() + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -53,12 +65,20 @@ def build(verbose: bool = False) -> str:
         for src, txt in failed:
             sys.stderr.write(f"--- {src} ---\n{txt}\n")
         raise RuntimeError("hipcc failed for " + ", ".join(s for s, _ in failed))
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    tmp = lib + f".tmp{os.getpid()}"
+    link_extra = []
+    if sanitize:
+        # the sanitizer runtime is found through the compiler's resource directory
+        res = subprocess.check_output([os.path.join(os.path.dirname(os.path.realpath(HIPCC)),
+                                                    "..", "lib", "llvm", "bin", "clang++"),
+                                       "-print-resource-dir"], text=True).strip()
+        rt = os.path.join(res, "lib", "linux")
+        link_extra = ["-fsanitize=undefined", "-shared-libsan", f"-Wl,-rpath,{rt}"]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + link_extra + objs
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--ubsan" in sys.argv))
