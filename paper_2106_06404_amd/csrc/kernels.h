@@ -160,6 +160,9 @@ void launch_update_p_chunk(hipStream_t s, int nch, const i64* ch_lo, const i64* 
                            int first);
 void launch_seg_reduce(hipStream_t s, int nseg, const i64* seg_ch, const double* partial,
                        double* D, int* I, int rule, double rtol, int maxit, double* hist);
+// *flag = 1 if a row's columns leave its problem's dof range [pdp[t], pdp[t+1])
+void launch_check_problem_coupling(hipStream_t s, i64 n, const i64* rowptr, const i32* col,
+                                   const i64* pdp, int nprob, int* flag);
 void launch_apply_fine_restrict(hipStream_t s, int P, int nd_max, const i32* nd, const i64* doff,
                                 const i32* dglob, const i32* msub, const i64* moff,
                                 const i64* phid_off, const double* PhiD, const double* r,

@@ -444,6 +444,11 @@ struct msdd_ctx {
   std::vector<double> scr_pou;
   std::vector<int32_t> scr_cnt;
   std::vector<int32_t> scr_ecnt;
+  // per planning thread: global dof -> local index maps of size n, all -1 between uses
+  // (plan_group restores the entries it sets); kept across setups so that the n-sized
+  // arrays are not allocated and filled again; marked dirty while a planning pass runs
+  std::vector<std::vector<int>> scr_maps;
+  bool scr_maps_clean = false;
   std::vector<int64_t> scr_pos;
   msdd_tuning_t tune{};            // launch-shape choices (0 = by shape)
   ~msdd_ctx() {
@@ -564,7 +569,12 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   }
   std::vector<SubPlan> sp(P);
   const int nthr = host_threads(P);
-  std::vector<std::vector<int>> maps(nthr);
+  std::vector<std::vector<int>>& maps = c->scr_maps;
+  if (!c->scr_maps_clean) maps.clear();  // a pass that did not finish may have left entries
+  if ((int)maps.size() < nthr) maps.resize(nthr);
+  for (auto& mp : maps)
+    if (!mp.empty() && (int64_t)mp.size() != n) mp.clear();
+  c->scr_maps_clean = false;
   parallel_for(P, nthr, [&](int i, int t) {
     if (maps[t].empty()) maps[t].assign(n, -1);
     SubPlan& S = sp[i];
@@ -668,6 +678,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
       S.ell_w = std::max(S.ell_w, S.ell_ptr[r + 1] - S.ell_ptr[r]);
     }
   });
+  c->scr_maps_clean = true;  // every plan_group call restored its entries
   for (int i = 0; i < P; ++i)
     if (!sp[i].err.empty()) throw MsddError{MSDD_EINVAL, sp[i].err};
   vlog(c, "plan: subdomain groups (parallel)", &tv);
@@ -2310,11 +2321,6 @@ int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
       std::vector<char> has(nprob, 0);
       for (int32_t t : prob_cur) has[t] = 1;
       for (int t = 0; t < nprob; ++t) REQUIRE(has[t], "problem " + std::to_string(t) + " has no subdomain");
-      std::vector<int32_t> hcol = to_host(col, (size_t)c->nnz);
-      for (int t = 0; t < nprob; ++t)
-        for (int64_t r = pdp[t]; r < pdp[t + 1]; ++r)
-          for (int64_t e = h_rowptr[r]; e < h_rowptr[r + 1]; ++e)
-            REQUIRE(hcol[e] >= pdp[t] && hcol[e] < pdp[t + 1], "the matrix couples two problems");
     }
     std::vector<std::vector<int32_t>> prob_lvl(1, prob_cur);  // [0] = finest, then coarser
     for (const auto& pm : parents) {
@@ -2338,6 +2344,17 @@ int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     to_device(c->rowptr, rowptr, (size_t)n + 1, s);
     to_device(c->col, col, (size_t)c->nnz, s);
     to_device(c->val, val, (size_t)c->nnz, s);
+    if (nprob > 1) {
+      // A must not couple problems: checked on the device copies, one thread per row
+      DVec<int64_t> dpdp;
+      dpdp.upload(pdp, s);
+      DVec<int> flag;
+      flag.alloc(1);
+      flag.zero(s);
+      launch_check_problem_coupling(s, n, c->rowptr.p, c->col.p, dpdp.p, nprob, flag.p);
+      HIPCHK(hipGetLastError());
+      REQUIRE(flag.download(s)[0] == 0, "the matrix couples two problems");
+    }
     DVec<double> emat_holder;
     const double* d_emat = elem_mat;
     if (!is_device_ptr(elem_mat)) {

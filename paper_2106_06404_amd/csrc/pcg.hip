@@ -534,3 +534,30 @@ void* noalloc_scratch(int device) {
   std::lock_guard<std::mutex> lk(g_scratch_mu);
   return g_scratch_ptr[device];
 }
+
+// Input check of a batched matrix: every row's columns lie in its own problem's dof range
+// (pdp[t] <= col < pdp[t+1] for the problem t holding the row).  One thread per row; a
+// violation sets *flag (any writer, same value).
+__global__ void k_check_problem_coupling(i64 n, const i64* __restrict__ rowptr,
+                                         const i32* __restrict__ col, const i64* __restrict__ pdp,
+                                         int nprob, int* __restrict__ flag) {
+  for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x) {
+    int lo = 0, hi = nprob;  // pdp[lo] <= r < pdp[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pdp[mid] <= r) lo = mid;
+      else hi = mid;
+    }
+    const i64 a = pdp[lo], b = pdp[lo + 1];
+    bool bad = false;
+    for (i64 e = rowptr[r]; e < rowptr[r + 1]; ++e) bad |= col[e] < a || col[e] >= b;
+    if (bad) *flag = 1;
+  }
+}
+void launch_check_problem_coupling(hipStream_t s, i64 n, const i64* rowptr, const i32* col,
+                                   const i64* pdp, int nprob, int* flag) {
+  if (n == 0) return;
+  const int g = (int)std::min<i64>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_check_problem_coupling, dim3(g), dim3(256), 0, s, n, rowptr, col, pdp, nprob,
+                     flag);
+}

@@ -80,6 +80,15 @@ def test_batch_rules_are_checked():
     with pytest.raises(B.MsddError) as e:
         m.setup_batch(**bad)
     assert e.value.code == B.MSDD_EINVAL
+    # a matrix entry of problem 0 pointing into problem 1 (subdomains unchanged): the
+    # device-side check of the matrix's problem blocks rejects it
+    bad = dict(arrs)
+    col = arrs["col"].copy()
+    col[arrs["rowptr"][0]] = arrs["prob_dof_ptr"][1]
+    bad["col"] = col
+    with pytest.raises(B.MsddError) as e:
+        m.setup_batch(**bad)
+    assert e.value.code == B.MSDD_EINVAL and "couples two problems" in str(e.value)
     m.setup_batch(**arrs)   # the context is still usable
     m.close()
 
