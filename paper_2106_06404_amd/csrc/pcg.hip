@@ -255,9 +255,9 @@ __global__ void __launch_bounds__(ROT_NT) k_apply_fine_rot(
   T* tiles = rl + ((nd_max + 3) & ~3);
   double* ui = u + doff[i];
   const double* si = scale ? scale + doff[i] : nullptr;
-  for (int q = threadIdx.x; q < n; q += ROT_NT) rl[q] = (T)(si ? ui[q] * si[q] : ui[q]);
-  __syncthreads();
-  wg_ldl_solve_rot<T, T>(n, bd[i], Fc + dboff[i], Fr + dboff[i], rl, tiles);
+  wg_ldl_solve_rot<T, T>(n, bd[i], Fc + dboff[i], Fr + dboff[i], rl, tiles, [&] {
+    for (int q = threadIdx.x; q < n; q += ROT_NT) rl[q] = (T)(si ? ui[q] * si[q] : ui[q]);
+  });
   for (int q = threadIdx.x; q < n; q += ROT_NT) ui[q] = si ? (double)rl[q] * si[q] : (double)rl[q];
 }
 

@@ -246,9 +246,12 @@ __device__ __forceinline__ void rot_block(const V* buf, int lane, V& a, V& a2) {
   }
 }
 
-template <typename T, typename V>
+//   init(): called by all threads once the first table segment's reads are in flight;
+//   fills v (the reads of the segment and of the vector then overlap).
+template <typename T, typename V, typename Init>
 __device__ __forceinline__ void wg_ldl_solve_rot(int n, int b, const T* __restrict__ Fc,
-                                                 const T* __restrict__ Fr, V* v, V* tiles) {
+                                                 const T* __restrict__ Fr, V* v, V* tiles,
+                                                 Init init) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int w = b + 1;
   const int nblk = (n + 63) >> 6;
@@ -296,11 +299,13 @@ __device__ __forceinline__ void wg_ldl_solve_rot(int n, int b, const T* __restri
     }
     if (tl < 64) buf[8192 + tl] = (V)gd;
   };
-  // zero both buffers (positions without an entry stay zero), then stage step 0
+  // read step 0's segment, zero both buffers (positions without an entry stay zero) and
+  // fill the vector while it is in flight, then stage step 0
+  if (wave > 0) stage_load(0);
   for (int t = threadIdx.x; t < 2 * ROT_TILE; t += ROT_NT) tiles[t] = (V)0;
+  init();
   __syncthreads();
   if (wave > 0) {
-    stage_load(0);
     stage_store(tiles);
     if (nsteps > 1) stage_load(1);
   }
