@@ -14,6 +14,8 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <functional>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -39,6 +41,62 @@ int host_threads(int work) {
   return std::max(1, std::min(nt, work));
 }
 
+// Worker threads kept for the life of the process (created on first use, never joined),
+// shared by the planning loops of every context, so that a setup does not create and join
+// its threads loop after loop.  run() executes body(t) on workers t = 1 .. nthr-1 and on
+// the caller as t = 0 and returns when all have finished; a caller that finds the workers
+// busy (another thread planning at the same time) gets false and runs on threads of its
+// own instead.
+class HostPool {
+ public:
+  static HostPool& get() {
+    static HostPool* p = new HostPool;  // never destroyed: its threads outlive static exit
+    return *p;
+  }
+  bool run(int nthr, const std::function<void(int)>& body) {
+    std::unique_lock<std::mutex> busy(run_mu_, std::try_to_lock);
+    if (!busy.owns_lock()) return false;
+    while ((int)workers_ < nthr - 1) {
+      const int id = ++workers_;
+      std::thread([this, id] { loop(id); }).detach();
+    }
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      body_ = &body;
+      want_ = nthr - 1;
+      pending_ = nthr - 1;
+      ++gen_;
+    }
+    cv_.notify_all();
+    body(0);
+    std::unique_lock<std::mutex> g(mu_);
+    done_.wait(g, [&] { return pending_ == 0; });
+    body_ = nullptr;
+    return true;
+  }
+
+ private:
+  void loop(int id) {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> g(mu_);
+    for (;;) {
+      cv_.wait(g, [&] { return gen_ != seen; });
+      seen = gen_;
+      if (id > want_) continue;  // not needed in this loop
+      const std::function<void(int)>* b = body_;
+      g.unlock();
+      (*b)(id);
+      g.lock();
+      if (--pending_ == 0) done_.notify_one();
+    }
+  }
+  std::mutex run_mu_, mu_;
+  std::condition_variable cv_, done_;
+  int workers_ = 0, want_ = 0, pending_ = 0;
+  uint64_t gen_ = 0;
+  const std::function<void(int)>* body_ = nullptr;
+};
+
 // f(i, thread) for i in [0, n) on nthr threads (dynamic schedule); MsddError from a
 // worker is rethrown on the caller.
 template <class F>
@@ -48,21 +106,23 @@ void parallel_for(int n, int nthr, F f) {
     return;
   }
   std::atomic<int> next(0);
-  std::vector<std::thread> th;
   std::vector<MsddError> errs;
   std::mutex mu;
-  for (int t = 0; t < nthr; ++t)
-    th.emplace_back([&, t] {
-      try {
-        int i;
-        while ((i = next++) < n) f(i, t);
-      } catch (const MsddError& e) {
-        std::lock_guard<std::mutex> g(mu);
-        errs.push_back(e);
-        next = n;
-      }
-    });
-  for (auto& x : th) x.join();
+  const std::function<void(int)> body = [&](int t) {
+    try {
+      int i;
+      while ((i = next++) < n) f(i, t);
+    } catch (const MsddError& e) {
+      std::lock_guard<std::mutex> g(mu);
+      errs.push_back(e);
+      next = n;
+    }
+  };
+  if (!HostPool::get().run(nthr, body)) {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nthr; ++t) th.emplace_back(body, t);
+    for (auto& x : th) x.join();
+  }
   if (!errs.empty()) throw errs.front();
 }
 
