@@ -172,7 +172,7 @@ __host__ __device__ inline int wave_ring_size(int b) {
 
 // ---------------------------------------------------------------------------
 // Rolling-window LDL^T band solve for b < 64 with one workgroup of ROT_NT
-// threads: wavefront 0 runs the substitution, the others stage the factor.
+// threads: wavefront 0 runs the substitution, six others stage the factor.
 //
 //   Fc (column layout, ld w = b+1): Fc[c*w + d] = Lt(c+d, c) for 1 <= d <= b;
 //   Fr (row layout):                Fr[j*w + d] = Lt(j, j-d) for 1 <= d <= b,
@@ -207,7 +207,11 @@ __host__ __device__ inline int wave_ring_size(int b) {
 // ---------------------------------------------------------------------------
 constexpr int ROT_NT = 512;
 constexpr int ROT_TILE = 2 * 4096 + 64;          // Tc, Tn, 1/D of the next block's rows
-constexpr int ROT_PER = (64 * 64 + ROT_NT - 65) / (ROT_NT - 64);  // segment entries per stager
+// staging threads: wavefronts 1-3 and 5-7; wavefront 4 shares the substitution's SIMD
+// (wavefront w runs on SIMD w mod 4) and only takes part in the barriers (measured: 61.3
+// -> 58.6 us per apply on 1225-row subdomains)
+constexpr int ROT_NS = ROT_NT - 128;
+constexpr int ROT_PER = (64 * 64 + ROT_NS - 1) / ROT_NS;  // segment entries per stager
 
 // 64 substitution steps of one block, in chunks of CH; the table entries of chunk
 // c+1 are read while chunk c runs (scheduling barriers keep the reads ahead).
@@ -258,8 +262,8 @@ __device__ __forceinline__ void wg_ldl_solve_rot(int n, int b, const T* __restri
   const int nsteps = 2 * nblk;
   const int N = nblk * 64;
   const int seg = 64 * w;
-  const int tl = threadIdx.x - 64;  // staging thread index
-  constexpr int NS = ROT_NT - 64;
+  const int tl = wave < 4 ? threadIdx.x - 64 : threadIdx.x - 128;  // staging thread index
+  constexpr int NS = ROT_NS;
   // staging registers: one segment of the step after next
   T gv[ROT_PER];
   int gpos[ROT_PER];  // table position (k*64 + l) + 1, 0 = no entry; bit 30 = Tn
@@ -301,11 +305,11 @@ __device__ __forceinline__ void wg_ldl_solve_rot(int n, int b, const T* __restri
   };
   // read step 0's segment, zero both buffers (positions without an entry stay zero) and
   // fill the vector while it is in flight, then stage step 0
-  if (wave > 0) stage_load(0);
+  if (wave > 0 && wave != 4) stage_load(0);
   for (int t = threadIdx.x; t < 2 * ROT_TILE; t += ROT_NT) tiles[t] = (V)0;
   init();
   __syncthreads();
-  if (wave > 0) {
+  if (wave > 0 && wave != 4) {
     stage_store(tiles);
     if (nsteps > 1) stage_load(1);
   }
@@ -313,7 +317,9 @@ __device__ __forceinline__ void wg_ldl_solve_rot(int n, int b, const T* __restri
   V a = 0, a2 = 0;
   for (int s = 0; s < nsteps; ++s) {
     V* buf = tiles + (s & 1) * ROT_TILE;
-    if (wave > 0) {
+    if (wave == 4) {
+      // idle: barriers only
+    } else if (wave > 0) {
       if (s + 1 < nsteps) {
         stage_store(tiles + ((s + 1) & 1) * ROT_TILE);
         if (s + 2 < nsteps) stage_load(s + 2);
