@@ -207,11 +207,16 @@ __host__ __device__ inline int wave_ring_size(int b) {
 // ---------------------------------------------------------------------------
 constexpr int ROT_NT = 512;
 constexpr int ROT_TILE = 2 * 4096 + 64;          // Tc, Tn, 1/D of the next block's rows
-// staging threads: wavefronts 1-3 and 5-7; wavefront 4 shares the substitution's SIMD
-// (wavefront w runs on SIMD w mod 4) and only takes part in the barriers (measured: 61.3
-// -> 58.6 us per apply on 1225-row subdomains)
-constexpr int ROT_NS = ROT_NT - 128;
-constexpr int ROT_PER = (64 * 64 + ROT_NS - 1) / ROT_NS;  // segment entries per stager
+// Staging threads: in FP64, wavefronts 1-3 and 5-7, wavefront 4 (which shares the
+// substitution's SIMD: wavefront w runs on SIMD w mod 4) only taking part in the barriers
+// (measured on 1225-row subdomains: 61.3 -> 58.6 us per apply); in FP32, whose faster
+// substitution leaves the staging the longer part, all seven.
+template <typename V>
+struct RotStage {
+  static constexpr bool skip4 = sizeof(V) == 8;
+  static constexpr int ns = skip4 ? ROT_NT - 128 : ROT_NT - 64;
+  static constexpr int per = (64 * 64 + ns - 1) / ns;  // segment entries per stager
+};
 
 // 64 substitution steps of one block, in chunks of CH; the table entries of chunk
 // c+1 are read while chunk c runs (scheduling barriers keep the reads ahead).
@@ -262,8 +267,11 @@ __device__ __forceinline__ void wg_ldl_solve_rot(int n, int b, const T* __restri
   const int nsteps = 2 * nblk;
   const int N = nblk * 64;
   const int seg = 64 * w;
-  const int tl = wave < 4 ? threadIdx.x - 64 : threadIdx.x - 128;  // staging thread index
-  constexpr int NS = ROT_NS;
+  constexpr int NS = RotStage<V>::ns;
+  constexpr int ROT_PER = RotStage<V>::per;
+  const bool stager = wave > 0 && !(RotStage<V>::skip4 && wave == 4);
+  // staging thread index
+  const int tl = (RotStage<V>::skip4 && wave > 4) ? threadIdx.x - 128 : threadIdx.x - 64;
   // staging registers: one segment of the step after next
   T gv[ROT_PER];
   int gpos[ROT_PER];  // table position (k*64 + l) + 1, 0 = no entry; bit 30 = Tn
@@ -305,11 +313,11 @@ __device__ __forceinline__ void wg_ldl_solve_rot(int n, int b, const T* __restri
   };
   // read step 0's segment, zero both buffers (positions without an entry stay zero) and
   // fill the vector while it is in flight, then stage step 0
-  if (wave > 0 && wave != 4) stage_load(0);
+  if (stager) stage_load(0);
   for (int t = threadIdx.x; t < 2 * ROT_TILE; t += ROT_NT) tiles[t] = (V)0;
   init();
   __syncthreads();
-  if (wave > 0 && wave != 4) {
+  if (stager) {
     stage_store(tiles);
     if (nsteps > 1) stage_load(1);
   }
@@ -317,10 +325,8 @@ __device__ __forceinline__ void wg_ldl_solve_rot(int n, int b, const T* __restri
   V a = 0, a2 = 0;
   for (int s = 0; s < nsteps; ++s) {
     V* buf = tiles + (s & 1) * ROT_TILE;
-    if (wave == 4) {
-      // idle: barriers only
-    } else if (wave > 0) {
-      if (s + 1 < nsteps) {
+    if (wave > 0) {
+      if (stager && s + 1 < nsteps) {
         stage_store(tiles + ((s + 1) & 1) * ROT_TILE);
         if (s + 2 < nsteps) stage_load(s + 2);
       }
