@@ -103,6 +103,16 @@ typedef struct {
                          are cells and faces, a basis function lives on one cell, and the
                          subdomain's element set holds only the faces interior to it, so a
                          face to a neighbour outside must not exclude the cell's dofs) */
+  int eig_fp32;       /* finest-level eigensolver (Sec. 2.3 GEVP): 0 = shift-invert with the
+                         FP64 factor of S = abar + sigma b (default); 1 = the factor of
+                         diag(s) S diag(s), s = diag(S)^{-1/2}, in single precision, used as
+                         the preconditioner of the block iteration
+                         Y = X N + diag(s) M^{-1} diag(s) (B X - S X N) (N the current Ritz
+                         values), with S Y formed in FP64 for the Rayleigh-Ritz step, so the
+                         pairs, residuals and counts are those of the FP64 pencil; a
+                         subdomain that does not certify its count within
+                         min(eig_maxit, 64) iterations is solved again with the FP64
+                         factor (built then); b = b^1 only (geneo_rhs = 1) */
 } msdd_options;
 
 typedef struct {
@@ -136,6 +146,10 @@ typedef struct {
                              tolerance */
   double eig_energy_resid_max; /* largest energy residual of a selected finest-level pair
                              (of its iterate one step before acceptance) */
+  int32_t eig_fp64_fallbacks; /* eig_fp32 = 1: finest-level subdomains whose single-precision
+                             factor iteration did not certify its count within
+                             min(eig_maxit, 64) iterations and that were solved again
+                             with the FP64 factor */
 } msdd_stats_t;
 
 /* Fill *opt with defaults. */

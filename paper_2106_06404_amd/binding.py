@@ -38,7 +38,8 @@ class MsddOptions(ctypes.Structure):
                 ("eig_tol", ctypes.c_double), ("eig_maxit", ctypes.c_int),
                 ("block", ctypes.c_int), ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("verbose", ctypes.c_int), ("geneo_rhs", ctypes.c_int), ("nev_fixed", ctypes.c_int),
-                ("eig_tol_energy", ctypes.c_double), ("dirichlet_rule", ctypes.c_int)]
+                ("eig_tol_energy", ctypes.c_double), ("dirichlet_rule", ctypes.c_int),
+                ("eig_fp32", ctypes.c_int)]
 
 
 class MsddStats(ctypes.Structure):
@@ -53,7 +54,7 @@ class MsddStats(ctypes.Structure):
                 ("pcg_relres", ctypes.c_double), ("eig_iters_sum", ctypes.c_int64),
                 ("warm_started", ctypes.c_int32), ("warm_fallbacks", ctypes.c_int32),
                 ("eig_unconverged", ctypes.c_int32), ("eig_stagnated", ctypes.c_int32),
-                ("eig_energy_resid_max", ctypes.c_double)]
+                ("eig_energy_resid_max", ctypes.c_double), ("eig_fp64_fallbacks", ctypes.c_int32)]
 
     def as_dict(self):
         L = self.n_levels

@@ -884,6 +884,11 @@ template void launch_band_solve_multi<double, double>(hipStream_t, int, const i3
                                                       const double*, const double*, const i64*,
                                                       int, const double*, double*, const int*,
                                                       int, int);
+template void launch_band_solve_multi<float, double>(hipStream_t, int, const i32*, int,
+                                                     const i32*, const i32*, const i64*,
+                                                     const float*, const float*, const i64*, int,
+                                                     const double*, double*, const int*, int,
+                                                     int);
 template void launch_band_solve_multi<float, float>(hipStream_t, int, const i32*, int,
                                                     const i32*, const i32*, const i64*,
                                                     const float*, const float*, const i64*, int,

@@ -412,13 +412,15 @@ __global__ void k_rayleigh_ritz(int K, const double* __restrict__ GS,
 // logic.  One workgroup per subdomain; K divides the workgroup size.
 // Also the energy residual of the previous pair (X_old, SX_old, BX_old, nu_old = nu_prev):
 // per column sum (y - nu_old x_old)(bx_old - nu_old sx_old) and a bound on its rounding.
+// SY: S Y when the solves are not exact (the FP32-factor iteration), else null and
+// S Y = BX_old.
 template <typename V, int TR>
 __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__ kvoff, int K,
                              const double* __restrict__ Cm, const double* __restrict__ nu,
                              const V* __restrict__ Y, const V* __restrict__ Z,
                              V* __restrict__ X, V* __restrict__ BX, V* __restrict__ SX,
                              const int* __restrict__ status, double* __restrict__ part, int S,
-                             const double* __restrict__ nu_prev) {
+                             const double* __restrict__ nu_prev, const V* __restrict__ SY) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = blockIdx.x, sp = blockIdx.y;  // subdomain, row split
   if (status[i] != ST_RUNNING) return;
@@ -430,6 +432,7 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
   V* ty = reinterpret_cast<V*>(C + KK);             // TR*K
   V* tz = ty + TR * K;
   V* tb = tz + TR * K;
+  V* tsy = SY ? tb + TR * K : tb;  // the tile that gives S X_new = (S Y) C
   __shared__ double red_r[MSDD_WG], red_s[MSDD_WG], red_e[MSDD_WG], red_f[MSDD_WG];
   const int tid = threadIdx.x;
   for (int t = tid; t < KK; t += blockDim.x) C[t] = Cm[(i64)i * KK + t];
@@ -446,6 +449,7 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
   V* Xi = X + kvoff[i];
   V* Bi = BX + kvoff[i];
   V* Si = SX + kvoff[i];
+  const V* SYi = SY ? SY + kvoff[i] : nullptr;
   for (int r0 = r_lo; r0 < r_hi; r0 += TR) {
     const int rn = min(TR, r_hi - r0);
     __syncthreads();
@@ -461,6 +465,7 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
       ty[rr * K + cc] = y;
       tz[rr * K + cc] = z;
       tb[rr * K + cc] = bb;
+      if (SYi) tsy[rr * K + cc] = rr < rn ? SYi[r0 + rr + (i64)cc * n] : (V)0;
     }
     __syncthreads();
     if (rl < lanes) {
@@ -470,7 +475,7 @@ __global__ void k_eig_update(const i32* __restrict__ nb, const i64* __restrict__
           const double ca = C[a * K + c];
           x += (double)ty[rr * K + a] * ca;
           bx += (double)tz[rr * K + a] * ca;
-          sx += (double)tb[rr * K + a] * ca;
+          sx += (double)tsy[rr * K + a] * ca;
         }
         const i64 idx = r0 + rr + (i64)c * n;
         if (nuo > 0.0) {  // read the previous pair before this thread overwrites it
@@ -769,11 +774,11 @@ void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, in
                        double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
                        const double* normS, double* nu_prev, double* part, int nsplit,
                        const double* gs_diag, const int* inertia, int nev_fixed, double tol_e,
-                       double* res_e_out) {
+                       double* res_e_out, const double* SY) {
   constexpr int TR = 16;
-  size_t lds = (size_t)K * K * sizeof(double) + 3 * TR * K * sizeof(double);
+  size_t lds = (size_t)K * K * sizeof(double) + (SY ? 4 : 3) * TR * K * sizeof(double);
   hipLaunchKernelGGL((k_eig_update<double, TR>), dim3(P, nsplit), dim3(MSDD_WG), lds, s, nb, kvoff,
-                     K, C, nu, Y, Z, X, BX, SX, status, part, nsplit, nu_prev);
+                     K, C, nu, Y, Z, X, BX, SX, status, part, nsplit, nu_prev, SY);
   hipLaunchKernelGGL(k_eig_judge, dim3(P), dim3(64), 0, s, K, nu, part, nsplit, sigma, eta,
                      nev_max, tol, maxit, status, iters, mcount, lam_out, res_out, Kmax_allowed,
                      rankb, normS, nu_prev, gs_diag, inertia, nev_fixed, tol_e, res_e_out);
@@ -785,4 +790,98 @@ void launch_eig_finalize(hipStream_t s, int P, const i32* nb, const i64* voff, c
                          const i64* doff, const i32* dpos, const i64* phid_off, double* PhiD) {
   hipLaunchKernelGGL(k_eig_finalize<double>, dim3(P), dim3(MSDD_WG), 0, s, nb, voff, kvoff, K, dv,
                      X, nu, mcount, phi_off, Phi, nd, doff, dpos, phid_off, PhiD);
+}
+
+// ---------------------------------------------------------------------------
+// Eigensolver with an FP32 factor of S (a10, opt-in): the scaled single-precision factor
+// M of diag(sc) S diag(sc), sc = diag(S)^{-1/2}, serves as the preconditioner of the
+// block iteration  Y = X N + diag(sc) M^{-1} diag(sc) (B X - S X N)  (N = the current Ritz
+// values; exact shift-invert when M = the scaled S), followed by the FP64 Rayleigh-Ritz
+// step on (Y^T S Y, Y^T B Y) with S Y formed explicitly, so the converged pairs are those
+// of the FP64 pencil.
+// ---------------------------------------------------------------------------
+// sc = (S_jj)^{-1/2}, S_jj = abar_jj (1 + sigma d_j^2) for b = D abar D; one thread per row
+__global__ void k_s_diag_scale(i64 total_rows, const i32* __restrict__ row_grp,
+                               const i64* __restrict__ voff, const i64* __restrict__ boff,
+                               const i32* __restrict__ bw, const double* __restrict__ band,
+                               const double* __restrict__ gw, double sigma,
+                               double* __restrict__ sc, int* __restrict__ status) {
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < total_rows;
+       g += (i64)gridDim.x * blockDim.x) {
+    const int i = row_grp[g];
+    const i64 j = g - voff[i];
+    const double a = band[boff[i] + j * (bw[i] + 1)];
+    const double d = gw[g];
+    const double sjj = a * (1.0 + sigma * d * d);
+    if (!(sjj > 0.0)) status[i] = ST_NOTSPD;
+    sc[g] = sjj > 0.0 ? 1.0 / sqrt(sjj) : 0.0;
+  }
+}
+
+// out = diag(sc) band diag(sc) in the column layout (out[c*w + d] = A(c+d, c)); one thread
+// per column
+__global__ void k_band_scale_sym(i64 total_rows, const i32* __restrict__ row_grp,
+                                 const i64* __restrict__ voff, const i64* __restrict__ boff,
+                                 const i32* __restrict__ bw, const i32* __restrict__ nrows,
+                                 const double* __restrict__ band, const double* __restrict__ sc,
+                                 double* __restrict__ out) {
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < total_rows;
+       g += (i64)gridDim.x * blockDim.x) {
+    const int i = row_grp[g];
+    const i64 c = g - voff[i];
+    const int w = bw[i] + 1, n = nrows[i];
+    const i64 o = boff[i] + c * w;
+    for (int d = 0; d < w; ++d) out[o + d] = c + d < n ? band[o + d] * sc[g] * sc[g + d] : 0.0;
+  }
+}
+
+// Per running subdomain, over its n x K block (column c at c*n):
+//   mode 0: W = sc (BX - SX nu_c)            (the scaled residual)
+//   mode 1: Y = X nu_c + sc W                (the new block)
+//   mode 2: SY = T + sigma Z                 (S Y = abar Y + sigma b Y)
+__global__ void k_eig32_combine(int mode, const i32* __restrict__ nb, const i64* __restrict__ voff,
+                                const i64* __restrict__ kvoff, int K, const double* __restrict__ P1,
+                                const double* __restrict__ P2, const double* __restrict__ nu,
+                                const double* __restrict__ sc, double sigma,
+                                double* __restrict__ out, const int* __restrict__ status) {
+  const int i = blockIdx.y;
+  if (status[i] != ST_RUNNING) return;
+  const int n = nb[i];
+  const i64 cnt = (i64)n * K, o = kvoff[i];
+  const double* sci = sc + voff[i];
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (i64)gridDim.x * blockDim.x) {
+    const int c = (int)(e / n), r = (int)(e - (i64)c * n);
+    const double nuc = nu[(i64)i * K + c];
+    double v;
+    if (mode == 0) v = sci[r] * (P1[o + e] - nuc * P2[o + e]);
+    else if (mode == 1) v = nuc * P1[o + e] + sci[r] * P2[o + e];
+    else v = P1[o + e] + sigma * P2[o + e];
+    out[o + e] = v;
+  }
+}
+
+void launch_s_diag_scale(hipStream_t s, i64 total_rows, const i32* row_grp, const i64* voff,
+                         const i64* boff, const i32* bw, const double* band, const double* gw,
+                         double sigma, double* sc, int* status) {
+  if (!total_rows) return;
+  const int g = (int)std::min<i64>((total_rows + 255) / 256, 65535);
+  hipLaunchKernelGGL(k_s_diag_scale, dim3(g), dim3(256), 0, s, total_rows, row_grp, voff, boff,
+                     bw, band, gw, sigma, sc, status);
+}
+void launch_band_scale_sym(hipStream_t s, i64 total_rows, const i32* row_grp, const i64* voff,
+                           const i64* boff, const i32* bw, const i32* nrows, const double* band,
+                           const double* sc, double* out) {
+  if (!total_rows) return;
+  const int g = (int)std::min<i64>((total_rows + 255) / 256, 65535);
+  hipLaunchKernelGGL(k_band_scale_sym, dim3(g), dim3(256), 0, s, total_rows, row_grp, voff, boff,
+                     bw, nrows, band, sc, out);
+}
+void launch_eig32_combine(hipStream_t s, int mode, int P, int nmax, const i32* nb,
+                          const i64* voff, const i64* kvoff, int K, const double* P1,
+                          const double* P2, const double* nu, const double* sc, double sigma,
+                          double* out, const int* status) {
+  if (!P) return;
+  const int gx = (int)std::min<i64>(((i64)nmax * K + 255) / 256, 64);
+  hipLaunchKernelGGL(k_eig32_combine, dim3(gx, P), dim3(256), 0, s, mode, nb, voff, kvoff, K, P1,
+                     P2, nu, sc, sigma, out, status);
 }

@@ -89,7 +89,7 @@ void launch_eig_update(hipStream_t s, int P, const i32* nb, const i64* kvoff, in
                        double* lam_out, double* res_out, int Kmax_allowed, const i32* rankb,
                        const double* normS, double* nu_prev, double* part, int nsplit,
                        const double* gs_diag, const int* inertia, int nev_fixed, double tol_e,
-                       double* res_e_out);
+                       double* res_e_out, const double* SY = nullptr);
 void launch_row_norm(hipStream_t s, int P, const i64* voff, int ell_w, const i32* ell_col,
                      const double* ell_val, const double* dv, double sigma, double* normS,
                      const double* ell_val2 = nullptr);
@@ -174,6 +174,17 @@ void launch_apply_fine_solve(hipStream_t s, int P, int nd_max, int bd_max, const
                              const i32* bd, const i64* doff, const i64* dboff, const void* Fc,
                              const void* Fr, int fp32, const double* scale, double* u,
                              int variant = 0);
+// eig.hip, the FP32-factor eigensolver: scaling of S, scaled band, block combinations
+void launch_s_diag_scale(hipStream_t s, i64 total_rows, const i32* row_grp, const i64* voff,
+                         const i64* boff, const i32* bw, const double* band, const double* gw,
+                         double sigma, double* sc, int* status);
+void launch_band_scale_sym(hipStream_t s, i64 total_rows, const i32* row_grp, const i64* voff,
+                           const i64* boff, const i32* bw, const i32* nrows, const double* band,
+                           const double* sc, double* out);
+void launch_eig32_combine(hipStream_t s, int mode, int P, int nmax, const i32* nb,
+                          const i64* voff, const i64* kvoff, int K, const double* P1,
+                          const double* P2, const double* nu, const double* sc, double sigma,
+                          double* out, const int* status);
 // twist.hip: two-sided Dirichlet solves (top and bottom parts as two chains, explicit
 // inverse of the separator's Schur complement)
 void twist_split(int n, int b, int* nbt, int* nbb);  // nbt = 0: no split

@@ -287,6 +287,13 @@ struct FineLevel {
   DVec<int32_t> ell_col;
   DVec<double> ell_val;
   DVec<double> LSc, LSr;                // LDL^T factor of S = abar + sigma*b (column, row layouts)
+  // FP32-factor eigensolver (opt-in): sc = diag(S)^{-1/2} per Neumann row, the LDL^T factor
+  // of diag(sc) S diag(sc) in single precision, a vector of ones (abar Y through the b
+  // product with unit weights)
+  bool eig32 = false;
+  bool f64_built = false;  // LSc/LSr hold the FP64 factor
+  DVec<double> esc, eones;
+  DVec<float> LS32c, LS32r;
   // blocked form of the same factor (per 64-row block: inverse of the diagonal block and
   // the couplings multiplied by it); built when every half-bandwidth is at most 64
   std::vector<int64_t> h_lbo;
@@ -943,6 +950,52 @@ void ensure_side_stream(msdd_ctx* c) {
   HIPCHK(hipEventCreateWithFlags(&c->iev, hipEventDisableTiming));
 }
 
+// FP64 LDL^T factor of S = abar + sigma*b for the shift-invert eigensolver, and its
+// blocked form where the band allows it.  With the single-precision factor it is built
+// only when a subdomain falls back to the FP64 iteration.
+void build_eig_factor64(msdd_ctx* c, hipStream_t s, int* status) {
+  FineLevel& F = c->F;
+  const int P = F.P;
+  F.LSc.alloc(F.h_boff.back());
+  F.LSr.alloc(F.h_boff.back());
+  F.LSc.zero(s);
+  F.LSr.zero(s);
+  {
+    ProfScope ps(c, PR_CHOL, F.s_band * 8.0 * 3.0, F.s_nbb * (F.bw_max + 2.0));
+    launch_band_cholesky<double>(s, P, nullptr, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.band.p,
+                                 F.gs.voff.p, F.gw(), c->sigma, F.boff.p, F.LSc.p, F.LSr.p,
+                                 status, F.band2.p);
+  }
+  HIPCHK(hipGetLastError());
+  // the eigensolver's solves use the LDL^T form: row layout in LSr, column layout in LSc
+  launch_band_to_ldl<double>(s, P, F.nb_max, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.LSc.p,
+                             F.LSr.p);
+  HIPCHK(hipGetLastError());
+  // the blocked form (about 3.4 times the band factor for half-bandwidths near 40) is
+  // built when the band allows it; if its memory cannot be had, the eigensolver uses
+  // the band-factor solves instead
+  F.has_lb = F.bw_max <= 64;
+  if (F.has_lb) {
+    F.h_lbo.assign(P + 1, 0);
+    for (int i = 0; i < P; ++i) F.h_lbo[i + 1] = F.h_lbo[i] + band_block_doubles(F.gs.h_n[i]);
+    try {
+      F.LB.alloc(F.h_lbo.back());
+    } catch (const MsddError&) {
+      F.has_lb = false;
+      F.LB.release();
+    }
+  }
+  if (F.has_lb) {
+    F.lbo.upload(F.h_lbo, s);
+    ProfScope ps(c, PR_CHOL, F.s_band * 8.0 + (double)F.h_lbo.back() * 8.0,
+                 (double)F.h_lbo.back() * 1.25 * F.bw_max);
+    launch_band_block_build(s, P, F.nb_max, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.LSr.p,
+                            F.lbo.p, F.LB.p);
+    HIPCHK(hipGetLastError());
+  }
+  F.f64_built = true;
+}
+
 void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
   FineLevel& F = c->F;
   hipStream_t s = c->stream;
@@ -1084,43 +1137,33 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
     }
     HIPCHK(hipGetLastError());
   }
-  F.LSc.alloc(F.h_boff.back());
-  F.LSr.alloc(F.h_boff.back());
-  F.LSc.zero(s);
-  F.LSr.zero(s);
-  {
-  ProfScope ps(c, PR_CHOL, F.s_band * 8.0 * 3.0, F.s_nbb * (F.bw_max + 2.0));
-  launch_band_cholesky<double>(s, P, nullptr, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.band.p,
-                               F.gs.voff.p, F.gw(), c->sigma, F.boff.p, F.LSc.p, F.LSr.p,
-                               status.p, F.band2.p);
-  }
-  HIPCHK(hipGetLastError());
-  // the eigensolver's solves use the LDL^T form: row layout in LSr, column layout in LSc
-  launch_band_to_ldl<double>(s, P, F.nb_max, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.LSc.p,
-                             F.LSr.p);
-  HIPCHK(hipGetLastError());
-  // the blocked form (about 3.4 times the band factor for half-bandwidths near 40) is
-  // built when the band allows it; if its memory cannot be had, the eigensolver uses
-  // the band-factor solves instead
-  F.has_lb = F.bw_max <= 64;
-  if (F.has_lb) {
-    F.h_lbo.assign(P + 1, 0);
-    for (int i = 0; i < P; ++i) F.h_lbo[i + 1] = F.h_lbo[i] + band_block_doubles(F.gs.h_n[i]);
-    try {
-      F.LB.alloc(F.h_lbo.back());
-    } catch (const MsddError&) {
-      F.has_lb = false;
-      F.LB.release();
-    }
-  }
-  if (F.has_lb) {
-    F.lbo.upload(F.h_lbo, s);
-    ProfScope ps(c, PR_CHOL, F.s_band * 8.0 + (double)F.h_lbo.back() * 8.0,
-                 (double)F.h_lbo.back() * 1.25 * F.bw_max);
-    launch_band_block_build(s, P, F.nb_max, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.LSr.p,
-                            F.lbo.p, F.LB.p);
+  F.eig32 = c->opt.eig_fp32 == 1;
+  if (F.eig32) {
+    // single-precision factor of diag(sc) S diag(sc): the scaled Neumann band, then the
+    // shifted factorisation with the same weights (b = D abar D commutes with the scaling)
+    ProfScope ps(c, PR_CHOL, F.s_band * (8.0 * 3.0 + 4.0 * 2.0), F.s_nbb * (F.bw_max + 2.0));
+    F.esc.alloc(std::max<int64_t>(F.gs.total_rows, 1));
+    DVec<double> sband;
+    sband.alloc(std::max<int64_t>(F.h_boff.back(), 1));
+    launch_s_diag_scale(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.boff.p, F.gs.bw.p,
+                        F.band.p, F.gw(), c->sigma, F.esc.p, status.p);
+    launch_band_scale_sym(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.boff.p, F.gs.bw.p,
+                          F.gs.n.p, F.band.p, F.esc.p, sband.p);
+    F.LS32c.alloc(F.h_boff.back());
+    F.LS32r.alloc(F.h_boff.back());
+    F.LS32c.zero(s);
+    F.LS32r.zero(s);
+    launch_band_cholesky<float>(s, P, nullptr, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, sband.p,
+                                F.gs.voff.p, F.gw(), c->sigma, F.boff.p, F.LS32c.p, F.LS32r.p,
+                                status.p);
+    launch_band_to_ldl<float>(s, P, F.nb_max, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.LS32c.p,
+                              F.LS32r.p);
+    std::vector<double> ones((size_t)F.gs.total_rows, 1.0);
+    F.eones.upload(ones, s);
     HIPCHK(hipGetLastError());
+    F.has_lb = false;
   }
+  if (!F.eig32) build_eig_factor64(c, s, status.p);
   HIPCHK(hipEventRecord(c->cev1, s2));
   HIPCHK(hipStreamWaitEvent(s, c->cev1, 0));
   HIPCHK(hipStreamWaitEvent(s, c->iev, 0));
@@ -1147,6 +1190,17 @@ void eig_bapply(msdd_ctx* c, hipStream_t s, const int64_t* kvoff, int K, const d
                     F.ell_w, F.ell_col.p, ev, Y, Z, status);
 }
 
+// T = abar Y (the b product with unit weights), for S Y = abar Y + sigma b Y
+void eig_abar_apply(msdd_ctx* c, hipStream_t s, const int64_t* kvoff, int K, const double* Y,
+                    double* T, const int* status) {
+  FineLevel& F = c->F;
+  if (launch_bapply_tile(s, F.P, F.nb_max, F.bw_max, F.gs.voff.p, F.gs.n.p, F.gs.bw.p, kvoff, K,
+                         F.eones.p, F.ell_w, F.ell_col.p, F.ell_val.p, Y, T, status))
+    return;
+  launch_bapply_ell(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, kvoff, K,
+                    F.eones.p, F.ell_w, F.ell_col.p, F.ell_val.p, Y, T, status);
+}
+
 // Band solves Y = S^{-1} W of the eigensolver (K columns per subdomain, skipped where
 // status is not running).  variant: 0 = by shape (blocked in four launches when the
 // blocked factor exists), 1..7 = rolling-window / per-column shapes, 8 = blocked in
@@ -1169,6 +1223,11 @@ void eig_band_solve(msdd_ctx* c, hipStream_t s, const int64_t* kvoff, int K, con
                                           F.boff.p, F.LSc.p, F.LSr.p, kvoff, K, W, Y, status,
                                           F.bw_max, variant >= 8 ? 0 : variant);
 }
+
+// iteration cap of a pass with the single-precision factor (the FP64 iteration needs
+// about 10 to 20 on the inclusion workloads; the preconditioned one converges linearly at
+// a rate set by the factor's rounding, so a pass that has not finished by then is stalled)
+constexpr int EIG32_MAXIT = 64;
 
 void fine_eigensolve(msdd_ctx* c) {
   FineLevel& F = c->F;
@@ -1201,10 +1260,25 @@ void fine_eigensolve(msdd_ctx* c) {
   }
   std::vector<int> iters_tot(P, 0);
   int fallbacks = 0;
+  // single-precision factor: a subdomain whose iteration stops short of its certificate
+  // within EIG32_MAXIT is solved again with the FP64 factor (built on first need)
+  std::vector<int> e32_ok(P, F.eig32 ? 1 : 0);
+  int fallbacks64 = 0;
   while (true) {
     int nwant = 0;
-    for (int i = 0; i < P; ++i) nwant += want[i];
+    bool pass32 = F.eig32;
+    for (int i = 0; i < P; ++i) {
+      nwant += want[i];
+      if (want[i] && !e32_ok[i]) pass32 = false;
+    }
     if (!nwant) break;
+    if (!pass32 && !F.f64_built) {
+      DVec<int> st64;
+      st64.alloc(P);
+      st64.zero(s);
+      build_eig_factor64(c, s, st64.p);
+      check_status(st64.download(s), "Cholesky of abar + sigma*b");
+    }
     auto ps = std::make_unique<EigPass>();
     EigPass& E = *ps;
     E.K = K;
@@ -1237,6 +1311,16 @@ void fine_eigensolve(msdd_ctx* c) {
     DVec<double> nu_prev, normS, gsd;
     nu_prev.alloc((size_t)P * K);
     nu_prev.zero(s);
+    // FP32-factor iteration: residual and correction blocks, S Y; N = 0 and S X = 0 on the
+    // first iteration (Y = the scaled solve of B X)
+    DVec<double> W32a, W32b, SY;
+    if (pass32) {
+      W32a.alloc(tot);
+      W32b.alloc(tot);
+      SY.alloc(tot);
+      E.nu.zero(s);
+      SX.zero(s);
+    }
     gsd.alloc((size_t)P * K);
     gsd.zero(s);
     normS.alloc(P);
@@ -1259,7 +1343,7 @@ void fine_eigensolve(msdd_ctx* c) {
                       F.gw(), E.X.p, 0x5eed5eedull + (unsigned long long)K, F.seed_id.p);
     }
     eig_bapply(c, s, dkvoff.p, K, E.X.p, BX.p, status.p);
-    const int maxit = o.eig_maxit;
+    const int maxit = pass32 ? std::min(o.eig_maxit, EIG32_MAXIT) : o.eig_maxit;
     std::vector<int> st;
     c->eig_active = nwant;
     for (int it = 0; it < maxit; ++it) {
@@ -1267,16 +1351,34 @@ void fine_eigensolve(msdd_ctx* c) {
       {
         ProfScope ps(c, PR_EIG_SOLVE, f * (2.0 * F.s_band * 8.0 + 4.0 * F.s_nb * K * 8.0),
                      f * 4.0 * F.s_nbb * K);
-        eig_band_solve(c, s, dkvoff.p, K, BX.p, Y.p, status.p, c->tune.eig_solve);
+        if (pass32) {
+          // Y = X N + diag(sc) M^{-1} diag(sc) (B X - S X N), M the FP32 factor
+          launch_eig32_combine(s, 0, P, F.nb_max, F.gs.n.p, F.gs.voff.p, dkvoff.p, K, BX.p, SX.p,
+                               E.nu.p, F.esc.p, 0.0, W32a.p, status.p);
+          const int v = c->tune.eig_solve >= 1 && c->tune.eig_solve <= 7 ? c->tune.eig_solve : 0;
+          launch_band_solve_multi<float, double>(s, P, nullptr, F.nb_max, F.gs.n.p, F.gs.bw.p,
+                                                 F.boff.p, F.LS32c.p, F.LS32r.p, dkvoff.p, K,
+                                                 W32a.p, W32b.p, status.p, F.bw_max, v);
+          launch_eig32_combine(s, 1, P, F.nb_max, F.gs.n.p, F.gs.voff.p, dkvoff.p, K, E.X.p,
+                               W32b.p, E.nu.p, F.esc.p, 0.0, Y.p, status.p);
+        } else {
+          eig_band_solve(c, s, dkvoff.p, K, BX.p, Y.p, status.p, c->tune.eig_solve);
+        }
       }
       {
         ProfScope ps(c, PR_EIG_BAPPLY, f * (F.s_nb * F.ell_w * 12.0 + 2.0 * F.s_nb * K * 8.0),
                      f * 2.0 * F.s_nb * F.ell_w * K);
         eig_bapply(c, s, dkvoff.p, K, Y.p, Z.p, status.p);
+        if (pass32) {  // S Y = abar Y + sigma Z
+          eig_abar_apply(c, s, dkvoff.p, K, Y.p, W32a.p, status.p);
+          launch_eig32_combine(s, 2, P, F.nb_max, F.gs.n.p, F.gs.voff.p, dkvoff.p, K, W32a.p,
+                               Z.p, E.nu.p, F.esc.p, c->sigma, SY.p, status.p);
+        }
       }
       {
         ProfScope ps(c, PR_EIG_GRAM, f * 3.0 * F.s_nb * K * 8.0, f * 4.0 * F.s_nb * K * K);
-        launch_gram(s, P, F.gs.n.p, dkvoff.p, K, Y.p, BX.p, Z.p, GS.p, GB.p, status.p, nsplit);
+        launch_gram(s, P, F.gs.n.p, dkvoff.p, K, Y.p, pass32 ? SY.p : BX.p, Z.p, GS.p, GB.p,
+                    status.p, nsplit);
       }
       {
         ProfScope ps(c, PR_EIG_RR, c->eig_active * 3.0 * K * K * 8.0, 0.0);
@@ -1289,7 +1391,7 @@ void fine_eigensolve(msdd_ctx* c) {
                           c->sigma, c->eta, o.nev_max, o.eig_tol, maxit, status.p, iters.p,
                           E.mcount.p, E.lam.p, E.res.p, 64, F.rankb.p, normS.p, nu_prev.p,
                           upart.p, nsplit, gsd.p, F.inertia.p, o.nev_fixed, o.eig_tol_energy,
-                          E.res_e.p);
+                          E.res_e.p, pass32 ? SY.p : nullptr);
       }
       HIPCHK(hipGetLastError());
       if (it >= 3 && (it % 2 == 1 || it == maxit - 1)) {
@@ -1315,6 +1417,15 @@ void fine_eigensolve(msdd_ctx* c) {
         grew = true;
         ++restarts;
         continue;  // stays wanted for the next pass
+      }
+      if (pass32 && st[i] != ST_DONE) {
+        e32_ok[i] = 0;
+        fell = true;
+        ++fallbacks64;
+        if (c->opt.verbose)
+          std::fprintf(stderr, "msdd: subdomain %d not converged with the FP32 factor (status %d), "
+                       "FP64 pass\n", i, st[i]);
+        continue;
       }
       if (warm_ok[i] && st[i] != ST_DONE) {
         // the warm-started iteration did not converge: solve again from the random start
@@ -1371,6 +1482,7 @@ void fine_eigensolve(msdd_ctx* c) {
   c->stats.eig_energy_resid_max = rese_max;
   c->stats.eig_unconverged = unconverged;
   c->stats.eig_stagnated = stagnated;
+  c->stats.eig_fp64_fallbacks = fallbacks64;
   if (unconverged > 0)
     throw MsddError{MSDD_EEIG, "local eigensolver: " + std::to_string(unconverged) +
                                    " finest-level subdomain(s) not converged within eig_maxit "
@@ -2263,6 +2375,7 @@ void msdd_default_options(msdd_options* o) {
   o->nev_fixed = 0;
   o->eig_tol_energy = 1e-10;
   o->dirichlet_rule = 0;
+  o->eig_fp32 = 0;
 }
 
 int msdd_create(msdd_ctx** out, const msdd_options* opt) {
@@ -2285,7 +2398,9 @@ int msdd_create(msdd_ctx** out, const msdd_options* opt) {
   }
   if ((c->opt.precision != MSDD_FP64 && c->opt.precision != MSDD_MIXED) ||
       c->opt.geneo_rhs < 1 || c->opt.geneo_rhs > 3 || c->opt.nev_fixed < 0 ||
-      (c->opt.dirichlet_rule != 0 && c->opt.dirichlet_rule != 1)) {
+      (c->opt.dirichlet_rule != 0 && c->opt.dirichlet_rule != 1) ||
+      (c->opt.eig_fp32 != 0 && c->opt.eig_fp32 != 1) ||
+      (c->opt.eig_fp32 == 1 && c->opt.geneo_rhs != 1)) {
     delete c;
     return MSDD_EINVAL;
   }
@@ -2323,6 +2438,8 @@ int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
             "bad eigensolver options");
     REQUIRE(c->opt.dirichlet_rule == 0 || c->opt.dirichlet_rule == 1,
             "dirichlet_rule must be 0 or 1");
+    REQUIRE(c->opt.eig_fp32 == 0 || (c->opt.eig_fp32 == 1 && c->opt.geneo_rhs == 1),
+            "eig_fp32 must be 0, or 1 with geneo_rhs = 1");
     c->n = n;
     c->k = k;
     c->eta = eta;
@@ -3065,7 +3182,9 @@ int msdd_autotune(msdd_ctx* c, int32_t what, int32_t reps) {
     FineLevel& F = c->F;
     const int P = F.P;
     msdd_tuning_t& T = c->tune;
-    if (what & MSDD_TUNE_EIG) {
+    // the eigensolver's launch shapes are those of the FP64 factor; a context set up with
+    // the FP32 factor keeps the by-shape choice
+    if ((what & MSDD_TUNE_EIG) && !F.eig32) {
       const int K = c->opt.block <= 16 ? 16 : (c->opt.block <= 32 ? 32 : 64);
       std::vector<int64_t> kvoff(P + 1, 0);
       for (int i = 0; i < P; ++i) kvoff[i + 1] = kvoff[i] + (int64_t)F.gs.h_n[i] * K;
