@@ -640,6 +640,33 @@ def main():
                                   traffic=None)
                              if p32.get("apply_fine_solve", (0, 0))[1] else None),
     }
+    if args.workload == "c2":
+        # finest-level eigensolver with the single-precision factor of the shifted pencil
+        # (opt-in eig_fp32) against the FP64 factor: setups only, same launch shapes (no
+        # tuning on either side), one untimed setup then three timed
+        def setups(**opts):
+            ctx = B.Msdd(**opts)
+            ctx.setup(**arrs)
+            ts, gv = [], []
+            for _ in range(3):
+                ctx.setup(**arrs)
+                s_ = ctx.stats()
+                ts.append(s_["t_setup_ms"])
+                gv.append(s_["t_gevp_ms"])
+            ctx.close()
+            return float(np.median(ts)), float(np.median(gv)), s_
+        t64, g64, _ = setups()
+        te, ge, se = setups(eig_fp32=1)
+        out["eig_fp32"] = {
+            "what": ("finest-level eigensolver preconditioned by the FP32 factor of the scaled "
+                     "shifted pencil, FP64 residuals and Rayleigh-Ritz (same pairs and counts); "
+                     "subdomains not certified within 64 iterations re-solved with the FP64 "
+                     "factor; setup only, untuned launch shapes on both sides"),
+            "setup_s": te * 1e-3, "gevp_ms": ge,
+            "fp64_setup_s": t64 * 1e-3, "fp64_gevp_ms": g64,
+            "setup_speedup_vs_fp64": t64 / te,
+            "eig_iters_sum": se["eig_iters_sum"], "fp64_fallbacks": se["eig_fp64_fallbacks"],
+        }
     if learned:
         from msdd_inputs import problems as P
         net, info = train_warm_start(*members, verbose=args.verbose)
