@@ -490,8 +490,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
-              f"of the method is described in DESIGN.md, not run.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the sharding of the "
+              f"subdomains over several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "c4":
         bench_batch(args)
