@@ -243,6 +243,13 @@ void launch_apply_fine_up(hipStream_t s, i64 n, const i64* dinc_ptr, const i32* 
                           const i64* phid_off, const double* PhiD, const double* u,
                           const double* zc, double* z,
                           const double* w = nullptr, int acc = 0);
+// the same gather over the PCG chunks (nch workgroups, rows ch_lo[c] .. ch_hi[c], at most
+// 256 each), also writing partial[c] = the chunk's r.z as launch_dot_chunk computes it
+void launch_apply_fine_up_dot(hipStream_t s, int nch, const i64* ch_lo, const i64* ch_hi,
+                              const i64* dinc_ptr, const i32* dinc_sub, const i32* dinc_q,
+                              const i64* doff, const i32* msub, const i64* moff,
+                              const i64* phid_off, const double* PhiD, const double* u,
+                              const double* zc, double* z, const double* r, double* partial);
 
 // mlp.hip (warm-start network of the local eigensolver)
 // C_z = opA(A) opB(B) over split z of K (row-major M x N partials); every split is

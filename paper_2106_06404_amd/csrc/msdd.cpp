@@ -2218,7 +2218,9 @@ static void fine_local_solve(msdd_ctx* c, hipStream_t s, double* u, int variant)
                             F.LDc.p, F.LDr.p, 0, nullptr, u, v);
 }
 
-void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
+// dot_partial (PCG): also the chunk partial sums of r.z, written by the gather kernel
+void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s,
+                double* dot_partial = nullptr) {
   FineLevel& F = c->F;
   const int L = c->n_levels - 1;
   double* rc_top = c->rlev[L - 1].p;  // level L-1 vector
@@ -2271,11 +2273,18 @@ void apply_prec(msdd_ctx* c, const double* r, double* z, hipStream_t s) {
     HIPCHK(hipStreamWaitEvent(s, c->cev1, 0));
   }
   {
+    // with the r.z partial sums: r read as well
     ProfScope ps(c, PR_APPLY_GATHER,
-                 (double)(c->n + 1) * 8.0 + F.s_nd * 16.0 + F.s_ndm * 8.0 + c->n * 8.0 + F.s_m * 8.0,
-                 2.0 * F.s_ndm + F.s_nd);
-    launch_apply_fine_up(s, c->n, F.dinc_ptr.p, F.dinc_sub.p, F.dinc_q.p, F.doff.p, F.dm.p,
-                         F.moff.p, F.phid_off.p, F.PhiD.p, c->u.p, c->zlev[L - 1].p, z);
+                 (double)(c->n + 1) * 8.0 + F.s_nd * 16.0 + F.s_ndm * 8.0 + c->n * 8.0 + F.s_m * 8.0 +
+                     (dot_partial ? c->n * 8.0 : 0.0),
+                 2.0 * F.s_ndm + F.s_nd + (dot_partial ? 2.0 * c->n : 0.0));
+    if (dot_partial)
+      launch_apply_fine_up_dot(s, c->nch, c->ch_lo.p, c->ch_hi.p, F.dinc_ptr.p, F.dinc_sub.p,
+                               F.dinc_q.p, F.doff.p, F.dm.p, F.moff.p, F.phid_off.p, F.PhiD.p,
+                               c->u.p, c->zlev[L - 1].p, z, r, dot_partial);
+    else
+      launch_apply_fine_up(s, c->n, F.dinc_ptr.p, F.dinc_sub.p, F.dinc_q.p, F.doff.p, F.dm.p,
+                           F.moff.p, F.phid_off.p, F.PhiD.p, c->u.p, c->zlev[L - 1].p, z);
   }
 }
 
@@ -2734,10 +2743,9 @@ void pcg_iteration(msdd_ctx* c, hipStream_t s, double* xx, int maxit, const PcgB
                            w.partial);
     launch_seg_reduce(s, ns, c->seg_ch.p, w.partial, w.segD, w.segI, PCG_R_RR, 0.0, maxit, w.hist);
   }
-  apply_prec(c, w.r, w.z, s);
+  apply_prec(c, w.r, w.z, s, w.partial);  // z = M r and the chunk sums of r.z
   {
-    ProfScope ps(c, PR_VEC, 5.0 * n * 8.0, 4.0 * n);
-    launch_dot_chunk(s, nch, c->ch_lo.p, c->ch_hi.p, w.r, w.z, w.partial);
+    ProfScope ps(c, PR_VEC, 3.0 * n * 8.0, 2.0 * n);
     launch_seg_reduce(s, ns, c->seg_ch.p, w.partial, w.segD, w.segI, PCG_R_RZ, 0.0, maxit, w.hist);
     launch_update_p_chunk(s, nch, c->ch_lo.p, c->ch_hi.p, c->ch_seg.p, w.z, w.p, w.segD, 0);
   }
@@ -2800,8 +2808,7 @@ int pcg_run(msdd_ctx* c, const double* bb, double* xx, double rtol, int32_t maxi
                     xx, w.q, w.partial);
   launch_residual_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, bb, w.q, w.r, w.partial);
   launch_seg_reduce(s, ns, c->seg_ch.p, w.partial, w.segD, w.segI, PCG_R_RR0, rtol, maxit, w.hist);
-  apply_prec(c, w.r, w.z, s);
-  launch_dot_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, w.r, w.z, w.partial);
+  apply_prec(c, w.r, w.z, s, w.partial);
   launch_seg_reduce(s, ns, c->seg_ch.p, w.partial, w.segD, w.segI, PCG_R_RZ0, 0.0, maxit, w.hist);
   launch_update_p_chunk(s, c->nch, c->ch_lo.p, c->ch_hi.p, c->ch_seg.p, w.z, w.p, w.segD, 1);
   HIPCHK(hipGetLastError());

@@ -349,6 +349,34 @@ __global__ void k_apply_coarse_up(const i32* __restrict__ nown, const i64* __res
 // contains p of (u_i + PhiD_i zc_i)[local index of p].  Variants for the hybrid form:
 // w (per Dirichlet entry, may be null) weights u_i (restricted additive Schwarz: the
 // partition of unity), u or zc null drops that term, acc adds to z instead of writing it.
+__device__ __forceinline__ double fine_up_row(i64 p, const i64* __restrict__ dinc_ptr,
+                                              const i32* __restrict__ dinc_sub,
+                                              const i32* __restrict__ dinc_q,
+                                              const i64* __restrict__ doff,
+                                              const i32* __restrict__ msub,
+                                              const i64* __restrict__ moff,
+                                              const i64* __restrict__ phid_off,
+                                              const double* __restrict__ PhiD,
+                                              const double* __restrict__ u,
+                                              const double* __restrict__ zc,
+                                              const double* __restrict__ w) {
+  double s = 0.0;
+  for (i64 e = dinc_ptr[p]; e < dinc_ptr[p + 1]; ++e) {
+    const int i = dinc_sub[e];
+    const int q = dinc_q[e];
+    double v = 0.0;
+    if (u) v = w ? w[doff[i] + q] * u[doff[i] + q] : u[doff[i] + q];
+    if (zc) {
+      const int m = msub[i];
+      const double* row = PhiD + phid_off[i] + (i64)q * m;
+      const double* zz = zc + moff[i];
+      for (int c = 0; c < m; ++c) v += row[c] * zz[c];
+    }
+    s += v;
+  }
+  return s;
+}
+
 __global__ void k_apply_fine_up(i64 n, const i64* __restrict__ dinc_ptr,
                                 const i32* __restrict__ dinc_sub, const i32* __restrict__ dinc_q,
                                 const i64* __restrict__ doff, const i32* __restrict__ msub,
@@ -357,22 +385,32 @@ __global__ void k_apply_fine_up(i64 n, const i64* __restrict__ dinc_ptr,
                                 const double* __restrict__ zc, double* __restrict__ z,
                                 const double* __restrict__ w, int acc) {
   for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (i64)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (i64 e = dinc_ptr[p]; e < dinc_ptr[p + 1]; ++e) {
-      const int i = dinc_sub[e];
-      const int q = dinc_q[e];
-      double v = 0.0;
-      if (u) v = w ? w[doff[i] + q] * u[doff[i] + q] : u[doff[i] + q];
-      if (zc) {
-        const int m = msub[i];
-        const double* row = PhiD + phid_off[i] + (i64)q * m;
-        const double* zz = zc + moff[i];
-        for (int c = 0; c < m; ++c) v += row[c] * zz[c];
-      }
-      s += v;
-    }
+    const double s = fine_up_row(p, dinc_ptr, dinc_sub, dinc_q, doff, msub, moff, phid_off, PhiD,
+                                 u, zc, w);
     z[p] = acc ? z[p] + s : s;
   }
+}
+
+// The same gather over the PCG chunks (one workgroup per chunk), each also writing its
+// chunk's partial sum of r.z, summed as k_dot_chunk sums it (same rows per thread, same
+// workgroup sum), for the CG scalar that follows the preconditioner.
+__global__ void __launch_bounds__(256) k_apply_fine_up_dot(
+    const i64* __restrict__ ch_lo, const i64* __restrict__ ch_hi, const i64* __restrict__ dinc_ptr,
+    const i32* __restrict__ dinc_sub, const i32* __restrict__ dinc_q, const i64* __restrict__ doff,
+    const i32* __restrict__ msub, const i64* __restrict__ moff, const i64* __restrict__ phid_off,
+    const double* __restrict__ PhiD, const double* __restrict__ u, const double* __restrict__ zc,
+    double* __restrict__ z, const double* __restrict__ r, double* __restrict__ partial) {
+  __shared__ double sh[16];
+  const int c = blockIdx.x;
+  double acc = 0.0;
+  for (i64 p = ch_lo[c] + threadIdx.x; p < ch_hi[c]; p += blockDim.x) {
+    const double s = fine_up_row(p, dinc_ptr, dinc_sub, dinc_q, doff, msub, moff, phid_off, PhiD,
+                                 u, zc, nullptr);
+    z[p] = s;
+    acc += r[p] * s;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[c] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -500,6 +538,14 @@ void launch_apply_fine_up(hipStream_t s, i64 n, const i64* dinc_ptr, const i32* 
                           const double* zc, double* z, const double* w, int acc) {
   hipLaunchKernelGGL(k_apply_fine_up, dim3(grid_for(n)), dim3(MSDD_WG), 0, s, n, dinc_ptr,
                      dinc_sub, dinc_q, doff, msub, moff, phid_off, PhiD, u, zc, z, w, acc);
+}
+void launch_apply_fine_up_dot(hipStream_t s, int nch, const i64* ch_lo, const i64* ch_hi,
+                              const i64* dinc_ptr, const i32* dinc_sub, const i32* dinc_q,
+                              const i64* doff, const i32* msub, const i64* moff,
+                              const i64* phid_off, const double* PhiD, const double* u,
+                              const double* zc, double* z, const double* r, double* partial) {
+  hipLaunchKernelGGL(k_apply_fine_up_dot, dim3(nch), dim3(256), 0, s, ch_lo, ch_hi, dinc_ptr,
+                     dinc_sub, dinc_q, doff, msub, moff, phid_off, PhiD, u, zc, z, r, partial);
 }
 
 // ---------------------------------------------------------------------------
