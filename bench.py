@@ -482,6 +482,8 @@ def main():
                     help="keep the launch shapes chosen by problem shape (no msdd_autotune)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start leg (training + warm-started steps)")
+    ap.add_argument("--no-eig32", action="store_true",
+                    help="skip the setups with the FP32-factor eigensolver (c2)")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration under rocprofv3)")
@@ -640,7 +642,7 @@ def main():
                                   traffic=None)
                              if p32.get("apply_fine_solve", (0, 0))[1] else None),
     }
-    if args.workload == "c2":
+    if args.workload == "c2" and not args.no_eig32:
         # finest-level eigensolver with the single-precision factor of the shifted pencil
         # (opt-in eig_fp32) against the FP64 factor: setups only, same launch shapes (no
         # tuning on either side), one untimed setup then three timed
