@@ -608,6 +608,66 @@ struct SubPlan {
 // largest finest subdomain (Neumann dofs)
 constexpr int kMaxLocalDofs = 1 << 24;
 
+// Number of elements containing each dof (deg[d], d < n), with the range check of the
+// element dofs (-1 or below n; MsddError otherwise).  Element ranges are counted in parallel,
+// each into a private window of the dofs it touches; the windows are then added up per dof
+// range.  Elements numbered without locality (windows summing to more than 4 n) are counted
+// in one serial pass instead.
+std::unique_ptr<int32_t[]> dof_degrees(const std::vector<int32_t>& ed, int64_t n) {
+  const int64_t m = (int64_t)ed.size();
+  const int T = host_threads((int)std::min<int64_t>(16, (m + 65535) / 65536));
+  struct Win {
+    int64_t lo = 0, hi = -1, bad = -1;  // dofs lo..hi; first out-of-range entry
+    std::vector<int32_t> cnt;
+  };
+  std::vector<Win> w(T);
+  parallel_for(T, T, [&](int t, int) {
+    Win& W = w[t];
+    int64_t lo = n, hi = -1;
+    for (int64_t q = m * t / T; q < m * (t + 1) / T; ++q) {
+      const int64_t d = ed[q];
+      if (d < -1 || d >= n) {
+        W.bad = q;
+        return;
+      }
+      if (d >= 0) {
+        lo = std::min(lo, d);
+        hi = std::max(hi, d);
+      }
+    }
+    W.lo = lo;
+    W.hi = hi;
+  });
+  int64_t span = 0;
+  for (const Win& W : w) {
+    REQUIRE(W.bad < 0, "elem_dofs entry out of range");
+    span += std::max<int64_t>(0, W.hi - W.lo + 1);
+  }
+  std::unique_ptr<int32_t[]> deg(new int32_t[std::max<int64_t>(n, 1)]);  // every entry set below
+  if (T == 1 || span > 4 * n) {
+    std::fill(deg.get(), deg.get() + n, 0);
+    for (int64_t q = 0; q < m; ++q)
+      if (ed[q] >= 0) deg[ed[q]]++;
+    return deg;
+  }
+  parallel_for(T, T, [&](int t, int) {
+    Win& W = w[t];
+    if (W.hi < W.lo) return;
+    W.cnt.assign(W.hi - W.lo + 1, 0);
+    for (int64_t q = m * t / T; q < m * (t + 1) / T; ++q)
+      if (ed[q] >= 0) W.cnt[ed[q] - W.lo]++;
+  });
+  parallel_for(T, T, [&](int r, int) {
+    const int64_t a = n * r / T, b = n * (r + 1) / T;
+    std::fill(deg.get() + a, deg.get() + b, 0);
+    for (const Win& W : w) {
+      const int64_t lo = std::max(a, W.lo), hi = std::min(b, W.hi + 1);
+      for (int64_t d = lo; d < hi; ++d) deg[d] += W.cnt[d - W.lo];
+    }
+  });
+  return deg;
+}
+
 void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
                const std::vector<int64_t>& sep, const std::vector<int32_t>& se,
                const std::vector<int64_t>& sdp, const std::vector<int32_t>& sd,
@@ -617,14 +677,22 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   const int64_t n = c->n;
   const int P = F.P;
   double tv = now_ms();
-  std::vector<int32_t> deg(n, 0);
-  for (size_t e = 0; e < ed.size(); ++e) {
-    REQUIRE(ed[e] >= -1 && ed[e] < n, "elem_dofs entry out of range");
-    if (ed[e] >= 0) deg[ed[e]]++;
-  }
+  const std::unique_ptr<int32_t[]> deg = dof_degrees(ed, n);
   for (int i = 0; i < P; ++i)
     REQUIRE(sep[i + 1] >= sep[i] && sdp[i + 1] >= sdp[i], "subdomain pointers not monotone");
-  for (int32_t e : se) REQUIRE(e >= 0 && e < n_elem, "sub_elem entry out of range");
+  {
+    const int64_t m = (int64_t)se.size();
+    const int nr = host_threads((int)std::min<int64_t>(16, (m + 65535) / 65536));
+    std::vector<int64_t> first(nr, -1);
+    parallel_for(nr, nr, [&](int t, int) {
+      for (int64_t q = m * t / nr; q < m * (t + 1) / nr; ++q)
+        if (se[q] < 0 || se[q] >= n_elem) {
+          first[t] = q;
+          break;
+        }
+    });
+    for (int t = 0; t < nr; ++t) REQUIRE(first[t] < 0, "sub_elem entry out of range");
+  }
   F.elems.assign(P, {});
   F.plans.assign(P, {});
   // b^2: elements that belong to more than one subdomain (the overlap elements)
@@ -764,8 +832,8 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   F.ell_w = 0;
   std::vector<double>& pou_sum = c->scr_pou;
   std::vector<int32_t>& dcount = c->scr_cnt;
-  pou_sum.assign(n, 0.0);
-  dcount.assign(n, 0);
+  pou_sum.resize(n);  // zeroed range by range below
+  dcount.resize(n);
   // offsets of each subdomain's entries, sizes and maxima (serial, per subdomain)
   std::vector<int64_t> nbo(P + 1, 0), ndo(P + 1, 0);
   for (int i = 0; i < P; ++i) {
@@ -839,10 +907,13 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   // PoU sums and Dirichlet multiplicities, each thread over a range of dofs and all
   // subdomains in order (each subdomain's dofs are sorted), so every sum runs in subdomain
   // order as a serial loop would
-  const int nrange = std::max(1, (int)std::min<int64_t>(nthr, (n + 65535) / 65536));
+  const int nrange = std::max(1, (int)std::min<int64_t>(nthr, (n + 16383) / 16384));
   auto range_lo = [&](int t) { return (int32_t)((n * (int64_t)t) / nrange); };
+  std::vector<int64_t> rtot(nrange + 1, 0);  // Dirichlet memberships per range
   parallel_for(nrange, nrange, [&](int t, int) {
     const int32_t lo = range_lo(t), hi = range_lo(t + 1);
+    std::fill(pou_sum.begin() + lo, pou_sum.begin() + hi, 0.0);
+    std::fill(dcount.begin() + lo, dcount.begin() + hi, 0);
     for (int i = 0; i < P; ++i) {
       const GroupPlan& g = F.plans[i];
       const SubPlan& S = sp[i];
@@ -852,21 +923,32 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
       auto d0 = std::lower_bound(S.dglob.begin(), S.dglob.end(), lo);
       for (auto it = d0; it != S.dglob.end() && *it < hi; ++it) dcount[*it]++;
     }
+    int64_t tot = 0;
     for (int32_t d = lo; d < hi; ++d) {
       REQUIRE(std::fabs(pou_sum[d] - 1.0) <= 1e-12,
               "partition-of-unity weights do not sum to 1 at dof " + std::to_string(d));
       REQUIRE(dcount[d] > 0, "dof " + std::to_string(d) + " lies in no subdomain's Dirichlet space");
+      tot += dcount[d];
     }
+    rtot[t + 1] = tot;
   });
   // fine dof -> (subdomain, Dirichlet position), in subdomain order
   // (upload-only arrays in the pinned staging arena; every entry is written)
+  for (int t = 0; t < nrange; ++t) rtot[t + 1] += rtot[t];
   HostBuf<int64_t> dptr(n + 1);
-  dptr[0] = 0;
-  for (int64_t d = 0; d < n; ++d) dptr[d + 1] = dptr[d] + dcount[d];
+  dptr[n] = rtot[nrange];
   HostBuf<int32_t> dsub(dptr[n]), dq(dptr[n]);
   {
     std::vector<int64_t>& pos = c->scr_pos;
-    pos.assign(dptr.p, dptr.p + n);
+    pos.resize(n);
+    parallel_for(nrange, nrange, [&](int t, int) {  // prefix sums of the memberships
+      int64_t run = rtot[t];
+      for (int32_t d = range_lo(t); d < range_lo(t + 1); ++d) {
+        dptr[d] = run;
+        pos[d] = run;
+        run += dcount[d];
+      }
+    });
     parallel_for(nrange, nrange, [&](int t, int) {
       const int32_t lo = range_lo(t), hi = range_lo(t + 1);
       for (int i = 0; i < P; ++i) {
