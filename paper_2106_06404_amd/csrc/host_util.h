@@ -282,6 +282,19 @@ std::vector<T> to_host(const T* ptr, size_t cnt) {
   return v;
 }
 
+// host copy into v (resized to cnt; its storage is reused when v already holds that many)
+template <class T>
+void to_host_into(std::vector<T>& v, const T* ptr, size_t cnt) {
+  v.resize(cnt);
+  if (cnt == 0) return;
+  REQUIRE(ptr != nullptr, "null array argument");
+  if (is_device_ptr(ptr)) {
+    HIPCHK(hipMemcpy(v.data(), ptr, cnt * sizeof(T), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(v.data(), ptr, cnt * sizeof(T));
+  }
+}
+
 // device copy owned by the context (from host or device source)
 template <class T>
 void to_device(DVec<T>& dst, const T* src, size_t cnt, hipStream_t s) {

@@ -269,12 +269,11 @@ struct FineLevel {
   GroupSetDev gs;                       // Neumann-space plans
   std::vector<std::vector<int32_t>> elems;
   std::vector<GroupPlan> plans;
-  std::vector<double> h_dv;             // PoU weights (sorted order)
-  DVec<double> dv;
-  std::vector<double> h_dw;             // PoU weight per Dirichlet entry (doff order)
-  DVec<double> dw;                      // (the restricted additive Schwarz weights)
-  std::vector<double> h_dg;             // b^3: weights 1 - dv of the GEVP right-hand side
-  DVec<double> dg;                      // (empty for b^1 and b^2, which use dv)
+  DVec<double> dv;                      // PoU weights (sorted order)
+  DVec<double> dw;                      // PoU weight per Dirichlet entry (doff order): the
+                                        // restricted additive Schwarz weights
+  DVec<double> dg;                      // b^3: weights 1 - dv of the GEVP right-hand side
+                                        // (empty for b^1 and b^2, which use dv)
   DVec<int32_t> elem_ov;                // b^2: 1 for overlap elements (else empty)
   DVec<double> band2, ell_val2;         // b^2: the overlap elements' sum, band and ELL
   // weights of the GEVP right-hand side b = D_g M D_g (M = abar, or band2 / ell_val2)
@@ -301,7 +300,7 @@ struct FineLevel {
   DVec<double> LB;
   bool has_lb = false;
   // Dirichlet
-  std::vector<int32_t> h_nd, h_bd, h_dpos, h_dglob, h_rankb;
+  std::vector<int32_t> h_nd, h_bd, h_rankb;
   std::vector<int64_t> h_doff, h_dboff;
   DVec<int32_t> nd, bd, dpos, dglob, drow_sub, rankb;
   DVec<int> inertia;  // eigenvalues below eta per subdomain (-1: unknown)
@@ -309,8 +308,7 @@ struct FineLevel {
   DVec<double> Dband, LDc, LDr;
   DVec<float> LDc32, LDr32;  // single-precision mode: factor of diag(sc) A_i diag(sc)
   DVec<int32_t> seed_id;     // index of the subdomain within its problem (start blocks)
-  std::vector<int32_t> h_wpos;  // warm-start frame position per Neumann row (-1 = none)
-  DVec<int32_t> wpos;
+  DVec<int32_t> wpos;  // warm-start frame position per Neumann row (-1 = none)
   DVec<double> dscale;       // sc per Dirichlet dof (single-precision mode)
   // two-sided form of the Dirichlet solves (twist.hip): blocks before the separator of
   // the top and bottom parts, the bottom part's reversed band and LDL^T factor (nB rows
@@ -517,6 +515,10 @@ struct msdd_ctx {
   std::vector<std::vector<int>> scr_maps;
   bool scr_maps_clean = false;
   std::vector<int64_t> scr_pos;
+  // host copies of the setup's index inputs, kept between setups (their storage is reused)
+  std::vector<int64_t> in_rowptr, in_sep, in_sdp;
+  std::vector<int32_t> in_ed, in_se, in_sd;
+  std::vector<double> in_sw;
   msdd_tuning_t tune{};            // launch-shape choices (0 = by shape)
   ~msdd_ctx() {
     if (h_segI) (void)hipHostFree(h_segI);
@@ -818,17 +820,11 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
     if (!sp[i].err.empty()) throw MsddError{MSDD_EINVAL, sp[i].err};
   vlog(c, "plan: subdomain groups (parallel)", &tv);
   // merge in subdomain order
-  F.h_dv.clear();
-  F.h_dw.clear();
-  F.h_dg.clear();
-  F.h_wpos.clear();
   F.h_nd.assign(P, 0);
   F.h_bd.assign(P, 0);
   F.h_rankb.assign(P, 0);
   F.h_doff.assign(P + 1, 0);
   F.h_dboff.assign(P + 1, 0);
-  F.h_dpos.clear();
-  F.h_dglob.clear();
   F.ell_w = 0;
   std::vector<double>& pou_sum = c->scr_pou;
   std::vector<int32_t>& dcount = c->scr_cnt;
@@ -889,20 +885,18 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   REQUIRE(F.nb_max <= kMaxLocalDofs,
           "a finest subdomain has " + std::to_string(F.nb_max) + " dofs; at most " +
           std::to_string(kMaxLocalDofs) + " are supported (use more subdomains)");
-  F.h_dv.resize(nbo[P]);
-  F.h_wpos.resize(nbo[P]);
-  if (rhs == 3) F.h_dg.resize(nbo[P]);
-  F.h_dpos.resize(ndo[P]);
-  F.h_dw.resize(ndo[P]);
-  F.h_dglob.resize(ndo[P]);
+  // the subdomains' weights and Dirichlet index lists, concatenated (upload-only arrays
+  // in the pinned staging arena; every entry is written)
+  HostBuf<double> h_dv(nbo[P]), h_dw(ndo[P]), h_dg(rhs == 3 ? nbo[P] : 0);
+  HostBuf<int32_t> h_wpos(nbo[P]), h_dpos(ndo[P]), h_dglob(ndo[P]);
   parallel_for(P, nthr, [&](int i, int) {
     const SubPlan& S = sp[i];
-    std::copy(S.dv.begin(), S.dv.end(), F.h_dv.begin() + nbo[i]);
-    std::copy(S.wpos.begin(), S.wpos.end(), F.h_wpos.begin() + nbo[i]);
-    if (rhs == 3) std::copy(S.dg.begin(), S.dg.end(), F.h_dg.begin() + nbo[i]);
-    std::copy(S.dpos.begin(), S.dpos.end(), F.h_dpos.begin() + ndo[i]);
-    std::copy(S.dglob.begin(), S.dglob.end(), F.h_dglob.begin() + ndo[i]);
-    for (int q = 0; q < S.nD; ++q) F.h_dw[ndo[i] + q] = S.dv[S.dpos[q]];
+    std::copy(S.dv.begin(), S.dv.end(), h_dv.begin() + nbo[i]);
+    std::copy(S.wpos.begin(), S.wpos.end(), h_wpos.begin() + nbo[i]);
+    if (rhs == 3) std::copy(S.dg.begin(), S.dg.end(), h_dg.begin() + nbo[i]);
+    std::copy(S.dpos.begin(), S.dpos.end(), h_dpos.begin() + ndo[i]);
+    std::copy(S.dglob.begin(), S.dglob.end(), h_dglob.begin() + ndo[i]);
+    for (int q = 0; q < S.nD; ++q) h_dw[ndo[i] + q] = S.dv[S.dpos[q]];
   });
   // PoU sums and Dirichlet multiplicities, each thread over a range of dofs and all
   // subdomains in order (each subdomain's dofs are sorted), so every sum runs in subdomain
@@ -966,9 +960,9 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   vlog(c, "plan: merge + PoU check", &tv);
   hipStream_t s = c->stream;
   build_groupset(F.plans, F.elems, k, F.gs, s);
-  F.dv.upload(F.h_dv, s);
-  F.dw.upload(F.h_dw, s);
-  if (rhs == 3) F.dg.upload(F.h_dg, s);
+  F.dv.upload_raw(h_dv.p, h_dv.n, s);
+  F.dw.upload_raw(h_dw.p, h_dw.n, s);
+  if (rhs == 3) F.dg.upload_raw(h_dg.p, h_dg.n, s);
   else F.dg.release();
   if (rhs == 2) {
     std::vector<int32_t> ov(n_elem);
@@ -977,7 +971,7 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   } else {
     F.elem_ov.release();
   }
-  F.wpos.upload(F.h_wpos, s);
+  F.wpos.upload_raw(h_wpos.p, h_wpos.n, s);
   F.h_boff.assign(P + 1, 0);
   for (int i = 0; i < P; ++i)
     F.h_boff[i + 1] = F.h_boff[i] + (int64_t)F.plans[i].dofs.size() * (F.plans[i].bw + 1);
@@ -997,10 +991,11 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
   });
   F.ell_col.upload_raw(ell.p, ell.n, s);
   F.boff.upload(F.h_boff, s);
-  std::vector<int32_t> drow_sub(F.h_doff.back());
-  for (int i = 0; i < P; ++i)
-    for (int64_t g = F.h_doff[i]; g < F.h_doff[i + 1]; ++g) drow_sub[g] = i;
-  F.drow_sub.upload(drow_sub, s);
+  HostBuf<int32_t> drow_sub(F.h_doff.back());
+  parallel_for(P, nthr, [&](int i, int) {
+    std::fill(drow_sub.begin() + F.h_doff[i], drow_sub.begin() + F.h_doff[i + 1], i);
+  });
+  F.drow_sub.upload_raw(drow_sub.p, drow_sub.n, s);
   F.nd.upload(F.h_nd, s);
   F.bd.upload(F.h_bd, s);
   F.doff.upload(F.h_doff, s);
@@ -1012,8 +1007,8 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
     F.toff.upload(F.h_toff, s);
     F.coff.upload(F.h_coff, s);
   }
-  F.dpos.upload(F.h_dpos, s);
-  F.dglob.upload(F.h_dglob, s);
+  F.dpos.upload_raw(h_dpos.p, h_dpos.n, s);
+  F.dglob.upload_raw(h_dglob.p, h_dglob.n, s);
   F.rankb.upload(F.h_rankb, s);
   F.dinc_ptr.upload_raw(dptr.p, dptr.n, s);
   F.dinc_sub.upload_raw(dsub.p, dsub.n, s);
@@ -2539,17 +2534,36 @@ int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     hipStream_t s = c->stream;
     double tv = now_ms();
     // host copies of the index arrays (planning)
-    std::vector<int64_t> h_rowptr = to_host(rowptr, (size_t)n + 1);
+    std::vector<int64_t>& h_rowptr = c->in_rowptr;
+    to_host_into(h_rowptr, rowptr, (size_t)n + 1);
     REQUIRE(h_rowptr[0] == 0, "rowptr[0] must be 0");
-    for (int64_t i = 0; i < n; ++i) REQUIRE(h_rowptr[i + 1] >= h_rowptr[i], "rowptr not monotone");
+    {
+      const int nr = host_threads((int)std::min<int64_t>(16, (n + 65535) / 65536));
+      std::vector<int64_t> first(nr, -1);
+      parallel_for(nr, nr, [&](int t, int) {
+        for (int64_t i = n * t / nr; i < n * (t + 1) / nr; ++i)
+          if (h_rowptr[i + 1] < h_rowptr[i]) {
+            first[t] = i;
+            break;
+          }
+      });
+      for (int t = 0; t < nr; ++t) REQUIRE(first[t] < 0, "rowptr not monotone");
+    }
     c->nnz = h_rowptr[n];
-    std::vector<int32_t> ed = to_host(elem_dofs, (size_t)n_elem * k);
-    std::vector<int64_t> sep = to_host(sub_elem_ptr, (size_t)n_sub + 1);
-    std::vector<int64_t> sdp = to_host(sub_dof_ptr, (size_t)n_sub + 1);
+    std::vector<int32_t>& ed = c->in_ed;
+    std::vector<int64_t>& sep = c->in_sep;
+    std::vector<int64_t>& sdp = c->in_sdp;
+    to_host_into(ed, elem_dofs, (size_t)n_elem * k);
+    to_host_into(sep, sub_elem_ptr, (size_t)n_sub + 1);
+    to_host_into(sdp, sub_dof_ptr, (size_t)n_sub + 1);
     REQUIRE(sep[0] == 0 && sdp[0] == 0, "subdomain pointers must start at 0");
-    std::vector<int32_t> se = to_host(sub_elem, (size_t)sep[n_sub]);
-    std::vector<int32_t> sd = to_host(sub_dof, (size_t)sdp[n_sub]);
-    std::vector<double> sw = to_host(sub_pou, (size_t)sdp[n_sub]);
+    std::vector<int32_t>& se = c->in_se;
+    std::vector<int32_t>& sd = c->in_sd;
+    std::vector<double>& sw = c->in_sw;
+    to_host_into(se, sub_elem, (size_t)sep[n_sub]);
+    to_host_into(sd, sub_dof, (size_t)sdp[n_sub]);
+    to_host_into(sw, sub_pou, (size_t)sdp[n_sub]);
+    vlog(c, "setup: host copies of the index inputs", &tv);
     std::vector<std::vector<int32_t>> parents;
     {
       int cnt = n_sub;
