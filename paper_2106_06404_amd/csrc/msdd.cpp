@@ -734,9 +734,10 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
     std::vector<DofW> dw((size_t)nd_in);
     for (int64_t q = 0; q < nd_in; ++q)
       dw[q] = {sd[sdp[i] + q], sw[sdp[i] + q], wp ? (*wp)[sdp[i] + q] : -1};
-    std::sort(dw.begin(), dw.end(), [](const DofW& a, const DofW& b) {
+    const auto dw_less = [](const DofW& a, const DofW& b) {
       return a.d < b.d || (a.d == b.d && a.w < b.w);
-    });
+    };
+    if (!std::is_sorted(dw.begin(), dw.end(), dw_less)) std::sort(dw.begin(), dw.end(), dw_less);
     const int nb = (int)g.dofs.size();
     std::vector<int32_t> dloc(nb, -1);
     S.dv.resize(nb);
@@ -811,7 +812,18 @@ void plan_fine(msdd_ctx* c, int32_t n_elem, const std::vector<int32_t>& ed,
         }
       }
       S.ell_ptr[r + 1] = (int32_t)S.ell_col.size();
-      std::sort(S.ell_col.begin() + S.ell_ptr[r], S.ell_col.end());
+      // a row holds a few distinct neighbours: insertion sort
+      int32_t* rc = S.ell_col.data() + S.ell_ptr[r];
+      const int len = S.ell_ptr[r + 1] - S.ell_ptr[r];
+      for (int a = 1; a < len; ++a) {
+        const int32_t v = rc[a];
+        int b = a - 1;
+        while (b >= 0 && rc[b] > v) {
+          rc[b + 1] = rc[b];
+          --b;
+        }
+        rc[b + 1] = v;
+      }
       S.ell_w = std::max(S.ell_w, S.ell_ptr[r + 1] - S.ell_ptr[r]);
     }
   });
