@@ -78,8 +78,13 @@ class PinnedArena {
   void* stage(const void* src, size_t bytes) {
     char* dst = static_cast<char*>(alloc(bytes));
     if (!dst) return nullptr;
-    // large arrays are copied by several threads (a single thread moves only a few GB/s)
+    copy_bytes(dst, src, bytes);
+    return dst;
+  }
+  // memcpy; large blocks by several threads (a single thread moves only a few GB/s)
+  static void copy_bytes(void* dstv, const void* src, size_t bytes) {
     constexpr size_t kPar = (size_t)4 << 20;
+    char* dst = static_cast<char*>(dstv);
     if (bytes >= kPar) {
       constexpr int kThr = 8;
       const size_t part = ((bytes + kThr - 1) / kThr + 255) & ~(size_t)255;
@@ -94,7 +99,6 @@ class PinnedArena {
     } else {
       std::memcpy(dst, src, bytes);
     }
-    return dst;
   }
   void reset() {
     std::lock_guard<std::mutex> lk(mu_);
@@ -283,15 +287,29 @@ std::vector<T> to_host(const T* ptr, size_t cnt) {
 }
 
 // host copy into v (resized to cnt; its storage is reused when v already holds that many)
+// (device sources through pinned staging space, in pieces of at most 16 MB)
 template <class T>
 void to_host_into(std::vector<T>& v, const T* ptr, size_t cnt) {
   v.resize(cnt);
   if (cnt == 0) return;
   REQUIRE(ptr != nullptr, "null array argument");
+  const size_t bytes = cnt * sizeof(T);
   if (is_device_ptr(ptr)) {
-    HIPCHK(hipMemcpy(v.data(), ptr, cnt * sizeof(T), hipMemcpyDeviceToHost));
+    constexpr size_t kPiece = (size_t)16 << 20;
+    char* st = bytes >= ((size_t)64 << 10)
+                   ? static_cast<char*>(PinnedArena::get().alloc(bytes < kPiece ? bytes : kPiece))
+                   : nullptr;
+    if (!st) {
+      HIPCHK(hipMemcpy(v.data(), ptr, bytes, hipMemcpyDeviceToHost));
+      return;
+    }
+    for (size_t a = 0; a < bytes; a += kPiece) {
+      const size_t len = bytes - a < kPiece ? bytes - a : kPiece;
+      HIPCHK(hipMemcpy(st, reinterpret_cast<const char*>(ptr) + a, len, hipMemcpyDeviceToHost));
+      PinnedArena::copy_bytes(reinterpret_cast<char*>(v.data()) + a, st, len);
+    }
   } else {
-    std::memcpy(v.data(), ptr, cnt * sizeof(T));
+    PinnedArena::copy_bytes(v.data(), ptr, bytes);
   }
 }
 
