@@ -2565,16 +2565,53 @@ int setup_impl(msdd_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col
     std::vector<int32_t>& ed = c->in_ed;
     std::vector<int64_t>& sep = c->in_sep;
     std::vector<int64_t>& sdp = c->in_sdp;
-    to_host_into(ed, elem_dofs, (size_t)n_elem * k);
     to_host_into(sep, sub_elem_ptr, (size_t)n_sub + 1);
     to_host_into(sdp, sub_dof_ptr, (size_t)n_sub + 1);
     REQUIRE(sep[0] == 0 && sdp[0] == 0, "subdomain pointers must start at 0");
     std::vector<int32_t>& se = c->in_se;
     std::vector<int32_t>& sd = c->in_sd;
     std::vector<double>& sw = c->in_sw;
-    to_host_into(se, sub_elem, (size_t)sep[n_sub]);
-    to_host_into(sd, sub_dof, (size_t)sdp[n_sub]);
-    to_host_into(sw, sub_pou, (size_t)sdp[n_sub]);
+    {
+      // the element and subdomain arrays: device sources of up to 16 MB leave together as
+      // asynchronous copies on the null stream (ordered as the synchronous copies are
+      // against the caller's work) into pinned staging, then move to the host vectors in
+      // parallel; larger or host sources go one by one
+      struct In {
+        void* dst;
+        const void* src;
+        size_t bytes;
+        char* st;
+      };
+      std::vector<In> batch;
+      auto take = [&](auto& v, const auto* src, size_t cnt) {
+        v.resize(cnt);
+        const size_t bytes = cnt * sizeof(v[0]);
+        char* st = nullptr;
+        if (cnt && src && is_device_ptr(src) && bytes <= ((size_t)16 << 20))
+          st = static_cast<char*>(PinnedArena::get().alloc(bytes));
+        if (st)
+          batch.push_back({v.data(), src, bytes, st});
+        else
+          to_host_into(v, src, cnt);
+      };
+      take(ed, elem_dofs, (size_t)n_elem * k);
+      take(se, sub_elem, (size_t)sep[n_sub]);
+      take(sd, sub_dof, (size_t)sdp[n_sub]);
+      take(sw, sub_pou, (size_t)sdp[n_sub]);
+      for (const In& b : batch)
+        HIPCHK(hipMemcpyAsync(b.st, b.src, b.bytes, hipMemcpyDeviceToHost, nullptr));
+      HIPCHK(hipStreamSynchronize(nullptr));
+      // out of staging in pieces of 1 MB over the planning threads
+      constexpr size_t kPc = (size_t)1 << 20;
+      std::vector<std::pair<int, size_t>> pieces;
+      for (int q = 0; q < (int)batch.size(); ++q)
+        for (size_t a = 0; a < batch[q].bytes; a += kPc) pieces.push_back({q, a});
+      parallel_for((int)pieces.size(), host_threads((int)pieces.size()), [&](int t, int) {
+        const In& b = batch[pieces[t].first];
+        const size_t a = pieces[t].second, len = std::min(kPc, b.bytes - a);
+        std::memcpy(static_cast<char*>(b.dst) + a, b.st + a, len);
+      });
+    }
     vlog(c, "setup: host copies of the index inputs", &tv);
     std::vector<std::vector<int32_t>> parents;
     {
