@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libmsdd.so")
 
-SOURCES = ["band.hip", "band_blocked.hip", "eig.hip", "coarse.hip", "dense_blocked.hip", "pcg.hip", "twist.hip", "gmres.hip", "mlp.hip", "msdd.cpp", "net.cpp"]
+SOURCES = ["band.hip", "band_blocked.hip", "eig.hip", "eig32.hip", "coarse.hip", "dense_blocked.hip", "pcg.hip", "twist.hip", "gmres.hip", "mlp.hip", "msdd.cpp", "net.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -139,6 +139,15 @@ void launch_coarse_collect(hipStream_t s, int nt, const i32* ng_arr, const i32* 
                            const i64* soff, const double* scratch, const int* m_arr,
                            const i64* yoff, double* Y);
 
+// abar Y in difference form for the eigensolver with the single-precision factor
+// (eig32.hip): rs = compensated row sums of the Neumann matrices (ELL), then
+// T = abar Y row by row as sum_j a_rj (y_j - y_r) + rs_r y_r over the running subdomains
+void launch_abar_rowsum(hipStream_t s, i64 total_rows, int ell_w, const i32* ell_col,
+                        const double* ell_val, double* rs);
+void launch_abar_diff(hipStream_t s, i64 total_rows, const i32* row_sub, const i64* voff,
+                      const i32* nb, const i64* kvoff, int K, int ell_w, const i32* ell_col,
+                      const double* ell_val, const double* rs, const double* Y, double* T,
+                      const int* active);
 // pcg.hip
 // segmented PCG (see pcg.hip): per-segment state fields and reduction rules
 enum { PCG_RZ = 0, PCG_PQ, PCG_RR, PCG_ALPHA, PCG_BETA, PCG_RR0, PCG_TOL2, PCG_SD };

@@ -291,7 +291,7 @@ struct FineLevel {
   // product with unit weights)
   bool eig32 = false;
   bool f64_built = false;  // LSc/LSr hold the FP64 factor
-  DVec<double> esc, eones;
+  DVec<double> esc, abar_rs;  // abar_rs: compensated row sums of abar (difference form)
   DVec<float> LS32c, LS32r;
   // blocked form of the same factor (per 64-row block: inverse of the diagonal block and
   // the couplings multiplied by it); built when every half-bandwidth is at most 64
@@ -1247,8 +1247,8 @@ void fine_local_matrices(msdd_ctx* c, const double* d_elem_mat) {
                                 status.p);
     launch_band_to_ldl<float>(s, P, F.nb_max, F.bw_max, F.gs.n.p, F.gs.bw.p, F.boff.p, F.LS32c.p,
                               F.LS32r.p);
-    std::vector<double> ones((size_t)F.gs.total_rows, 1.0);
-    F.eones.upload(ones, s);
+    F.abar_rs.alloc(std::max<int64_t>(F.gs.total_rows, 1));
+    launch_abar_rowsum(s, F.gs.total_rows, F.ell_w, F.ell_col.p, F.ell_val.p, F.abar_rs.p);
     HIPCHK(hipGetLastError());
     F.has_lb = false;
   }
@@ -1279,15 +1279,13 @@ void eig_bapply(msdd_ctx* c, hipStream_t s, const int64_t* kvoff, int K, const d
                     F.ell_w, F.ell_col.p, ev, Y, Z, status);
 }
 
-// T = abar Y (the b product with unit weights), for S Y = abar Y + sigma b Y
+// T = abar Y in difference form (rounding error scaled by the differences y_j - y_r, small
+// for vectors near the kernel of abar), for S Y = abar Y + sigma b Y
 void eig_abar_apply(msdd_ctx* c, hipStream_t s, const int64_t* kvoff, int K, const double* Y,
                     double* T, const int* status) {
   FineLevel& F = c->F;
-  if (launch_bapply_tile(s, F.P, F.nb_max, F.bw_max, F.gs.voff.p, F.gs.n.p, F.gs.bw.p, kvoff, K,
-                         F.eones.p, F.ell_w, F.ell_col.p, F.ell_val.p, Y, T, status))
-    return;
-  launch_bapply_ell(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, kvoff, K,
-                    F.eones.p, F.ell_w, F.ell_col.p, F.ell_val.p, Y, T, status);
+  launch_abar_diff(s, F.gs.total_rows, F.gs.row_grp.p, F.gs.voff.p, F.gs.n.p, kvoff, K, F.ell_w,
+                   F.ell_col.p, F.ell_val.p, F.abar_rs.p, Y, T, status);
 }
 
 // Band solves Y = S^{-1} W of the eigensolver (K columns per subdomain, skipped where

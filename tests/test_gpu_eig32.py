@@ -7,8 +7,8 @@ the pair that certifies the count, coarse-space blocks, the preconditioner apply
 512x512 workload against its stored oracle run (tests/golden/c2_oracle.*) with the bars
 of that workload's parity test.  Alone and with the FP32 preconditioner (MSDD_MIXED).
 Subdomains whose FP32-factor iteration does not certify its count in 64 iterations are
-solved again with the FP64 factor (on the 512x512 workload 15 of 256): the bars hold for
-the whole mix."""
+solved again with the FP64 factor (none on the 512x512 workload since abar Y is formed in
+difference form); the bars hold for either."""
 import os
 
 import numpy as np
